@@ -1,0 +1,987 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU reference of the adaptive finite-volume
+ * method for the compressible Euler equations (ideal gas, Cartesian 2D/3D)
+ * of Deiterding, Domingues, Gomes and Schneider, "Comparison of adaptive
+ * multiresolution and adaptive mesh refinement applied to simulations of the
+ * compressible Euler equations" (arXiv:1603.05211).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+ * the benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant with the GPU library and includes nothing of it.
+ *
+ * Every routine is written for a reader to check against the paper by eye:
+ * one cell at a time, FP64 throughout, no blocking, no fusion.  Loops over
+ * independent cells carry an OpenMP pragma; every output cell is computed by
+ * the same expression whatever the thread count, so results do not depend
+ * on it.  Build with -O2 -ffp-contract=off (no FMA contraction).
+ *
+ * Layout: level l holds a dense grid of n_l^d cells, n_l = n0 * 2^l.  The
+ * conserved fields (rho, m_1..m_d, E) are stored one after another, x fastest:
+ *     Q[f * n^d + x + n * (y + n * z)]          (z = 0 in 2D).
+ * Cells of a level that belong to no refinement patch still have storage;
+ * they are read only where they are ghost cells (filled by prediction).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXL 10
+#define NVMAX 5
+
+enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1 };
+
+/* ------------------------------------------------------------------------ */
+/* grid helpers                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Ghost index map for the physical boundary.  Outflow (transmissive) takes
+ * the nearest interior cell (zero-order extrapolation); periodic wraps.
+ * Sec. 4.1 / 4.2: outflow conditions at all sides of the domain. */
+static int bcmap(int i, int n, int bc)
+{
+    if (bc == BC_PERIODIC) {
+        i %= n;
+        if (i < 0) i += n;
+        return i;
+    }
+    if (i < 0) return 0;
+    if (i >= n) return n - 1;
+    return i;
+}
+
+static int64_t ncells(int dim, int n)
+{
+    return dim == 2 ? (int64_t)n * n : (int64_t)n * n * n;
+}
+
+static int64_t cidx(int n, const int *c)
+{
+    return c[0] + (int64_t)n * (c[1] + (int64_t)n * c[2]);
+}
+
+static void cdecode(int dim, int n, int64_t i, int *c)
+{
+    c[0] = (int)(i % n);
+    c[1] = (int)((i / n) % n);
+    c[2] = dim == 3 ? (int)(i / ((int64_t)n * n)) : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* physics: Sec. 2, conservation law, fluxes f_1..f_3 and ideal-gas relation */
+/* ------------------------------------------------------------------------ */
+
+/* conserved (rho, rho v, rho e) -> primitive (rho, v, p);
+ * p = (gamma - 1) (rho e - rho |v|^2 / 2). */
+static void cons2prim(int dim, double g, const double *q, double *w)
+{
+    double rho = q[0], K = 0.0;
+    w[0] = rho;
+    for (int d = 0; d < dim; ++d) {
+        double v = q[1 + d] / rho;
+        w[1 + d] = v;
+        K = K + v * v;
+    }
+    w[dim + 1] = (g - 1.0) * (q[dim + 1] - (0.5 * rho) * K);
+}
+
+/* primitive -> conserved; rho e = p / (gamma - 1) + rho |v|^2 / 2. */
+static void prim2cons(int dim, double g, const double *w, double *q)
+{
+    double rho = w[0], K = 0.0, gi = 1.0 / (g - 1.0);
+    q[0] = rho;
+    for (int d = 0; d < dim; ++d) {
+        q[1 + d] = rho * w[1 + d];
+        K = K + w[1 + d] * w[1 + d];
+    }
+    q[dim + 1] = w[dim + 1] * gi + (0.5 * rho) * K;
+}
+
+/* van Albada limited slope of the MUSCL reconstruction (Sec. 2, MR scheme),
+ * in slope form: sigma = a b (a + b) / (a^2 + b^2) for a b > 0, else 0,
+ * with a, b the backward and forward differences. */
+static double slope_va(double wm, double w0, double wp)
+{
+    double a = w0 - wm, b = wp - w0, ab = a * b;
+    if (ab > 0.0) return (ab * (a + b)) / (a * a + b * b);
+    return 0.0;
+}
+
+/* AUSM+ flux-vector splitting (Liou 1996; Sec. 2, MR scheme) across a face
+ * with normal along axis dn.  wL / wR are the primitive face states.
+ * Interface sound speed: arithmetic mean; alpha = 3/16, beta = 1/8. */
+static void ausm_plus(int dim, double g, int dn, const double *wL,
+                      const double *wR, double *F)
+{
+    double gi = 1.0 / (g - 1.0);
+    double rL = wL[0], pL = wL[dim + 1], uL = wL[1 + dn];
+    double rR = wR[0], pR = wR[dim + 1], uR = wR[1 + dn];
+    double cL = sqrt((g * pL) / rL);
+    double cR = sqrt((g * pR) / rR);
+    double ch = 0.5 * (cL + cR);
+    double ML = uL / ch, MR = uR / ch;
+    double Mp, Pp, Mm, Pm;
+    /* split Mach number M4+ and pressure P5+ of the left state */
+    if (fabs(ML) >= 1.0) {
+        Mp = 0.5 * (ML + fabs(ML));
+        Pp = ML > 0.0 ? 1.0 : 0.0;
+    } else {
+        double a = ML + 1.0, b = ML - 1.0;
+        double m2p = 0.25 * (a * a), m2m = -0.25 * (b * b);
+        Mp = m2p * (1.0 - 2.0 * m2m);                 /* 16 beta = 2  */
+        Pp = m2p * ((2.0 - ML) - (3.0 * ML) * m2m);   /* 16 alpha = 3 */
+    }
+    /* split Mach number M4- and pressure P5- of the right state */
+    if (fabs(MR) >= 1.0) {
+        Mm = 0.5 * (MR - fabs(MR));
+        Pm = MR < 0.0 ? 1.0 : 0.0;
+    } else {
+        double a = MR + 1.0, b = MR - 1.0;
+        double m2p = 0.25 * (a * a), m2m = -0.25 * (b * b);
+        Mm = m2m * (1.0 + 2.0 * m2p);
+        Pm = m2m * ((-2.0 - MR) + (3.0 * MR) * m2p);
+    }
+    double mh = Mp + Mm;
+    double ph = Pp * pL + Pm * pR;
+    double mf = ch * mh;
+    const double *wu = mh >= 0.0 ? wL : wR;        /* upwind state */
+    double ru = wu[0], pu = wu[dim + 1], K = 0.0;
+    for (int k = 0; k < dim; ++k) K = K + wu[1 + k] * wu[1 + k];
+    double rH = (pu * gi + (0.5 * ru) * K) + pu;     /* rho e + p */
+    F[0] = mf * ru;
+    for (int k = 0; k < dim; ++k) {
+        F[1 + k] = mf * (ru * wu[1 + k]);
+        if (k == dn) F[1 + k] = F[1 + k] + ph;
+    }
+    F[dim + 1] = mf * rH;
+}
+
+/* Numerical flux at the face between cell c (coordinates, axis dn may be
+ * outside the domain) and c + e_dn, from the 4-cell stencil c-1 .. c+2 along
+ * dn of array A on an n^d grid: primitive MUSCL face states + AUSM+. */
+static void face_flux(int dim, int n, int bc, double g, const double *A,
+                      int dn, const int *c, double *F)
+{
+    int64_t N = ncells(dim, n);
+    double w[4][NVMAX], q[NVMAX], wL[NVMAX], wR[NVMAX];
+    int nv = dim + 2;
+    for (int k = 0; k < 4; ++k) {
+        int p[3] = {c[0], c[1], c[2]};
+        p[dn] = bcmap(c[dn] + k - 1, n, bc);
+        int64_t id = cidx(n, p);
+        for (int f = 0; f < nv; ++f) q[f] = A[f * N + id];
+        cons2prim(dim, g, q, w[k]);
+    }
+    for (int f = 0; f < nv; ++f) {
+        wL[f] = w[1][f] + 0.5 * slope_va(w[0][f], w[1][f], w[2][f]);
+        wR[f] = w[2][f] - 0.5 * slope_va(w[1][f], w[2][f], w[3][f]);
+    }
+    ausm_plus(dim, g, dn, wL, wR, F);
+}
+
+/* ------------------------------------------------------------------------ */
+/* multiresolution operators: Sec. 2.1 (projection / prediction, details)    */
+/* ------------------------------------------------------------------------ */
+
+/* Projection: a parent's cell average is the mean of its 2^d children. */
+static double restrict_cell(int dim, int nf, const double *Af, int64_t off,
+                            const int *p)
+{
+    int c[3] = {2 * p[0], 2 * p[1], dim == 3 ? 2 * p[2] : 0};
+#define AF(dx, dy, dz) Af[off + (c[0] + (dx)) + (int64_t)nf * ((c[1] + (dy)) + (int64_t)nf * (c[2] + (dz)))]
+    if (dim == 2)
+        return 0.25 * ((AF(0, 0, 0) + AF(1, 0, 0)) + (AF(0, 1, 0) + AF(1, 1, 0)));
+    return 0.125 * (((AF(0, 0, 0) + AF(1, 0, 0)) + (AF(0, 1, 0) + AF(1, 1, 0))) +
+                    ((AF(0, 0, 1) + AF(1, 0, 1)) + (AF(0, 1, 1) + AF(1, 1, 1))));
+#undef AF
+}
+
+/* Harten's third-order cell-average prediction in 1D (quadratic
+ * interpolation of the parent and its two neighbours): lower child
+ * q0 + (q_{-1} - q_{+1}) / 8, upper child q0 - (q_{-1} - q_{+1}) / 8. */
+static double pred1(double qm, double q0, double qp, int upper)
+{
+    double s8 = upper ? -0.125 : 0.125;
+    return q0 + s8 * (qm - qp);
+}
+
+/* Prediction of child ch (bits: x, y, z) of coarse cell p for one field of
+ * array Ac (n_c^d grid), tensor product applied x, then y, then z. */
+static double predict_child(int dim, int nc, int bc, const double *Ac,
+                            int64_t off, const int *p, const int *ch)
+{
+    int xs[3], ys[3], zs[3];
+    for (int k = 0; k < 3; ++k) {
+        xs[k] = bcmap(p[0] + k - 1, nc, bc);
+        ys[k] = bcmap(p[1] + k - 1, nc, bc);
+        zs[k] = dim == 3 ? bcmap(p[2] + k - 1, nc, bc) : 0;
+    }
+#define AC(x, y, z) Ac[off + (x) + (int64_t)nc * ((y) + (int64_t)nc * (z))]
+    if (dim == 2) {
+        double r[3];
+        for (int j = 0; j < 3; ++j)
+            r[j] = pred1(AC(xs[0], ys[j], 0), AC(xs[1], ys[j], 0), AC(xs[2], ys[j], 0), ch[0]);
+        return pred1(r[0], r[1], r[2], ch[1]);
+    }
+    double s[3];
+    for (int k = 0; k < 3; ++k) {
+        double r[3];
+        for (int j = 0; j < 3; ++j)
+            r[j] = pred1(AC(xs[0], ys[j], zs[k]), AC(xs[1], ys[j], zs[k]), AC(xs[2], ys[j], zs[k]), ch[0]);
+        s[k] = pred1(r[0], r[1], r[2], ch[1]);
+    }
+    return pred1(s[0], s[1], s[2], ch[2]);
+#undef AC
+}
+
+/* ------------------------------------------------------------------------ */
+/* standalone operators on caller arrays (used by the tests as pins)         */
+/* ------------------------------------------------------------------------ */
+
+void orc_prim2cons(int dim, double g, int64_t ncell, const double *W, double *Q)
+{
+    int nv = dim + 2;
+    for (int64_t i = 0; i < ncell; ++i) {
+        double w[NVMAX], q[NVMAX];
+        for (int f = 0; f < nv; ++f) w[f] = W[f * ncell + i];
+        prim2cons(dim, g, w, q);
+        for (int f = 0; f < nv; ++f) Q[f * ncell + i] = q[f];
+    }
+}
+
+void orc_cons2prim(int dim, double g, int64_t ncell, const double *Q, double *W)
+{
+    int nv = dim + 2;
+    for (int64_t i = 0; i < ncell; ++i) {
+        double w[NVMAX], q[NVMAX];
+        for (int f = 0; f < nv; ++f) q[f] = Q[f * ncell + i];
+        cons2prim(dim, g, q, w);
+        for (int f = 0; f < nv; ++f) W[f * ncell + i] = w[f];
+    }
+}
+
+/* AUSM+ flux of a single face; wL, wR primitive (nv values each). */
+void orc_ausm_plus(int dim, double g, int dn, const double *wL, const double *wR, double *F)
+{
+    ausm_plus(dim, g, dn, wL, wR, F);
+}
+
+double orc_slope(double wm, double w0, double wp) { return slope_va(wm, w0, wp); }
+
+/* Restrict one field-major array (nv fields) from an (2 nc)^d grid to nc^d. */
+void orc_restrict(int dim, int nv, int nc, const double *Af, double *Ac)
+{
+    int nf = 2 * nc;
+    int64_t Nc = ncells(dim, nc), Nf = ncells(dim, nf);
+    for (int f = 0; f < nv; ++f)
+        for (int64_t i = 0; i < Nc; ++i) {
+            int p[3];
+            cdecode(dim, nc, i, p);
+            Ac[f * Nc + i] = restrict_cell(dim, nf, Af, f * Nf, p);
+        }
+}
+
+/* Predict every child of an nc^d grid onto a (2 nc)^d grid. */
+void orc_predict(int dim, int nv, int nc, int bc, const double *Ac, double *Af)
+{
+    int nf = 2 * nc;
+    int64_t Nc = ncells(dim, nc), Nf = ncells(dim, nf);
+    for (int f = 0; f < nv; ++f)
+        for (int64_t i = 0; i < Nf; ++i) {
+            int k[3], p[3], ch[3];
+            cdecode(dim, nf, i, k);
+            for (int d = 0; d < 3; ++d) { p[d] = k[d] / 2; ch[d] = k[d] & 1; }
+            Af[f * Nf + i] = predict_child(dim, nc, bc, Ac, f * Nc, p, ch);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* the hierarchy                                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int lvl, o[3], size;
+} orc_patch;
+
+typedef struct {
+    int dim, L, n0, bc, nv;
+    double g, lo, hi, eps, eta;
+    int pmin, pmax;
+    int n[MAXL];
+    double dx[MAXL];
+    double *Q[MAXL];     /* current state                                 */
+    double *Qs[MAXL];    /* RK2 intermediate state Q*                      */
+    double *Qo[MAXL];    /* level state at the start of its step (LTS)     */
+    uint8_t *act[MAXL];  /* cell belongs to a patch of its level           */
+    uint8_t *nact[MAXL]; /* scratch for the new hierarchy                  */
+    uint8_t *sig[MAXL];  /* significant detail (0 .. L-2)                  */
+    uint8_t *flag[MAXL]; /* final refinement flags after closure (0..L-2)  */
+    double *D[MAXL];     /* detail norm (0 .. L-2)                         */
+    double *regC[MAXL];  /* LTS flux registers, coarse side [d][f][cell]   */
+    double *regF[MAXL];  /* LTS flux registers, fine side [sub][d][f][cell] */
+    orc_patch *patches;
+    int npatch, cappatch;
+} orc_h;
+
+static int64_t hN(const orc_h *h, int l) { return ncells(h->dim, h->n[l]); }
+
+void orc_h_free(orc_h *h)
+{
+    if (!h) return;
+    for (int l = 0; l < h->L; ++l) {
+        free(h->Q[l]); free(h->Qs[l]); free(h->Qo[l]);
+        free(h->act[l]); free(h->nact[l]); free(h->sig[l]); free(h->flag[l]);
+        free(h->D[l]); free(h->regC[l]); free(h->regF[l]);
+    }
+    free(h->patches);
+    free(h);
+}
+
+/* Returns NULL on invalid parameters or allocation failure. */
+orc_h *orc_h_new(int dim, int L, int n0, int bc, double g, double lo, double hi,
+                 double eps, double eta, int pmin, int pmax)
+{
+    if ((dim != 2 && dim != 3) || L < 1 || L > MAXL || n0 < 1) return NULL;
+    if (L > 1 && ((2 * n0) % pmax != 0 || pmin < 2 || pmax < pmin)) return NULL;
+    orc_h *h = (orc_h *)calloc(1, sizeof(orc_h));
+    if (!h) return NULL;
+    h->dim = dim; h->L = L; h->n0 = n0; h->bc = bc; h->nv = dim + 2;
+    h->g = g; h->lo = lo; h->hi = hi; h->eps = eps; h->eta = eta;
+    h->pmin = pmin; h->pmax = pmax;
+    for (int l = 0; l < L; ++l) {
+        h->n[l] = n0 << l;
+        h->dx[l] = (hi - lo) / (double)h->n[l];
+        int64_t N = hN(h, l);
+        h->Q[l] = (double *)calloc((size_t)(h->nv * N), sizeof(double));
+        h->Qs[l] = (double *)calloc((size_t)(h->nv * N), sizeof(double));
+        h->act[l] = (uint8_t *)malloc((size_t)N);
+        h->nact[l] = (uint8_t *)malloc((size_t)N);
+        if (!h->Q[l] || !h->Qs[l] || !h->act[l] || !h->nact[l]) { orc_h_free(h); return NULL; }
+        memset(h->act[l], l == 0 ? 1 : 0, (size_t)N);
+        if (l < L - 1) {
+            h->sig[l] = (uint8_t *)calloc((size_t)N, 1);
+            h->flag[l] = (uint8_t *)calloc((size_t)N, 1);
+            h->D[l] = (double *)calloc((size_t)N, sizeof(double));
+            if (!h->sig[l] || !h->flag[l] || !h->D[l]) { orc_h_free(h); return NULL; }
+        }
+    }
+    return h;
+}
+
+double *orc_h_level(orc_h *h, int l) { return h->Q[l]; }
+double *orc_h_level_stage(orc_h *h, int l) { return h->Qs[l]; }
+uint8_t *orc_h_active(orc_h *h, int l) { return h->act[l]; }
+uint8_t *orc_h_flags(orc_h *h, int l) { return l < h->L - 1 ? h->flag[l] : NULL; }
+double *orc_h_details(orc_h *h, int l) { return l < h->L - 1 ? h->D[l] : NULL; }
+int orc_h_n(const orc_h *h, int l) { return h->n[l]; }
+double orc_h_dx(const orc_h *h, int l) { return h->dx[l]; }
+
+/* covered: the cell's children belong to a patch of the next finer level */
+static int covered(const orc_h *h, const uint8_t *const *act, int l, const int *p)
+{
+    if (l + 1 >= h->L) return 0;
+    int c[3] = {2 * p[0], 2 * p[1], h->dim == 3 ? 2 * p[2] : 0};
+    return act[l + 1][cidx(h->n[l + 1], c)];
+}
+
+static int is_leaf(const orc_h *h, int l, const int *p)
+{
+    return h->act[l][cidx(h->n[l], p)] && !covered(h, (const uint8_t *const *)h->act, l, p);
+}
+
+/* ghost cell: outside every patch of its level but within two cells
+ * (max-norm, through the boundary map) of a cell that is inside one. */
+static int is_ghost(const orc_h *h, int l, const int *p)
+{
+    int n = h->n[l];
+    if (l == 0 || h->act[l][cidx(n, p)]) return 0;
+    int r3 = h->dim == 3 ? 2 : 0;
+    for (int dz = -r3; dz <= r3; ++dz)
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx) {
+                int q[3] = {bcmap(p[0] + dx, n, h->bc), bcmap(p[1] + dy, n, h->bc),
+                            h->dim == 3 ? bcmap(p[2] + dz, n, h->bc) : 0};
+                if (h->act[l][cidx(n, q)]) return 1;
+            }
+    return 0;
+}
+
+/* ---- inter-level transfer on the hierarchy ---- */
+
+/* Projection onto every covered cell, finest level first (Sec. 2.2: cells
+ * covered by finer patches hold averaged fine values). */
+static void h_restrict(orc_h *h, double **A)
+{
+    for (int l = h->L - 2; l >= 0; --l) {
+        int n = h->n[l];
+        int64_t N = hN(h, l), Nf = hN(h, l + 1);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            int p[3];
+            cdecode(h->dim, n, i, p);
+            if (!h->act[l][i] || !covered(h, (const uint8_t *const *)h->act, l, p)) continue;
+            for (int f = 0; f < h->nv; ++f)
+                A[l][f * N + i] = restrict_cell(h->dim, h->n[l + 1], A[l + 1], f * Nf, p);
+        }
+    }
+}
+
+/* Ghost cells of every level l >= 1 by prediction from level l-1
+ * (Sec. 2.2: spatial interpolation at internal refinement boundaries; the
+ * interpolation is the MR prediction of Sec. 2.1). */
+static void h_ghost(orc_h *h, double **A)
+{
+    for (int l = 1; l < h->L; ++l) {
+        int n = h->n[l];
+        int64_t N = hN(h, l), Nc = hN(h, l - 1);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            int k[3], p[3], ch[3];
+            cdecode(h->dim, n, i, k);
+            if (!is_ghost(h, l, k)) continue;
+            for (int d = 0; d < 3; ++d) { p[d] = k[d] / 2; ch[d] = k[d] & 1; }
+            for (int f = 0; f < h->nv; ++f)
+                A[l][f * N + i] = predict_child(h->dim, h->n[l - 1], h->bc, A[l - 1], f * Nc, p, ch);
+        }
+    }
+}
+
+/* Same as h_ghost, but the coarse data is the linear time interpolation
+ * (1 - theta) A_old + theta A_new at level l-1 (Sec. 2.2, space-time
+ * interpolation with recursive time steps).  Only for level l. */
+static void h_ghost_time(orc_h *h, int l, double **A, double **Aold, double **Anew,
+                         double theta)
+{
+    int n = h->n[l], nc = h->n[l - 1];
+    int64_t N = hN(h, l), Nc = hN(h, l - 1);
+    double *tmp = (double *)malloc((size_t)(h->nv * Nc) * sizeof(double));
+    for (int64_t i = 0; i < h->nv * Nc; ++i)
+        tmp[i] = (1.0 - theta) * Aold[l - 1][i] + theta * Anew[l - 1][i];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int k[3], p[3], ch[3];
+        cdecode(h->dim, n, i, k);
+        if (!is_ghost(h, l, k)) continue;
+        for (int d = 0; d < 3; ++d) { p[d] = k[d] / 2; ch[d] = k[d] & 1; }
+        for (int f = 0; f < h->nv; ++f)
+            A[l][f * N + i] = predict_child(h->dim, nc, h->bc, tmp, f * Nc, p, ch);
+    }
+    free(tmp);
+}
+
+void orc_h_restrict(orc_h *h) { h_restrict(h, h->Q); }
+void orc_h_ghost(orc_h *h) { h_ghost(h, h->Q); }
+
+/* ---- the finite-volume update ---- */
+
+/* Flux across the face between coarse cell p (level l) and its covered
+ * neighbour on side s (+1 / -1) of axis dn: the mean of the 2^(d-1) level
+ * l+1 fluxes along that face, computed from level l+1 data (the virtual
+ * leaves of Sec. 2.1, which keep the flux balance between levels
+ * conservative). */
+static void flux_fine_mean(const orc_h *h, int l, double **src, int dn,
+                           const int *p, int s, double *F)
+{
+    int dim = h->dim, nf = h->n[l + 1], nv = h->nv;
+    int t1 = dn == 0 ? 1 : 0, t2 = dn == 2 ? 1 : 2;
+    int base[3] = {2 * p[0], 2 * p[1], dim == 3 ? 2 * p[2] : 0};
+    base[dn] = s > 0 ? 2 * p[dn] + 1 : 2 * p[dn] - 1;
+    if (dim == 2) {
+        double Fa[NVMAX], Fb[NVMAX];
+        int c0[3] = {base[0], base[1], 0}, c1[3] = {base[0], base[1], 0};
+        c1[t1] += 1;
+        face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c0, Fa);
+        face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c1, Fb);
+        for (int f = 0; f < nv; ++f) F[f] = 0.5 * (Fa[f] + Fb[f]);
+        return;
+    }
+    double F00[NVMAX], F10[NVMAX], F01[NVMAX], F11[NVMAX];
+    int c00[3] = {base[0], base[1], base[2]};
+    int c10[3] = {base[0], base[1], base[2]};
+    int c01[3] = {base[0], base[1], base[2]};
+    int c11[3] = {base[0], base[1], base[2]};
+    c10[t1] += 1; c01[t2] += 1; c11[t1] += 1; c11[t2] += 1;
+    face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c00, F00);
+    face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c10, F10);
+    face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c01, F01);
+    face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c11, F11);
+    for (int f = 0; f < nv; ++f) F[f] = 0.25 * ((F00[f] + F10[f]) + (F01[f] + F11[f]));
+}
+
+/* One explicit stage on every leaf of level l:
+ *   out = base - lam * ((dF_1 + dF_2) + dF_3),  dF_d = F_{+1/2} - F_{-1/2},
+ * the semi-discrete form dQ/dt = -F(Q) of Sec. 2 with fluxes from src.
+ * A face next to a covered cell takes the fine-flux mean (flux_fine_mean). */
+static void h_fv_level(orc_h *h, int l, double **src, double **base,
+                       double **out, double lam)
+{
+    int dim = h->dim, n = h->n[l], nv = h->nv;
+    int64_t N = hN(h, l);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < N; ++i) {
+        int p[3];
+        cdecode(dim, n, i, p);
+        if (!is_leaf(h, l, p)) continue;
+        double dF[3][NVMAX];
+        for (int d = 0; d < dim; ++d) {
+            double Fhi[NVMAX], Flo[NVMAX];
+            int nb[3] = {p[0], p[1], p[2]};
+            nb[d] = bcmap(p[d] + 1, n, h->bc);
+            if (covered(h, (const uint8_t *const *)h->act, l, nb))
+                flux_fine_mean(h, l, src, d, p, +1, Fhi);
+            else
+                face_flux(dim, n, h->bc, h->g, src[l], d, p, Fhi);
+            nb[d] = bcmap(p[d] - 1, n, h->bc);
+            if (covered(h, (const uint8_t *const *)h->act, l, nb)) {
+                flux_fine_mean(h, l, src, d, p, -1, Flo);
+            } else {
+                int lc[3] = {p[0], p[1], p[2]};
+                lc[d] = p[d] - 1;
+                face_flux(dim, n, h->bc, h->g, src[l], d, lc, Flo);
+            }
+            for (int f = 0; f < nv; ++f) dF[d][f] = Fhi[f] - Flo[f];
+        }
+        for (int f = 0; f < nv; ++f) {
+            double R = dF[0][f] + dF[1][f];
+            if (dim == 3) R = R + dF[2][f];
+            out[l][f * N + i] = base[l][f * N + i] - lam * R;
+        }
+    }
+}
+
+/* CFL time step over all leaves: dt = min over levels of
+ * cfl dx_l / max_leaves sum_d (|v_d| + c), clipped to reach t_end. */
+double orc_h_cfl(orc_h *h, double cfl, double t, double t_end, double *smax_out)
+{
+    int dim = h->dim;
+    double dt = INFINITY;
+    for (int l = 0; l < h->L; ++l) {
+        int n = h->n[l];
+        int64_t N = hN(h, l);
+        double smax = 0.0;
+        int any = 0;
+        for (int64_t i = 0; i < N; ++i) {
+            int p[3];
+            cdecode(dim, n, i, p);
+            if (!is_leaf(h, l, p)) continue;
+            double q[NVMAX], w[NVMAX];
+            for (int f = 0; f < h->nv; ++f) q[f] = h->Q[l][f * N + i];
+            cons2prim(dim, h->g, q, w);
+            double c = sqrt((h->g * w[dim + 1]) / w[0]);
+            double S = 0.0;
+            for (int d = 0; d < dim; ++d) S = S + (fabs(w[1 + d]) + c);
+            if (S > smax) smax = S;
+            any = 1;
+        }
+        if (smax_out) smax_out[l] = smax;
+        if (any) {
+            double dtl = (cfl * h->dx[l]) / smax;
+            if (dtl < dt) dt = dtl;
+        }
+    }
+    if (dt > t_end - t) dt = t_end - t;
+    return dt;
+}
+
+/* Conserved totals sum over leaves of Q_f |cell|, with Neumaier's
+ * compensated summation. */
+void orc_h_totals(orc_h *h, double *tot)
+{
+    int dim = h->dim;
+    for (int f = 0; f < h->nv; ++f) {
+        double s = 0.0, comp = 0.0;
+        for (int l = 0; l < h->L; ++l) {
+            int n = h->n[l];
+            int64_t N = hN(h, l);
+            double vol = dim == 2 ? h->dx[l] * h->dx[l] : h->dx[l] * h->dx[l] * h->dx[l];
+            for (int64_t i = 0; i < N; ++i) {
+                int p[3];
+                cdecode(dim, n, i, p);
+                if (!is_leaf(h, l, p)) continue;
+                double x = h->Q[l][f * N + i] * vol;
+                double t = s + x;
+                if (fabs(s) >= fabs(x)) comp += (s - t) + x;
+                else comp += (x - t) + s;
+                s = t;
+            }
+        }
+        tot[f] = s + comp;
+    }
+}
+
+void orc_h_counts(orc_h *h, int64_t *leaves, int64_t *active)
+{
+    for (int l = 0; l < h->L; ++l) {
+        int n = h->n[l];
+        int64_t N = hN(h, l), nl = 0, na = 0;
+        for (int64_t i = 0; i < N; ++i) {
+            int p[3];
+            cdecode(h->dim, n, i, p);
+            if (h->act[l][i]) ++na;
+            if (is_leaf(h, l, p)) ++nl;
+        }
+        leaves[l] = nl;
+        active[l] = na;
+    }
+}
+
+/* ---- MR analysis, thresholding, closure and tiling ---- */
+
+/* Details of every refined level-l cell: the largest magnitude of the
+ * prediction error of its children's densities (Sec. 2.1: details are the
+ * prediction errors between consecutive levels).  A detail is significant
+ * when it is not smaller than eps (hard thresholding; the same eps on every
+ * level). */
+static void h_details(orc_h *h)
+{
+    for (int l = 0; l < h->L - 1; ++l) {
+        int n = h->n[l], nf = h->n[l + 1];
+        int64_t N = hN(h, l);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            int p[3];
+            cdecode(h->dim, n, i, p);
+            h->D[l][i] = 0.0;
+            h->sig[l][i] = 0;
+            if (!h->act[l][i] || !covered(h, (const uint8_t *const *)h->act, l, p)) continue;
+            double Dm = 0.0;
+            int nch = 1 << h->dim;
+            for (int k = 0; k < nch; ++k) {
+                int ch[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
+                int c[3] = {2 * p[0] + ch[0], 2 * p[1] + ch[1], h->dim == 3 ? 2 * p[2] + ch[2] : 0};
+                double rho = h->Q[l + 1][cidx(nf, c)];
+                double pr = predict_child(h->dim, n, h->bc, h->Q[l], 0, p, ch);
+                double dd = fabs(rho - pr);
+                if (dd > Dm) Dm = dd;
+            }
+            h->D[l][i] = Dm;
+            h->sig[l][i] = Dm >= h->eps;
+        }
+    }
+}
+
+/* raw refinement flag of level-l cell p (l <= L-2): keep cells with
+ * significant details, and refine significant cells by one more level
+ * (Sec. 2.1, refinement: the mesh is refined by one level before the
+ * evolution). */
+static int raw_flag(const orc_h *h, int l, const int *p)
+{
+    int n = h->n[l];
+    if (h->sig[l][cidx(n, p)]) return 1;
+    if (l >= 1) {
+        int q[3] = {p[0] / 2, p[1] / 2, p[2] / 2};
+        if (h->sig[l - 1][cidx(h->n[l - 1], q)]) return 1;
+    }
+    return 0;
+}
+
+/* Final flags of level l (decide level l+1 of the new hierarchy):
+ *  1. raw flags dilated by one cell (buffer layer, Sec. 2.2; gradedness,
+ *     Sec. 2.1);
+ *  2. nesting: level-l+1 cells within two cells of a level-l+1 cell covered
+ *     by the new level l+2 must exist, so their parents are flagged. */
+static void h_flags(orc_h *h, int l)
+{
+    int dim = h->dim, n = h->n[l], nf = h->n[l + 1];
+    int64_t N = hN(h, l);
+    int r3 = dim == 3 ? 1 : 0;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int p[3];
+        cdecode(dim, n, i, p);
+        int fl = 0;
+        for (int dz = -r3; dz <= r3 && !fl; ++dz)
+            for (int dy = -1; dy <= 1 && !fl; ++dy)
+                for (int dx = -1; dx <= 1 && !fl; ++dx) {
+                    int q[3] = {bcmap(p[0] + dx, n, h->bc), bcmap(p[1] + dy, n, h->bc),
+                                dim == 3 ? bcmap(p[2] + dz, n, h->bc) : 0};
+                    if (raw_flag(h, l, q)) fl = 1;
+                }
+        if (!fl && l + 2 < h->L) {
+            /* children span 2p .. 2p+1; cells within 2 of them: 2p-2 .. 2p+3 */
+            int z0 = dim == 3 ? -2 : 0, z1 = dim == 3 ? 3 : 0;
+            for (int dz = z0; dz <= z1 && !fl; ++dz)
+                for (int dy = -2; dy <= 3 && !fl; ++dy)
+                    for (int dx = -2; dx <= 3 && !fl; ++dx) {
+                        int q[3] = {bcmap(2 * p[0] + dx, nf, h->bc), bcmap(2 * p[1] + dy, nf, h->bc),
+                                    dim == 3 ? bcmap(2 * p[2] + dz, nf, h->bc) : 0};
+                        if (covered(h, (const uint8_t *const *)h->nact, l + 1, q)) fl = 1;
+                    }
+        }
+        h->flag[l][i] = (uint8_t)fl;
+    }
+}
+
+static void emit_patch(orc_h *h, int lvl, const int *o, int S)
+{
+    if (h->npatch == h->cappatch) {
+        h->cappatch = h->cappatch ? 2 * h->cappatch : 256;
+        h->patches = (orc_patch *)realloc(h->patches, (size_t)h->cappatch * sizeof(orc_patch));
+    }
+    orc_patch *P = &h->patches[h->npatch++];
+    P->lvl = lvl;
+    P->o[0] = o[0]; P->o[1] = o[1]; P->o[2] = o[2];
+    P->size = S;
+    int nf = h->n[lvl];
+    int z1 = h->dim == 3 ? S : 1;
+    for (int z = 0; z < z1; ++z)
+        for (int y = 0; y < S; ++y)
+            for (int x = 0; x < S; ++x) {
+                int c[3] = {o[0] + x, o[1] + y, h->dim == 3 ? o[2] + z : 0};
+                h->nact[lvl][cidx(nf, c)] = 1;
+            }
+}
+
+/* Patch generation for level l+1 from the flags of level l (stands in for
+ * the clustering of Sec. 2.2, same efficiency rule): an aligned block of
+ * S^d level-(l+1) cells whose parents include flagged ones becomes a patch
+ * when the flagged fraction reaches eta or S is the smallest patch size;
+ * otherwise it is split into its 2^d half-size blocks. */
+static void tile_block(orc_h *h, int l, const int *o, int S)
+{
+    int dim = h->dim, n = h->n[l], hs = S / 2;
+    int64_t cnt = 0, cells = dim == 2 ? (int64_t)hs * hs : (int64_t)hs * hs * hs;
+    int z1 = dim == 3 ? hs : 1;
+    for (int z = 0; z < z1; ++z)
+        for (int y = 0; y < hs; ++y)
+            for (int x = 0; x < hs; ++x) {
+                int c[3] = {o[0] / 2 + x, o[1] / 2 + y, dim == 3 ? o[2] / 2 + z : 0};
+                cnt += h->flag[l][cidx(n, c)];
+            }
+    if (cnt == 0) return;
+    if (S == h->pmin || (double)cnt >= h->eta * (double)cells) {
+        emit_patch(h, l + 1, o, S);
+        return;
+    }
+    int nch = 1 << dim;
+    for (int k = 0; k < nch; ++k) {
+        int oc[3] = {o[0] + hs * (k & 1), o[1] + hs * ((k >> 1) & 1), dim == 3 ? o[2] + hs * ((k >> 2) & 1) : 0};
+        tile_block(h, l, oc, hs);
+    }
+}
+
+/* Tile level l's flags into patches of level l+1; blocks of size pmax are
+ * visited in Morton (Z) order of their block coordinates. */
+static void h_tile(orc_h *h, int l)
+{
+    int dim = h->dim, nb = h->n[l + 1] / h->pmax;
+    int64_t nbt = dim == 2 ? (int64_t)nb * nb : (int64_t)nb * nb * nb;
+    memset(h->nact[l + 1], 0, (size_t)hN(h, l + 1));
+    /* Morton codes range over the next power of two of nb per axis */
+    int bits = 0;
+    while ((1 << bits) < nb) ++bits;
+    int64_t ncode = (int64_t)1 << (bits * dim);
+    int64_t seen = 0;
+    for (int64_t m = 0; m < ncode && seen < nbt; ++m) {
+        int b[3] = {0, 0, 0};
+        for (int k = 0; k < bits; ++k)
+            for (int d = 0; d < dim; ++d)
+                b[d] |= (int)((m >> (k * dim + d)) & 1) << k;
+        if (b[0] >= nb || b[1] >= nb || b[2] >= nb) continue;
+        ++seen;
+        int o[3] = {b[0] * h->pmax, b[1] * h->pmax, b[2] * h->pmax};
+        tile_block(h, l, o, h->pmax);
+    }
+}
+
+/* Build the new hierarchy (flags, closure and tiling from the finest level
+ * down, Sec. 2.2 Remesh), then predict newly created cells from the next
+ * coarser level (coarse to fine) and keep the data of cells that stay. */
+static void h_regrid(orc_h *h, int prolong)
+{
+    h->npatch = 0;
+    h_details(h);
+    memset(h->nact[0], 1, (size_t)hN(h, 0));
+    for (int l = h->L - 2; l >= 0; --l) {
+        h_flags(h, l);
+        h_tile(h, l);
+    }
+    /* patches were emitted finest level first; order them by level */
+    if (h->npatch > 1) {
+        orc_patch *tmp = (orc_patch *)malloc((size_t)h->npatch * sizeof(orc_patch));
+        int k = 0;
+        for (int lv = 1; lv < h->L; ++lv)
+            for (int i = 0; i < h->npatch; ++i)
+                if (h->patches[i].lvl == lv) tmp[k++] = h->patches[i];
+        memcpy(h->patches, tmp, (size_t)h->npatch * sizeof(orc_patch));
+        free(tmp);
+    }
+    if (prolong) {
+        for (int l = 1; l < h->L; ++l) {
+            int n = h->n[l];
+            int64_t N = hN(h, l), Nc = hN(h, l - 1);
+#pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < N; ++i) {
+                if (!h->nact[l][i] || h->act[l][i]) continue;
+                int k[3], p[3], ch[3];
+                cdecode(h->dim, n, i, k);
+                for (int d = 0; d < 3; ++d) { p[d] = k[d] / 2; ch[d] = k[d] & 1; }
+                for (int f = 0; f < h->nv; ++f)
+                    h->Q[l][f * N + i] = predict_child(h->dim, h->n[l - 1], h->bc, h->Q[l - 1], f * Nc, p, ch);
+            }
+            /* level l+1 predicts from level l with the new activity of l */
+            memcpy(h->act[l], h->nact[l], (size_t)N);
+        }
+    } else {
+        for (int l = 1; l < h->L; ++l) memcpy(h->act[l], h->nact[l], (size_t)hN(h, l));
+    }
+}
+
+/* Initialise the hierarchy from the finest-level data already written into
+ * level L-1: restrict it down through every level, analyse every level with
+ * all cells present, flag, close and tile; every patch keeps the restricted
+ * initial data; then fill ghost cells. */
+void orc_h_init(orc_h *h)
+{
+    for (int l = h->L - 2; l >= 0; --l) orc_restrict(h->dim, h->nv, h->n[l], h->Q[l + 1], h->Q[l]);
+    for (int l = 0; l < h->L; ++l) memset(h->act[l], 1, (size_t)hN(h, l));
+    if (h->L > 1) h_regrid(h, 0);
+    h_ghost(h, h->Q);
+}
+
+/* MR analysis + thresholding + closure + tiling + prediction of new cells
+ * + ghost fill: the coarsening / refinement half of the MR cycle. */
+void orc_h_regrid(orc_h *h)
+{
+    if (h->L > 1) h_regrid(h, 1);
+    h_ghost(h, h->Q);
+}
+
+void orc_h_analyse(orc_h *h) { h_details(h); }
+
+int orc_h_npatch(const orc_h *h) { return h->npatch; }
+
+/* patches as int32 rows {level, ox, oy, oz, size} */
+void orc_h_patches(const orc_h *h, int32_t *out)
+{
+    for (int i = 0; i < h->npatch; ++i) {
+        out[5 * i + 0] = h->patches[i].lvl;
+        out[5 * i + 1] = h->patches[i].o[0];
+        out[5 * i + 2] = h->patches[i].o[1];
+        out[5 * i + 3] = h->patches[i].o[2];
+        out[5 * i + 4] = h->patches[i].size;
+    }
+}
+
+/* One explicit stage on every level (FV on leaves, projection onto covered
+ * cells).  Ghost cells are filled separately. */
+static void h_stage(orc_h *h, double **src, double **out, double dt, double fac)
+{
+    for (int l = 0; l < h->L; ++l) {
+        double lam = (dt * fac) / h->dx[l];
+        h_fv_level(h, l, src, h->Q, out, lam);
+    }
+    h_restrict(h, out);
+}
+
+void orc_h_stage(orc_h *h, int stage, double dt)
+{
+    if (stage == 1) {
+        h_stage(h, h->Q, h->Qs, dt, 0.5);
+        h_ghost(h, h->Qs);
+    } else {
+        h_stage(h, h->Qs, h->Q, dt, 1.0);
+        h_ghost(h, h->Q);
+    }
+}
+
+/* One global time step (Sec. 2: explicit second-order midpoint rule):
+ *   Q* = Q^n - (dt/2) F(Q^n),   Q^{n+1} = Q^n - dt F(Q*),
+ * on the leaves of every level, then the MR coarsening / refinement.
+ * Returns dt.  When regrid is 0 the hierarchy is left as it is. */
+double orc_h_step(orc_h *h, double cfl, double t, double t_end, int regrid)
+{
+    double dt = orc_h_cfl(h, cfl, t, t_end, NULL);
+    h_stage(h, h->Q, h->Qs, dt, 0.5);
+    h_ghost(h, h->Qs);
+    h_stage(h, h->Qs, h->Q, dt, 1.0);
+    if (regrid && h->L > 1) h_regrid(h, 1);
+    h_ghost(h, h->Q);
+    return dt;
+}
+
+/* One step with a caller-given dt, no regrid (tests). */
+void orc_h_step_fixed(orc_h *h, double dt)
+{
+    h_stage(h, h->Q, h->Qs, dt, 0.5);
+    h_ghost(h, h->Qs);
+    h_stage(h, h->Qs, h->Q, dt, 1.0);
+    h_ghost(h, h->Q);
+}
+
+/* ------------------------------------------------------------------------ */
+/* initial data on the finest level (cell-centre sampling)                  */
+/* ------------------------------------------------------------------------ */
+
+/* 2D four-quadrant Riemann problem (Sec. 4.1, Table 1 layout): quadrant I
+ * x>x0,y>y0; II x<x0,y>y0; III x<x0,y<y0; IV x>x0,y<y0.  prim[4][4] holds
+ * (rho, v1, v2, p) per quadrant I..IV. */
+void orc_init_quadrant(int n, double lo, double hi, double g, double x0, double y0,
+                       const double *prim, double *Q)
+{
+    double dx = (hi - lo) / (double)n;
+    int64_t N = (int64_t)n * n;
+    for (int y = 0; y < n; ++y)
+        for (int x = 0; x < n; ++x) {
+            double xc = lo + ((double)x + 0.5) * dx, yc = lo + ((double)y + 0.5) * dx;
+            int qd;
+            if (xc > x0) qd = yc > y0 ? 0 : 3;
+            else qd = yc > y0 ? 1 : 2;
+            double q[4];
+            prim2cons(2, g, prim + 4 * qd, q);
+            for (int f = 0; f < 4; ++f) Q[f * N + x + (int64_t)n * y] = q[f];
+        }
+}
+
+/* 3D ellipsoid (Sec. 4.2): rotated coordinates
+ *   x1r = x cos(th) - y sin(th), s = x sin(th) + y cos(th),
+ *   x2r = s cos(ph) - z sin(ph), x3r = s sin(ph) + z cos(ph),
+ * r^2 = (x1r/a)^2 + (x2r/b)^2 + (x3r/c)^2; inside iff r^2 < rc^2.
+ * e[11] = {a, b, c, cos th, sin th, cos ph, sin ph, rc, 0, 0, 0};
+ * st[4] = {rho_in, p_in, rho_out, p_out}; velocity zero. */
+void orc_init_ellipsoid(int n, double lo, double hi, double g, const double *e,
+                        const double *st, double *Q)
+{
+    double dx = (hi - lo) / (double)n;
+    int64_t N = (int64_t)n * n * n;
+    double rc2 = e[7] * e[7];
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < n; ++x) {
+                double xc = lo + ((double)x + 0.5) * dx;
+                double yc = lo + ((double)y + 0.5) * dx;
+                double zc = lo + ((double)z + 0.5) * dx;
+                double x1 = xc * e[3] - yc * e[4];
+                double s = xc * e[4] + yc * e[3];
+                double x2 = s * e[5] - zc * e[6];
+                double x3 = s * e[6] + zc * e[5];
+                double r2 = ((x1 / e[0]) * (x1 / e[0]) + (x2 / e[1]) * (x2 / e[1])) + (x3 / e[2]) * (x3 / e[2]);
+                int in = r2 < rc2;
+                double w[5] = {in ? st[0] : st[2], 0.0, 0.0, 0.0, in ? st[1] : st[3]};
+                double q[5];
+                prim2cons(3, g, w, q);
+                int64_t id = x + (int64_t)n * (y + (int64_t)n * z);
+                for (int f = 0; f < 5; ++f) Q[f * N + id] = q[f];
+            }
+}
+
+/* 1D Riemann problem along axis ax: left state for x_ax < x0, right state
+ * otherwise; lr[6] = {rho_L, u_L, p_L, rho_R, u_R, p_R}, u along ax. */
+void orc_init_riemann1d(int dim, int n, double lo, double hi, double g, int ax,
+                        double x0, const double *lr, double *Q)
+{
+    double dx = (hi - lo) / (double)n;
+    int64_t N = ncells(dim, n);
+    int nv = dim + 2;
+    for (int64_t i = 0; i < N; ++i) {
+        int c[3];
+        cdecode(dim, n, i, c);
+        double xc = lo + ((double)c[ax] + 0.5) * dx;
+        const double *s = xc < x0 ? lr : lr + 3;
+        double w[5] = {s[0], 0.0, 0.0, 0.0, 0.0}, q[5];
+        w[1 + ax] = s[1];
+        w[dim + 1] = s[2];
+        prim2cons(dim, g, w, q);
+        for (int f = 0; f < nv; ++f) Q[f * N + i] = q[f];
+    }
+}

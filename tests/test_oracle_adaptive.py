@@ -1,0 +1,281 @@
+"""Pins of the oracle's adaptive (MR-flagged block-patch) hierarchy.
+
+Special cases that reduce to the uniform scheme, invariants of the
+hierarchy (alignment, nesting, gradedness, flag coverage, the tiling rule),
+conservation, free-stream preservation, threshold monotonicity, and the
+paper's accuracy-perturbation measure against a uniform finest-grid run.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact_riemann as er
+from paper_1603_05211_amd import inputs
+
+G = 1.4
+
+
+def coarsen_mask(m, dim):
+    return m[0::2, 0::2] if dim == 2 else m[0::2, 0::2, 0::2]
+
+
+def dilate(m, r, periodic=False):
+    out = m.copy()
+    dim = m.ndim
+    n = m.shape[0]
+    idx = np.arange(n)
+    for ax in range(dim):
+        acc = np.zeros_like(out)
+        for s in range(-r, r + 1):
+            j = (idx + s) % n if periodic else np.clip(idx + s, 0, n - 1)
+            acc |= np.take(out, j, axis=ax)
+        out = acc
+    return out
+
+
+def check_hierarchy(h, periodic=False):
+    """Structural invariants of the hierarchy after init or regrid."""
+    dim, L = h.dim, h.L
+    P = h.patches()
+    acts = [h.active(l).astype(bool) for l in range(L)]
+    assert acts[0].all()
+    # patches: aligned, sizes in {pmin..pmax} powers of two, disjoint, union = active
+    for l in range(1, L):
+        cover = np.zeros_like(acts[l], dtype=np.int32)
+        for lv, ox, oy, oz, S in P:
+            if lv != l:
+                continue
+            assert S in (8, 16, 32) and ox % S == 0 and oy % S == 0 and oz % S == 0
+            sl = (slice(oy, oy + S), slice(ox, ox + S)) if dim == 2 else \
+                (slice(oz, oz + S), slice(oy, oy + S), slice(ox, ox + S))
+            cover[sl] += 1
+        assert cover.max() <= 1
+        assert np.array_equal(cover.astype(bool), acts[l])
+    # proper nesting: level-l cells within 2 of the parents of level l+1 exist
+    for l in range(0, L - 1):
+        par = coarsen_mask(acts[l + 1], dim)
+        if l >= 1:
+            need = dilate(par, 2, periodic)
+            assert not (need & ~acts[l]).any(), l
+    # graded: a leaf's face neighbours are leaves of the same level, or
+    # covered (finer leaves), or lie on the next coarser level
+    return P, acts
+
+
+def leaf_level_map(h):
+    """Level of the leaf covering each finest cell."""
+    dim, L = h.dim, h.L
+    nF = h.n(L - 1)
+    out = np.full((nF,) * dim, -1)
+    for l in range(L):
+        leaf = h.leaf_mask(l)
+        k = 2 ** (L - 1 - l)
+        up = leaf
+        for ax in range(dim):
+            up = np.repeat(up, k, axis=ax)
+        out[up] = l
+    return out
+
+
+def test_init_hierarchy_invariants(orc):
+    for seed in (0, 1, 2):
+        prim = inputs.quadrant_states(seed)
+        h = orc.Hierarchy(2, 4, 32, eps=1e-3)
+        h.init_finest(orc.init_quadrant(256, G, prim))
+        P, acts = check_hierarchy(h)
+        lm = leaf_level_map(h)
+        assert (lm >= 0).all()  # leaves tile the domain exactly once
+        # gradedness: neighbouring leaves differ by at most one level
+        for ax in range(2):
+            d = np.abs(np.diff(lm, axis=ax))
+            assert d.max() <= 1
+
+
+def test_tiling_rule_and_flag_coverage(orc):
+    """Every flagged cell's children are in a patch; every patch reached the
+    efficiency eta (or has the smallest size); every block that was split
+    (the parent block of a patch) fell short of eta."""
+    prim = inputs.quadrant_states(5)
+    h = orc.Hierarchy(2, 4, 32, eps=1e-3, eta=0.8)
+    h.init_finest(orc.init_quadrant(256, G, prim))
+    for _ in range(3):
+        h.step(0.45)
+    P, acts = check_hierarchy(h)
+    for l in range(h.L - 1):
+        F = h.flags(l).astype(bool)
+        child_cov = coarsen_mask(acts[l + 1], 2)
+        assert not (F & ~child_cov).any()
+        for lv, ox, oy, oz, S in P:
+            if lv != l + 1:
+                continue
+            fill = F[oy // 2:(oy + S) // 2, ox // 2:(ox + S) // 2].mean()
+            assert fill > 0
+            assert S == 8 or fill >= 0.8
+            if S < 32:
+                px, py = ox - ox % (2 * S), oy - oy % (2 * S)
+                pfill = F[py // 2:(py + 2 * S) // 2, px // 2:(px + 2 * S) // 2].mean()
+                assert pfill < 0.8
+        # the flags contain the raw flags dilated by one cell
+        D = h.details(l)
+        sig = D >= h.eps
+        assert not (sig & ~F).any()
+
+
+def test_flags_follow_details(orc):
+    """Raw flags: significant details (D >= eps) and their children's parents
+    (preventive refinement).  Checked on the initial analysis, where every
+    detail is computed from the full finest data."""
+    prim = inputs.quadrant_states(1)
+    h = orc.Hierarchy(2, 4, 32, eps=2e-3)
+    Qf = orc.init_quadrant(256, G, prim)
+    h.init_finest(Qf)
+    # independent detail computation: restrict, predict, compare densities
+    lev = [None] * 4
+    lev[3] = Qf
+    for l in (2, 1, 0):
+        lev[l] = orc.restrict(2, lev[l + 1])
+    for l in range(3):
+        pred = orc.predict(2, lev[l])[0]
+        err = np.abs(lev[l + 1][0] - pred)
+        D = err.reshape(h.n(l), 2, h.n(l), 2).max(axis=(1, 3))
+        assert np.array_equal(D, h.details(l))
+        sig = D >= h.eps
+        raw = sig.copy()
+        if l >= 1:
+            Dp = (np.abs(lev[l][0] - orc.predict(2, lev[l - 1])[0])
+                  .reshape(h.n(l - 1), 2, h.n(l - 1), 2).max(axis=(1, 3)))
+            raw |= np.repeat(np.repeat(Dp >= h.eps, 2, 0), 2, 1)
+        F = h.flags(l).astype(bool)
+        assert not (dilate(raw, 1) & ~F).any()
+
+
+def test_threshold_monotone(orc):
+    prim = inputs.quadrant_states(2)
+    Qf = orc.init_quadrant(256, G, prim)
+    prev = None
+    for eps in (1e-4, 1e-3, 1e-2, 1e-1):
+        h = orc.Hierarchy(2, 4, 32, eps=eps)
+        h.init_finest(Qf)
+        acts = [h.active(l).astype(bool) for l in range(4)]
+        if prev is not None:
+            for a, b in zip(acts, prev):
+                assert not (a & ~b).any()
+        prev = acts
+    # constant data: no details, no patches
+    W = np.stack([np.full((256, 256), v) for v in (1.0, 0.2, 0.1, 1.0)])
+    h = orc.Hierarchy(2, 4, 32, eps=1e-12)
+    h.init_finest(orc.prim2cons(2, G, W))
+    assert len(h.patches()) == 0
+
+
+def test_eps_zero_equals_uniform_finest(orc):
+    """eps = 0 refines everywhere: leaves are exactly the finest grid and the
+    adaptive step reduces to the uniform scheme on it, bit for bit."""
+    prim = inputs.quadrant_states(4)
+    Qf = orc.init_quadrant(128, G, prim)
+    h = orc.Hierarchy(2, 3, 32, eps=0.0)
+    h.init_finest(Qf)
+    u = orc.Hierarchy(2, 1, 128)
+    u.init_finest(Qf)
+    for _ in range(8):
+        dta = h.step(0.45)
+        dtu = u.step(0.45)
+        assert dta == dtu
+    assert np.array_equal(h.level(2), u.level(0))
+
+
+def test_eps_huge_equals_uniform_coarse(orc):
+    prim = inputs.quadrant_states(4)
+    Qf = orc.init_quadrant(128, G, prim)
+    h = orc.Hierarchy(2, 3, 32, eps=1e30)
+    h.init_finest(Qf)
+    assert len(h.patches()) == 0
+    u = orc.Hierarchy(2, 1, 32)
+    u.init_finest(orc.restrict(2, orc.restrict(2, Qf)))
+    for _ in range(8):
+        assert h.step(0.45) == u.step(0.45)
+    assert np.array_equal(h.level(0), u.level(0))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_adaptive_conservation_periodic(orc, dim):
+    if dim == 2:
+        Qf = orc.init_quadrant(128, G, inputs.quadrant_states(6))
+        h = orc.Hierarchy(2, 3, 32, bc=orc.BC_PERIODIC, eps=1e-3)
+    else:
+        e = inputs.ellipsoid(6)
+        Qf = orc.init_ellipsoid(64, G, e.a, e.b, e.c, e.theta, e.phi, e.states)
+        h = orc.Hierarchy(3, 2, 32, bc=orc.BC_PERIODIC, lo=-1.0, hi=1.0, eps=1e-3)
+    h.init_finest(Qf)
+    check_hierarchy(h, periodic=True)
+    T0 = h.totals()
+    npatch = []
+    for _ in range(12):
+        h.step(0.4)
+        npatch.append(len(h.patches()))
+    check_hierarchy(h, periodic=True)
+    T1 = h.totals()
+    assert len(set(npatch)) > 1 or dim == 3  # the mesh adapts while conserving
+    assert np.all(np.abs(T1 - T0) <= 2e-13 * np.maximum(1.0, np.abs(T0))), (T0, T1)
+
+
+def test_adaptive_free_stream_bitwise(orc):
+    """Uniform state written onto a partially refined hierarchy stays
+    bit-exact: prediction and projection reproduce constants, fine-flux
+    means of equal fluxes are the flux itself."""
+    prim = inputs.quadrant_states(8)
+    h = orc.Hierarchy(2, 3, 32, eps=1e-3)
+    h.init_finest(orc.init_quadrant(128, G, prim))
+    assert len(h.patches()) > 0
+    w = np.array([0.8, 0.35, -0.25, 1.1])
+    q = orc.prim2cons(2, G, w.reshape(4, 1)).ravel()
+    for l in range(3):
+        h.level(l)[...] = q.reshape(4, 1, 1)
+    for _ in range(10):
+        h.step(0.45, regrid=False)
+    for l in range(3):
+        assert np.array_equal(h.level(l), np.broadcast_to(q.reshape(4, 1, 1), h.level(l).shape))
+
+
+def test_mr_reconstruction(orc):
+    """The composite (adaptive data projected up by prediction) reproduces
+    the finest data exactly when no detail is dropped (eps = 0), and within a
+    multiple of eps per level otherwise."""
+    x = (np.arange(128) + 0.5) / 128
+    X, Y = np.meshgrid(x, x)
+    rho = 1.0 + 0.3 * np.tanh((X + 0.5 * Y - 0.7) / 0.03)
+    W = np.stack([rho, 0.1 * np.ones_like(rho), -0.2 * np.ones_like(rho), np.ones_like(rho)])
+    Qf = orc.prim2cons(2, G, W)
+    h = orc.Hierarchy(2, 3, 32, eps=0.0)
+    h.init_finest(Qf)
+    assert np.array_equal(h.composite(), Qf)
+    for eps in (1e-3, 1e-2):
+        h = orc.Hierarchy(2, 3, 32, eps=eps)
+        h.init_finest(Qf)
+        err = np.abs(h.composite()[0] - Qf[0]).max()
+        assert err <= 4 * 3 * eps, (eps, err)
+
+
+def test_accuracy_perturbation_sod(orc):
+    """The paper's accuracy perturbation |L1_FV - L1_a| / L1_FV (Sec. 3) of
+    an adaptive Sod run against the uniform finest-grid run stays small."""
+    L_, R_ = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    n = 256
+    Qf = orc.init_riemann1d(2, n, G, 0, L_, R_)
+    t_end = 0.15
+    h = orc.Hierarchy(2, 4, 32, eps=1e-3)
+    h.init_finest(Qf)
+    while h.t < t_end:
+        h.step(0.45, t_end)
+    u = orc.Hierarchy(2, 1, n)
+    u.init_finest(Qf)
+    while u.t < t_end:
+        u.step(0.45, t_end)
+    ex, _, _ = er.cell_averages(L_, R_, n, t_end)
+    comp = h.composite()[0]
+    l1a = np.abs(comp - ex[None, :]).sum() / n ** 2
+    l1u = np.abs(u.level(0)[0] - ex[None, :]).sum() / n ** 2
+    leaves, _ = h.counts()
+    assert leaves.sum() < 0.5 * n * n  # it did adapt
+    assert abs(l1u - l1a) / l1u < 0.15, (l1u, l1a)
