@@ -1,0 +1,222 @@
+/*
+ * eu.h -- C-ABI of the MI355X (gfx950) adaptive finite-volume library for the
+ * compressible Euler equations (ideal gas, Cartesian 2D/3D), after
+ * Deiterding, Domingues, Gomes, Schneider, "Comparison of adaptive
+ * multiresolution and adaptive mesh refinement applied to simulations of the
+ * compressible Euler equations" (arXiv:1603.05211).
+ *
+ * Method (Sec. 2): cell averages Q of (rho, rho v, rho e) on nested Cartesian
+ * levels, dQ/dt = -F(Q) with a second-order MUSCL reconstruction in primitive
+ * variables, van Albada limiter, AUSM+ flux (Liou 1996) and the explicit
+ * midpoint rule (RK2).  Adaptivity (Sec. 2.1, 2.2): cell-average
+ * multiresolution analysis (projection = mean of children, third-order
+ * quadratic prediction), hard thresholding of the density details, one level
+ * of preventive refinement, a one-cell buffer, proper nesting, and block
+ * patches generated with the efficiency rule eta_tol.
+ *
+ * Conventions
+ *  - Every function returns an int status (EU_OK = 0); no exception and no
+ *    exit() crosses this boundary.  The text of the last error of a context
+ *    is available from eu_last_error().
+ *  - Device memory is owned by the caller.  eu_query_sizes() reports the
+ *    bytes of the two buffers the caller allocates (state, scratch); the
+ *    library carves everything it needs out of them and never allocates or
+ *    frees device memory itself.  The context owns only host metadata and
+ *    the HIP graphs it creates.
+ *  - Pointers are device pointers unless the name ends in _host.  A _host
+ *    output makes the call synchronise the context's stream.
+ *  - All work is enqueued on the stream given in eu_config.stream (a
+ *    hipStream_t; NULL = the legacy default stream).  A context is not
+ *    thread-safe; one context per stream.
+ *  - State layout (per level or instance): the d+2 conserved fields rho,
+ *    m_1..m_d, E stored one after another, each a dense n^d array with x
+ *    fastest; the element type is double (EU_FP64) or float (EU_FP32).
+ */
+#ifndef EU_H
+#define EU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+    EU_OK = 0,
+    EU_EINVAL = 1,    /* invalid argument or configuration                  */
+    EU_ENOMEM = 2,    /* a caller buffer is too small                        */
+    EU_EHIP = 3,      /* a HIP runtime call failed (text in eu_last_error)   */
+    EU_ENONPHYS = 4,  /* rho <= 0, p <= 0 or NaN met; sticky until cleared   */
+    EU_ESTATE = 5     /* call out of order (e.g. stepping before init)       */
+};
+
+enum { EU_FP64 = 0, EU_FP32 = 1 };               /* state / flux precision   */
+enum { EU_BC_TRANSMISSIVE = 0, EU_BC_PERIODIC = 1 };
+enum { EU_DT_GLOBAL = 0, EU_DT_LTS = 1 };        /* time stepping           */
+enum { EU_RESTRICT = 0, EU_PROLONG = 1, EU_GHOST = 2 }; /* eu_project modes */
+enum { EU_IC_QUADRANT = 0, EU_IC_ELLIPSOID = 1, EU_IC_RIEMANN1D = 2, EU_IC_UNIFORM = 3 };
+
+/* Problem size and method parameters (Sec. 2; Sec. 4 for the values used
+ * there).  All fields are read by eu_query_sizes / eu_create. */
+typedef struct {
+    int dim;             /* 2 or 3                                            */
+    int precision;       /* EU_FP64 | EU_FP32 (FP32 state and flux; the CFL
+                            reduction, conserved totals and detail threshold
+                            stay FP64)                                        */
+    double gamma;        /* ratio of specific heats (1.4)                     */
+    double lo, hi;       /* cubic domain [lo, hi]^d                           */
+    int n0;              /* cells per side of level 0 (power of two)          */
+    int levels;          /* number of levels L >= 1; level l has n0 2^l cells
+                            per side; 1 = uniform grid                        */
+    int bc;              /* EU_BC_TRANSMISSIVE (outflow) | EU_BC_PERIODIC      */
+    double cfl;          /* CFL number of eu_cfl_dt                           */
+    double t_end;        /* end time: the last step is clipped to reach it
+                            (INFINITY: never clipped)                         */
+    double eps;          /* MR threshold on density details (same on all
+                            levels)                                           */
+    double eta;          /* patch efficiency eta_tol (flagged / all cells)    */
+    int patch_min;       /* smallest patch side (must be 8)                   */
+    int patch_max;       /* largest patch side (8, 16, 32 or 64)              */
+    int time_mode;       /* EU_DT_GLOBAL | EU_DT_LTS                          */
+    int n_instances;     /* > 1: batch of independent uniform grids            */
+    const int32_t *inst_side_host; /* per-instance cells per side (multiples
+                            of 8), n_instances entries; NULL when 1 instance  */
+    void *stream;        /* hipStream_t                                       */
+} eu_config;
+
+/* Initial data (Sec. 4.1 four-quadrant Riemann problem, Sec. 4.2 ellipsoid,
+ * a 1D Riemann problem along one axis, or a uniform state).  Cell-centre
+ * sampling on the finest level. */
+typedef struct {
+    int kind;                /* EU_IC_*                                       */
+    double quad[4][4];       /* quadrants I..IV: rho, v1, v2, p               */
+    double x0, y0;           /* quadrant split point                          */
+    double ell[8];           /* a, b, c, cos th, sin th, cos ph, sin ph, r_c  */
+    double ell_states[4];    /* rho_in, p_in, rho_out, p_out                  */
+    double lr[6];            /* 1D Riemann: rho_L, u_L, p_L, rho_R, u_R, p_R  */
+    int axis;                /* 1D Riemann: axis of the velocity / split      */
+    double split;            /* 1D Riemann: split coordinate                  */
+    double uniform[5];       /* uniform primitive state rho, v..., p          */
+    const double *inst_quad_host; /* batch: n_instances x 16 quadrant states
+                                 (rows I..IV of rho, v1, v2, p), or NULL to use
+                                 quad for every instance                      */
+} eu_problem;
+
+typedef struct eu_ctx eu_ctx;
+
+/* Bytes of the state buffer and the scratch buffer for a configuration.
+ * Returns EU_EINVAL for an invalid configuration. */
+int eu_query_sizes(const eu_config *cfg, size_t *state_bytes, size_t *scratch_bytes);
+
+/* Create a context on caller buffers of at least the queried sizes (device
+ * memory, 256-byte aligned).  *out receives the context. */
+int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes,
+              void *scratch_dev, size_t scratch_bytes, eu_ctx **out);
+
+/* Destroy a context (host metadata and graphs only; caller buffers stay). */
+int eu_destroy(eu_ctx *ctx);
+
+/* Initial data (Sec. 4): write the finest level (every instance), project it
+ * down through all levels, analyse every level, flag, close and tile (the
+ * patches keep the projected data), fill ghost cells; t = 0. */
+int eu_init_state(eu_ctx *ctx, const eu_problem *p);
+
+/* Same as eu_init_state with arbitrary finest-level data of instance inst
+ * given as FP64 host values in the state layout (converted to the state
+ * precision).  For a batch, call once per instance. */
+int eu_set_finest(eu_ctx *ctx, int inst, const double *q_host);
+
+/* MR decomposition (Sec. 2.1): project every level onto the cells it covers
+ * (finest first) and compute, in FP64, the detail norm
+ * D = max over the 2^d children |rho - predicted rho| of every refined cell. */
+int eu_mr_decompose(eu_ctx *ctx);
+
+/* MR thresholding and new mesh (Sec. 2.1 refinement/coarsening, Sec. 2.2
+ * Remesh): significant details (D >= eps) keep their children; their
+ * children are refined one more level (preventive refinement); flags get a
+ * one-cell buffer and the nesting closure, finest level first, and are tiled
+ * into aligned patches with the efficiency rule.  Old cells keep their data;
+ * new cells are predicted from the next coarser level; ghost cells are
+ * filled.  nflag_host (nullable, levels entries) receives the number of
+ * flagged cells per level. */
+int eu_mr_flag(eu_ctx *ctx, int64_t *nflag_host);
+
+/* Inter-level transfer (Sec. 2.1 projection / prediction, Sec. 2.2 ghost
+ * cells): EU_RESTRICT projects every covered cell (finest first);
+ * EU_PROLONG predicts cells created by the last eu_mr_flag; EU_GHOST fills
+ * every ghost cell by prediction from the next coarser level. */
+int eu_project(eu_ctx *ctx, int mode);
+
+/* CFL time step (FP64): dt = min over levels cfl dx_l / max over leaves of
+ * sum_d (|v_d| + c), clipped to reach t_end, per instance for a batch.  The
+ * result stays on the device for eu_fv_step; dt_host (nullable) receives it
+ * (instance 0).  Detects non-physical leaves (EU_ENONPHYS at the next
+ * synchronising call). */
+int eu_cfl_dt(eu_ctx *ctx, double *dt_host);
+
+/* One explicit midpoint (RK2) step of every leaf with the device dt of the
+ * last eu_cfl_dt (Sec. 2): Q* = Q - dt/2 F(Q), Q <- Q - dt F(Q*), each
+ * stage followed by projection onto covered cells and ghost fill; faces
+ * between a leaf and a covered cell take the mean of the fine fluxes; t += dt.
+ * In EU_DT_LTS mode one call advances one level-0 step with the recursive
+ * level cycle (Sec. 2.2, Fig. 2). */
+int eu_fv_step(eu_ctx *ctx);
+
+/* One full time step: eu_cfl_dt, eu_fv_step and, if regrid != 0,
+ * eu_mr_decompose + eu_mr_flag. */
+int eu_step(eu_ctx *ctx, int regrid);
+
+/* nsteps calls of eu_step(ctx, 1) (or until t_end), replayed from one
+ * captured HIP graph when use_graph != 0.  steps_done_host (nullable)
+ * receives the number of steps taken. */
+int eu_advance(eu_ctx *ctx, int nsteps, int use_graph, int *steps_done_host);
+
+/* Conserved totals sum over leaves of Q_f |cell| in FP64 (fixed summation
+ * order), per instance: totals_host receives n_instances x (d+2) values. */
+int eu_conserved_totals(eu_ctx *ctx, double *totals_host);
+
+/* Copy one level (instance inst for a batch, level ignored) of the current
+ * state (which = 0) or the RK2 stage state (which = 1) to FP64 host memory
+ * in the state layout: (d+2) n^d values. */
+int eu_copy_level(eu_ctx *ctx, int inst, int level, int which, double *dst_host);
+
+/* Per-cell masks of a level (n^d bytes): patch membership (eu_get_active),
+ * final refinement flags (eu_get_flags, levels 0..L-2), FP64 details
+ * (eu_get_details, levels 0..L-2). */
+int eu_get_active(eu_ctx *ctx, int level, uint8_t *dst_host);
+int eu_get_flags(eu_ctx *ctx, int level, uint8_t *dst_host);
+int eu_get_details(eu_ctx *ctx, int level, double *dst_host);
+
+/* Patch table rows {level, ox, oy, oz, size} ordered by level, then Morton
+ * order of the enclosing patch_max block, then recursive split order.  At
+ * most cap rows are written; *npatch_host receives the total. */
+int eu_patch_table(eu_ctx *ctx, int32_t *dst_host, int cap, int *npatch_host);
+
+/* Leaf and active (patch) cell counts per level (levels entries each). */
+int eu_counters(eu_ctx *ctx, int64_t *leaves_host, int64_t *active_host);
+
+/* Leaf cells advanced and steps taken since initialisation (a leaf advanced
+ * one step of its level counts once; a batch counts every cell). */
+int eu_leaf_updates(eu_ctx *ctx, int64_t *updates_host, int *steps_host);
+
+/* Simulation time and last dt (instance 0). */
+int eu_time(eu_ctx *ctx, double *t_host, double *dt_host);
+
+/* Kernel timing with HIP events on the context's stream: when enabled,
+ * every finite-volume stage launch is bracketed by events; eu_kernel_time
+ * returns the summed milliseconds and the launch count since enabling. */
+int eu_profile(eu_ctx *ctx, int enable);
+int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
+
+/* Non-physical status: EU_OK or EU_ENONPHYS (synchronises). */
+int eu_status(eu_ctx *ctx);
+int eu_clear_status(eu_ctx *ctx);
+const char *eu_last_error(const eu_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EU_H */

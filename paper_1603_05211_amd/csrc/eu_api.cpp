@@ -1,0 +1,846 @@
+// eu_api.cpp -- host side of the C-ABI (include/eu.h): configuration
+// checks, carving of the caller's device buffers, the launch sequences of
+// the method's steps, HIP graph capture and replay, host copies.
+#include "../../include/eu.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "eu_internal.hpp"
+#include "eu_kset.hpp"
+
+using namespace eu;
+
+struct eu_ctx {
+    eu_config cfg;
+    std::vector<int32_t> sides;
+    const KSet *ks = nullptr;
+    View v{};
+    std::vector<Grid> grids;
+    hipStream_t stream = nullptr;
+    int L = 1, ngrid = 1, dim = 2, nv = 4, mode = MODE_HIER;
+    int64_t nbt = 0;            // blocks of all grids
+    int max_tiles = 0;
+    int ngroups = 1;
+    int64_t state_elems = 0;    // elements of one state array
+    bool initialized = false;
+    std::string err;
+    // graphs: [0] step with regrid, [1] step without
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    double prof_ms = 0.0;
+    int64_t prof_n = 0;
+};
+
+namespace {
+
+int set_err(eu_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return set_err((ctx), EU_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+int64_t ipow(int64_t b, int e)
+{
+    int64_t r = 1;
+    while (e--) r *= b;
+    return r;
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Layout of the two caller buffers.
+struct Layout {
+    int L, ngrid, dim, nv, mode;
+    std::vector<Grid> grids;
+    int64_t state_elems = 0;
+    int narrays = 2;
+    int64_t nbt = 0, ncoarse = 0, nslot = 0, max_tiles = 0, max_patch = 0;
+    int ngroups = 1;
+    std::vector<int64_t> pbase;
+    // scratch offsets
+    size_t o_grids, o_act, o_nact, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
+        o_pcnt, o_pbase, o_patches, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
+    size_t scratch = 0, state = 0;
+};
+
+int validate(const eu_config *c, std::string &why)
+{
+    if (!c) { why = "null config"; return EU_EINVAL; }
+    if (c->dim != 2 && c->dim != 3) { why = "dim must be 2 or 3"; return EU_EINVAL; }
+    if (c->precision != EU_FP64 && c->precision != EU_FP32) { why = "bad precision"; return EU_EINVAL; }
+    if (!(c->gamma > 1.0)) { why = "gamma must exceed 1"; return EU_EINVAL; }
+    if (!(c->hi > c->lo)) { why = "hi must exceed lo"; return EU_EINVAL; }
+    if (c->bc != EU_BC_TRANSMISSIVE && c->bc != EU_BC_PERIODIC) { why = "bad bc"; return EU_EINVAL; }
+    if (!(c->cfl > 0.0)) { why = "cfl must be positive"; return EU_EINVAL; }
+    if (c->time_mode != EU_DT_GLOBAL && c->time_mode != EU_DT_LTS) { why = "bad time_mode"; return EU_EINVAL; }
+    if (c->time_mode == EU_DT_LTS) { why = "local time stepping is not available in this build"; return EU_EINVAL; }
+    if (c->n_instances > 1) {
+        if (!c->inst_side_host) { why = "inst_side_host required for a batch"; return EU_EINVAL; }
+        if (c->levels != 1) { why = "a batch holds uniform grids (levels = 1)"; return EU_EINVAL; }
+        for (int i = 0; i < c->n_instances; ++i)
+            if (c->inst_side_host[i] < eu::BS || c->inst_side_host[i] % eu::BS) {
+                why = "instance sides must be positive multiples of 8";
+                return EU_EINVAL;
+            }
+        return EU_OK;
+    }
+    if (c->n_instances < 0) { why = "bad n_instances"; return EU_EINVAL; }
+    if (c->levels < 1 || c->levels > eu::MAXLEV) { why = "levels out of range"; return EU_EINVAL; }
+    if (!is_pow2(c->n0) || c->n0 < eu::BS) { why = "n0 must be a power of two >= 8"; return EU_EINVAL; }
+    if (c->levels > 1) {
+        if (c->patch_min != eu::BS) { why = "patch_min must be 8"; return EU_EINVAL; }
+        if (!is_pow2(c->patch_max) || c->patch_max < 8 || c->patch_max > 64) {
+            why = "patch_max must be 8, 16, 32 or 64";
+            return EU_EINVAL;
+        }
+        if ((2 * c->n0) % c->patch_max) { why = "2 n0 must be a multiple of patch_max"; return EU_EINVAL; }
+        if (!(c->eta > 0.0 && c->eta <= 1.0)) { why = "eta must lie in (0, 1]"; return EU_EINVAL; }
+        if (!(c->eps >= 0.0)) { why = "eps must be >= 0"; return EU_EINVAL; }
+    }
+    if (c->bc == EU_BC_PERIODIC && c->n0 < 4) { why = "periodic grids need n0 >= 4"; return EU_EINVAL; }
+    return EU_OK;
+}
+
+void make_layout(const eu_config *c, Layout &lay)
+{
+    const int D = c->dim;
+    lay.dim = D;
+    lay.nv = D + 2;
+    const bool batch = c->n_instances > 1;
+    lay.mode = batch ? MODE_BATCH : MODE_HIER;
+    lay.L = batch ? 1 : c->levels;
+    lay.ngrid = batch ? c->n_instances : c->levels;
+    lay.grids.resize(lay.ngrid);
+    int64_t off = 0, boff = 0, coff = 0;
+    for (int g = 0; g < lay.ngrid; ++g) {
+        Grid &G = lay.grids[g];
+        G.n = batch ? c->inst_side_host[g] : (c->n0 << g);
+        G.nb = G.n / eu::BS;
+        G.ncell = ipow(G.n, D);
+        G.off = off;
+        off += lay.nv * G.ncell;
+        G.boff = boff;
+        boff += ipow(G.nb, D);
+        G.lvl = batch ? 0 : g;
+        G.fine = (!batch && g + 1 < lay.L) ? g + 1 : -1;
+        G.coarse = (!batch && g >= 1) ? g - 1 : -1;
+        if (!batch && g < lay.L - 1) {
+            G.coff = coff;
+            coff += G.ncell;
+        } else {
+            G.coff = -1;
+        }
+        G.pad = 0;
+        G.dx = (c->hi - c->lo) / (double)G.n;
+    }
+    lay.state_elems = off;
+    lay.nbt = boff;
+    lay.ncoarse = coff;
+    lay.max_tiles = boff;
+    lay.pbase.assign(eu::MAXLEV + 1, 0);
+    int64_t ns = 0;
+    if (!batch && lay.L > 1) {
+        for (int l = 1; l < lay.L; ++l) {
+            lay.pbase[l] = ns;
+            ns += ipow(lay.grids[l].n / c->patch_max, D);
+        }
+    }
+    lay.nslot = ns;
+    const int64_t R = (!batch && lay.L > 1) ? c->patch_max / eu::BS : 1;
+    const int64_t nsub = ipow(R, D);
+    lay.max_patch = boff > 0 ? boff : 1;
+    lay.ngroups = batch ? lay.ngrid : 1;
+
+    const size_t es = c->precision == EU_FP64 ? 8 : 4;
+    lay.narrays = 2;
+    lay.state = lay.narrays * align256((size_t)lay.state_elems * es);
+
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes ? bytes : 1); return r; };
+    lay.o_grids = take(sizeof(Grid) * lay.ngrid);
+    lay.o_act = take(lay.nbt);
+    lay.o_nact = take(lay.nbt);
+    lay.o_sig = take(lay.ncoarse);
+    lay.o_flag = take(lay.ncoarse);
+    lay.o_D = take(8 * lay.ncoarse);
+    lay.o_leaf = take(sizeof(Tile) * lay.max_tiles);
+    lay.o_cov = take(sizeof(Tile) * lay.nbt);
+    lay.o_ghost = take(sizeof(Tile) * lay.nbt);
+    lay.o_fresh = take(sizeof(Tile) * lay.nbt);
+    lay.o_pslot = take(sizeof(int) * 5 * lay.nslot * nsub);
+    lay.o_pcnt = take(sizeof(int) * lay.nslot);
+    lay.o_pbase = take(sizeof(int64_t) * (eu::MAXLEV + 1));
+    lay.o_patches = take(sizeof(int) * 5 * lay.max_patch);
+    lay.o_meta = take(sizeof(Meta));
+    lay.o_smax = take(8 * lay.ngrid);
+    lay.o_dt = take(8 * lay.ngrid);
+    lay.o_t = take(8 * lay.ngrid);
+    lay.o_partial = take(8 * lay.nv * lay.max_tiles);
+    lay.o_totals = take(8 * lay.nv * lay.ngroups);
+    lay.o_goff = take(sizeof(int) * lay.ngroups);
+    lay.o_gcnt = take(sizeof(int) * lay.ngroups);
+    lay.scratch = o;
+}
+
+template <typename P> P *at(void *base, size_t off) { return (P *)((char *)base + off); }
+
+int sync_status(eu_ctx *c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int st = 0;
+    HIPCHK(c, hipMemcpy(&st, &c->v.meta->status, sizeof(int), hipMemcpyDeviceToHost));
+    if (st & 1) return set_err(c, EU_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN)");
+    return EU_OK;
+}
+
+int check_launch(eu_ctx *c)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_err(c, EU_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return EU_OK;
+}
+
+int64_t nblocks_grid(const eu_ctx *c, int g) { return ipow(c->grids[g].nb, c->dim); }
+
+// ---- launch sequences ------------------------------------------------------
+
+void seq_restrict(eu_ctx *c, int arr)
+{
+    for (int l = c->L - 2; l >= 0; --l)
+        c->ks->restrict_cov(c->v, arr, l, (int)nblocks_grid(c, l), c->stream);
+}
+
+void seq_ghost(eu_ctx *c, int arr)
+{
+    if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, (int)(c->nbt), c->stream);
+}
+
+void seq_cfl(eu_ctx *c)
+{
+    c->ks->cfl(c->v, c->max_tiles, c->stream);
+    launch_cfl_finalize(c->v, c->stream);
+}
+
+void prof_begin(eu_ctx *c, hipEvent_t *a)
+{
+    *a = nullptr;
+    if (!c->prof) return;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return; }
+    (void)hipEventRecord(e0, c->stream);
+    c->ev_pending.push_back({e0, e1});
+    *a = e1;
+}
+
+void prof_end(eu_ctx *c, hipEvent_t e1)
+{
+    if (e1) (void)hipEventRecord(e1, c->stream);
+}
+
+void seq_fv_step(eu_ctx *c, bool ghost_after)
+{
+    hipEvent_t e;
+    prof_begin(c, &e);
+    c->ks->fv_stage(c->v, 1, c->max_tiles, c->stream);
+    prof_end(c, e);
+    seq_restrict(c, ARR_QS);
+    seq_ghost(c, ARR_QS);
+    prof_begin(c, &e);
+    c->ks->fv_stage(c->v, 2, c->max_tiles, c->stream);
+    prof_end(c, e);
+    seq_restrict(c, ARR_Q);
+    if (ghost_after) seq_ghost(c, ARR_Q);
+    launch_time_advance(c->v, c->stream);
+}
+
+void seq_details(eu_ctx *c)
+{
+    for (int l = 0; l < c->L - 1; ++l) c->ks->details(c->v, l, c->grids[l].ncell, c->stream);
+}
+
+// flags, closure and tiling (finest first), lists, then optional prediction
+// of new cells (coarse to fine) and ghost fill.
+void seq_flag_tile(eu_ctx *c, bool prolong)
+{
+    launch_zero_meta_flags(c->v, c->stream);
+    for (int l = c->L - 2; l >= 0; --l) {
+        launch_flags(c->v, l, c->grids[l].ncell, c->stream);
+        const int nbp = c->grids[l + 1].n / c->cfg.patch_max;
+        launch_tile(c->v, l, (int)ipow(nbp, c->dim), c->stream);
+    }
+    launch_build_lists(c->v, c->nbt, c->stream);
+    if (prolong)
+        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 0, (int)nblocks_grid(c, l), c->stream);
+    seq_ghost(c, ARR_Q);
+}
+
+void seq_step(eu_ctx *c, bool regrid)
+{
+    seq_cfl(c);
+    const bool rg = regrid && c->L > 1;
+    seq_fv_step(c, !rg);
+    if (rg) {
+        seq_details(c);
+        seq_flag_tile(c, true);
+    }
+}
+
+int upload(eu_ctx *c, void *dst, const void *src, size_t bytes)
+{
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return EU_OK;
+}
+
+void drop_graphs(eu_ctx *c)
+{
+    for (auto &g : c->gexec)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
+int harvest_profile(eu_ctx *c)
+{
+    for (auto &p : c->ev_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second) == hipSuccess && hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) {
+            c->prof_ms += ms;
+            c->prof_n += 1;
+        }
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    c->ev_pending.clear();
+    return EU_OK;
+}
+
+InitArgs make_init(const eu_ctx *c, const eu_problem *p, int inst)
+{
+    InitArgs a{};
+    a.kind = p->kind;
+    a.axis = p->axis;
+    a.lo = c->cfg.lo;
+    a.hi = c->cfg.hi;
+    a.x0 = p->x0;
+    a.y0 = p->y0;
+    const double *q = (p->inst_quad_host && inst >= 0) ? p->inst_quad_host + 16 * inst : &p->quad[0][0];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) a.quad[i][j] = q[4 * i + j];
+    for (int i = 0; i < 8; ++i) a.ell[i] = p->ell[i];
+    for (int i = 0; i < 4; ++i) a.es[i] = p->ell_states[i];
+    for (int i = 0; i < 6; ++i) a.lr[i] = p->lr[i];
+    a.split = p->split;
+    for (int i = 0; i < 5; ++i) a.uni[i] = p->uniform[i];
+    return a;
+}
+
+// After the finest level holds initial data: project down, analyse every
+// level with all cells present, flag, tile; the patches keep the projected
+// data; ghost fill.  t = 0.
+int finish_init(eu_ctx *c)
+{
+    HIPCHK(c, hipMemsetAsync(c->v.meta, 0, sizeof(Meta), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->v.t, 0, 8 * c->ngrid, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->v.dt, 0, 8 * c->ngrid, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->v.smax, 0, 8 * c->ngrid, c->stream));
+    if (c->mode == MODE_HIER) {
+        for (int l = c->L - 2; l >= 0; --l)
+            c->ks->restrict_full(c->v, ARR_Q, l, c->grids[l].ncell, c->stream);
+        launch_fill_u8(c->v.act, c->nbt, 1, c->stream);
+        launch_fill_u8(c->v.nact, c->nbt, 1, c->stream);
+        seq_details(c);
+        seq_flag_tile(c, false);
+    } else {
+        // batch: every block of every instance is a leaf; the lists are static
+        std::vector<Tile> leaf;
+        std::vector<int> goff(c->ngrid), gcnt(c->ngrid);
+        leaf.reserve(c->nbt);
+        for (int g = 0; g < c->ngrid; ++g) {
+            goff[g] = (int)leaf.size();
+            const int64_t nb = nblocks_grid(c, g);
+            for (int64_t b = 0; b < nb; ++b) leaf.push_back(Tile{g, (int)b});
+            gcnt[g] = (int)nb;
+        }
+        launch_fill_u8(c->v.act, c->nbt, 1, c->stream);
+        Meta m{};
+        m.nleaf = (int)leaf.size();
+        for (int g = 0; g < c->ngrid && g < eu::MAXLEV; ++g) {}
+        int r;
+        if ((r = upload(c, c->v.leaf, leaf.data(), sizeof(Tile) * leaf.size()))) return r;
+        if ((r = upload(c, (void *)c->v.grp_off, goff.data(), sizeof(int) * c->ngrid))) return r;
+        if ((r = upload(c, (void *)c->v.grp_cnt, gcnt.data(), sizeof(int) * c->ngrid))) return r;
+        if ((r = upload(c, c->v.meta, &m, sizeof(Meta)))) return r;
+    }
+    int r = check_launch(c);
+    if (r) return r;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->initialized = true;
+    return EU_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C-ABI
+// ============================================================================
+extern "C" {
+
+int eu_query_sizes(const eu_config *cfg, size_t *state_bytes, size_t *scratch_bytes)
+{
+    std::string why;
+    if (validate(cfg, why)) return EU_EINVAL;
+    Layout lay;
+    make_layout(cfg, lay);
+    if (state_bytes) *state_bytes = lay.state;
+    if (scratch_bytes) *scratch_bytes = lay.scratch;
+    return EU_OK;
+}
+
+int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *scratch_dev,
+              size_t scratch_bytes, eu_ctx **out)
+{
+    if (!out) return EU_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (validate(cfg, why)) return EU_EINVAL;
+    if (!state_dev || !scratch_dev) return EU_EINVAL;
+    if (((uintptr_t)state_dev & 255) || ((uintptr_t)scratch_dev & 255)) return EU_EINVAL;
+    Layout lay;
+    make_layout(cfg, lay);
+    if (state_bytes < lay.state || scratch_bytes < lay.scratch) return EU_ENOMEM;
+
+    eu_ctx *c = new (std::nothrow) eu_ctx();
+    if (!c) return EU_ENOMEM;
+    c->cfg = *cfg;
+    if (cfg->n_instances > 1) c->sides.assign(cfg->inst_side_host, cfg->inst_side_host + cfg->n_instances);
+    c->cfg.inst_side_host = c->sides.empty() ? nullptr : c->sides.data();
+    c->ks = cfg->precision == EU_FP64 ? &kset_f64 : &kset_f32;
+    c->stream = (hipStream_t)cfg->stream;
+    c->L = lay.L;
+    c->ngrid = lay.ngrid;
+    c->dim = lay.dim;
+    c->nv = lay.nv;
+    c->mode = lay.mode;
+    c->nbt = lay.nbt;
+    c->max_tiles = (int)lay.max_tiles;
+    c->ngroups = lay.ngroups;
+    c->grids = lay.grids;
+    c->state_elems = lay.state_elems;
+
+    View &v = c->v;
+    v.dim = lay.dim;
+    v.nv = lay.nv;
+    v.L = lay.L;
+    v.ngrid = lay.ngrid;
+    v.bc = cfg->bc;
+    v.mode = lay.mode;
+    v.pmin = cfg->patch_min;
+    v.pmax = cfg->patch_max > 0 ? cfg->patch_max : eu::BS;
+    v.gamma = cfg->gamma;
+    v.cfl = cfg->cfl;
+    v.t_end = cfg->t_end;
+    v.eps = cfg->eps;
+    v.eta = cfg->eta;
+    const size_t es = cfg->precision == EU_FP64 ? 8 : 4;
+    v.Q = state_dev;
+    v.Qs = (char *)state_dev + align256((size_t)lay.state_elems * es);
+    v.Qo = nullptr;
+    v.grids = at<Grid>(scratch_dev, lay.o_grids);
+    v.act = at<uint8_t>(scratch_dev, lay.o_act);
+    v.nact = at<uint8_t>(scratch_dev, lay.o_nact);
+    v.sig = at<uint8_t>(scratch_dev, lay.o_sig);
+    v.flag = at<uint8_t>(scratch_dev, lay.o_flag);
+    v.D = at<double>(scratch_dev, lay.o_D);
+    v.leaf = at<Tile>(scratch_dev, lay.o_leaf);
+    v.cov = at<Tile>(scratch_dev, lay.o_cov);
+    v.ghost = at<Tile>(scratch_dev, lay.o_ghost);
+    v.fresh = at<Tile>(scratch_dev, lay.o_fresh);
+    v.pslot = at<int>(scratch_dev, lay.o_pslot);
+    v.pcnt = at<int>(scratch_dev, lay.o_pcnt);
+    v.pbase = at<int64_t>(scratch_dev, lay.o_pbase);
+    v.patches = at<int>(scratch_dev, lay.o_patches);
+    v.meta = at<Meta>(scratch_dev, lay.o_meta);
+    v.smax = at<unsigned long long>(scratch_dev, lay.o_smax);
+    v.dt = at<double>(scratch_dev, lay.o_dt);
+    v.t = at<double>(scratch_dev, lay.o_t);
+    v.partial = at<double>(scratch_dev, lay.o_partial);
+    v.totals = at<double>(scratch_dev, lay.o_totals);
+    v.grp_off = at<int>(scratch_dev, lay.o_goff);
+    v.grp_cnt = at<int>(scratch_dev, lay.o_gcnt);
+    v.max_tiles = (int)lay.max_tiles;
+    v.max_patch = (int)lay.max_patch;
+
+    int r;
+    if ((r = upload(c, (void *)v.grids, lay.grids.data(), sizeof(Grid) * lay.ngrid)) ||
+        (r = upload(c, v.pbase, lay.pbase.data(), sizeof(int64_t) * (eu::MAXLEV + 1)))) {
+        delete c;
+        return r;
+    }
+    hipError_t e = hipMemsetAsync(v.meta, 0, sizeof(Meta), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(v.act, 0, c->nbt, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(v.nact, 0, c->nbt, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return EU_EHIP;
+    }
+    *out = c;
+    return EU_OK;
+}
+
+int eu_destroy(eu_ctx *c)
+{
+    if (!c) return EU_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    harvest_profile(c);
+    drop_graphs(c);
+    delete c;
+    return EU_OK;
+}
+
+int eu_init_state(eu_ctx *c, const eu_problem *p)
+{
+    if (!c || !p) return EU_EINVAL;
+    if (p->kind < EU_IC_QUADRANT || p->kind > EU_IC_UNIFORM) return set_err(c, EU_EINVAL, "bad problem kind");
+    if (p->kind == EU_IC_QUADRANT && c->dim != 2) return set_err(c, EU_EINVAL, "quadrant data is 2D");
+    if (p->kind == EU_IC_ELLIPSOID && c->dim != 3) return set_err(c, EU_EINVAL, "ellipsoid data is 3D");
+    if (p->kind == EU_IC_RIEMANN1D && (p->axis < 0 || p->axis >= c->dim))
+        return set_err(c, EU_EINVAL, "bad axis");
+    if (c->mode == MODE_HIER) {
+        const int g = c->L - 1;
+        c->ks->init(c->v, make_init(c, p, -1), g, c->grids[g].ncell, c->stream);
+    } else {
+        for (int g = 0; g < c->ngrid; ++g)
+            c->ks->init(c->v, make_init(c, p, g), g, c->grids[g].ncell, c->stream);
+    }
+    int r = check_launch(c);
+    if (r) return r;
+    return finish_init(c);
+}
+
+int eu_set_finest(eu_ctx *c, int inst, const double *q_host)
+{
+    if (!c || !q_host) return EU_EINVAL;
+    const int g = c->mode == MODE_BATCH ? inst : c->L - 1;
+    if (g < 0 || g >= c->ngrid) return set_err(c, EU_EINVAL, "bad instance");
+    const Grid &G = c->grids[g];
+    const int64_t n = c->nv * G.ncell;
+    if (c->cfg.precision == EU_FP64) {
+        HIPCHK(c, hipMemcpy((double *)c->v.Q + G.off, q_host, 8 * n, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> tmp(n);
+        for (int64_t i = 0; i < n; ++i) tmp[i] = (float)q_host[i];
+        HIPCHK(c, hipMemcpy((float *)c->v.Q + G.off, tmp.data(), 4 * n, hipMemcpyHostToDevice));
+    }
+    if (c->mode == MODE_BATCH && c->initialized) return EU_OK;
+    return finish_init(c);
+}
+
+int eu_mr_decompose(eu_ctx *c)
+{
+    if (!c) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    if (c->mode != MODE_HIER) return set_err(c, EU_EINVAL, "a batch has no hierarchy");
+    seq_restrict(c, ARR_Q);
+    seq_details(c);
+    return check_launch(c);
+}
+
+int eu_mr_flag(eu_ctx *c, int64_t *nflag_host)
+{
+    if (!c) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    if (c->mode != MODE_HIER) return set_err(c, EU_EINVAL, "a batch has no hierarchy");
+    if (c->L > 1) seq_flag_tile(c, true);
+    int r = check_launch(c);
+    if (r) return r;
+    if (nflag_host) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        Meta m;
+        HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
+        for (int l = 0; l < c->L; ++l) nflag_host[l] = l < c->L - 1 ? m.nflag[l] : 0;
+    }
+    return EU_OK;
+}
+
+int eu_project(eu_ctx *c, int mode)
+{
+    if (!c) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    if (mode == EU_RESTRICT) seq_restrict(c, ARR_Q);
+    else if (mode == EU_PROLONG) {
+        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 0, (int)nblocks_grid(c, l), c->stream);
+    } else if (mode == EU_GHOST) seq_ghost(c, ARR_Q);
+    else return set_err(c, EU_EINVAL, "bad projection mode");
+    return check_launch(c);
+}
+
+int eu_cfl_dt(eu_ctx *c, double *dt_host)
+{
+    if (!c) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    seq_cfl(c);
+    int r = check_launch(c);
+    if (r) return r;
+    if (dt_host) {
+        if ((r = sync_status(c))) return r;
+        HIPCHK(c, hipMemcpy(dt_host, c->v.dt, 8, hipMemcpyDeviceToHost));
+    }
+    return EU_OK;
+}
+
+int eu_fv_step(eu_ctx *c)
+{
+    if (!c) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    seq_fv_step(c, true);
+    return check_launch(c);
+}
+
+int eu_step(eu_ctx *c, int regrid)
+{
+    if (!c) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    seq_step(c, regrid != 0);
+    return check_launch(c);
+}
+
+int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
+{
+    if (!c || nsteps < 0) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    int s0 = 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&s0, &c->v.meta->steps, sizeof(int), hipMemcpyDeviceToHost));
+    if (use_graph && !c->prof) {
+        if (!c->stream) return set_err(c, EU_EINVAL, "graph capture needs a non-default stream");
+        if (!c->gexec[0]) {
+            hipGraph_t g;
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            seq_step(c, true);
+            hipError_t e = hipStreamEndCapture(c->stream, &g);
+            if (e != hipSuccess) return set_err(c, EU_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&c->gexec[0], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                c->gexec[0] = nullptr;
+                return set_err(c, EU_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+            }
+        }
+        for (int i = 0; i < nsteps; ++i) HIPCHK(c, hipGraphLaunch(c->gexec[0], c->stream));
+    } else {
+        for (int i = 0; i < nsteps; ++i) {
+            seq_step(c, true);
+            int r = check_launch(c);
+            if (r) return r;
+        }
+    }
+    int r = sync_status(c);
+    if (c->prof) harvest_profile(c);
+    int s1 = 0;
+    HIPCHK(c, hipMemcpy(&s1, &c->v.meta->steps, sizeof(int), hipMemcpyDeviceToHost));
+    if (steps_done) *steps_done = s1 - s0;
+    return r;
+}
+
+int eu_conserved_totals(eu_ctx *c, double *totals_host)
+{
+    if (!c) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    c->ks->totals(c->v, c->max_tiles, c->stream);
+    launch_totals_final(c->v, c->ngroups, c->stream);
+    int r = check_launch(c);
+    if (r) return r;
+    if (totals_host) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(totals_host, c->v.totals, 8 * c->nv * c->ngroups, hipMemcpyDeviceToHost));
+    }
+    return EU_OK;
+}
+
+int eu_copy_level(eu_ctx *c, int inst, int level, int which, double *dst)
+{
+    if (!c || !dst) return EU_EINVAL;
+    const int g = c->mode == MODE_BATCH ? inst : level;
+    if (g < 0 || g >= c->ngrid) return set_err(c, EU_EINVAL, "bad level / instance");
+    if (which != 0 && which != 1) return set_err(c, EU_EINVAL, "bad array");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Grid &G = c->grids[g];
+    const int64_t n = c->nv * G.ncell;
+    const void *base = which == 0 ? c->v.Q : c->v.Qs;
+    if (c->cfg.precision == EU_FP64) {
+        HIPCHK(c, hipMemcpy(dst, (const double *)base + G.off, 8 * n, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(n);
+        HIPCHK(c, hipMemcpy(tmp.data(), (const float *)base + G.off, 4 * n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) dst[i] = tmp[i];
+    }
+    return EU_OK;
+}
+
+int eu_get_active(eu_ctx *c, int level, uint8_t *dst)
+{
+    if (!c || !dst) return EU_EINVAL;
+    if (level < 0 || level >= c->ngrid) return set_err(c, EU_EINVAL, "bad level");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Grid &G = c->grids[level];
+    const int64_t nbk = nblocks_grid(c, level);
+    std::vector<uint8_t> m(nbk);
+    HIPCHK(c, hipMemcpy(m.data(), c->v.act + G.boff, nbk, hipMemcpyDeviceToHost));
+    const int n = G.n, nb = G.nb;
+    for (int64_t i = 0; i < G.ncell; ++i) {
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = c->dim == 3 ? (int)(i / ((int64_t)n * n)) : 0;
+        dst[i] = m[(x >> 3) + (int64_t)nb * ((y >> 3) + (int64_t)nb * (z >> 3))];
+    }
+    return EU_OK;
+}
+
+int eu_get_flags(eu_ctx *c, int level, uint8_t *dst)
+{
+    if (!c || !dst) return EU_EINVAL;
+    if (c->mode != MODE_HIER || level < 0 || level >= c->L - 1) return set_err(c, EU_EINVAL, "bad level");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Grid &G = c->grids[level];
+    HIPCHK(c, hipMemcpy(dst, c->v.flag + G.coff, G.ncell, hipMemcpyDeviceToHost));
+    return EU_OK;
+}
+
+int eu_get_details(eu_ctx *c, int level, double *dst)
+{
+    if (!c || !dst) return EU_EINVAL;
+    if (c->mode != MODE_HIER || level < 0 || level >= c->L - 1) return set_err(c, EU_EINVAL, "bad level");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Grid &G = c->grids[level];
+    HIPCHK(c, hipMemcpy(dst, c->v.D + G.coff, 8 * G.ncell, hipMemcpyDeviceToHost));
+    return EU_OK;
+}
+
+int eu_patch_table(eu_ctx *c, int32_t *dst, int cap, int *npatch)
+{
+    if (!c || !npatch || cap < 0 || (cap > 0 && !dst)) return EU_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Meta m;
+    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
+    *npatch = c->mode == MODE_HIER ? m.npatch : 0;
+    const int k = *npatch < cap ? *npatch : cap;
+    if (k > 0) HIPCHK(c, hipMemcpy(dst, c->v.patches, sizeof(int) * 5 * k, hipMemcpyDeviceToHost));
+    return EU_OK;
+}
+
+int eu_counters(eu_ctx *c, int64_t *leaves, int64_t *active)
+{
+    if (!c) return EU_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Meta m;
+    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
+    for (int l = 0; l < c->L; ++l) {
+        if (c->mode == MODE_HIER) {
+            if (leaves) leaves[l] = m.leaf_cells[l];
+            if (active) active[l] = m.act_cells[l];
+        } else {
+            int64_t s = 0;
+            for (int g = 0; g < c->ngrid; ++g) s += c->grids[g].ncell;
+            if (leaves) leaves[l] = s;
+            if (active) active[l] = s;
+        }
+    }
+    return EU_OK;
+}
+
+int eu_leaf_updates(eu_ctx *c, int64_t *updates_host, int *steps_host)
+{
+    if (!c) return EU_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Meta m;
+    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
+    if (steps_host) *steps_host = m.steps;
+    if (updates_host) {
+        if (c->mode == MODE_HIER) *updates_host = m.leaf_updates;
+        else {
+            int64_t s = 0;
+            for (int g = 0; g < c->ngrid; ++g) s += c->grids[g].ncell;
+            *updates_host = s * (int64_t)m.steps;
+        }
+    }
+    return EU_OK;
+}
+
+int eu_time(eu_ctx *c, double *t_host, double *dt_host)
+{
+    if (!c) return EU_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (t_host) HIPCHK(c, hipMemcpy(t_host, c->v.t, 8, hipMemcpyDeviceToHost));
+    if (dt_host) HIPCHK(c, hipMemcpy(dt_host, c->v.dt, 8, hipMemcpyDeviceToHost));
+    return EU_OK;
+}
+
+int eu_profile(eu_ctx *c, int enable)
+{
+    if (!c) return EU_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    harvest_profile(c);
+    c->prof = enable != 0;
+    c->prof_ms = 0.0;
+    c->prof_n = 0;
+    return EU_OK;
+}
+
+int eu_kernel_time(eu_ctx *c, double *ms, int64_t *launches)
+{
+    if (!c) return EU_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    harvest_profile(c);
+    if (ms) *ms = c->prof_ms;
+    if (launches) *launches = c->prof_n;
+    return EU_OK;
+}
+
+int eu_status(eu_ctx *c)
+{
+    if (!c) return EU_EINVAL;
+    return sync_status(c);
+}
+
+int eu_clear_status(eu_ctx *c)
+{
+    if (!c) return EU_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int z = 0;
+    HIPCHK(c, hipMemcpy(&c->v.meta->status, &z, sizeof(int), hipMemcpyHostToDevice));
+    return EU_OK;
+}
+
+const char *eu_last_error(const eu_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+}  // extern "C"

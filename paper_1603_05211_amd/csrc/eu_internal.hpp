@@ -1,0 +1,79 @@
+// eu_internal.hpp -- data structures shared by the host library and the
+// gfx950 kernels.  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eu {
+
+constexpr int BS = 8;          // block side in cells: the unit of patches and tiles
+constexpr int MAXLEV = 10;
+
+// One dense grid: a level of the hierarchy, the single uniform grid, or one
+// instance of a batch.  Field f of cell (x, y, z) lives at
+//   state[off + f * ncell + x + n * (y + n * z)].
+struct Grid {
+    int64_t off;     // element offset of field 0 in every state array
+    int64_t ncell;   // n^d (field stride)
+    int64_t boff;    // offset of this grid's blocks in the block-mask arrays
+    int64_t coff;    // offset of this grid's cells in the per-cell MR arrays (-1: none)
+    int n;           // cells per side
+    int nb;          // blocks per side (n / BS)
+    int fine;        // grid index of the next finer level (-1: none)
+    int coarse;      // grid index of the next coarser level (-1: none)
+    int lvl;         // level (0 for uniform and batch grids)
+    int pad;
+    double dx;       // cell width
+};
+
+// A tile of work: one BS^d block of one grid.
+struct Tile {
+    int grid;
+    int block;       // block index within the grid, x fastest
+};
+
+// Device-resident counters written by the mesh kernels.
+struct Meta {
+    int nleaf;                 // tiles in the leaf list (blocks holding leaves)
+    int nghost;                // tiles in the ghost list
+    int npatch;                // rows of the patch table
+    int status;                // bit 0: non-physical state met
+    int done;                  // the current step starts at t >= t_end: skip it
+    int steps;                 // steps taken since initialisation
+    long long leaf_updates;    // leaf cells advanced since initialisation
+    int cov_off[MAXLEV], cov_cnt[MAXLEV];   // per-level ranges of the covered-block list
+    int new_off[MAXLEV], new_cnt[MAXLEV];   // per-level ranges of the new-block list
+    int nflag[MAXLEV];                      // flagged cells per level
+    long long leaf_cells[MAXLEV];
+    long long act_cells[MAXLEV];
+};
+
+enum { MODE_HIER = 0, MODE_BATCH = 1 };
+
+// Everything a kernel needs, passed by value.
+struct View {
+    int dim, nv, L, ngrid, bc, mode;
+    int pmin, pmax;
+    double gamma, cfl, t_end, eps, eta;
+    const Grid *grids;                // device copy of the grid table
+    void *Q, *Qs, *Qo;                // state arrays (element type per precision)
+    uint8_t *act, *nact;              // per-block patch membership (current / new)
+    uint8_t *sig, *flag;              // per-cell significance and refinement flags
+    double *D;                        // per-cell FP64 detail norm
+    Tile *leaf, *cov, *ghost, *fresh; // work lists
+    int *pslot;                       // per pmax-block patch slots (5 ints each)
+    int *pcnt;                        // per pmax-block patch counts
+    int64_t *pbase;                   // per-level offset into pslot / pcnt
+    int *patches;                     // compacted patch table (5 ints per row)
+    Meta *meta;
+    unsigned long long *smax;         // per grid: max wave-speed sum (FP64 bits)
+    double *dt, *t;                   // per grid (batch) or entry 0 (hierarchy)
+    double *partial;                  // per tile x nv partial totals
+    double *totals;                   // per group x nv
+    const int *grp_off, *grp_cnt;     // batch: tile range of each instance
+    int max_tiles;                    // capacity of the leaf list
+    int max_patch;                    // capacity of the patch table
+};
+
+}  // namespace eu

@@ -1,0 +1,674 @@
+// eu_kernels.hpp -- gfx950 kernels of the finite-volume / multiresolution
+// path, templated on the state type T (double | float) and the dimension D.
+// Included by eu_fp64.hip (built without FMA contraction, so FP64 results
+// follow the reference expression trees operation for operation) and by
+// eu_fp32.hip (contraction allowed, hardware reciprocal and square root).
+#pragma once
+
+#include "eu_internal.hpp"
+#include "eu_kset.hpp"
+
+namespace eu {
+
+// ----------------------------------------------------------------------------
+// arithmetic per precision
+// ----------------------------------------------------------------------------
+template <typename T> struct Ar;
+template <> struct Ar<double> {
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double sqrt(double a) { return __builtin_sqrt(a); }
+    static __device__ __forceinline__ double abs(double a) { return __builtin_fabs(a); }
+};
+template <> struct Ar<float> {
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float sqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+    static __device__ __forceinline__ float abs(float a) { return __builtin_fabsf(a); }
+};
+
+// Boundary index map: outflow (zero-order extrapolation) clamps to the
+// nearest interior cell; periodic wraps.  |i| stays within one period.
+__device__ __forceinline__ int bcmap(int i, int n, int bc)
+{
+    if (bc == 1) return i < 0 ? i + n : (i >= n ? i - n : i);
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ int64_t gidx(int n, int x, int y, int z)
+{
+    return x + (int64_t)n * (y + (int64_t)n * z);
+}
+
+// ----------------------------------------------------------------------------
+// physics (Sec. 2): conserved <-> primitive, van Albada slope, AUSM+
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__device__ __forceinline__ void cons2prim(const T *q, T *w, T g)
+{
+    T rho = q[0], K = T(0);
+    w[0] = rho;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        T v = Ar<T>::div(q[1 + d], rho);
+        w[1 + d] = v;
+        K = K + v * v;
+    }
+    w[D + 1] = (g - T(1)) * (q[D + 1] - (T(0.5) * rho) * K);
+}
+
+template <typename T>
+__device__ __forceinline__ T slope_va(T wm, T w0, T wp)
+{
+    T a = w0 - wm, b = wp - w0, ab = a * b;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: with differences below ~1e-19 the denominator underflows and
+        // the hardware reciprocal returns inf (0 * inf = NaN); such a slope
+        // is below FP32 resolution of the state, so it is taken as zero.
+        const T den = a * a + b * b;
+        return (ab > T(0) && den >= T(1.1754944e-38f)) ? Ar<T>::div(ab * (a + b), den) : T(0);
+    } else {
+        return ab > T(0) ? Ar<T>::div(ab * (a + b), a * a + b * b) : T(0);
+    }
+}
+
+// AUSM+ (Liou 1996) across a face with normal along axis DN; wL, wR are the
+// primitive face states; gi = 1 / (gamma - 1).
+template <typename T, int D, int DN>
+__device__ __forceinline__ void ausm_plus(T g, T gi, const T *wL, const T *wR, T *F)
+{
+    const T rL = wL[0], pL = wL[D + 1], uL = wL[1 + DN];
+    const T rR = wR[0], pR = wR[D + 1], uR = wR[1 + DN];
+    const T cL = Ar<T>::sqrt(Ar<T>::div(g * pL, rL));
+    const T cR = Ar<T>::sqrt(Ar<T>::div(g * pR, rR));
+    const T ch = T(0.5) * (cL + cR);
+    const T ML = Ar<T>::div(uL, ch), MR = Ar<T>::div(uR, ch);
+    T Mp, Pp, Mm, Pm;
+    if (Ar<T>::abs(ML) >= T(1)) {
+        Mp = T(0.5) * (ML + Ar<T>::abs(ML));
+        Pp = ML > T(0) ? T(1) : T(0);
+    } else {
+        const T a = ML + T(1), b = ML - T(1);
+        const T m2p = T(0.25) * (a * a), m2m = T(-0.25) * (b * b);
+        Mp = m2p * (T(1) - T(2) * m2m);
+        Pp = m2p * ((T(2) - ML) - (T(3) * ML) * m2m);
+    }
+    if (Ar<T>::abs(MR) >= T(1)) {
+        Mm = T(0.5) * (MR - Ar<T>::abs(MR));
+        Pm = MR < T(0) ? T(1) : T(0);
+    } else {
+        const T a = MR + T(1), b = MR - T(1);
+        const T m2p = T(0.25) * (a * a), m2m = T(-0.25) * (b * b);
+        Mm = m2m * (T(1) + T(2) * m2p);
+        Pm = m2m * ((T(-2) - MR) + (T(3) * MR) * m2p);
+    }
+    const T mh = Mp + Mm;
+    const T ph = Pp * pL + Pm * pR;
+    const T mf = ch * mh;
+    const bool up = mh >= T(0);
+    T wu[D + 2];
+#pragma unroll
+    for (int f = 0; f < D + 2; ++f) wu[f] = up ? wL[f] : wR[f];
+    const T ru = wu[0], pu = wu[D + 1];
+    T K = T(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) K = K + wu[1 + k] * wu[1 + k];
+    const T rH = (pu * gi + (T(0.5) * ru) * K) + pu;
+    F[0] = mf * ru;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        F[1 + k] = mf * (ru * wu[1 + k]);
+        if (k == DN) F[1 + k] = F[1 + k] + ph;
+    }
+    F[D + 1] = mf * rH;
+}
+
+// Face flux from the primitive states of the 4 cells i-1, i, i+1, i+2 along DN.
+template <typename T, int D, int DN>
+__device__ __forceinline__ void face_flux4(T g, T gi, const T *wa, const T *wb, const T *wc,
+                                           const T *wd, T *F)
+{
+    T wL[D + 2], wR[D + 2];
+#pragma unroll
+    for (int f = 0; f < D + 2; ++f) {
+        wL[f] = wb[f] + T(0.5) * slope_va<T>(wa[f], wb[f], wc[f]);
+        wR[f] = wc[f] - T(0.5) * slope_va<T>(wb[f], wc[f], wd[f]);
+    }
+    ausm_plus<T, D, DN>(g, gi, wL, wR, F);
+}
+
+// Mean of the 2^(D-1) fine fluxes on the face between coarse cell p (global
+// coordinates on grid G) and its covered neighbour on side s of axis DN,
+// computed from the next finer grid of the stencil source (virtual leaves,
+// Sec. 2.1).
+template <typename T, int D, int DN>
+__device__ void fine_mean(const View &v, const Grid &G, const T *src, int px, int py, int pz,
+                          int s, T g, T gi, T *F)
+{
+    const Grid gf = v.grids[G.fine];
+    const T *S = src + gf.off;
+    const int nf = gf.n;
+    const int64_t Nf = gf.ncell;
+    int b[3] = {2 * px, 2 * py, 2 * pz};
+    b[DN] = s > 0 ? 2 * (DN == 0 ? px : DN == 1 ? py : pz) + 1
+                  : 2 * (DN == 0 ? px : DN == 1 ? py : pz) - 1;
+    constexpr int T1 = DN == 0 ? 1 : 0;
+    constexpr int T2 = DN == 2 ? 1 : 2;
+    constexpr int NS = D == 2 ? 2 : 4;
+    T Fs[NS][D + 2];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        int c[3] = {b[0], b[1], b[2]};
+        c[T1] += k & 1;
+        if (D == 3) c[T2] += (k >> 1) & 1;
+        T w[4][D + 2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int e[3] = {c[0], c[1], c[2]};
+            e[DN] = bcmap(c[DN] + j - 1, nf, v.bc);
+            const int64_t id = gidx(nf, e[0], e[1], D == 3 ? e[2] : 0);
+            T q[D + 2];
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) q[f] = S[f * Nf + id];
+            cons2prim<T, D>(q, w[j], g);
+        }
+        face_flux4<T, D, DN>(g, gi, w[0], w[1], w[2], w[3], Fs[k]);
+    }
+#pragma unroll
+    for (int f = 0; f < D + 2; ++f) {
+        if (D == 2) F[f] = T(0.5) * (Fs[0][f] + Fs[1][f]);
+        else F[f] = T(0.25) * ((Fs[0][f] + Fs[1][f]) + (Fs[2][f] + Fs[3][f]));
+    }
+}
+
+// ----------------------------------------------------------------------------
+// MR operators (Sec. 2.1)
+// ----------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T pred1(T qm, T q0, T qp, int upper)
+{
+    const T s8 = upper ? T(-0.125) : T(0.125);
+    return q0 + s8 * (qm - qp);
+}
+
+// Third-order prediction of child ch of coarse cell p for one field (array A
+// is the coarse field, n its side), separable x, then y, then z.
+template <typename T, int D, typename TA>
+__device__ __forceinline__ T predict_child(const TA *A, int n, int bc, int px, int py, int pz,
+                                           int cx, int cy, int cz)
+{
+    int xs[3], ys[3], zs[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        xs[k] = bcmap(px + k - 1, n, bc);
+        ys[k] = bcmap(py + k - 1, n, bc);
+        zs[k] = D == 3 ? bcmap(pz + k - 1, n, bc) : 0;
+    }
+    if (D == 2) {
+        T r[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r[j] = pred1<T>((T)A[gidx(n, xs[0], ys[j], 0)], (T)A[gidx(n, xs[1], ys[j], 0)],
+                            (T)A[gidx(n, xs[2], ys[j], 0)], cx);
+        return pred1<T>(r[0], r[1], r[2], cy);
+    }
+    T s[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T r[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r[j] = pred1<T>((T)A[gidx(n, xs[0], ys[j], zs[k])], (T)A[gidx(n, xs[1], ys[j], zs[k])],
+                            (T)A[gidx(n, xs[2], ys[j], zs[k])], cx);
+        s[k] = pred1<T>(r[0], r[1], r[2], cy);
+    }
+    return pred1<T>(s[0], s[1], s[2], cz);
+}
+
+// Projection: mean of the 2^D children (pairwise order).
+template <typename T, int D>
+__device__ __forceinline__ T restrict_cell(const T *Af, int nf, int px, int py, int pz)
+{
+    const int x = 2 * px, y = 2 * py, z = 2 * pz;
+    if (D == 2)
+        return T(0.25) * ((Af[gidx(nf, x, y, 0)] + Af[gidx(nf, x + 1, y, 0)]) +
+                          (Af[gidx(nf, x, y + 1, 0)] + Af[gidx(nf, x + 1, y + 1, 0)]));
+    return T(0.125) * (((Af[gidx(nf, x, y, z)] + Af[gidx(nf, x + 1, y, z)]) +
+                        (Af[gidx(nf, x, y + 1, z)] + Af[gidx(nf, x + 1, y + 1, z)])) +
+                       ((Af[gidx(nf, x, y, z + 1)] + Af[gidx(nf, x + 1, y, z + 1)]) +
+                        (Af[gidx(nf, x, y + 1, z + 1)] + Af[gidx(nf, x + 1, y + 1, z + 1)])));
+}
+
+__device__ __forceinline__ bool block_active(const View &v, const uint8_t *mask, const Grid &G,
+                                             int x, int y, int z)
+{
+    return mask[G.boff + (x >> 3) + (int64_t)G.nb * ((y >> 3) + (int64_t)G.nb * (z >> 3))] != 0;
+}
+
+// covered: the children of cell (x, y, z) belong to a patch of the finer grid.
+__device__ __forceinline__ bool covered(const View &v, const uint8_t *mask, const Grid &G, int x,
+                                        int y, int z)
+{
+    if (G.fine < 0) return false;
+    const Grid &F = v.grids[G.fine];
+    return mask[F.boff + (x >> 2) + (int64_t)F.nb * ((y >> 2) + (int64_t)F.nb * (z >> 2))] != 0;
+}
+
+// ----------------------------------------------------------------------------
+// finite-volume stage on every leaf of the tiles of the leaf list
+// ----------------------------------------------------------------------------
+template <int D> struct FV {
+    static constexpr int B = BS, H = 2, E = BS + 4;
+    static constexpr int NT = D == 2 ? 64 : 256;
+    static constexpr int NE = D == 2 ? E * E : E * E * E;
+    static constexpr int NV = D + 2;
+    static constexpr int TC = D == 2 ? B * B : B * B * B;
+    static constexpr int CPT = TC / NT;
+    static constexpr int NF = (B + 1) * (D == 2 ? B : B * B);
+};
+
+template <typename T, int D, int DN>
+__device__ __forceinline__ void fv_faces(const View &v, const Grid &G, const T *src, int ox, int oy,
+                                         int oz, const T (*sW)[FV<D>::NE], const uint8_t *sCov,
+                                         T (*sF)[FV<D>::NF], T g, T gi)
+{
+    using C = FV<D>;
+    constexpr int E = C::E, H = C::H, B = C::B;
+    constexpr int SD = DN == 0 ? 1 : DN == 1 ? E : E * E;
+    for (int fi = threadIdx.x; fi < C::NF; fi += C::NT) {
+        const int a = fi % (B + 1), r = fi / (B + 1);
+        int l[3];
+        // local coordinates of the left cell
+        if (DN == 0) { l[0] = a - 1; l[1] = r % B; l[2] = D == 3 ? r / B : 0; }
+        else if (DN == 1) { l[1] = a - 1; l[0] = r % B; l[2] = D == 3 ? r / B : 0; }
+        else { l[2] = a - 1; l[0] = r % B; l[1] = r / B; }
+        const int hl = (l[0] + H) + E * ((l[1] + H) + (D == 3 ? E * (l[2] + H) : 0));
+        const int hr = hl + SD;
+        const bool lin = a >= 1, rin = a <= B - 1;
+        const bool lcov = sCov[hl] != 0, rcov = sCov[hr] != 0;
+        const bool need = (lin && !lcov) || (rin && !rcov);
+        T F[D + 2];
+        if (!need) {
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) F[f] = T(0);
+        } else if (lcov || rcov) {
+            int p[3] = {ox + l[0], oy + l[1], oz + l[2]};
+            int s = +1;
+            if (lcov) { p[DN] += 1; s = -1; }
+            fine_mean<T, D, DN>(v, G, src, p[0], p[1], D == 3 ? p[2] : 0, s, g, gi, F);
+        } else {
+            T wa[D + 2], wb[D + 2], wc[D + 2], wd[D + 2];
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) {
+                wa[f] = sW[f][hl - SD];
+                wb[f] = sW[f][hl];
+                wc[f] = sW[f][hr];
+                wd[f] = sW[f][hr + SD];
+            }
+            face_flux4<T, D, DN>(g, gi, wa, wb, wc, wd, F);
+        }
+#pragma unroll
+        for (int f = 0; f < D + 2; ++f) sF[f][fi] = F[f];
+    }
+}
+
+template <typename T, int D, int DN>
+__device__ __forceinline__ void fv_collect(const T (*sF)[FV<D>::NF], T (*dF)[D][D + 2])
+{
+    using C = FV<D>;
+    constexpr int B = C::B;
+#pragma unroll
+    for (int k = 0; k < C::CPT; ++k) {
+        const int c = threadIdx.x + k * C::NT;
+        const int x = c % B, y = (c / B) % B, z = c / (B * B);
+        int a, r;
+        if (DN == 0) { a = x; r = y + B * z; }
+        else if (DN == 1) { a = y; r = x + B * z; }
+        else { a = z; r = x + B * y; }
+        const int lo = a + (B + 1) * r, hi = lo + 1;
+#pragma unroll
+        for (int f = 0; f < D + 2; ++f) dF[k][DN][f] = sF[f][hi] - sF[f][lo];
+    }
+}
+
+// One explicit stage: out = base - lam ((dF_1 + dF_2) + dF_3) on every leaf,
+// lam = (dt * fac) / dx (FP64, then cast), fluxes from src.
+template <typename T, int D>
+__global__ void __launch_bounds__(FV<D>::NT)
+k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac)
+{
+    using C = FV<D>;
+    constexpr int E = C::E, H = C::H, B = C::B, NV = C::NV;
+    __shared__ T sW[NV][C::NE];
+    __shared__ T sF[NV][C::NF];
+    __shared__ uint8_t sCov[C::NE];
+    if (v.meta->done) return;
+    const T g = (T)v.gamma;
+    const T gi = (T)(1.0 / (v.gamma - 1.0));
+    const int count = v.meta->nleaf;
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const Tile tl = v.leaf[t];
+        const Grid G = v.grids[tl.grid];
+        const int n = G.n, nb = G.nb;
+        const int ox = (tl.block % nb) * B;
+        const int oy = ((tl.block / nb) % nb) * B;
+        const int oz = D == 3 ? (tl.block / (nb * nb)) * B : 0;
+        const T *S = src + G.off;
+        const int64_t N = G.ncell;
+        for (int c = threadIdx.x; c < C::NE; c += C::NT) {
+            const int lx = c % E, ly = (c / E) % E, lz = D == 3 ? c / (E * E) : 0;
+            const int x = bcmap(ox + lx - H, n, v.bc);
+            const int y = bcmap(oy + ly - H, n, v.bc);
+            const int z = D == 3 ? bcmap(oz + lz - H, n, v.bc) : 0;
+            const int64_t id = gidx(n, x, y, z);
+            T q[NV], w[NV];
+#pragma unroll
+            for (int f = 0; f < NV; ++f) q[f] = S[f * N + id];
+            cons2prim<T, D>(q, w, g);
+#pragma unroll
+            for (int f = 0; f < NV; ++f) sW[f][c] = w[f];
+            sCov[c] = covered(v, v.act, G, x, y, z) ? 1 : 0;
+        }
+        __syncthreads();
+        T dF[C::CPT][D][NV];
+        fv_faces<T, D, 0>(v, G, src, ox, oy, oz, sW, sCov, sF, g, gi);
+        __syncthreads();
+        fv_collect<T, D, 0>(sF, dF);
+        __syncthreads();
+        fv_faces<T, D, 1>(v, G, src, ox, oy, oz, sW, sCov, sF, g, gi);
+        __syncthreads();
+        fv_collect<T, D, 1>(sF, dF);
+        __syncthreads();
+        if constexpr (D == 3) {
+            fv_faces<T, D, 2>(v, G, src, ox, oy, oz, sW, sCov, sF, g, gi);
+            __syncthreads();
+            fv_collect<T, D, 2>(sF, dF);
+        }
+        const double dt = v.dt[v.mode == MODE_BATCH ? tl.grid : 0];
+        const T lam = (T)((dt * fac) / G.dx);
+#pragma unroll
+        for (int k = 0; k < C::CPT; ++k) {
+            const int c = threadIdx.x + k * C::NT;
+            const int x = c % B, y = (c / B) % B, z = c / (B * B);
+            const int h = (x + H) + E * ((y + H) + (D == 3 ? E * (z + H) : 0));
+            if (sCov[h]) continue;
+            const int64_t id = G.off + gidx(n, ox + x, oy + y, oz + z);
+#pragma unroll
+            for (int f = 0; f < NV; ++f) {
+                T R = dF[k][0][f] + dF[k][1][f];
+                if (D == 3) R = R + dF[k][D - 1][f];
+                out[f * N + id] = base[f * N + id] - lam * R;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// CFL reduction over leaves (FP64): per-grid max of sum_d (|v_d| + c)
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
+{
+#pragma clang fp contract(off)
+    __shared__ double sm[4];
+    if (v.meta->done) return;
+    const int count = v.meta->nleaf;
+    constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
+    const double g = v.gamma;
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const Tile tl = v.leaf[t];
+        const Grid G = v.grids[tl.grid];
+        const int n = G.n, nb = G.nb;
+        const int ox = (tl.block % nb) * BS;
+        const int oy = ((tl.block / nb) % nb) * BS;
+        const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
+        double m = 0.0;
+        bool bad = false;
+        for (int c = threadIdx.x; c < TC; c += blockDim.x) {
+            const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
+            if (covered(v, v.act, G, x, y, z)) continue;
+            const int64_t id = G.off + gidx(n, x, y, z);
+            double q[D + 2], w[D + 2];
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) q[f] = (double)Q[f * G.ncell + id];
+            cons2prim<double, D>(q, w, g);
+            if (!(w[0] > 0.0) || !(w[D + 1] > 0.0)) bad = true;
+            const double cs = __builtin_sqrt((g * w[D + 1]) / w[0]);
+            double S = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) S = S + (__builtin_fabs(w[1 + d]) + cs);
+            if (S > m) m = S;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double r = __shfl_xor(m, o);
+            m = r > m ? r : m;
+        }
+        if (bad) atomicOr(&v.meta->status, 1);
+        if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double mm = sm[0];
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) mm = sm[k] > mm ? sm[k] : mm;
+            if (mm > 0.0)
+                atomicMax(&v.smax[tl.grid], (unsigned long long)__double_as_longlong(mm));
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// conserved totals: per-tile partial sums in a fixed order (FP64)
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_totals(View v, const T *__restrict__ Q)
+{
+#pragma clang fp contract(off)
+    __shared__ double sm[D + 2][256];
+    const int count = v.meta->nleaf;
+    constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const Tile tl = v.leaf[t];
+        const Grid G = v.grids[tl.grid];
+        const int n = G.n, nb = G.nb;
+        const int ox = (tl.block % nb) * BS;
+        const int oy = ((tl.block / nb) % nb) * BS;
+        const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
+        const double vol = D == 2 ? G.dx * G.dx : G.dx * G.dx * G.dx;
+        double acc[D + 2];
+#pragma unroll
+        for (int f = 0; f < D + 2; ++f) acc[f] = 0.0;
+        for (int c = threadIdx.x; c < TC; c += blockDim.x) {
+            const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
+            if (covered(v, v.act, G, x, y, z)) continue;
+            const int64_t id = G.off + gidx(n, x, y, z);
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) acc[f] = acc[f] + (double)Q[f * G.ncell + id] * vol;
+        }
+#pragma unroll
+        for (int f = 0; f < D + 2; ++f) sm[f][threadIdx.x] = acc[f];
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s)
+#pragma unroll
+                for (int f = 0; f < D + 2; ++f) sm[f][threadIdx.x] += sm[f][threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x < D + 2) v.partial[(int64_t)t * (D + 2) + threadIdx.x] = sm[threadIdx.x][0];
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// initial data (cell-centre sampling, FP64 arithmetic, then cast)
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_init(View v, InitArgs a, int grid, T *Q)
+{
+#pragma clang fp contract(off)
+    const Grid G = v.grids[grid];
+    const int n = G.n;
+    const double g = v.gamma, gi = 1.0 / (g - 1.0);
+    const double lo = a.lo, dx = (a.hi - a.lo) / (double)n;
+    const int64_t N = G.ncell;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = D == 3 ? (int)(i / ((int64_t)n * n)) : 0;
+        const double xc = lo + ((double)x + 0.5) * dx;
+        const double yc = lo + ((double)y + 0.5) * dx;
+        const double zc = lo + ((double)z + 0.5) * dx;
+        double w[5] = {0, 0, 0, 0, 0};
+        if (a.kind == 0) {  // four quadrants (2D)
+            const int qd = xc > a.x0 ? (yc > a.y0 ? 0 : 3) : (yc > a.y0 ? 1 : 2);
+            w[0] = a.quad[qd][0]; w[1] = a.quad[qd][1]; w[2] = a.quad[qd][2];
+            w[D + 1] = a.quad[qd][3];
+        } else if (a.kind == 1) {  // rotated ellipsoid (3D)
+            const double x1 = xc * a.ell[3] - yc * a.ell[4];
+            const double s = xc * a.ell[4] + yc * a.ell[3];
+            const double x2 = s * a.ell[5] - zc * a.ell[6];
+            const double x3 = s * a.ell[6] + zc * a.ell[5];
+            const double r2 = ((x1 / a.ell[0]) * (x1 / a.ell[0]) + (x2 / a.ell[1]) * (x2 / a.ell[1])) +
+                              (x3 / a.ell[2]) * (x3 / a.ell[2]);
+            const bool in = r2 < a.ell[7] * a.ell[7];
+            w[0] = in ? a.es[0] : a.es[2];
+            w[D + 1] = in ? a.es[1] : a.es[3];
+        } else if (a.kind == 2) {  // 1D Riemann problem along an axis
+            const double xa = a.axis == 0 ? xc : a.axis == 1 ? yc : zc;
+            const int s = xa < a.split ? 0 : 3;
+            w[0] = a.lr[s];
+            w[1 + a.axis] = a.lr[s + 1];
+            w[D + 1] = a.lr[s + 2];
+        } else {  // uniform state
+            for (int f = 0; f < D + 2; ++f) w[f] = a.uni[f];
+        }
+        double K = 0.0;
+        Q[G.off + i] = (T)w[0];
+        for (int d = 0; d < D; ++d) {
+            Q[G.off + (1 + d) * N + i] = (T)(w[0] * w[1 + d]);
+            K = K + w[1 + d] * w[1 + d];
+        }
+        Q[G.off + (D + 1) * N + i] = (T)(w[D + 1] * gi + (0.5 * w[0]) * K);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// projection / prediction / ghost cells
+// ----------------------------------------------------------------------------
+// Projection of every cell of coarse grid gc from its finer grid (set-up).
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_restrict_full(View v, T *A, int gc)
+{
+    const Grid G = v.grids[gc];
+    const Grid F = v.grids[G.fine];
+    const int n = G.n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.ncell;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = D == 3 ? (int)(i / ((int64_t)n * n)) : 0;
+#pragma unroll
+        for (int f = 0; f < D + 2; ++f)
+            A[G.off + f * G.ncell + i] = restrict_cell<T, D>(A + F.off + f * F.ncell, F.n, x, y, z);
+    }
+}
+
+// Projection onto the covered cells of the blocks of level lvl's covered list.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_restrict_cov(View v, T *A, int lvl)
+{
+    if (v.meta->done) return;
+    const int off = v.meta->cov_off[lvl], count = v.meta->cov_cnt[lvl];
+    constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const Tile tl = v.cov[off + t];
+        const Grid G = v.grids[tl.grid];
+        const Grid F = v.grids[G.fine];
+        const int nb = G.nb;
+        const int ox = (tl.block % nb) * BS;
+        const int oy = ((tl.block / nb) % nb) * BS;
+        const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
+        for (int c = threadIdx.x; c < TC; c += blockDim.x) {
+            const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
+            if (!covered(v, v.act, G, x, y, z)) continue;
+            const int64_t id = gidx(G.n, x, y, z);
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f)
+                A[G.off + f * G.ncell + id] = restrict_cell<T, D>(A + F.off + f * F.ncell, F.n, x, y, z);
+        }
+    }
+}
+
+// ghost cell: outside every patch of its level, within two cells of a patch
+template <int D>
+__device__ __forceinline__ bool is_ghost(const View &v, const Grid &G, int x, int y, int z)
+{
+    const int n = G.n;
+    if (block_active(v, v.act, G, x, y, z)) return false;
+    const int r3 = D == 3 ? 2 : 0;
+    for (int dz = -r3; dz <= r3; ++dz)
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx)
+                if (block_active(v, v.act, G, bcmap(x + dx, n, v.bc), bcmap(y + dy, n, v.bc),
+                                 D == 3 ? bcmap(z + dz, n, v.bc) : 0))
+                    return true;
+    return false;
+}
+
+// Fill ghost cells (ghost list) or newly created cells (new list of level
+// lvl) by prediction from the next coarser level.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int ghost)
+{
+    if (v.meta->done) return;
+    const int off = ghost ? 0 : v.meta->new_off[lvl];
+    const int count = ghost ? v.meta->nghost : v.meta->new_cnt[lvl];
+    const Tile *list = ghost ? v.ghost : v.fresh;
+    constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const Tile tl = list[off + t];
+        const Grid G = v.grids[tl.grid];
+        const Grid Cg = v.grids[G.coarse];
+        const int nb = G.nb;
+        const int ox = (tl.block % nb) * BS;
+        const int oy = ((tl.block / nb) % nb) * BS;
+        const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
+        for (int c = threadIdx.x; c < TC; c += blockDim.x) {
+            const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
+            if (ghost && !is_ghost<D>(v, G, x, y, z)) continue;
+            const int64_t id = gidx(G.n, x, y, z);
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f)
+                A[G.off + f * G.ncell + id] = predict_child<T, D, T>(
+                    A + Cg.off + f * Cg.ncell, Cg.n, v.bc, x >> 1, y >> 1, z >> 1, x & 1, y & 1, z & 1);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// MR details (FP64) of every refined cell of level lvl; dense over the level
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q, int lvl)
+{
+#pragma clang fp contract(off)
+    if (v.meta->done) return;
+    const Grid G = v.grids[lvl];
+    const Grid F = v.grids[G.fine];
+    const int n = G.n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.ncell;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = D == 3 ? (int)(i / ((int64_t)n * n)) : 0;
+        double Dm = 0.0;
+        if (block_active(v, v.act, G, x, y, z) && covered(v, v.act, G, x, y, z)) {
+            const T *Ac = Q + G.off;  // density field of the coarse level
+            const T *Af = Q + F.off;
+            for (int k = 0; k < (1 << D); ++k) {
+                const int cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
+                const double rho = (double)Af[gidx(F.n, 2 * x + cx, 2 * y + cy, D == 3 ? 2 * z + cz : 0)];
+                const double pr = predict_child<double, D, T>(Ac, n, v.bc, x, y, z, cx, cy, cz);
+                const double dd = __builtin_fabs(rho - pr);
+                if (dd > Dm) Dm = dd;
+            }
+        }
+        v.D[G.coff + i] = Dm;
+        v.sig[G.coff + i] = Dm >= v.eps ? 1 : 0;
+    }
+}
+
+}  // namespace eu

@@ -1,0 +1,50 @@
+// eu_kset.hpp -- per-precision kernel launchers (one table per state type).
+#pragma once
+
+#include "eu_internal.hpp"
+
+namespace eu {
+
+// Initial data parameters (host values passed by value to the kernel).
+struct InitArgs {
+    int kind;          // 0 quadrants, 1 ellipsoid, 2 1D Riemann, 3 uniform
+    int axis;
+    double lo, hi;
+    double x0, y0;
+    double quad[4][4];
+    double ell[8];
+    double es[4];
+    double lr[6];
+    double split;
+    double uni[5];
+};
+
+// Which state array a launcher works on.
+enum { ARR_Q = 0, ARR_QS = 1, ARR_QO = 2 };
+
+struct KSet {
+    size_t elem;  // bytes per state value
+    void (*init)(const View &, const InitArgs &, int grid, int64_t ncell, hipStream_t);
+    void (*restrict_full)(const View &, int arr, int grid_coarse, int64_t ncell, hipStream_t);
+    void (*restrict_cov)(const View &, int arr, int lvl, int maxblocks, hipStream_t);
+    void (*predict)(const View &, int arr, int lvl, int ghost, int maxblocks, hipStream_t);
+    void (*fv_stage)(const View &, int stage, int maxtiles, hipStream_t);
+    void (*cfl)(const View &, int maxtiles, hipStream_t);
+    void (*totals)(const View &, int maxtiles, hipStream_t);
+    void (*details)(const View &, int lvl, int64_t ncell, hipStream_t);
+};
+
+extern const KSet kset_f64;
+extern const KSet kset_f32;
+
+// precision-independent mesh kernels (eu_mesh.hip)
+void launch_cfl_finalize(const View &, hipStream_t);
+void launch_time_advance(const View &, hipStream_t);
+void launch_flags(const View &, int lvl, int64_t ncell, hipStream_t);
+void launch_tile(const View &, int lvl, int nblocks, hipStream_t);
+void launch_build_lists(const View &, int64_t nblocks_total, hipStream_t);
+void launch_fill_u8(uint8_t *p, int64_t n, uint8_t val, hipStream_t);
+void launch_zero_meta_flags(const View &, hipStream_t);
+void launch_totals_final(const View &, int ngroups, hipStream_t);
+
+}  // namespace eu

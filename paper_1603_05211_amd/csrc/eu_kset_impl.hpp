@@ -1,0 +1,96 @@
+// eu_kset_impl.hpp -- launcher bodies, instantiated once per state type by
+// eu_fp64.hip and eu_fp32.hip.
+#pragma once
+
+#include "eu_kernels.hpp"
+
+namespace eu {
+namespace impl {
+
+inline int clamp_grid(int64_t want, int cap)
+{
+    if (want < 1) return 1;
+    return want > cap ? cap : (int)want;
+}
+
+template <typename T> T *arr(const View &v, int a)
+{
+    return (T *)(a == ARR_Q ? v.Q : a == ARR_QS ? v.Qs : v.Qo);
+}
+
+template <typename T> void init(const View &v, const InitArgs &a, int grid, int64_t ncell, hipStream_t s)
+{
+    const int nblk = clamp_grid((ncell + 255) / 256, 8192);
+    if (v.dim == 2) k_init<T, 2><<<nblk, 256, 0, s>>>(v, a, grid, (T *)v.Q);
+    else k_init<T, 3><<<nblk, 256, 0, s>>>(v, a, grid, (T *)v.Q);
+}
+
+template <typename T> void restrict_full(const View &v, int a, int gc, int64_t ncell, hipStream_t s)
+{
+    const int nblk = clamp_grid((ncell + 255) / 256, 8192);
+    if (v.dim == 2) k_restrict_full<T, 2><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), gc);
+    else k_restrict_full<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), gc);
+}
+
+template <typename T> void restrict_cov(const View &v, int a, int lvl, int maxb, hipStream_t s)
+{
+    const int nblk = clamp_grid(maxb, 4096);
+    if (v.dim == 2) k_restrict_cov<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl);
+    else k_restrict_cov<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl);
+}
+
+template <typename T> void predict(const View &v, int a, int lvl, int ghost, int maxb, hipStream_t s)
+{
+    const int nblk = clamp_grid(maxb, 4096);
+    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, ghost);
+    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, ghost);
+}
+
+template <typename T> void fv_stage(const View &v, int stage, int maxt, hipStream_t s)
+{
+    const int nblk = clamp_grid(maxt, 16384);
+    const T *src = (const T *)(stage == 1 ? v.Q : v.Qs);
+    T *out = (T *)(stage == 1 ? v.Qs : v.Q);
+    const double fac = stage == 1 ? 0.5 : 1.0;
+    if (v.dim == 2) k_fv_stage<T, 2><<<nblk, FV<2>::NT, 0, s>>>(v, src, (const T *)v.Q, out, fac);
+    else k_fv_stage<T, 3><<<nblk, FV<3>::NT, 0, s>>>(v, src, (const T *)v.Q, out, fac);
+}
+
+template <typename T> void cfl(const View &v, int maxt, hipStream_t s)
+{
+    const int nblk = clamp_grid(maxt, 8192);
+    if (v.dim == 2) k_cfl<T, 2><<<nblk, 64, 0, s>>>(v, (const T *)v.Q);
+    else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
+}
+
+template <typename T> void totals(const View &v, int maxt, hipStream_t s)
+{
+    const int nblk = clamp_grid(maxt, 8192);
+    if (v.dim == 2) k_totals<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
+    else k_totals<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
+}
+
+template <typename T> void details(const View &v, int lvl, int64_t ncell, hipStream_t s)
+{
+    const int nblk = clamp_grid((ncell + 255) / 256, 8192);
+    if (v.dim == 2) k_details<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q, lvl);
+    else k_details<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q, lvl);
+}
+
+template <typename T> KSet make()
+{
+    KSet k;
+    k.elem = sizeof(T);
+    k.init = init<T>;
+    k.restrict_full = restrict_full<T>;
+    k.restrict_cov = restrict_cov<T>;
+    k.predict = predict<T>;
+    k.fv_stage = fv_stage<T>;
+    k.cfl = cfl<T>;
+    k.totals = totals<T>;
+    k.details = details<T>;
+    return k;
+}
+
+}  // namespace impl
+}  // namespace eu

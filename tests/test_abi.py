@@ -1,0 +1,97 @@
+"""The C-ABI library loads, exports every entry point of include/eu.h, and its
+host-only logic (configuration checks, buffer sizing) behaves; no GPU needed."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_1603_05211_amd import _abi
+
+
+def declared_entry_points():
+    text = open(_abi.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(eu_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    names = declared_entry_points()
+    assert len(names) >= 20
+    assert sorted(_abi.SIGNATURES) == names
+
+
+def test_library_exports_every_symbol():
+    lib = _abi.load()
+    for name in declared_entry_points():
+        assert hasattr(lib, name), name
+
+
+def cfg(**kw):
+    c = _abi.EuConfig()
+    c.dim, c.precision, c.gamma, c.lo, c.hi = 2, _abi.EU_FP64, 1.4, 0.0, 1.0
+    c.n0, c.levels, c.bc, c.cfl, c.t_end = 32, 5, 0, 0.45, math.inf
+    c.eps, c.eta, c.patch_min, c.patch_max, c.time_mode = 1e-3, 0.8, 8, 32, 0
+    c.n_instances = 1
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def sizes(c):
+    lib = _abi.load()
+    s, k = C.c_size_t(0), C.c_size_t(0)
+    r = lib.eu_query_sizes(C.byref(c), C.byref(s), C.byref(k))
+    return r, s.value, k.value
+
+
+def test_query_sizes_dense_levels():
+    r, s, k = sizes(cfg())
+    assert r == _abi.EU_OK
+    cells = sum((32 << l) ** 2 for l in range(5))
+    assert s >= 2 * 4 * 8 * cells and s < 2 * 4 * 8 * cells + 4096
+    r32, s32, _ = sizes(cfg(precision=_abi.EU_FP32))
+    assert r32 == 0 and s32 < s
+    r3, s3, _ = sizes(cfg(dim=3, n0=32, levels=4, lo=-1.0))
+    assert r3 == 0 and s3 >= 2 * 5 * 8 * sum((32 << l) ** 3 for l in range(4))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=4), dict(precision=7), dict(gamma=1.0), dict(hi=0.0), dict(n0=24), dict(n0=4),
+    dict(levels=0), dict(levels=11), dict(patch_min=16), dict(patch_max=48), dict(eta=0.0),
+    dict(eps=-1.0), dict(cfl=0.0), dict(bc=5), dict(time_mode=3), dict(n0=8, patch_max=32),
+])
+def test_invalid_configurations_rejected(bad):
+    r, _, _ = sizes(cfg(**bad))
+    assert r == _abi.EU_EINVAL
+
+
+def test_batch_sizes():
+    sides = (C.c_int32 * 3)(32, 64, 96)
+    c = cfg(levels=1, n_instances=3, inst_side_host=C.cast(sides, C.POINTER(C.c_int32)))
+    r, s, _ = sizes(c)
+    assert r == 0 and s >= 2 * 4 * 8 * (32 ** 2 + 64 ** 2 + 96 ** 2)
+    bad = (C.c_int32 * 2)(32, 20)
+    c = cfg(levels=1, n_instances=2, inst_side_host=C.cast(bad, C.POINTER(C.c_int32)))
+    assert sizes(c)[0] == _abi.EU_EINVAL
+
+
+def test_create_rejects_small_or_null_buffers():
+    lib = _abi.load()
+    c = cfg()
+    ctx = C.c_void_p()
+    assert lib.eu_create(C.byref(c), None, 0, None, 0, C.byref(ctx)) == _abi.EU_EINVAL
+    # non-null but too small: rejected before any device access
+    assert lib.eu_create(C.byref(c), C.c_void_p(256), 256, C.c_void_p(512), 256,
+                         C.byref(ctx)) == _abi.EU_ENOMEM
+    # misaligned
+    assert lib.eu_create(C.byref(c), C.c_void_p(100), 1 << 40, C.c_void_p(512), 1 << 40,
+                         C.byref(ctx)) == _abi.EU_EINVAL
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = _abi.load()
+    assert lib.eu_step(None, 1) == _abi.EU_EINVAL
+    assert lib.eu_destroy(None) == _abi.EU_EINVAL
+    assert lib.eu_last_error(None) == b"null context"
