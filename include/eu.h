@@ -152,14 +152,16 @@ int eu_project(eu_ctx *ctx, int mode);
 /* CFL time step (FP64): dt = min over levels cfl dx_l / max over leaves of
  * sum_d (|v_d| + c), clipped to reach t_end, per instance for a batch.  The
  * result stays on the device for eu_fv_step; dt_host (nullable) receives it
- * (instance 0).  Detects non-physical leaves (EU_ENONPHYS at the next
- * synchronising call). */
+ * (instance 0).  Computing dt commits the step it sizes: the context time
+ * advances to t + dt here (a step starting at t >= t_end is marked done and
+ * every later kernel of that step does nothing).  Detects non-physical
+ * leaves (EU_ENONPHYS at the next synchronising call). */
 int eu_cfl_dt(eu_ctx *ctx, double *dt_host);
 
 /* One explicit midpoint (RK2) step of every leaf with the device dt of the
  * last eu_cfl_dt (Sec. 2): Q* = Q - dt/2 F(Q), Q <- Q - dt F(Q*), each
  * stage followed by projection onto covered cells and ghost fill; faces
- * between a leaf and a covered cell take the mean of the fine fluxes; t += dt.
+ * between a leaf and a covered cell take the mean of the fine fluxes.
  * In EU_DT_LTS mode one call advances one level-0 step with the recursive
  * level cycle (Sec. 2.2, Fig. 2). */
 int eu_fv_step(eu_ctx *ctx);

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -81,11 +82,12 @@ struct Layout {
     int64_t state_elems = 0;
     int narrays = 2;
     int64_t nbt = 0, ncoarse = 0, nslot = 0, max_tiles = 0, max_patch = 0;
+    int ncls = 1;
     int ngroups = 1;
     std::vector<int64_t> pbase;
     // scratch offsets
-    size_t o_grids, o_act, o_nact, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
-        o_pcnt, o_pbase, o_patches, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
+    size_t o_grids, o_act, o_nact, o_code, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
+        o_pcnt, o_fcnt, o_cpart, o_pbase, o_patches, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
     size_t scratch = 0, state = 0;
 };
 
@@ -186,6 +188,7 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_grids = take(sizeof(Grid) * lay.ngrid);
     lay.o_act = take(lay.nbt);
     lay.o_nact = take(lay.nbt);
+    lay.o_code = take(lay.nbt);
     lay.o_sig = take(lay.ncoarse);
     lay.o_flag = take(lay.ncoarse);
     lay.o_D = take(8 * lay.ncoarse);
@@ -195,6 +198,9 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_fresh = take(sizeof(Tile) * lay.nbt);
     lay.o_pslot = take(sizeof(int) * 5 * lay.nslot * nsub);
     lay.o_pcnt = take(sizeof(int) * lay.nslot);
+    lay.o_fcnt = take(sizeof(int) * lay.nslot);
+    lay.ncls = (int)std::min<int64_t>(std::max<int64_t>((lay.nbt + 255) / 256, 1), 256);
+    lay.o_cpart = take(sizeof(long long) * 4 * eu::MAXLEV * lay.ncls);
     lay.o_pbase = take(sizeof(int64_t) * (eu::MAXLEV + 1));
     lay.o_patches = take(sizeof(int) * 5 * lay.max_patch);
     lay.o_meta = take(sizeof(Meta));
@@ -241,11 +247,7 @@ void seq_ghost(eu_ctx *c, int arr)
     if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, (int)(c->nbt), c->stream);
 }
 
-void seq_cfl(eu_ctx *c)
-{
-    c->ks->cfl(c->v, c->max_tiles, c->stream);
-    launch_cfl_finalize(c->v, c->stream);
-}
+void seq_cfl(eu_ctx *c) { c->ks->cfl(c->v, c->max_tiles, c->stream); }
 
 void prof_begin(eu_ctx *c, hipEvent_t *a)
 {
@@ -277,23 +279,23 @@ void seq_fv_step(eu_ctx *c, bool ghost_after)
     prof_end(c, e);
     seq_restrict(c, ARR_Q);
     if (ghost_after) seq_ghost(c, ARR_Q);
-    launch_time_advance(c->v, c->stream);
 }
 
 void seq_details(eu_ctx *c)
 {
-    for (int l = 0; l < c->L - 1; ++l) c->ks->details(c->v, l, c->grids[l].ncell, c->stream);
+    if (c->L < 2) return;
+    int64_t n = 0;
+    for (int l = 0; l < c->L - 1; ++l) n += c->grids[l].ncell;
+    c->ks->details(c->v, n, c->stream);
 }
 
 // flags, closure and tiling (finest first), lists, then optional prediction
 // of new cells (coarse to fine) and ghost fill.
 void seq_flag_tile(eu_ctx *c, bool prolong)
 {
-    launch_zero_meta_flags(c->v, c->stream);
     for (int l = c->L - 2; l >= 0; --l) {
-        launch_flags(c->v, l, c->grids[l].ncell, c->stream);
         const int nbp = c->grids[l + 1].n / c->cfg.patch_max;
-        launch_tile(c->v, l, (int)ipow(nbp, c->dim), c->stream);
+        launch_flag_tile(c->v, l, (int)ipow(nbp, c->dim), c->stream);
     }
     launch_build_lists(c->v, c->nbt, c->stream);
     if (prolong)
@@ -475,6 +477,8 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.grids = at<Grid>(scratch_dev, lay.o_grids);
     v.act = at<uint8_t>(scratch_dev, lay.o_act);
     v.nact = at<uint8_t>(scratch_dev, lay.o_nact);
+    v.code = at<uint8_t>(scratch_dev, lay.o_code);
+    v.nslot = lay.nslot;
     v.sig = at<uint8_t>(scratch_dev, lay.o_sig);
     v.flag = at<uint8_t>(scratch_dev, lay.o_flag);
     v.D = at<double>(scratch_dev, lay.o_D);
@@ -484,6 +488,9 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.fresh = at<Tile>(scratch_dev, lay.o_fresh);
     v.pslot = at<int>(scratch_dev, lay.o_pslot);
     v.pcnt = at<int>(scratch_dev, lay.o_pcnt);
+    v.fcnt = at<int>(scratch_dev, lay.o_fcnt);
+    v.cpart = at<long long>(scratch_dev, lay.o_cpart);
+    v.ncls = lay.ncls;
     v.pbase = at<int64_t>(scratch_dev, lay.o_pbase);
     v.patches = at<int>(scratch_dev, lay.o_patches);
     v.meta = at<Meta>(scratch_dev, lay.o_meta);

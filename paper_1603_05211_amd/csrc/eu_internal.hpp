@@ -42,6 +42,8 @@ struct Meta {
     int done;                  // the current step starts at t >= t_end: skip it
     int steps;                 // steps taken since initialisation
     long long leaf_updates;    // leaf cells advanced since initialisation
+    unsigned int ticket;       // blocks of the CFL reduction that have finished
+    int pad_;
     int cov_off[MAXLEV], cov_cnt[MAXLEV];   // per-level ranges of the covered-block list
     int new_off[MAXLEV], new_cnt[MAXLEV];   // per-level ranges of the new-block list
     int nflag[MAXLEV];                      // flagged cells per level
@@ -60,10 +62,15 @@ struct View {
     void *Q, *Qs, *Qo;                // state arrays (element type per precision)
     uint8_t *act, *nact;              // per-block patch membership (current / new)
     uint8_t *sig, *flag;              // per-cell significance and refinement flags
+    uint8_t *code;                    // per-block classification of the new hierarchy
     double *D;                        // per-cell FP64 detail norm
     Tile *leaf, *cov, *ghost, *fresh; // work lists
     int *pslot;                       // per pmax-block patch slots (5 ints each)
     int *pcnt;                        // per pmax-block patch counts
+    int *fcnt;                        // per pmax-block flagged-cell counts
+    long long *cpart;                 // per classification workgroup and level:
+                                      // leaf cells, patch cells, covered blocks, new blocks
+    int ncls;                         // workgroups of the classification kernel
     int64_t *pbase;                   // per-level offset into pslot / pcnt
     int *patches;                     // compacted patch table (5 ints per row)
     Meta *meta;
@@ -72,6 +79,7 @@ struct View {
     double *partial;                  // per tile x nv partial totals
     double *totals;                   // per group x nv
     const int *grp_off, *grp_cnt;     // batch: tile range of each instance
+    int64_t nslot;                    // pmax blocks of levels 1 .. L-1
     int max_tiles;                    // capacity of the leaf list
     int max_patch;                    // capacity of the patch table
 };

@@ -403,18 +403,74 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac)
 }
 
 // ----------------------------------------------------------------------------
-// CFL reduction over leaves (FP64): per-grid max of sum_d (|v_d| + c)
+// CFL reduction over leaves (FP64): per-grid max of sum_d (|v_d| + c); the
+// last block to finish turns the maxima into dt (finalisation below).
 // ----------------------------------------------------------------------------
+// dt = min over levels of cfl dx_l / smax_l (hierarchy) or per instance
+// (batch), clipped to reach t_end.  A step that starts at t >= t_end is
+// marked done and skipped by every later kernel of the step; otherwise the
+// step is committed: t += dt, steps += 1, leaf updates counted.
+__device__ void cfl_finalize(const View &v)
+{
+    if (v.mode == MODE_HIER) {
+        if (threadIdx.x != 0) return;
+        double dt = __builtin_inf();
+        for (int g = 0; g < v.ngrid; ++g) {
+            const unsigned long long b = atomicExch(&v.smax[g], 0ull);
+            if (b) {
+                const double s = __longlong_as_double((long long)b);
+                const double dtl = (v.cfl * v.grids[g].dx) / s;
+                if (dtl < dt) dt = dtl;
+            }
+        }
+        const double t = v.t[0];
+        const int done = t < v.t_end ? 0 : 1;
+        if (dt > v.t_end - t) dt = v.t_end - t;
+        v.dt[0] = dt;
+        v.meta->done = done;
+        if (!done) {
+            v.t[0] = t + dt;
+            v.meta->steps += 1;
+            long long s = 0;
+            for (int l = 0; l < v.L; ++l) s += v.meta->leaf_cells[l];
+            v.meta->leaf_updates += s;
+        }
+        v.meta->ticket = 0u;
+        return;
+    }
+    for (int g = threadIdx.x; g < v.ngrid; g += blockDim.x) {
+        const unsigned long long b = atomicExch(&v.smax[g], 0ull);
+        const double s = __longlong_as_double((long long)b);
+        double dt = b ? (v.cfl * v.grids[g].dx) / s : 0.0;
+        const double t = v.t[g];
+        if (dt > v.t_end - t) dt = v.t_end - t;
+        if (!(dt > 0.0)) dt = 0.0;
+        v.dt[g] = dt;
+        v.t[g] = t + dt;
+    }
+    if (threadIdx.x == 0) {
+        v.meta->done = 0;
+        v.meta->steps += 1;
+        v.meta->ticket = 0u;
+    }
+}
+
+// One wave per tile; each block folds its waves' maxima per level before one
+// atomic per level (hierarchy) or per tile (batch).
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
 {
 #pragma clang fp contract(off)
-    __shared__ double sm[4];
-    if (v.meta->done) return;
+    __shared__ double lmax[4][MAXLEV];
+    __shared__ int last;
     const int count = v.meta->nleaf;
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     const double g = v.gamma;
-    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const bool hier = v.mode == MODE_HIER;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < MAXLEV) lmax[wave][lane] = 0.0;
+    bool bad = false;
+    for (int t = blockIdx.x * 4 + wave; t < count; t += gridDim.x * 4) {
         const Tile tl = v.leaf[t];
         const Grid G = v.grids[tl.grid];
         const int n = G.n, nb = G.nb;
@@ -422,8 +478,7 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
         const int oy = ((tl.block / nb) % nb) * BS;
         const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
         double m = 0.0;
-        bool bad = false;
-        for (int c = threadIdx.x; c < TC; c += blockDim.x) {
+        for (int c = lane; c < TC; c += 64) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
             if (covered(v, v.act, G, x, y, z)) continue;
             const int64_t id = G.off + gidx(n, x, y, z);
@@ -442,16 +497,31 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
             const double r = __shfl_xor(m, o);
             m = r > m ? r : m;
         }
-        if (bad) atomicOr(&v.meta->status, 1);
-        if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double mm = sm[0];
-            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) mm = sm[k] > mm ? sm[k] : mm;
-            if (mm > 0.0)
-                atomicMax(&v.smax[tl.grid], (unsigned long long)__double_as_longlong(mm));
+        if (lane == 0) {
+            if (hier) {
+                if (m > lmax[wave][tl.grid]) lmax[wave][tl.grid] = m;
+            } else if (m > 0.0) {
+                atomicMax(&v.smax[tl.grid], (unsigned long long)__double_as_longlong(m));
+            }
         }
-        __syncthreads();
+    }
+    if (__any(bad) && lane == 0) atomicOr(&v.meta->status, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (hier)
+            for (int l = 0; l < v.ngrid; ++l) {
+                double mm = lmax[0][l];
+                for (int w = 1; w < 4; ++w) mm = lmax[w][l] > mm ? lmax[w][l] : mm;
+                if (mm > 0.0) atomicMax(&v.smax[l], (unsigned long long)__double_as_longlong(mm));
+            }
+        __threadfence();
+        const unsigned int prev = atomicAdd(&v.meta->ticket, 1u);
+        last = prev == gridDim.x - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        cfl_finalize(v);
     }
 }
 
@@ -595,19 +665,37 @@ __global__ void __launch_bounds__(256) k_restrict_cov(View v, T *A, int lvl)
 }
 
 // ghost cell: outside every patch of its level, within two cells of a patch
+// (cells c-2 .. c+2 lie in at most three blocks per axis; loads issued first)
 template <int D>
 __device__ __forceinline__ bool is_ghost(const View &v, const Grid &G, int x, int y, int z)
 {
     const int n = G.n;
     if (block_active(v, v.act, G, x, y, z)) return false;
-    const int r3 = D == 3 ? 2 : 0;
-    for (int dz = -r3; dz <= r3; ++dz)
-        for (int dy = -2; dy <= 2; ++dy)
-            for (int dx = -2; dx <= 2; ++dx)
-                if (block_active(v, v.act, G, bcmap(x + dx, n, v.bc), bcmap(y + dy, n, v.bc),
-                                 D == 3 ? bcmap(z + dz, n, v.bc) : 0))
-                    return true;
-    return false;
+    int b[3][3], nb[3];
+    const int c[3] = {x, y, z};
+    for (int d = 0; d < 3; ++d) {
+        nb[d] = 0;
+        if (d >= D) { b[d][0] = 0; nb[d] = 1; continue; }
+        for (int o = -2; o <= 2; ++o) {
+            const int q = bcmap(c[d] + o, n, v.bc) >> 3;
+            bool seen = false;
+            for (int j = 0; j < nb[d]; ++j) seen |= b[d][j] == q;
+            if (!seen) b[d][nb[d]++] = q;
+        }
+    }
+    uint8_t a[27];
+    int j = 0;
+    for (int kz = 0; kz < 3; ++kz)
+        for (int ky = 0; ky < 3; ++ky)
+            for (int kx = 0; kx < 3; ++kx) {
+                a[j] = (kx < nb[0] && ky < nb[1] && kz < nb[2])
+                           ? v.act[G.boff + b[0][kx] + (int64_t)G.nb * (b[1][ky] + (int64_t)G.nb * b[2][kz])]
+                           : 0;
+                ++j;
+            }
+    int hit = 0;
+    for (int i = 0; i < 27; ++i) hit |= a[i];
+    return hit != 0;
 }
 
 // Fill ghost cells (ghost list) or newly created cells (new list of level
@@ -641,18 +729,22 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int ghos
 }
 
 // ----------------------------------------------------------------------------
-// MR details (FP64) of every refined cell of level lvl; dense over the level
+// MR details (FP64) of every refined cell of levels 0 .. L-2, one launch over
+// the concatenated cells of those levels
 // ----------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q, int lvl)
+__global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q, int64_t ntot)
 {
 #pragma clang fp contract(off)
     if (v.meta->done) return;
-    const Grid G = v.grids[lvl];
-    const Grid F = v.grids[G.fine];
-    const int n = G.n;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.ncell;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ntot;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int lvl = 0;
+        while (lvl + 1 < v.L - 1 && j >= v.grids[lvl + 1].coff) ++lvl;
+        const Grid G = v.grids[lvl];
+        const Grid F = v.grids[G.fine];
+        const int n = G.n;
+        const int64_t i = j - G.coff;
         const int x = (int)(i % n), y = (int)((i / n) % n), z = D == 3 ? (int)(i / ((int64_t)n * n)) : 0;
         double Dm = 0.0;
         if (block_active(v, v.act, G, x, y, z) && covered(v, v.act, G, x, y, z)) {
@@ -666,8 +758,8 @@ __global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q
                 if (dd > Dm) Dm = dd;
             }
         }
-        v.D[G.coff + i] = Dm;
-        v.sig[G.coff + i] = Dm >= v.eps ? 1 : 0;
+        v.D[j] = Dm;
+        v.sig[j] = Dm >= v.eps ? 1 : 0;
     }
 }
 

@@ -31,20 +31,16 @@ struct KSet {
     void (*fv_stage)(const View &, int stage, int maxtiles, hipStream_t);
     void (*cfl)(const View &, int maxtiles, hipStream_t);
     void (*totals)(const View &, int maxtiles, hipStream_t);
-    void (*details)(const View &, int lvl, int64_t ncell, hipStream_t);
+    void (*details)(const View &, int64_t ncell_coarse_levels, hipStream_t);
 };
 
 extern const KSet kset_f64;
 extern const KSet kset_f32;
 
 // precision-independent mesh kernels (eu_mesh.hip)
-void launch_cfl_finalize(const View &, hipStream_t);
-void launch_time_advance(const View &, hipStream_t);
-void launch_flags(const View &, int lvl, int64_t ncell, hipStream_t);
-void launch_tile(const View &, int lvl, int nblocks, hipStream_t);
+void launch_flag_tile(const View &, int lvl, int nblocks, hipStream_t);
 void launch_build_lists(const View &, int64_t nblocks_total, hipStream_t);
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t val, hipStream_t);
-void launch_zero_meta_flags(const View &, hipStream_t);
 void launch_totals_final(const View &, int ngroups, hipStream_t);
 
 }  // namespace eu

@@ -34,14 +34,14 @@ template <typename T> void restrict_full(const View &v, int a, int gc, int64_t n
 
 template <typename T> void restrict_cov(const View &v, int a, int lvl, int maxb, hipStream_t s)
 {
-    const int nblk = clamp_grid(maxb, 4096);
+    const int nblk = clamp_grid(maxb, 1024);
     if (v.dim == 2) k_restrict_cov<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl);
     else k_restrict_cov<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl);
 }
 
 template <typename T> void predict(const View &v, int a, int lvl, int ghost, int maxb, hipStream_t s)
 {
-    const int nblk = clamp_grid(maxb, 4096);
+    const int nblk = clamp_grid(maxb, 1024);
     if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, ghost);
     else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, ghost);
 }
@@ -58,8 +58,10 @@ template <typename T> void fv_stage(const View &v, int stage, int maxt, hipStrea
 
 template <typename T> void cfl(const View &v, int maxt, hipStream_t s)
 {
-    const int nblk = clamp_grid(maxt, 8192);
-    if (v.dim == 2) k_cfl<T, 2><<<nblk, 64, 0, s>>>(v, (const T *)v.Q);
+    // few blocks (one wave per tile): each folds its tiles before one atomic
+    // per level, and the last block to finish computes dt
+    const int nblk = clamp_grid((maxt + 3) / 4, 128);
+    if (v.dim == 2) k_cfl<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
 }
 
@@ -70,11 +72,11 @@ template <typename T> void totals(const View &v, int maxt, hipStream_t s)
     else k_totals<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
 }
 
-template <typename T> void details(const View &v, int lvl, int64_t ncell, hipStream_t s)
+template <typename T> void details(const View &v, int64_t ncell, hipStream_t s)
 {
     const int nblk = clamp_grid((ncell + 255) / 256, 8192);
-    if (v.dim == 2) k_details<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q, lvl);
-    else k_details<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q, lvl);
+    if (v.dim == 2) k_details<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q, ncell);
+    else k_details<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q, ncell);
 }
 
 template <typename T> KSet make()

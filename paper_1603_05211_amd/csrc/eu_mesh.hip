@@ -1,138 +1,106 @@
-// eu_mesh.hip -- precision-independent kernels: CFL time-step finalisation,
-// time advance, refinement flags with buffer and nesting closure, patch
-// tiling with the efficiency rule, work-list construction, totals.
-// Built with -ffp-contract=off.
+// eu_mesh.hip -- precision-independent kernels: refinement flags with buffer
+// and nesting closure fused with the patch tiling (efficiency rule), work-list
+// construction (parallel classification + one-workgroup compaction), fills,
+// totals.  Built with -ffp-contract=off.
 #include "eu_kernels.hpp"
 
 namespace eu {
 
 // ----------------------------------------------------------------------------
-// dt = min over levels of cfl dx_l / smax_l (hierarchy) or per instance
-// (batch), clipped to reach t_end; a step starting at t >= t_end is skipped
-// by every later kernel of the step (meta->done).
+// refinement flag of level-lvl cell (x, y, z): it decides whether the cell's
+// children belong to level lvl+1 of the new hierarchy
 // ----------------------------------------------------------------------------
-__global__ void k_cfl_finalize(View v)
+// Distinct blocks (block side 8 at level side n) touched by cells
+// c + lo .. c + hi through the boundary map; at most 3 for hi - lo <= 5 at
+// half resolution, returned in out[], count returned.
+__device__ __forceinline__ int distinct_blocks(int c0, int lo, int hi, int n, int bc, int shift, int *out)
 {
-    if (v.mode == MODE_HIER) {
-        if (threadIdx.x != 0 || blockIdx.x != 0) return;
-        double dt = __builtin_inf();
-        for (int g = 0; g < v.ngrid; ++g) {
-            const unsigned long long b = v.smax[g];
-            if (b) {
-                const double s = __longlong_as_double((long long)b);
-                const double dtl = (v.cfl * v.grids[g].dx) / s;
-                if (dtl < dt) dt = dtl;
-            }
-            v.smax[g] = 0ull;
-        }
-        const double t = v.t[0];
-        v.meta->done = t < v.t_end ? 0 : 1;
-        if (dt > v.t_end - t) dt = v.t_end - t;
-        v.dt[0] = dt;
-        return;
+    int k = 0;
+    for (int o = lo; o <= hi; ++o) {
+        const int b = bcmap(c0 + o, n, bc) >> shift;
+        bool seen = false;
+        for (int j = 0; j < k; ++j) seen |= out[j] == b;
+        if (!seen) out[k++] = b;
     }
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < v.ngrid; g += gridDim.x * blockDim.x) {
-        const unsigned long long b = v.smax[g];
-        const double s = __longlong_as_double((long long)b);
-        double dt = b ? (v.cfl * v.grids[g].dx) / s : 0.0;
-        const double t = v.t[g];
-        if (dt > v.t_end - t) dt = v.t_end - t;
-        v.dt[g] = dt;
-        v.smax[g] = 0ull;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) v.meta->done = 0;
+    return k;
 }
 
-__global__ void k_time_advance(View v)
-{
-    if (v.meta->done) return;
-    const int ng = v.mode == MODE_HIER ? 1 : v.ngrid;
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += gridDim.x * blockDim.x)
-        v.t[g] = v.t[g] + v.dt[g];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        v.meta->steps += 1;
-        if (v.mode == MODE_HIER) {
-            long long s = 0;
-            for (int l = 0; l < v.L; ++l) s += v.meta->leaf_cells[l];
-            v.meta->leaf_updates += s;
-        }
-    }
-}
-
-__global__ void k_zero_nflag(View v)
-{
-    if (v.meta->done) return;
-    if (threadIdx.x < MAXLEV) v.meta->nflag[threadIdx.x] = 0;
-}
-
-// ----------------------------------------------------------------------------
-// refinement flags of level lvl (decide level lvl+1 of the new hierarchy)
-// ----------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(256) k_flags(View v, int lvl)
+__device__ __forceinline__ bool refine_flag(const View &v, const Grid &G, int lvl, int x, int y, int z)
 {
-    if (v.meta->done) return;
-    const Grid G = v.grids[lvl];
     const int n = G.n;
-    const bool has2 = lvl + 2 < v.L;
-    int cnt = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.ncell;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % n), y = (int)((i / n) % n), z = D == 3 ? (int)(i / ((int64_t)n * n)) : 0;
-        bool fl = false;
-        const int r3 = D == 3 ? 1 : 0;
-        // raw flags (significant details; preventive refinement of the
-        // children of significant cells), dilated by one cell
-        for (int dz = -r3; dz <= r3 && !fl; ++dz)
-            for (int dy = -1; dy <= 1 && !fl; ++dy)
-                for (int dx = -1; dx <= 1 && !fl; ++dx) {
-                    const int qx = bcmap(x + dx, n, v.bc), qy = bcmap(y + dy, n, v.bc);
-                    const int qz = D == 3 ? bcmap(z + dz, n, v.bc) : 0;
-                    if (v.sig[G.coff + gidx(n, qx, qy, qz)]) fl = true;
-                    else if (lvl >= 1) {
-                        const Grid &Cg = v.grids[G.coarse];
-                        if (v.sig[Cg.coff + gidx(Cg.n, qx >> 1, qy >> 1, qz >> 1)]) fl = true;
-                    }
+    constexpr int R3 = D == 3 ? 1 : 0;
+    constexpr int NN = D == 3 ? 27 : 9;
+    // raw flags (significant details; preventive refinement of the children
+    // of significant cells), dilated by one cell; all loads issued first
+    uint8_t s[NN], sp[NN];
+    int k = 0;
+#pragma unroll
+    for (int dz = -R3; dz <= R3; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int qx = bcmap(x + dx, n, v.bc), qy = bcmap(y + dy, n, v.bc);
+                const int qz = D == 3 ? bcmap(z + dz, n, v.bc) : 0;
+                s[k] = v.sig[G.coff + gidx(n, qx, qy, qz)];
+                sp[k] = 0;
+                if (lvl >= 1) {
+                    const Grid &Cg = v.grids[G.coarse];
+                    sp[k] = v.sig[Cg.coff + gidx(Cg.n, qx >> 1, qy >> 1, qz >> 1)];
                 }
-        // nesting: level-(lvl+1) cells within two cells of a level-(lvl+1)
-        // cell covered by the new level lvl+2
-        if (!fl && has2) {
-            const Grid &F = v.grids[G.fine];
-            const Grid &F2 = v.grids[F.fine];
-            const int nf = F.n;
-            const int z0 = D == 3 ? -2 : 0, z1 = D == 3 ? 3 : 0;
-            for (int dz = z0; dz <= z1 && !fl; ++dz)
-                for (int dy = -2; dy <= 3 && !fl; ++dy)
-                    for (int dx = -2; dx <= 3 && !fl; ++dx) {
-                        const int qx = bcmap(2 * x + dx, nf, v.bc), qy = bcmap(2 * y + dy, nf, v.bc);
-                        const int qz = D == 3 ? bcmap(2 * z + dz, nf, v.bc) : 0;
-                        if (v.nact[F2.boff + (qx >> 2) + (int64_t)F2.nb * ((qy >> 2) + (int64_t)F2.nb * (qz >> 2))])
-                            fl = true;
-                    }
-        }
-        v.flag[G.coff + i] = fl ? 1 : 0;
-        cnt += fl ? 1 : 0;
+                ++k;
+            }
+    int any = 0;
+#pragma unroll
+    for (int j = 0; j < NN; ++j) any |= s[j] | sp[j];
+    if (any) return true;
+    // nesting: level-(lvl+1) cells within two cells of a level-(lvl+1) cell
+    // covered by the new level lvl+2; cells 2x-2 .. 2x+3 of level lvl+1 lie
+    // in at most three blocks of level lvl+2 per axis
+    if (lvl + 2 < v.L) {
+        const Grid &F = v.grids[G.fine];
+        const Grid &F2 = v.grids[F.fine];
+        const int nf = F.n;
+        int bx[3], by[3], bz[3] = {0, 0, 0};
+        const int nx = distinct_blocks(2 * x, -2, 3, nf, v.bc, 2, bx);
+        const int ny = distinct_blocks(2 * y, -2, 3, nf, v.bc, 2, by);
+        const int nz = D == 3 ? distinct_blocks(2 * z, -2, 3, nf, v.bc, 2, bz) : 1;
+        uint8_t a[27];
+        int j = 0;
+        for (int kz = 0; kz < 3; ++kz)
+            for (int ky = 0; ky < 3; ++ky)
+                for (int kx = 0; kx < 3; ++kx) {
+                    a[j] = (kx < nx && ky < ny && kz < nz)
+                               ? v.nact[F2.boff + bx[kx] + (int64_t)F2.nb * (by[ky] + (int64_t)F2.nb * bz[kz])]
+                               : 0;
+                    ++j;
+                }
+        int hit = 0;
+        for (int i = 0; i < 27; ++i) hit |= a[i];
+        if (hit) return true;
     }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(&v.meta->nflag[lvl], cnt);
+    return false;
 }
 
 // ----------------------------------------------------------------------------
-// tiling of level lvl's flags into patches of level lvl+1: one 64-lane
-// workgroup per aligned pmax block (Morton index = blockIdx.x); counts per
-// BS-block in LDS, then the recursive split decided by lane 0 in the same
-// order as a depth-first recursion over children (x fastest).
+// flags of level lvl + tiling into patches of level lvl+1: one workgroup per
+// aligned pmax block of level lvl+1 (Morton index = blockIdx.x).  The
+// workgroup flags the block's coarse footprint, counts flags per BS-block in
+// LDS, and lane 0 takes the recursive split decisions in the order of a
+// depth-first recursion over children (x fastest).
 // ----------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(64) k_tile(View v, int lvl)
+__global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
 {
     if (v.meta->done) return;
     constexpr int MAXSUB = D == 2 ? 64 : 512;       // (pmax / BS)^D, pmax <= 64
     __shared__ int cnt8[MAXSUB];
     __shared__ uint8_t emit8[MAXSUB];
+    __shared__ int wsum[4];
     const Grid G = v.grids[lvl];
     const Grid F = v.grids[lvl + 1];
-    const int R = v.pmax / BS;                      // BS-blocks per pmax block side
+    const int R = v.pmax / BS;
     const int nsub = D == 2 ? R * R : R * R * R;
     const int m = blockIdx.x;
     int bp[3] = {0, 0, 0};
@@ -143,37 +111,47 @@ __global__ void __launch_bounds__(64) k_tile(View v, int lvl)
         for (int k = 0; k < bits; ++k)
             for (int d = 0; d < D; ++d) bp[d] |= ((m >> (k * D + d)) & 1) << k;
     }
-    // flagged parents per BS-block (coarse footprint (BS/2)^D)
-    for (int s = threadIdx.x; s < nsub; s += 64) {
-        const int sx = s % R, sy = (s / R) % R, sz = D == 3 ? s / (R * R) : 0;
-        const int cx = (bp[0] * v.pmax + sx * BS) / 2, cy = (bp[1] * v.pmax + sy * BS) / 2;
-        const int cz = D == 3 ? (bp[2] * v.pmax + sz * BS) / 2 : 0;
-        int c = 0;
-        const int hz = D == 3 ? BS / 2 : 1;
-        for (int z = 0; z < hz; ++z)
-            for (int y = 0; y < BS / 2; ++y)
-                for (int x = 0; x < BS / 2; ++x) c += v.flag[G.coff + gidx(G.n, cx + x, cy + y, cz + z)];
-        cnt8[s] = c;
+    for (int s = threadIdx.x; s < nsub; s += blockDim.x) {
+        cnt8[s] = 0;
         emit8[s] = 0;
     }
     __syncthreads();
+    const int hp = v.pmax / 2;
+    const int nfoot = D == 2 ? hp * hp : hp * hp * hp;
+    int mine = 0;
+    for (int k = threadIdx.x; k < nfoot; k += blockDim.x) {
+        const int lx = k % hp, ly = (k / hp) % hp, lz = D == 3 ? k / (hp * hp) : 0;
+        const int x = bp[0] * hp + lx, y = bp[1] * hp + ly, z = D == 3 ? bp[2] * hp + lz : 0;
+        const bool fl = refine_flag<D>(v, G, lvl, x, y, z);
+        v.flag[G.coff + gidx(G.n, x, y, z)] = fl ? 1 : 0;
+        if (fl) {
+            atomicAdd(&cnt8[(lx >> 2) + R * ((ly >> 2) + R * (lz >> 2))], 1);
+            ++mine;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = mine;
+    __syncthreads();
     if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
         const int64_t slot = v.pbase[lvl + 1] + m;
+        v.fcnt[slot] = tot;
         int *out = v.pslot + slot * (int64_t)nsub * 5;
         int np = 0;
-        short st[4 * 32];
-        int sp = 0;
-        st[0] = 0; st[1] = 0; st[2] = 0; st[3] = (short)R;
-        sp = 1;
-        while (sp) {
-            --sp;
-            const int ex = st[4 * sp], ey = st[4 * sp + 1], ez = st[4 * sp + 2], es = st[4 * sp + 3];
-            long long c = 0;
+        // flagged parents inside the block of es^D BS-blocks at (ex, ey, ez)
+        auto count = [&](int ex, int ey, int ez, int es) {
+            int c = 0;
             const int ezs = D == 3 ? es : 1;
-            for (int z = 0; z < ezs; ++z)
-                for (int y = 0; y < es; ++y)
-                    for (int x = 0; x < es; ++x) c += cnt8[(ex + x) + R * ((ey + y) + (D == 3 ? R * (ez + z) : 0))];
-            if (c == 0) continue;
+            for (int zz = 0; zz < ezs; ++zz)
+                for (int yy = 0; yy < es; ++yy)
+                    for (int xx = 0; xx < es; ++xx) c += cnt8[(ex + xx) + R * ((ey + yy) + R * (ez + zz))];
+            return c;
+        };
+        // 0: empty, 1: emitted as a patch, 2: to be split
+        auto decide = [&](int ex, int ey, int ez, int es) {
+            const int c = count(ex, ey, ez, es);
+            if (c == 0) return 0;
             const int S = es * BS, hsz = S / 2;
             const long long cells = D == 2 ? (long long)hsz * hsz : (long long)hsz * hsz * hsz;
             if (S == v.pmin || (double)c >= v.eta * (double)cells) {
@@ -183,25 +161,36 @@ __global__ void __launch_bounds__(64) k_tile(View v, int lvl)
                 out[5 * np + 3] = D == 3 ? bp[2] * v.pmax + ez * BS : 0;
                 out[5 * np + 4] = S;
                 ++np;
-                for (int z = 0; z < ezs; ++z)
-                    for (int y = 0; y < es; ++y)
-                        for (int x = 0; x < es; ++x)
-                            emit8[(ex + x) + R * ((ey + y) + (D == 3 ? R * (ez + z) : 0))] = 1;
-                continue;
+                const int ezs = D == 3 ? es : 1;
+                for (int zz = 0; zz < ezs; ++zz)
+                    for (int yy = 0; yy < es; ++yy)
+                        for (int xx = 0; xx < es; ++xx) emit8[(ex + xx) + R * ((ey + yy) + R * (ez + zz))] = 1;
+                return 1;
             }
-            const int hs = es / 2;
-            for (int k = (1 << D) - 1; k >= 0; --k) {
-                st[4 * sp] = (short)(ex + hs * (k & 1));
-                st[4 * sp + 1] = (short)(ey + hs * ((k >> 1) & 1));
-                st[4 * sp + 2] = (short)(D == 3 ? ez + hs * ((k >> 2) & 1) : 0);
-                st[4 * sp + 3] = (short)hs;
-                ++sp;
+            return 2;
+        };
+        constexpr int NC = 1 << D;
+        // depth-first over the split levels (R <= 8: at most four levels),
+        // children in x-fastest order
+        if (decide(0, 0, 0, R) == 2) {
+            const int h1 = R / 2;
+            for (int k1 = 0; k1 < NC; ++k1) {
+                const int x1 = h1 * (k1 & 1), y1 = h1 * ((k1 >> 1) & 1), z1 = h1 * ((k1 >> 2) & 1);
+                if (decide(x1, y1, z1, h1) != 2) continue;
+                const int h2 = h1 / 2;
+                for (int k2 = 0; k2 < NC; ++k2) {
+                    const int x2 = x1 + h2 * (k2 & 1), y2 = y1 + h2 * ((k2 >> 1) & 1), z2 = z1 + h2 * ((k2 >> 2) & 1);
+                    if (decide(x2, y2, z2, h2) != 2) continue;
+                    const int h3 = h2 / 2;
+                    for (int k3 = 0; k3 < NC; ++k3)
+                        decide(x2 + h3 * (k3 & 1), y2 + h3 * ((k3 >> 1) & 1), z2 + h3 * ((k3 >> 2) & 1), h3);
+                }
             }
         }
         v.pcnt[slot] = np;
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < nsub; s += 64) {
+    for (int s = threadIdx.x; s < nsub; s += blockDim.x) {
         const int sx = s % R, sy = (s / R) % R, sz = D == 3 ? s / (R * R) : 0;
         const int bx = bp[0] * R + sx, by = bp[1] * R + sy, bz = D == 3 ? bp[2] * R + sz : 0;
         v.nact[F.boff + bx + (int64_t)F.nb * (by + (int64_t)F.nb * bz)] = emit8[s];
@@ -209,185 +198,215 @@ __global__ void __launch_bounds__(64) k_tile(View v, int lvl)
 }
 
 // ----------------------------------------------------------------------------
-// work lists from the new hierarchy (one workgroup; deterministic order:
-// level, then block index x fastest); then current = new.
+// work lists of the new hierarchy
 // ----------------------------------------------------------------------------
-constexpr int LT = 1024;
-
-__device__ __forceinline__ void block_coords(int b, int nb, int D, int &x, int &y, int &z)
-{
-    x = b % nb;
-    y = (b / nb) % nb;
-    z = D == 3 ? b / (nb * nb) : 0;
-}
-
-// exclusive scan over the LT threads of K counters held in sc[K][LT]
-template <int K>
-__device__ void scan_lt(int (*sc)[LT], int *tot)
-{
-    for (int off = 1; off < LT; off <<= 1) {
-        int add[K];
-        for (int k = 0; k < K; ++k) add[k] = threadIdx.x >= (unsigned)off ? sc[k][threadIdx.x - off] : 0;
-        __syncthreads();
-        for (int k = 0; k < K; ++k) sc[k][threadIdx.x] += add[k];
-        __syncthreads();
-    }
-    // inclusive -> exclusive
-    int mine[K];
-    for (int k = 0; k < K; ++k) mine[k] = threadIdx.x ? sc[k][threadIdx.x - 1] : 0;
-    if (threadIdx.x == LT - 1)
-        for (int k = 0; k < K; ++k) tot[k] = sc[k][LT - 1];
-    __syncthreads();
-    for (int k = 0; k < K; ++k) sc[k][threadIdx.x] = mine[k];
-    __syncthreads();
-}
-
+// Per-block classification (one thread per block of every level):
+//   bit 0 leaf  (in a patch, not every child block in a finer patch)
+//   bit 1 cov   (in a patch, some child block in a finer patch)
+//   bit 2 ghost (level >= 1, in no patch, a neighbouring block in one)
+//   bit 3 fresh (level >= 1, in a patch now but not before)
+//   bits 4-7    number of child blocks in finer patches
+// then the block's current patch membership becomes the new one.
 template <int D>
-__device__ void classify(const View &v, int lvl, int b, bool &leaf, bool &cov, bool &ghost, bool &fresh,
-                         int &nleafcell)
+__global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
 {
-    const Grid &G = v.grids[lvl];
-    const int nb = G.nb;
-    int bx, by, bz;
-    block_coords(b, nb, D, bx, by, bz);
-    const bool a = v.nact[G.boff + b] != 0;
-    const bool old = v.act[G.boff + b] != 0;
-    int nchild = 0;
-    if (a && G.fine >= 0) {
-        const Grid &F = v.grids[G.fine];
-        const int zs = D == 3 ? 2 : 1;
-        for (int z = 0; z < zs; ++z)
-            for (int y = 0; y < 2; ++y)
-                for (int x = 0; x < 2; ++x)
-                    nchild += v.nact[F.boff + (2 * bx + x) + (int64_t)F.nb * ((2 * by + y) + (int64_t)F.nb * (2 * bz + z))];
-    }
-    const int nch_all = D == 2 ? 4 : 8;
-    leaf = a && nchild < nch_all;
-    cov = a && nchild > 0;
-    fresh = a && !old && lvl >= 1;
-    const int cpb = D == 2 ? BS * BS : BS * BS * BS;
-    const int cpc = D == 2 ? (BS / 2) * (BS / 2) : (BS / 2) * (BS / 2) * (BS / 2);
-    nleafcell = a ? cpb - nchild * cpc : 0;
-    ghost = false;
-    if (!a && lvl >= 1) {
-        const int r3 = D == 3 ? 1 : 0;
-        for (int dz = -r3; dz <= r3 && !ghost; ++dz)
-            for (int dy = -1; dy <= 1 && !ghost; ++dy)
-                for (int dx = -1; dx <= 1 && !ghost; ++dx) {
-                    const int qx = bcmap(bx + dx, nb, v.bc), qy = bcmap(by + dy, nb, v.bc);
-                    const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
-                    if (v.nact[G.boff + qx + (int64_t)nb * (qy + (int64_t)nb * qz)]) ghost = true;
-                }
-    }
-}
-
-template <int D>
-__global__ void __launch_bounds__(LT) k_build_lists(View v, int64_t nbt)
-{
-    __shared__ int sc[4][LT];
-    __shared__ int tot[4];
-    __shared__ int lvl_start[MAXLEV + 1];
-    __shared__ int covc[MAXLEV], newc[MAXLEV];
-    __shared__ long long leafcells[MAXLEV], actcells[MAXLEV];
+    __shared__ unsigned long long part[MAXLEV][4];
     if (v.meta->done) return;
-    if (threadIdx.x == 0) {
-        int64_t s = 0;
-        for (int l = 0; l < v.L; ++l) {
-            lvl_start[l] = (int)s;
-            const int nb = v.grids[l].nb;
-            s += D == 2 ? (int64_t)nb * nb : (int64_t)nb * nb * nb;
+    if (threadIdx.x < MAXLEV * 4) part[threadIdx.x / 4][threadIdx.x % 4] = 0ull;
+    __syncthreads();
+    constexpr int cpb = D == 2 ? BS * BS : BS * BS * BS;
+    constexpr int cpc = cpb >> D;   // cells of a coarse block covered by one child block
+    for (int64_t gb = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gb < nbt;
+         gb += (int64_t)gridDim.x * blockDim.x) {
+        int lvl = 0;
+        while (lvl + 1 < v.L && gb >= v.grids[lvl + 1].boff) ++lvl;
+        const Grid &G = v.grids[lvl];
+        const int nb = G.nb;
+        const int b = (int)(gb - G.boff);
+        const int bx = b % nb, by = (b / nb) % nb, bz = D == 3 ? b / (nb * nb) : 0;
+        const bool a = v.nact[gb] != 0;
+        const bool old = v.act[gb] != 0;
+        int nchild = 0;
+        if (a && G.fine >= 0) {
+            const Grid &F = v.grids[G.fine];
+            const int zs = D == 3 ? 2 : 1;
+            for (int z = 0; z < zs; ++z)
+                for (int y = 0; y < 2; ++y)
+                    for (int x = 0; x < 2; ++x)
+                        nchild += v.nact[F.boff + (2 * bx + x) + (int64_t)F.nb * ((2 * by + y) + (int64_t)F.nb * (2 * bz + z))];
         }
-        lvl_start[v.L] = (int)s;
-    }
-    if (threadIdx.x < MAXLEV) {
-        covc[threadIdx.x] = 0; newc[threadIdx.x] = 0;
-        leafcells[threadIdx.x] = 0; actcells[threadIdx.x] = 0;
-    }
-    __syncthreads();
-    const int64_t chunk = (nbt + LT - 1) / LT;
-    const int64_t b0 = threadIdx.x * chunk, b1 = b0 + chunk < nbt ? b0 + chunk : nbt;
-    int c[4] = {0, 0, 0, 0};
-    long long lc[MAXLEV], ac[MAXLEV];
-    int cc[MAXLEV], nc[MAXLEV];
-    for (int l = 0; l < MAXLEV; ++l) { lc[l] = 0; ac[l] = 0; cc[l] = 0; nc[l] = 0; }
-    int lvl = 0;
-    for (int64_t gb = b0; gb < b1; ++gb) {
-        while (gb >= lvl_start[lvl + 1]) ++lvl;
-        bool leaf, cov, ghost, fresh;
-        int nlc;
-        classify<D>(v, lvl, (int)(gb - lvl_start[lvl]), leaf, cov, ghost, fresh, nlc);
-        c[0] += leaf; c[1] += cov; c[2] += ghost; c[3] += fresh;
-        cc[lvl] += cov; nc[lvl] += fresh;
-        lc[lvl] += nlc;
-        ac[lvl] += v.nact[v.grids[lvl].boff + (gb - lvl_start[lvl])] ? (D == 2 ? BS * BS : BS * BS * BS) : 0;
-    }
-    for (int l = 0; l < v.L; ++l) {
-        if (cc[l]) atomicAdd(&covc[l], cc[l]);
-        if (nc[l]) atomicAdd(&newc[l], nc[l]);
-        if (lc[l]) atomicAdd((unsigned long long *)&leafcells[l], (unsigned long long)lc[l]);
-        if (ac[l]) atomicAdd((unsigned long long *)&actcells[l], (unsigned long long)ac[l]);
-    }
-    for (int k = 0; k < 4; ++k) sc[k][threadIdx.x] = c[k];
-    __syncthreads();
-    scan_lt<4>(sc, tot);
-    int pos[4];
-    for (int k = 0; k < 4; ++k) pos[k] = sc[k][threadIdx.x];
-    lvl = 0;
-    for (int64_t gb = b0; gb < b1; ++gb) {
-        while (gb >= lvl_start[lvl + 1]) ++lvl;
-        const int b = (int)(gb - lvl_start[lvl]);
-        bool leaf, cov, ghost, fresh;
-        int nlc;
-        classify<D>(v, lvl, b, leaf, cov, ghost, fresh, nlc);
-        const Tile tl = {lvl, b};
-        if (leaf) v.leaf[pos[0]++] = tl;
-        if (cov) v.cov[pos[1]++] = tl;
-        if (ghost) v.ghost[pos[2]++] = tl;
-        if (fresh) v.fresh[pos[3]++] = tl;
+        const int nch_all = D == 2 ? 4 : 8;
+        bool ghost = false;
+        if (!a && lvl >= 1) {
+            const int r3 = D == 3 ? 1 : 0;
+            uint8_t nbv[27];
+            int j = 0;
+            for (int dz = -r3; dz <= r3; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int qx = bcmap(bx + dx, nb, v.bc), qy = bcmap(by + dy, nb, v.bc);
+                        const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
+                        nbv[j++] = v.nact[G.boff + qx + (int64_t)nb * (qy + (int64_t)nb * qz)];
+                    }
+            int hit = 0;
+            for (int i = 0; i < j; ++i) hit |= nbv[i];
+            ghost = hit != 0;
+        }
+        int code = 0;
+        if (a && nchild < nch_all) code |= 1;
+        if (a && nchild > 0) code |= 2;
+        if (ghost) code |= 4;
+        if (a && !old && lvl >= 1) code |= 8;
+        code |= nchild << 4;
+        v.code[gb] = (uint8_t)code;
+        v.act[gb] = a ? 1 : 0;
+        if (a) {
+            atomicAdd(&part[lvl][0], (unsigned long long)(cpb - nchild * cpc));
+            atomicAdd(&part[lvl][1], (unsigned long long)cpb);
+        }
+        if (code & 2) atomicAdd(&part[lvl][2], 1ull);
+        if (code & 8) atomicAdd(&part[lvl][3], 1ull);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        v.meta->nleaf = tot[0];
-        v.meta->nghost = tot[2];
+    if (threadIdx.x < MAXLEV * 4)
+        v.cpart[((int64_t)blockIdx.x * MAXLEV + threadIdx.x / 4) * 4 + threadIdx.x % 4] =
+            (long long)part[threadIdx.x / 4][threadIdx.x % 4];
+}
+
+constexpr int LT = 1024;
+constexpr int NW = LT / 64;
+
+// One workgroup: compaction of the classified blocks into the leaf, covered,
+// ghost and new-block lists (order: level, then block index, x fastest),
+// per-level counts, and the patch table (levels in order, pmax blocks in
+// Morton order, each block's patches in split order).
+template <int D>
+__global__ void __launch_bounds__(LT) k_compact(View v, int64_t nbt, int64_t nslot, int nsub)
+{
+    constexpr int PER = 4;                 // blocks per thread per chunk
+    __shared__ int wcnt[4][NW];
+    __shared__ int base[4];
+    __shared__ int64_t lstart[MAXLEV + 1];
+    if (v.meta->done) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 4) base[tid] = 0;
+    if (tid <= MAXLEV) lstart[tid] = tid < v.L ? v.grids[tid].boff : nbt;
+    // per-level totals of the classification partials and of the flagged
+    // cells (integer sums: the result does not depend on the order)
+    __shared__ unsigned long long lsum[MAXLEV][4];
+    __shared__ int nfl[MAXLEV];
+    if (tid < MAXLEV * 4) lsum[tid / 4][tid % 4] = 0ull;
+    if (tid < MAXLEV) nfl[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < v.ncls * v.L * 4; i += LT) {
+        const int w = i / (v.L * 4), r = i % (v.L * 4);
+        const long long p = v.cpart[((int64_t)w * MAXLEV + r / 4) * 4 + r % 4];
+        if (p) atomicAdd(&lsum[r / 4][r % 4], (unsigned long long)p);
+    }
+    for (int64_t s = tid; s < nslot; s += LT) {
+        const int f = v.fcnt[s];
+        if (f) {
+            int l = 1;
+            while (l + 1 < v.L && s >= v.pbase[l + 1]) ++l;
+            atomicAdd(&nfl[l - 1], f);
+        }
+    }
+    __syncthreads();
+    if (tid < MAXLEV) {
+        const bool in = tid < v.L;
+        v.meta->leaf_cells[tid] = in ? (long long)lsum[tid][0] : 0;
+        v.meta->act_cells[tid] = in ? (long long)lsum[tid][1] : 0;
+        v.meta->cov_cnt[tid] = in ? (int)lsum[tid][2] : 0;
+        v.meta->new_cnt[tid] = in ? (int)lsum[tid][3] : 0;
+        v.meta->nflag[tid] = in ? nfl[tid] : 0;
+    }
+    __syncthreads();
+    Tile *lists[4] = {v.leaf, v.cov, v.ghost, v.fresh};
+    for (int64_t c0 = 0; c0 < nbt; c0 += (int64_t)LT * PER) {
+        const int64_t g0 = c0 + (int64_t)tid * PER;
+        int codes[PER], lv[PER];
+        int cnt[4] = {0, 0, 0, 0};
+        for (int j = 0; j < PER; ++j) {
+            const int64_t gb = g0 + j;
+            codes[j] = 0;
+            lv[j] = 0;
+            if (gb < nbt) {
+                const int code = v.code[gb];
+                int lvl = 0;
+                while (gb >= lstart[lvl + 1]) ++lvl;
+                codes[j] = code;
+                lv[j] = lvl;
+                for (int k = 0; k < 4; ++k) cnt[k] += (code >> k) & 1;
+            }
+        }
+    // exclusive scan of the per-thread counts (wave scan + wave totals)
+        int excl[4];
+        for (int k = 0; k < 4; ++k) {
+            int incl = cnt[k];
+            for (int o = 1; o < 64; o <<= 1) {
+                const int r = __shfl_up(incl, o);
+                if (lane >= o) incl += r;
+            }
+            excl[k] = incl - cnt[k];
+            if (lane == 63) wcnt[k][wave] = incl;
+        }
+        __syncthreads();
+        for (int k = 0; k < 4; ++k) {
+            int off = base[k] + excl[k];
+            for (int w = 0; w < wave; ++w) off += wcnt[k][w];
+            for (int j = 0; j < PER; ++j)
+                if ((codes[j] >> k) & 1) {
+                    const int64_t gb = g0 + j;
+                    lists[k][off++] = Tile{lv[j], (int)(gb - lstart[lv[j]])};
+                }
+        }
+        __syncthreads();
+        if (tid < 4) {
+            int s = 0;
+            for (int w = 0; w < NW; ++w) s += wcnt[tid][w];
+            base[tid] += s;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        v.meta->nleaf = base[0];
+        v.meta->nghost = base[2];
         int co = 0, no = 0;
         for (int l = 0; l < MAXLEV; ++l) {
-            const int cl = l < v.L ? covc[l] : 0, nl = l < v.L ? newc[l] : 0;
-            v.meta->cov_off[l] = co; v.meta->cov_cnt[l] = cl; co += cl;
-            v.meta->new_off[l] = no; v.meta->new_cnt[l] = nl; no += nl;
-            v.meta->leaf_cells[l] = l < v.L ? leafcells[l] : 0;
-            v.meta->act_cells[l] = l < v.L ? actcells[l] : 0;
+            v.meta->cov_off[l] = co; co += v.meta->cov_cnt[l];
+            v.meta->new_off[l] = no; no += v.meta->new_cnt[l];
         }
     }
-    // patch table: per level >= 1, pmax blocks in Morton order
-    int64_t nslot = 0;
-    for (int l = 1; l < v.L; ++l) {
-        const int nbp = v.grids[l].n / v.pmax;
-        nslot += D == 2 ? (int64_t)nbp * nbp : (int64_t)nbp * nbp * nbp;
-    }
-    const int R = v.pmax / BS;
-    const int nsub = D == 2 ? R * R : R * R * R;
-    const int64_t pch = (nslot + LT - 1) / LT;
-    const int64_t s0 = v.L > 1 ? v.pbase[1] : 0;
-    const int64_t p0 = s0 + threadIdx.x * pch;
-    const int64_t p1 = p0 + pch < s0 + nslot ? p0 + pch : s0 + nslot;
-    int np = 0;
-    for (int64_t s = p0; s < p1; ++s) np += v.pcnt[s];
-    sc[0][threadIdx.x] = np;
+    // patch table
     __syncthreads();
-    scan_lt<1>(sc, tot);
-    int w = sc[0][threadIdx.x];
-    for (int64_t s = p0; s < p1; ++s) {
-        const int k = v.pcnt[s];
+    if (tid == 0) base[0] = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nslot; c0 += LT) {
+        const int64_t s = c0 + tid;
+        const int k = s < nslot ? v.pcnt[s] : 0;
+        int incl = k;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int r = __shfl_up(incl, o);
+            if (lane >= o) incl += r;
+        }
+        if (lane == 63) wcnt[0][wave] = incl;
+        __syncthreads();
+        int off = base[0] + incl - k;
+        for (int w = 0; w < wave; ++w) off += wcnt[0][w];
         for (int j = 0; j < k; ++j) {
-            if (w < v.max_patch)
-                for (int e = 0; e < 5; ++e) v.patches[5 * (int64_t)w + e] = v.pslot[(s * nsub + j) * 5 + e];
-            ++w;
+            if (off + j < v.max_patch)
+                for (int e = 0; e < 5; ++e)
+                    v.patches[5 * (int64_t)(off + j) + e] = v.pslot[(s * nsub + j) * 5 + e];
         }
+        __syncthreads();
+        if (tid == 0) {
+            int t = 0;
+            for (int w = 0; w < NW; ++w) t += wcnt[0][w];
+            base[0] += t;
+        }
+        __syncthreads();
     }
-    if (threadIdx.x == 0) v.meta->npatch = tot[0];
-    __syncthreads();
-    // the new hierarchy becomes the current one
-    for (int64_t gb = threadIdx.x; gb < nbt; gb += LT) v.act[gb] = v.nact[gb];
+    if (tid == 0) v.meta->npatch = base[0];
 }
 
 __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t val)
@@ -420,34 +439,23 @@ static inline int grid_for(int64_t n, int bs, int cap)
     return g > cap ? cap : (int)g;
 }
 
-void launch_cfl_finalize(const View &v, hipStream_t s)
+void launch_flag_tile(const View &v, int lvl, int nblocks, hipStream_t s)
 {
-    k_cfl_finalize<<<v.mode == MODE_HIER ? 1 : grid_for(v.ngrid, 256, 64), v.mode == MODE_HIER ? 64 : 256, 0, s>>>(v);
-}
-
-void launch_time_advance(const View &v, hipStream_t s)
-{
-    k_time_advance<<<v.mode == MODE_HIER ? 1 : grid_for(v.ngrid, 256, 64), 256, 0, s>>>(v);
-}
-
-void launch_zero_meta_flags(const View &v, hipStream_t s) { k_zero_nflag<<<1, 64, 0, s>>>(v); }
-
-void launch_flags(const View &v, int lvl, int64_t ncell, hipStream_t s)
-{
-    if (v.dim == 2) k_flags<2><<<grid_for(ncell, 256, 8192), 256, 0, s>>>(v, lvl);
-    else k_flags<3><<<grid_for(ncell, 256, 8192), 256, 0, s>>>(v, lvl);
-}
-
-void launch_tile(const View &v, int lvl, int nblocks, hipStream_t s)
-{
-    if (v.dim == 2) k_tile<2><<<nblocks, 64, 0, s>>>(v, lvl);
-    else k_tile<3><<<nblocks, 64, 0, s>>>(v, lvl);
+    if (v.dim == 2) k_flag_tile<2><<<nblocks, 256, 0, s>>>(v, lvl);
+    else k_flag_tile<3><<<nblocks, 256, 0, s>>>(v, lvl);
 }
 
 void launch_build_lists(const View &v, int64_t nbt, hipStream_t s)
 {
-    if (v.dim == 2) k_build_lists<2><<<1, LT, 0, s>>>(v, nbt);
-    else k_build_lists<3><<<1, LT, 0, s>>>(v, nbt);
+    const int R = v.pmax / BS;
+    const int nsub = v.dim == 2 ? R * R : R * R * R;
+    if (v.dim == 2) {
+        k_classify<2><<<v.ncls, 256, 0, s>>>(v, nbt);
+        k_compact<2><<<1, LT, 0, s>>>(v, nbt, v.nslot, nsub);
+    } else {
+        k_classify<3><<<v.ncls, 256, 0, s>>>(v, nbt);
+        k_compact<3><<<1, LT, 0, s>>>(v, nbt, v.nslot, nsub);
+    }
 }
 
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t val, hipStream_t s)
