@@ -95,10 +95,12 @@ def lib():
             "orc_h_regrid": (None, [vp]),
             "orc_h_analyse": (None, [vp]),
             "orc_h_npatch": (C.c_int, [vp]),
+            "orc_h_set_no_reflux": (None, [vp, C.c_int]),
             "orc_h_patches": (None, [vp, i32p]),
             "orc_h_stage": (None, [vp, C.c_int, C.c_double]),
             "orc_h_step": (C.c_double, [vp, C.c_double, C.c_double, C.c_double, C.c_int]),
             "orc_h_step_fixed": (None, [vp, C.c_double]),
+            "orc_h_step_lts": (C.c_double, [vp, C.c_double, C.c_double, C.c_double, C.c_int, i64p]),
             "orc_init_quadrant": (None, [C.c_int, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double, dp, dp]),
             "orc_init_ellipsoid": (None, [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp, dp]),
@@ -283,6 +285,15 @@ class Hierarchy:
         dt = lib().orc_h_step(self._h, cfl, self.t, t_end, int(regrid))
         self.t = self.t + dt
         return dt
+
+    def step_lts(self, cfl: float, t_end: float = np.inf, regrid: bool = True):
+        """One level-0 step with local time steps; returns (dt_0, leaf updates)."""
+        upd = C.c_int64(0)
+        dt = lib().orc_h_step_lts(self._h, cfl, self.t, t_end, int(regrid), C.byref(upd))
+        if dt < 0:
+            raise MemoryError("oracle: local time stepping buffers")
+        self.t = self.t + dt
+        return dt, upd.value
 
     def step_fixed(self, dt: float):
         lib().orc_h_step_fixed(self._h, dt)

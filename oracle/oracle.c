@@ -321,6 +321,7 @@ typedef struct {
     double *regF[MAXL];  /* LTS flux registers, fine side [sub][d][f][cell] */
     orc_patch *patches;
     int npatch, cappatch;
+    int no_reflux;       /* test-only planted mistake: skip the flux correction */
 } orc_h;
 
 static int64_t hN(const orc_h *h, int l) { return ncells(h->dim, h->n[l]); }
@@ -851,6 +852,9 @@ void orc_h_analyse(orc_h *h) { h_details(h); }
 
 int orc_h_npatch(const orc_h *h) { return h->npatch; }
 
+/* Test-only: plant the mistake of skipping the flux correction. */
+void orc_h_set_no_reflux(orc_h *h, int on) { h->no_reflux = on; }
+
 /* patches as int32 rows {level, ox, oy, oz, size} */
 void orc_h_patches(const orc_h *h, int32_t *out)
 {
@@ -907,6 +911,193 @@ void orc_h_step_fixed(orc_h *h, double dt)
     h_ghost(h, h->Qs);
     h_stage(h, h->Qs, h->Q, dt, 1.0);
     h_ghost(h, h->Q);
+}
+
+/* ------------------------------------------------------------------------ */
+/* local time stepping: the recursive level cycle of Sec. 2.2 (Fig. 2)      */
+/* ------------------------------------------------------------------------ */
+
+static int lts_alloc(orc_h *h)
+{
+    for (int l = 0; l < h->L; ++l) {
+        int64_t N = hN(h, l);
+        if (!h->Qo[l]) h->Qo[l] = (double *)calloc((size_t)(h->nv * N), sizeof(double));
+        if (l < h->L - 1 && !h->regC[l])
+            h->regC[l] = (double *)calloc((size_t)(h->dim * h->nv * N), sizeof(double));
+        if (l >= 1 && !h->regF[l])
+            h->regF[l] = (double *)calloc((size_t)(2 * h->dim * h->nv * N), sizeof(double));
+        if (!h->Qo[l] || (l < h->L - 1 && !h->regC[l]) || (l >= 1 && !h->regF[l])) return -1;
+    }
+    return 0;
+}
+
+/* One explicit stage on every cell in a patch of level l (leaves and covered
+ * cells, as the single-level update of Sec. 2.2 acts on whole patches),
+ * with the level's own fluxes: out = Q - lam ((dF_1 + dF_2) + dF_3).  When
+ * record is set (second stage), the fluxes across refinement boundaries are
+ * kept for the flux correction: coarse side (a leaf next to a covered cell)
+ * in regC[l], fine side (a cell next to a ghost cell) in regF[l] for
+ * substep sub. */
+static void h_fv_level_all(orc_h *h, int l, double **src, double **out, double lam,
+                           int record, int sub)
+{
+    int dim = h->dim, n = h->n[l], nv = h->nv;
+    int64_t N = hN(h, l);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < N; ++i) {
+        if (!h->act[l][i]) continue;
+        int p[3];
+        cdecode(dim, n, i, p);
+        int leaf = !covered(h, (const uint8_t *const *)h->act, l, p);
+        double dF[3][NVMAX];
+        for (int d = 0; d < dim; ++d) {
+            double Fhi[NVMAX], Flo[NVMAX];
+            int lc[3] = {p[0], p[1], p[2]};
+            lc[d] = p[d] - 1;
+            face_flux(dim, n, h->bc, h->g, src[l], d, p, Fhi);
+            face_flux(dim, n, h->bc, h->g, src[l], d, lc, Flo);
+            if (record) {
+                int nh[3] = {p[0], p[1], p[2]}, nl[3] = {p[0], p[1], p[2]};
+                nh[d] = bcmap(p[d] + 1, n, h->bc);
+                nl[d] = bcmap(p[d] - 1, n, h->bc);
+                int64_t ih = cidx(n, nh), il = cidx(n, nl);
+                if (leaf && covered(h, (const uint8_t *const *)h->act, l, nh))
+                    for (int f = 0; f < nv; ++f) h->regC[l][((int64_t)d * nv + f) * N + i] = Fhi[f];
+                if (leaf && covered(h, (const uint8_t *const *)h->act, l, nl))
+                    for (int f = 0; f < nv; ++f) h->regC[l][((int64_t)d * nv + f) * N + il] = Flo[f];
+                if (l >= 1 && !h->act[l][ih])
+                    for (int f = 0; f < nv; ++f)
+                        h->regF[l][(((int64_t)sub * dim + d) * nv + f) * N + i] = Fhi[f];
+                if (l >= 1 && !h->act[l][il])
+                    for (int f = 0; f < nv; ++f)
+                        h->regF[l][(((int64_t)sub * dim + d) * nv + f) * N + il] = Flo[f];
+            }
+            for (int f = 0; f < nv; ++f) dF[d][f] = Fhi[f] - Flo[f];
+        }
+        for (int f = 0; f < nv; ++f) {
+            double R = dF[0][f] + dF[1][f];
+            if (dim == 3) R = R + dF[2][f];
+            out[l][f * N + i] = h->Q[l][f * N + i] - lam * R;
+        }
+    }
+}
+
+/* Projection of level l+1 onto the covered cells of level l only. */
+static void h_restrict_level(orc_h *h, double **A, int l)
+{
+    int n = h->n[l];
+    int64_t N = hN(h, l), Nf = hN(h, l + 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int p[3];
+        cdecode(h->dim, n, i, p);
+        if (!h->act[l][i] || !covered(h, (const uint8_t *const *)h->act, l, p)) continue;
+        for (int f = 0; f < h->nv; ++f)
+            A[l][f * N + i] = restrict_cell(h->dim, h->n[l + 1], A[l + 1], f * Nf, p);
+    }
+}
+
+/* Flux correction of level l (Sec. 2.2; Berger and Colella): at every face
+ * between a leaf of level l and a covered cell, the coarse flux of the step
+ * is replaced by the time and area mean of the fine fluxes of the two
+ * substeps of level l+1:  Q += s lam (F_c - Fbar), s = +1 on the high face,
+ * -1 on the low face, Fbar = (A_0 + A_1) / 2 with A_k the area mean of
+ * substep k.  Faces are visited axis by axis, low face first. */
+static void h_reflux(orc_h *h, int l, double lam)
+{
+    int dim = h->dim, n = h->n[l], nf = h->n[l + 1], nv = h->nv;
+    int64_t N = hN(h, l), Nf = hN(h, l + 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int p[3];
+        cdecode(dim, n, i, p);
+        if (!is_leaf(h, l, p)) continue;
+        for (int d = 0; d < dim; ++d) {
+            int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            for (int s = -1; s <= 1; s += 2) {
+                int nb[3] = {p[0], p[1], p[2]};
+                nb[d] = bcmap(p[d] + s, n, h->bc);
+                if (!covered(h, (const uint8_t *const *)h->act, l, nb)) continue;
+                int64_t ic = s > 0 ? i : cidx(n, nb);
+                int fb[3] = {2 * p[0], 2 * p[1], dim == 3 ? 2 * p[2] : 0};
+                fb[d] = bcmap(s > 0 ? 2 * p[d] + 1 : 2 * p[d] - 1, nf, h->bc);
+                for (int f = 0; f < nv; ++f) {
+                    double A[2];
+                    for (int k = 0; k < 2; ++k) {
+                        const double *R = h->regF[l + 1] + (((int64_t)k * dim + d) * nv + f) * Nf;
+                        if (dim == 2) {
+                            int c1[3] = {fb[0], fb[1], 0};
+                            c1[t1] += 1;
+                            A[k] = 0.5 * (R[cidx(nf, fb)] + R[cidx(nf, c1)]);
+                        } else {
+                            int c10[3] = {fb[0], fb[1], fb[2]}, c01[3] = {fb[0], fb[1], fb[2]},
+                                c11[3] = {fb[0], fb[1], fb[2]};
+                            c10[t1] += 1; c01[t2] += 1; c11[t1] += 1; c11[t2] += 1;
+                            A[k] = 0.25 * ((R[cidx(nf, fb)] + R[cidx(nf, c10)]) +
+                                           (R[cidx(nf, c01)] + R[cidx(nf, c11)]));
+                        }
+                    }
+                    double Fbar = 0.5 * (A[0] + A[1]);
+                    double Fc = h->regC[l][((int64_t)d * nv + f) * N + ic];
+                    if (s > 0) h->Q[l][f * N + i] = h->Q[l][f * N + i] + lam * (Fc - Fbar);
+                    else h->Q[l][f * N + i] = h->Q[l][f * N + i] - lam * (Fc - Fbar);
+                }
+            }
+        }
+    }
+}
+
+/* Advance level l by one step of dt_l (substep k of its parent's step):
+ * keep the level's state at the start of the step (for the time
+ * interpolation of finer ghost cells), two explicit stages on every cell of
+ * the level, with second-stage ghost cells interpolated at the stage time,
+ * then two substeps of level l+1 with ghost cells interpolated in time, the
+ * projection of level l+1 onto level l and the flux correction. */
+static void lts_advance(orc_h *h, int l, double dt, int k)
+{
+    int64_t N = hN(h, l);
+    memcpy(h->Qo[l], h->Q[l], (size_t)(h->nv * N) * sizeof(double));
+    h_fv_level_all(h, l, h->Q, h->Qs, (dt * 0.5) / h->dx[l], 0, k);
+    if (l >= 1) h_ghost_time(h, l, h->Qs, h->Qo, h->Q, (double)(2 * k + 1) * 0.25);
+    h_fv_level_all(h, l, h->Qs, h->Q, dt / h->dx[l], 1, k);
+    if (l + 1 < h->L) {
+        for (int kk = 0; kk < 2; ++kk) {
+            h_ghost_time(h, l + 1, h->Q, h->Qo, h->Q, (double)kk * 0.5);
+            lts_advance(h, l + 1, dt * 0.5, kk);
+        }
+        h_restrict_level(h, h->Q, l);
+        if (!h->no_reflux) h_reflux(h, l, dt / h->dx[l]);
+    }
+}
+
+/* One level-0 step with local time steps dt_l = dt_0 / 2^l (Sec. 2.1,
+ * MRLT; Sec. 2.2, AMRLT): dt_0 = min over levels of (cfl dx_l / smax_l) 2^l
+ * from the leaves, clipped to reach t_end; then the MR coarsening /
+ * refinement when regrid is set and a spatial ghost fill.  Returns dt_0;
+ * *leaf_updates receives sum over levels of leaves_l 2^l. */
+double orc_h_step_lts(orc_h *h, double cfl, double t, double t_end, int regrid,
+                      int64_t *leaf_updates)
+{
+    if (lts_alloc(h)) return -1.0;
+    double smax[MAXL];
+    orc_h_cfl(h, cfl, t, t_end, smax);
+    int64_t leaves[MAXL], active[MAXL];
+    orc_h_counts(h, leaves, active);
+    double dt = INFINITY;
+    int64_t upd = 0;
+    for (int l = 0; l < h->L; ++l) {
+        if (leaves[l] > 0) {
+            double d = ((cfl * h->dx[l]) / smax[l]) * (double)(1 << l);
+            if (d < dt) dt = d;
+        }
+        upd += leaves[l] << l;
+    }
+    if (dt > t_end - t) dt = t_end - t;
+    if (leaf_updates) *leaf_updates = upd;
+    lts_advance(h, 0, dt, 0);
+    if (regrid && h->L > 1) h_regrid(h, 1);
+    h_ghost(h, h->Q);
+    return dt;
 }
 
 /* ------------------------------------------------------------------------ */

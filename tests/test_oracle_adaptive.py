@@ -279,3 +279,103 @@ def test_accuracy_perturbation_sod(orc):
     leaves, _ = h.counts()
     assert leaves.sum() < 0.5 * n * n  # it did adapt
     assert abs(l1u - l1a) / l1u < 0.15, (l1u, l1a)
+
+
+# --------------------------------------------------------------------------
+# local time stepping (recursive level cycle with flux correction)
+# --------------------------------------------------------------------------
+
+def test_lts_single_level_is_global_step(orc):
+    Qf = orc.init_quadrant(64, G, inputs.quadrant_states(1))
+    a = orc.Hierarchy(2, 1, 64)
+    b = orc.Hierarchy(2, 1, 64)
+    a.init_finest(Qf)
+    b.init_finest(Qf)
+    for _ in range(5):
+        dta, _ = a.step_lts(0.45)
+        dtb = b.step(0.45)
+        assert dta == dtb
+    assert np.array_equal(a.level(0), b.level(0))
+
+
+def test_lts_eps_zero_equals_uniform_substeps(orc):
+    """Fully refined hierarchy: only the finest level has leaves and no ghost
+    cells, so one level-0 step equals 2^(L-1) uniform steps of dt_0/2^(L-1)."""
+    Qf = orc.init_quadrant(128, G, inputs.quadrant_states(2))
+    h = orc.Hierarchy(2, 3, 32, eps=0.0)
+    h.init_finest(Qf)
+    u = orc.Hierarchy(2, 1, 128)
+    u.init_finest(Qf)
+    for _ in range(3):
+        dt0, upd = h.step_lts(0.45)
+        assert upd == 4 * 128 * 128
+        for _ in range(4):
+            u.step_fixed(dt0 * 0.25)
+    assert np.array_equal(h.level(2), u.level(0))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_lts_conservation_periodic(orc, dim):
+    if dim == 2:
+        Qf = orc.init_quadrant(128, G, inputs.quadrant_states(6))
+        h = orc.Hierarchy(2, 3, 32, bc=orc.BC_PERIODIC, eps=1e-3)
+    else:
+        e = inputs.ellipsoid(6)
+        Qf = orc.init_ellipsoid(64, G, e.a, e.b, e.c, e.theta, e.phi, e.states)
+        h = orc.Hierarchy(3, 2, 32, bc=orc.BC_PERIODIC, lo=-1.0, hi=1.0, eps=1e-3)
+    h.init_finest(Qf)
+    T0 = h.totals()
+    for _ in range(6):
+        h.step_lts(0.4)
+    check_hierarchy(h, periodic=True)
+    T1 = h.totals()
+    assert np.all(np.abs(T1 - T0) <= 2e-13 * np.maximum(1.0, np.abs(T0))), (T0, T1)
+
+
+def test_lts_without_correction_does_not_conserve(orc):
+    """Control for the test above, with a mistake planted in the oracle: with
+    the flux correction skipped, the totals drift well beyond rounding, so
+    the conservation above is the correction's doing."""
+    Qf = orc.init_quadrant(128, G, inputs.quadrant_states(6))
+    h = orc.Hierarchy(2, 3, 32, bc=orc.BC_PERIODIC, eps=1e-3)
+    h.init_finest(Qf)
+    orc.lib().orc_h_set_no_reflux(h._h, 1)
+    T0 = h.totals()
+    for _ in range(6):
+        h.step_lts(0.4)
+    drift = np.abs(h.totals() - T0) / np.maximum(1.0, np.abs(T0))
+    assert drift.max() > 10 * 2e-13, drift
+
+
+def test_lts_free_stream_bitwise(orc):
+    prim = inputs.quadrant_states(8)
+    h = orc.Hierarchy(2, 3, 32, eps=1e-3)
+    h.init_finest(orc.init_quadrant(128, G, prim))
+    w = np.array([0.8, 0.35, -0.25, 1.1])
+    q = orc.prim2cons(2, G, w.reshape(4, 1)).ravel()
+    for l in range(3):
+        h.level(l)[...] = q.reshape(4, 1, 1)
+    for _ in range(4):
+        h.step_lts(0.45, regrid=False)
+    for l in range(3):
+        assert np.array_equal(h.level(l), np.broadcast_to(q.reshape(4, 1, 1), h.level(l).shape))
+
+
+def test_lts_accuracy_perturbation_sod(orc):
+    L_, R_ = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    n = 256
+    Qf = orc.init_riemann1d(2, n, G, 0, L_, R_)
+    t_end = 0.15
+    h = orc.Hierarchy(2, 4, 32, eps=1e-3)
+    h.init_finest(Qf)
+    while h.t < t_end:
+        h.step_lts(0.4, t_end)
+        check_hierarchy(h)
+    u = orc.Hierarchy(2, 1, n)
+    u.init_finest(Qf)
+    while u.t < t_end:
+        u.step(0.4, t_end)
+    ex, _, _ = er.cell_averages(L_, R_, n, t_end)
+    l1a = np.abs(h.composite()[0] - ex[None, :]).sum() / n ** 2
+    l1u = np.abs(u.level(0)[0] - ex[None, :]).sum() / n ** 2
+    assert abs(l1u - l1a) / l1u < 0.2, (l1u, l1a)
