@@ -81,13 +81,13 @@ struct Layout {
     std::vector<Grid> grids;
     int64_t state_elems = 0;
     int narrays = 2;
-    int64_t nbt = 0, ncoarse = 0, nslot = 0, max_tiles = 0, max_patch = 0;
+    int64_t nbt = 0, ncoarse = 0, nslot = 0, max_tiles = 0, max_patch = 0, reg_elems = 0;
     int ncls = 1;
     int ngroups = 1;
     std::vector<int64_t> pbase;
     // scratch offsets
     size_t o_grids, o_act, o_nact, o_code, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
-        o_pcnt, o_fcnt, o_cpart, o_pbase, o_patches, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
+        o_pcnt, o_fcnt, o_cpart, o_pbase, o_actv, o_reg, o_patches, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
     size_t scratch = 0, state = 0;
 };
 
@@ -101,7 +101,7 @@ int validate(const eu_config *c, std::string &why)
     if (c->bc != EU_BC_TRANSMISSIVE && c->bc != EU_BC_PERIODIC) { why = "bad bc"; return EU_EINVAL; }
     if (!(c->cfl > 0.0)) { why = "cfl must be positive"; return EU_EINVAL; }
     if (c->time_mode != EU_DT_GLOBAL && c->time_mode != EU_DT_LTS) { why = "bad time_mode"; return EU_EINVAL; }
-    if (c->time_mode == EU_DT_LTS) { why = "local time stepping is not available in this build"; return EU_EINVAL; }
+    if (c->time_mode == EU_DT_LTS && c->n_instances > 1) { why = "a batch has no levels to step locally"; return EU_EINVAL; }
     if (c->n_instances > 1) {
         if (!c->inst_side_host) { why = "inst_side_host required for a batch"; return EU_EINVAL; }
         if (c->levels != 1) { why = "a batch holds uniform grids (levels = 1)"; return EU_EINVAL; }
@@ -180,8 +180,21 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.ngroups = batch ? lay.ngrid : 1;
 
     const size_t es = c->precision == EU_FP64 ? 8 : 4;
-    lay.narrays = 2;
+    const bool lts = !batch && c->time_mode == EU_DT_LTS;
+    lay.narrays = lts ? 3 : 2;
     lay.state = lay.narrays * align256((size_t)lay.state_elems * es);
+    // local time stepping flux registers: coarse side on levels 0 .. L-2
+    // (d fields of faces per cell), fine side on levels 1 .. L-1 (two substeps)
+    int64_t roff = 0;
+    for (int g = 0; g < lay.ngrid; ++g) {
+        Grid &G = lay.grids[g];
+        G.rcoff = -1;
+        G.rfoff = -1;
+        if (!lts) continue;
+        if (g < lay.L - 1) { G.rcoff = roff; roff += (int64_t)D * lay.nv * G.ncell; }
+        if (g >= 1) { G.rfoff = roff; roff += 2 * (int64_t)D * lay.nv * G.ncell; }
+    }
+    lay.reg_elems = roff;
 
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes ? bytes : 1); return r; };
@@ -196,11 +209,13 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_cov = take(sizeof(Tile) * lay.nbt);
     lay.o_ghost = take(sizeof(Tile) * lay.nbt);
     lay.o_fresh = take(sizeof(Tile) * lay.nbt);
+    lay.o_actv = take(sizeof(Tile) * lay.nbt);
+    lay.o_reg = take(es * lay.reg_elems);
     lay.o_pslot = take(sizeof(int) * 5 * lay.nslot * nsub);
     lay.o_pcnt = take(sizeof(int) * lay.nslot);
     lay.o_fcnt = take(sizeof(int) * lay.nslot);
     lay.ncls = (int)std::min<int64_t>(std::max<int64_t>((lay.nbt + 255) / 256, 1), 256);
-    lay.o_cpart = take(sizeof(long long) * 4 * eu::MAXLEV * lay.ncls);
+    lay.o_cpart = take(sizeof(long long) * eu::NPART * eu::MAXLEV * lay.ncls);
     lay.o_pbase = take(sizeof(int64_t) * (eu::MAXLEV + 1));
     lay.o_patches = take(sizeof(int) * 5 * lay.max_patch);
     lay.o_meta = take(sizeof(Meta));
@@ -244,7 +259,7 @@ void seq_restrict(eu_ctx *c, int arr)
 
 void seq_ghost(eu_ctx *c, int arr)
 {
-    if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, (int)(c->nbt), c->stream);
+    if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, 0.0, (int)(c->nbt), c->stream);
 }
 
 void seq_cfl(eu_ctx *c) { c->ks->cfl(c->v, c->max_tiles, c->stream); }
@@ -270,12 +285,12 @@ void seq_fv_step(eu_ctx *c, bool ghost_after)
 {
     hipEvent_t e;
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 1, c->max_tiles, c->stream);
+    c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, c->stream);
     prof_end(c, e);
     seq_restrict(c, ARR_QS);
     seq_ghost(c, ARR_QS);
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 2, c->max_tiles, c->stream);
+    c->ks->fv_stage(c->v, 2, -1, 0, 0, c->max_tiles, c->stream);
     prof_end(c, e);
     seq_restrict(c, ARR_Q);
     if (ghost_after) seq_ghost(c, ARR_Q);
@@ -299,14 +314,52 @@ void seq_flag_tile(eu_ctx *c, bool prolong)
     }
     launch_build_lists(c->v, c->nbt, c->stream);
     if (prolong)
-        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 0, (int)nblocks_grid(c, l), c->stream);
+        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 0, 0.0, (int)nblocks_grid(c, l), c->stream);
     seq_ghost(c, ARR_Q);
+}
+
+// Local time stepping: advance level l by one of its steps (substep k of
+// its parent's step): keep its start state, two stages on its patches (the
+// second-stage ghost cells interpolated in time at the stage time), then two
+// substeps of level l+1 with time-interpolated ghost cells, projection of
+// level l+1 onto level l, and the flux correction.
+void lts_advance(eu_ctx *c, int l, int k)
+{
+    const int nbl = (int)nblocks_grid(c, l);
+    hipEvent_t e;
+    c->ks->copy_level(c->v, l, nbl, c->stream);
+    prof_begin(c, &e);
+    c->ks->fv_stage(c->v, 1, l, k, 0, nbl, c->stream);
+    prof_end(c, e);
+    if (l >= 1) c->ks->predict(c->v, ARR_QS, l, 2, (double)(2 * k + 1) * 0.25, nbl, c->stream);
+    prof_begin(c, &e);
+    c->ks->fv_stage(c->v, 2, l, k, 1, nbl, c->stream);
+    prof_end(c, e);
+    if (l + 1 < c->L) {
+        const int nbf = (int)nblocks_grid(c, l + 1);
+        for (int kk = 0; kk < 2; ++kk) {
+            c->ks->predict(c->v, ARR_Q, l + 1, 2, (double)kk * 0.5, nbf, c->stream);
+            lts_advance(c, l + 1, kk);
+        }
+        c->ks->restrict_cov(c->v, ARR_Q, l, nbl, c->stream);
+        c->ks->reflux(c->v, l, nbl, c->stream);
+    }
 }
 
 void seq_step(eu_ctx *c, bool regrid)
 {
     seq_cfl(c);
     const bool rg = regrid && c->L > 1;
+    if (c->v.lts) {
+        lts_advance(c, 0, 0);
+        if (rg) {
+            seq_details(c);
+            seq_flag_tile(c, true);
+        } else {
+            seq_ghost(c, ARR_Q);
+        }
+        return;
+    }
     seq_fv_step(c, !rg);
     if (rg) {
         seq_details(c);
@@ -473,7 +526,10 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     const size_t es = cfg->precision == EU_FP64 ? 8 : 4;
     v.Q = state_dev;
     v.Qs = (char *)state_dev + align256((size_t)lay.state_elems * es);
-    v.Qo = nullptr;
+    v.Qo = lay.narrays == 3 ? (char *)state_dev + 2 * align256((size_t)lay.state_elems * es) : nullptr;
+    v.lts = lay.narrays == 3 ? 1 : 0;
+    v.actv = at<Tile>(scratch_dev, lay.o_actv);
+    v.reg = at<char>(scratch_dev, lay.o_reg);
     v.grids = at<Grid>(scratch_dev, lay.o_grids);
     v.act = at<uint8_t>(scratch_dev, lay.o_act);
     v.nact = at<uint8_t>(scratch_dev, lay.o_nact);
@@ -603,7 +659,7 @@ int eu_project(eu_ctx *c, int mode)
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
     if (mode == EU_RESTRICT) seq_restrict(c, ARR_Q);
     else if (mode == EU_PROLONG) {
-        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 0, (int)nblocks_grid(c, l), c->stream);
+        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 0, 0.0, (int)nblocks_grid(c, l), c->stream);
     } else if (mode == EU_GHOST) seq_ghost(c, ARR_Q);
     else return set_err(c, EU_EINVAL, "bad projection mode");
     return check_launch(c);
@@ -627,7 +683,12 @@ int eu_fv_step(eu_ctx *c)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
-    seq_fv_step(c, true);
+    if (c->v.lts) {
+        lts_advance(c, 0, 0);
+        seq_ghost(c, ARR_Q);
+    } else {
+        seq_fv_step(c, true);
+    }
     return check_launch(c);
 }
 

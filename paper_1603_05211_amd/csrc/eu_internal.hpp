@@ -9,6 +9,7 @@ namespace eu {
 
 constexpr int BS = 8;          // block side in cells: the unit of patches and tiles
 constexpr int MAXLEV = 10;
+constexpr int NPART = 8;       // classification partial sums per level
 
 // One dense grid: a level of the hierarchy, the single uniform grid, or one
 // instance of a batch.  Field f of cell (x, y, z) lives at
@@ -25,6 +26,8 @@ struct Grid {
     int lvl;         // level (0 for uniform and batch grids)
     int pad;
     double dx;       // cell width
+    int64_t rcoff;   // local time stepping: coarse-side flux registers of this level (-1: none)
+    int64_t rfoff;   // local time stepping: fine-side flux registers of this level (-1: none)
 };
 
 // A tile of work: one BS^d block of one grid.
@@ -46,6 +49,9 @@ struct Meta {
     int pad_;
     int cov_off[MAXLEV], cov_cnt[MAXLEV];   // per-level ranges of the covered-block list
     int new_off[MAXLEV], new_cnt[MAXLEV];   // per-level ranges of the new-block list
+    int leaf_off[MAXLEV], leaf_cnt[MAXLEV]; // per-level ranges of the leaf list
+    int ghost_off[MAXLEV], ghost_cnt[MAXLEV];
+    int act_off[MAXLEV], act_cnt[MAXLEV];   // per-level ranges of the all-patch-block list
     int nflag[MAXLEV];                      // flagged cells per level
     long long leaf_cells[MAXLEV];
     long long act_cells[MAXLEV];
@@ -56,6 +62,7 @@ enum { MODE_HIER = 0, MODE_BATCH = 1 };
 // Everything a kernel needs, passed by value.
 struct View {
     int dim, nv, L, ngrid, bc, mode;
+    int lts;                          // local time stepping (recursive level cycle)
     int pmin, pmax;
     double gamma, cfl, t_end, eps, eta;
     const Grid *grids;                // device copy of the grid table
@@ -65,11 +72,14 @@ struct View {
     uint8_t *code;                    // per-block classification of the new hierarchy
     double *D;                        // per-cell FP64 detail norm
     Tile *leaf, *cov, *ghost, *fresh; // work lists
+    Tile *actv;                       // every block in a patch, by level
+    void *reg;                        // local time stepping flux registers (state type)
     int *pslot;                       // per pmax-block patch slots (5 ints each)
     int *pcnt;                        // per pmax-block patch counts
     int *fcnt;                        // per pmax-block flagged-cell counts
-    long long *cpart;                 // per classification workgroup and level:
-                                      // leaf cells, patch cells, covered blocks, new blocks
+    long long *cpart;                 // per classification workgroup and level (NPART values):
+                                      // leaf cells, patch cells, covered, new, leaf, ghost and
+                                      // patch blocks
     int ncls;                         // workgroups of the classification kernel
     int64_t *pbase;                   // per-level offset into pslot / pcnt
     int *patches;                     // compacted patch table (5 ints per row)

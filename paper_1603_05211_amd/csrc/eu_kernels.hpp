@@ -268,7 +268,8 @@ template <int D> struct FV {
 template <typename T, int D, int DN>
 __device__ __forceinline__ void fv_faces(const View &v, const Grid &G, const T *src, int ox, int oy,
                                          int oz, const T (*sW)[FV<D>::NE], const uint8_t *sCov,
-                                         T (*sF)[FV<D>::NF], T g, T gi)
+                                         const uint8_t *sAct, T (*sF)[FV<D>::NF], T g, T gi,
+                                         bool lts, bool record, int sub)
 {
     using C = FV<D>;
     constexpr int E = C::E, H = C::H, B = C::B;
@@ -284,12 +285,14 @@ __device__ __forceinline__ void fv_faces(const View &v, const Grid &G, const T *
         const int hr = hl + SD;
         const bool lin = a >= 1, rin = a <= B - 1;
         const bool lcov = sCov[hl] != 0, rcov = sCov[hr] != 0;
-        const bool need = (lin && !lcov) || (rin && !rcov);
+        // global mode: fluxes of faces next to a leaf of the tile; local time
+        // stepping: every face of the tile (whole patches are updated)
+        const bool need = lts ? (lin || rin) : ((lin && !lcov) || (rin && !rcov));
         T F[D + 2];
         if (!need) {
 #pragma unroll
             for (int f = 0; f < D + 2; ++f) F[f] = T(0);
-        } else if (lcov || rcov) {
+        } else if (!lts && (lcov || rcov)) {
             int p[3] = {ox + l[0], oy + l[1], oz + l[2]};
             int s = +1;
             if (lcov) { p[DN] += 1; s = -1; }
@@ -304,14 +307,33 @@ __device__ __forceinline__ void fv_faces(const View &v, const Grid &G, const T *
                 wd[f] = sW[f][hr + SD];
             }
             face_flux4<T, D, DN>(g, gi, wa, wb, wc, wd, F);
+            if (record) {
+                // registers are indexed by the cell on the low side of the face
+                int q[3] = {ox + l[0], oy + l[1], oz + l[2]};
+                q[DN] = bcmap(q[DN], G.n, v.bc);
+                const int64_t iq = gidx(G.n, q[0], q[1], D == 3 ? q[2] : 0);
+                const bool lact = sAct[hl] != 0, ract = sAct[hr] != 0;
+                const bool lleaf = lact && !lcov, rleaf = ract && !rcov;
+                T *reg = (T *)v.reg;
+                if (G.rcoff >= 0 && ((lleaf && rcov) || (rleaf && lcov)))
+#pragma unroll
+                    for (int f = 0; f < D + 2; ++f)
+                        reg[G.rcoff + ((int64_t)DN * (D + 2) + f) * G.ncell + iq] = F[f];
+                if (G.rfoff >= 0 && lact != ract)
+#pragma unroll
+                    for (int f = 0; f < D + 2; ++f)
+                        reg[G.rfoff + (((int64_t)sub * D + DN) * (D + 2) + f) * G.ncell + iq] = F[f];
+            }
         }
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) sF[f][fi] = F[f];
     }
 }
 
+// Residual of the thread's cells, accumulated axis by axis in the order
+// ((dF_1 + dF_2) + dF_3), dF = F_{+1/2} - F_{-1/2}.
 template <typename T, int D, int DN>
-__device__ __forceinline__ void fv_collect(const T (*sF)[FV<D>::NF], T (*dF)[D][D + 2])
+__device__ __forceinline__ void fv_collect(const T (*sF)[FV<D>::NF], T (*R)[D + 2], bool first)
 {
     using C = FV<D>;
     constexpr int B = C::B;
@@ -325,27 +347,38 @@ __device__ __forceinline__ void fv_collect(const T (*sF)[FV<D>::NF], T (*dF)[D][
         else { a = z; r = x + B * y; }
         const int lo = a + (B + 1) * r, hi = lo + 1;
 #pragma unroll
-        for (int f = 0; f < D + 2; ++f) dF[k][DN][f] = sF[f][hi] - sF[f][lo];
+        for (int f = 0; f < D + 2; ++f) {
+            const T d = sF[f][hi] - sF[f][lo];
+            R[k][f] = first ? d : R[k][f] + d;
+        }
     }
 }
 
-// One explicit stage: out = base - lam ((dF_1 + dF_2) + dF_3) on every leaf,
-// lam = (dt * fac) / dx (FP64, then cast), fluxes from src.
+// One explicit stage: out = base - lam ((dF_1 + dF_2) + dF_3), lam = (dt *
+// fac) / dx (FP64, then cast), fluxes from src.  Global time step (lvl < 0):
+// every leaf of every level (leaf list), faces next to a covered cell take
+// the fine-flux mean.  Local time stepping (lvl >= 0): every cell in a patch
+// of level lvl with the level's own fluxes; with record set, fluxes across
+// refinement boundaries go to the flux registers (substep sub).
 template <typename T, int D>
 __global__ void __launch_bounds__(FV<D>::NT)
-k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac)
+k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac, int lvl, int sub,
+           int record)
 {
     using C = FV<D>;
     constexpr int E = C::E, H = C::H, B = C::B, NV = C::NV;
     __shared__ T sW[NV][C::NE];
     __shared__ T sF[NV][C::NF];
     __shared__ uint8_t sCov[C::NE];
+    __shared__ uint8_t sAct[C::NE];
     if (v.meta->done) return;
     const T g = (T)v.gamma;
     const T gi = (T)(1.0 / (v.gamma - 1.0));
-    const int count = v.meta->nleaf;
+    const bool lts = lvl >= 0;
+    const Tile *list = lts ? v.actv + v.meta->act_off[lvl] : v.leaf;
+    const int count = lts ? v.meta->act_cnt[lvl] : v.meta->nleaf;
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
-        const Tile tl = v.leaf[t];
+        const Tile tl = list[t];
         const Grid G = v.grids[tl.grid];
         const int n = G.n, nb = G.nb;
         const int ox = (tl.block % nb) * B;
@@ -366,37 +399,34 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac)
 #pragma unroll
             for (int f = 0; f < NV; ++f) sW[f][c] = w[f];
             sCov[c] = covered(v, v.act, G, x, y, z) ? 1 : 0;
+            if (record) sAct[c] = block_active(v, v.act, G, x, y, z) ? 1 : 0;
         }
         __syncthreads();
-        T dF[C::CPT][D][NV];
-        fv_faces<T, D, 0>(v, G, src, ox, oy, oz, sW, sCov, sF, g, gi);
+        T R[C::CPT][NV];
+        fv_faces<T, D, 0>(v, G, src, ox, oy, oz, sW, sCov, sAct, sF, g, gi, lts, record, sub);
         __syncthreads();
-        fv_collect<T, D, 0>(sF, dF);
+        fv_collect<T, D, 0>(sF, R, true);
         __syncthreads();
-        fv_faces<T, D, 1>(v, G, src, ox, oy, oz, sW, sCov, sF, g, gi);
+        fv_faces<T, D, 1>(v, G, src, ox, oy, oz, sW, sCov, sAct, sF, g, gi, lts, record, sub);
         __syncthreads();
-        fv_collect<T, D, 1>(sF, dF);
+        fv_collect<T, D, 1>(sF, R, false);
         __syncthreads();
         if constexpr (D == 3) {
-            fv_faces<T, D, 2>(v, G, src, ox, oy, oz, sW, sCov, sF, g, gi);
+            fv_faces<T, D, 2>(v, G, src, ox, oy, oz, sW, sCov, sAct, sF, g, gi, lts, record, sub);
             __syncthreads();
-            fv_collect<T, D, 2>(sF, dF);
+            fv_collect<T, D, 2>(sF, R, false);
         }
-        const double dt = v.dt[v.mode == MODE_BATCH ? tl.grid : 0];
+        const double dt = v.dt[(v.mode == MODE_BATCH || lts) ? tl.grid : 0];
         const T lam = (T)((dt * fac) / G.dx);
 #pragma unroll
         for (int k = 0; k < C::CPT; ++k) {
             const int c = threadIdx.x + k * C::NT;
             const int x = c % B, y = (c / B) % B, z = c / (B * B);
             const int h = (x + H) + E * ((y + H) + (D == 3 ? E * (z + H) : 0));
-            if (sCov[h]) continue;
+            if (!lts && sCov[h]) continue;
             const int64_t id = G.off + gidx(n, ox + x, oy + y, oz + z);
 #pragma unroll
-            for (int f = 0; f < NV; ++f) {
-                T R = dF[k][0][f] + dF[k][1][f];
-                if (D == 3) R = R + dF[k][D - 1][f];
-                out[f * N + id] = base[f * N + id] - lam * R;
-            }
+            for (int f = 0; f < NV; ++f) out[f * N + id] = base[f * N + id] - lam * R[k][f];
         }
         __syncthreads();
     }
@@ -412,6 +442,37 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac)
 // step is committed: t += dt, steps += 1, leaf updates counted.
 __device__ void cfl_finalize(const View &v)
 {
+    if (v.lts) {
+        // level-0 step dt_0 = min over levels (cfl dx_l / smax_l) 2^l; dt_l = dt_0 / 2^l
+        if (threadIdx.x != 0) return;
+        double dt = __builtin_inf();
+        for (int g = 0; g < v.ngrid; ++g) {
+            const unsigned long long b = atomicExch(&v.smax[g], 0ull);
+            if (b) {
+                const double s = __longlong_as_double((long long)b);
+                const double d = ((v.cfl * v.grids[g].dx) / s) * (double)(1 << g);
+                if (d < dt) dt = d;
+            }
+        }
+        const double t = v.t[0];
+        const int done = t < v.t_end ? 0 : 1;
+        if (dt > v.t_end - t) dt = v.t_end - t;
+        double dl = dt;
+        for (int g = 0; g < v.ngrid; ++g) {
+            v.dt[g] = dl;
+            dl = dl * 0.5;
+        }
+        v.meta->done = done;
+        if (!done) {
+            v.t[0] = t + dt;
+            v.meta->steps += 1;
+            long long s = 0;
+            for (int l = 0; l < v.L; ++l) s += v.meta->leaf_cells[l] << l;
+            v.meta->leaf_updates += s;
+        }
+        v.meta->ticket = 0u;
+        return;
+    }
     if (v.mode == MODE_HIER) {
         if (threadIdx.x != 0) return;
         double dt = __builtin_inf();
@@ -698,15 +759,57 @@ __device__ __forceinline__ bool is_ghost(const View &v, const Grid &G, int x, in
     return hit != 0;
 }
 
-// Fill ghost cells (ghost list) or newly created cells (new list of level
-// lvl) by prediction from the next coarser level.
+// Third-order prediction of child (cx, cy, cz) of coarse cell p from the
+// linear time interpolation (1 - theta) Ao + theta An of the coarse field.
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int ghost)
+__device__ __forceinline__ T predict_child_t(const T *Ao, const T *An, T theta, int n, int bc, int px,
+                                             int py, int pz, int cx, int cy, int cz)
+{
+    int xs[3], ys[3], zs[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        xs[k] = bcmap(px + k - 1, n, bc);
+        ys[k] = bcmap(py + k - 1, n, bc);
+        zs[k] = D == 3 ? bcmap(pz + k - 1, n, bc) : 0;
+    }
+    const T om = T(1) - theta;
+    auto at = [&](int x, int y, int z) {
+        const int64_t i = gidx(n, x, y, z);
+        return om * Ao[i] + theta * An[i];
+    };
+    if (D == 2) {
+        T r[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r[j] = pred1<T>(at(xs[0], ys[j], 0), at(xs[1], ys[j], 0), at(xs[2], ys[j], 0), cx);
+        return pred1<T>(r[0], r[1], r[2], cy);
+    }
+    T s[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        T r[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r[j] = pred1<T>(at(xs[0], ys[j], zs[k]), at(xs[1], ys[j], zs[k]), at(xs[2], ys[j], zs[k]), cx);
+        s[k] = pred1<T>(r[0], r[1], r[2], cy);
+    }
+    return pred1<T>(s[0], s[1], s[2], cz);
+}
+
+// Prediction from the next coarser level into array A:
+//   mode 0: every cell of the blocks created at level lvl (new list);
+//   mode 1: every ghost cell of every level (ghost list);
+//   mode 2: the ghost cells of level lvl, from the coarse level's state
+//           interpolated in time between Qo (theta = 0) and Q (theta = 1).
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta)
 {
     if (v.meta->done) return;
-    const int off = ghost ? 0 : v.meta->new_off[lvl];
-    const int count = ghost ? v.meta->nghost : v.meta->new_cnt[lvl];
-    const Tile *list = ghost ? v.ghost : v.fresh;
+    int off, count;
+    const Tile *list;
+    if (mode == 0) { off = v.meta->new_off[lvl]; count = v.meta->new_cnt[lvl]; list = v.fresh; }
+    else if (mode == 1) { off = 0; count = v.meta->nghost; list = v.ghost; }
+    else { off = v.meta->ghost_off[lvl]; count = v.meta->ghost_cnt[lvl]; list = v.ghost; }
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const Tile tl = list[off + t];
@@ -718,12 +821,107 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int ghos
         const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
         for (int c = threadIdx.x; c < TC; c += blockDim.x) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
-            if (ghost && !is_ghost<D>(v, G, x, y, z)) continue;
+            if (mode != 0 && !is_ghost<D>(v, G, x, y, z)) continue;
             const int64_t id = gidx(G.n, x, y, z);
 #pragma unroll
-            for (int f = 0; f < D + 2; ++f)
-                A[G.off + f * G.ncell + id] = predict_child<T, D, T>(
-                    A + Cg.off + f * Cg.ncell, Cg.n, v.bc, x >> 1, y >> 1, z >> 1, x & 1, y & 1, z & 1);
+            for (int f = 0; f < D + 2; ++f) {
+                T val;
+                if (mode == 2)
+                    val = predict_child_t<T, D>((const T *)v.Qo + Cg.off + f * Cg.ncell,
+                                                (const T *)v.Q + Cg.off + f * Cg.ncell, (T)theta, Cg.n, v.bc,
+                                                x >> 1, y >> 1, z >> 1, x & 1, y & 1, z & 1);
+                else
+                    val = predict_child<T, D, T>(A + Cg.off + f * Cg.ncell, Cg.n, v.bc, x >> 1, y >> 1,
+                                                 z >> 1, x & 1, y & 1, z & 1);
+                A[G.off + f * G.ncell + id] = val;
+            }
+        }
+    }
+}
+
+// Local time stepping: keep level lvl's state at the start of its step (the
+// cells of its patches) for the time interpolation of finer ghost cells.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_copy_level(View v, int lvl)
+{
+    if (v.meta->done) return;
+    const int off = v.meta->act_off[lvl], count = v.meta->act_cnt[lvl];
+    constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
+    const T *Q = (const T *)v.Q;
+    T *Qo = (T *)v.Qo;
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const Tile tl = v.actv[off + t];
+        const Grid G = v.grids[tl.grid];
+        const int nb = G.nb;
+        const int ox = (tl.block % nb) * BS;
+        const int oy = ((tl.block / nb) % nb) * BS;
+        const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
+        for (int c = threadIdx.x; c < TC; c += blockDim.x) {
+            const int64_t id = G.off + gidx(G.n, ox + c % BS, oy + (c / BS) % BS, oz + (D == 3 ? c / (BS * BS) : 0));
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) Qo[f * G.ncell + id] = Q[f * G.ncell + id];
+        }
+    }
+}
+
+// Flux correction of level lvl after the two substeps of level lvl+1
+// (Berger-Colella): at every face between a leaf and a covered cell,
+// Q += s lam (F_c - Fbar), Fbar = (A_0 + A_1) / 2 with A_k the area mean of
+// the fine fluxes of substep k; axes in order, low face first.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_reflux(View v, int lvl)
+{
+    if (v.meta->done) return;
+    const int off = v.meta->leaf_off[lvl], count = v.meta->leaf_cnt[lvl];
+    constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
+    T *Q = (T *)v.Q;
+    const T *reg = (const T *)v.reg;
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const Tile tl = v.leaf[off + t];
+        const Grid G = v.grids[tl.grid];
+        const Grid F = v.grids[G.fine];
+        const int n = G.n, nb = G.nb, nf = F.n;
+        const int ox = (tl.block % nb) * BS;
+        const int oy = ((tl.block / nb) % nb) * BS;
+        const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
+        const T lam = (T)(v.dt[lvl] / G.dx);
+        for (int c = threadIdx.x; c < TC; c += blockDim.x) {
+            const int p[3] = {ox + c % BS, oy + (c / BS) % BS, oz + (D == 3 ? c / (BS * BS) : 0)};
+            if (covered(v, v.act, G, p[0], p[1], p[2])) continue;
+            const int64_t ip = gidx(n, p[0], p[1], p[2]);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                for (int s = -1; s <= 1; s += 2) {
+                    int nbc[3] = {p[0], p[1], p[2]};
+                    nbc[d] = bcmap(p[d] + s, n, v.bc);
+                    if (!covered(v, v.act, G, nbc[0], nbc[1], nbc[2])) continue;
+                    const int64_t ic = s > 0 ? ip : gidx(n, nbc[0], nbc[1], nbc[2]);
+                    int fb[3] = {2 * p[0], 2 * p[1], D == 3 ? 2 * p[2] : 0};
+                    fb[d] = bcmap(s > 0 ? 2 * p[d] + 1 : 2 * p[d] - 1, nf, v.bc);
+                    int c10[3] = {fb[0], fb[1], fb[2]}, c01[3] = {fb[0], fb[1], fb[2]}, c11[3] = {fb[0], fb[1], fb[2]};
+                    c10[t1] += 1;
+                    c01[t2] += 1;
+                    c11[t1] += 1;
+                    c11[t2] += 1;
+                    for (int f = 0; f < D + 2; ++f) {
+                        T A[2];
+                        for (int k = 0; k < 2; ++k) {
+                            const T *Rg = reg + F.rfoff + (((int64_t)k * D + d) * (D + 2) + f) * F.ncell;
+                            if (D == 2)
+                                A[k] = T(0.5) * (Rg[gidx(nf, fb[0], fb[1], 0)] + Rg[gidx(nf, c10[0], c10[1], 0)]);
+                            else
+                                A[k] = T(0.25) * ((Rg[gidx(nf, fb[0], fb[1], fb[2])] + Rg[gidx(nf, c10[0], c10[1], c10[2])]) +
+                                                  (Rg[gidx(nf, c01[0], c01[1], c01[2])] + Rg[gidx(nf, c11[0], c11[1], c11[2])]));
+                        }
+                        const T Fbar = T(0.5) * (A[0] + A[1]);
+                        const T Fc = reg[G.rcoff + ((int64_t)d * (D + 2) + f) * G.ncell + ic];
+                        T &q = Q[G.off + f * G.ncell + ip];
+                        if (s > 0) q = q + lam * (Fc - Fbar);
+                        else q = q - lam * (Fc - Fbar);
+                    }
+                }
+            }
         }
     }
 }

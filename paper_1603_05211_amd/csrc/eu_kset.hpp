@@ -27,8 +27,10 @@ struct KSet {
     void (*init)(const View &, const InitArgs &, int grid, int64_t ncell, hipStream_t);
     void (*restrict_full)(const View &, int arr, int grid_coarse, int64_t ncell, hipStream_t);
     void (*restrict_cov)(const View &, int arr, int lvl, int maxblocks, hipStream_t);
-    void (*predict)(const View &, int arr, int lvl, int ghost, int maxblocks, hipStream_t);
-    void (*fv_stage)(const View &, int stage, int maxtiles, hipStream_t);
+    void (*predict)(const View &, int arr, int lvl, int mode, double theta, int maxblocks, hipStream_t);
+    void (*fv_stage)(const View &, int stage, int lvl, int sub, int record, int maxtiles, hipStream_t);
+    void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
+    void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*cfl)(const View &, int maxtiles, hipStream_t);
     void (*totals)(const View &, int maxtiles, hipStream_t);
     void (*details)(const View &, int64_t ncell_coarse_levels, hipStream_t);

@@ -39,21 +39,35 @@ template <typename T> void restrict_cov(const View &v, int a, int lvl, int maxb,
     else k_restrict_cov<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl);
 }
 
-template <typename T> void predict(const View &v, int a, int lvl, int ghost, int maxb, hipStream_t s)
+template <typename T> void predict(const View &v, int a, int lvl, int mode, double theta, int maxb, hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 1024);
-    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, ghost);
-    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, ghost);
+    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta);
+    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta);
 }
 
-template <typename T> void fv_stage(const View &v, int stage, int maxt, hipStream_t s)
+template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, int record, int maxt, hipStream_t s)
 {
     const int nblk = clamp_grid(maxt, 16384);
     const T *src = (const T *)(stage == 1 ? v.Q : v.Qs);
     T *out = (T *)(stage == 1 ? v.Qs : v.Q);
     const double fac = stage == 1 ? 0.5 : 1.0;
-    if (v.dim == 2) k_fv_stage<T, 2><<<nblk, FV<2>::NT, 0, s>>>(v, src, (const T *)v.Q, out, fac);
-    else k_fv_stage<T, 3><<<nblk, FV<3>::NT, 0, s>>>(v, src, (const T *)v.Q, out, fac);
+    if (v.dim == 2) k_fv_stage<T, 2><<<nblk, FV<2>::NT, 0, s>>>(v, src, (const T *)v.Q, out, fac, lvl, sub, record);
+    else k_fv_stage<T, 3><<<nblk, FV<3>::NT, 0, s>>>(v, src, (const T *)v.Q, out, fac, lvl, sub, record);
+}
+
+template <typename T> void copy_level(const View &v, int lvl, int maxb, hipStream_t s)
+{
+    const int nblk = clamp_grid(maxb, 2048);
+    if (v.dim == 2) k_copy_level<T, 2><<<nblk, 64, 0, s>>>(v, lvl);
+    else k_copy_level<T, 3><<<nblk, 256, 0, s>>>(v, lvl);
+}
+
+template <typename T> void reflux(const View &v, int lvl, int maxb, hipStream_t s)
+{
+    const int nblk = clamp_grid(maxb, 1024);
+    if (v.dim == 2) k_reflux<T, 2><<<nblk, 64, 0, s>>>(v, lvl);
+    else k_reflux<T, 3><<<nblk, 256, 0, s>>>(v, lvl);
 }
 
 template <typename T> void cfl(const View &v, int maxt, hipStream_t s)
@@ -88,6 +102,8 @@ template <typename T> KSet make()
     k.restrict_cov = restrict_cov<T>;
     k.predict = predict<T>;
     k.fv_stage = fv_stage<T>;
+    k.copy_level = copy_level<T>;
+    k.reflux = reflux<T>;
     k.cfl = cfl<T>;
     k.totals = totals<T>;
     k.details = details<T>;

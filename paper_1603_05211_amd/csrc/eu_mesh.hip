@@ -210,9 +210,9 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
 template <int D>
 __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
 {
-    __shared__ unsigned long long part[MAXLEV][4];
+    __shared__ unsigned long long part[MAXLEV][NPART];
     if (v.meta->done) return;
-    if (threadIdx.x < MAXLEV * 4) part[threadIdx.x / 4][threadIdx.x % 4] = 0ull;
+    if (threadIdx.x < MAXLEV * NPART) part[threadIdx.x / NPART][threadIdx.x % NPART] = 0ull;
     __syncthreads();
     constexpr int cpb = D == 2 ? BS * BS : BS * BS * BS;
     constexpr int cpc = cpb >> D;   // cells of a coarse block covered by one child block
@@ -263,14 +263,17 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
         if (a) {
             atomicAdd(&part[lvl][0], (unsigned long long)(cpb - nchild * cpc));
             atomicAdd(&part[lvl][1], (unsigned long long)cpb);
+            atomicAdd(&part[lvl][6], 1ull);
         }
+        if (code & 1) atomicAdd(&part[lvl][4], 1ull);
         if (code & 2) atomicAdd(&part[lvl][2], 1ull);
+        if (code & 4) atomicAdd(&part[lvl][5], 1ull);
         if (code & 8) atomicAdd(&part[lvl][3], 1ull);
     }
     __syncthreads();
-    if (threadIdx.x < MAXLEV * 4)
-        v.cpart[((int64_t)blockIdx.x * MAXLEV + threadIdx.x / 4) * 4 + threadIdx.x % 4] =
-            (long long)part[threadIdx.x / 4][threadIdx.x % 4];
+    if (threadIdx.x < MAXLEV * NPART)
+        v.cpart[(int64_t)blockIdx.x * MAXLEV * NPART + threadIdx.x] =
+            (long long)part[threadIdx.x / NPART][threadIdx.x % NPART];
 }
 
 constexpr int LT = 1024;
@@ -284,24 +287,25 @@ template <int D>
 __global__ void __launch_bounds__(LT) k_compact(View v, int64_t nbt, int64_t nslot, int nsub)
 {
     constexpr int PER = 4;                 // blocks per thread per chunk
-    __shared__ int wcnt[4][NW];
-    __shared__ int base[4];
+    constexpr int NL = 5;                  // leaf, covered, ghost, new, patch blocks
+    __shared__ int wcnt[NL][NW];
+    __shared__ int base[NL];
     __shared__ int64_t lstart[MAXLEV + 1];
     if (v.meta->done) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < 4) base[tid] = 0;
+    if (tid < NL) base[tid] = 0;
     if (tid <= MAXLEV) lstart[tid] = tid < v.L ? v.grids[tid].boff : nbt;
     // per-level totals of the classification partials and of the flagged
     // cells (integer sums: the result does not depend on the order)
-    __shared__ unsigned long long lsum[MAXLEV][4];
+    __shared__ unsigned long long lsum[MAXLEV][NPART];
     __shared__ int nfl[MAXLEV];
-    if (tid < MAXLEV * 4) lsum[tid / 4][tid % 4] = 0ull;
+    if (tid < MAXLEV * NPART) lsum[tid / NPART][tid % NPART] = 0ull;
     if (tid < MAXLEV) nfl[tid] = 0;
     __syncthreads();
-    for (int i = tid; i < v.ncls * v.L * 4; i += LT) {
-        const int w = i / (v.L * 4), r = i % (v.L * 4);
-        const long long p = v.cpart[((int64_t)w * MAXLEV + r / 4) * 4 + r % 4];
-        if (p) atomicAdd(&lsum[r / 4][r % 4], (unsigned long long)p);
+    for (int i = tid; i < v.ncls * v.L * NPART; i += LT) {
+        const int w = i / (v.L * NPART), r = i % (v.L * NPART);
+        const long long p = v.cpart[((int64_t)w * MAXLEV + r / NPART) * NPART + r % NPART];
+        if (p) atomicAdd(&lsum[r / NPART][r % NPART], (unsigned long long)p);
     }
     for (int64_t s = tid; s < nslot; s += LT) {
         const int f = v.fcnt[s];
@@ -318,30 +322,34 @@ __global__ void __launch_bounds__(LT) k_compact(View v, int64_t nbt, int64_t nsl
         v.meta->act_cells[tid] = in ? (long long)lsum[tid][1] : 0;
         v.meta->cov_cnt[tid] = in ? (int)lsum[tid][2] : 0;
         v.meta->new_cnt[tid] = in ? (int)lsum[tid][3] : 0;
+        v.meta->leaf_cnt[tid] = in ? (int)lsum[tid][4] : 0;
+        v.meta->ghost_cnt[tid] = in ? (int)lsum[tid][5] : 0;
+        v.meta->act_cnt[tid] = in ? (int)lsum[tid][6] : 0;
         v.meta->nflag[tid] = in ? nfl[tid] : 0;
     }
     __syncthreads();
-    Tile *lists[4] = {v.leaf, v.cov, v.ghost, v.fresh};
+    Tile *lists[NL] = {v.leaf, v.cov, v.ghost, v.fresh, v.actv};
     for (int64_t c0 = 0; c0 < nbt; c0 += (int64_t)LT * PER) {
         const int64_t g0 = c0 + (int64_t)tid * PER;
         int codes[PER], lv[PER];
-        int cnt[4] = {0, 0, 0, 0};
+        int cnt[NL] = {0, 0, 0, 0, 0};
         for (int j = 0; j < PER; ++j) {
             const int64_t gb = g0 + j;
             codes[j] = 0;
             lv[j] = 0;
             if (gb < nbt) {
-                const int code = v.code[gb];
+                int code = v.code[gb] & 15;
+                if (code & 3) code |= 16;  // bit 4: in a patch
                 int lvl = 0;
                 while (gb >= lstart[lvl + 1]) ++lvl;
                 codes[j] = code;
                 lv[j] = lvl;
-                for (int k = 0; k < 4; ++k) cnt[k] += (code >> k) & 1;
+                for (int k = 0; k < NL; ++k) cnt[k] += (code >> k) & 1;
             }
         }
     // exclusive scan of the per-thread counts (wave scan + wave totals)
-        int excl[4];
-        for (int k = 0; k < 4; ++k) {
+        int excl[NL];
+        for (int k = 0; k < NL; ++k) {
             int incl = cnt[k];
             for (int o = 1; o < 64; o <<= 1) {
                 const int r = __shfl_up(incl, o);
@@ -351,7 +359,7 @@ __global__ void __launch_bounds__(LT) k_compact(View v, int64_t nbt, int64_t nsl
             if (lane == 63) wcnt[k][wave] = incl;
         }
         __syncthreads();
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NL; ++k) {
             int off = base[k] + excl[k];
             for (int w = 0; w < wave; ++w) off += wcnt[k][w];
             for (int j = 0; j < PER; ++j)
@@ -361,7 +369,7 @@ __global__ void __launch_bounds__(LT) k_compact(View v, int64_t nbt, int64_t nsl
                 }
         }
         __syncthreads();
-        if (tid < 4) {
+        if (tid < NL) {
             int s = 0;
             for (int w = 0; w < NW; ++w) s += wcnt[tid][w];
             base[tid] += s;
@@ -371,10 +379,13 @@ __global__ void __launch_bounds__(LT) k_compact(View v, int64_t nbt, int64_t nsl
     if (tid == 0) {
         v.meta->nleaf = base[0];
         v.meta->nghost = base[2];
-        int co = 0, no = 0;
+        int co = 0, no = 0, lo = 0, go = 0, ao = 0;
         for (int l = 0; l < MAXLEV; ++l) {
             v.meta->cov_off[l] = co; co += v.meta->cov_cnt[l];
             v.meta->new_off[l] = no; no += v.meta->new_cnt[l];
+            v.meta->leaf_off[l] = lo; lo += v.meta->leaf_cnt[l];
+            v.meta->ghost_off[l] = go; go += v.meta->ghost_cnt[l];
+            v.meta->act_off[l] = ao; ao += v.meta->act_cnt[l];
         }
     }
     // patch table

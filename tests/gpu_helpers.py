@@ -6,7 +6,7 @@ import sys
 import numpy as np
 
 import oracle as orc
-from paper_1603_05211_amd import EU_FP32, EU_FP64, Solver, inputs
+from paper_1603_05211_amd import EU_DT_GLOBAL, EU_DT_LTS, EU_FP32, EU_FP64, Solver, inputs
 
 G = 1.4
 
@@ -63,13 +63,14 @@ def state_errors(h, s, which=0):
 
 
 def make_pair(dim, levels, n0, precision=EU_FP64, bc=0, eps=1e-3, lo=None, hi=None, cfl=0.45,
-              t_end=math.inf, pmax=32):
+              t_end=math.inf, pmax=32, lts=False):
     lo = (0.0 if dim == 2 else -1.0) if lo is None else lo
     hi = 1.0 if hi is None else hi
     h = orc.Hierarchy(dim, levels, n0, bc=bc, lo=lo, hi=hi, eps=eps, pmax=pmax)
     s = Solver(dim, n0=n0, levels=levels, precision=precision, bc=bc, cfl=cfl, t_end=t_end, eps=eps,
-               lo=lo, hi=hi, patch_max=pmax)
+               lo=lo, hi=hi, patch_max=pmax, time_mode=EU_DT_LTS if lts else EU_DT_GLOBAL)
     h.cfl_number = cfl
+    h.lts = lts
     return h, s
 
 
@@ -95,7 +96,10 @@ def run_pair(h, s, steps, t_end=math.inf, regrid=True):
     for _ in range(steps):
         if h.t >= t_end:
             break
-        dts_o.append(h.step(cfl, t_end, regrid=regrid))
+        if getattr(h, "lts", False):
+            dts_o.append(h.step_lts(cfl, t_end, regrid=regrid)[0])
+        else:
+            dts_o.append(h.step(cfl, t_end, regrid=regrid))
         s.step(regrid)
         dts_g.append(s.time()[1])
     return np.array(dts_o), np.array(dts_g)
