@@ -111,6 +111,23 @@ def extra_uniform(dim, n, precision, steps, seed=0):
     return out
 
 
+def extra_adaptive3d_lts(precision, steps, seed=0):
+    """3D ellipsoid, 4 levels 32^3..256^3, eps 1e-3, local time stepping."""
+    from paper_1603_05211_amd import EU_DT_LTS, EU_FP32, EU_FP64, Solver, inputs
+    e = inputs.ellipsoid(seed)
+    s = Solver(3, n0=32, levels=4, precision=EU_FP32 if precision == "fp32" else EU_FP64, cfl=0.4,
+               t_end=0.2, eps=1e-3, eta=0.8, patch_min=8, patch_max=32, lo=-1.0, hi=1.0,
+               time_mode=EU_DT_LTS)
+    s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
+    s.advance(2, use_graph=True)
+    done, upd, dt = timed_advance(s, steps)
+    leaves, active = s.counters()
+    out = {"value": upd / dt, "steps": done, "ms_per_level0_step": 1e3 * dt / max(done, 1),
+           "leaves": [int(x) for x in leaves], "patch_cells": [int(x) for x in active]}
+    s.close()
+    return out
+
+
 def extra_batch(precision, steps, seed=0):
     from paper_1603_05211_amd import EU_FP32, EU_FP64, Solver, inputs
     b = inputs.batch(seed)
@@ -201,6 +218,7 @@ def main():
         ex["ellip3d_uniform256_fp32"] = extra_uniform(3, 256, "fp32", 40)
         ex["ellip3d_uniform256_fp64"] = extra_uniform(3, 256, "fp64", 20)
         ex["quad2d_batch512_fp32"] = extra_batch("fp32", 20)
+        ex["ellip3d_adaptive4_lts_fp32"] = extra_adaptive3d_lts("fp32", 10)
         result["extra"] = ex
     print(json.dumps(result), flush=True)
 

@@ -1,0 +1,90 @@
+"""Full-size workloads (the configurations the benchmark runs), compared with
+the oracle where the oracle can follow: whole runs for a few steps, or the
+instances of a batch sampled one by one (instances are independent)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1603_05211_amd import EU_DT_LTS, EU_FP32, EU_FP64, Solver, inputs
+
+from gpu_helpers import G, compare_masks, init_pair, make_pair, run_pair, say, state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def test_full_3d_adaptive_lts_fp64_one_step():
+    """3D ellipsoid, 4 levels 32^3..256^3, eps 1e-3, local time stepping:
+    initial hierarchy and one level-0 step (8 finest substeps), FP64."""
+    say("full 3d adaptive lts fp64")
+    h, s = make_pair(3, 4, 32, cfl=0.4, lts=True, t_end=0.2)
+    init_pair(h, s, "ellipsoid", 0)
+    compare_masks(h, s)
+    do, dg = run_pair(h, s, 1, t_end=0.2)
+    assert np.array_equal(do, dg)
+    compare_masks(h, s)
+    linf, _ = state_errors(h, s)
+    say("  linf", linf)
+    assert linf.max() <= 1e-12
+
+
+def test_full_3d_adaptive_lts_fp32_runs():
+    """The same configuration in FP32 (the benchmarked precision) for several
+    level-0 steps: physical state, totals conserved to FP32 rounding."""
+    e = inputs.ellipsoid(0)
+    s = Solver(3, n0=32, levels=4, precision=EU_FP32, cfl=0.4, t_end=0.2, eps=1e-3, lo=-1.0, hi=1.0,
+               time_mode=EU_DT_LTS)
+    s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
+    T0 = s.conserved_totals()
+    n = s.advance(5, use_graph=True)
+    assert n == 5 and s.status() == 0
+    T1 = s.conserved_totals()
+    rel = np.abs(T1 - T0) / np.maximum(np.abs(T0), 1.0)
+    say("  fp32 lts totals drift", rel)
+    # outflow boundaries: mass and energy only change by boundary fluxes, which
+    # vanish while the blast stays inside the domain
+    assert rel[0] < 1e-5 and rel[4] < 1e-5
+
+
+@pytest.mark.parametrize("precision", [EU_FP64, EU_FP32])
+def test_full_batch_512_sampled_instances(precision):
+    """512 instances (sides 32..512), one launch per stage for all of them;
+    sampled instances against the oracle run on that instance alone."""
+    b = inputs.batch(0)
+    s = Solver(2, sides=list(b.sides), precision=precision, cfl=0.45)
+    s.init_quadrant_batch(b.states)
+    steps = 6 if precision == EU_FP64 else 20
+    assert s.advance(steps, use_graph=True) == steps
+    rng = np.random.default_rng(123)
+    small = np.flatnonzero(b.sides <= 128)
+    picks = list(rng.choice(small, size=4, replace=False)) + [int(np.argmax(b.sides))]
+    for i in picks:
+        n = int(b.sides[i])
+        h = orc.Hierarchy(2, 1, n)
+        h.init_finest(orc.init_quadrant(n, G, b.states[i]))
+        for _ in range(steps):
+            h.step(0.45)
+        Qo, Qg = h.level(0), s.level(0, inst=i)
+        if precision == EU_FP64:
+            err = np.abs(Qg - Qo).max() / np.abs(Qo).max()
+            say(f"  instance {i} side {n}: linf {err:.2e}")
+            assert err <= 1e-12
+        else:
+            rel = np.abs(Qg[0] - Qo[0]).sum() / np.abs(Qo[0]).sum()
+            say(f"  instance {i} side {n}: fp32 rho L1 rel {rel:.2e}")
+            assert rel <= 1e-5
+
+
+def test_full_3d_uniform_256_fp32_error():
+    """256^3 ellipsoid in FP32 against the FP64 oracle after 2 steps."""
+    h, s = make_pair(3, 1, 256, precision=EU_FP32, cfl=0.4)
+    init_pair(h, s, "ellipsoid", 0)
+    for _ in range(2):
+        h.step(0.4)
+    s.advance(2, use_graph=True)
+    Qo, Qg = h.level(0), s.level(0)
+    rel = np.abs(Qg[0] - Qo[0]).sum() / np.abs(Qo[0]).sum()
+    linf = np.abs(Qg - Qo).max(axis=(1, 2, 3)) / np.abs(Qo).max(axis=(1, 2, 3))
+    say(f"  fp32 256^3: rho L1 rel {rel:.2e}, linf {linf}")
+    assert rel <= 1e-5
