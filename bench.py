@@ -104,9 +104,10 @@ def extra_uniform(dim, n, precision, steps, seed=0):
         s = Solver(3, n0=n, levels=1, precision=prec, cfl=0.4, lo=-1.0, hi=1.0)
         s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
     s.advance(3, use_graph=True)
+    variant, _ = s.autotune(reps=5)
     done, upd, dt = timed_advance(s, steps)
     ms, nl, cells = kernel_profile(s, 4)
-    out = {"value": upd / dt, "steps": done, "fv_stage_ms": ms}
+    out = {"value": upd / dt, "steps": done, "fv_stage_ms": ms, "stage_schedule": variant}
     s.close()
     return out
 
@@ -120,9 +121,11 @@ def extra_adaptive3d_lts(precision, steps, seed=0):
                time_mode=EU_DT_LTS)
     s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
     s.advance(2, use_graph=True)
+    variant, _ = s.autotune(reps=3)
     done, upd, dt = timed_advance(s, steps)
     leaves, active = s.counters()
     out = {"value": upd / dt, "steps": done, "ms_per_level0_step": 1e3 * dt / max(done, 1),
+           "stage_schedule": variant,
            "leaves": [int(x) for x in leaves], "patch_cells": [int(x) for x in active]}
     s.close()
     return out
@@ -134,10 +137,11 @@ def extra_batch(precision, steps, seed=0):
     s = Solver(2, sides=list(b.sides), precision=EU_FP32 if precision == "fp32" else EU_FP64, cfl=0.45)
     s.init_quadrant_batch(b.states)
     s.advance(3, use_graph=True)
+    variant, _ = s.autotune(reps=3)
     done, upd, dt = timed_advance(s, steps)
     ms, nl, cells = kernel_profile(s, 4)
     out = {"value": upd / dt, "steps": done, "cells_per_step": int(b.sides.astype(float).__pow__(2).sum()),
-           "fv_stage_ms": ms}
+           "fv_stage_ms": ms, "stage_schedule": variant}
     s.close()
     return out
 
@@ -161,6 +165,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     s = make_adaptive(args.precision)
+    variant, variant_ms = s.autotune(reps=10)
+    log(f"autotuned stage schedule {variant} ({variant_ms})")
     log(f"warmup {args.warmup} steps")
     s.advance(args.warmup, use_graph=True)
     log(f"timing {args.steps} steps")
@@ -194,6 +200,7 @@ def main():
                                "32^2..512^2, eps 1e-3, eta 0.8, patches 8..32, global dt, CFL 0.45, "
                                "t_end 0.25",
                    "precision": args.precision, "leaf_updates": upd,
+                   "stage_schedule": variant, "stage_schedule_ms": variant_ms,
                    "leaves_per_step_mean": upd / max(done, 1)},
         "roofline": {"bound": "alu", "kernel": "k_fv_stage", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,

@@ -212,6 +212,16 @@ int eu_time(eu_ctx *ctx, double *t_host, double *dt_host);
 int eu_profile(eu_ctx *ctx, int enable);
 int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
 
+/* Schedule of the finite-volume stage kernel (threads per tile, faces axis by
+ * axis or in one pass).  Every schedule gives bit-identical results.
+ * eu_autotune times each schedule (reps launches of the first stage on the
+ * current state, HIP events on the context's stream; the state is left
+ * unchanged) and keeps the fastest: *variant_host receives it, ms_host
+ * (nullable, 4 entries) the mean time of each.  eu_set_variant forces one
+ * (0..3).  Both drop captured graphs. */
+int eu_autotune(eu_ctx *ctx, int reps, int *variant_host, float *ms_host);
+int eu_set_variant(eu_ctx *ctx, int variant);
+
 /* Non-physical status: EU_OK or EU_ENONPHYS (synchronises). */
 int eu_status(eu_ctx *ctx);
 int eu_clear_status(eu_ctx *ctx);

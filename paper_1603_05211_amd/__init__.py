@@ -247,6 +247,17 @@ class Solver:
         self._check(self._lib.eu_kernel_time(self._ctx, C.byref(ms), C.byref(n)), "eu_kernel_time")
         return ms.value, n.value
 
+    def autotune(self, reps: int = 20):
+        """Time every stage-kernel schedule on the current state and keep the
+        fastest; returns (variant, per-variant ms)."""
+        var = C.c_int(0)
+        ms = (C.c_float * 4)()
+        self._check(self._lib.eu_autotune(self._ctx, reps, C.byref(var), ms), "eu_autotune")
+        return var.value, list(ms)
+
+    def set_variant(self, variant: int):
+        self._check(self._lib.eu_set_variant(self._ctx, variant), "eu_set_variant")
+
     def status(self):
         return self._lib.eu_status(self._ctx)
 

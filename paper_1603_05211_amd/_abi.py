@@ -66,6 +66,8 @@ SIGNATURES = {
     "eu_time": (C.c_int, [_vp, _dp, _dp]),
     "eu_profile": (C.c_int, [_vp, C.c_int]),
     "eu_kernel_time": (C.c_int, [_vp, _dp, _i64p]),
+    "eu_autotune": (C.c_int, [_vp, C.c_int, _ip, C.POINTER(C.c_float)]),
+    "eu_set_variant": (C.c_int, [_vp, C.c_int]),
     "eu_status": (C.c_int, [_vp]),
     "eu_clear_status": (C.c_int, [_vp]),
     "eu_last_error": (C.c_char_p, [_vp]),

@@ -31,6 +31,7 @@ struct eu_ctx {
     int ngroups = 1;
     int64_t state_elems = 0;    // elements of one state array
     bool initialized = false;
+    int variant = 0;            // stage-kernel schedule (eu_autotune)
     std::string err;
     // graphs: [0] step with regrid, [1] step without
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -285,12 +286,12 @@ void seq_fv_step(eu_ctx *c, bool ghost_after)
 {
     hipEvent_t e;
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, c->stream);
+    c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, c->variant, c->stream);
     prof_end(c, e);
     seq_restrict(c, ARR_QS);
     seq_ghost(c, ARR_QS);
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 2, -1, 0, 0, c->max_tiles, c->stream);
+    c->ks->fv_stage(c->v, 2, -1, 0, 0, c->max_tiles, c->variant, c->stream);
     prof_end(c, e);
     seq_restrict(c, ARR_Q);
     if (ghost_after) seq_ghost(c, ARR_Q);
@@ -329,11 +330,11 @@ void lts_advance(eu_ctx *c, int l, int k)
     hipEvent_t e;
     c->ks->copy_level(c->v, l, nbl, c->stream);
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 1, l, k, 0, nbl, c->stream);
+    c->ks->fv_stage(c->v, 1, l, k, 0, nbl, c->variant, c->stream);
     prof_end(c, e);
     if (l >= 1) c->ks->predict(c->v, ARR_QS, l, 2, (double)(2 * k + 1) * 0.25, nbl, c->stream);
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 2, l, k, 1, nbl, c->stream);
+    c->ks->fv_stage(c->v, 2, l, k, 1, nbl, c->variant, c->stream);
     prof_end(c, e);
     if (l + 1 < c->L) {
         const int nbf = (int)nblocks_grid(c, l + 1);
@@ -887,6 +888,64 @@ int eu_kernel_time(eu_ctx *c, double *ms, int64_t *launches)
     harvest_profile(c);
     if (ms) *ms = c->prof_ms;
     if (launches) *launches = c->prof_n;
+    return EU_OK;
+}
+
+int eu_set_variant(eu_ctx *c, int variant)
+{
+    if (!c) return EU_EINVAL;
+    if (variant < 0 || variant >= FV_VARIANTS) return set_err(c, EU_EINVAL, "bad variant");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->variant = variant;
+    drop_graphs(c);
+    return EU_OK;
+}
+
+int eu_autotune(eu_ctx *c, int reps, int *variant_host, float *ms_host)
+{
+    if (!c || reps < 1) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Meta m;
+    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
+    if (m.done) return set_err(c, EU_ESTATE, "the run has reached t_end");
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    // first stage only: it reads Q and writes the stage array, which every
+    // step recomputes, so timing it leaves the state untouched
+    auto stage1 = [&](int var) {
+        if (c->v.lts)
+            for (int l = 0; l < c->L; ++l) c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, c->stream);
+        else
+            c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, var, c->stream);
+    };
+    int best = 0;
+    float best_ms = 0.f;
+    for (int var = 0; var < FV_VARIANTS; ++var) {
+        stage1(var);
+        (void)hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps; ++r) stage1(var);
+        (void)hipEventRecord(e1, c->stream);
+        hipError_t err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return set_err(c, EU_EHIP, "autotune timing failed: %s", hipGetErrorString(err));
+        }
+        ms /= (float)reps;
+        if (ms_host) ms_host[var] = ms;
+        if (var == 0 || ms < best_ms) { best = var; best_ms = ms; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int r = check_launch(c);
+    if (r) return r;
+    c->variant = best;
+    drop_graphs(c);
+    if (variant_host) *variant_host = best;
     return EU_OK;
 }
 

@@ -70,13 +70,24 @@ __device__ __forceinline__ T slope_va(T wm, T w0, T wp)
     }
 }
 
-// AUSM+ (Liou 1996) across a face with normal along axis DN; wL, wR are the
-// primitive face states; gi = 1 / (gamma - 1).
-template <typename T, int D, int DN>
-__device__ __forceinline__ void ausm_plus(T g, T gi, const T *wL, const T *wR, T *F)
+// velocity component along axis dn of a primitive state (selects, so a
+// runtime axis stays in registers)
+template <typename T, int D>
+__device__ __forceinline__ T vel_along(const T *w, int dn)
 {
-    const T rL = wL[0], pL = wL[D + 1], uL = wL[1 + DN];
-    const T rR = wR[0], pR = wR[D + 1], uR = wR[1 + DN];
+    T u = w[1];
+    if (D >= 2) u = dn == 1 ? w[2] : u;
+    if (D >= 3) u = dn == 2 ? w[3] : u;
+    return u;
+}
+
+// AUSM+ (Liou 1996) across a face with normal along axis dn; wL, wR are the
+// primitive face states; gi = 1 / (gamma - 1).
+template <typename T, int D>
+__device__ __forceinline__ void ausm_plus(T g, T gi, int dn, const T *wL, const T *wR, T *F)
+{
+    const T rL = wL[0], pL = wL[D + 1], uL = vel_along<T, D>(wL, dn);
+    const T rR = wR[0], pR = wR[D + 1], uR = vel_along<T, D>(wR, dn);
     const T cL = Ar<T>::sqrt(Ar<T>::div(g * pL, rL));
     const T cR = Ar<T>::sqrt(Ar<T>::div(g * pR, rR));
     const T ch = T(0.5) * (cL + cR);
@@ -115,15 +126,15 @@ __device__ __forceinline__ void ausm_plus(T g, T gi, const T *wL, const T *wR, T
     F[0] = mf * ru;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        F[1 + k] = mf * (ru * wu[1 + k]);
-        if (k == DN) F[1 + k] = F[1 + k] + ph;
+        const T fk = mf * (ru * wu[1 + k]);
+        F[1 + k] = k == dn ? fk + ph : fk;
     }
     F[D + 1] = mf * rH;
 }
 
-// Face flux from the primitive states of the 4 cells i-1, i, i+1, i+2 along DN.
-template <typename T, int D, int DN>
-__device__ __forceinline__ void face_flux4(T g, T gi, const T *wa, const T *wb, const T *wc,
+// Face flux from the primitive states of the 4 cells i-1, i, i+1, i+2 along dn.
+template <typename T, int D>
+__device__ __forceinline__ void face_flux4(T g, T gi, int dn, const T *wa, const T *wb, const T *wc,
                                            const T *wd, T *F)
 {
     T wL[D + 2], wR[D + 2];
@@ -132,45 +143,45 @@ __device__ __forceinline__ void face_flux4(T g, T gi, const T *wa, const T *wb, 
         wL[f] = wb[f] + T(0.5) * slope_va<T>(wa[f], wb[f], wc[f]);
         wR[f] = wc[f] - T(0.5) * slope_va<T>(wb[f], wc[f], wd[f]);
     }
-    ausm_plus<T, D, DN>(g, gi, wL, wR, F);
+    ausm_plus<T, D>(g, gi, dn, wL, wR, F);
 }
 
 // Mean of the 2^(D-1) fine fluxes on the face between coarse cell p (global
-// coordinates on grid G) and its covered neighbour on side s of axis DN,
+// coordinates on grid G) and its covered neighbour on side s of axis dn,
 // computed from the next finer grid of the stencil source (virtual leaves,
-// Sec. 2.1).
-template <typename T, int D, int DN>
-__device__ void fine_mean(const View &v, const Grid &G, const T *src, int px, int py, int pz,
-                          int s, T g, T gi, T *F)
+// Sec. 2.1).  Transverse offsets: first along the lower transverse axis.
+template <typename T, int D>
+__device__ void fine_mean(const View &v, const Grid &G, const T *src, int px, int py, int pz, int s,
+                          int dn, T g, T gi, T *F)
 {
     const Grid gf = v.grids[G.fine];
     const T *S = src + gf.off;
     const int nf = gf.n;
     const int64_t Nf = gf.ncell;
-    int b[3] = {2 * px, 2 * py, 2 * pz};
-    b[DN] = s > 0 ? 2 * (DN == 0 ? px : DN == 1 ? py : pz) + 1
-                  : 2 * (DN == 0 ? px : DN == 1 ? py : pz) - 1;
-    constexpr int T1 = DN == 0 ? 1 : 0;
-    constexpr int T2 = DN == 2 ? 1 : 2;
+    const int along = dn == 0 ? px : dn == 1 ? py : pz;
+    const int bd = s > 0 ? 2 * along + 1 : 2 * along - 1;
+    const int t1 = dn == 0 ? 1 : 0;   // lower transverse axis
+    const int t2 = dn == 2 ? 1 : 2;   // upper transverse axis (3D)
     constexpr int NS = D == 2 ? 2 : 4;
     T Fs[NS][D + 2];
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        int c[3] = {b[0], b[1], b[2]};
-        c[T1] += k & 1;
-        if (D == 3) c[T2] += (k >> 1) & 1;
+        const int o1 = k & 1, o2 = D == 3 ? (k >> 1) & 1 : 0;
+        int c[3] = {2 * px, 2 * py, 2 * pz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c[a] += (a == t1 ? o1 : 0) + (a == t2 ? o2 : 0);
         T w[4][D + 2];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            int e[3] = {c[0], c[1], c[2]};
-            e[DN] = bcmap(c[DN] + j - 1, nf, v.bc);
-            const int64_t id = gidx(nf, e[0], e[1], D == 3 ? e[2] : 0);
+            const int e = bcmap(bd + j - 1, nf, v.bc);
+            const int ex = dn == 0 ? e : c[0], ey = dn == 1 ? e : c[1], ez = dn == 2 ? e : c[2];
+            const int64_t id = gidx(nf, ex, ey, D == 3 ? ez : 0);
             T q[D + 2];
 #pragma unroll
             for (int f = 0; f < D + 2; ++f) q[f] = S[f * Nf + id];
             cons2prim<T, D>(q, w[j], g);
         }
-        face_flux4<T, D, DN>(g, gi, w[0], w[1], w[2], w[3], Fs[k]);
+        face_flux4<T, D>(g, gi, dn, w[0], w[1], w[2], w[3], Fs[k]);
     }
 #pragma unroll
     for (int f = 0; f < D + 2; ++f) {
@@ -255,101 +266,106 @@ __device__ __forceinline__ bool covered(const View &v, const uint8_t *mask, cons
 // ----------------------------------------------------------------------------
 // finite-volume stage on every leaf of the tiles of the leaf list
 // ----------------------------------------------------------------------------
-template <int D> struct FV {
+// Tile geometry of the stage kernel: one BS^D block with a 2-cell halo,
+// NT threads.
+template <int D, int NT_> struct FV {
     static constexpr int B = BS, H = 2, E = BS + 4;
-    static constexpr int NT = D == 2 ? 64 : 256;
+    static constexpr int NT = NT_;
     static constexpr int NE = D == 2 ? E * E : E * E * E;
     static constexpr int NV = D + 2;
     static constexpr int TC = D == 2 ? B * B : B * B * B;
-    static constexpr int CPT = TC / NT;
-    static constexpr int NF = (B + 1) * (D == 2 ? B : B * B);
+    static constexpr int CPT = (TC + NT - 1) / NT;
+    static constexpr int NF = (B + 1) * (D == 2 ? B : B * B);   // faces per axis
 };
 
-template <typename T, int D, int DN>
-__device__ __forceinline__ void fv_faces(const View &v, const Grid &G, const T *src, int ox, int oy,
-                                         int oz, const T (*sW)[FV<D>::NE], const uint8_t *sCov,
-                                         const uint8_t *sAct, T (*sF)[FV<D>::NF], T g, T gi,
-                                         bool lts, bool record, int sub)
+// Flux of face fi of axis dn of the tile (fi = a + (B+1) r: a-th face along
+// the axis, r-th line across it), written to F.
+template <typename T, int D, int NT>
+__device__ __forceinline__ void fv_face(const View &v, const Grid &G, const T *src, int ox, int oy, int oz,
+                                        const T (*sW)[FV<D, NT>::NE], const uint8_t *sCov,
+                                        const uint8_t *sAct, T g, T gi, bool lts, bool record, int sub,
+                                        int dn, int fi, T *F)
 {
-    using C = FV<D>;
+    using C = FV<D, NT>;
     constexpr int E = C::E, H = C::H, B = C::B;
-    constexpr int SD = DN == 0 ? 1 : DN == 1 ? E : E * E;
-    for (int fi = threadIdx.x; fi < C::NF; fi += C::NT) {
-        const int a = fi % (B + 1), r = fi / (B + 1);
-        int l[3];
-        // local coordinates of the left cell
-        if (DN == 0) { l[0] = a - 1; l[1] = r % B; l[2] = D == 3 ? r / B : 0; }
-        else if (DN == 1) { l[1] = a - 1; l[0] = r % B; l[2] = D == 3 ? r / B : 0; }
-        else { l[2] = a - 1; l[0] = r % B; l[1] = r / B; }
-        const int hl = (l[0] + H) + E * ((l[1] + H) + (D == 3 ? E * (l[2] + H) : 0));
-        const int hr = hl + SD;
-        const bool lin = a >= 1, rin = a <= B - 1;
-        const bool lcov = sCov[hl] != 0, rcov = sCov[hr] != 0;
-        // global mode: fluxes of faces next to a leaf of the tile; local time
-        // stepping: every face of the tile (whole patches are updated)
-        const bool need = lts ? (lin || rin) : ((lin && !lcov) || (rin && !rcov));
-        T F[D + 2];
-        if (!need) {
+    const int SD = dn == 0 ? 1 : dn == 1 ? E : E * E;
+    const int a = fi % (B + 1), r = fi / (B + 1);
+    // local coordinates of the left cell
+    const int r0 = r % B, r1 = D == 3 ? r / B : 0;
+    const int lx = dn == 0 ? a - 1 : r0;
+    const int ly = dn == 1 ? a - 1 : (dn == 0 ? r0 : r1);
+    const int lz = D == 3 ? (dn == 2 ? a - 1 : r1) : 0;
+    const int hl = (lx + H) + E * ((ly + H) + (D == 3 ? E * (lz + H) : 0));
+    const int hr = hl + SD;
+    const bool lin = a >= 1, rin = a <= B - 1;
+    const bool lcov = sCov[hl] != 0, rcov = sCov[hr] != 0;
+    // global mode: fluxes of faces next to a leaf of the tile; local time
+    // stepping: every face of the tile (whole patches are updated)
+    const bool need = lts ? (lin || rin) : ((lin && !lcov) || (rin && !rcov));
+    if (!need) {
 #pragma unroll
-            for (int f = 0; f < D + 2; ++f) F[f] = T(0);
-        } else if (!lts && (lcov || rcov)) {
-            int p[3] = {ox + l[0], oy + l[1], oz + l[2]};
-            int s = +1;
-            if (lcov) { p[DN] += 1; s = -1; }
-            fine_mean<T, D, DN>(v, G, src, p[0], p[1], D == 3 ? p[2] : 0, s, g, gi, F);
-        } else {
-            T wa[D + 2], wb[D + 2], wc[D + 2], wd[D + 2];
-#pragma unroll
-            for (int f = 0; f < D + 2; ++f) {
-                wa[f] = sW[f][hl - SD];
-                wb[f] = sW[f][hl];
-                wc[f] = sW[f][hr];
-                wd[f] = sW[f][hr + SD];
-            }
-            face_flux4<T, D, DN>(g, gi, wa, wb, wc, wd, F);
-            if (record) {
-                // registers are indexed by the cell on the low side of the face
-                int q[3] = {ox + l[0], oy + l[1], oz + l[2]};
-                q[DN] = bcmap(q[DN], G.n, v.bc);
-                const int64_t iq = gidx(G.n, q[0], q[1], D == 3 ? q[2] : 0);
-                const bool lact = sAct[hl] != 0, ract = sAct[hr] != 0;
-                const bool lleaf = lact && !lcov, rleaf = ract && !rcov;
-                T *reg = (T *)v.reg;
-                if (G.rcoff >= 0 && ((lleaf && rcov) || (rleaf && lcov)))
-#pragma unroll
-                    for (int f = 0; f < D + 2; ++f)
-                        reg[G.rcoff + ((int64_t)DN * (D + 2) + f) * G.ncell + iq] = F[f];
-                if (G.rfoff >= 0 && lact != ract)
-#pragma unroll
-                    for (int f = 0; f < D + 2; ++f)
-                        reg[G.rfoff + (((int64_t)sub * D + DN) * (D + 2) + f) * G.ncell + iq] = F[f];
-            }
+        for (int f = 0; f < D + 2; ++f) F[f] = T(0);
+        return;
+    }
+    if (!lts && (lcov || rcov)) {
+        int px = ox + lx, py = oy + ly, pz = oz + lz, s = +1;
+        if (lcov) {
+            s = -1;
+            px += dn == 0 ? 1 : 0;
+            py += dn == 1 ? 1 : 0;
+            pz += dn == 2 ? 1 : 0;
         }
+        fine_mean<T, D>(v, G, src, px, py, D == 3 ? pz : 0, s, dn, g, gi, F);
+        return;
+    }
+    T wa[D + 2], wb[D + 2], wc[D + 2], wd[D + 2];
 #pragma unroll
-        for (int f = 0; f < D + 2; ++f) sF[f][fi] = F[f];
+    for (int f = 0; f < D + 2; ++f) {
+        wa[f] = sW[f][hl - SD];
+        wb[f] = sW[f][hl];
+        wc[f] = sW[f][hr];
+        wd[f] = sW[f][hr + SD];
+    }
+    face_flux4<T, D>(g, gi, dn, wa, wb, wc, wd, F);
+    if (record) {
+        // registers are indexed by the cell on the low side of the face
+        int qx = ox + lx, qy = oy + ly, qz = oz + lz;
+        if (dn == 0) qx = bcmap(qx, G.n, v.bc);
+        else if (dn == 1) qy = bcmap(qy, G.n, v.bc);
+        else qz = bcmap(qz, G.n, v.bc);
+        const int64_t iq = gidx(G.n, qx, qy, D == 3 ? qz : 0);
+        const bool lact = sAct[hl] != 0, ract = sAct[hr] != 0;
+        const bool lleaf = lact && !lcov, rleaf = ract && !rcov;
+        T *reg = (T *)v.reg;
+        if (G.rcoff >= 0 && ((lleaf && rcov) || (rleaf && lcov)))
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) reg[G.rcoff + ((int64_t)dn * (D + 2) + f) * G.ncell + iq] = F[f];
+        if (G.rfoff >= 0 && lact != ract)
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f)
+                reg[G.rfoff + (((int64_t)sub * D + dn) * (D + 2) + f) * G.ncell + iq] = F[f];
     }
 }
 
-// Residual of the thread's cells, accumulated axis by axis in the order
-// ((dF_1 + dF_2) + dF_3), dF = F_{+1/2} - F_{-1/2}.
-template <typename T, int D, int DN>
-__device__ __forceinline__ void fv_collect(const T (*sF)[FV<D>::NF], T (*R)[D + 2], bool first)
+// Residual of the thread's cells along axis dn, accumulated axis by axis in
+// the order ((dF_1 + dF_2) + dF_3), dF = F_{+1/2} - F_{-1/2}.
+template <typename T, int D, int NT>
+__device__ __forceinline__ void fv_collect(const T (*sF)[FV<D, NT>::NF], T (*R)[D + 2], int dn)
 {
-    using C = FV<D>;
+    using C = FV<D, NT>;
     constexpr int B = C::B;
 #pragma unroll
     for (int k = 0; k < C::CPT; ++k) {
         const int c = threadIdx.x + k * C::NT;
+        if (c >= C::TC) break;
         const int x = c % B, y = (c / B) % B, z = c / (B * B);
-        int a, r;
-        if (DN == 0) { a = x; r = y + B * z; }
-        else if (DN == 1) { a = y; r = x + B * z; }
-        else { a = z; r = x + B * y; }
+        const int a = dn == 0 ? x : dn == 1 ? y : z;
+        const int r = dn == 0 ? y + B * z : dn == 1 ? x + B * z : x + B * y;
         const int lo = a + (B + 1) * r, hi = lo + 1;
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) {
             const T d = sF[f][hi] - sF[f][lo];
-            R[k][f] = first ? d : R[k][f] + d;
+            R[k][f] = dn == 0 ? d : R[k][f] + d;
         }
     }
 }
@@ -360,15 +376,19 @@ __device__ __forceinline__ void fv_collect(const T (*sF)[FV<D>::NF], T (*R)[D + 
 // the fine-flux mean.  Local time stepping (lvl >= 0): every cell in a patch
 // of level lvl with the level's own fluxes; with record set, fluxes across
 // refinement boundaries go to the flux registers (substep sub).
-template <typename T, int D>
-__global__ void __launch_bounds__(FV<D>::NT)
+// Schedules (bit-identical results): MERGED = false computes the faces axis
+// by axis (one LDS flux array reused per axis); MERGED = true computes the
+// faces of all axes in one pass over all threads (one array per axis).
+template <typename T, int D, int NT, bool MERGED>
+__global__ void __launch_bounds__(NT)
 k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac, int lvl, int sub,
            int record)
 {
-    using C = FV<D>;
+    using C = FV<D, NT>;
     constexpr int E = C::E, H = C::H, B = C::B, NV = C::NV;
+    constexpr int NA = MERGED ? D : 1;   // flux arrays held at once
     __shared__ T sW[NV][C::NE];
-    __shared__ T sF[NV][C::NF];
+    __shared__ T sF[NA][NV][C::NF];
     __shared__ uint8_t sCov[C::NE];
     __shared__ uint8_t sAct[C::NE];
     if (v.meta->done) return;
@@ -386,7 +406,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
         const int oz = D == 3 ? (tl.block / (nb * nb)) * B : 0;
         const T *S = src + G.off;
         const int64_t N = G.ncell;
-        for (int c = threadIdx.x; c < C::NE; c += C::NT) {
+        for (int c = threadIdx.x; c < C::NE; c += NT) {
             const int lx = c % E, ly = (c / E) % E, lz = D == 3 ? c / (E * E) : 0;
             const int x = bcmap(ox + lx - H, n, v.bc);
             const int y = bcmap(oy + ly - H, n, v.bc);
@@ -403,24 +423,37 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
         }
         __syncthreads();
         T R[C::CPT][NV];
-        fv_faces<T, D, 0>(v, G, src, ox, oy, oz, sW, sCov, sAct, sF, g, gi, lts, record, sub);
-        __syncthreads();
-        fv_collect<T, D, 0>(sF, R, true);
-        __syncthreads();
-        fv_faces<T, D, 1>(v, G, src, ox, oy, oz, sW, sCov, sAct, sF, g, gi, lts, record, sub);
-        __syncthreads();
-        fv_collect<T, D, 1>(sF, R, false);
-        __syncthreads();
-        if constexpr (D == 3) {
-            fv_faces<T, D, 2>(v, G, src, ox, oy, oz, sW, sCov, sAct, sF, g, gi, lts, record, sub);
+        if constexpr (MERGED) {
+            for (int j = threadIdx.x; j < D * C::NF; j += NT) {
+                const int dn = j / C::NF, fi = j - dn * C::NF;
+                T F[NV];
+                fv_face<T, D, NT>(v, G, src, ox, oy, oz, sW, sCov, sAct, g, gi, lts, record, sub, dn, fi, F);
+#pragma unroll
+                for (int f = 0; f < NV; ++f) sF[dn][f][fi] = F[f];
+            }
             __syncthreads();
-            fv_collect<T, D, 2>(sF, R, false);
+#pragma unroll
+            for (int dn = 0; dn < D; ++dn) fv_collect<T, D, NT>(sF[dn], R, dn);
+        } else {
+#pragma unroll
+            for (int dn = 0; dn < D; ++dn) {
+                for (int fi = threadIdx.x; fi < C::NF; fi += NT) {
+                    T F[NV];
+                    fv_face<T, D, NT>(v, G, src, ox, oy, oz, sW, sCov, sAct, g, gi, lts, record, sub, dn, fi, F);
+#pragma unroll
+                    for (int f = 0; f < NV; ++f) sF[0][f][fi] = F[f];
+                }
+                __syncthreads();
+                fv_collect<T, D, NT>(sF[0], R, dn);
+                __syncthreads();
+            }
         }
         const double dt = v.dt[(v.mode == MODE_BATCH || lts) ? tl.grid : 0];
         const T lam = (T)((dt * fac) / G.dx);
 #pragma unroll
         for (int k = 0; k < C::CPT; ++k) {
-            const int c = threadIdx.x + k * C::NT;
+            const int c = threadIdx.x + k * NT;
+            if (c >= C::TC) break;
             const int x = c % B, y = (c / B) % B, z = c / (B * B);
             const int h = (x + H) + E * ((y + H) + (D == 3 ? E * (z + H) : 0));
             if (!lts && sCov[h]) continue;

@@ -22,13 +22,16 @@ struct InitArgs {
 // Which state array a launcher works on.
 enum { ARR_Q = 0, ARR_QS = 1, ARR_QO = 2 };
 
+constexpr int FV_VARIANTS = 4;   // schedules of the stage kernel (autotuned)
+
 struct KSet {
     size_t elem;  // bytes per state value
     void (*init)(const View &, const InitArgs &, int grid, int64_t ncell, hipStream_t);
     void (*restrict_full)(const View &, int arr, int grid_coarse, int64_t ncell, hipStream_t);
     void (*restrict_cov)(const View &, int arr, int lvl, int maxblocks, hipStream_t);
     void (*predict)(const View &, int arr, int lvl, int mode, double theta, int maxblocks, hipStream_t);
-    void (*fv_stage)(const View &, int stage, int lvl, int sub, int record, int maxtiles, hipStream_t);
+    void (*fv_stage)(const View &, int stage, int lvl, int sub, int record, int maxtiles, int variant,
+                     hipStream_t);
     void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*cfl)(const View &, int maxtiles, hipStream_t);

@@ -46,14 +46,40 @@ template <typename T> void predict(const View &v, int a, int lvl, int mode, doub
     else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta);
 }
 
-template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, int record, int maxt, hipStream_t s)
+// Stage-kernel schedules the autotuner chooses from (variant index):
+//   2D: 0 = 64 threads, per-axis faces; 1 = 64 threads, merged faces;
+//       2 = 128 threads, per-axis;      3 = 128 threads, merged.
+//   3D: 0 = 256 threads, per-axis;      1 = 256 threads, merged;
+//       2 = 512 threads, per-axis;      3 = 512 threads, merged.
+template <typename T, int D, int NT, bool M>
+void fv_launch(const View &v, int nblk, const T *src, T *out, double fac, int lvl, int sub, int record,
+               hipStream_t s)
+{
+    k_fv_stage<T, D, NT, M><<<nblk, NT, 0, s>>>(v, src, (const T *)v.Q, out, fac, lvl, sub, record);
+}
+
+template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, int record, int maxt,
+                                    int variant, hipStream_t s)
 {
     const int nblk = clamp_grid(maxt, 16384);
     const T *src = (const T *)(stage == 1 ? v.Q : v.Qs);
     T *out = (T *)(stage == 1 ? v.Qs : v.Q);
     const double fac = stage == 1 ? 0.5 : 1.0;
-    if (v.dim == 2) k_fv_stage<T, 2><<<nblk, FV<2>::NT, 0, s>>>(v, src, (const T *)v.Q, out, fac, lvl, sub, record);
-    else k_fv_stage<T, 3><<<nblk, FV<3>::NT, 0, s>>>(v, src, (const T *)v.Q, out, fac, lvl, sub, record);
+    if (v.dim == 2) {
+        switch (variant) {
+        case 1: fv_launch<T, 2, 64, true>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 2: fv_launch<T, 2, 128, false>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 3: fv_launch<T, 2, 128, true>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        default: fv_launch<T, 2, 64, false>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        }
+    } else {
+        switch (variant) {
+        case 1: fv_launch<T, 3, 256, true>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 2: fv_launch<T, 3, 512, false>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 3: fv_launch<T, 3, 512, true>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        default: fv_launch<T, 3, 256, false>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        }
+    }
 }
 
 template <typename T> void copy_level(const View &v, int lvl, int maxb, hipStream_t s)
