@@ -38,6 +38,31 @@ __device__ __forceinline__ int64_t gidx(int n, int x, int y, int z)
     return x + (int64_t)n * (y + (int64_t)n * z);
 }
 
+// XCD-aware assignment of list items to workgroups.  Workgroups are
+// dispatched to the 8 XCDs round robin (blockIdx % 8), each XCD with its own
+// L2; XCD x walks the contiguous x-th eighth of the list, its workgroups
+// taking consecutive items, so tiles processed together on one XCD are
+// neighbours and share their halo cells in that L2.  The grid is a multiple
+// of 8 (launchers round it up) or 1..7 workgroups (one region).
+struct XcdWalk {
+    int nx, per, x, R, j;
+    __device__ XcdWalk(int count)
+    {
+        nx = (gridDim.x % 8 == 0) ? 8 : 1;
+        per = gridDim.x / nx;
+        x = blockIdx.x % nx;
+        j = blockIdx.x / nx;
+        R = (count + nx - 1) / nx;
+    }
+    __device__ bool next(int count, int &t)
+    {
+        if (j >= R) return false;
+        t = x * R + j;
+        j += per;
+        return t < count;
+    }
+};
+
 // ----------------------------------------------------------------------------
 // physics (Sec. 2): conserved <-> primitive, van Albada slope, AUSM+
 // ----------------------------------------------------------------------------
@@ -397,7 +422,9 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     const bool lts = lvl >= 0;
     const Tile *list = lts ? v.actv + v.meta->act_off[lvl] : v.leaf;
     const int count = lts ? v.meta->act_cnt[lvl] : v.meta->nleaf;
-    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    XcdWalk walk(count);
+    int t;
+    while (walk.next(count, t)) {
         const Tile tl = list[t];
         const Grid G = v.grids[tl.grid];
         const int n = G.n, nb = G.nb;

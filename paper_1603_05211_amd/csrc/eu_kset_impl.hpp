@@ -13,6 +13,13 @@ inline int clamp_grid(int64_t want, int cap)
     return want > cap ? cap : (int)want;
 }
 
+// grid for XCD-aware walks: a multiple of 8 once there are 8 items or more
+inline int xcd_grid(int64_t want, int cap)
+{
+    int g = clamp_grid(want, cap);
+    return g < 8 ? g : (g + 7) / 8 * 8;
+}
+
 template <typename T> T *arr(const View &v, int a)
 {
     return (T *)(a == ARR_Q ? v.Q : a == ARR_QS ? v.Qs : v.Qo);
@@ -61,7 +68,7 @@ void fv_launch(const View &v, int nblk, const T *src, T *out, double fac, int lv
 template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, int record, int maxt,
                                     int variant, hipStream_t s)
 {
-    const int nblk = clamp_grid(maxt, 16384);
+    const int nblk = xcd_grid(maxt, 16384);
     const T *src = (const T *)(stage == 1 ? v.Q : v.Qs);
     T *out = (T *)(stage == 1 ? v.Qs : v.Q);
     const double fac = stage == 1 ? 0.5 : 1.0;
