@@ -88,7 +88,7 @@ struct Layout {
     std::vector<int64_t> pbase;
     // scratch offsets
     size_t o_grids, o_act, o_nact, o_code, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
-        o_pcnt, o_fcnt, o_cpart, o_pbase, o_actv, o_reg, o_patches, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
+        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_pbase, o_actv, o_reg, o_patches, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
     size_t scratch = 0, state = 0;
 };
 
@@ -217,6 +217,7 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_fcnt = take(sizeof(int) * lay.nslot);
     lay.ncls = (int)std::min<int64_t>(std::max<int64_t>((lay.nbt + 255) / 256, 1), 256);
     lay.o_cpart = take(sizeof(long long) * eu::NPART * eu::MAXLEV * lay.ncls);
+    lay.o_wcnt = take(sizeof(int) * 5 * lay.ncls);
     lay.o_pbase = take(sizeof(int64_t) * (eu::MAXLEV + 1));
     lay.o_patches = take(sizeof(int) * 5 * lay.max_patch);
     lay.o_meta = take(sizeof(Meta));
@@ -548,6 +549,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.fcnt = at<int>(scratch_dev, lay.o_fcnt);
     v.cpart = at<long long>(scratch_dev, lay.o_cpart);
     v.ncls = lay.ncls;
+    v.wcnt = at<int>(scratch_dev, lay.o_wcnt);
     v.pbase = at<int64_t>(scratch_dev, lay.o_pbase);
     v.patches = at<int>(scratch_dev, lay.o_patches);
     v.meta = at<Meta>(scratch_dev, lay.o_meta);

@@ -81,6 +81,7 @@ struct View {
                                       // leaf cells, patch cells, covered, new, leaf, ghost and
                                       // patch blocks
     int ncls;                         // workgroups of the classification kernel
+    int *wcnt;                        // per classification workgroup: entries of each list
     int64_t *pbase;                   // per-level offset into pslot / pcnt
     int *patches;                     // compacted patch table (5 ints per row)
     Meta *meta;

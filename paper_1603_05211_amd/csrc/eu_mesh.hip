@@ -1,7 +1,7 @@
 // eu_mesh.hip -- precision-independent kernels: refinement flags with buffer
 // and nesting closure fused with the patch tiling (efficiency rule), work-list
-// construction (parallel classification + one-workgroup compaction), fills,
-// totals.  Built with -ffp-contract=off.
+// construction (classification and compaction over contiguous block ranges),
+// fills, totals.  Built with -ffp-contract=off.
 #include "eu_kernels.hpp"
 
 namespace eu {
@@ -87,8 +87,9 @@ __device__ __forceinline__ bool refine_flag(const View &v, const Grid &G, int lv
 // flags of level lvl + tiling into patches of level lvl+1: one workgroup per
 // aligned pmax block of level lvl+1 (Morton index = blockIdx.x).  The
 // workgroup flags the block's coarse footprint, counts flags per BS-block in
-// LDS, and lane 0 takes the recursive split decisions in the order of a
-// depth-first recursion over children (x fastest).
+// LDS, sums them over the nodes of the split tree, and every lane decides for
+// one BS-block which node of the recursive split (Sec. 2.3) holds it; patches
+// come out in the order of a depth-first recursion over children (x fastest).
 // ----------------------------------------------------------------------------
 template <int D>
 __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
@@ -131,63 +132,86 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
     }
     for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = mine;
+    // flagged-parent counts of every node of the split tree: level k holds
+    // the nodes of 2^k BS-blocks per side, (R >> k)^D of them
+    __shared__ int ncnt[MAXSUB + MAXSUB / 4 + 16];
+    __shared__ int lvo[5];
+    __shared__ int wlead[8];
+    int K = 0;
+    while ((1 << K) < R) ++K;
+    if (threadIdx.x == 0) {
+        int o = 0;
+        for (int k = 0; k <= K; ++k) {
+            lvo[k] = o;
+            const int r = R >> k;
+            o += D == 2 ? r * r : r * r * r;
+        }
+    }
     __syncthreads();
+    for (int s = threadIdx.x; s < nsub; s += blockDim.x) ncnt[s] = cnt8[s];
+    for (int k = 1; k <= K; ++k) {
+        __syncthreads();
+        const int r = R >> k, rc = R >> (k - 1);
+        const int nn = D == 2 ? r * r : r * r * r;
+        for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+            const int ix = i % r, iy = (i / r) % r, iz = D == 3 ? i / (r * r) : 0;
+            int c = 0;
+            for (int ch = 0; ch < (1 << D); ++ch)
+                c += ncnt[lvo[k - 1] + (2 * ix + (ch & 1)) + rc * ((2 * iy + ((ch >> 1) & 1)) + rc * (2 * iz + ((ch >> 2) & 1)))];
+            ncnt[lvo[k] + i] = c;
+        }
+    }
+    __syncthreads();
+    // Each sub-block, taken in Morton order (the order in which a depth-first
+    // recursion over children, x fastest, meets it), walks from the root to
+    // the node that is emitted as a patch (or is empty).  The node's first
+    // sub-block writes the patch; patches are ranked by that Morton order.
+    const int64_t slot = v.pbase[lvl + 1] + m;
+    int *out = v.pslot + slot * (int64_t)nsub * 5;
+    int nlead_total = 0;
+    for (int c0 = 0; c0 < nsub; c0 += blockDim.x) {
+        const int mc = c0 + threadIdx.x;   // Morton code of this lane's sub-block
+        int sx = 0, sy = 0, sz = 0;
+        for (int b = 0; b < K; ++b) {
+            sx |= ((mc >> (b * D)) & 1) << b;
+            sy |= ((mc >> (b * D + 1)) & 1) << b;
+            if (D == 3) sz |= ((mc >> (b * D + 2)) & 1) << b;
+        }
+        int emit_k = -1;
+        if (mc < nsub) {
+            for (int k = K; k >= 0; --k) {
+                const int r = R >> k;
+                const int c = ncnt[lvo[k] + (sx >> k) + r * ((sy >> k) + r * (sz >> k))];
+                if (c == 0) break;
+                const int S = BS << k, hsz = S / 2;
+                const long long cells = D == 2 ? (long long)hsz * hsz : (long long)hsz * hsz * hsz;
+                if (S == v.pmin || (double)c >= v.eta * (double)cells) { emit_k = k; break; }
+            }
+        }
+        const int em = (1 << (emit_k < 0 ? 0 : emit_k)) - 1;
+        const bool lead = emit_k >= 0 && (sx & em) == 0 && (sy & em) == 0 && (sz & em) == 0;
+        if (mc < nsub) emit8[sx + R * (sy + R * sz)] = emit_k >= 0 ? 1 : 0;
+        const unsigned long long mask = __ballot(lead);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane == 0) wlead[wave] = __popcll(mask);
+        __syncthreads();
+        int pos = nlead_total + __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
+        for (int w = 0; w < wave; ++w) pos += wlead[w];
+        if (lead) {
+            out[5 * pos + 0] = lvl + 1;
+            out[5 * pos + 1] = bp[0] * v.pmax + sx * BS;
+            out[5 * pos + 2] = bp[1] * v.pmax + sy * BS;
+            out[5 * pos + 3] = D == 3 ? bp[2] * v.pmax + sz * BS : 0;
+            out[5 * pos + 4] = BS << emit_k;
+        }
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) nlead_total += wlead[w];
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         int tot = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
-        const int64_t slot = v.pbase[lvl + 1] + m;
         v.fcnt[slot] = tot;
-        int *out = v.pslot + slot * (int64_t)nsub * 5;
-        int np = 0;
-        // flagged parents inside the block of es^D BS-blocks at (ex, ey, ez)
-        auto count = [&](int ex, int ey, int ez, int es) {
-            int c = 0;
-            const int ezs = D == 3 ? es : 1;
-            for (int zz = 0; zz < ezs; ++zz)
-                for (int yy = 0; yy < es; ++yy)
-                    for (int xx = 0; xx < es; ++xx) c += cnt8[(ex + xx) + R * ((ey + yy) + R * (ez + zz))];
-            return c;
-        };
-        // 0: empty, 1: emitted as a patch, 2: to be split
-        auto decide = [&](int ex, int ey, int ez, int es) {
-            const int c = count(ex, ey, ez, es);
-            if (c == 0) return 0;
-            const int S = es * BS, hsz = S / 2;
-            const long long cells = D == 2 ? (long long)hsz * hsz : (long long)hsz * hsz * hsz;
-            if (S == v.pmin || (double)c >= v.eta * (double)cells) {
-                out[5 * np + 0] = lvl + 1;
-                out[5 * np + 1] = bp[0] * v.pmax + ex * BS;
-                out[5 * np + 2] = bp[1] * v.pmax + ey * BS;
-                out[5 * np + 3] = D == 3 ? bp[2] * v.pmax + ez * BS : 0;
-                out[5 * np + 4] = S;
-                ++np;
-                const int ezs = D == 3 ? es : 1;
-                for (int zz = 0; zz < ezs; ++zz)
-                    for (int yy = 0; yy < es; ++yy)
-                        for (int xx = 0; xx < es; ++xx) emit8[(ex + xx) + R * ((ey + yy) + R * (ez + zz))] = 1;
-                return 1;
-            }
-            return 2;
-        };
-        constexpr int NC = 1 << D;
-        // depth-first over the split levels (R <= 8: at most four levels),
-        // children in x-fastest order
-        if (decide(0, 0, 0, R) == 2) {
-            const int h1 = R / 2;
-            for (int k1 = 0; k1 < NC; ++k1) {
-                const int x1 = h1 * (k1 & 1), y1 = h1 * ((k1 >> 1) & 1), z1 = h1 * ((k1 >> 2) & 1);
-                if (decide(x1, y1, z1, h1) != 2) continue;
-                const int h2 = h1 / 2;
-                for (int k2 = 0; k2 < NC; ++k2) {
-                    const int x2 = x1 + h2 * (k2 & 1), y2 = y1 + h2 * ((k2 >> 1) & 1), z2 = z1 + h2 * ((k2 >> 2) & 1);
-                    if (decide(x2, y2, z2, h2) != 2) continue;
-                    const int h3 = h2 / 2;
-                    for (int k3 = 0; k3 < NC; ++k3)
-                        decide(x2 + h3 * (k3 & 1), y2 + h3 * ((k3 >> 1) & 1), z2 + h3 * ((k3 >> 2) & 1), h3);
-                }
-            }
-        }
-        v.pcnt[slot] = np;
+        v.pcnt[slot] = nlead_total;
     }
     __syncthreads();
     for (int s = threadIdx.x; s < nsub; s += blockDim.x) {
@@ -214,10 +238,15 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
     if (v.meta->done) return;
     if (threadIdx.x < MAXLEV * NPART) part[threadIdx.x / NPART][threadIdx.x % NPART] = 0ull;
     __syncthreads();
+    __shared__ int lcnt[5];
+    if (threadIdx.x < 5) lcnt[threadIdx.x] = 0;
+    __syncthreads();
     constexpr int cpb = D == 2 ? BS * BS : BS * BS * BS;
     constexpr int cpc = cpb >> D;   // cells of a coarse block covered by one child block
-    for (int64_t gb = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; gb < nbt;
-         gb += (int64_t)gridDim.x * blockDim.x) {
+    // workgroup w classifies the contiguous range [w chunk, (w+1) chunk)
+    const int64_t chunk = (nbt + gridDim.x - 1) / gridDim.x;
+    const int64_t g0 = blockIdx.x * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
+    for (int64_t gb = g0 + threadIdx.x; gb < g1; gb += blockDim.x) {
         int lvl = 0;
         while (lvl + 1 < v.L && gb >= v.grids[lvl + 1].boff) ++lvl;
         const Grid &G = v.grids[lvl];
@@ -269,45 +298,142 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
         if (code & 2) atomicAdd(&part[lvl][2], 1ull);
         if (code & 4) atomicAdd(&part[lvl][5], 1ull);
         if (code & 8) atomicAdd(&part[lvl][3], 1ull);
+        // entries of this range in the leaf, covered, ghost, new, patch lists
+        if (code & 1) atomicAdd(&lcnt[0], 1);
+        if (code & 2) atomicAdd(&lcnt[1], 1);
+        if (code & 4) atomicAdd(&lcnt[2], 1);
+        if (code & 8) atomicAdd(&lcnt[3], 1);
+        if (code & 3) atomicAdd(&lcnt[4], 1);
     }
     __syncthreads();
+    if (threadIdx.x < 5) v.wcnt[(int64_t)blockIdx.x * 5 + threadIdx.x] = lcnt[threadIdx.x];
     if (threadIdx.x < MAXLEV * NPART)
         v.cpart[(int64_t)blockIdx.x * MAXLEV * NPART + threadIdx.x] =
             (long long)part[threadIdx.x / NPART][threadIdx.x % NPART];
 }
 
-constexpr int LT = 1024;
-constexpr int NW = LT / 64;
-
-// One workgroup: compaction of the classified blocks into the leaf, covered,
-// ghost and new-block lists (order: level, then block index, x fastest),
-// per-level counts, and the patch table (levels in order, pmax blocks in
-// Morton order, each block's patches in split order).
+// Compaction of the classified blocks into the leaf, covered, ghost, new and
+// all-patch lists (order: level, then block index, x fastest), with the same
+// contiguous ranges as the classification: workgroup w sums the list counts
+// of the ranges before its own and writes its entries from there.  The patch
+// table (levels in order, pmax blocks in Morton order, each block's patches
+// in split order) is compacted the same way over pmax-block slots.
+// Workgroup 0 also writes the per-level counts and list ranges.
 template <int D>
-__global__ void __launch_bounds__(LT) k_compact(View v, int64_t nbt, int64_t nslot, int nsub)
+__global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt, int64_t nslot, int nsub)
 {
-    constexpr int PER = 4;                 // blocks per thread per chunk
     constexpr int NL = 5;                  // leaf, covered, ghost, new, patch blocks
-    __shared__ int wcnt[NL][NW];
     __shared__ int base[NL];
+    __shared__ int wsum[4][NL];
     __shared__ int64_t lstart[MAXLEV + 1];
+    __shared__ int pbase_s;
     if (v.meta->done) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < NL) base[tid] = 0;
+    const int W = gridDim.x, w = blockIdx.x;
     if (tid <= MAXLEV) lstart[tid] = tid < v.L ? v.grids[tid].boff : nbt;
-    // per-level totals of the classification partials and of the flagged
-    // cells (integer sums: the result does not depend on the order)
+    // offsets of this range: sums of the counts of the ranges before it
+    {
+        int acc[NL] = {0, 0, 0, 0, 0};
+        for (int i = tid; i < w; i += blockDim.x)
+            for (int k = 0; k < NL; ++k) acc[k] += v.wcnt[(int64_t)i * 5 + k];
+        for (int k = 0; k < NL; ++k)
+            for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+        if (lane == 0)
+            for (int k = 0; k < NL; ++k) wsum[wave][k] = acc[k];
+    }
+    __syncthreads();
+    if (tid < NL) {
+        int s = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wsum[i][tid];
+        base[tid] = s;
+    }
+    __syncthreads();
+    Tile *lists[NL] = {v.leaf, v.cov, v.ghost, v.fresh, v.actv};
+    const int64_t chunk = (nbt + W - 1) / W;
+    const int64_t g0 = w * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
+    for (int64_t c = g0; c < g1; c += blockDim.x) {
+        const int64_t gb = c + tid;
+        int code = 0, lvl = 0;
+        if (gb < g1) {
+            code = v.code[gb] & 15;
+            if (code & 3) code |= 16;  // bit 4: in a patch
+            while (gb >= lstart[lvl + 1]) ++lvl;
+        }
+        int pre[NL];
+        __shared__ int wc[4][NL];
+        for (int k = 0; k < NL; ++k) {
+            const unsigned long long mask = __ballot((code >> k) & 1);
+            pre[k] = __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
+            if (lane == 0) wc[wave][k] = __popcll(mask);
+        }
+        __syncthreads();
+        for (int k = 0; k < NL; ++k)
+            if ((code >> k) & 1) {
+                int off = base[k] + pre[k];
+                for (int i = 0; i < wave; ++i) off += wc[i][k];
+                lists[k][off] = Tile{lvl, (int)(gb - lstart[lvl])};
+            }
+        __syncthreads();
+        if (tid < NL) {
+            int s = 0;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wc[i][tid];
+            base[tid] += s;
+        }
+        __syncthreads();
+    }
+    // patch table: slots [s0, s1) of this workgroup
+    const int64_t schunk = (nslot + W - 1) / W;
+    const int64_t s0 = w * schunk, s1 = s0 + schunk < nslot ? s0 + schunk : nslot;
+    {
+        int acc = 0;
+        for (int64_t i = tid; i < s0; i += blockDim.x) acc += v.pcnt[i];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) wsum[wave][0] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            int s = 0;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wsum[i][0];
+            pbase_s = s;
+        }
+        __syncthreads();
+    }
+    for (int64_t c = s0; c < s1; c += blockDim.x) {
+        const int64_t s = c + tid;
+        const int k = s < s1 ? v.pcnt[s] : 0;
+        int incl = k;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int r = __shfl_up(incl, o);
+            if (lane >= o) incl += r;
+        }
+        __shared__ int wt[4];
+        if (lane == 63) wt[wave] = incl;
+        __syncthreads();
+        int off = pbase_s + incl - k;
+        for (int i = 0; i < wave; ++i) off += wt[i];
+        for (int j = 0; j < k; ++j)
+            if (off + j < v.max_patch)
+                for (int e = 0; e < 5; ++e) v.patches[5 * (int64_t)(off + j) + e] = v.pslot[(s * nsub + j) * 5 + e];
+        __syncthreads();
+        if (tid == 0) {
+            int t = 0;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += wt[i];
+            pbase_s += t;
+        }
+        __syncthreads();
+    }
+    if (w != W - 1) return;
+    // the last workgroup knows the totals; it also writes the per-level counts
     __shared__ unsigned long long lsum[MAXLEV][NPART];
     __shared__ int nfl[MAXLEV];
     if (tid < MAXLEV * NPART) lsum[tid / NPART][tid % NPART] = 0ull;
     if (tid < MAXLEV) nfl[tid] = 0;
     __syncthreads();
-    for (int i = tid; i < v.ncls * v.L * NPART; i += LT) {
-        const int w = i / (v.L * NPART), r = i % (v.L * NPART);
-        const long long p = v.cpart[((int64_t)w * MAXLEV + r / NPART) * NPART + r % NPART];
+    for (int i = tid; i < v.ncls * v.L * NPART; i += blockDim.x) {
+        const int ww = i / (v.L * NPART), r = i % (v.L * NPART);
+        const long long p = v.cpart[((int64_t)ww * MAXLEV + r / NPART) * NPART + r % NPART];
         if (p) atomicAdd(&lsum[r / NPART][r % NPART], (unsigned long long)p);
     }
-    for (int64_t s = tid; s < nslot; s += LT) {
+    for (int64_t s = tid; s < nslot; s += blockDim.x) {
         const int f = v.fcnt[s];
         if (f) {
             int l = 1;
@@ -316,108 +442,25 @@ __global__ void __launch_bounds__(LT) k_compact(View v, int64_t nbt, int64_t nsl
         }
     }
     __syncthreads();
-    if (tid < MAXLEV) {
-        const bool in = tid < v.L;
-        v.meta->leaf_cells[tid] = in ? (long long)lsum[tid][0] : 0;
-        v.meta->act_cells[tid] = in ? (long long)lsum[tid][1] : 0;
-        v.meta->cov_cnt[tid] = in ? (int)lsum[tid][2] : 0;
-        v.meta->new_cnt[tid] = in ? (int)lsum[tid][3] : 0;
-        v.meta->leaf_cnt[tid] = in ? (int)lsum[tid][4] : 0;
-        v.meta->ghost_cnt[tid] = in ? (int)lsum[tid][5] : 0;
-        v.meta->act_cnt[tid] = in ? (int)lsum[tid][6] : 0;
-        v.meta->nflag[tid] = in ? nfl[tid] : 0;
-    }
-    __syncthreads();
-    Tile *lists[NL] = {v.leaf, v.cov, v.ghost, v.fresh, v.actv};
-    for (int64_t c0 = 0; c0 < nbt; c0 += (int64_t)LT * PER) {
-        const int64_t g0 = c0 + (int64_t)tid * PER;
-        int codes[PER], lv[PER];
-        int cnt[NL] = {0, 0, 0, 0, 0};
-        for (int j = 0; j < PER; ++j) {
-            const int64_t gb = g0 + j;
-            codes[j] = 0;
-            lv[j] = 0;
-            if (gb < nbt) {
-                int code = v.code[gb] & 15;
-                if (code & 3) code |= 16;  // bit 4: in a patch
-                int lvl = 0;
-                while (gb >= lstart[lvl + 1]) ++lvl;
-                codes[j] = code;
-                lv[j] = lvl;
-                for (int k = 0; k < NL; ++k) cnt[k] += (code >> k) & 1;
-            }
-        }
-    // exclusive scan of the per-thread counts (wave scan + wave totals)
-        int excl[NL];
-        for (int k = 0; k < NL; ++k) {
-            int incl = cnt[k];
-            for (int o = 1; o < 64; o <<= 1) {
-                const int r = __shfl_up(incl, o);
-                if (lane >= o) incl += r;
-            }
-            excl[k] = incl - cnt[k];
-            if (lane == 63) wcnt[k][wave] = incl;
-        }
-        __syncthreads();
-        for (int k = 0; k < NL; ++k) {
-            int off = base[k] + excl[k];
-            for (int w = 0; w < wave; ++w) off += wcnt[k][w];
-            for (int j = 0; j < PER; ++j)
-                if ((codes[j] >> k) & 1) {
-                    const int64_t gb = g0 + j;
-                    lists[k][off++] = Tile{lv[j], (int)(gb - lstart[lv[j]])};
-                }
-        }
-        __syncthreads();
-        if (tid < NL) {
-            int s = 0;
-            for (int w = 0; w < NW; ++w) s += wcnt[tid][w];
-            base[tid] += s;
-        }
-        __syncthreads();
-    }
     if (tid == 0) {
         v.meta->nleaf = base[0];
         v.meta->nghost = base[2];
-        int co = 0, no = 0, lo = 0, go = 0, ao = 0;
+        v.meta->npatch = pbase_s;
+        int o[5] = {0, 0, 0, 0, 0};
         for (int l = 0; l < MAXLEV; ++l) {
-            v.meta->cov_off[l] = co; co += v.meta->cov_cnt[l];
-            v.meta->new_off[l] = no; no += v.meta->new_cnt[l];
-            v.meta->leaf_off[l] = lo; lo += v.meta->leaf_cnt[l];
-            v.meta->ghost_off[l] = go; go += v.meta->ghost_cnt[l];
-            v.meta->act_off[l] = ao; ao += v.meta->act_cnt[l];
+            const bool in = l < v.L;
+            v.meta->leaf_cells[l] = in ? (long long)lsum[l][0] : 0;
+            v.meta->act_cells[l] = in ? (long long)lsum[l][1] : 0;
+            v.meta->nflag[l] = in ? nfl[l] : 0;
+            const int cnts[5] = {in ? (int)lsum[l][2] : 0, in ? (int)lsum[l][3] : 0, in ? (int)lsum[l][4] : 0,
+                                 in ? (int)lsum[l][5] : 0, in ? (int)lsum[l][6] : 0};
+            v.meta->cov_off[l] = o[0]; v.meta->cov_cnt[l] = cnts[0]; o[0] += cnts[0];
+            v.meta->new_off[l] = o[1]; v.meta->new_cnt[l] = cnts[1]; o[1] += cnts[1];
+            v.meta->leaf_off[l] = o[2]; v.meta->leaf_cnt[l] = cnts[2]; o[2] += cnts[2];
+            v.meta->ghost_off[l] = o[3]; v.meta->ghost_cnt[l] = cnts[3]; o[3] += cnts[3];
+            v.meta->act_off[l] = o[4]; v.meta->act_cnt[l] = cnts[4]; o[4] += cnts[4];
         }
     }
-    // patch table
-    __syncthreads();
-    if (tid == 0) base[0] = 0;
-    __syncthreads();
-    for (int64_t c0 = 0; c0 < nslot; c0 += LT) {
-        const int64_t s = c0 + tid;
-        const int k = s < nslot ? v.pcnt[s] : 0;
-        int incl = k;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int r = __shfl_up(incl, o);
-            if (lane >= o) incl += r;
-        }
-        if (lane == 63) wcnt[0][wave] = incl;
-        __syncthreads();
-        int off = base[0] + incl - k;
-        for (int w = 0; w < wave; ++w) off += wcnt[0][w];
-        for (int j = 0; j < k; ++j) {
-            if (off + j < v.max_patch)
-                for (int e = 0; e < 5; ++e)
-                    v.patches[5 * (int64_t)(off + j) + e] = v.pslot[(s * nsub + j) * 5 + e];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int t = 0;
-            for (int w = 0; w < NW; ++w) t += wcnt[0][w];
-            base[0] += t;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) v.meta->npatch = base[0];
 }
 
 __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t val)
@@ -462,10 +505,10 @@ void launch_build_lists(const View &v, int64_t nbt, hipStream_t s)
     const int nsub = v.dim == 2 ? R * R : R * R * R;
     if (v.dim == 2) {
         k_classify<2><<<v.ncls, 256, 0, s>>>(v, nbt);
-        k_compact<2><<<1, LT, 0, s>>>(v, nbt, v.nslot, nsub);
+        k_compact<2><<<v.ncls, 256, 0, s>>>(v, nbt, v.nslot, nsub);
     } else {
         k_classify<3><<<v.ncls, 256, 0, s>>>(v, nbt);
-        k_compact<3><<<1, LT, 0, s>>>(v, nbt, v.nslot, nsub);
+        k_compact<3><<<v.ncls, 256, 0, s>>>(v, nbt, v.nslot, nsub);
     }
 }
 
