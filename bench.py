@@ -98,20 +98,23 @@ def timed_advance(s, steps, use_graph=True):
     return done, u1 - u0, t1 - t0
 
 
-def kernel_profile(s, steps):
-    """Average duration of the finite-volume stage kernel, from HIP events the
-    library records around each of its launches on the context's stream, and
-    the cells advanced per launch (leaf updates of the profiled steps times
-    the two stages, over the launches)."""
-    u0, st0 = s.leaf_updates()
-    s.profile(True)
-    s.advance(steps, use_graph=False)
-    ms, n = s.kernel_time()
-    s.profile(False)
-    u1, st1 = s.leaf_updates()
-    launches_per_step = n / max(st1 - st0, 1)
-    cells_per_launch = 2 * (u1 - u0) / max(n, 1)
-    return ms / max(n, 1), n, cells_per_launch, launches_per_step
+def kernel_profile(s, steps, reps=5):
+    """Average duration of the finite-volume stage kernel: after each of the
+    next `steps` time steps, `reps` back-to-back first-stage passes on that
+    state between two HIP events on the library's stream (the state is left
+    unchanged).  Returns ms per launch, launches timed, cells per launch and
+    launches per pass."""
+    ms_sum, cells_sum, launches = 0.0, 0, 0
+    lpp = 1
+    for _ in range(steps):
+        if s.advance(1, use_graph=True) != 1:
+            break
+        ms, cells, lpp = s.stage_time(reps)
+        ms_sum += ms * reps
+        cells_sum += cells * reps
+        launches += lpp * reps
+    n = max(launches, 1)
+    return ms_sum / n, launches, cells_sum / n, lpp
 
 
 def source_hash():
@@ -122,9 +125,12 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload, precision):
-    """HBM bytes per stage launch from the committed counter summary of this
-    workload, when it was taken on the current kernel sources (else None)."""
+def traffic_from_profile(workload, precision, cells_per_launch):
+    """HBM bytes per stage launch: the committed counter summary of this
+    workload (FETCH_SIZE and WRITE_SIZE per launch, scaled by the readings of
+    a plain 256 MiB device copy) gives bytes per cell advanced, which is
+    scaled to this run's cells per launch.  None when the summary is missing
+    or the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"k_fv_stage_{workload}_{precision}_traffic.json")
     try:
         with open(path) as f:
@@ -133,7 +139,7 @@ def traffic_from_profile(workload, precision):
         return None, "no counter summary"
     if d.get("source_hash") != source_hash():
         return None, "kernel changed since the counters were taken"
-    return d.get("traffic_bytes_per_launch"), os.path.relpath(path, ROOT)
+    return d["traffic_bytes_per_cell"] * cells_per_launch, os.path.relpath(path, ROOT)
 
 
 def cpu_baseline(workload, budget_s=15.0, seed=0):
@@ -224,6 +230,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the context configurations")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=40)
+    ap.add_argument("--schedule", type=int, default=-1, choices=[-1, 0, 1, 2, 3],
+                    help="force a stage-kernel schedule instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -243,8 +251,13 @@ def main():
         del a, c
 
     s, dim = make_solver(args.workload, args.precision)
-    variant, variant_ms = s.autotune(reps=10 if dim == 2 else 3)
-    log(f"autotuned stage schedule {variant} ({variant_ms})")
+    if args.schedule >= 0:
+        s.set_variant(args.schedule)
+        variant, variant_ms = args.schedule, None
+        log(f"stage schedule {variant} (forced)")
+    else:
+        variant, variant_ms = s.autotune(reps=10 if dim == 2 else 3)
+        log(f"autotuned stage schedule {variant} ({variant_ms})")
     log(f"warmup {args.warmup} steps")
     s.advance(args.warmup, use_graph=True)
     log(f"timing {args.steps} steps")
@@ -252,15 +265,15 @@ def main():
     if done != args.steps:
         log(f"warning: only {done} of {args.steps} steps before t_end")
     value = upd / wall
-    log(f"profiling {args.profile_steps} steps with events")
-    fv_ms, nlaunch, cells_per_launch, launches_per_step = kernel_profile(s, args.profile_steps)
+    log(f"timing the stage kernel with events over the next {args.profile_steps} steps")
+    fv_ms, nlaunch, cells_per_launch, launches_per_pass = kernel_profile(s, args.profile_steps)
     s.close()
     flops = FLOPS_PER_CELL_STAGE[dim] * cells_per_launch
     achieved = flops / (fv_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     es = 4 if args.precision == "fp32" else 8
     nv = dim + 2
-    traffic, traffic_src = traffic_from_profile(args.workload, args.precision)
+    traffic, traffic_src = traffic_from_profile(args.workload, args.precision, cells_per_launch)
 
     result = {
         "metric": "cell-updates/s (FP32 batched vs FP64 plain) at stated L1 err; % HBM roofline",
@@ -286,7 +299,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "traffic_source": traffic_src,
                      "avg_launch_ms": fv_ms, "launches": nlaunch,
-                     "launches_per_step": launches_per_step,
+                     "launches_per_pass": launches_per_pass,
                      "cells_per_launch": cells_per_launch,
                      "flops_per_cell": FLOPS_PER_CELL_STAGE[dim],
                      "hbm_whole_job_GBs": value * 2 * nv * es / 1e9,

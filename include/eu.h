@@ -213,13 +213,25 @@ int eu_profile(eu_ctx *ctx, int enable);
 int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
 
 /* Schedule of the finite-volume stage kernel (threads per tile, faces axis by
- * axis or in one pass).  Every schedule gives bit-identical results.
+ * axis or in one pass).  In FP64 every schedule gives bit-identical results;
+ * in FP32 they agree to rounding (the compiler contracts each differently).
  * eu_autotune times each schedule (reps launches of the first stage on the
  * current state, HIP events on the context's stream; the state is left
  * unchanged) and keeps the fastest: *variant_host receives it, ms_host
  * (nullable, 4 entries) the mean time of each.  eu_set_variant forces one
  * (0..3).  Both drop captured graphs. */
 int eu_autotune(eu_ctx *ctx, int reps, int *variant_host, float *ms_host);
+
+/* Duration of the finite-volume stage kernel on the current state, with the
+ * current schedule: one untimed pass of the first stage (Sec. 2.2, the
+ * midpoint rule's predictor), then reps passes back to back between two HIP
+ * events on the context's stream; the state is left unchanged.  A pass is one
+ * launch (global time step, batch) or one launch per level (local time
+ * stepping).  *ms_host: mean milliseconds per pass; *cells_host: cells one
+ * pass advances (leaves; patch cells of every level with local time stepping;
+ * every cell of a uniform grid or batch); *launches_host: launches per pass.
+ * Outputs are nullable.  EU_ESTATE before initialisation or after t_end. */
+int eu_stage_time(eu_ctx *ctx, int reps, float *ms_host, int64_t *cells_host, int *launches_host);
 int eu_set_variant(eu_ctx *ctx, int variant);
 
 /* Non-physical status: EU_OK or EU_ENONPHYS (synchronises). */

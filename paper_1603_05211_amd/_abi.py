@@ -67,6 +67,7 @@ SIGNATURES = {
     "eu_profile": (C.c_int, [_vp, C.c_int]),
     "eu_kernel_time": (C.c_int, [_vp, _dp, _i64p]),
     "eu_autotune": (C.c_int, [_vp, C.c_int, _ip, C.POINTER(C.c_float)]),
+    "eu_stage_time": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_float), _i64p, _ip]),
     "eu_set_variant": (C.c_int, [_vp, C.c_int]),
     "eu_status": (C.c_int, [_vp]),
     "eu_clear_status": (C.c_int, [_vp]),

@@ -382,6 +382,53 @@ void drop_graphs(eu_ctx *c)
         if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
+// Launches of the first stage over the current state (one per level for
+// local time stepping): it reads Q and writes the stage array, which every
+// step recomputes, so repeating it leaves the state untouched.
+void stage1_pass(eu_ctx *c, int var)
+{
+    if (c->v.lts)
+        for (int l = 0; l < c->L; ++l) c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, c->stream);
+    else
+        c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, var, c->stream);
+}
+
+int stage_ready(eu_ctx *c)
+{
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Meta m;
+    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
+    if (m.done) return set_err(c, EU_ESTATE, "the run has reached t_end");
+    return EU_OK;
+}
+
+// Mean time of one first-stage pass of schedule var: one untimed pass, then
+// reps passes back to back between two events on the context's stream.
+int time_stage1(eu_ctx *c, int var, int reps, float *ms_out)
+{
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_err(c, EU_EHIP, "hipEventCreate failed");
+    }
+    stage1_pass(c, var);
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps; ++r) stage1_pass(c, var);
+    (void)hipEventRecord(e1, c->stream);
+    hipError_t err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return set_err(c, EU_EHIP, "stage timing failed: %s", hipGetErrorString(err));
+    int r = check_launch(c);
+    if (r) return r;
+    *ms_out = ms / (float)reps;
+    return EU_OK;
+}
+
 int harvest_profile(eu_ctx *c)
 {
     for (auto &p : c->ev_pending) {
@@ -906,48 +953,44 @@ int eu_set_variant(eu_ctx *c, int variant)
 int eu_autotune(eu_ctx *c, int reps, int *variant_host, float *ms_host)
 {
     if (!c || reps < 1) return EU_EINVAL;
-    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    Meta m;
-    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
-    if (m.done) return set_err(c, EU_ESTATE, "the run has reached t_end");
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
-    // first stage only: it reads Q and writes the stage array, which every
-    // step recomputes, so timing it leaves the state untouched
-    auto stage1 = [&](int var) {
-        if (c->v.lts)
-            for (int l = 0; l < c->L; ++l) c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, c->stream);
-        else
-            c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, var, c->stream);
-    };
+    int r = stage_ready(c);
+    if (r) return r;
     int best = 0;
     float best_ms = 0.f;
     for (int var = 0; var < FV_VARIANTS; ++var) {
-        stage1(var);
-        (void)hipEventRecord(e0, c->stream);
-        for (int r = 0; r < reps; ++r) stage1(var);
-        (void)hipEventRecord(e1, c->stream);
-        hipError_t err = hipEventSynchronize(e1);
         float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err != hipSuccess) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return set_err(c, EU_EHIP, "autotune timing failed: %s", hipGetErrorString(err));
-        }
-        ms /= (float)reps;
+        r = time_stage1(c, var, reps, &ms);
+        if (r) return r;
         if (ms_host) ms_host[var] = ms;
         if (var == 0 || ms < best_ms) { best = var; best_ms = ms; }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    int r = check_launch(c);
-    if (r) return r;
     c->variant = best;
     drop_graphs(c);
     if (variant_host) *variant_host = best;
+    return EU_OK;
+}
+
+int eu_stage_time(eu_ctx *c, int reps, float *ms_host, int64_t *cells_host, int *launches_host)
+{
+    if (!c || reps < 1) return EU_EINVAL;
+    int r = stage_ready(c);
+    if (r) return r;
+    float ms = 0.f;
+    r = time_stage1(c, c->variant, reps, &ms);
+    if (r) return r;
+    Meta m;
+    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
+    int64_t cells = 0;
+    for (int l = 0; l < c->L; ++l) {
+        if (c->mode != MODE_HIER) {
+            for (int g = 0; g < c->ngrid; ++g) cells += c->grids[g].ncell;
+            break;
+        }
+        cells += c->v.lts ? m.act_cells[l] : m.leaf_cells[l];
+    }
+    if (ms_host) *ms_host = ms;
+    if (cells_host) *cells_host = cells;
+    if (launches_host) *launches_host = c->v.lts ? c->L : 1;
     return EU_OK;
 }
 

@@ -1,5 +1,6 @@
-"""Every stage-kernel schedule gives bit-identical results, and the autotuner
-leaves the state untouched while choosing one."""
+"""Every stage-kernel schedule gives bit-identical FP64 results (FP32 ones
+agree to rounding), and the autotuner and the stage timer leave the state
+untouched."""
 import numpy as np
 import pytest
 
@@ -54,7 +55,30 @@ def test_autotune_leaves_state_and_picks_a_schedule():
     t = Solver(2, n0=32, levels=4, precision=EU_FP32, cfl=0.45, t_end=0.25)
     t.init_quadrant(inputs.quadrant_states(0))
     t.advance(3)
+    t.set_variant(var)
     s.advance(5)
     t.advance(5)
     for l in range(4):
         assert np.array_equal(s.level(l), t.level(l))
+
+
+@pytest.mark.parametrize("lts", [False, True])
+def test_stage_time_leaves_state_and_counts_cells(lts):
+    """The event-timed stage passes change nothing, and the cells they report
+    are the leaves (global step) or the patch cells (local time stepping)."""
+    if lts:
+        s = Solver(3, n0=16, levels=3, precision=EU_FP32, cfl=0.4, lo=-1.0, hi=1.0, time_mode=EU_DT_LTS)
+        e = inputs.ellipsoid(0)
+        s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
+    else:
+        s = Solver(2, n0=32, levels=4, precision=EU_FP32, cfl=0.45, t_end=0.25)
+        s.init_quadrant(inputs.quadrant_states(0))
+    s.advance(2)
+    before = [s.level(l) for l in range(s.levels)]
+    ms, cells, nl = s.stage_time(reps=4)
+    say("  stage_time", ms, cells, nl)
+    assert ms > 0 and nl == (s.levels if lts else 1)
+    leaves, active = s.counters()
+    assert cells == int((active if lts else leaves).sum())
+    for l in range(s.levels):
+        assert np.array_equal(s.level(l), before[l])
