@@ -253,8 +253,18 @@ int64_t nblocks_grid(const eu_ctx *c, int g) { return ipow(c->grids[g].nb, c->di
 
 // ---- launch sequences ------------------------------------------------------
 
+// Projection of every covered cell, finest level first: in 2D two levels
+// per launch, in 3D one.
 void seq_restrict(eu_ctx *c, int arr)
 {
+    if (c->dim == 2) {
+        for (int l = c->L - 2; l >= 0; l -= 2) {
+            const int lo = l >= 1 ? l - 1 : l, nlev = l - lo + 1;
+            c->ks->restrict2(c->v, arr, lo, nlev,
+                             (int)(nblocks_grid(c, lo) + (nlev == 2 ? nblocks_grid(c, l) : 0)), c->stream);
+        }
+        return;
+    }
     for (int l = c->L - 2; l >= 0; --l)
         c->ks->restrict_cov(c->v, arr, l, (int)nblocks_grid(c, l), c->stream);
 }
@@ -306,8 +316,9 @@ void seq_details(eu_ctx *c)
     c->ks->details(c->v, n, c->stream);
 }
 
-// flags, closure and tiling (finest first), lists, then optional prediction
-// of new cells (coarse to fine) and ghost fill.
+// flags, closure and tiling (finest first), lists, then either the
+// prediction of new cells and ghost cells level by level (coarse to fine, one
+// launch per level) or the ghost fill alone.
 void seq_flag_tile(eu_ctx *c, bool prolong)
 {
     for (int l = c->L - 2; l >= 0; --l) {
@@ -316,8 +327,9 @@ void seq_flag_tile(eu_ctx *c, bool prolong)
     }
     launch_build_lists(c->v, c->nbt, c->stream);
     if (prolong)
-        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 0, 0.0, (int)nblocks_grid(c, l), c->stream);
-    seq_ghost(c, ARR_Q);
+        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 3, 0.0, (int)nblocks_grid(c, l), c->stream);
+    else
+        seq_ghost(c, ARR_Q);
 }
 
 // Local time stepping: advance level l by one of its steps (substep k of

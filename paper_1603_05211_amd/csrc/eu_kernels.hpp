@@ -63,6 +63,53 @@ struct XcdWalk {
     }
 };
 
+// issued(a, b, ...): the values are needed at this point.  The compiler
+// would otherwise sink a load whose result is only used under a later
+// branch into that branch, after the loads that decide it, and pay two
+// round trips to memory instead of one.  (An empty statement with the values
+// as inputs; it emits no instruction.)
+__device__ __forceinline__ void issued() {}
+template <typename A, typename... R>
+__device__ __forceinline__ void issued(A a, R... r)
+{
+    asm volatile("" ::"v"(a));
+    issued(r...);
+}
+
+// Grid table of a hierarchy in LDS.  Kernels look grids up by the level of a
+// tile they have just loaded; reading the table (at most MAXLEV grids, grid
+// index = level) into LDS at kernel start, together with the first reads of
+// the device counters, keeps those lookups off the chain of dependent global
+// loads.  A workgroup barrier must separate grid_tab_load and grid_tab.
+struct GridTab {
+    static constexpr int W = (int)(sizeof(Grid) / 4);
+    int w[MAXLEV][W];
+};
+__device__ __forceinline__ void grid_tab_load(const View &v, GridTab &s)
+{
+    const int n = (v.ngrid < MAXLEV ? v.ngrid : MAXLEV) * GridTab::W;
+    const int *src = reinterpret_cast<const int *>(v.grids);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s.w[i / GridTab::W][i % GridTab::W] = src[i];
+}
+// Grid i (workgroup-uniform) from the table, in scalar registers.
+__device__ __forceinline__ Grid grid_tab(const GridTab &s, int i)
+{
+    int w[GridTab::W];
+#pragma unroll
+    for (int k = 0; k < GridTab::W; ++k) w[k] = __builtin_amdgcn_readfirstlane(s.w[i][k]);
+    Grid G;
+    __builtin_memcpy(&G, w, sizeof(Grid));
+    return G;
+}
+
+// Grid i (may differ between lanes) from the table.
+__device__ __forceinline__ Grid grid_tab_lane(const GridTab &s, int i)
+{
+    Grid G;
+    __builtin_memcpy(&G, s.w[i], sizeof(Grid));
+    return G;
+}
+
 // ----------------------------------------------------------------------------
 // physics (Sec. 2): conserved <-> primitive, van Albada slope, AUSM+
 // ----------------------------------------------------------------------------
@@ -172,14 +219,13 @@ __device__ __forceinline__ void face_flux4(T g, T gi, int dn, const T *wa, const
 }
 
 // Mean of the 2^(D-1) fine fluxes on the face between coarse cell p (global
-// coordinates on grid G) and its covered neighbour on side s of axis dn,
-// computed from the next finer grid of the stencil source (virtual leaves,
-// Sec. 2.1).  Transverse offsets: first along the lower transverse axis.
+// coordinates on its grid) and its covered neighbour on side s of axis dn,
+// computed from the next finer grid gf of the stencil source (virtual
+// leaves, Sec. 2.1).  Transverse offsets: first along the lower transverse axis.
 template <typename T, int D>
-__device__ void fine_mean(const View &v, const Grid &G, const T *src, int px, int py, int pz, int s,
+__device__ void fine_mean(const View &v, const Grid &gf, const T *src, int px, int py, int pz, int s,
                           int dn, T g, T gi, T *F)
 {
-    const Grid gf = v.grids[G.fine];
     const T *S = src + gf.off;
     const int nf = gf.n;
     const int64_t Nf = gf.ncell;
@@ -279,12 +325,10 @@ __device__ __forceinline__ bool block_active(const View &v, const uint8_t *mask,
     return mask[G.boff + (x >> 3) + (int64_t)G.nb * ((y >> 3) + (int64_t)G.nb * (z >> 3))] != 0;
 }
 
-// covered: the children of cell (x, y, z) belong to a patch of the finer grid.
-__device__ __forceinline__ bool covered(const View &v, const uint8_t *mask, const Grid &G, int x,
-                                        int y, int z)
+// covered: the children of cell (x, y, z) belong to a patch of the finer
+// grid F (the caller checks that the cell's grid has one).
+__device__ __forceinline__ bool covered(const uint8_t *mask, const Grid &F, int x, int y, int z)
 {
-    if (G.fine < 0) return false;
-    const Grid &F = v.grids[G.fine];
     return mask[F.boff + (x >> 2) + (int64_t)F.nb * ((y >> 2) + (int64_t)F.nb * (z >> 2))] != 0;
 }
 
@@ -306,7 +350,7 @@ template <int D, int NT_> struct FV {
 // Flux of face fi of axis dn of the tile (fi = a + (B+1) r: a-th face along
 // the axis, r-th line across it), written to F.
 template <typename T, int D, int NT>
-__device__ __forceinline__ void fv_face(const View &v, const Grid &G, const T *src, int ox, int oy, int oz,
+__device__ __forceinline__ void fv_face(const View &v, const Grid &G, const Grid &GF, const T *src, int ox, int oy, int oz,
                                         const T (*sW)[FV<D, NT>::NE], const uint8_t *sCov,
                                         const uint8_t *sAct, T g, T gi, bool lts, bool record, int sub,
                                         int dn, int fi, T *F)
@@ -340,7 +384,7 @@ __device__ __forceinline__ void fv_face(const View &v, const Grid &G, const T *s
             py += dn == 1 ? 1 : 0;
             pz += dn == 2 ? 1 : 0;
         }
-        fine_mean<T, D>(v, G, src, px, py, D == 3 ? pz : 0, s, dn, g, gi, F);
+        fine_mean<T, D>(v, GF, src, px, py, D == 3 ? pz : 0, s, dn, g, gi, F);
         return;
     }
     T wa[D + 2], wb[D + 2], wc[D + 2], wd[D + 2];
@@ -416,17 +460,27 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     __shared__ T sF[NA][NV][C::NF];
     __shared__ uint8_t sCov[C::NE];
     __shared__ uint8_t sAct[C::NE];
-    if (v.meta->done) return;
-    const T g = (T)v.gamma;
-    const T gi = (T)(1.0 / (v.gamma - 1.0));
+    __shared__ GridTab tab;
+    // first reads, independent of each other: counters, grid table, dt
     const bool lts = lvl >= 0;
+    const bool hier = v.mode == MODE_HIER;
+    const int done = v.meta->done;
     const Tile *list = lts ? v.actv + v.meta->act_off[lvl] : v.leaf;
     const int count = lts ? v.meta->act_cnt[lvl] : v.meta->nleaf;
+    const double dt0 = v.dt[lts ? lvl : 0];
+    if (hier) grid_tab_load(v, tab);
+    issued(list, count, dt0);
+    if (done) return;
+    __syncthreads();
+    const T g = (T)v.gamma;
+    const T gi = (T)(1.0 / (v.gamma - 1.0));
     XcdWalk walk(count);
     int t;
     while (walk.next(count, t)) {
         const Tile tl = list[t];
-        const Grid G = v.grids[tl.grid];
+        const Grid G = hier ? grid_tab(tab, tl.grid) : v.grids[tl.grid];
+        const bool hasf = G.fine >= 0;
+        const Grid GF = hasf ? grid_tab(tab, G.fine) : G;
         const int n = G.n, nb = G.nb;
         const int ox = (tl.block % nb) * B;
         const int oy = ((tl.block / nb) % nb) * B;
@@ -442,11 +496,24 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             T q[NV], w[NV];
 #pragma unroll
             for (int f = 0; f < NV; ++f) q[f] = S[f * N + id];
+            const bool cv = hasf && covered(v.act, GF, x, y, z);
+            const bool ac = record && block_active(v, v.act, G, x, y, z);
             cons2prim<T, D>(q, w, g);
 #pragma unroll
             for (int f = 0; f < NV; ++f) sW[f][c] = w[f];
-            sCov[c] = covered(v, v.act, G, x, y, z) ? 1 : 0;
-            if (record) sAct[c] = block_active(v, v.act, G, x, y, z) ? 1 : 0;
+            sCov[c] = cv ? 1 : 0;
+            if (record) sAct[c] = ac ? 1 : 0;
+        }
+        // base state of the thread's cells, read while the fluxes are computed
+        T qb[C::CPT][NV];
+#pragma unroll
+        for (int k = 0; k < C::CPT; ++k) {
+            const int c = threadIdx.x + k * NT;
+            if (c >= C::TC) break;
+            const int x = c % B, y = (c / B) % B, z = c / (B * B);
+            const int64_t id = G.off + gidx(n, ox + x, oy + y, oz + z);
+#pragma unroll
+            for (int f = 0; f < NV; ++f) qb[k][f] = base[f * N + id];
         }
         __syncthreads();
         T R[C::CPT][NV];
@@ -454,7 +521,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             for (int j = threadIdx.x; j < D * C::NF; j += NT) {
                 const int dn = j / C::NF, fi = j - dn * C::NF;
                 T F[NV];
-                fv_face<T, D, NT>(v, G, src, ox, oy, oz, sW, sCov, sAct, g, gi, lts, record, sub, dn, fi, F);
+                fv_face<T, D, NT>(v, G, GF, src, ox, oy, oz, sW, sCov, sAct, g, gi, lts, record, sub, dn, fi, F);
 #pragma unroll
                 for (int f = 0; f < NV; ++f) sF[dn][f][fi] = F[f];
             }
@@ -466,7 +533,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             for (int dn = 0; dn < D; ++dn) {
                 for (int fi = threadIdx.x; fi < C::NF; fi += NT) {
                     T F[NV];
-                    fv_face<T, D, NT>(v, G, src, ox, oy, oz, sW, sCov, sAct, g, gi, lts, record, sub, dn, fi, F);
+                    fv_face<T, D, NT>(v, G, GF, src, ox, oy, oz, sW, sCov, sAct, g, gi, lts, record, sub, dn, fi, F);
 #pragma unroll
                     for (int f = 0; f < NV; ++f) sF[0][f][fi] = F[f];
                 }
@@ -475,7 +542,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
                 __syncthreads();
             }
         }
-        const double dt = v.dt[(v.mode == MODE_BATCH || lts) ? tl.grid : 0];
+        const double dt = v.mode == MODE_BATCH ? v.dt[tl.grid] : dt0;
         const T lam = (T)((dt * fac) / G.dx);
 #pragma unroll
         for (int k = 0; k < C::CPT; ++k) {
@@ -486,7 +553,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             if (!lts && sCov[h]) continue;
             const int64_t id = G.off + gidx(n, ox + x, oy + y, oz + z);
 #pragma unroll
-            for (int f = 0; f < NV; ++f) out[f * N + id] = base[f * N + id] - lam * R[k][f];
+            for (int f = 0; f < NV; ++f) out[f * N + id] = qb[k][f] - lam * R[k][f];
         }
         __syncthreads();
     }
@@ -502,59 +569,52 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
 // step is committed: t += dt, steps += 1, leaf updates counted.
 __device__ void cfl_finalize(const View &v)
 {
-    if (v.lts) {
-        // level-0 step dt_0 = min over levels (cfl dx_l / smax_l) 2^l; dt_l = dt_0 / 2^l
-        if (threadIdx.x != 0) return;
-        double dt = __builtin_inf();
-        for (int g = 0; g < v.ngrid; ++g) {
-            const unsigned long long b = atomicExch(&v.smax[g], 0ull);
-            if (b) {
-                const double s = __longlong_as_double((long long)b);
-                const double d = ((v.cfl * v.grids[g].dx) / s) * (double)(1 << g);
-                if (d < dt) dt = d;
-            }
-        }
-        const double t = v.t[0];
-        const int done = t < v.t_end ? 0 : 1;
-        if (dt > v.t_end - t) dt = v.t_end - t;
-        double dl = dt;
-        for (int g = 0; g < v.ngrid; ++g) {
-            v.dt[g] = dl;
-            dl = dl * 0.5;
-        }
-        v.meta->done = done;
-        if (!done) {
-            v.t[0] = t + dt;
-            v.meta->steps += 1;
-            long long s = 0;
-            for (int l = 0; l < v.L; ++l) s += v.meta->leaf_cells[l] << l;
-            v.meta->leaf_updates += s;
-        }
-        v.meta->ticket = 0u;
-        return;
-    }
     if (v.mode == MODE_HIER) {
-        if (threadIdx.x != 0) return;
-        double dt = __builtin_inf();
-        for (int g = 0; g < v.ngrid; ++g) {
-            const unsigned long long b = atomicExch(&v.smax[g], 0ull);
-            if (b) {
-                const double s = __longlong_as_double((long long)b);
-                const double dtl = (v.cfl * v.grids[g].dx) / s;
-                if (dtl < dt) dt = dtl;
-            }
+        // dt = min over levels of cfl dx_l / smax_l; with local time stepping
+        // the level-0 step dt_0 = min over levels (cfl dx_l / smax_l) 2^l and
+        // dt_l = dt_0 / 2^l.  One thread per level, then thread 0 commits.
+        __shared__ double sdt[MAXLEV];
+        const int g = threadIdx.x;
+        double t = 0.0;
+        long long upd = 0;
+        if (g == 0) {
+            t = v.t[0];
+            for (int l = 0; l < v.L; ++l) upd += v.meta->leaf_cells[l] << (v.lts ? l : 0);
         }
-        const double t = v.t[0];
+        if (g < MAXLEV) {
+            double d = __builtin_inf();
+            if (g < v.ngrid) {
+                const double dx = v.grids[g].dx;
+                const unsigned long long b = atomicExch(&v.smax[g], 0ull);
+                if (b) {
+                    const double sm = __longlong_as_double((long long)b);
+                    d = (v.cfl * dx) / sm;
+                    if (v.lts) d = d * (double)(1 << g);
+                }
+            }
+            sdt[g] = d;
+        }
+        __syncthreads();
+        if (g != 0) return;
+        double dt = __builtin_inf();
+        for (int l = 0; l < v.ngrid; ++l)
+            if (sdt[l] < dt) dt = sdt[l];
         const int done = t < v.t_end ? 0 : 1;
         if (dt > v.t_end - t) dt = v.t_end - t;
-        v.dt[0] = dt;
+        if (v.lts) {
+            double dl = dt;
+            for (int l = 0; l < v.ngrid; ++l) {
+                v.dt[l] = dl;
+                dl = dl * 0.5;
+            }
+        } else {
+            v.dt[0] = dt;
+        }
         v.meta->done = done;
         if (!done) {
             v.t[0] = t + dt;
             v.meta->steps += 1;
-            long long s = 0;
-            for (int l = 0; l < v.L; ++l) s += v.meta->leaf_cells[l];
-            v.meta->leaf_updates += s;
+            v.meta->leaf_updates += upd;
         }
         v.meta->ticket = 0u;
         return;
@@ -584,16 +644,21 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
 #pragma clang fp contract(off)
     __shared__ double lmax[4][MAXLEV];
     __shared__ int last;
+    __shared__ GridTab tab;
+    const bool hier = v.mode == MODE_HIER;
     const int count = v.meta->nleaf;
+    if (hier) grid_tab_load(v, tab);
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     const double g = v.gamma;
-    const bool hier = v.mode == MODE_HIER;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane < MAXLEV) lmax[wave][lane] = 0.0;
+    __syncthreads();
     bool bad = false;
     for (int t = blockIdx.x * 4 + wave; t < count; t += gridDim.x * 4) {
         const Tile tl = v.leaf[t];
-        const Grid G = v.grids[tl.grid];
+        const Grid G = hier ? grid_tab(tab, tl.grid) : v.grids[tl.grid];
+        const bool hasf = G.fine >= 0;
+        const Grid GF = hasf ? grid_tab(tab, G.fine) : G;
         const int n = G.n, nb = G.nb;
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
@@ -601,18 +666,21 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
         double m = 0.0;
         for (int c = lane; c < TC; c += 64) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
-            if (covered(v, v.act, G, x, y, z)) continue;
             const int64_t id = G.off + gidx(n, x, y, z);
+            // the state is read whether or not the cell is covered (a
+            // covered cell holds its children's mean); it only counts for
+            // leaves
             double q[D + 2], w[D + 2];
 #pragma unroll
             for (int f = 0; f < D + 2; ++f) q[f] = (double)Q[f * G.ncell + id];
+            const bool leaf = !(hasf && covered(v.act, GF, x, y, z));
             cons2prim<double, D>(q, w, g);
-            if (!(w[0] > 0.0) || !(w[D + 1] > 0.0)) bad = true;
+            if (leaf && (!(w[0] > 0.0) || !(w[D + 1] > 0.0))) bad = true;
             const double cs = __builtin_sqrt((g * w[D + 1]) / w[0]);
             double S = 0.0;
 #pragma unroll
             for (int d = 0; d < D; ++d) S = S + (__builtin_fabs(w[1 + d]) + cs);
-            if (S > m) m = S;
+            if (leaf && S > m) m = S;
         }
         for (int o = 32; o > 0; o >>= 1) {
             const double r = __shfl_xor(m, o);
@@ -629,6 +697,8 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
     if (__any(bad) && lane == 0) atomicOr(&v.meta->status, 1);
     __syncthreads();
     if (threadIdx.x == 0) {
+        // one thread folds the waves' maxima and publishes them: a single
+        // device-scope fence per workgroup (each one writes back this XCD's L2)
         if (hier)
             for (int l = 0; l < v.ngrid; ++l) {
                 double mm = lmax[0][l];
@@ -659,6 +729,8 @@ __global__ void __launch_bounds__(256) k_totals(View v, const T *__restrict__ Q)
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const Tile tl = v.leaf[t];
         const Grid G = v.grids[tl.grid];
+        const bool hasf = G.fine >= 0;
+        const Grid GF = hasf ? v.grids[G.fine] : G;
         const int n = G.n, nb = G.nb;
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
@@ -669,7 +741,7 @@ __global__ void __launch_bounds__(256) k_totals(View v, const T *__restrict__ Q)
         for (int f = 0; f < D + 2; ++f) acc[f] = 0.0;
         for (int c = threadIdx.x; c < TC; c += blockDim.x) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
-            if (covered(v, v.act, G, x, y, z)) continue;
+            if (hasf && covered(v.act, GF, x, y, z)) continue;
             const int64_t id = G.off + gidx(n, x, y, z);
 #pragma unroll
             for (int f = 0; f < D + 2; ++f) acc[f] = acc[f] + (double)Q[f * G.ncell + id] * vol;
@@ -763,35 +835,116 @@ __global__ void __launch_bounds__(256) k_restrict_full(View v, T *A, int gc)
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_restrict_cov(View v, T *A, int lvl)
 {
-    if (v.meta->done) return;
+    // first reads, independent of each other (grid index = level)
+    const int done = v.meta->done;
     const int off = v.meta->cov_off[lvl], count = v.meta->cov_cnt[lvl];
+    const Grid G = v.grids[lvl];
+    const Grid F = v.grids[lvl + 1];
+    issued(off, count, G.n, G.off, G.ncell, F.n, F.off, F.ncell, F.boff, F.nb);
+    if (done) return;
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
+    const int nb = G.nb;
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const Tile tl = v.cov[off + t];
-        const Grid G = v.grids[tl.grid];
-        const Grid F = v.grids[G.fine];
-        const int nb = G.nb;
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
         const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
         for (int c = threadIdx.x; c < TC; c += blockDim.x) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
-            if (!covered(v, v.act, G, x, y, z)) continue;
+            // children read whether or not the cell is covered (they exist
+            // on the dense finer grid); every load before the first store
+            T val[D + 2];
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) val[f] = restrict_cell<T, D>(A + F.off + f * F.ncell, F.n, x, y, z);
+            const bool cv = covered(v.act, F, x, y, z);
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) issued(val[f]);
+            if (!cv) continue;
             const int64_t id = gidx(G.n, x, y, z);
 #pragma unroll
-            for (int f = 0; f < D + 2; ++f)
-                A[G.off + f * G.ncell + id] = restrict_cell<T, D>(A + F.off + f * F.ncell, F.n, x, y, z);
+            for (int f = 0; f < D + 2; ++f) A[G.off + f * G.ncell + id] = val[f];
+        }
+    }
+}
+
+// Projection of the covered cells of levels lvl .. lvl+nlev-1 (nlev = 1 or
+// 2) in one launch (Sec. 2.1: a covered cell is the mean of its children),
+// 2D.  The covered
+// blocks of the two levels are adjacent in the covered list.  A cell of
+// level lvl+1 is the mean of its four children; a cell of level lvl is the
+// mean of its four children, each of which is either final (a leaf) or
+// itself the mean of its own four children.  The four children of a cell
+// lie in one block of the next level and its sixteen grandchildren in one
+// block of the level after, so one mask read tells whether the children are
+// covered.  Every read is issued before any result is stored, and the
+// arithmetic is that of two successive one-level projections.
+template <typename T>
+__global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev)
+{
+    constexpr int NV = 4;
+    __shared__ GridTab tab;
+    // first reads, independent of each other
+    const int done = v.meta->done;
+    const int off = v.meta->cov_off[lvl];
+    const int count = v.meta->cov_cnt[lvl] + (nlev == 2 ? v.meta->cov_cnt[lvl + 1] : 0);
+    grid_tab_load(v, tab);
+    issued(off, count);
+    if (done) return;
+    __syncthreads();
+    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+        const Tile tl = v.cov[off + t];
+        const Grid G = grid_tab(tab, tl.grid);
+        const Grid F1 = grid_tab(tab, tl.grid + 1);
+        const bool two = nlev == 2 && tl.grid == lvl;   // through the children's children
+        const Grid F2 = two ? grid_tab(tab, tl.grid + 2) : F1;
+        const int nb = G.nb;
+        const int x = (tl.block % nb) * BS + threadIdx.x % BS;
+        const int y = ((tl.block / nb) % nb) * BS + threadIdx.x / BS;
+        const bool cov = covered(v.act, F1, x, y, 0);
+        // the children's children lie in block (4x/8, 4y/8) of level +2
+        const bool gcov = two && v.act[F2.boff + ((4 * x) >> 3) + (int64_t)F2.nb * ((4 * y) >> 3)] != 0;
+        T ch[NV][4];
+#pragma unroll
+        for (int f = 0; f < NV; ++f)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                ch[f][k] = A[F1.off + f * F1.ncell + gidx(F1.n, 2 * x + (k & 1), 2 * y + (k >> 1), 0)];
+        T gc[NV][4];
+        if (two) {
+#pragma unroll
+            for (int f = 0; f < NV; ++f)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    gc[f][k] = restrict_cell<T, 2>(A + F2.off + f * F2.ncell, F2.n, 2 * x + (k & 1), 2 * y + (k >> 1), 0);
+#pragma unroll
+            for (int f = 0; f < NV; ++f)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) issued(gc[f][k]);
+        }
+#pragma unroll
+        for (int f = 0; f < NV; ++f)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) issued(ch[f][k]);
+        if (!cov) continue;
+        const int64_t id = G.off + gidx(G.n, x, y, 0);
+#pragma unroll
+        for (int f = 0; f < NV; ++f) {
+            T c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = gcov ? gc[f][k] : ch[f][k];
+            A[id + f * G.ncell] = T(0.25) * ((c[0] + c[1]) + (c[2] + c[3]));
         }
     }
 }
 
 // ghost cell: outside every patch of its level, within two cells of a patch
-// (cells c-2 .. c+2 lie in at most three blocks per axis; loads issued first)
+// (cells c-2 .. c+2 lie in at most three blocks per axis; every mask read is
+// issued before any is tested)
 template <int D>
 __device__ __forceinline__ bool is_ghost(const View &v, const Grid &G, int x, int y, int z)
 {
     const int n = G.n;
-    if (block_active(v, v.act, G, x, y, z)) return false;
+    const bool own = block_active(v, v.act, G, x, y, z);
     int b[3][3], nb[3];
     const int c[3] = {x, y, z};
     for (int d = 0; d < 3; ++d) {
@@ -816,7 +969,7 @@ __device__ __forceinline__ bool is_ghost(const View &v, const Grid &G, int x, in
             }
     int hit = 0;
     for (int i = 0; i < 27; ++i) hit |= a[i];
-    return hit != 0;
+    return !own && hit != 0;
 }
 
 // Third-order prediction of child (cx, cy, cz) of coarse cell p from the
@@ -860,41 +1013,63 @@ __device__ __forceinline__ T predict_child_t(const T *Ao, const T *An, T theta, 
 //   mode 0: every cell of the blocks created at level lvl (new list);
 //   mode 1: every ghost cell of every level (ghost list);
 //   mode 2: the ghost cells of level lvl, from the coarse level's state
-//           interpolated in time between Qo (theta = 0) and Q (theta = 1).
+//           interpolated in time between Qo (theta = 0) and Q (theta = 1);
+//   mode 3: mode 0, then the ghost cells of level lvl, in one launch (both
+//           read level lvl-1 only, which is final by then).
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta)
 {
-    if (v.meta->done) return;
-    int off, count;
-    const Tile *list;
-    if (mode == 0) { off = v.meta->new_off[lvl]; count = v.meta->new_cnt[lvl]; list = v.fresh; }
-    else if (mode == 1) { off = 0; count = v.meta->nghost; list = v.ghost; }
-    else { off = v.meta->ghost_off[lvl]; count = v.meta->ghost_cnt[lvl]; list = v.ghost; }
+    __shared__ GridTab tab;
+    // first reads, independent of each other (grid index = level)
+    const int done = v.meta->done;
+    int off0 = 0, cnt0 = 0, off1 = 0, cnt1 = 0;   // ranges in the new and ghost lists
+    if (mode == 0 || mode == 3) { off0 = v.meta->new_off[lvl]; cnt0 = v.meta->new_cnt[lvl]; }
+    if (mode == 1) cnt1 = v.meta->nghost;
+    if (mode >= 2) { off1 = v.meta->ghost_off[lvl]; cnt1 = v.meta->ghost_cnt[lvl]; }
+    const bool all = mode == 1;
+    Grid Gl, Cl;
+    if (all) {
+        grid_tab_load(v, tab);
+    } else {
+        Gl = v.grids[lvl];
+        Cl = v.grids[lvl - 1];
+        issued(Gl.n, Gl.nb, Gl.off, Gl.ncell, Gl.boff, Cl.n, Cl.off, Cl.ncell);
+    }
+    issued(off0, cnt0, off1, cnt1);
+    if (done) return;
+    if (all) __syncthreads();
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
+    constexpr int NV = D + 2;
+    const int count = cnt0 + cnt1;
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
-        const Tile tl = list[off + t];
-        const Grid G = v.grids[tl.grid];
-        const Grid Cg = v.grids[G.coarse];
+        const bool fresh = t < cnt0;
+        const Tile tl = fresh ? v.fresh[off0 + t] : v.ghost[off1 + t - cnt0];
+        const Grid G = all ? grid_tab(tab, tl.grid) : Gl;
+        const Grid Cg = all ? grid_tab(tab, G.coarse) : Cl;
         const int nb = G.nb;
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
         const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
         for (int c = threadIdx.x; c < TC; c += blockDim.x) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
-            if (mode != 0 && !is_ghost<D>(v, G, x, y, z)) continue;
+            // every cell of a new block is predicted; in a ghost block only
+            // the ghost cells (tested first: most cells of a ghost block
+            // are not ghost cells)
+            if (!fresh && !is_ghost<D>(v, G, x, y, z)) continue;
+            T val[NV];
+#pragma unroll
+            for (int f = 0; f < NV; ++f) {
+                if (mode == 2)
+                    val[f] = predict_child_t<T, D>((const T *)v.Qo + Cg.off + f * Cg.ncell,
+                                                   (const T *)v.Q + Cg.off + f * Cg.ncell, (T)theta, Cg.n, v.bc,
+                                                   x >> 1, y >> 1, z >> 1, x & 1, y & 1, z & 1);
+                else
+                    val[f] = predict_child<T, D, T>(A + Cg.off + f * Cg.ncell, Cg.n, v.bc, x >> 1, y >> 1,
+                                                    z >> 1, x & 1, y & 1, z & 1);
+            }
             const int64_t id = gidx(G.n, x, y, z);
 #pragma unroll
-            for (int f = 0; f < D + 2; ++f) {
-                T val;
-                if (mode == 2)
-                    val = predict_child_t<T, D>((const T *)v.Qo + Cg.off + f * Cg.ncell,
-                                                (const T *)v.Q + Cg.off + f * Cg.ncell, (T)theta, Cg.n, v.bc,
-                                                x >> 1, y >> 1, z >> 1, x & 1, y & 1, z & 1);
-                else
-                    val = predict_child<T, D, T>(A + Cg.off + f * Cg.ncell, Cg.n, v.bc, x >> 1, y >> 1,
-                                                 z >> 1, x & 1, y & 1, z & 1);
-                A[G.off + f * G.ncell + id] = val;
-            }
+            for (int f = 0; f < NV; ++f) A[G.off + f * G.ncell + id] = val[f];
         }
     }
 }
@@ -947,7 +1122,7 @@ __global__ void __launch_bounds__(256) k_reflux(View v, int lvl)
         const T lam = (T)(v.dt[lvl] / G.dx);
         for (int c = threadIdx.x; c < TC; c += blockDim.x) {
             const int p[3] = {ox + c % BS, oy + (c / BS) % BS, oz + (D == 3 ? c / (BS * BS) : 0)};
-            if (covered(v, v.act, G, p[0], p[1], p[2])) continue;
+            if (covered(v.act, F, p[0], p[1], p[2])) continue;
             const int64_t ip = gidx(n, p[0], p[1], p[2]);
 #pragma unroll
             for (int d = 0; d < D; ++d) {
@@ -955,7 +1130,7 @@ __global__ void __launch_bounds__(256) k_reflux(View v, int lvl)
                 for (int s = -1; s <= 1; s += 2) {
                     int nbc[3] = {p[0], p[1], p[2]};
                     nbc[d] = bcmap(p[d] + s, n, v.bc);
-                    if (!covered(v, v.act, G, nbc[0], nbc[1], nbc[2])) continue;
+                    if (!covered(v.act, F, nbc[0], nbc[1], nbc[2])) continue;
                     const int64_t ic = s > 0 ? ip : gidx(n, nbc[0], nbc[1], nbc[2]);
                     int fb[3] = {2 * p[0], 2 * p[1], D == 3 ? 2 * p[2] : 0};
                     fb[d] = bcmap(s > 0 ? 2 * p[d] + 1 : 2 * p[d] - 1, nf, v.bc);
@@ -994,18 +1169,24 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q, int64_t ntot)
 {
 #pragma clang fp contract(off)
-    if (v.meta->done) return;
+    __shared__ GridTab tab;
+    const int done = v.meta->done;
+    grid_tab_load(v, tab);
+    if (done) return;
+    __syncthreads();
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ntot;
          j += (int64_t)gridDim.x * blockDim.x) {
         int lvl = 0;
-        while (lvl + 1 < v.L - 1 && j >= v.grids[lvl + 1].coff) ++lvl;
-        const Grid G = v.grids[lvl];
-        const Grid F = v.grids[G.fine];
+        while (lvl + 1 < v.L - 1 && j >= grid_tab_lane(tab, lvl + 1).coff) ++lvl;
+        const Grid G = grid_tab_lane(tab, lvl);
+        const Grid F = grid_tab_lane(tab, lvl + 1);
         const int n = G.n;
         const int64_t i = j - G.coff;
         const int x = (int)(i % n), y = (int)((i / n) % n), z = D == 3 ? (int)(i / ((int64_t)n * n)) : 0;
         double Dm = 0.0;
-        if (block_active(v, v.act, G, x, y, z) && covered(v, v.act, G, x, y, z)) {
+        const bool act = block_active(v, v.act, G, x, y, z);
+        const bool cov = covered(v.act, F, x, y, z);
+        if (act && cov) {
             const T *Ac = Q + G.off;  // density field of the coarse level
             const T *Af = Q + F.off;
             for (int k = 0; k < (1 << D); ++k) {

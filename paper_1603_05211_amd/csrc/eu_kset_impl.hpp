@@ -46,6 +46,13 @@ template <typename T> void restrict_cov(const View &v, int a, int lvl, int maxb,
     else k_restrict_cov<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl);
 }
 
+// two levels per launch (2D only)
+template <typename T> void restrict2(const View &v, int a, int lvl, int nlev, int maxb, hipStream_t s)
+{
+    const int nblk = clamp_grid(maxb, 2048);
+    k_restrict2<T><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, nlev);
+}
+
 template <typename T> void predict(const View &v, int a, int lvl, int mode, double theta, int maxb, hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 1024);
@@ -133,6 +140,7 @@ template <typename T> KSet make()
     k.init = init<T>;
     k.restrict_full = restrict_full<T>;
     k.restrict_cov = restrict_cov<T>;
+    k.restrict2 = restrict2<T>;
     k.predict = predict<T>;
     k.fv_stage = fv_stage<T>;
     k.copy_level = copy_level<T>;

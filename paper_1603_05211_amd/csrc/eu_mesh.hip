@@ -25,14 +25,22 @@ __device__ __forceinline__ int distinct_blocks(int c0, int lo, int hi, int n, in
     return k;
 }
 
+// Grids of the levels around level lvl that the flag of a level-lvl cell
+// reads (grid index = level): lvl-1 (when lvl >= 1), lvl and lvl+2 (when
+// lvl+2 < L).
+struct FlagGrids {
+    Grid C, G, F2;
+};
+
 template <int D>
-__device__ __forceinline__ bool refine_flag(const View &v, const Grid &G, int lvl, int x, int y, int z)
+__device__ __forceinline__ bool refine_flag(const View &v, const FlagGrids &fg, int lvl, int x, int y, int z)
 {
+    const Grid &G = fg.G;
     const int n = G.n;
     constexpr int R3 = D == 3 ? 1 : 0;
     constexpr int NN = D == 3 ? 27 : 9;
     // raw flags (significant details; preventive refinement of the children
-    // of significant cells), dilated by one cell; all loads issued first
+    // of significant cells), dilated by one cell
     uint8_t s[NN], sp[NN];
     int k = 0;
 #pragma unroll
@@ -44,29 +52,21 @@ __device__ __forceinline__ bool refine_flag(const View &v, const Grid &G, int lv
                 const int qx = bcmap(x + dx, n, v.bc), qy = bcmap(y + dy, n, v.bc);
                 const int qz = D == 3 ? bcmap(z + dz, n, v.bc) : 0;
                 s[k] = v.sig[G.coff + gidx(n, qx, qy, qz)];
-                sp[k] = 0;
-                if (lvl >= 1) {
-                    const Grid &Cg = v.grids[G.coarse];
-                    sp[k] = v.sig[Cg.coff + gidx(Cg.n, qx >> 1, qy >> 1, qz >> 1)];
-                }
+                sp[k] = lvl >= 1 ? v.sig[fg.C.coff + gidx(fg.C.n, qx >> 1, qy >> 1, qz >> 1)] : 0;
                 ++k;
             }
-    int any = 0;
-#pragma unroll
-    for (int j = 0; j < NN; ++j) any |= s[j] | sp[j];
-    if (any) return true;
     // nesting: level-(lvl+1) cells within two cells of a level-(lvl+1) cell
     // covered by the new level lvl+2; cells 2x-2 .. 2x+3 of level lvl+1 lie
-    // in at most three blocks of level lvl+2 per axis
+    // in at most three blocks of level lvl+2 per axis.  Read together with
+    // the flags above.
+    uint8_t a[27];
     if (lvl + 2 < v.L) {
-        const Grid &F = v.grids[G.fine];
-        const Grid &F2 = v.grids[F.fine];
-        const int nf = F.n;
+        const Grid &F2 = fg.F2;
+        const int nf = 2 * n;
         int bx[3], by[3], bz[3] = {0, 0, 0};
         const int nx = distinct_blocks(2 * x, -2, 3, nf, v.bc, 2, bx);
         const int ny = distinct_blocks(2 * y, -2, 3, nf, v.bc, 2, by);
         const int nz = D == 3 ? distinct_blocks(2 * z, -2, 3, nf, v.bc, 2, bz) : 1;
-        uint8_t a[27];
         int j = 0;
         for (int kz = 0; kz < 3; ++kz)
             for (int ky = 0; ky < 3; ++ky)
@@ -76,11 +76,14 @@ __device__ __forceinline__ bool refine_flag(const View &v, const Grid &G, int lv
                                : 0;
                     ++j;
                 }
-        int hit = 0;
-        for (int i = 0; i < 27; ++i) hit |= a[i];
-        if (hit) return true;
+    } else {
+        for (int j = 0; j < 27; ++j) a[j] = 0;
     }
-    return false;
+    int any = 0;
+#pragma unroll
+    for (int j = 0; j < NN; ++j) any |= s[j] | sp[j];
+    for (int i = 0; i < 27; ++i) any |= a[i];
+    return any != 0;
 }
 
 // ----------------------------------------------------------------------------
@@ -94,13 +97,23 @@ __device__ __forceinline__ bool refine_flag(const View &v, const Grid &G, int lv
 template <int D>
 __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
 {
-    if (v.meta->done) return;
     constexpr int MAXSUB = D == 2 ? 64 : 512;       // (pmax / BS)^D, pmax <= 64
     __shared__ int cnt8[MAXSUB];
     __shared__ uint8_t emit8[MAXSUB];
     __shared__ int wsum[4];
-    const Grid G = v.grids[lvl];
+    // first reads, independent of each other (grid index = level)
+    const int done = v.meta->done;
+    FlagGrids fg;
+    fg.G = v.grids[lvl];
     const Grid F = v.grids[lvl + 1];
+    if (lvl >= 1) fg.C = v.grids[lvl - 1];
+    if (lvl + 2 < v.L) fg.F2 = v.grids[lvl + 2];
+    const int64_t slot = v.pbase[lvl + 1] + blockIdx.x;
+    issued(slot, fg.G.n, fg.G.coff, F.boff, F.nb);
+    if (lvl >= 1) issued(fg.C.n, fg.C.coff);
+    if (lvl + 2 < v.L) issued(fg.F2.boff, fg.F2.nb);
+    if (done) return;
+    const Grid &G = fg.G;
     const int R = v.pmax / BS;
     const int nsub = D == 2 ? R * R : R * R * R;
     const int m = blockIdx.x;
@@ -123,7 +136,7 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
     for (int k = threadIdx.x; k < nfoot; k += blockDim.x) {
         const int lx = k % hp, ly = (k / hp) % hp, lz = D == 3 ? k / (hp * hp) : 0;
         const int x = bp[0] * hp + lx, y = bp[1] * hp + ly, z = D == 3 ? bp[2] * hp + lz : 0;
-        const bool fl = refine_flag<D>(v, G, lvl, x, y, z);
+        const bool fl = refine_flag<D>(v, fg, lvl, x, y, z);
         v.flag[G.coff + gidx(G.n, x, y, z)] = fl ? 1 : 0;
         if (fl) {
             atomicAdd(&cnt8[(lx >> 2) + R * ((ly >> 2) + R * (lz >> 2))], 1);
@@ -166,7 +179,6 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
     // recursion over children, x fastest, meets it), walks from the root to
     // the node that is emitted as a patch (or is empty).  The node's first
     // sub-block writes the patch; patches are ranked by that Morton order.
-    const int64_t slot = v.pbase[lvl + 1] + m;
     int *out = v.pslot + slot * (int64_t)nsub * 5;
     int nlead_total = 0;
     for (int c0 = 0; c0 < nsub; c0 += blockDim.x) {
@@ -235,10 +247,12 @@ template <int D>
 __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
 {
     __shared__ unsigned long long part[MAXLEV][NPART];
-    if (v.meta->done) return;
-    if (threadIdx.x < MAXLEV * NPART) part[threadIdx.x / NPART][threadIdx.x % NPART] = 0ull;
-    __syncthreads();
     __shared__ int lcnt[5];
+    __shared__ GridTab tab;
+    const int done = v.meta->done;
+    grid_tab_load(v, tab);
+    if (done) return;
+    if (threadIdx.x < MAXLEV * NPART) part[threadIdx.x / NPART][threadIdx.x % NPART] = 0ull;
     if (threadIdx.x < 5) lcnt[threadIdx.x] = 0;
     __syncthreads();
     constexpr int cpb = D == 2 ? BS * BS : BS * BS * BS;
@@ -248,35 +262,43 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
     const int64_t g0 = blockIdx.x * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
     for (int64_t gb = g0 + threadIdx.x; gb < g1; gb += blockDim.x) {
         int lvl = 0;
-        while (lvl + 1 < v.L && gb >= v.grids[lvl + 1].boff) ++lvl;
-        const Grid &G = v.grids[lvl];
+        while (lvl + 1 < v.L && gb >= grid_tab_lane(tab, lvl + 1).boff) ++lvl;
+        const Grid G = grid_tab_lane(tab, lvl);
         const int nb = G.nb;
         const int b = (int)(gb - G.boff);
         const int bx = b % nb, by = (b / nb) % nb, bz = D == 3 ? b / (nb * nb) : 0;
-        const bool a = v.nact[gb] != 0;
-        const bool old = v.act[gb] != 0;
-        int nchild = 0;
-        if (a && G.fine >= 0) {
-            const Grid &F = v.grids[G.fine];
+        // every mask read (the block, its children, its neighbours) is issued
+        // before any is tested
+        const uint8_t na = v.nact[gb];
+        const uint8_t oa = v.act[gb];
+        uint8_t ch[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (lvl + 1 < v.L) {
+            const Grid F = grid_tab_lane(tab, lvl + 1);
             const int zs = D == 3 ? 2 : 1;
             for (int z = 0; z < zs; ++z)
                 for (int y = 0; y < 2; ++y)
                     for (int x = 0; x < 2; ++x)
-                        nchild += v.nact[F.boff + (2 * bx + x) + (int64_t)F.nb * ((2 * by + y) + (int64_t)F.nb * (2 * bz + z))];
+                        ch[x + 2 * (y + 2 * z)] =
+                            v.nact[F.boff + (2 * bx + x) + (int64_t)F.nb * ((2 * by + y) + (int64_t)F.nb * (2 * bz + z))];
         }
+        uint8_t nbv[27];
+        const int r3 = D == 3 ? 1 : 0;
+        int j = 0;
+        for (int dz = -r3; dz <= r3; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int qx = bcmap(bx + dx, nb, v.bc), qy = bcmap(by + dy, nb, v.bc);
+                    const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
+                    nbv[j++] = lvl >= 1 ? v.nact[G.boff + qx + (int64_t)nb * (qy + (int64_t)nb * qz)] : 0;
+                }
+        const bool a = na != 0;
+        const bool old = oa != 0;
+        int nchild = 0;
+        if (a)
+            for (int i = 0; i < 8; ++i) nchild += ch[i];
         const int nch_all = D == 2 ? 4 : 8;
         bool ghost = false;
-        if (!a && lvl >= 1) {
-            const int r3 = D == 3 ? 1 : 0;
-            uint8_t nbv[27];
-            int j = 0;
-            for (int dz = -r3; dz <= r3; ++dz)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        const int qx = bcmap(bx + dx, nb, v.bc), qy = bcmap(by + dy, nb, v.bc);
-                        const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
-                        nbv[j++] = v.nact[G.boff + qx + (int64_t)nb * (qy + (int64_t)nb * qz)];
-                    }
+        if (!a) {
             int hit = 0;
             for (int i = 0; i < j; ++i) hit |= nbv[i];
             ghost = hit != 0;
@@ -327,25 +349,42 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt, int64_t ns
     __shared__ int wsum[4][NL];
     __shared__ int64_t lstart[MAXLEV + 1];
     __shared__ int pbase_s;
-    if (v.meta->done) return;
+    __shared__ int wp[4];
+    __shared__ int64_t pb[MAXLEV + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = gridDim.x, w = blockIdx.x;
+    // first reads, independent of each other: the done flag, the level
+    // starts, the list counts of the ranges before this one and the patch
+    // counts of the slots before this workgroup's slots
+    const int done = v.meta->done;
     if (tid <= MAXLEV) lstart[tid] = tid < v.L ? v.grids[tid].boff : nbt;
-    // offsets of this range: sums of the counts of the ranges before it
-    {
-        int acc[NL] = {0, 0, 0, 0, 0};
-        for (int i = tid; i < w; i += blockDim.x)
-            for (int k = 0; k < NL; ++k) acc[k] += v.wcnt[(int64_t)i * 5 + k];
-        for (int k = 0; k < NL; ++k)
-            for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
-        if (lane == 0)
-            for (int k = 0; k < NL; ++k) wsum[wave][k] = acc[k];
+    if (tid <= MAXLEV) pb[tid] = v.pbase[tid];
+    const int64_t schunk = (nslot + W - 1) / W;
+    const int64_t s0 = w * schunk, s1 = s0 + schunk < nslot ? s0 + schunk : nslot;
+    int acc[NL] = {0, 0, 0, 0, 0};
+    for (int i = tid; i < w; i += blockDim.x)
+        for (int k = 0; k < NL; ++k) acc[k] += v.wcnt[(int64_t)i * 5 + k];
+    int pacc = 0;
+    for (int64_t i = tid; i < s0; i += blockDim.x) pacc += v.pcnt[i];
+    issued(acc[0], acc[1], acc[2], acc[3], acc[4], pacc);
+    if (done) return;
+    for (int k = 0; k < NL; ++k)
+        for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
+    for (int o = 32; o > 0; o >>= 1) pacc += __shfl_xor(pacc, o);
+    if (lane == 0) {
+        for (int k = 0; k < NL; ++k) wsum[wave][k] = acc[k];
+        wp[wave] = pacc;
     }
     __syncthreads();
     if (tid < NL) {
         int s = 0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wsum[i][tid];
         base[tid] = s;
+    }
+    if (tid == 0) {
+        int s = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wp[i];
+        pbase_s = s;
     }
     __syncthreads();
     Tile *lists[NL] = {v.leaf, v.cov, v.ghost, v.fresh, v.actv};
@@ -382,21 +421,6 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt, int64_t ns
         __syncthreads();
     }
     // patch table: slots [s0, s1) of this workgroup
-    const int64_t schunk = (nslot + W - 1) / W;
-    const int64_t s0 = w * schunk, s1 = s0 + schunk < nslot ? s0 + schunk : nslot;
-    {
-        int acc = 0;
-        for (int64_t i = tid; i < s0; i += blockDim.x) acc += v.pcnt[i];
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (lane == 0) wsum[wave][0] = acc;
-        __syncthreads();
-        if (tid == 0) {
-            int s = 0;
-            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wsum[i][0];
-            pbase_s = s;
-        }
-        __syncthreads();
-    }
     for (int64_t c = s0; c < s1; c += blockDim.x) {
         const int64_t s = c + tid;
         const int k = s < s1 ? v.pcnt[s] : 0;
@@ -437,7 +461,7 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt, int64_t ns
         const int f = v.fcnt[s];
         if (f) {
             int l = 1;
-            while (l + 1 < v.L && s >= v.pbase[l + 1]) ++l;
+            while (l + 1 < v.L && s >= pb[l + 1]) ++l;
             atomicAdd(&nfl[l - 1], f);
         }
     }
