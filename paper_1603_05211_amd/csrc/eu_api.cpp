@@ -30,6 +30,7 @@ struct eu_ctx {
     int max_tiles = 0;
     int ngroups = 1;
     int64_t state_elems = 0;    // elements of one state array
+    std::vector<int64_t> pbase; // per level: first pmax-block slot (levels 1 .. L-1)
     bool initialized = false;
     int variant = 0;            // stage-kernel schedule (eu_autotune)
     std::string err;
@@ -82,13 +83,13 @@ struct Layout {
     std::vector<Grid> grids;
     int64_t state_elems = 0;
     int narrays = 2;
-    int64_t nbt = 0, ncoarse = 0, nslot = 0, max_tiles = 0, max_patch = 0, reg_elems = 0;
+    int64_t nbt = 0, ncoarse = 0, nslot = 0, max_tiles = 0, reg_elems = 0;
     int ncls = 1;
     int ngroups = 1;
     std::vector<int64_t> pbase;
     // scratch offsets
     size_t o_grids, o_act, o_nact, o_code, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
-        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_pbase, o_actv, o_reg, o_patches, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
+        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
     size_t scratch = 0, state = 0;
 };
 
@@ -177,7 +178,6 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.nslot = ns;
     const int64_t R = (!batch && lay.L > 1) ? c->patch_max / eu::BS : 1;
     const int64_t nsub = ipow(R, D);
-    lay.max_patch = boff > 0 ? boff : 1;
     lay.ngroups = batch ? lay.ngrid : 1;
 
     const size_t es = c->precision == EU_FP64 ? 8 : 4;
@@ -219,7 +219,6 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_cpart = take(sizeof(long long) * eu::NPART * eu::MAXLEV * lay.ncls);
     lay.o_wcnt = take(sizeof(int) * 5 * lay.ncls);
     lay.o_pbase = take(sizeof(int64_t) * (eu::MAXLEV + 1));
-    lay.o_patches = take(sizeof(int) * 5 * lay.max_patch);
     lay.o_meta = take(sizeof(Meta));
     lay.o_smax = take(8 * lay.ngrid);
     lay.o_dt = take(8 * lay.ngrid);
@@ -250,6 +249,36 @@ int check_launch(eu_ctx *c)
 }
 
 int64_t nblocks_grid(const eu_ctx *c, int g) { return ipow(c->grids[g].nb, c->dim); }
+
+// Leaf and patch cells per level of the current hierarchy: host sums of the
+// classification partials (one pair per workgroup and level).
+int level_cells(eu_ctx *c, int64_t *leaf, int64_t *act)
+{
+    std::vector<long long> p((size_t)c->v.ncls * MAXLEV * NPART);
+    HIPCHK(c, hipMemcpy(p.data(), c->v.cpart, sizeof(long long) * p.size(), hipMemcpyDeviceToHost));
+    for (int l = 0; l < c->L; ++l) {
+        int64_t a = 0, b = 0;
+        for (int w = 0; w < c->v.ncls; ++w) {
+            a += p[((size_t)w * MAXLEV + l) * NPART + 0];
+            b += p[((size_t)w * MAXLEV + l) * NPART + 1];
+        }
+        if (leaf) leaf[l] = a;
+        if (act) act[l] = b;
+    }
+    return EU_OK;
+}
+
+// Flagged cells per level (levels 0 .. L-2) from the per pmax-block counts
+// of the last flagging.
+int level_flags(eu_ctx *c, int64_t *nflag)
+{
+    std::vector<int> f((size_t)c->v.nslot);
+    if (!f.empty()) HIPCHK(c, hipMemcpy(f.data(), c->v.fcnt, sizeof(int) * f.size(), hipMemcpyDeviceToHost));
+    for (int l = 0; l < c->L; ++l) nflag[l] = 0;
+    for (int l = 1; l < c->L; ++l)
+        for (int64_t s = c->pbase[l]; s < (l + 1 < c->L ? c->pbase[l + 1] : c->v.nslot); ++s) nflag[l - 1] += f[(size_t)s];
+    return EU_OK;
+}
 
 // ---- launch sequences ------------------------------------------------------
 
@@ -506,7 +535,6 @@ int finish_init(eu_ctx *c)
         launch_fill_u8(c->v.act, c->nbt, 1, c->stream);
         Meta m{};
         m.nleaf = (int)leaf.size();
-        for (int g = 0; g < c->ngrid && g < eu::MAXLEV; ++g) {}
         int r;
         if ((r = upload(c, c->v.leaf, leaf.data(), sizeof(Tile) * leaf.size()))) return r;
         if ((r = upload(c, (void *)c->v.grp_off, goff.data(), sizeof(int) * c->ngrid))) return r;
@@ -569,6 +597,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     c->ngroups = lay.ngroups;
     c->grids = lay.grids;
     c->state_elems = lay.state_elems;
+    c->pbase = lay.pbase;
 
     View &v = c->v;
     v.dim = lay.dim;
@@ -610,7 +639,6 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.ncls = lay.ncls;
     v.wcnt = at<int>(scratch_dev, lay.o_wcnt);
     v.pbase = at<int64_t>(scratch_dev, lay.o_pbase);
-    v.patches = at<int>(scratch_dev, lay.o_patches);
     v.meta = at<Meta>(scratch_dev, lay.o_meta);
     v.smax = at<unsigned long long>(scratch_dev, lay.o_smax);
     v.dt = at<double>(scratch_dev, lay.o_dt);
@@ -620,7 +648,6 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.grp_off = at<int>(scratch_dev, lay.o_goff);
     v.grp_cnt = at<int>(scratch_dev, lay.o_gcnt);
     v.max_tiles = (int)lay.max_tiles;
-    v.max_patch = (int)lay.max_patch;
 
     int r;
     if ((r = upload(c, (void *)v.grids, lay.grids.data(), sizeof(Grid) * lay.ngrid)) ||
@@ -708,9 +735,8 @@ int eu_mr_flag(eu_ctx *c, int64_t *nflag_host)
     if (r) return r;
     if (nflag_host) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        Meta m;
-        HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
-        for (int l = 0; l < c->L; ++l) nflag_host[l] = l < c->L - 1 ? m.nflag[l] : 0;
+        r = level_flags(c, nflag_host);
+        if (r) return r;
     }
     return EU_OK;
 }
@@ -872,15 +898,26 @@ int eu_get_details(eu_ctx *c, int level, double *dst)
     return EU_OK;
 }
 
+// The rows come from the per pmax-block slots of the last flagging, read in
+// slot order (levels in order, pmax blocks in Morton order) and, within a
+// slot, in the order the split emitted them.
 int eu_patch_table(eu_ctx *c, int32_t *dst, int cap, int *npatch)
 {
     if (!c || !npatch || cap < 0 || (cap > 0 && !dst)) return EU_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    Meta m;
-    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
-    *npatch = c->mode == MODE_HIER ? m.npatch : 0;
-    const int k = *npatch < cap ? *npatch : cap;
-    if (k > 0) HIPCHK(c, hipMemcpy(dst, c->v.patches, sizeof(int) * 5 * k, hipMemcpyDeviceToHost));
+    *npatch = 0;
+    if (c->mode != MODE_HIER || c->v.nslot == 0) return EU_OK;
+    const int R = c->cfg.patch_max / BS;
+    const int64_t nsub = c->dim == 2 ? R * R : R * R * R;
+    std::vector<int> cnt((size_t)c->v.nslot), rows((size_t)(c->v.nslot * nsub * 5));
+    HIPCHK(c, hipMemcpy(cnt.data(), c->v.pcnt, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(rows.data(), c->v.pslot, sizeof(int) * rows.size(), hipMemcpyDeviceToHost));
+    int n = 0;
+    for (int64_t sl = 0; sl < c->v.nslot; ++sl)
+        for (int j = 0; j < cnt[(size_t)sl]; ++j, ++n)
+            if (n < cap)
+                for (int e = 0; e < 5; ++e) dst[5 * (int64_t)n + e] = rows[(size_t)((sl * nsub + j) * 5 + e)];
+    *npatch = n;
     return EU_OK;
 }
 
@@ -888,18 +925,12 @@ int eu_counters(eu_ctx *c, int64_t *leaves, int64_t *active)
 {
     if (!c) return EU_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    Meta m;
-    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
+    if (c->mode == MODE_HIER) return level_cells(c, leaves, active);
+    int64_t s = 0;
+    for (int g = 0; g < c->ngrid; ++g) s += c->grids[g].ncell;
     for (int l = 0; l < c->L; ++l) {
-        if (c->mode == MODE_HIER) {
-            if (leaves) leaves[l] = m.leaf_cells[l];
-            if (active) active[l] = m.act_cells[l];
-        } else {
-            int64_t s = 0;
-            for (int g = 0; g < c->ngrid; ++g) s += c->grids[g].ncell;
-            if (leaves) leaves[l] = s;
-            if (active) active[l] = s;
-        }
+        if (leaves) leaves[l] = s;
+        if (active) active[l] = s;
     }
     return EU_OK;
 }
@@ -990,15 +1021,14 @@ int eu_stage_time(eu_ctx *c, int reps, float *ms_host, int64_t *cells_host, int 
     float ms = 0.f;
     r = time_stage1(c, c->variant, reps, &ms);
     if (r) return r;
-    Meta m;
-    HIPCHK(c, hipMemcpy(&m, c->v.meta, sizeof(Meta), hipMemcpyDeviceToHost));
     int64_t cells = 0;
-    for (int l = 0; l < c->L; ++l) {
-        if (c->mode != MODE_HIER) {
-            for (int g = 0; g < c->ngrid; ++g) cells += c->grids[g].ncell;
-            break;
-        }
-        cells += c->v.lts ? m.act_cells[l] : m.leaf_cells[l];
+    if (c->mode != MODE_HIER) {
+        for (int g = 0; g < c->ngrid; ++g) cells += c->grids[g].ncell;
+    } else {
+        int64_t lc[MAXLEV], ac[MAXLEV];
+        r = level_cells(c, lc, ac);
+        if (r) return r;
+        for (int l = 0; l < c->L; ++l) cells += c->v.lts ? ac[l] : lc[l];
     }
     if (ms_host) *ms_host = ms;
     if (cells_host) *cells_host = cells;

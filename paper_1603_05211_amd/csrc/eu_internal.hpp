@@ -9,7 +9,7 @@ namespace eu {
 
 constexpr int BS = 8;          // block side in cells: the unit of patches and tiles
 constexpr int MAXLEV = 10;
-constexpr int NPART = 8;       // classification partial sums per level
+constexpr int NPART = 2;       // classification partial sums per level
 
 // One dense grid: a level of the hierarchy, the single uniform grid, or one
 // instance of a batch.  Field f of cell (x, y, z) lives at
@@ -40,22 +40,20 @@ struct Tile {
 struct Meta {
     int nleaf;                 // tiles in the leaf list (blocks holding leaves)
     int nghost;                // tiles in the ghost list
-    int npatch;                // rows of the patch table
     int status;                // bit 0: non-physical state met
     int done;                  // the current step starts at t >= t_end: skip it
     int steps;                 // steps taken since initialisation
     long long leaf_updates;    // leaf cells advanced since initialisation
     unsigned int ticket;       // blocks of the CFL reduction that have finished
     int pad_;
-    int cov_off[MAXLEV], cov_cnt[MAXLEV];   // per-level ranges of the covered-block list
-    int new_off[MAXLEV], new_cnt[MAXLEV];   // per-level ranges of the new-block list
-    int leaf_off[MAXLEV], leaf_cnt[MAXLEV]; // per-level ranges of the leaf list
-    int ghost_off[MAXLEV], ghost_cnt[MAXLEV];
-    int act_off[MAXLEV], act_cnt[MAXLEV];   // per-level ranges of the all-patch-block list
-    int nflag[MAXLEV];                      // flagged cells per level
-    long long leaf_cells[MAXLEV];
-    long long act_cells[MAXLEV];
+    unsigned long long upd_acc;  // leaf cells counted by the CFL reduction of the current step
+    // work lists by level: level l of list k occupies entries
+    // [loff[k][l], loff[k][l+1]); loff[k][l] for l >= L is the list length
+    int loff[5][MAXLEV + 1];
 };
+
+// work lists (index k of Meta::loff)
+enum { LST_LEAF = 0, LST_COV = 1, LST_GHOST = 2, LST_NEW = 3, LST_ACT = 4 };
 
 enum { MODE_HIER = 0, MODE_BATCH = 1 };
 
@@ -78,12 +76,10 @@ struct View {
     int *pcnt;                        // per pmax-block patch counts
     int *fcnt;                        // per pmax-block flagged-cell counts
     long long *cpart;                 // per classification workgroup and level (NPART values):
-                                      // leaf cells, patch cells, covered, new, leaf, ghost and
-                                      // patch blocks
+                                      // leaf cells, patch cells
     int ncls;                         // workgroups of the classification kernel
     int *wcnt;                        // per classification workgroup: entries of each list
     int64_t *pbase;                   // per-level offset into pslot / pcnt
-    int *patches;                     // compacted patch table (5 ints per row)
     Meta *meta;
     unsigned long long *smax;         // per grid: max wave-speed sum (FP64 bits)
     double *dt, *t;                   // per grid (batch) or entry 0 (hierarchy)
@@ -92,7 +88,6 @@ struct View {
     const int *grp_off, *grp_cnt;     // batch: tile range of each instance
     int64_t nslot;                    // pmax blocks of levels 1 .. L-1
     int max_tiles;                    // capacity of the leaf list
-    int max_patch;                    // capacity of the patch table
 };
 
 }  // namespace eu

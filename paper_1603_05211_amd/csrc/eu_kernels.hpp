@@ -465,8 +465,8 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     const bool lts = lvl >= 0;
     const bool hier = v.mode == MODE_HIER;
     const int done = v.meta->done;
-    const Tile *list = lts ? v.actv + v.meta->act_off[lvl] : v.leaf;
-    const int count = lts ? v.meta->act_cnt[lvl] : v.meta->nleaf;
+    const Tile *list = lts ? v.actv + v.meta->loff[LST_ACT][lvl] : v.leaf;
+    const int count = lts ? v.meta->loff[LST_ACT][lvl + 1] - v.meta->loff[LST_ACT][lvl] : v.meta->nleaf;
     const double dt0 = v.dt[lts ? lvl : 0];
     if (hier) grid_tab_load(v, tab);
     issued(list, count, dt0);
@@ -576,10 +576,10 @@ __device__ void cfl_finalize(const View &v)
         __shared__ double sdt[MAXLEV];
         const int g = threadIdx.x;
         double t = 0.0;
-        long long upd = 0;
+        unsigned long long upd = 0;
         if (g == 0) {
             t = v.t[0];
-            for (int l = 0; l < v.L; ++l) upd += v.meta->leaf_cells[l] << (v.lts ? l : 0);
+            upd = atomicExch(&v.meta->upd_acc, 0ull);
         }
         if (g < MAXLEV) {
             double d = __builtin_inf();
@@ -614,7 +614,7 @@ __device__ void cfl_finalize(const View &v)
         if (!done) {
             v.t[0] = t + dt;
             v.meta->steps += 1;
-            v.meta->leaf_updates += upd;
+            v.meta->leaf_updates += (long long)upd;
         }
         v.meta->ticket = 0u;
         return;
@@ -643,6 +643,7 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
 {
 #pragma clang fp contract(off)
     __shared__ double lmax[4][MAXLEV];
+    __shared__ unsigned long long lcnt[4];
     __shared__ int last;
     __shared__ GridTab tab;
     const bool hier = v.mode == MODE_HIER;
@@ -652,6 +653,7 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
     const double g = v.gamma;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane < MAXLEV) lmax[wave][lane] = 0.0;
+    if (lane == 0) lcnt[wave] = 0ull;
     __syncthreads();
     bool bad = false;
     for (int t = blockIdx.x * 4 + wave; t < count; t += gridDim.x * 4) {
@@ -664,6 +666,7 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
         const int oy = ((tl.block / nb) % nb) * BS;
         const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
         double m = 0.0;
+        int nl = 0;   // leaf cells of the tile
         for (int c = lane; c < TC; c += 64) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
             const int64_t id = G.off + gidx(n, x, y, z);
@@ -681,13 +684,18 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
 #pragma unroll
             for (int d = 0; d < D; ++d) S = S + (__builtin_fabs(w[1 + d]) + cs);
             if (leaf && S > m) m = S;
+            nl += leaf ? 1 : 0;
         }
         for (int o = 32; o > 0; o >>= 1) {
             const double r = __shfl_xor(m, o);
             m = r > m ? r : m;
+            nl += __shfl_xor(nl, o);
         }
         if (lane == 0) {
             if (hier) {
+                // leaf cells advanced this step (a level-l leaf 2^l times
+                // with local time stepping)
+                lcnt[wave] += (unsigned long long)nl << (v.lts ? tl.grid : 0);
                 if (m > lmax[wave][tl.grid]) lmax[wave][tl.grid] = m;
             } else if (m > 0.0) {
                 atomicMax(&v.smax[tl.grid], (unsigned long long)__double_as_longlong(m));
@@ -699,12 +707,15 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
     if (threadIdx.x == 0) {
         // one thread folds the waves' maxima and publishes them: a single
         // device-scope fence per workgroup (each one writes back this XCD's L2)
-        if (hier)
+        if (hier) {
             for (int l = 0; l < v.ngrid; ++l) {
                 double mm = lmax[0][l];
                 for (int w = 1; w < 4; ++w) mm = lmax[w][l] > mm ? lmax[w][l] : mm;
                 if (mm > 0.0) atomicMax(&v.smax[l], (unsigned long long)__double_as_longlong(mm));
             }
+            const unsigned long long nc = (lcnt[0] + lcnt[1]) + (lcnt[2] + lcnt[3]);
+            if (nc) atomicAdd(&v.meta->upd_acc, nc);
+        }
         __threadfence();
         const unsigned int prev = atomicAdd(&v.meta->ticket, 1u);
         last = prev == gridDim.x - 1 ? 1 : 0;
@@ -837,7 +848,7 @@ __global__ void __launch_bounds__(256) k_restrict_cov(View v, T *A, int lvl)
 {
     // first reads, independent of each other (grid index = level)
     const int done = v.meta->done;
-    const int off = v.meta->cov_off[lvl], count = v.meta->cov_cnt[lvl];
+    const int off = v.meta->loff[LST_COV][lvl], count = v.meta->loff[LST_COV][lvl + 1] - off;
     const Grid G = v.grids[lvl];
     const Grid F = v.grids[lvl + 1];
     issued(off, count, G.n, G.off, G.ncell, F.n, F.off, F.ncell, F.boff, F.nb);
@@ -885,8 +896,8 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
     __shared__ GridTab tab;
     // first reads, independent of each other
     const int done = v.meta->done;
-    const int off = v.meta->cov_off[lvl];
-    const int count = v.meta->cov_cnt[lvl] + (nlev == 2 ? v.meta->cov_cnt[lvl + 1] : 0);
+    const int off = v.meta->loff[LST_COV][lvl];
+    const int count = v.meta->loff[LST_COV][lvl + nlev] - off;
     grid_tab_load(v, tab);
     issued(off, count);
     if (done) return;
@@ -1023,9 +1034,15 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
     // first reads, independent of each other (grid index = level)
     const int done = v.meta->done;
     int off0 = 0, cnt0 = 0, off1 = 0, cnt1 = 0;   // ranges in the new and ghost lists
-    if (mode == 0 || mode == 3) { off0 = v.meta->new_off[lvl]; cnt0 = v.meta->new_cnt[lvl]; }
+    if (mode == 0 || mode == 3) {
+        off0 = v.meta->loff[LST_NEW][lvl];
+        cnt0 = v.meta->loff[LST_NEW][lvl + 1] - off0;
+    }
     if (mode == 1) cnt1 = v.meta->nghost;
-    if (mode >= 2) { off1 = v.meta->ghost_off[lvl]; cnt1 = v.meta->ghost_cnt[lvl]; }
+    if (mode >= 2) {
+        off1 = v.meta->loff[LST_GHOST][lvl];
+        cnt1 = v.meta->loff[LST_GHOST][lvl + 1] - off1;
+    }
     const bool all = mode == 1;
     Grid Gl, Cl;
     if (all) {
@@ -1080,7 +1097,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256) k_copy_level(View v, int lvl)
 {
     if (v.meta->done) return;
-    const int off = v.meta->act_off[lvl], count = v.meta->act_cnt[lvl];
+    const int off = v.meta->loff[LST_ACT][lvl], count = v.meta->loff[LST_ACT][lvl + 1] - off;
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     const T *Q = (const T *)v.Q;
     T *Qo = (T *)v.Qo;
@@ -1107,7 +1124,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256) k_reflux(View v, int lvl)
 {
     if (v.meta->done) return;
-    const int off = v.meta->leaf_off[lvl], count = v.meta->leaf_cnt[lvl];
+    const int off = v.meta->loff[LST_LEAF][lvl], count = v.meta->loff[LST_LEAF][lvl + 1] - off;
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     T *Q = (T *)v.Q;
     const T *reg = (const T *)v.reg;

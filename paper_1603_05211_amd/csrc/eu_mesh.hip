@@ -314,12 +314,7 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
         if (a) {
             atomicAdd(&part[lvl][0], (unsigned long long)(cpb - nchild * cpc));
             atomicAdd(&part[lvl][1], (unsigned long long)cpb);
-            atomicAdd(&part[lvl][6], 1ull);
         }
-        if (code & 1) atomicAdd(&part[lvl][4], 1ull);
-        if (code & 2) atomicAdd(&part[lvl][2], 1ull);
-        if (code & 4) atomicAdd(&part[lvl][5], 1ull);
-        if (code & 8) atomicAdd(&part[lvl][3], 1ull);
         // entries of this range in the leaf, covered, ghost, new, patch lists
         if (code & 1) atomicAdd(&lcnt[0], 1);
         if (code & 2) atomicAdd(&lcnt[1], 1);
@@ -337,54 +332,37 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
 // Compaction of the classified blocks into the leaf, covered, ghost, new and
 // all-patch lists (order: level, then block index, x fastest), with the same
 // contiguous ranges as the classification: workgroup w sums the list counts
-// of the ranges before its own and writes its entries from there.  The patch
-// table (levels in order, pmax blocks in Morton order, each block's patches
-// in split order) is compacted the same way over pmax-block slots.
-// Workgroup 0 also writes the per-level counts and list ranges.
+// of the ranges before its own and writes its entries from there.  The
+// thread holding the first block of a level records where that level starts
+// in every list.  The last workgroup writes the list lengths.  (The patch
+// table is read from the per pmax-block slots when it is asked for.)
 template <int D>
-__global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt, int64_t nslot, int nsub)
+__global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
 {
     constexpr int NL = 5;                  // leaf, covered, ghost, new, patch blocks
     __shared__ int base[NL];
     __shared__ int wsum[4][NL];
     __shared__ int64_t lstart[MAXLEV + 1];
-    __shared__ int pbase_s;
-    __shared__ int wp[4];
-    __shared__ int64_t pb[MAXLEV + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = gridDim.x, w = blockIdx.x;
     // first reads, independent of each other: the done flag, the level
-    // starts, the list counts of the ranges before this one and the patch
-    // counts of the slots before this workgroup's slots
+    // starts and the list counts of the ranges before this one
     const int done = v.meta->done;
     if (tid <= MAXLEV) lstart[tid] = tid < v.L ? v.grids[tid].boff : nbt;
-    if (tid <= MAXLEV) pb[tid] = v.pbase[tid];
-    const int64_t schunk = (nslot + W - 1) / W;
-    const int64_t s0 = w * schunk, s1 = s0 + schunk < nslot ? s0 + schunk : nslot;
     int acc[NL] = {0, 0, 0, 0, 0};
     for (int i = tid; i < w; i += blockDim.x)
         for (int k = 0; k < NL; ++k) acc[k] += v.wcnt[(int64_t)i * 5 + k];
-    int pacc = 0;
-    for (int64_t i = tid; i < s0; i += blockDim.x) pacc += v.pcnt[i];
-    issued(acc[0], acc[1], acc[2], acc[3], acc[4], pacc);
+    issued(acc[0], acc[1], acc[2], acc[3], acc[4]);
     if (done) return;
     for (int k = 0; k < NL; ++k)
         for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
-    for (int o = 32; o > 0; o >>= 1) pacc += __shfl_xor(pacc, o);
-    if (lane == 0) {
+    if (lane == 0)
         for (int k = 0; k < NL; ++k) wsum[wave][k] = acc[k];
-        wp[wave] = pacc;
-    }
     __syncthreads();
     if (tid < NL) {
         int s = 0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wsum[i][tid];
         base[tid] = s;
-    }
-    if (tid == 0) {
-        int s = 0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wp[i];
-        pbase_s = s;
     }
     __syncthreads();
     Tile *lists[NL] = {v.leaf, v.cov, v.ghost, v.fresh, v.actv};
@@ -406,12 +384,13 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt, int64_t ns
             if (lane == 0) wc[wave][k] = __popcll(mask);
         }
         __syncthreads();
-        for (int k = 0; k < NL; ++k)
-            if ((code >> k) & 1) {
-                int off = base[k] + pre[k];
-                for (int i = 0; i < wave; ++i) off += wc[i][k];
-                lists[k][off] = Tile{lvl, (int)(gb - lstart[lvl])};
-            }
+        const bool first = gb < g1 && gb == lstart[lvl];   // first block of its level
+        for (int k = 0; k < NL; ++k) {
+            int off = base[k] + pre[k];
+            for (int i = 0; i < wave; ++i) off += wc[i][k];
+            if ((code >> k) & 1) lists[k][off] = Tile{lvl, (int)(gb - lstart[lvl])};
+            if (first) v.meta->loff[k][lvl] = off;
+        }
         __syncthreads();
         if (tid < NL) {
             int s = 0;
@@ -420,70 +399,13 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt, int64_t ns
         }
         __syncthreads();
     }
-    // patch table: slots [s0, s1) of this workgroup
-    for (int64_t c = s0; c < s1; c += blockDim.x) {
-        const int64_t s = c + tid;
-        const int k = s < s1 ? v.pcnt[s] : 0;
-        int incl = k;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int r = __shfl_up(incl, o);
-            if (lane >= o) incl += r;
-        }
-        __shared__ int wt[4];
-        if (lane == 63) wt[wave] = incl;
-        __syncthreads();
-        int off = pbase_s + incl - k;
-        for (int i = 0; i < wave; ++i) off += wt[i];
-        for (int j = 0; j < k; ++j)
-            if (off + j < v.max_patch)
-                for (int e = 0; e < 5; ++e) v.patches[5 * (int64_t)(off + j) + e] = v.pslot[(s * nsub + j) * 5 + e];
-        __syncthreads();
-        if (tid == 0) {
-            int t = 0;
-            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += wt[i];
-            pbase_s += t;
-        }
-        __syncthreads();
-    }
     if (w != W - 1) return;
-    // the last workgroup knows the totals; it also writes the per-level counts
-    __shared__ unsigned long long lsum[MAXLEV][NPART];
-    __shared__ int nfl[MAXLEV];
-    if (tid < MAXLEV * NPART) lsum[tid / NPART][tid % NPART] = 0ull;
-    if (tid < MAXLEV) nfl[tid] = 0;
-    __syncthreads();
-    for (int i = tid; i < v.ncls * v.L * NPART; i += blockDim.x) {
-        const int ww = i / (v.L * NPART), r = i % (v.L * NPART);
-        const long long p = v.cpart[((int64_t)ww * MAXLEV + r / NPART) * NPART + r % NPART];
-        if (p) atomicAdd(&lsum[r / NPART][r % NPART], (unsigned long long)p);
-    }
-    for (int64_t s = tid; s < nslot; s += blockDim.x) {
-        const int f = v.fcnt[s];
-        if (f) {
-            int l = 1;
-            while (l + 1 < v.L && s >= pb[l + 1]) ++l;
-            atomicAdd(&nfl[l - 1], f);
-        }
-    }
-    __syncthreads();
+    // the last workgroup has seen every entry: list lengths
+    if (tid < NL)
+        for (int l = v.L; l <= MAXLEV; ++l) v.meta->loff[tid][l] = base[tid];
     if (tid == 0) {
         v.meta->nleaf = base[0];
         v.meta->nghost = base[2];
-        v.meta->npatch = pbase_s;
-        int o[5] = {0, 0, 0, 0, 0};
-        for (int l = 0; l < MAXLEV; ++l) {
-            const bool in = l < v.L;
-            v.meta->leaf_cells[l] = in ? (long long)lsum[l][0] : 0;
-            v.meta->act_cells[l] = in ? (long long)lsum[l][1] : 0;
-            v.meta->nflag[l] = in ? nfl[l] : 0;
-            const int cnts[5] = {in ? (int)lsum[l][2] : 0, in ? (int)lsum[l][3] : 0, in ? (int)lsum[l][4] : 0,
-                                 in ? (int)lsum[l][5] : 0, in ? (int)lsum[l][6] : 0};
-            v.meta->cov_off[l] = o[0]; v.meta->cov_cnt[l] = cnts[0]; o[0] += cnts[0];
-            v.meta->new_off[l] = o[1]; v.meta->new_cnt[l] = cnts[1]; o[1] += cnts[1];
-            v.meta->leaf_off[l] = o[2]; v.meta->leaf_cnt[l] = cnts[2]; o[2] += cnts[2];
-            v.meta->ghost_off[l] = o[3]; v.meta->ghost_cnt[l] = cnts[3]; o[3] += cnts[3];
-            v.meta->act_off[l] = o[4]; v.meta->act_cnt[l] = cnts[4]; o[4] += cnts[4];
-        }
     }
 }
 
@@ -525,14 +447,12 @@ void launch_flag_tile(const View &v, int lvl, int nblocks, hipStream_t s)
 
 void launch_build_lists(const View &v, int64_t nbt, hipStream_t s)
 {
-    const int R = v.pmax / BS;
-    const int nsub = v.dim == 2 ? R * R : R * R * R;
     if (v.dim == 2) {
         k_classify<2><<<v.ncls, 256, 0, s>>>(v, nbt);
-        k_compact<2><<<v.ncls, 256, 0, s>>>(v, nbt, v.nslot, nsub);
+        k_compact<2><<<v.ncls, 256, 0, s>>>(v, nbt);
     } else {
         k_classify<3><<<v.ncls, 256, 0, s>>>(v, nbt);
-        k_compact<3><<<v.ncls, 256, 0, s>>>(v, nbt, v.nslot, nsub);
+        k_compact<3><<<v.ncls, 256, 0, s>>>(v, nbt);
     }
 }
 
