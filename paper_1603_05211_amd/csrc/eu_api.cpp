@@ -223,7 +223,8 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_smax = take(8 * lay.ngrid);
     lay.o_dt = take(8 * lay.ngrid);
     lay.o_t = take(8 * lay.ngrid);
-    lay.o_partial = take(8 * lay.nv * lay.max_tiles);
+    // per-tile partial totals, or the CFL reduction's per-workgroup maxima
+    lay.o_partial = take(8 * std::max<int64_t>(lay.nv * lay.max_tiles, (int64_t)eu::CFL_MAXBLK * eu::CFL_STRIDE));
     lay.o_totals = take(8 * lay.nv * lay.ngroups);
     lay.o_goff = take(sizeof(int) * lay.ngroups);
     lay.o_gcnt = take(sizeof(int) * lay.ngroups);

@@ -10,6 +10,8 @@ namespace eu {
 constexpr int BS = 8;          // block side in cells: the unit of patches and tiles
 constexpr int MAXLEV = 10;
 constexpr int NPART = 2;       // classification partial sums per level
+constexpr int CFL_STRIDE = MAXLEV + 1;   // CFL partials per workgroup: level maxima, leaf count
+constexpr int CFL_MAXBLK = 512;          // workgroups of the CFL reduction
 
 // One dense grid: a level of the hierarchy, the single uniform grid, or one
 // instance of a batch.  Field f of cell (x, y, z) lives at
@@ -44,9 +46,6 @@ struct Meta {
     int done;                  // the current step starts at t >= t_end: skip it
     int steps;                 // steps taken since initialisation
     long long leaf_updates;    // leaf cells advanced since initialisation
-    unsigned int ticket;       // blocks of the CFL reduction that have finished
-    int pad_;
-    unsigned long long upd_acc;  // leaf cells counted by the CFL reduction of the current step
     // work lists by level: level l of list k occupies entries
     // [loff[k][l], loff[k][l+1]); loff[k][l] for l >= L is the list length
     int loff[5][MAXLEV + 1];

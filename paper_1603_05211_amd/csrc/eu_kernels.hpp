@@ -560,91 +560,18 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
 }
 
 // ----------------------------------------------------------------------------
-// CFL reduction over leaves (FP64): per-grid max of sum_d (|v_d| + c); the
-// last block to finish turns the maxima into dt (finalisation below).
+// CFL reduction over leaves (FP64): per-grid max of sum_d (|v_d| + c), then
+// dt (second kernel)
 // ----------------------------------------------------------------------------
-// dt = min over levels of cfl dx_l / smax_l (hierarchy) or per instance
-// (batch), clipped to reach t_end.  A step that starts at t >= t_end is
-// marked done and skipped by every later kernel of the step; otherwise the
-// step is committed: t += dt, steps += 1, leaf updates counted.
-__device__ void cfl_finalize(const View &v)
-{
-    if (v.mode == MODE_HIER) {
-        // dt = min over levels of cfl dx_l / smax_l; with local time stepping
-        // the level-0 step dt_0 = min over levels (cfl dx_l / smax_l) 2^l and
-        // dt_l = dt_0 / 2^l.  One thread per level, then thread 0 commits.
-        __shared__ double sdt[MAXLEV];
-        const int g = threadIdx.x;
-        double t = 0.0;
-        unsigned long long upd = 0;
-        if (g == 0) {
-            t = v.t[0];
-            upd = atomicExch(&v.meta->upd_acc, 0ull);
-        }
-        if (g < MAXLEV) {
-            double d = __builtin_inf();
-            if (g < v.ngrid) {
-                const double dx = v.grids[g].dx;
-                const unsigned long long b = atomicExch(&v.smax[g], 0ull);
-                if (b) {
-                    const double sm = __longlong_as_double((long long)b);
-                    d = (v.cfl * dx) / sm;
-                    if (v.lts) d = d * (double)(1 << g);
-                }
-            }
-            sdt[g] = d;
-        }
-        __syncthreads();
-        if (g != 0) return;
-        double dt = __builtin_inf();
-        for (int l = 0; l < v.ngrid; ++l)
-            if (sdt[l] < dt) dt = sdt[l];
-        const int done = t < v.t_end ? 0 : 1;
-        if (dt > v.t_end - t) dt = v.t_end - t;
-        if (v.lts) {
-            double dl = dt;
-            for (int l = 0; l < v.ngrid; ++l) {
-                v.dt[l] = dl;
-                dl = dl * 0.5;
-            }
-        } else {
-            v.dt[0] = dt;
-        }
-        v.meta->done = done;
-        if (!done) {
-            v.t[0] = t + dt;
-            v.meta->steps += 1;
-            v.meta->leaf_updates += (long long)upd;
-        }
-        v.meta->ticket = 0u;
-        return;
-    }
-    for (int g = threadIdx.x; g < v.ngrid; g += blockDim.x) {
-        const unsigned long long b = atomicExch(&v.smax[g], 0ull);
-        const double s = __longlong_as_double((long long)b);
-        double dt = b ? (v.cfl * v.grids[g].dx) / s : 0.0;
-        const double t = v.t[g];
-        if (dt > v.t_end - t) dt = v.t_end - t;
-        if (!(dt > 0.0)) dt = 0.0;
-        v.dt[g] = dt;
-        v.t[g] = t + dt;
-    }
-    if (threadIdx.x == 0) {
-        v.meta->done = 0;
-        v.meta->steps += 1;
-        v.meta->ticket = 0u;
-    }
-}
-
-// One wave per tile; each block folds its waves' maxima per level before one
-// atomic per level (hierarchy) or per tile (batch).
+// Hierarchy: workgroup b writes its per-level maxima and its count of leaf
+// cells advanced to v.partial[b * CFL_STRIDE ...] (plain stores; the kernel
+// boundary publishes them).  Batch: one atomic max per tile on its instance.
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
 {
 #pragma clang fp contract(off)
     __shared__ double lmax[4][MAXLEV];
     __shared__ unsigned long long lcnt[4];
-    __shared__ int last;
     __shared__ GridTab tab;
     const bool hier = v.mode == MODE_HIER;
     const int count = v.meta->nleaf;
@@ -704,26 +631,16 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
     }
     if (__any(bad) && lane == 0) atomicOr(&v.meta->status, 1);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // one thread folds the waves' maxima and publishes them: a single
-        // device-scope fence per workgroup (each one writes back this XCD's L2)
-        if (hier) {
-            for (int l = 0; l < v.ngrid; ++l) {
-                double mm = lmax[0][l];
-                for (int w = 1; w < 4; ++w) mm = lmax[w][l] > mm ? lmax[w][l] : mm;
-                if (mm > 0.0) atomicMax(&v.smax[l], (unsigned long long)__double_as_longlong(mm));
-            }
-            const unsigned long long nc = (lcnt[0] + lcnt[1]) + (lcnt[2] + lcnt[3]);
-            if (nc) atomicAdd(&v.meta->upd_acc, nc);
+    if (hier) {
+        const int l = threadIdx.x;
+        double *P = v.partial + (int64_t)blockIdx.x * CFL_STRIDE;
+        if (l < MAXLEV) {
+            double mm = lmax[0][l];
+            for (int w = 1; w < 4; ++w) mm = lmax[w][l] > mm ? lmax[w][l] : mm;
+            P[l] = mm;
+        } else if (l == MAXLEV) {
+            P[MAXLEV] = (double)((lcnt[0] + lcnt[1]) + (lcnt[2] + lcnt[3]));
         }
-        __threadfence();
-        const unsigned int prev = atomicAdd(&v.meta->ticket, 1u);
-        last = prev == gridDim.x - 1 ? 1 : 0;
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        cfl_finalize(v);
     }
 }
 

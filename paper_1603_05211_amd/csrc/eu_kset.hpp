@@ -46,6 +46,7 @@ extern const KSet kset_f32;
 // precision-independent mesh kernels (eu_mesh.hip)
 void launch_flag_tile(const View &, int lvl, int nblocks, hipStream_t);
 void launch_build_lists(const View &, int64_t nblocks_total, hipStream_t);
+void launch_cfl_final(const View &, int nblocks_cfl, hipStream_t);
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t val, hipStream_t);
 void launch_totals_final(const View &, int ngroups, hipStream_t);
 

@@ -112,11 +112,12 @@ template <typename T> void reflux(const View &v, int lvl, int maxb, hipStream_t 
 
 template <typename T> void cfl(const View &v, int maxt, hipStream_t s)
 {
-    // few blocks (one wave per tile): each folds its tiles before one atomic
-    // per level, and the last block to finish computes dt
-    const int nblk = clamp_grid((maxt + 3) / 4, 128);
+    // one wave per tile (up to CFL_MAXBLK workgroups), then one workgroup
+    // turns the partial maxima into dt
+    const int nblk = clamp_grid((maxt + 3) / 4, CFL_MAXBLK);
     if (v.dim == 2) k_cfl<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
+    launch_cfl_final(v, nblk, s);
 }
 
 template <typename T> void totals(const View &v, int maxt, hipStream_t s)

@@ -409,6 +409,91 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
     }
 }
 
+// ----------------------------------------------------------------------------
+// CFL: time step from the per-workgroup maxima of the reduction kernel
+// ----------------------------------------------------------------------------
+// dt = min over levels of cfl dx_l / smax_l (hierarchy; with local time
+// stepping the level-0 step dt_0 = min over levels (cfl dx_l / smax_l) 2^l
+// and dt_l = dt_0 / 2^l) or per instance (batch), clipped to reach t_end.
+// A step that starts at t >= t_end is marked done and skipped by every later
+// kernel of the step; otherwise the step is committed: t += dt, steps += 1,
+// leaf updates counted.  One workgroup.
+__global__ void __launch_bounds__(256) k_cfl_final(View v, int nblk)
+{
+#pragma clang fp contract(off)
+    if (v.mode != MODE_HIER) {
+        for (int g = threadIdx.x; g < v.ngrid; g += blockDim.x) {
+            const unsigned long long b = atomicExch(&v.smax[g], 0ull);
+            const double s = __longlong_as_double((long long)b);
+            double dt = b ? (v.cfl * v.grids[g].dx) / s : 0.0;
+            const double t = v.t[g];
+            if (dt > v.t_end - t) dt = v.t_end - t;
+            if (!(dt > 0.0)) dt = 0.0;
+            v.dt[g] = dt;
+            v.t[g] = t + dt;
+        }
+        if (threadIdx.x == 0) {
+            v.meta->done = 0;
+            v.meta->steps += 1;
+        }
+        return;
+    }
+    __shared__ double smax[4][MAXLEV];
+    __shared__ double scnt[4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double t = v.t[0];
+    // per-level maxima and the leaf count over the workgroups' partials
+    double m[MAXLEV], cnt = 0.0;
+    for (int l = 0; l < MAXLEV; ++l) m[l] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        const double *P = v.partial + (int64_t)b * CFL_STRIDE;
+#pragma unroll
+        for (int l = 0; l < MAXLEV; ++l) m[l] = P[l] > m[l] ? P[l] : m[l];
+        cnt = cnt + P[MAXLEV];
+    }
+#pragma unroll
+    for (int l = 0; l < MAXLEV; ++l)
+        for (int o = 32; o > 0; o >>= 1) {
+            const double r = __shfl_xor(m[l], o);
+            m[l] = r > m[l] ? r : m[l];
+        }
+    for (int o = 32; o > 0; o >>= 1) cnt = cnt + __shfl_xor(cnt, o);
+    if (lane == 0) {
+        for (int l = 0; l < MAXLEV; ++l) smax[wave][l] = m[l];
+        scnt[wave] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double dt = __builtin_inf();
+    for (int l = 0; l < v.ngrid; ++l) {
+        double sm = smax[0][l];
+        for (int w = 1; w < 4; ++w) sm = smax[w][l] > sm ? smax[w][l] : sm;
+        if (sm > 0.0) {
+            double d = (v.cfl * v.grids[l].dx) / sm;
+            if (v.lts) d = d * (double)(1 << l);
+            if (d < dt) dt = d;
+        }
+    }
+    const long long upd = (long long)((scnt[0] + scnt[1]) + (scnt[2] + scnt[3]));
+    const int done = t < v.t_end ? 0 : 1;
+    if (dt > v.t_end - t) dt = v.t_end - t;
+    if (v.lts) {
+        double dl = dt;
+        for (int l = 0; l < v.ngrid; ++l) {
+            v.dt[l] = dl;
+            dl = dl * 0.5;
+        }
+    } else {
+        v.dt[0] = dt;
+    }
+    v.meta->done = done;
+    if (!done) {
+        v.t[0] = t + dt;
+        v.meta->steps += 1;
+        v.meta->leaf_updates += upd;
+    }
+}
+
 __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t val)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -443,6 +528,11 @@ void launch_flag_tile(const View &v, int lvl, int nblocks, hipStream_t s)
 {
     if (v.dim == 2) k_flag_tile<2><<<nblocks, 256, 0, s>>>(v, lvl);
     else k_flag_tile<3><<<nblocks, 256, 0, s>>>(v, lvl);
+}
+
+void launch_cfl_final(const View &v, int nblk, hipStream_t s)
+{
+    k_cfl_final<<<1, 256, 0, s>>>(v, nblk);
 }
 
 void launch_build_lists(const View &v, int64_t nbt, hipStream_t s)
