@@ -88,7 +88,7 @@ struct Layout {
     int ngroups = 1;
     std::vector<int64_t> pbase;
     // scratch offsets
-    size_t o_grids, o_act, o_nact, o_code, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
+    size_t o_grids, o_act, o_nact, o_code, o_gmask, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
         o_pcnt, o_fcnt, o_cpart, o_wcnt, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
     size_t scratch = 0, state = 0;
 };
@@ -203,6 +203,7 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_act = take(lay.nbt);
     lay.o_nact = take(lay.nbt);
     lay.o_code = take(lay.nbt);
+    lay.o_gmask = take(sizeof(uint32_t) * lay.nbt);
     lay.o_sig = take(lay.ncoarse);
     lay.o_flag = take(lay.ncoarse);
     lay.o_D = take(8 * lay.ncoarse);
@@ -625,6 +626,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.act = at<uint8_t>(scratch_dev, lay.o_act);
     v.nact = at<uint8_t>(scratch_dev, lay.o_nact);
     v.code = at<uint8_t>(scratch_dev, lay.o_code);
+    v.gmask = at<uint32_t>(scratch_dev, lay.o_gmask);
     v.nslot = lay.nslot;
     v.sig = at<uint8_t>(scratch_dev, lay.o_sig);
     v.flag = at<uint8_t>(scratch_dev, lay.o_flag);

@@ -32,8 +32,10 @@ struct Grid {
     int64_t rfoff;   // local time stepping: fine-side flux registers of this level (-1: none)
 };
 
-// A tile of work: one BS^d block of one grid.
+// A tile of work: one BS^d block of one grid.  In the ghost list the grid
+// field also carries the block's neighbour mask (Tile::GRID_BITS up).
 struct Tile {
+    static constexpr int GRID_BITS = 4;   // grid index < 16 in the ghost list (levels)
     int grid;
     int block;       // block index within the grid, x fastest
 };
@@ -67,6 +69,8 @@ struct View {
     uint8_t *act, *nact;              // per-block patch membership (current / new)
     uint8_t *sig, *flag;              // per-cell significance and refinement flags
     uint8_t *code;                    // per-block classification of the new hierarchy
+    uint32_t *gmask;                  // per ghost block: which of its 3^D neighbour blocks are
+                                      // in a patch (bit (dx+1) + 3 (dy+1) [+ 9 (dz+1) in 3D])
     double *D;                        // per-cell FP64 detail norm
     Tile *leaf, *cov, *ghost, *fresh; // work lists
     Tile *actv;                       // every block in a patch, by level

@@ -865,39 +865,26 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
     }
 }
 
-// ghost cell: outside every patch of its level, within two cells of a patch
-// (cells c-2 .. c+2 lie in at most three blocks per axis; every mask read is
-// issued before any is tested)
+// ghost cell of a ghost block (a block outside every patch of its level):
+// a cell within two cells of a patch.  Cells x-2 .. x+2 reach the lower
+// neighbour block along an axis when x mod 8 < 2 and the upper one when
+// x mod 8 > 5 (the boundary map is applied to blocks as to cells), so the
+// test reads the block's neighbour mask only.
 template <int D>
-__device__ __forceinline__ bool is_ghost(const View &v, const Grid &G, int x, int y, int z)
+__device__ __forceinline__ bool ghost_cell(uint32_t gm, int x, int y, int z)
 {
-    const int n = G.n;
-    const bool own = block_active(v, v.act, G, x, y, z);
-    int b[3][3], nb[3];
-    const int c[3] = {x, y, z};
+    const int c[3] = {x & 7, y & 7, z & 7};
+    int lo[3], hi[3];
     for (int d = 0; d < 3; ++d) {
-        nb[d] = 0;
-        if (d >= D) { b[d][0] = 0; nb[d] = 1; continue; }
-        for (int o = -2; o <= 2; ++o) {
-            const int q = bcmap(c[d] + o, n, v.bc) >> 3;
-            bool seen = false;
-            for (int j = 0; j < nb[d]; ++j) seen |= b[d][j] == q;
-            if (!seen) b[d][nb[d]++] = q;
-        }
+        lo[d] = d < D && c[d] < 2 ? -1 : 0;
+        hi[d] = d < D && c[d] > 5 ? 1 : 0;
     }
-    uint8_t a[27];
-    int j = 0;
-    for (int kz = 0; kz < 3; ++kz)
-        for (int ky = 0; ky < 3; ++ky)
-            for (int kx = 0; kx < 3; ++kx) {
-                a[j] = (kx < nb[0] && ky < nb[1] && kz < nb[2])
-                           ? v.act[G.boff + b[0][kx] + (int64_t)G.nb * (b[1][ky] + (int64_t)G.nb * b[2][kz])]
-                           : 0;
-                ++j;
-            }
-    int hit = 0;
-    for (int i = 0; i < 27; ++i) hit |= a[i];
-    return !own && hit != 0;
+    bool hit = false;
+    for (int dz = lo[2]; dz <= hi[2]; ++dz)
+        for (int dy = lo[1]; dy <= hi[1]; ++dy)
+            for (int dx = lo[0]; dx <= hi[0]; ++dx)
+                hit |= ((gm >> ((dx + 1) + 3 * (dy + 1) + (D == 3 ? 9 * (dz + 1) : 0))) & 1u) != 0;
+    return hit;
 }
 
 // Third-order prediction of child (cx, cy, cz) of coarse cell p from the
@@ -978,7 +965,9 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const bool fresh = t < cnt0;
         const Tile tl = fresh ? v.fresh[off0 + t] : v.ghost[off1 + t - cnt0];
-        const Grid G = all ? grid_tab(tab, tl.grid) : Gl;
+        const int lv = fresh ? tl.grid : tl.grid & ((1 << Tile::GRID_BITS) - 1);
+        const uint32_t gm = fresh ? 0u : (uint32_t)tl.grid >> Tile::GRID_BITS;
+        const Grid G = all ? grid_tab(tab, lv) : Gl;
         const Grid Cg = all ? grid_tab(tab, G.coarse) : Cl;
         const int nb = G.nb;
         const int ox = (tl.block % nb) * BS;
@@ -987,9 +976,8 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         for (int c = threadIdx.x; c < TC; c += blockDim.x) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
             // every cell of a new block is predicted; in a ghost block only
-            // the ghost cells (tested first: most cells of a ghost block
-            // are not ghost cells)
-            if (!fresh && !is_ghost<D>(v, G, x, y, z)) continue;
+            // the ghost cells
+            if (!fresh && !ghost_cell<D>(gm, x, y, z)) continue;
             T val[NV];
 #pragma unroll
             for (int f = 0; f < NV; ++f) {

@@ -298,10 +298,10 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
             for (int i = 0; i < 8; ++i) nchild += ch[i];
         const int nch_all = D == 2 ? 4 : 8;
         bool ghost = false;
+        uint32_t gm = 0;
         if (!a) {
-            int hit = 0;
-            for (int i = 0; i < j; ++i) hit |= nbv[i];
-            ghost = hit != 0;
+            for (int i = 0; i < j; ++i) gm |= (nbv[i] ? 1u : 0u) << i;
+            ghost = gm != 0;
         }
         int code = 0;
         if (a && nchild < nch_all) code |= 1;
@@ -310,6 +310,7 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
         if (a && !old && lvl >= 1) code |= 8;
         code |= nchild << 4;
         v.code[gb] = (uint8_t)code;
+        v.gmask[gb] = gm;
         v.act[gb] = a ? 1 : 0;
         if (a) {
             atomicAdd(&part[lvl][0], (unsigned long long)(cpb - nchild * cpc));
@@ -371,8 +372,10 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
     for (int64_t c = g0; c < g1; c += blockDim.x) {
         const int64_t gb = c + tid;
         int code = 0, lvl = 0;
+        uint32_t gm = 0;
         if (gb < g1) {
             code = v.code[gb] & 15;
+            gm = v.gmask[gb];
             if (code & 3) code |= 16;  // bit 4: in a patch
             while (gb >= lstart[lvl + 1]) ++lvl;
         }
@@ -388,7 +391,8 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
         for (int k = 0; k < NL; ++k) {
             int off = base[k] + pre[k];
             for (int i = 0; i < wave; ++i) off += wc[i][k];
-            if ((code >> k) & 1) lists[k][off] = Tile{lvl, (int)(gb - lstart[lvl])};
+            if ((code >> k) & 1)
+                lists[k][off] = Tile{k == LST_GHOST ? (int)(lvl | (gm << Tile::GRID_BITS)) : lvl, (int)(gb - lstart[lvl])};
             if (first) v.meta->loff[k][lvl] = off;
         }
         __syncthreads();
