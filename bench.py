@@ -230,7 +230,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the context configurations")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=40)
-    ap.add_argument("--schedule", type=int, default=-1, choices=[-1, 0, 1, 2, 3],
+    ap.add_argument("--schedule", type=int, default=-1, choices=list(range(-1, 6)),
                     help="force a stage-kernel schedule instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration)")

@@ -57,6 +57,7 @@ enum { EU_BC_TRANSMISSIVE = 0, EU_BC_PERIODIC = 1 };
 enum { EU_DT_GLOBAL = 0, EU_DT_LTS = 1 };        /* time stepping           */
 enum { EU_RESTRICT = 0, EU_PROLONG = 1, EU_GHOST = 2 }; /* eu_project modes */
 enum { EU_IC_QUADRANT = 0, EU_IC_ELLIPSOID = 1, EU_IC_RIEMANN1D = 2, EU_IC_UNIFORM = 3 };
+enum { EU_STAGE_SCHEDULES = 6 };                 /* see eu_autotune           */
 
 /* Problem size and method parameters (Sec. 2; Sec. 4 for the values used
  * there).  All fields are read by eu_query_sizes / eu_create. */
@@ -212,14 +213,15 @@ int eu_time(eu_ctx *ctx, double *t_host, double *dt_host);
 int eu_profile(eu_ctx *ctx, int enable);
 int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
 
-/* Schedule of the finite-volume stage kernel (threads per tile, faces axis by
- * axis or in one pass).  In FP64 every schedule gives bit-identical results;
+/* Schedule of the finite-volume stage kernel (threads per tile; faces axis by
+ * axis, axis by axis from per-cell face states, or all axes in one pass).  In FP64 every schedule gives bit-identical results;
  * in FP32 they agree to rounding (the compiler contracts each differently).
  * eu_autotune times each schedule (reps launches of the first stage on the
  * current state, HIP events on the context's stream; the state is left
  * unchanged) and keeps the fastest: *variant_host receives it, ms_host
- * (nullable, 4 entries) the mean time of each.  eu_set_variant forces one
- * (0..3).  Both drop captured graphs. */
+ * (nullable, EU_STAGE_SCHEDULES entries) the mean time of each.
+ * eu_set_variant forces one (0 .. EU_STAGE_SCHEDULES-1).  Both drop captured
+ * graphs. */
 int eu_autotune(eu_ctx *ctx, int reps, int *variant_host, float *ms_host);
 
 /* Duration of the finite-volume stage kernel on the current state, with the

@@ -16,11 +16,11 @@ import numpy as np
 
 from . import _abi
 from ._abi import (EU_BC_PERIODIC, EU_BC_TRANSMISSIVE, EU_DT_GLOBAL, EU_DT_LTS, EU_FP32, EU_FP64,
-                   EU_GHOST, EU_IC_ELLIPSOID, EU_IC_QUADRANT, EU_IC_RIEMANN1D, EU_IC_UNIFORM,
+                   EU_GHOST, EU_STAGE_SCHEDULES, EU_IC_ELLIPSOID, EU_IC_QUADRANT, EU_IC_RIEMANN1D, EU_IC_UNIFORM,
                    EU_PROLONG, EU_RESTRICT)
 
 __all__ = ["Solver", "EuError", "EU_FP32", "EU_FP64", "EU_BC_PERIODIC", "EU_BC_TRANSMISSIVE",
-           "EU_RESTRICT", "EU_PROLONG", "EU_GHOST", "EU_DT_GLOBAL", "EU_DT_LTS"]
+           "EU_RESTRICT", "EU_PROLONG", "EU_GHOST", "EU_DT_GLOBAL", "EU_DT_LTS", "EU_STAGE_SCHEDULES"]
 
 
 class EuError(RuntimeError):
@@ -251,7 +251,7 @@ class Solver:
         """Time every stage-kernel schedule on the current state and keep the
         fastest; returns (variant, per-variant ms)."""
         var = C.c_int(0)
-        ms = (C.c_float * 4)()
+        ms = (C.c_float * EU_STAGE_SCHEDULES)()
         self._check(self._lib.eu_autotune(self._ctx, reps, C.byref(var), ms), "eu_autotune")
         return var.value, list(ms)
 

@@ -345,15 +345,20 @@ template <int D, int NT_> struct FV {
     static constexpr int TC = D == 2 ? B * B : B * B * B;
     static constexpr int CPT = (TC + NT - 1) / NT;
     static constexpr int NF = (B + 1) * (D == 2 ? B : B * B);   // faces per axis
+    static constexpr int NS = (B + 2) * (D == 2 ? B : B * B);   // cells -1 .. B of the lines of an axis
 };
 
 // Flux of face fi of axis dn of the tile (fi = a + (B+1) r: a-th face along
 // the axis, r-th line across it), written to F.
+// With sFm/sFp given (per-cell face states of axis dn, see k_fv_stage), the
+// face states of a face between two cells of the tile's level are read from
+// them instead of being reconstructed here.
 template <typename T, int D, int NT>
 __device__ __forceinline__ void fv_face(const View &v, const Grid &G, const Grid &GF, const T *src, int ox, int oy, int oz,
                                         const T (*sW)[FV<D, NT>::NE], const uint8_t *sCov,
                                         const uint8_t *sAct, T g, T gi, bool lts, bool record, int sub,
-                                        int dn, int fi, T *F)
+                                        int dn, int fi, T *F, const T (*sFm)[FV<D, NT>::NS] = nullptr,
+                                        const T (*sFp)[FV<D, NT>::NS] = nullptr)
 {
     using C = FV<D, NT>;
     constexpr int E = C::E, H = C::H, B = C::B;
@@ -387,15 +392,26 @@ __device__ __forceinline__ void fv_face(const View &v, const Grid &G, const Grid
         fine_mean<T, D>(v, GF, src, px, py, D == 3 ? pz : 0, s, dn, g, gi, F);
         return;
     }
-    T wa[D + 2], wb[D + 2], wc[D + 2], wd[D + 2];
+    if (sFp) {
+        // left cell a-1 and right cell a of line r: entries a and a+1
+        T wL[D + 2], wR[D + 2];
 #pragma unroll
-    for (int f = 0; f < D + 2; ++f) {
-        wa[f] = sW[f][hl - SD];
-        wb[f] = sW[f][hl];
-        wc[f] = sW[f][hr];
-        wd[f] = sW[f][hr + SD];
+        for (int f = 0; f < D + 2; ++f) {
+            wL[f] = sFp[f][a + (B + 2) * r];
+            wR[f] = sFm[f][a + 1 + (B + 2) * r];
+        }
+        ausm_plus<T, D>(g, gi, dn, wL, wR, F);
+    } else {
+        T wa[D + 2], wb[D + 2], wc[D + 2], wd[D + 2];
+#pragma unroll
+        for (int f = 0; f < D + 2; ++f) {
+            wa[f] = sW[f][hl - SD];
+            wb[f] = sW[f][hl];
+            wc[f] = sW[f][hr];
+            wd[f] = sW[f][hr + SD];
+        }
+        face_flux4<T, D>(g, gi, dn, wa, wb, wc, wd, F);
     }
-    face_flux4<T, D>(g, gi, dn, wa, wb, wc, wd, F);
     if (record) {
         // registers are indexed by the cell on the low side of the face
         int qx = ox + lx, qy = oy + ly, qz = oz + lz;
@@ -445,19 +461,25 @@ __device__ __forceinline__ void fv_collect(const T (*sF)[FV<D, NT>::NF], T (*R)[
 // the fine-flux mean.  Local time stepping (lvl >= 0): every cell in a patch
 // of level lvl with the level's own fluxes; with record set, fluxes across
 // refinement boundaries go to the flux registers (substep sub).
-// Schedules (bit-identical results): MERGED = false computes the faces axis
-// by axis (one LDS flux array reused per axis); MERGED = true computes the
+// Schedules (bit-identical FP64 results): SCHED 0 computes the faces axis
+// by axis (one LDS flux array reused per axis); SCHED 2 does the same but
+// first reconstructs the two face states of every cell of the axis' lines
+// once (slope, then W -/+ slope/2) instead of twice per cell, once for each
+// of its faces; SCHED 1 computes the
 // faces of all axes in one pass over all threads (one array per axis).
-template <typename T, int D, int NT, bool MERGED>
+template <typename T, int D, int NT, int SCHED>
 __global__ void __launch_bounds__(NT)
 k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac, int lvl, int sub,
            int record)
 {
     using C = FV<D, NT>;
     constexpr int E = C::E, H = C::H, B = C::B, NV = C::NV;
+    constexpr bool MERGED = SCHED == 1;
+    constexpr bool CELLS = SCHED == 2;
     constexpr int NA = MERGED ? D : 1;   // flux arrays held at once
     __shared__ T sW[NV][C::NE];
     __shared__ T sF[NA][NV][C::NF];
+    __shared__ T sFm[CELLS ? NV : 1][CELLS ? C::NS : 1], sFp[CELLS ? NV : 1][CELLS ? C::NS : 1];
     __shared__ uint8_t sCov[C::NE];
     __shared__ uint8_t sAct[C::NE];
     __shared__ GridTab tab;
@@ -531,9 +553,33 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
         } else {
 #pragma unroll
             for (int dn = 0; dn < D; ++dn) {
+                if constexpr (CELLS) {
+                    // face states of cells -1 .. B of every line of axis dn
+                    const int SD = dn == 0 ? 1 : dn == 1 ? E : E * E;
+                    for (int c = threadIdx.x; c < C::NS; c += NT) {
+                        const int a = c % (B + 2) - 1, r = c / (B + 2);
+                        const int r0 = r % B, r1 = D == 3 ? r / B : 0;
+                        const int lx = dn == 0 ? a : r0;
+                        const int ly = dn == 1 ? a : (dn == 0 ? r0 : r1);
+                        const int lz = D == 3 ? (dn == 2 ? a : r1) : 0;
+                        const int h = (lx + H) + E * ((ly + H) + (D == 3 ? E * (lz + H) : 0));
+#pragma unroll
+                        for (int f = 0; f < NV; ++f) {
+                            const T w0 = sW[f][h];
+                            const T sl = slope_va<T>(sW[f][h - SD], w0, sW[f][h + SD]);
+                            sFm[f][c] = w0 - T(0.5) * sl;
+                            sFp[f][c] = w0 + T(0.5) * sl;
+                        }
+                    }
+                    __syncthreads();
+                }
                 for (int fi = threadIdx.x; fi < C::NF; fi += NT) {
                     T F[NV];
-                    fv_face<T, D, NT>(v, G, GF, src, ox, oy, oz, sW, sCov, sAct, g, gi, lts, record, sub, dn, fi, F);
+                    if constexpr (CELLS)
+                        fv_face<T, D, NT>(v, G, GF, src, ox, oy, oz, sW, sCov, sAct, g, gi, lts, record, sub, dn, fi, F,
+                                          sFm, sFp);
+                    else
+                        fv_face<T, D, NT>(v, G, GF, src, ox, oy, oz, sW, sCov, sAct, g, gi, lts, record, sub, dn, fi, F);
 #pragma unroll
                     for (int f = 0; f < NV; ++f) sF[0][f][fi] = F[f];
                 }

@@ -22,7 +22,7 @@ struct InitArgs {
 // Which state array a launcher works on.
 enum { ARR_Q = 0, ARR_QS = 1, ARR_QO = 2 };
 
-constexpr int FV_VARIANTS = 4;   // schedules of the stage kernel (autotuned)
+constexpr int FV_VARIANTS = 6;   // schedules of the stage kernel (autotuned)
 
 struct KSet {
     size_t elem;  // bytes per state value

@@ -62,10 +62,11 @@ template <typename T> void predict(const View &v, int a, int lvl, int mode, doub
 
 // Stage-kernel schedules the autotuner chooses from (variant index):
 //   2D: 0 = 64 threads, per-axis faces; 1 = 64 threads, merged faces;
-//       2 = 128 threads, per-axis;      3 = 128 threads, merged.
-//   3D: 0 = 256 threads, per-axis;      1 = 256 threads, merged;
-//       2 = 512 threads, per-axis;      3 = 512 threads, merged.
-template <typename T, int D, int NT, bool M>
+//       2 = 128 threads, per-axis;      3 = 128 threads, merged;
+//       4 = 64 threads, per-axis with per-cell face states;
+//       5 = 128 threads, per-axis with per-cell face states.
+//   3D: the same with 256 and 512 threads.
+template <typename T, int D, int NT, int M>
 void fv_launch(const View &v, int nblk, const T *src, T *out, double fac, int lvl, int sub, int record,
                hipStream_t s)
 {
@@ -81,17 +82,21 @@ template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, 
     const double fac = stage == 1 ? 0.5 : 1.0;
     if (v.dim == 2) {
         switch (variant) {
-        case 1: fv_launch<T, 2, 64, true>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 2: fv_launch<T, 2, 128, false>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 3: fv_launch<T, 2, 128, true>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        default: fv_launch<T, 2, 64, false>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 1: fv_launch<T, 2, 64, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 2: fv_launch<T, 2, 128, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 3: fv_launch<T, 2, 128, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 4: fv_launch<T, 2, 64, 2>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 5: fv_launch<T, 2, 128, 2>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        default: fv_launch<T, 2, 64, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
         }
     } else {
         switch (variant) {
-        case 1: fv_launch<T, 3, 256, true>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 2: fv_launch<T, 3, 512, false>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 3: fv_launch<T, 3, 512, true>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        default: fv_launch<T, 3, 256, false>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 1: fv_launch<T, 3, 256, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 2: fv_launch<T, 3, 512, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 3: fv_launch<T, 3, 512, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 4: fv_launch<T, 3, 256, 2>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 5: fv_launch<T, 3, 512, 2>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        default: fv_launch<T, 3, 256, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
         }
     }
 }
