@@ -348,6 +348,41 @@ template <int D, int NT_> struct FV {
     static constexpr int NS = (B + 2) * (D == 2 ? B : B * B);   // cells -1 .. B of the lines of an axis
 };
 
+// Face layout of axis dn: face a (0..B) between local cells a-1 and a along
+// dn, on the line given by the other coordinates; x varies fastest in every
+// axis' layout, so consecutive lanes read consecutive LDS words for every
+// axis (a layout with the axis coordinate fastest puts y and z faces on a
+// few LDS banks).  Returns a and the left cell's local coordinates.
+template <int D, int B>
+__device__ __forceinline__ void face_coords(int dn, int fi, int &a, int &lx, int &ly, int &lz)
+{
+    if (dn == 0) {
+        a = fi % (B + 1);
+        const int r = fi / (B + 1);
+        lx = a - 1;
+        ly = r % B;
+        lz = D == 3 ? r / B : 0;
+    } else if (dn == 1) {
+        lx = fi % B;
+        const int q = fi / B;
+        a = q % (B + 1);
+        ly = a - 1;
+        lz = D == 3 ? q / (B + 1) : 0;
+    } else {
+        lx = fi % B;
+        ly = (fi / B) % B;
+        a = fi / (B * B);
+        lz = a - 1;
+    }
+}
+// Index of the per-cell face states of axis dn for the cell at position
+// p - 1 (p = 0..B+1) along dn on the line of cell (lx, ly, lz); x fastest.
+template <int B>
+__device__ __forceinline__ int cell_state_idx(int dn, int lx, int ly, int lz, int p)
+{
+    return dn == 0 ? p + (B + 2) * (ly + B * lz) : dn == 1 ? lx + B * (p + (B + 2) * lz) : lx + B * (ly + B * p);
+}
+
 // Flux of face fi of axis dn of the tile (fi = a + (B+1) r: a-th face along
 // the axis, r-th line across it), written to F.
 // With sFm/sFp given (per-cell face states of axis dn, see k_fv_stage), the
@@ -363,12 +398,9 @@ __device__ __forceinline__ void fv_face(const View &v, const Grid &G, const Grid
     using C = FV<D, NT>;
     constexpr int E = C::E, H = C::H, B = C::B;
     const int SD = dn == 0 ? 1 : dn == 1 ? E : E * E;
-    const int a = fi % (B + 1), r = fi / (B + 1);
-    // local coordinates of the left cell
-    const int r0 = r % B, r1 = D == 3 ? r / B : 0;
-    const int lx = dn == 0 ? a - 1 : r0;
-    const int ly = dn == 1 ? a - 1 : (dn == 0 ? r0 : r1);
-    const int lz = D == 3 ? (dn == 2 ? a - 1 : r1) : 0;
+    // face a (0..B) along axis dn; local coordinates of its left cell
+    int a, lx, ly, lz;
+    face_coords<D, B>(dn, fi, a, lx, ly, lz);
     const int hl = (lx + H) + E * ((ly + H) + (D == 3 ? E * (lz + H) : 0));
     const int hr = hl + SD;
     const bool lin = a >= 1, rin = a <= B - 1;
@@ -397,8 +429,8 @@ __device__ __forceinline__ void fv_face(const View &v, const Grid &G, const Grid
         T wL[D + 2], wR[D + 2];
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) {
-            wL[f] = sFp[f][a + (B + 2) * r];
-            wR[f] = sFm[f][a + 1 + (B + 2) * r];
+            wL[f] = sFp[f][cell_state_idx<B>(dn, lx, ly, lz, a)];
+            wR[f] = sFm[f][cell_state_idx<B>(dn, lx, ly, lz, a + 1)];
         }
         ausm_plus<T, D>(g, gi, dn, wL, wR, F);
     } else {
@@ -444,9 +476,9 @@ __device__ __forceinline__ void fv_collect(const T (*sF)[FV<D, NT>::NF], T (*R)[
         const int c = threadIdx.x + k * C::NT;
         if (c >= C::TC) break;
         const int x = c % B, y = (c / B) % B, z = c / (B * B);
-        const int a = dn == 0 ? x : dn == 1 ? y : z;
-        const int r = dn == 0 ? y + B * z : dn == 1 ? x + B * z : x + B * y;
-        const int lo = a + (B + 1) * r, hi = lo + 1;
+        // faces x and x+1 of the cell along axis dn (x-fastest face layout)
+        const int lo = dn == 0 ? x + (B + 1) * (y + B * z) : dn == 1 ? x + B * (y + (B + 1) * z) : x + B * (y + B * z);
+        const int hi = lo + (dn == 0 ? 1 : dn == 1 ? B : B * B);
 #pragma unroll
         for (int f = 0; f < D + 2; ++f) {
             const T d = sF[f][hi] - sF[f][lo];
@@ -557,11 +589,21 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
                     // face states of cells -1 .. B of every line of axis dn
                     const int SD = dn == 0 ? 1 : dn == 1 ? E : E * E;
                     for (int c = threadIdx.x; c < C::NS; c += NT) {
-                        const int a = c % (B + 2) - 1, r = c / (B + 2);
-                        const int r0 = r % B, r1 = D == 3 ? r / B : 0;
-                        const int lx = dn == 0 ? a : r0;
-                        const int ly = dn == 1 ? a : (dn == 0 ? r0 : r1);
-                        const int lz = D == 3 ? (dn == 2 ? a : r1) : 0;
+                        // cell p - 1 along dn (p = 0..B+1), x fastest as in cell_state_idx
+                        int lx, ly, lz;
+                        if (dn == 0) {
+                            lx = c % (B + 2) - 1;
+                            ly = (c / (B + 2)) % B;
+                            lz = D == 3 ? c / ((B + 2) * B) : 0;
+                        } else if (dn == 1) {
+                            lx = c % B;
+                            ly = (c / B) % (B + 2) - 1;
+                            lz = D == 3 ? c / (B * (B + 2)) : 0;
+                        } else {
+                            lx = c % B;
+                            ly = (c / B) % B;
+                            lz = c / (B * B) - 1;
+                        }
                         const int h = (lx + H) + E * ((ly + H) + (D == 3 ? E * (lz + H) : 0));
 #pragma unroll
                         for (int f = 0; f < NV; ++f) {
