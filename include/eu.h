@@ -185,6 +185,15 @@ int eu_conserved_totals(eu_ctx *ctx, double *totals_host);
  * in the state layout: (d+2) n^d values. */
 int eu_copy_level(eu_ctx *ctx, int inst, int level, int which, double *dst_host);
 
+/* The adaptive solution projected onto the finest uniform grid (the error
+ * assessment of Sec. 3): level 0, then on each finer level every cell in a
+ * patch keeps its value and every other cell is predicted (Sec. 2.1) from
+ * the level below.  dst_host receives nv fields of n_finest^d values (SoA,
+ * x fastest, converted to double).  The composite is built in the stage
+ * array, which the next step recomputes.  Hierarchy only (EU_EINVAL for a
+ * batch); synchronises the stream. */
+int eu_copy_uniform(eu_ctx *ctx, double *dst_host);
+
 /* Per-cell masks of a level (n^d bytes): patch membership (eu_get_active),
  * final refinement flags (eu_get_flags, levels 0..L-2), FP64 details
  * (eu_get_details, levels 0..L-2). */

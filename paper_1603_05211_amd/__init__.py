@@ -194,6 +194,14 @@ class Solver:
         self._check(self._lib.eu_copy_level(self._ctx, inst, level, which, _dp(out)), "eu_copy_level")
         return out
 
+    def composite(self) -> np.ndarray:
+        """The adaptive solution projected onto the finest uniform grid
+        (eu_copy_uniform); overwrites the stage array."""
+        n = self.n(self.levels - 1)
+        out = np.empty((self.nv,) + (n,) * self.dim)
+        self._check(self._lib.eu_copy_uniform(self._ctx, _dp(out)), "eu_copy_uniform")
+        return out
+
     def active(self, level: int) -> np.ndarray:
         n = self.n(level)
         out = np.empty((n,) * self.dim, dtype=np.uint8)

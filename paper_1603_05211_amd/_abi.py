@@ -58,6 +58,7 @@ SIGNATURES = {
     "eu_advance": (C.c_int, [_vp, C.c_int, C.c_int, _ip]),
     "eu_conserved_totals": (C.c_int, [_vp, _dp]),
     "eu_copy_level": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
+    "eu_copy_uniform": (C.c_int, [_vp, _dp]),
     "eu_get_active": (C.c_int, [_vp, C.c_int, _u8p]),
     "eu_get_flags": (C.c_int, [_vp, C.c_int, _u8p]),
     "eu_get_details": (C.c_int, [_vp, C.c_int, _dp]),

@@ -864,6 +864,17 @@ int eu_copy_level(eu_ctx *c, int inst, int level, int which, double *dst)
     return EU_OK;
 }
 
+int eu_copy_uniform(eu_ctx *c, double *dst)
+{
+    if (!c || !dst) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    if (c->mode != MODE_HIER) return set_err(c, EU_EINVAL, "a batch has no hierarchy");
+    for (int l = 0; l < c->L; ++l) c->ks->composite(c->v, l, c->grids[l].ncell, c->stream);
+    int r = check_launch(c);
+    if (r) return r;
+    return eu_copy_level(c, 0, c->L - 1, 1, dst);
+}
+
 int eu_get_active(eu_ctx *c, int level, uint8_t *dst)
 {
     if (!c || !dst) return EU_EINVAL;

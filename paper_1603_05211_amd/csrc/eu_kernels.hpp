@@ -1084,6 +1084,34 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
     }
 }
 
+// Composite solution on level lvl, in the stage array (error assessment,
+// Sec. 3): level 0 is copied; on a finer level a cell in a patch keeps its
+// value and every other cell is predicted from the composite of the level
+// below.  Called for lvl = 0, 1, .., L-1 in order.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_composite(View v, int lvl)
+{
+    const Grid G = v.grids[lvl];
+    const T *Q = (const T *)v.Q;
+    T *U = (T *)v.Qs;
+    const int n = G.n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.ncell;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = D == 3 ? (int)(i / ((int64_t)n * n)) : 0;
+        const bool keep = lvl == 0 || block_active(v, v.act, G, x, y, z);
+        if (keep) {
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) U[G.off + f * G.ncell + i] = Q[G.off + f * G.ncell + i];
+        } else {
+            const Grid Cg = v.grids[lvl - 1];
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f)
+                U[G.off + f * G.ncell + i] = predict_child<T, D, T>(U + Cg.off + f * Cg.ncell, Cg.n, v.bc, x >> 1,
+                                                                    y >> 1, z >> 1, x & 1, y & 1, z & 1);
+        }
+    }
+}
+
 // Local time stepping: keep level lvl's state at the start of its step (the
 // cells of its patches) for the time interpolation of finer ghost cells.
 template <typename T, int D>

@@ -38,6 +38,7 @@ struct KSet {
     void (*cfl)(const View &, int maxtiles, hipStream_t);
     void (*totals)(const View &, int maxtiles, hipStream_t);
     void (*details)(const View &, int64_t ncell_coarse_levels, hipStream_t);
+    void (*composite)(const View &, int lvl, int64_t ncell, hipStream_t);
 };
 
 extern const KSet kset_f64;

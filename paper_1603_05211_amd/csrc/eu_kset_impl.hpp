@@ -132,6 +132,13 @@ template <typename T> void totals(const View &v, int maxt, hipStream_t s)
     else k_totals<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
 }
 
+template <typename T> void composite(const View &v, int lvl, int64_t ncell, hipStream_t s)
+{
+    const int nblk = clamp_grid((ncell + 255) / 256, 8192);
+    if (v.dim == 2) k_composite<T, 2><<<nblk, 256, 0, s>>>(v, lvl);
+    else k_composite<T, 3><<<nblk, 256, 0, s>>>(v, lvl);
+}
+
 template <typename T> void details(const View &v, int64_t ncell, hipStream_t s)
 {
     const int nblk = clamp_grid((ncell + 255) / 256, 8192);
@@ -147,6 +154,7 @@ template <typename T> KSet make()
     k.restrict_full = restrict_full<T>;
     k.restrict_cov = restrict_cov<T>;
     k.restrict2 = restrict2<T>;
+    k.composite = composite<T>;
     k.predict = predict<T>;
     k.fv_stage = fv_stage<T>;
     k.copy_level = copy_level<T>;

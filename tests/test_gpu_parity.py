@@ -171,13 +171,8 @@ def test_fp32_error_report(dim):
 
 
 def composite_gpu(s, h):
-    U = s.level(0)
-    for l in range(1, h.L):
-        P = orc.predict(h.dim, U, h.bc)
-        act = s.active(l).astype(bool)
-        P[:, act] = s.level(l)[:, act]
-        U = P
-    return U
+    """The GPU's finest-grid projection (eu_copy_uniform)."""
+    return s.composite()
 
 
 def test_batch_fp64_instances():
@@ -238,3 +233,26 @@ def test_full_size_uniform3d_256_fp64():
     err = np.abs(Qg - Qo).max(axis=(1, 2, 3)) / np.abs(Qo).max(axis=(1, 2, 3))
     say("  linf", err)
     assert err.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_composite_fp64_bit_exact(dim):
+    """eu_copy_uniform against the oracle's projection onto the finest grid
+    (Sec. 3 error assessment), FP64, after adaptive steps."""
+    if dim == 2:
+        h, s = make_pair(2, 4, 32)
+        init_pair(h, s, "quadrant", 4)
+        steps = 6
+    else:
+        h, s = make_pair(3, 3, 16, cfl=0.4)
+        init_pair(h, s, "ellipsoid", 2)
+        steps = 3
+    run_pair(h, s, steps)
+    Uo, Ug = h.composite(), s.composite()
+    assert Ug.shape == Uo.shape
+    assert np.array_equal(Ug, Uo)
+    # the stage array it used as scratch is rebuilt by the next step
+    do, dg = run_pair(h, s, 2)
+    assert np.array_equal(do, dg)
+    linf, _ = state_errors(h, s)
+    assert linf.max() <= FP64_TOL
