@@ -623,6 +623,8 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.actv = at<Tile>(scratch_dev, lay.o_actv);
     v.reg = at<char>(scratch_dev, lay.o_reg);
     v.grids = at<Grid>(scratch_dev, lay.o_grids);
+    for (int g = 0; g < lay.ngrid && g < eu::MAXLEV; ++g) v.gt[g] = lay.grids[(size_t)g];
+    for (int l = 0; l <= eu::MAXLEV; ++l) v.pb[l] = lay.pbase[(size_t)l];
     v.act = at<uint8_t>(scratch_dev, lay.o_act);
     v.nact = at<uint8_t>(scratch_dev, lay.o_nact);
     v.code = at<uint8_t>(scratch_dev, lay.o_code);

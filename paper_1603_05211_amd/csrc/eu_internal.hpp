@@ -65,6 +65,8 @@ struct View {
     int pmin, pmax;
     double gamma, cfl, t_end, eps, eta;
     const Grid *grids;                // device copy of the grid table
+    Grid gt[MAXLEV];                  // the first MAXLEV grids (every level of a hierarchy), by
+                                      // value: kernels read them with their arguments
     void *Q, *Qs, *Qo;                // state arrays (element type per precision)
     uint8_t *act, *nact;              // per-block patch membership (current / new)
     uint8_t *sig, *flag;              // per-cell significance and refinement flags
@@ -83,6 +85,7 @@ struct View {
     int ncls;                         // workgroups of the classification kernel
     int *wcnt;                        // per classification workgroup: entries of each list
     int64_t *pbase;                   // per-level offset into pslot / pcnt
+    int64_t pb[MAXLEV + 1];           // the same offsets, by value
     Meta *meta;
     unsigned long long *smax;         // per grid: max wave-speed sum (FP64 bits)
     double *dt, *t;                   // per grid (batch) or entry 0 (hierarchy)

@@ -76,37 +76,13 @@ __device__ __forceinline__ void issued(A a, R... r)
     issued(r...);
 }
 
-// Grid table of a hierarchy in LDS.  Kernels look grids up by the level of a
-// tile they have just loaded; reading the table (at most MAXLEV grids, grid
-// index = level) into LDS at kernel start, together with the first reads of
-// the device counters, keeps those lookups off the chain of dependent global
-// loads.  A workgroup barrier must separate grid_tab_load and grid_tab.
-struct GridTab {
-    static constexpr int W = (int)(sizeof(Grid) / 4);
-    int w[MAXLEV][W];
-};
-__device__ __forceinline__ void grid_tab_load(const View &v, GridTab &s)
+// Grid `lvl` of a hierarchy when lvl may differ between lanes: a select over
+// the grids passed by value (no dynamic indexing of the argument block).
+__device__ __forceinline__ Grid grid_lane(const View &v, int lvl)
 {
-    const int n = (v.ngrid < MAXLEV ? v.ngrid : MAXLEV) * GridTab::W;
-    const int *src = reinterpret_cast<const int *>(v.grids);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s.w[i / GridTab::W][i % GridTab::W] = src[i];
-}
-// Grid i (workgroup-uniform) from the table, in scalar registers.
-__device__ __forceinline__ Grid grid_tab(const GridTab &s, int i)
-{
-    int w[GridTab::W];
-#pragma unroll
-    for (int k = 0; k < GridTab::W; ++k) w[k] = __builtin_amdgcn_readfirstlane(s.w[i][k]);
-    Grid G;
-    __builtin_memcpy(&G, w, sizeof(Grid));
-    return G;
-}
-
-// Grid i (may differ between lanes) from the table.
-__device__ __forceinline__ Grid grid_tab_lane(const GridTab &s, int i)
-{
-    Grid G;
-    __builtin_memcpy(&G, s.w[i], sizeof(Grid));
+    Grid G = v.gt[0];
+    for (int k = 1; k < MAXLEV && k < v.L; ++k)
+        if (lvl == k) G = v.gt[k];
     return G;
 }
 
@@ -189,7 +165,10 @@ __device__ __forceinline__ void ausm_plus(T g, T gi, int dn, const T *wL, const 
     const bool up = mh >= T(0);
     T wu[D + 2];
 #pragma unroll
-    for (int f = 0; f < D + 2; ++f) wu[f] = up ? wL[f] : wR[f];
+    for (int f = 0; f < D + 2; ++f) {
+        const T l = wL[f], r = wR[f];   // select values, not addresses (keeps the arrays in registers)
+        wu[f] = up ? l : r;
+    }
     const T ru = wu[0], pu = wu[D + 1];
     T K = T(0);
 #pragma unroll
@@ -514,27 +493,24 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     __shared__ T sFm[CELLS ? NV : 1][CELLS ? C::NS : 1], sFp[CELLS ? NV : 1][CELLS ? C::NS : 1];
     __shared__ uint8_t sCov[C::NE];
     __shared__ uint8_t sAct[C::NE];
-    __shared__ GridTab tab;
-    // first reads, independent of each other: counters, grid table, dt
+    // first reads, independent of each other: counters, dt
     const bool lts = lvl >= 0;
     const bool hier = v.mode == MODE_HIER;
     const int done = v.meta->done;
     const Tile *list = lts ? v.actv + v.meta->loff[LST_ACT][lvl] : v.leaf;
     const int count = lts ? v.meta->loff[LST_ACT][lvl + 1] - v.meta->loff[LST_ACT][lvl] : v.meta->nleaf;
     const double dt0 = v.dt[lts ? lvl : 0];
-    if (hier) grid_tab_load(v, tab);
     issued(list, count, dt0);
     if (done) return;
-    __syncthreads();
     const T g = (T)v.gamma;
     const T gi = (T)(1.0 / (v.gamma - 1.0));
     XcdWalk walk(count);
     int t;
     while (walk.next(count, t)) {
         const Tile tl = list[t];
-        const Grid G = hier ? grid_tab(tab, tl.grid) : v.grids[tl.grid];
+        const Grid G = hier ? v.gt[tl.grid] : v.grids[tl.grid];
         const bool hasf = G.fine >= 0;
-        const Grid GF = hasf ? grid_tab(tab, G.fine) : G;
+        const Grid GF = hasf ? v.gt[G.fine] : G;
         const int n = G.n, nb = G.nb;
         const int ox = (tl.block % nb) * B;
         const int oy = ((tl.block / nb) % nb) * B;
@@ -660,10 +636,8 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
 #pragma clang fp contract(off)
     __shared__ double lmax[4][MAXLEV];
     __shared__ unsigned long long lcnt[4];
-    __shared__ GridTab tab;
     const bool hier = v.mode == MODE_HIER;
     const int count = v.meta->nleaf;
-    if (hier) grid_tab_load(v, tab);
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     const double g = v.gamma;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -673,9 +647,9 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
     bool bad = false;
     for (int t = blockIdx.x * 4 + wave; t < count; t += gridDim.x * 4) {
         const Tile tl = v.leaf[t];
-        const Grid G = hier ? grid_tab(tab, tl.grid) : v.grids[tl.grid];
+        const Grid G = hier ? v.gt[tl.grid] : v.grids[tl.grid];
         const bool hasf = G.fine >= 0;
-        const Grid GF = hasf ? grid_tab(tab, G.fine) : G;
+        const Grid GF = hasf ? v.gt[G.fine] : G;
         const int n = G.n, nb = G.nb;
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
@@ -898,21 +872,18 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev)
 {
     constexpr int NV = 4;
-    __shared__ GridTab tab;
     // first reads, independent of each other
     const int done = v.meta->done;
     const int off = v.meta->loff[LST_COV][lvl];
     const int count = v.meta->loff[LST_COV][lvl + nlev] - off;
-    grid_tab_load(v, tab);
     issued(off, count);
     if (done) return;
-    __syncthreads();
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const Tile tl = v.cov[off + t];
-        const Grid G = grid_tab(tab, tl.grid);
-        const Grid F1 = grid_tab(tab, tl.grid + 1);
+        const Grid G = v.gt[tl.grid];
+        const Grid F1 = v.gt[tl.grid + 1];
         const bool two = nlev == 2 && tl.grid == lvl;   // through the children's children
-        const Grid F2 = two ? grid_tab(tab, tl.grid + 2) : F1;
+        const Grid F2 = two ? v.gt[tl.grid + 2] : F1;
         const int nb = G.nb;
         const int x = (tl.block % nb) * BS + threadIdx.x % BS;
         const int y = ((tl.block / nb) % nb) * BS + threadIdx.x / BS;
@@ -925,7 +896,7 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 ch[f][k] = A[F1.off + f * F1.ncell + gidx(F1.n, 2 * x + (k & 1), 2 * y + (k >> 1), 0)];
-        T gc[NV][4];
+        T gc[NV][4] = {};
         if (two) {
 #pragma unroll
             for (int f = 0; f < NV; ++f)
@@ -947,7 +918,10 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
         for (int f = 0; f < NV; ++f) {
             T c[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) c[k] = gcov ? gc[f][k] : ch[f][k];
+            for (int k = 0; k < 4; ++k) {
+                const T a = gc[f][k], b = ch[f][k];   // select values, not addresses
+                c[k] = gcov ? a : b;
+            }
             A[id + f * G.ncell] = T(0.25) * ((c[0] + c[1]) + (c[2] + c[3]));
         }
     }
@@ -1022,7 +996,6 @@ __device__ __forceinline__ T predict_child_t(const T *Ao, const T *An, T theta, 
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta)
 {
-    __shared__ GridTab tab;
     // first reads, independent of each other (grid index = level)
     const int done = v.meta->done;
     int off0 = 0, cnt0 = 0, off1 = 0, cnt1 = 0;   // ranges in the new and ghost lists
@@ -1036,17 +1009,8 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         cnt1 = v.meta->loff[LST_GHOST][lvl + 1] - off1;
     }
     const bool all = mode == 1;
-    Grid Gl, Cl;
-    if (all) {
-        grid_tab_load(v, tab);
-    } else {
-        Gl = v.grids[lvl];
-        Cl = v.grids[lvl - 1];
-        issued(Gl.n, Gl.nb, Gl.off, Gl.ncell, Gl.boff, Cl.n, Cl.off, Cl.ncell);
-    }
     issued(off0, cnt0, off1, cnt1);
     if (done) return;
-    if (all) __syncthreads();
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     constexpr int NV = D + 2;
     const int count = cnt0 + cnt1;
@@ -1055,8 +1019,8 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         const Tile tl = fresh ? v.fresh[off0 + t] : v.ghost[off1 + t - cnt0];
         const int lv = fresh ? tl.grid : tl.grid & ((1 << Tile::GRID_BITS) - 1);
         const uint32_t gm = fresh ? 0u : (uint32_t)tl.grid >> Tile::GRID_BITS;
-        const Grid G = all ? grid_tab(tab, lv) : Gl;
-        const Grid Cg = all ? grid_tab(tab, G.coarse) : Cl;
+        const Grid G = v.gt[all ? lv : lvl];
+        const Grid Cg = v.gt[G.coarse];
         const int nb = G.nb;
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
@@ -1207,23 +1171,21 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q, int64_t ntot)
 {
 #pragma clang fp contract(off)
-    __shared__ GridTab tab;
     const int done = v.meta->done;
-    grid_tab_load(v, tab);
-    if (done) return;
-    __syncthreads();
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ntot;
          j += (int64_t)gridDim.x * blockDim.x) {
         int lvl = 0;
-        while (lvl + 1 < v.L - 1 && j >= grid_tab_lane(tab, lvl + 1).coff) ++lvl;
-        const Grid G = grid_tab_lane(tab, lvl);
-        const Grid F = grid_tab_lane(tab, lvl + 1);
+        for (int k = 1; k < MAXLEV && k < v.L - 1; ++k) lvl += j >= v.gt[k].coff ? 1 : 0;
+        const Grid G = grid_lane(v, lvl);
+        const Grid F = grid_lane(v, lvl + 1);
         const int n = G.n;
         const int64_t i = j - G.coff;
         const int x = (int)(i % n), y = (int)((i / n) % n), z = D == 3 ? (int)(i / ((int64_t)n * n)) : 0;
         double Dm = 0.0;
         const bool act = block_active(v, v.act, G, x, y, z);
         const bool cov = covered(v.act, F, x, y, z);
+        issued((int)act, (int)cov);
+        if (done) return;   // read with the masks above: one round trip for both
         if (act && cov) {
             const T *Ac = Q + G.off;  // density field of the coarse level
             const T *Af = Q + F.off;

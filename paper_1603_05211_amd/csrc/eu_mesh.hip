@@ -101,18 +101,16 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
     __shared__ int cnt8[MAXSUB];
     __shared__ uint8_t emit8[MAXSUB];
     __shared__ int wsum[4];
-    // first reads, independent of each other (grid index = level)
+    // the flags of this workgroup's cells are computed first, their reads
+    // issued together with the read of the done flag (grids and slot
+    // offsets come with the arguments)
     const int done = v.meta->done;
     FlagGrids fg;
-    fg.G = v.grids[lvl];
-    const Grid F = v.grids[lvl + 1];
-    if (lvl >= 1) fg.C = v.grids[lvl - 1];
-    if (lvl + 2 < v.L) fg.F2 = v.grids[lvl + 2];
-    const int64_t slot = v.pbase[lvl + 1] + blockIdx.x;
-    issued(slot, fg.G.n, fg.G.coff, F.boff, F.nb);
-    if (lvl >= 1) issued(fg.C.n, fg.C.coff);
-    if (lvl + 2 < v.L) issued(fg.F2.boff, fg.F2.nb);
-    if (done) return;
+    fg.G = v.gt[lvl];
+    const Grid F = v.gt[lvl + 1];
+    if (lvl >= 1) fg.C = v.gt[lvl - 1];
+    if (lvl + 2 < v.L) fg.F2 = v.gt[lvl + 2];
+    const int64_t slot = v.pb[lvl + 1] + blockIdx.x;
     const Grid &G = fg.G;
     const int R = v.pmax / BS;
     const int nsub = D == 2 ? R * R : R * R * R;
@@ -125,18 +123,26 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
         for (int k = 0; k < bits; ++k)
             for (int d = 0; d < D; ++d) bp[d] |= ((m >> (k * D + d)) & 1) << k;
     }
+    const int hp = v.pmax / 2;
+    const int nfoot = D == 2 ? hp * hp : hp * hp * hp;   // <= 128 per thread (pmax <= 64)
+    uint32_t fm[4] = {0u, 0u, 0u, 0u};
+    for (int k = threadIdx.x, i = 0; k < nfoot; k += blockDim.x, ++i) {
+        const int lx = k % hp, ly = (k / hp) % hp, lz = D == 3 ? k / (hp * hp) : 0;
+        const int x = bp[0] * hp + lx, y = bp[1] * hp + ly, z = D == 3 ? bp[2] * hp + lz : 0;
+        if (refine_flag<D>(v, fg, lvl, x, y, z)) fm[i >> 5] |= 1u << (i & 31);
+    }
+    issued(fm[0]);
+    if (done) return;
     for (int s = threadIdx.x; s < nsub; s += blockDim.x) {
         cnt8[s] = 0;
         emit8[s] = 0;
     }
     __syncthreads();
-    const int hp = v.pmax / 2;
-    const int nfoot = D == 2 ? hp * hp : hp * hp * hp;
     int mine = 0;
-    for (int k = threadIdx.x; k < nfoot; k += blockDim.x) {
+    for (int k = threadIdx.x, i = 0; k < nfoot; k += blockDim.x, ++i) {
         const int lx = k % hp, ly = (k / hp) % hp, lz = D == 3 ? k / (hp * hp) : 0;
         const int x = bp[0] * hp + lx, y = bp[1] * hp + ly, z = D == 3 ? bp[2] * hp + lz : 0;
-        const bool fl = refine_flag<D>(v, fg, lvl, x, y, z);
+        const bool fl = (fm[i >> 5] >> (i & 31)) & 1u;
         v.flag[G.coff + gidx(G.n, x, y, z)] = fl ? 1 : 0;
         if (fl) {
             atomicAdd(&cnt8[(lx >> 2) + R * ((ly >> 2) + R * (lz >> 2))], 1);
@@ -248,10 +254,7 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
 {
     __shared__ unsigned long long part[MAXLEV][NPART];
     __shared__ int lcnt[5];
-    __shared__ GridTab tab;
     const int done = v.meta->done;
-    grid_tab_load(v, tab);
-    if (done) return;
     if (threadIdx.x < MAXLEV * NPART) part[threadIdx.x / NPART][threadIdx.x % NPART] = 0ull;
     if (threadIdx.x < 5) lcnt[threadIdx.x] = 0;
     __syncthreads();
@@ -262,8 +265,8 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
     const int64_t g0 = blockIdx.x * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
     for (int64_t gb = g0 + threadIdx.x; gb < g1; gb += blockDim.x) {
         int lvl = 0;
-        while (lvl + 1 < v.L && gb >= grid_tab_lane(tab, lvl + 1).boff) ++lvl;
-        const Grid G = grid_tab_lane(tab, lvl);
+        for (int k = 1; k < MAXLEV && k < v.L; ++k) lvl += gb >= v.gt[k].boff ? 1 : 0;
+        const Grid G = grid_lane(v, lvl);
         const int nb = G.nb;
         const int b = (int)(gb - G.boff);
         const int bx = b % nb, by = (b / nb) % nb, bz = D == 3 ? b / (nb * nb) : 0;
@@ -273,7 +276,7 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
         const uint8_t oa = v.act[gb];
         uint8_t ch[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (lvl + 1 < v.L) {
-            const Grid F = grid_tab_lane(tab, lvl + 1);
+            const Grid F = grid_lane(v, lvl + 1);
             const int zs = D == 3 ? 2 : 1;
             for (int z = 0; z < zs; ++z)
                 for (int y = 0; y < 2; ++y)
@@ -291,6 +294,8 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
                     const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
                     nbv[j++] = lvl >= 1 ? v.nact[G.boff + qx + (int64_t)nb * (qy + (int64_t)nb * qz)] : 0;
                 }
+        issued((int)na, (int)oa, (int)nbv[0]);
+        if (done) break;   // read with the masks above: one round trip for both
         const bool a = na != 0;
         const bool old = oa != 0;
         int nchild = 0;
@@ -323,6 +328,7 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
         if (code & 8) atomicAdd(&lcnt[3], 1);
         if (code & 3) atomicAdd(&lcnt[4], 1);
     }
+    if (done) return;
     __syncthreads();
     if (threadIdx.x < 5) v.wcnt[(int64_t)blockIdx.x * 5 + threadIdx.x] = lcnt[threadIdx.x];
     if (threadIdx.x < MAXLEV * NPART)
@@ -349,11 +355,16 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
     // first reads, independent of each other: the done flag, the level
     // starts and the list counts of the ranges before this one
     const int done = v.meta->done;
-    if (tid <= MAXLEV) lstart[tid] = tid < v.L ? v.grids[tid].boff : nbt;
+    if (tid <= MAXLEV) lstart[tid] = tid < v.L && tid < MAXLEV ? v.gt[tid].boff : nbt;
+    const int64_t chunk = (nbt + W - 1) / W;
+    const int64_t g0 = w * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
+    // codes of the first chunk of this range
+    const int code0 = g0 + tid < g1 ? v.code[g0 + tid] : 0;
+    const uint32_t gm0 = g0 + tid < g1 ? v.gmask[g0 + tid] : 0u;
     int acc[NL] = {0, 0, 0, 0, 0};
     for (int i = tid; i < w; i += blockDim.x)
         for (int k = 0; k < NL; ++k) acc[k] += v.wcnt[(int64_t)i * 5 + k];
-    issued(acc[0], acc[1], acc[2], acc[3], acc[4]);
+    issued(acc[0], acc[1], acc[2], acc[3], acc[4], code0, gm0);
     if (done) return;
     for (int k = 0; k < NL; ++k)
         for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
@@ -367,15 +378,13 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
     }
     __syncthreads();
     Tile *lists[NL] = {v.leaf, v.cov, v.ghost, v.fresh, v.actv};
-    const int64_t chunk = (nbt + W - 1) / W;
-    const int64_t g0 = w * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
     for (int64_t c = g0; c < g1; c += blockDim.x) {
         const int64_t gb = c + tid;
         int code = 0, lvl = 0;
         uint32_t gm = 0;
         if (gb < g1) {
-            code = v.code[gb] & 15;
-            gm = v.gmask[gb];
+            code = (c == g0 ? code0 : v.code[gb]) & 15;
+            gm = c == g0 ? gm0 : v.gmask[gb];
             if (code & 3) code |= 16;  // bit 4: in a patch
             while (gb >= lstart[lvl + 1]) ++lvl;
         }
@@ -452,7 +461,10 @@ __global__ void __launch_bounds__(256) k_cfl_final(View v, int nblk)
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
         const double *P = v.partial + (int64_t)b * CFL_STRIDE;
 #pragma unroll
-        for (int l = 0; l < MAXLEV; ++l) m[l] = P[l] > m[l] ? P[l] : m[l];
+        for (int l = 0; l < MAXLEV; ++l) {
+            const double q = P[l];
+            m[l] = q > m[l] ? q : m[l];
+        }
         cnt = cnt + P[MAXLEV];
     }
 #pragma unroll
