@@ -76,6 +76,34 @@ __device__ __forceinline__ void issued(A a, R... r)
     issued(r...);
 }
 
+// Grid table of a hierarchy in LDS, for kernels that look a grid up by the
+// level of a tile they have just loaded: reading the table (at most MAXLEV
+// grids, grid index = level) into LDS at kernel start, alongside the first
+// reads of the device counters, keeps those lookups off the chain of
+// dependent memory reads (an argument-block read at a tile-dependent offset
+// is one more such read).  A workgroup barrier must separate grid_tab_load
+// and grid_tab.
+struct GridTab {
+    static constexpr int W = (int)(sizeof(Grid) / 4);
+    int w[MAXLEV][W];
+};
+__device__ __forceinline__ void grid_tab_load(const View &v, GridTab &s)
+{
+    const int n = (v.ngrid < MAXLEV ? v.ngrid : MAXLEV) * GridTab::W;
+    const int *src = reinterpret_cast<const int *>(v.grids);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s.w[i / GridTab::W][i % GridTab::W] = src[i];
+}
+// Grid i (workgroup-uniform) from the table, in scalar registers.
+__device__ __forceinline__ Grid grid_tab(const GridTab &s, int i)
+{
+    int w[GridTab::W];
+#pragma unroll
+    for (int k = 0; k < GridTab::W; ++k) w[k] = __builtin_amdgcn_readfirstlane(s.w[i][k]);
+    Grid G;
+    __builtin_memcpy(&G, w, sizeof(Grid));
+    return G;
+}
+
 // Grid `lvl` of a hierarchy when lvl may differ between lanes: a select over
 // the grids passed by value (no dynamic indexing of the argument block).
 __device__ __forceinline__ Grid grid_lane(const View &v, int lvl)
@@ -493,24 +521,27 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     __shared__ T sFm[CELLS ? NV : 1][CELLS ? C::NS : 1], sFp[CELLS ? NV : 1][CELLS ? C::NS : 1];
     __shared__ uint8_t sCov[C::NE];
     __shared__ uint8_t sAct[C::NE];
-    // first reads, independent of each other: counters, dt
+    __shared__ GridTab tab;
+    // first reads, independent of each other: counters, grid table, dt
     const bool lts = lvl >= 0;
     const bool hier = v.mode == MODE_HIER;
     const int done = v.meta->done;
     const Tile *list = lts ? v.actv + v.meta->loff[LST_ACT][lvl] : v.leaf;
     const int count = lts ? v.meta->loff[LST_ACT][lvl + 1] - v.meta->loff[LST_ACT][lvl] : v.meta->nleaf;
     const double dt0 = v.dt[lts ? lvl : 0];
+    if (hier) grid_tab_load(v, tab);
     issued(list, count, dt0);
     if (done) return;
+    __syncthreads();
     const T g = (T)v.gamma;
     const T gi = (T)(1.0 / (v.gamma - 1.0));
     XcdWalk walk(count);
     int t;
     while (walk.next(count, t)) {
         const Tile tl = list[t];
-        const Grid G = hier ? v.gt[tl.grid] : v.grids[tl.grid];
+        const Grid G = hier ? grid_tab(tab, tl.grid) : v.grids[tl.grid];
         const bool hasf = G.fine >= 0;
-        const Grid GF = hasf ? v.gt[G.fine] : G;
+        const Grid GF = hasf ? grid_tab(tab, G.fine) : G;
         const int n = G.n, nb = G.nb;
         const int ox = (tl.block % nb) * B;
         const int oy = ((tl.block / nb) % nb) * B;
@@ -636,8 +667,10 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
 #pragma clang fp contract(off)
     __shared__ double lmax[4][MAXLEV];
     __shared__ unsigned long long lcnt[4];
+    __shared__ GridTab tab;
     const bool hier = v.mode == MODE_HIER;
     const int count = v.meta->nleaf;
+    if (hier) grid_tab_load(v, tab);
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     const double g = v.gamma;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -647,9 +680,9 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
     bool bad = false;
     for (int t = blockIdx.x * 4 + wave; t < count; t += gridDim.x * 4) {
         const Tile tl = v.leaf[t];
-        const Grid G = hier ? v.gt[tl.grid] : v.grids[tl.grid];
+        const Grid G = hier ? grid_tab(tab, tl.grid) : v.grids[tl.grid];
         const bool hasf = G.fine >= 0;
-        const Grid GF = hasf ? v.gt[G.fine] : G;
+        const Grid GF = hasf ? grid_tab(tab, G.fine) : G;
         const int n = G.n, nb = G.nb;
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
@@ -872,18 +905,21 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev)
 {
     constexpr int NV = 4;
+    __shared__ GridTab tab;
     // first reads, independent of each other
     const int done = v.meta->done;
     const int off = v.meta->loff[LST_COV][lvl];
     const int count = v.meta->loff[LST_COV][lvl + nlev] - off;
+    grid_tab_load(v, tab);
     issued(off, count);
     if (done) return;
+    __syncthreads();
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const Tile tl = v.cov[off + t];
-        const Grid G = v.gt[tl.grid];
-        const Grid F1 = v.gt[tl.grid + 1];
+        const Grid G = grid_tab(tab, tl.grid);
+        const Grid F1 = grid_tab(tab, tl.grid + 1);
         const bool two = nlev == 2 && tl.grid == lvl;   // through the children's children
-        const Grid F2 = two ? v.gt[tl.grid + 2] : F1;
+        const Grid F2 = two ? grid_tab(tab, tl.grid + 2) : F1;
         const int nb = G.nb;
         const int x = (tl.block % nb) * BS + threadIdx.x % BS;
         const int y = ((tl.block / nb) % nb) * BS + threadIdx.x / BS;
@@ -996,6 +1032,7 @@ __device__ __forceinline__ T predict_child_t(const T *Ao, const T *An, T theta, 
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta)
 {
+    __shared__ GridTab tab;
     // first reads, independent of each other (grid index = level)
     const int done = v.meta->done;
     int off0 = 0, cnt0 = 0, off1 = 0, cnt1 = 0;   // ranges in the new and ghost lists
@@ -1009,8 +1046,11 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         cnt1 = v.meta->loff[LST_GHOST][lvl + 1] - off1;
     }
     const bool all = mode == 1;
+    if (all) grid_tab_load(v, tab);
+    const Grid Gl = v.gt[all ? 0 : lvl], Cl = v.gt[all ? 0 : lvl - 1];
     issued(off0, cnt0, off1, cnt1);
     if (done) return;
+    if (all) __syncthreads();
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     constexpr int NV = D + 2;
     const int count = cnt0 + cnt1;
@@ -1019,8 +1059,8 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         const Tile tl = fresh ? v.fresh[off0 + t] : v.ghost[off1 + t - cnt0];
         const int lv = fresh ? tl.grid : tl.grid & ((1 << Tile::GRID_BITS) - 1);
         const uint32_t gm = fresh ? 0u : (uint32_t)tl.grid >> Tile::GRID_BITS;
-        const Grid G = v.gt[all ? lv : lvl];
-        const Grid Cg = v.gt[G.coarse];
+        const Grid G = all ? grid_tab(tab, lv) : Gl;
+        const Grid Cg = all ? grid_tab(tab, G.coarse) : Cl;
         const int nb = G.nb;
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
