@@ -91,7 +91,7 @@ __device__ __forceinline__ bool refine_flag(const View &v, const FlagGrids &fg, 
 // aligned pmax block of level lvl+1 (Morton index = blockIdx.x).  The
 // workgroup flags the block's coarse footprint, counts flags per BS-block in
 // LDS, sums them over the nodes of the split tree, and every lane decides for
-// one BS-block which node of the recursive split (Sec. 2.3) holds it; patches
+// one BS-block which node of the recursive split (Sec. 2.2) holds it; patches
 // come out in the order of a depth-first recursion over children (x fastest).
 // ----------------------------------------------------------------------------
 template <int D>
