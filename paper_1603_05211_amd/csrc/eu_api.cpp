@@ -112,6 +112,11 @@ int validate(const eu_config *c, std::string &why)
                 why = "instance sides must be positive multiples of 8";
                 return EU_EINVAL;
             }
+        for (int i = 0; i < c->n_instances; ++i)
+            if (std::pow((double)c->inst_side_host[i], c->dim) >= 2147483648.0) {
+                why = "every instance must have fewer than 2^31 cells";
+                return EU_EINVAL;
+            }
         return EU_OK;
     }
     if (c->n_instances < 0) { why = "bad n_instances"; return EU_EINVAL; }
@@ -128,6 +133,11 @@ int validate(const eu_config *c, std::string &why)
         if (!(c->eps >= 0.0)) { why = "eps must be >= 0"; return EU_EINVAL; }
     }
     if (c->bc == EU_BC_PERIODIC && c->n0 < 4) { why = "periodic grids need n0 >= 4"; return EU_EINVAL; }
+    // every grid must have fewer than 2^31 cells (32-bit cell indices)
+    if (c->levels >= 1 && c->n0 > 0) {
+        const double nf = (double)c->n0 * (double)(1LL << (c->levels - 1));
+        if (std::pow(nf, c->dim) >= 2147483648.0) { why = "the finest grid must have fewer than 2^31 cells"; return EU_EINVAL; }
+    }
     return EU_OK;
 }
 

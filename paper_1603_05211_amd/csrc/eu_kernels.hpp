@@ -38,6 +38,14 @@ __device__ __forceinline__ int64_t gidx(int n, int x, int y, int z)
     return x + (int64_t)n * (y + (int64_t)n * z);
 }
 
+// The same index in 32 bits (every grid has fewer than 2^31 cells; the
+// library checks this at creation): with a per-field base pointer held in
+// scalar registers the address is one 32-bit offset.
+__device__ __forceinline__ uint32_t gidx32(int n, int x, int y, int z)
+{
+    return (uint32_t)x + (uint32_t)n * ((uint32_t)y + (uint32_t)n * (uint32_t)z);
+}
+
 // XCD-aware assignment of list items to workgroups.  Workgroups are
 // dispatched to the 8 XCDs round robin (blockIdx % 8), each XCD with its own
 // L2; XCD x walks the contiguous x-th eighth of the list, its workgroups
@@ -329,14 +337,14 @@ __device__ __forceinline__ T restrict_cell(const T *Af, int nf, int px, int py, 
 __device__ __forceinline__ bool block_active(const View &v, const uint8_t *mask, const Grid &G,
                                              int x, int y, int z)
 {
-    return mask[G.boff + (x >> 3) + (int64_t)G.nb * ((y >> 3) + (int64_t)G.nb * (z >> 3))] != 0;
+    return mask[G.boff + (int64_t)gidx32(G.nb, x >> 3, y >> 3, z >> 3)] != 0;
 }
 
 // covered: the children of cell (x, y, z) belong to a patch of the finer
 // grid F (the caller checks that the cell's grid has one).
 __device__ __forceinline__ bool covered(const uint8_t *mask, const Grid &F, int x, int y, int z)
 {
-    return mask[F.boff + (x >> 2) + (int64_t)F.nb * ((y >> 2) + (int64_t)F.nb * (z >> 2))] != 0;
+    return mask[F.boff + (int64_t)gidx32(F.nb, x >> 2, y >> 2, z >> 2)] != 0;
 }
 
 // ----------------------------------------------------------------------------
@@ -553,7 +561,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             const int x = bcmap(ox + lx - H, n, v.bc);
             const int y = bcmap(oy + ly - H, n, v.bc);
             const int z = D == 3 ? bcmap(oz + lz - H, n, v.bc) : 0;
-            const int64_t id = gidx(n, x, y, z);
+            const int64_t id = gidx32(n, x, y, z);
             T q[NV], w[NV];
 #pragma unroll
             for (int f = 0; f < NV; ++f) q[f] = S[f * N + id];
@@ -572,7 +580,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             const int c = threadIdx.x + k * NT;
             if (c >= C::TC) break;
             const int x = c % B, y = (c / B) % B, z = c / (B * B);
-            const int64_t id = G.off + gidx(n, ox + x, oy + y, oz + z);
+            const int64_t id = G.off + (int64_t)gidx32(n, ox + x, oy + y, oz + z);
 #pragma unroll
             for (int f = 0; f < NV; ++f) qb[k][f] = base[f * N + id];
         }
@@ -646,7 +654,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             const int x = c % B, y = (c / B) % B, z = c / (B * B);
             const int h = (x + H) + E * ((y + H) + (D == 3 ? E * (z + H) : 0));
             if (!lts && sCov[h]) continue;
-            const int64_t id = G.off + gidx(n, ox + x, oy + y, oz + z);
+            const int64_t id = G.off + (int64_t)gidx32(n, ox + x, oy + y, oz + z);
 #pragma unroll
             for (int f = 0; f < NV; ++f) out[f * N + id] = qb[k][f] - lam * R[k][f];
         }

@@ -61,10 +61,17 @@ def test_query_sizes_dense_levels():
     dict(dim=4), dict(precision=7), dict(gamma=1.0), dict(hi=0.0), dict(n0=24), dict(n0=4),
     dict(levels=0), dict(levels=11), dict(patch_min=16), dict(patch_max=48), dict(eta=0.0),
     dict(eps=-1.0), dict(cfl=0.0), dict(bc=5), dict(time_mode=3), dict(n0=8, patch_max=32),
+    # 32-bit cell indices: 2048^3 finest cells are too many, 1024^3 are not
+    dict(dim=3, n0=1024, levels=2, lo=-1.0), dict(dim=2, n0=65536, levels=1),
 ])
 def test_invalid_configurations_rejected(bad):
     r, _, _ = sizes(cfg(**bad))
     assert r == _abi.EU_EINVAL
+
+
+def test_largest_grids_accepted():
+    assert sizes(cfg(dim=3, n0=512, levels=2, lo=-1.0))[0] == _abi.EU_OK      # 1024^3 finest
+    assert sizes(cfg(dim=2, n0=32768, levels=1))[0] == _abi.EU_OK
 
 
 def test_batch_sizes():
