@@ -454,48 +454,38 @@ __global__ void __launch_bounds__(256) k_cfl_final(View v, int nblk)
     __shared__ double smax[4][MAXLEV];
     __shared__ double scnt[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // the commit's reads are issued with the partials' (thread 0 uses them)
     const double t = v.t[0];
-    const int steps = v.meta->steps;
-    const long long upd0 = v.meta->leaf_updates;
     // per-level maxima and the leaf count over the workgroups' partials
-    // (levels 0 .. L-1 only)
     double m[MAXLEV], cnt = 0.0;
-#pragma unroll
     for (int l = 0; l < MAXLEV; ++l) m[l] = 0.0;
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
         const double *P = v.partial + (int64_t)b * CFL_STRIDE;
 #pragma unroll
-        for (int l = 0; l < MAXLEV; ++l)
-            if (l < v.L) {
-                const double q = P[l];
-                m[l] = q > m[l] ? q : m[l];
-            }
+        for (int l = 0; l < MAXLEV; ++l) {
+            const double q = P[l];
+            m[l] = q > m[l] ? q : m[l];
+        }
         cnt = cnt + P[MAXLEV];
     }
 #pragma unroll
     for (int l = 0; l < MAXLEV; ++l)
-        if (l < v.L)
-            for (int o = 32; o > 0; o >>= 1) {
-                const double r = __shfl_xor(m[l], o);
-                m[l] = r > m[l] ? r : m[l];
-            }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double r = __shfl_xor(m[l], o);
+            m[l] = r > m[l] ? r : m[l];
+        }
     for (int o = 32; o > 0; o >>= 1) cnt = cnt + __shfl_xor(cnt, o);
     if (lane == 0) {
-#pragma unroll
         for (int l = 0; l < MAXLEV; ++l) smax[wave][l] = m[l];
         scnt[wave] = cnt;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
     double dt = __builtin_inf();
-#pragma unroll
-    for (int l = 0; l < MAXLEV; ++l) {
-        if (l >= v.L) break;
+    for (int l = 0; l < v.ngrid; ++l) {
         double sm = smax[0][l];
         for (int w = 1; w < 4; ++w) sm = smax[w][l] > sm ? smax[w][l] : sm;
         if (sm > 0.0) {
-            double d = (v.cfl * v.gt[l].dx) / sm;
+            double d = (v.cfl * v.grids[l].dx) / sm;
             if (v.lts) d = d * (double)(1 << l);
             if (d < dt) dt = d;
         }
@@ -505,7 +495,7 @@ __global__ void __launch_bounds__(256) k_cfl_final(View v, int nblk)
     if (dt > v.t_end - t) dt = v.t_end - t;
     if (v.lts) {
         double dl = dt;
-        for (int l = 0; l < v.L; ++l) {
+        for (int l = 0; l < v.ngrid; ++l) {
             v.dt[l] = dl;
             dl = dl * 0.5;
         }
@@ -515,8 +505,8 @@ __global__ void __launch_bounds__(256) k_cfl_final(View v, int nblk)
     v.meta->done = done;
     if (!done) {
         v.t[0] = t + dt;
-        v.meta->steps = steps + 1;
-        v.meta->leaf_updates = upd0 + upd;
+        v.meta->steps += 1;
+        v.meta->leaf_updates += upd;
     }
 }
 
