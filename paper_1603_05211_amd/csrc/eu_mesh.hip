@@ -7,86 +7,6 @@
 namespace eu {
 
 // ----------------------------------------------------------------------------
-// refinement flag of level-lvl cell (x, y, z): it decides whether the cell's
-// children belong to level lvl+1 of the new hierarchy
-// ----------------------------------------------------------------------------
-// Distinct blocks (block side 8 at level side n) touched by cells
-// c + lo .. c + hi through the boundary map; at most 3 for hi - lo <= 5 at
-// half resolution, returned in out[], count returned.
-__device__ __forceinline__ int distinct_blocks(int c0, int lo, int hi, int n, int bc, int shift, int *out)
-{
-    int k = 0;
-    for (int o = lo; o <= hi; ++o) {
-        const int b = bcmap(c0 + o, n, bc) >> shift;
-        bool seen = false;
-        for (int j = 0; j < k; ++j) seen |= out[j] == b;
-        if (!seen) out[k++] = b;
-    }
-    return k;
-}
-
-// Grids of the levels around level lvl that the flag of a level-lvl cell
-// reads (grid index = level): lvl-1 (when lvl >= 1), lvl and lvl+2 (when
-// lvl+2 < L).
-struct FlagGrids {
-    Grid C, G, F2;
-};
-
-template <int D>
-__device__ __forceinline__ bool refine_flag(const View &v, const FlagGrids &fg, int lvl, int x, int y, int z)
-{
-    const Grid &G = fg.G;
-    const int n = G.n;
-    constexpr int R3 = D == 3 ? 1 : 0;
-    constexpr int NN = D == 3 ? 27 : 9;
-    // raw flags (significant details; preventive refinement of the children
-    // of significant cells), dilated by one cell
-    uint8_t s[NN], sp[NN];
-    int k = 0;
-#pragma unroll
-    for (int dz = -R3; dz <= R3; ++dz)
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int qx = bcmap(x + dx, n, v.bc), qy = bcmap(y + dy, n, v.bc);
-                const int qz = D == 3 ? bcmap(z + dz, n, v.bc) : 0;
-                s[k] = v.sig[G.coff + gidx(n, qx, qy, qz)];
-                sp[k] = lvl >= 1 ? v.sig[fg.C.coff + gidx(fg.C.n, qx >> 1, qy >> 1, qz >> 1)] : 0;
-                ++k;
-            }
-    // nesting: level-(lvl+1) cells within two cells of a level-(lvl+1) cell
-    // covered by the new level lvl+2; cells 2x-2 .. 2x+3 of level lvl+1 lie
-    // in at most three blocks of level lvl+2 per axis.  Read together with
-    // the flags above.
-    uint8_t a[27];
-    if (lvl + 2 < v.L) {
-        const Grid &F2 = fg.F2;
-        const int nf = 2 * n;
-        int bx[3], by[3], bz[3] = {0, 0, 0};
-        const int nx = distinct_blocks(2 * x, -2, 3, nf, v.bc, 2, bx);
-        const int ny = distinct_blocks(2 * y, -2, 3, nf, v.bc, 2, by);
-        const int nz = D == 3 ? distinct_blocks(2 * z, -2, 3, nf, v.bc, 2, bz) : 1;
-        int j = 0;
-        for (int kz = 0; kz < 3; ++kz)
-            for (int ky = 0; ky < 3; ++ky)
-                for (int kx = 0; kx < 3; ++kx) {
-                    a[j] = (kx < nx && ky < ny && kz < nz)
-                               ? v.nact[F2.boff + bx[kx] + (int64_t)F2.nb * (by[ky] + (int64_t)F2.nb * bz[kz])]
-                               : 0;
-                    ++j;
-                }
-    } else {
-        for (int j = 0; j < 27; ++j) a[j] = 0;
-    }
-    int any = 0;
-#pragma unroll
-    for (int j = 0; j < NN; ++j) any |= s[j] | sp[j];
-    for (int i = 0; i < 27; ++i) any |= a[i];
-    return any != 0;
-}
-
-// ----------------------------------------------------------------------------
 // flags of level lvl + tiling into patches of level lvl+1: one workgroup per
 // aligned pmax block of level lvl+1 (Morton index = blockIdx.x).  The
 // workgroup flags the block's coarse footprint, counts flags per BS-block in
@@ -101,17 +21,23 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
     __shared__ int cnt8[MAXSUB];
     __shared__ uint8_t emit8[MAXSUB];
     __shared__ int wsum[4];
-    // the flags of this workgroup's cells are computed first, their reads
-    // issued together with the read of the done flag (grids and slot
-    // offsets come with the arguments)
+    // LDS staging of what the flags of the footprint read: the raw flags
+    // (significant detail of the cell or of its parent) over the footprint
+    // and a one-cell halo, and the new patch masks of level lvl+2 over the
+    // blocks the nesting test reaches (virtual block indices; the boundary
+    // map is applied when staging: clamping or wrapping a block index is the
+    // same as mapping the cells and dividing)
+    constexpr int HM = 32 + 2;                             // footprint side + halo, pmax <= 64
+    constexpr int VM = 32 / 2 + 3;                         // nesting blocks per side
+    __shared__ uint8_t sraw[D == 2 ? HM * HM : HM * HM * HM];
+    __shared__ uint8_t snest[D == 2 ? VM * VM : VM * VM * VM];
     const int done = v.meta->done;
-    FlagGrids fg;
-    fg.G = v.gt[lvl];
+    const Grid G = v.gt[lvl];
     const Grid F = v.gt[lvl + 1];
-    if (lvl >= 1) fg.C = v.gt[lvl - 1];
-    if (lvl + 2 < v.L) fg.F2 = v.gt[lvl + 2];
+    const bool hasc = lvl >= 1, nest = lvl + 2 < v.L;
+    const Grid Cg = v.gt[hasc ? lvl - 1 : lvl];
+    const Grid F2 = v.gt[nest ? lvl + 2 : lvl];
     const int64_t slot = v.pb[lvl + 1] + blockIdx.x;
-    const Grid &G = fg.G;
     const int R = v.pmax / BS;
     const int nsub = D == 2 ? R * R : R * R * R;
     const int m = blockIdx.x;
@@ -123,27 +49,64 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
         for (int k = 0; k < bits; ++k)
             for (int d = 0; d < D; ++d) bp[d] |= ((m >> (k * D + d)) & 1) << k;
     }
-    const int hp = v.pmax / 2;
-    const int nfoot = D == 2 ? hp * hp : hp * hp * hp;   // <= 128 per thread (pmax <= 64)
-    uint32_t fm[4] = {0u, 0u, 0u, 0u};
-    for (int k = threadIdx.x, i = 0; k < nfoot; k += blockDim.x, ++i) {
-        const int lx = k % hp, ly = (k / hp) % hp, lz = D == 3 ? k / (hp * hp) : 0;
-        const int x = bp[0] * hp + lx, y = bp[1] * hp + ly, z = D == 3 ? bp[2] * hp + lz : 0;
-        if (refine_flag<D>(v, fg, lvl, x, y, z)) fm[i >> 5] |= 1u << (i & 31);
+    const int hp = v.pmax / 2, he = hp + 2, n = G.n;
+    const int o0[3] = {bp[0] * hp, bp[1] * hp, D == 3 ? bp[2] * hp : 0};
+    const int nraw = D == 2 ? he * he : he * he * he;
+    for (int i = threadIdx.x; i < nraw; i += blockDim.x) {
+        const int ex = i % he, ey = (i / he) % he, ez = D == 3 ? i / (he * he) : 0;
+        const int qx = bcmap(o0[0] - 1 + ex, n, v.bc), qy = bcmap(o0[1] - 1 + ey, n, v.bc);
+        const int qz = D == 3 ? bcmap(o0[2] - 1 + ez, n, v.bc) : 0;
+        const uint8_t a = v.sig[G.coff + gidx(n, qx, qy, qz)];
+        const uint8_t b = hasc ? v.sig[Cg.coff + gidx(Cg.n, qx >> 1, qy >> 1, qz >> 1)] : 0;
+        sraw[i] = a | b;
     }
-    issued(fm[0]);
+    // level-(lvl+1) cells 2x-2 .. 2x+3 of the footprint's x lie in virtual
+    // level-(lvl+2) blocks (2x-2)>>2 .. (2x+3)>>2
+    int vb0[3] = {0, 0, 0}, nvb = 1;
+    if (nest) {
+        for (int d = 0; d < D; ++d) vb0[d] = (2 * o0[d] - 2) >> 2;
+        nvb = ((2 * (o0[0] + hp - 1) + 3) >> 2) - vb0[0] + 1;
+        const int nb2 = F2.nb, tot = D == 2 ? nvb * nvb : nvb * nvb * nvb;
+        for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+            int b[3] = {i % nvb, (i / nvb) % nvb, D == 3 ? i / (nvb * nvb) : 0};
+            for (int d = 0; d < D; ++d) {
+                const int q = vb0[d] + b[d];
+                b[d] = v.bc == 1 ? (q < 0 ? q + nb2 : q >= nb2 ? q - nb2 : q) : (q < 0 ? 0 : q >= nb2 ? nb2 - 1 : q);
+            }
+            snest[i] = v.nact[F2.boff + b[0] + (int64_t)nb2 * (b[1] + (int64_t)nb2 * b[2])];
+        }
+    }
     if (done) return;
     for (int s = threadIdx.x; s < nsub; s += blockDim.x) {
         cnt8[s] = 0;
         emit8[s] = 0;
     }
     __syncthreads();
+    // flag of each footprint cell: raw flags dilated by one cell, or the
+    // nesting closure (a level-(lvl+1) cell within two cells of the new level
+    // lvl+2)
+    const int nfoot = D == 2 ? hp * hp : hp * hp * hp;
     int mine = 0;
-    for (int k = threadIdx.x, i = 0; k < nfoot; k += blockDim.x, ++i) {
+    for (int k = threadIdx.x; k < nfoot; k += blockDim.x) {
         const int lx = k % hp, ly = (k / hp) % hp, lz = D == 3 ? k / (hp * hp) : 0;
-        const int x = bp[0] * hp + lx, y = bp[1] * hp + ly, z = D == 3 ? bp[2] * hp + lz : 0;
-        const bool fl = (fm[i >> 5] >> (i & 31)) & 1u;
-        v.flag[G.coff + gidx(G.n, x, y, z)] = fl ? 1 : 0;
+        int any = 0;
+        for (int dz = (D == 3 ? 0 : 1); dz <= (D == 3 ? 2 : 1); ++dz)
+            for (int dy = 0; dy <= 2; ++dy)
+                for (int dx = 0; dx <= 2; ++dx)
+                    any |= sraw[(lx + dx) + he * ((ly + dy) + (D == 3 ? he * (lz + dz) : 0))];
+        if (nest && !any) {
+            const int c[3] = {o0[0] + lx, o0[1] + ly, o0[2] + lz};
+            int lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = d < D ? ((2 * c[d] - 2) >> 2) - vb0[d] : 0;
+                hi[d] = d < D ? ((2 * c[d] + 3) >> 2) - vb0[d] : 0;
+            }
+            for (int bz = lo[2]; bz <= hi[2]; ++bz)
+                for (int by = lo[1]; by <= hi[1]; ++by)
+                    for (int bx = lo[0]; bx <= hi[0]; ++bx) any |= snest[bx + nvb * (by + nvb * bz)];
+        }
+        const bool fl = any != 0;
+        v.flag[G.coff + gidx(n, o0[0] + lx, o0[1] + ly, o0[2] + lz)] = fl ? 1 : 0;
         if (fl) {
             atomicAdd(&cnt8[(lx >> 2) + R * ((ly >> 2) + R * (lz >> 2))], 1);
             ++mine;
