@@ -11,7 +11,7 @@ constexpr int BS = 8;          // block side in cells: the unit of patches and t
 constexpr int MAXLEV = 10;
 constexpr int NPART = 2;       // classification partial sums per level
 constexpr int CFL_STRIDE = MAXLEV + 1;   // CFL partials per workgroup: level maxima, leaf count
-constexpr int CFL_MAXBLK = 512;          // workgroups of the CFL reduction
+constexpr int CFL_MAXBLK = 2048;         // workgroups of the CFL reduction (at most)
 
 // One dense grid: a level of the hierarchy, the single uniform grid, or one
 // instance of a batch.  Field f of cell (x, y, z) lives at

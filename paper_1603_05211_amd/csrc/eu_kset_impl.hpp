@@ -119,7 +119,8 @@ template <typename T> void cfl(const View &v, int maxt, hipStream_t s)
 {
     // one wave per tile (up to CFL_MAXBLK workgroups), then one workgroup
     // turns the partial maxima into dt
-    const int nblk = clamp_grid((maxt + 3) / 4, CFL_MAXBLK);
+    // (2D tiles are light: fewer workgroups keep the finishing kernel short)
+    const int nblk = clamp_grid((maxt + 3) / 4, v.dim == 2 ? 512 : CFL_MAXBLK);
     if (v.dim == 2) k_cfl<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     launch_cfl_final(v, nblk, s);
