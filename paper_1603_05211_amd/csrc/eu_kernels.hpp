@@ -993,41 +993,33 @@ __device__ __forceinline__ bool ghost_cell(uint32_t gm, int x, int y, int z)
     return hit;
 }
 
-// Third-order prediction of child (cx, cy, cz) of coarse cell p from the
-// linear time interpolation (1 - theta) Ao + theta An of the coarse field.
+// Third-order prediction of child (cx, cy, cz) of the coarse cell at local
+// position (px, py, pz) (1..4) of a staged 6^D region of one field (the
+// coarse cells around a block's parents, boundary map already applied);
+// the same separable x, y, z order as predict_child.
 template <typename T, int D>
-__device__ __forceinline__ T predict_child_t(const T *Ao, const T *An, T theta, int n, int bc, int px,
-                                             int py, int pz, int cx, int cy, int cz)
+__device__ __forceinline__ T predict_child_lds(const T *S, int px, int py, int pz, int cx, int cy, int cz)
 {
-    int xs[3], ys[3], zs[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        xs[k] = bcmap(px + k - 1, n, bc);
-        ys[k] = bcmap(py + k - 1, n, bc);
-        zs[k] = D == 3 ? bcmap(pz + k - 1, n, bc) : 0;
-    }
-    const T om = T(1) - theta;
-    auto at = [&](int x, int y, int z) {
-        const int64_t i = gidx(n, x, y, z);
-        return om * Ao[i] + theta * An[i];
-    };
+    constexpr int W = BS / 2 + 2;
+    auto at = [&](int x, int y, int z) { return S[x + W * (y + W * z)]; };
     if (D == 2) {
         T r[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            r[j] = pred1<T>(at(xs[0], ys[j], 0), at(xs[1], ys[j], 0), at(xs[2], ys[j], 0), cx);
+            r[j] = pred1<T>(at(px - 1, py + j - 1, 0), at(px, py + j - 1, 0), at(px + 1, py + j - 1, 0), cx);
         return pred1<T>(r[0], r[1], r[2], cy);
     }
-    T s[3];
+    T sz[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         T r[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            r[j] = pred1<T>(at(xs[0], ys[j], zs[k]), at(xs[1], ys[j], zs[k]), at(xs[2], ys[j], zs[k]), cx);
-        s[k] = pred1<T>(r[0], r[1], r[2], cy);
+            r[j] = pred1<T>(at(px - 1, py + j - 1, pz + k - 1), at(px, py + j - 1, pz + k - 1),
+                            at(px + 1, py + j - 1, pz + k - 1), cx);
+        sz[k] = pred1<T>(r[0], r[1], r[2], cy);
     }
-    return pred1<T>(s[0], s[1], s[2], cz);
+    return pred1<T>(sz[0], sz[1], sz[2], cz);
 }
 
 // Prediction from the next coarser level into array A:
@@ -1040,7 +1032,9 @@ __device__ __forceinline__ T predict_child_t(const T *Ao, const T *An, T theta, 
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta)
 {
+    constexpr int W = BS / 2 + 2, NS = D == 2 ? W * W : W * W * W;
     __shared__ GridTab tab;
+    __shared__ T sA[D + 2][NS];
     // first reads, independent of each other (grid index = level)
     const int done = v.meta->done;
     int off0 = 0, cnt0 = 0, off1 = 0, cnt1 = 0;   // ranges in the new and ghost lists
@@ -1073,26 +1067,37 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
         const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
+        // the coarse cells the block's predictions read (parents +-1 per
+        // axis), staged once per block; with time interpolation the staged
+        // value is the interpolated state
+        const int qx0 = (ox >> 1) - 1, qy0 = (oy >> 1) - 1, qz0 = D == 3 ? (oz >> 1) - 1 : 0;
+        for (int i = threadIdx.x; i < NS; i += blockDim.x) {
+            const int sx = i % W, sy = (i / W) % W, sz = D == 3 ? i / (W * W) : 0;
+            const int64_t ic = Cg.off + gidx(Cg.n, bcmap(qx0 + sx, Cg.n, v.bc), bcmap(qy0 + sy, Cg.n, v.bc),
+                                             D == 3 ? bcmap(qz0 + sz, Cg.n, v.bc) : 0);
+#pragma unroll
+            for (int f = 0; f < NV; ++f) {
+                if (mode == 2) {
+                    const T om = T(1) - (T)theta;
+                    sA[f][i] = om * ((const T *)v.Qo)[ic + f * Cg.ncell] + (T)theta * ((const T *)v.Q)[ic + f * Cg.ncell];
+                } else {
+                    sA[f][i] = A[ic + f * Cg.ncell];
+                }
+            }
+        }
+        __syncthreads();
         for (int c = threadIdx.x; c < TC; c += blockDim.x) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
             // every cell of a new block is predicted; in a ghost block only
             // the ghost cells
             if (!fresh && !ghost_cell<D>(gm, x, y, z)) continue;
-            T val[NV];
-#pragma unroll
-            for (int f = 0; f < NV; ++f) {
-                if (mode == 2)
-                    val[f] = predict_child_t<T, D>((const T *)v.Qo + Cg.off + f * Cg.ncell,
-                                                   (const T *)v.Q + Cg.off + f * Cg.ncell, (T)theta, Cg.n, v.bc,
-                                                   x >> 1, y >> 1, z >> 1, x & 1, y & 1, z & 1);
-                else
-                    val[f] = predict_child<T, D, T>(A + Cg.off + f * Cg.ncell, Cg.n, v.bc, x >> 1, y >> 1,
-                                                    z >> 1, x & 1, y & 1, z & 1);
-            }
+            const int px = (x >> 1) - qx0, py = (y >> 1) - qy0, pz = D == 3 ? (z >> 1) - qz0 : 0;
             const int64_t id = gidx(G.n, x, y, z);
 #pragma unroll
-            for (int f = 0; f < NV; ++f) A[G.off + f * G.ncell + id] = val[f];
+            for (int f = 0; f < NV; ++f)
+                A[G.off + f * G.ncell + id] = predict_child_lds<T, D>(sA[f], px, py, pz, x & 1, y & 1, z & 1);
         }
+        __syncthreads();
     }
 }
 
