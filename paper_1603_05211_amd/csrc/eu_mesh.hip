@@ -14,8 +14,16 @@ namespace eu {
 // one BS-block which node of the recursive split (Sec. 2.2) holds it; patches
 // come out in the order of a depth-first recursion over children (x fastest).
 // ----------------------------------------------------------------------------
+// The grids a flagging launch reads, at fixed offsets of its argument block
+// (a read of View::gt at a level-dependent offset would be one more
+// dependent read).
+struct FlagArgs {
+    Grid G, F, C, F2;   // levels lvl, lvl+1, lvl-1 (when lvl >= 1), lvl+2 (when lvl+2 < L)
+    int64_t slot0;      // first pmax-block slot of level lvl+1
+};
+
 template <int D>
-__global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
+__global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
 {
     constexpr int MAXSUB = D == 2 ? 64 : 512;       // (pmax / BS)^D, pmax <= 64
     __shared__ int cnt8[MAXSUB];
@@ -32,12 +40,9 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl)
     __shared__ uint8_t sraw[D == 2 ? HM * HM : HM * HM * HM];
     __shared__ uint8_t snest[D == 2 ? VM * VM : VM * VM * VM];
     const int done = v.meta->done;
-    const Grid G = v.gt[lvl];
-    const Grid F = v.gt[lvl + 1];
+    const Grid &G = fa.G, &F = fa.F, &Cg = fa.C, &F2 = fa.F2;
     const bool hasc = lvl >= 1, nest = lvl + 2 < v.L;
-    const Grid Cg = v.gt[hasc ? lvl - 1 : lvl];
-    const Grid F2 = v.gt[nest ? lvl + 2 : lvl];
-    const int64_t slot = v.pb[lvl + 1] + blockIdx.x;
+    const int64_t slot = fa.slot0 + blockIdx.x;
     const int R = v.pmax / BS;
     const int nsub = D == 2 ? R * R : R * R * R;
     const int m = blockIdx.x;
@@ -505,8 +510,14 @@ static inline int grid_for(int64_t n, int bs, int cap)
 
 void launch_flag_tile(const View &v, int lvl, int nblocks, hipStream_t s)
 {
-    if (v.dim == 2) k_flag_tile<2><<<nblocks, 256, 0, s>>>(v, lvl);
-    else k_flag_tile<3><<<nblocks, 256, 0, s>>>(v, lvl);
+    FlagArgs fa;
+    fa.G = v.gt[lvl];
+    fa.F = v.gt[lvl + 1];
+    fa.C = v.gt[lvl >= 1 ? lvl - 1 : lvl];
+    fa.F2 = v.gt[lvl + 2 < v.L ? lvl + 2 : lvl];
+    fa.slot0 = v.pb[lvl + 1];
+    if (v.dim == 2) k_flag_tile<2><<<nblocks, 256, 0, s>>>(v, lvl, fa);
+    else k_flag_tile<3><<<nblocks, 256, 0, s>>>(v, lvl, fa);
 }
 
 void launch_cfl_final(const View &v, int nblk, hipStream_t s)
