@@ -910,24 +910,23 @@ __global__ void __launch_bounds__(256) k_restrict_cov(View v, T *A, int lvl)
 // covered.  Every read is issued before any result is stored, and the
 // arithmetic is that of two successive one-level projections.
 template <typename T>
-__global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev)
+__global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev, Grid g0, Grid g1, Grid g2)
 {
     constexpr int NV = 4;
-    __shared__ GridTab tab;
-    // first reads, independent of each other
+    // first reads, independent of each other (the grids of levels lvl,
+    // lvl+1 and lvl+2 come at fixed argument offsets)
     const int done = v.meta->done;
     const int off = v.meta->loff[LST_COV][lvl];
     const int count = v.meta->loff[LST_COV][lvl + nlev] - off;
-    grid_tab_load(v, tab);
     issued(off, count);
     if (done) return;
-    __syncthreads();
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const Tile tl = v.cov[off + t];
-        const Grid G = grid_tab(tab, tl.grid);
-        const Grid F1 = grid_tab(tab, tl.grid + 1);
-        const bool two = nlev == 2 && tl.grid == lvl;   // through the children's children
-        const Grid F2 = two ? grid_tab(tab, tl.grid + 2) : F1;
+        const bool lo = tl.grid == lvl;
+        const Grid G = lo ? g0 : g1;
+        const Grid F1 = lo ? g1 : g2;
+        const bool two = nlev == 2 && lo;   // through the children's children
+        const Grid F2 = g2;
         const int nb = G.nb;
         const int x = (tl.block % nb) * BS + threadIdx.x % BS;
         const int y = ((tl.block / nb) % nb) * BS + threadIdx.x / BS;
@@ -1029,8 +1028,10 @@ __device__ __forceinline__ T predict_child_lds(const T *S, int px, int py, int p
 //           interpolated in time between Qo (theta = 0) and Q (theta = 1);
 //   mode 3: mode 0, then the ghost cells of level lvl, in one launch (both
 //           read level lvl-1 only, which is final by then).
+// Gl and Cl are the grids of levels lvl and lvl-1 (modes 0, 2, 3), passed at
+// fixed argument offsets.
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta)
+__global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta, Grid Gl, Grid Cl)
 {
     constexpr int W = BS / 2 + 2, NS = D == 2 ? W * W : W * W * W;
     __shared__ GridTab tab;
@@ -1049,7 +1050,6 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
     }
     const bool all = mode == 1;
     if (all) grid_tab_load(v, tab);
-    const Grid Gl = v.gt[all ? 0 : lvl], Cl = v.gt[all ? 0 : lvl - 1];
     issued(off0, cnt0, off1, cnt1);
     if (done) return;
     if (all) __syncthreads();

@@ -50,14 +50,16 @@ template <typename T> void restrict_cov(const View &v, int a, int lvl, int maxb,
 template <typename T> void restrict2(const View &v, int a, int lvl, int nlev, int maxb, hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 2048);
-    k_restrict2<T><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, nlev);
+    const Grid g0 = v.gt[lvl], g1 = v.gt[lvl + 1], g2 = v.gt[lvl + 2 < v.L ? lvl + 2 : lvl + 1];
+    k_restrict2<T><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, nlev, g0, g1, g2);
 }
 
 template <typename T> void predict(const View &v, int a, int lvl, int mode, double theta, int maxb, hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 1024);
-    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta);
-    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta);
+    const Grid Gl = v.gt[mode == 1 ? 0 : lvl], Cl = v.gt[mode == 1 ? 0 : lvl - 1];
+    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, Gl, Cl);
+    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, Gl, Cl);
 }
 
 // Stage-kernel schedules the autotuner chooses from (variant index):
