@@ -312,7 +312,7 @@ void seq_restrict(eu_ctx *c, int arr)
 
 void seq_ghost(eu_ctx *c, int arr)
 {
-    if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, 0.0, (int)(c->nbt), c->stream);
+    if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, 1, 0.0, (int)(c->nbt), c->stream);
 }
 
 void seq_cfl(eu_ctx *c) { c->ks->cfl(c->v, c->max_tiles, c->stream); }
@@ -358,8 +358,8 @@ void seq_details(eu_ctx *c)
 }
 
 // flags, closure and tiling (finest first), lists, then either the
-// prediction of new cells and ghost cells level by level (coarse to fine, one
-// launch per level) or the ghost fill alone.
+// prediction of new cells and ghost cells (coarse to fine, two levels per
+// launch) or the ghost fill alone.
 void seq_flag_tile(eu_ctx *c, bool prolong)
 {
     for (int l = c->L - 2; l >= 0; --l) {
@@ -368,7 +368,11 @@ void seq_flag_tile(eu_ctx *c, bool prolong)
     }
     launch_build_lists(c->v, c->nbt, c->stream);
     if (prolong)
-        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 3, 0.0, (int)nblocks_grid(c, l), c->stream);
+        for (int l = 1; l < c->L; l += 2) {
+            const int nlev = l + 1 < c->L ? 2 : 1;
+            c->ks->predict(c->v, ARR_Q, l, nlev, 3, 0.0,
+                           (int)(nblocks_grid(c, l) + (nlev == 2 ? nblocks_grid(c, l + 1) : 0)), c->stream);
+        }
     else
         seq_ghost(c, ARR_Q);
 }
@@ -386,14 +390,14 @@ void lts_advance(eu_ctx *c, int l, int k)
     prof_begin(c, &e);
     c->ks->fv_stage(c->v, 1, l, k, 0, nbl, c->variant, c->stream);
     prof_end(c, e);
-    if (l >= 1) c->ks->predict(c->v, ARR_QS, l, 2, (double)(2 * k + 1) * 0.25, nbl, c->stream);
+    if (l >= 1) c->ks->predict(c->v, ARR_QS, l, 1, 2, (double)(2 * k + 1) * 0.25, nbl, c->stream);
     prof_begin(c, &e);
     c->ks->fv_stage(c->v, 2, l, k, 1, nbl, c->variant, c->stream);
     prof_end(c, e);
     if (l + 1 < c->L) {
         const int nbf = (int)nblocks_grid(c, l + 1);
         for (int kk = 0; kk < 2; ++kk) {
-            c->ks->predict(c->v, ARR_Q, l + 1, 2, (double)kk * 0.5, nbf, c->stream);
+            c->ks->predict(c->v, ARR_Q, l + 1, 1, 2, (double)kk * 0.5, nbf, c->stream);
             lts_advance(c, l + 1, kk);
         }
         c->ks->restrict_cov(c->v, ARR_Q, l, nbl, c->stream);
@@ -762,7 +766,7 @@ int eu_project(eu_ctx *c, int mode)
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
     if (mode == EU_RESTRICT) seq_restrict(c, ARR_Q);
     else if (mode == EU_PROLONG) {
-        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 0, 0.0, (int)nblocks_grid(c, l), c->stream);
+        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 1, 0, 0.0, (int)nblocks_grid(c, l), c->stream);
     } else if (mode == EU_GHOST) seq_ghost(c, ARR_Q);
     else return set_err(c, EU_EINVAL, "bad projection mode");
     return check_launch(c);

@@ -1027,11 +1027,16 @@ __device__ __forceinline__ T predict_child_lds(const T *S, int px, int py, int p
 //   mode 2: the ghost cells of level lvl, from the coarse level's state
 //           interpolated in time between Qo (theta = 0) and Q (theta = 1);
 //   mode 3: mode 0, then the ghost cells of level lvl, in one launch (both
-//           read level lvl-1 only, which is final by then).
-// Gl and Cl are the grids of levels lvl and lvl-1 (modes 0, 2, 3), passed at
-// fixed argument offsets.
+//           read level lvl-1 only, which is final by then); with nlev = 2
+//           the same for levels lvl and lvl+1 in one launch: a level-(lvl+1)
+//           block recomputes the new level-lvl cells its stencils read from
+//           level lvl-1 (the same prediction, so the same bits) instead of
+//           waiting for them.
+// Gl, Cl and Gh are the grids of levels lvl, lvl-1 and lvl+1 (modes 0, 2, 3),
+// passed at fixed argument offsets.
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta, Grid Gl, Grid Cl)
+__global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta, int nlev, Grid Gl,
+                                                 Grid Cl, Grid Gh)
 {
     constexpr int W = BS / 2 + 2, NS = D == 2 ? W * W : W * W * W;
     __shared__ GridTab tab;
@@ -1041,12 +1046,12 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
     int off0 = 0, cnt0 = 0, off1 = 0, cnt1 = 0;   // ranges in the new and ghost lists
     if (mode == 0 || mode == 3) {
         off0 = v.meta->loff[LST_NEW][lvl];
-        cnt0 = v.meta->loff[LST_NEW][lvl + 1] - off0;
+        cnt0 = v.meta->loff[LST_NEW][lvl + nlev] - off0;
     }
     if (mode == 1) cnt1 = v.meta->nghost;
     if (mode >= 2) {
         off1 = v.meta->loff[LST_GHOST][lvl];
-        cnt1 = v.meta->loff[LST_GHOST][lvl + 1] - off1;
+        cnt1 = v.meta->loff[LST_GHOST][lvl + nlev] - off1;
     }
     const bool all = mode == 1;
     if (all) grid_tab_load(v, tab);
@@ -1061,8 +1066,9 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         const Tile tl = fresh ? v.fresh[off0 + t] : v.ghost[off1 + t - cnt0];
         const int lv = fresh ? tl.grid : tl.grid & ((1 << Tile::GRID_BITS) - 1);
         const uint32_t gm = fresh ? 0u : (uint32_t)tl.grid >> Tile::GRID_BITS;
-        const Grid G = all ? grid_tab(tab, lv) : Gl;
-        const Grid Cg = all ? grid_tab(tab, G.coarse) : Cl;
+        const bool up = !all && lv != lvl;   // a level-(lvl+1) block of a two-level launch
+        const Grid G = all ? grid_tab(tab, lv) : up ? Gh : Gl;
+        const Grid Cg = all ? grid_tab(tab, G.coarse) : up ? Gl : Cl;
         const int nb = G.nb;
         const int ox = (tl.block % nb) * BS;
         const int oy = ((tl.block / nb) % nb) * BS;
@@ -1073,11 +1079,17 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         const int qx0 = (ox >> 1) - 1, qy0 = (oy >> 1) - 1, qz0 = D == 3 ? (oz >> 1) - 1 : 0;
         for (int i = threadIdx.x; i < NS; i += blockDim.x) {
             const int sx = i % W, sy = (i / W) % W, sz = D == 3 ? i / (W * W) : 0;
-            const int64_t ic = Cg.off + gidx(Cg.n, bcmap(qx0 + sx, Cg.n, v.bc), bcmap(qy0 + sy, Cg.n, v.bc),
-                                             D == 3 ? bcmap(qz0 + sz, Cg.n, v.bc) : 0);
+            const int ax = bcmap(qx0 + sx, Cg.n, v.bc), ay = bcmap(qy0 + sy, Cg.n, v.bc);
+            const int az = D == 3 ? bcmap(qz0 + sz, Cg.n, v.bc) : 0;
+            const int64_t ic = Cg.off + gidx(Cg.n, ax, ay, az);
+            // in a new block of level lvl: predicted here from level lvl-1
+            const bool pre = up && (v.code[Cg.boff + gidx(Cg.nb, ax >> 3, ay >> 3, az >> 3)] & 8) != 0;
 #pragma unroll
             for (int f = 0; f < NV; ++f) {
-                if (mode == 2) {
+                if (pre) {
+                    sA[f][i] = predict_child<T, D, T>(A + Cl.off + f * Cl.ncell, Cl.n, v.bc, ax >> 1, ay >> 1,
+                                                      az >> 1, ax & 1, ay & 1, az & 1);
+                } else if (mode == 2) {
                     const T om = T(1) - (T)theta;
                     sA[f][i] = om * ((const T *)v.Qo)[ic + f * Cg.ncell] + (T)theta * ((const T *)v.Q)[ic + f * Cg.ncell];
                 } else {

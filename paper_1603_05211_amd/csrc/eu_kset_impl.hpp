@@ -54,12 +54,14 @@ template <typename T> void restrict2(const View &v, int a, int lvl, int nlev, in
     k_restrict2<T><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, nlev, g0, g1, g2);
 }
 
-template <typename T> void predict(const View &v, int a, int lvl, int mode, double theta, int maxb, hipStream_t s)
+template <typename T> void predict(const View &v, int a, int lvl, int nlev, int mode, double theta, int maxb,
+                                   hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 1024);
     const Grid Gl = v.gt[mode == 1 ? 0 : lvl], Cl = v.gt[mode == 1 ? 0 : lvl - 1];
-    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, Gl, Cl);
-    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, Gl, Cl);
+    const Grid Gh = v.gt[nlev == 2 ? lvl + 1 : (mode == 1 ? 0 : lvl)];
+    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh);
+    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh);
 }
 
 // Stage-kernel schedules the autotuner chooses from (variant index):
