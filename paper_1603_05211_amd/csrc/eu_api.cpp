@@ -295,19 +295,22 @@ int level_flags(eu_ctx *c, int64_t *nflag)
 // ---- launch sequences ------------------------------------------------------
 
 // Projection of every covered cell, finest level first: in 2D two levels
-// per launch, in 3D one.
-void seq_restrict(eu_ctx *c, int arr)
+// per launch, in 3D one.  With ghosts (2D), the last launch also fills the
+// ghost cells of every level.  Returns whether it did.
+bool seq_restrict(eu_ctx *c, int arr, bool ghosts = false)
 {
     if (c->dim == 2) {
         for (int l = c->L - 2; l >= 0; l -= 2) {
             const int lo = l >= 1 ? l - 1 : l, nlev = l - lo + 1;
-            c->ks->restrict2(c->v, arr, lo, nlev,
-                             (int)(nblocks_grid(c, lo) + (nlev == 2 ? nblocks_grid(c, l) : 0)), c->stream);
+            const bool last = lo == 0 && ghosts;
+            const int64_t nb = nblocks_grid(c, lo) + (nlev == 2 ? nblocks_grid(c, l) : 0) + (last ? c->nbt : 0);
+            c->ks->restrict2(c->v, arr, lo, nlev, last ? 1 : 0, (int)std::min<int64_t>(nb, INT32_MAX), c->stream);
         }
-        return;
+        return ghosts;
     }
     for (int l = c->L - 2; l >= 0; --l)
         c->ks->restrict_cov(c->v, arr, l, (int)nblocks_grid(c, l), c->stream);
+    return false;
 }
 
 void seq_ghost(eu_ctx *c, int arr)
@@ -340,8 +343,7 @@ void seq_fv_step(eu_ctx *c, bool ghost_after)
     prof_begin(c, &e);
     c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, c->variant, c->stream);
     prof_end(c, e);
-    seq_restrict(c, ARR_QS);
-    seq_ghost(c, ARR_QS);
+    if (!seq_restrict(c, ARR_QS, true)) seq_ghost(c, ARR_QS);
     prof_begin(c, &e);
     c->ks->fv_stage(c->v, 2, -1, 0, 0, c->max_tiles, c->variant, c->stream);
     prof_end(c, e);

@@ -900,7 +900,8 @@ __global__ void __launch_bounds__(256) k_restrict_cov(View v, T *A, int lvl)
 
 // Projection of the covered cells of levels lvl .. lvl+nlev-1 (nlev = 1 or
 // 2) in one launch (Sec. 2.1: a covered cell is the mean of its children),
-// 2D.  The covered
+// 2D; with ghosts set, in the same launch, the ghost fill of every level
+// (used when lvl .. lvl+nlev-1 are the coarsest levels, projected last).  The covered
 // blocks of the two levels are adjacent in the covered list.  A cell of
 // level lvl+1 is the mean of its four children; a cell of level lvl is the
 // mean of its four children, each of which is either final (a leaf) or
@@ -909,67 +910,6 @@ __global__ void __launch_bounds__(256) k_restrict_cov(View v, T *A, int lvl)
 // block of the level after, so one mask read tells whether the children are
 // covered.  Every read is issued before any result is stored, and the
 // arithmetic is that of two successive one-level projections.
-template <typename T>
-__global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev, Grid g0, Grid g1, Grid g2)
-{
-    constexpr int NV = 4;
-    // first reads, independent of each other (the grids of levels lvl,
-    // lvl+1 and lvl+2 come at fixed argument offsets)
-    const int done = v.meta->done;
-    const int off = v.meta->loff[LST_COV][lvl];
-    const int count = v.meta->loff[LST_COV][lvl + nlev] - off;
-    issued(off, count);
-    if (done) return;
-    for (int t = blockIdx.x; t < count; t += gridDim.x) {
-        const Tile tl = v.cov[off + t];
-        const bool lo = tl.grid == lvl;
-        const Grid G = lo ? g0 : g1;
-        const Grid F1 = lo ? g1 : g2;
-        const bool two = nlev == 2 && lo;   // through the children's children
-        const Grid F2 = g2;
-        const int nb = G.nb;
-        const int x = (tl.block % nb) * BS + threadIdx.x % BS;
-        const int y = ((tl.block / nb) % nb) * BS + threadIdx.x / BS;
-        const bool cov = covered(v.act, F1, x, y, 0);
-        // the children's children lie in block (4x/8, 4y/8) of level +2
-        const bool gcov = two && v.act[F2.boff + ((4 * x) >> 3) + (int64_t)F2.nb * ((4 * y) >> 3)] != 0;
-        T ch[NV][4];
-#pragma unroll
-        for (int f = 0; f < NV; ++f)
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                ch[f][k] = A[F1.off + f * F1.ncell + gidx(F1.n, 2 * x + (k & 1), 2 * y + (k >> 1), 0)];
-        T gc[NV][4] = {};
-        if (two) {
-#pragma unroll
-            for (int f = 0; f < NV; ++f)
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    gc[f][k] = restrict_cell<T, 2>(A + F2.off + f * F2.ncell, F2.n, 2 * x + (k & 1), 2 * y + (k >> 1), 0);
-#pragma unroll
-            for (int f = 0; f < NV; ++f)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) issued(gc[f][k]);
-        }
-#pragma unroll
-        for (int f = 0; f < NV; ++f)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) issued(ch[f][k]);
-        if (!cov) continue;
-        const int64_t id = G.off + gidx(G.n, x, y, 0);
-#pragma unroll
-        for (int f = 0; f < NV; ++f) {
-            T c[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const T a = gc[f][k], b = ch[f][k];   // select values, not addresses
-                c[k] = gcov ? a : b;
-            }
-            A[id + f * G.ncell] = T(0.25) * ((c[0] + c[1]) + (c[2] + c[3]));
-        }
-    }
-}
-
 // ghost cell of a ghost block (a block outside every patch of its level):
 // a cell within two cells of a patch.  Cells x-2 .. x+2 reach the lower
 // neighbour block along an axis when x mod 8 < 2 and the upper one when
@@ -1019,6 +959,154 @@ __device__ __forceinline__ T predict_child_lds(const T *S, int px, int py, int p
         sz[k] = pred1<T>(r[0], r[1], r[2], cy);
     }
     return pred1<T>(sz[0], sz[1], sz[2], cz);
+}
+
+// Value of level-k cell (x, y) of a 2D hierarchy after the projection of
+// levels lo .. hi-1 (k in that range): a covered cell is the mean of its
+// children, each of them final or, when level k+1 is projected in the same
+// pass, itself the mean of its children (level k+2 is final).  The same
+// arithmetic as the projection kernel; every read issued before any test.
+template <typename T>
+__device__ __forceinline__ void projected_value(const View &v, const T *A, const GridTab &tab, int k, int hi,
+                                                int x, int y, T *out)
+{
+    constexpr int NV = 4;
+    const Grid G = grid_tab(tab, k), F1 = grid_tab(tab, k + 1);
+    const bool two = k + 1 < hi;
+    const Grid F2 = grid_tab(tab, two ? k + 2 : k + 1);
+    const bool cov = covered(v.act, F1, x, y, 0);
+    const bool gcov = two && v.act[F2.boff + ((4 * x) >> 3) + (int64_t)F2.nb * ((4 * y) >> 3)] != 0;
+    T own[NV], ch[NV][4], gc[NV][4] = {};
+#pragma unroll
+    for (int f = 0; f < NV; ++f) {
+        own[f] = A[G.off + f * G.ncell + gidx(G.n, x, y, 0)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            ch[f][j] = A[F1.off + f * F1.ncell + gidx(F1.n, 2 * x + (j & 1), 2 * y + (j >> 1), 0)];
+    }
+    if (two)
+#pragma unroll
+        for (int f = 0; f < NV; ++f)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                gc[f][j] = restrict_cell<T, 2>(A + F2.off + f * F2.ncell, F2.n, 2 * x + (j & 1), 2 * y + (j >> 1), 0);
+#pragma unroll
+    for (int f = 0; f < NV; ++f) {
+        T c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const T a = gc[f][j], b = ch[f][j];
+            c[j] = gcov ? a : b;
+        }
+        const T m = T(0.25) * ((c[0] + c[1]) + (c[2] + c[3]));
+        const T o = own[f];
+        out[f] = cov ? m : o;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev, Grid g0, Grid g1, Grid g2,
+                                                  int ghosts)
+{
+    constexpr int NV = 4;
+    constexpr int W = BS / 2 + 2, NS = W * W;
+    __shared__ GridTab tab;
+    __shared__ T sA[NV][NS];
+    // first reads, independent of each other (the grids of levels lvl,
+    // lvl+1 and lvl+2 come at fixed argument offsets)
+    const int done = v.meta->done;
+    const int off = v.meta->loff[LST_COV][lvl];
+    const int count = v.meta->loff[LST_COV][lvl + nlev] - off;
+    const int ngh = ghosts ? v.meta->nghost : 0;
+    if (ghosts) grid_tab_load(v, tab);
+    issued(off, count, ngh);
+    if (done) return;
+    if (ghosts) __syncthreads();
+    for (int t = blockIdx.x; t < count + ngh; t += gridDim.x) {
+        if (t >= count) {
+            // ghost block of any level: predicted from the level below, whose
+            // values are final or, for the levels projected in this pass,
+            // projected here
+            const Tile tl = v.ghost[t - count];
+            const int lv = tl.grid & ((1 << Tile::GRID_BITS) - 1);
+            const uint32_t gm = (uint32_t)tl.grid >> Tile::GRID_BITS;
+            const Grid G = grid_tab(tab, lv), Cg = grid_tab(tab, lv - 1);
+            const bool otf = lv - 1 >= lvl && lv - 1 < lvl + nlev;
+            const int nb = G.nb;
+            const int ox = (tl.block % nb) * BS, oy = ((tl.block / nb) % nb) * BS;
+            const int qx0 = (ox >> 1) - 1, qy0 = (oy >> 1) - 1;
+            for (int i = threadIdx.x; i < NS; i += blockDim.x) {
+                const int ax = bcmap(qx0 + i % W, Cg.n, v.bc), ay = bcmap(qy0 + i / W, Cg.n, v.bc);
+                T val[NV];
+                if (otf) {
+                    projected_value<T>(v, A, tab, lv - 1, lvl + nlev, ax, ay, val);
+                } else {
+#pragma unroll
+                    for (int f = 0; f < NV; ++f) val[f] = A[Cg.off + f * Cg.ncell + gidx(Cg.n, ax, ay, 0)];
+                }
+#pragma unroll
+                for (int f = 0; f < NV; ++f) sA[f][i] = val[f];
+            }
+            __syncthreads();
+            for (int c = threadIdx.x; c < BS * BS; c += blockDim.x) {
+                const int x = ox + c % BS, y = oy + c / BS;
+                if (!ghost_cell<2>(gm, x, y, 0)) continue;
+                const int64_t id = gidx(G.n, x, y, 0);
+#pragma unroll
+                for (int f = 0; f < NV; ++f)
+                    A[G.off + f * G.ncell + id] =
+                        predict_child_lds<T, 2>(sA[f], (x >> 1) - qx0, (y >> 1) - qy0, 0, x & 1, y & 1, 0);
+            }
+            __syncthreads();
+            continue;
+        }
+        const Tile tl = v.cov[off + t];
+        const bool lo = tl.grid == lvl;
+        const Grid G = lo ? g0 : g1;
+        const Grid F1 = lo ? g1 : g2;
+        const bool two = nlev == 2 && lo;   // through the children's children
+        const Grid F2 = g2;
+        const int nb = G.nb;
+        const int x = (tl.block % nb) * BS + threadIdx.x % BS;
+        const int y = ((tl.block / nb) % nb) * BS + threadIdx.x / BS;
+        const bool cov = covered(v.act, F1, x, y, 0);
+        // the children's children lie in block (4x/8, 4y/8) of level +2
+        const bool gcov = two && v.act[F2.boff + ((4 * x) >> 3) + (int64_t)F2.nb * ((4 * y) >> 3)] != 0;
+        T ch[NV][4];
+#pragma unroll
+        for (int f = 0; f < NV; ++f)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                ch[f][k] = A[F1.off + f * F1.ncell + gidx(F1.n, 2 * x + (k & 1), 2 * y + (k >> 1), 0)];
+        T gc[NV][4] = {};
+        if (two) {
+#pragma unroll
+            for (int f = 0; f < NV; ++f)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    gc[f][k] = restrict_cell<T, 2>(A + F2.off + f * F2.ncell, F2.n, 2 * x + (k & 1), 2 * y + (k >> 1), 0);
+#pragma unroll
+            for (int f = 0; f < NV; ++f)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) issued(gc[f][k]);
+        }
+#pragma unroll
+        for (int f = 0; f < NV; ++f)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) issued(ch[f][k]);
+        if (!cov) continue;
+        const int64_t id = G.off + gidx(G.n, x, y, 0);
+#pragma unroll
+        for (int f = 0; f < NV; ++f) {
+            T c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const T a = gc[f][k], b = ch[f][k];   // select values, not addresses
+                c[k] = gcov ? a : b;
+            }
+            A[id + f * G.ncell] = T(0.25) * ((c[0] + c[1]) + (c[2] + c[3]));
+        }
+    }
 }
 
 // Prediction from the next coarser level into array A:
