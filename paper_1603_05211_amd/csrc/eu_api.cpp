@@ -295,18 +295,33 @@ int level_flags(eu_ctx *c, int64_t *nflag)
 // ---- launch sequences ------------------------------------------------------
 
 // Projection of every covered cell, finest level first: in 2D two levels
-// per launch, in 3D one.  With ghosts (2D), the last launch also fills the
-// ghost cells of every level.  Returns whether it did.
-bool seq_restrict(eu_ctx *c, int arr, bool ghosts = false)
+// per launch, in 3D one.  In 2D the last launch can also fill the ghost cells
+// of every level (ghosts) or compute the MR details (details), projecting
+// the values of the levels it projects itself where they are read (not both:
+// the details read ghost cells the fill writes).  Returns whether it did the
+// extra work.
+bool seq_restrict(eu_ctx *c, int arr, bool ghosts = false, bool details = false)
 {
+    if (ghosts && details) ghosts = details = false;
     if (c->dim == 2) {
+        int64_t ndet = 0;
+        if (details)
+            for (int l = 0; l < c->L - 1; ++l) ndet += c->grids[l].ncell;
         for (int l = c->L - 2; l >= 0; l -= 2) {
             const int lo = l >= 1 ? l - 1 : l, nlev = l - lo + 1;
-            const bool last = lo == 0 && ghosts;
-            const int64_t nb = nblocks_grid(c, lo) + (nlev == 2 ? nblocks_grid(c, l) : 0) + (last ? c->nbt : 0);
-            c->ks->restrict2(c->v, arr, lo, nlev, last ? 1 : 0, (int)std::min<int64_t>(nb, INT32_MAX), c->stream);
+            const bool last = lo == 0;
+            int64_t nb = nblocks_grid(c, lo) + (nlev == 2 ? nblocks_grid(c, l) : 0);
+            if (last && ghosts) nb += c->nbt;
+            if (last && details) {
+                // 8x8 blocks of the levels projected here, 64-cell chunks of the rest
+                int64_t fine = ndet;
+                for (int k = 0; k <= l; ++k) fine -= c->grids[k].ncell;
+                nb += nblocks_grid(c, 0) + (nlev == 2 ? nblocks_grid(c, 1) : 0) + (fine + 63) / 64;
+            }
+            c->ks->restrict2(c->v, arr, lo, nlev, last && ghosts ? 1 : 0, last ? ndet : 0,
+                             (int)std::min<int64_t>(nb, INT32_MAX), c->stream);
         }
-        return ghosts;
+        return c->L >= 2 && (ghosts || details);
     }
     for (int l = c->L - 2; l >= 0; --l)
         c->ks->restrict_cov(c->v, arr, l, (int)nblocks_grid(c, l), c->stream);
@@ -337,7 +352,11 @@ void prof_end(eu_ctx *c, hipEvent_t e1)
     if (e1) (void)hipEventRecord(e1, c->stream);
 }
 
-void seq_fv_step(eu_ctx *c, bool ghost_after)
+// One step of the FV scheme on every leaf (two stages), each stage followed
+// by the projection; after the second, the ghost fill (ghost_after) or the MR
+// details (details), folded into the last projection launch where it can.
+void seq_details(eu_ctx *c);
+void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
 {
     hipEvent_t e;
     prof_begin(c, &e);
@@ -347,8 +366,10 @@ void seq_fv_step(eu_ctx *c, bool ghost_after)
     prof_begin(c, &e);
     c->ks->fv_stage(c->v, 2, -1, 0, 0, c->max_tiles, c->variant, c->stream);
     prof_end(c, e);
-    seq_restrict(c, ARR_Q);
-    if (ghost_after) seq_ghost(c, ARR_Q);
+    if (!seq_restrict(c, ARR_Q, ghost_after, details)) {
+        if (ghost_after) seq_ghost(c, ARR_Q);
+        if (details) seq_details(c);
+    }
 }
 
 void seq_details(eu_ctx *c)
@@ -421,11 +442,8 @@ void seq_step(eu_ctx *c, bool regrid)
         }
         return;
     }
-    seq_fv_step(c, !rg);
-    if (rg) {
-        seq_details(c);
-        seq_flag_tile(c, true);
-    }
+    seq_fv_step(c, !rg, rg);
+    if (rg) seq_flag_tile(c, true);
 }
 
 int upload(eu_ctx *c, void *dst, const void *src, size_t bytes)
@@ -741,8 +759,7 @@ int eu_mr_decompose(eu_ctx *c)
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
     if (c->mode != MODE_HIER) return set_err(c, EU_EINVAL, "a batch has no hierarchy");
-    seq_restrict(c, ARR_Q);
-    seq_details(c);
+    if (!seq_restrict(c, ARR_Q, false, true)) seq_details(c);
     return check_launch(c);
 }
 

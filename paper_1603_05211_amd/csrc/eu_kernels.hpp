@@ -966,11 +966,11 @@ __device__ __forceinline__ T predict_child_lds(const T *S, int px, int py, int p
 // children, each of them final or, when level k+1 is projected in the same
 // pass, itself the mean of its children (level k+2 is final).  The same
 // arithmetic as the projection kernel; every read issued before any test.
-template <typename T>
+// The first NV fields (all four, or the density alone).
+template <typename T, int NV = 4>
 __device__ __forceinline__ void projected_value(const View &v, const T *A, const GridTab &tab, int k, int hi,
                                                 int x, int y, T *out)
 {
-    constexpr int NV = 4;
     const Grid G = grid_tab(tab, k), F1 = grid_tab(tab, k + 1);
     const bool two = k + 1 < hi;
     const Grid F2 = grid_tab(tab, two ? k + 2 : k + 1);
@@ -1004,25 +1004,136 @@ __device__ __forceinline__ void projected_value(const View &v, const T *A, const
     }
 }
 
+// MR detail (Sec. 2.1) of cell (x, y) of an 8x8 block at (ox, oy) from its
+// densities staged in LDS: S the 10x10 stencil region of the block's level
+// (periodic or mirrored at the domain edge), C the 16x16 children.  The same
+// FP64 expression as k_details.
+template <typename T>
+__device__ __forceinline__ double detail_lds(const T *S, const T *C, int lx, int ly)
+{
+#pragma clang fp contract(off)
+    double s[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) s[j][i] = (double)S[(ly + j) * (BS + 2) + lx + i];
+    double Dm = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int cx = c & 1, cy = c >> 1;
+        const double rho = (double)C[(2 * ly + cy) * (2 * BS) + 2 * lx + cx];
+        double r[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) r[j] = pred1<double>(s[j][0], s[j][1], s[j][2], cx);
+        const double pr = pred1<double>(r[0], r[1], r[2], cy);
+        const double dd = __builtin_fabs(rho - pr);
+        if (dd > Dm) Dm = dd;
+    }
+    return Dm;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev, Grid g0, Grid g1, Grid g2,
-                                                  int ghosts)
+                                                  int ghosts, int64_t ndet)
 {
     constexpr int NV = 4;
     constexpr int W = BS / 2 + 2, NS = W * W;
+    constexpr int SW = BS + 2, NSD = SW * SW, CW = 2 * BS;
     __shared__ GridTab tab;
     __shared__ T sA[NV][NS];
+    __shared__ T sS[NSD], sC[CW * CW];
     // first reads, independent of each other (the grids of levels lvl,
     // lvl+1 and lvl+2 come at fixed argument offsets)
     const int done = v.meta->done;
     const int off = v.meta->loff[LST_COV][lvl];
     const int count = v.meta->loff[LST_COV][lvl + nlev] - off;
     const int ngh = ghosts ? v.meta->nghost : 0;
-    if (ghosts) grid_tab_load(v, tab);
+    // MR details of levels 0 .. L-2 (ndet cells in all, only with lvl = 0):
+    // 8x8 blocks of the levels projected here, then chunks of 64 cells of
+    // the finer levels, from the first cell after those levels
+    const int64_t dfirst = nlev == 2 ? g1.coff + g1.ncell : g0.coff + g0.ncell;
+    const int nin = ndet ? g0.nb * g0.nb + (nlev == 2 ? g1.nb * g1.nb : 0) : 0;
+    const int nch = ndet ? nin + (int)((ndet - dfirst + 63) / 64) : 0;
+    if (ghosts || ndet) grid_tab_load(v, tab);
     issued(off, count, ngh);
     if (done) return;
-    if (ghosts) __syncthreads();
-    for (int t = blockIdx.x; t < count + ngh; t += gridDim.x) {
+    if (ghosts || ndet) __syncthreads();
+    for (int t = blockIdx.x; t < count + ngh + nch; t += gridDim.x) {
+        if (t >= count + ngh) {
+            const int r = t - count - ngh;
+            if (r < nin) {
+                // 8x8 block of level lvl or lvl+1: the projected densities
+                // of its stencil region and of its children staged in LDS
+                const bool first = r < g0.nb * g0.nb;
+                const int k = first ? lvl : lvl + 1;
+                const int b = first ? r : r - g0.nb * g0.nb;
+                const Grid G = first ? g0 : g1, F = first ? g1 : g2;
+                const bool fin = k + 1 < lvl + nlev;   // children projected here too
+                const int ox = (b % G.nb) * BS, oy = (b / G.nb) * BS;
+                const int lx = threadIdx.x % BS, ly = threadIdx.x / BS;
+                const bool act = block_active(v, v.act, G, ox, oy, 0);
+                const bool cov = covered(v.act, F, ox + lx, oy + ly, 0);
+                // every staging read in flight at once (64 threads)
+                T vs[2], vc[4];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int i = threadIdx.x + 64 * u < NSD ? threadIdx.x + 64 * u : NSD - 1;
+                    const int ax = bcmap(ox - 1 + i % SW, G.n, v.bc), ay = bcmap(oy - 1 + i / SW, G.n, v.bc);
+                    projected_value<T, 1>(v, A, tab, k, lvl + nlev, ax, ay, &vs[u]);
+                }
+                if (fin) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = threadIdx.x + 64 * u;
+                        projected_value<T, 1>(v, A, tab, k + 1, lvl + nlev, 2 * ox + i % CW, 2 * oy + i / CW,
+                                              &vc[u]);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = threadIdx.x + 64 * u;
+                        vc[u] = A[F.off + gidx(F.n, 2 * ox + i % CW, 2 * oy + i / CW, 0)];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (threadIdx.x + 64 * u < NSD) sS[threadIdx.x + 64 * u] = vs[u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sC[threadIdx.x + 64 * u] = vc[u];
+                __syncthreads();
+                const double Dm = act && cov ? detail_lds<T>(sS, sC, lx, ly) : 0.0;
+                const int64_t j = G.coff + gidx(G.n, ox + lx, oy + ly, 0);
+                v.D[j] = Dm;
+                v.sig[j] = Dm >= v.eps ? 1 : 0;
+                __syncthreads();
+                continue;
+            }
+            // one cell of a finer level per thread, its values final
+            const int64_t j = dfirst + (int64_t)(r - nin) * 64 + threadIdx.x;
+            if (j < ndet) {
+                int k = 0;
+                for (int q = 1; q < MAXLEV && q < v.L - 1; ++q) k += j >= v.gt[q].coff ? 1 : 0;
+                const Grid G = grid_lane(v, k), F = grid_lane(v, k + 1);
+                const int64_t i = j - G.coff;
+                const int x = (int)(i % G.n), y = (int)(i / G.n);
+                const bool act = block_active(v, v.act, G, x, y, 0);
+                const bool cov = covered(v.act, F, x, y, 0);
+                double Dm = 0.0;
+                if (act && cov) {
+#pragma clang fp contract(off)
+                    for (int c = 0; c < 4; ++c) {
+                        const int cx = c & 1, cy = c >> 1;
+                        const double rho = (double)A[F.off + gidx(F.n, 2 * x + cx, 2 * y + cy, 0)];
+                        const double pr = predict_child<double, 2, T>(A + G.off, G.n, v.bc, x, y, 0, cx, cy, 0);
+                        const double dd = __builtin_fabs(rho - pr);
+                        if (dd > Dm) Dm = dd;
+                    }
+                }
+                v.D[j] = Dm;
+                v.sig[j] = Dm >= v.eps ? 1 : 0;
+            }
+            continue;
+        }
         if (t >= count) {
             // ghost block of any level: predicted from the level below, whose
             // values are final or, for the levels projected in this pass,

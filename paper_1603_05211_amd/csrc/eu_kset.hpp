@@ -29,7 +29,8 @@ struct KSet {
     void (*init)(const View &, const InitArgs &, int grid, int64_t ncell, hipStream_t);
     void (*restrict_full)(const View &, int arr, int grid_coarse, int64_t ncell, hipStream_t);
     void (*restrict_cov)(const View &, int arr, int lvl, int maxblocks, hipStream_t);
-    void (*restrict2)(const View &, int arr, int lvl, int nlev, int ghosts, int maxblocks, hipStream_t);
+    void (*restrict2)(const View &, int arr, int lvl, int nlev, int ghosts, int64_t ndetails, int maxblocks,
+                      hipStream_t);
     void (*predict)(const View &, int arr, int lvl, int nlev, int mode, double theta, int maxblocks, hipStream_t);
     void (*fv_stage)(const View &, int stage, int lvl, int sub, int record, int maxtiles, int variant,
                      hipStream_t);

@@ -46,12 +46,14 @@ template <typename T> void restrict_cov(const View &v, int a, int lvl, int maxb,
     else k_restrict_cov<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl);
 }
 
-// two levels per launch (2D only), optionally with the ghost fill of every level
-template <typename T> void restrict2(const View &v, int a, int lvl, int nlev, int ghosts, int maxb, hipStream_t s)
+// two levels per launch (2D only), optionally with the ghost fill of every
+// level or the MR details of levels 0 .. L-2
+template <typename T> void restrict2(const View &v, int a, int lvl, int nlev, int ghosts, int64_t ndet, int maxb,
+                                     hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 2048);
     const Grid g0 = v.gt[lvl], g1 = v.gt[lvl + 1], g2 = v.gt[lvl + 2 < v.L ? lvl + 2 : lvl + 1];
-    k_restrict2<T><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, nlev, g0, g1, g2, ghosts);
+    k_restrict2<T><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, nlev, g0, g1, g2, ghosts, ndet);
 }
 
 template <typename T> void predict(const View &v, int a, int lvl, int nlev, int mode, double theta, int maxb,
