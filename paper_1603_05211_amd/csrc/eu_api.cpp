@@ -33,6 +33,7 @@ struct eu_ctx {
     std::vector<int64_t> pbase; // per level: first pmax-block slot (levels 1 .. L-1)
     bool initialized = false;
     int variant = 0;            // stage-kernel schedule (eu_autotune)
+    int cfl_parts = 0;          // CFL partials of the current state left by the last regrid (0: none)
     std::string err;
     // graphs: [0] step with regrid, [1] step without
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -330,10 +331,17 @@ bool seq_restrict(eu_ctx *c, int arr, bool ghosts = false, bool details = false)
 
 void seq_ghost(eu_ctx *c, int arr)
 {
-    if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, 1, 0.0, (int)(c->nbt), c->stream);
+    if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, 1, 0.0, 0, (int)(c->nbt), c->stream);
 }
 
-void seq_cfl(eu_ctx *c) { c->ks->cfl(c->v, c->max_tiles, c->stream); }
+// dt of the step: from the CFL partials the last regrid left, when the state
+// has not changed since, else from a reduction over the leaves
+void seq_cfl(eu_ctx *c)
+{
+    if (c->cfl_parts > 0) launch_cfl_final(c->v, c->cfl_parts, c->stream);
+    else c->ks->cfl(c->v, c->max_tiles, c->stream);
+    c->cfl_parts = 0;
+}
 
 void prof_begin(eu_ctx *c, hipEvent_t *a)
 {
@@ -380,9 +388,34 @@ void seq_details(eu_ctx *c)
     c->ks->details(c->v, n, c->stream);
 }
 
+// Prediction launches of a regrid, coarse to fine, two levels per launch:
+// the first level and the level count of launch i, and its block bound.
+int predict_launches(const eu_ctx *c, int *lvl, int *nlev, int64_t *maxb)
+{
+    int n = 0;
+    for (int l = 1; l < c->L; l += 2, ++n) {
+        lvl[n] = l;
+        nlev[n] = l + 1 < c->L ? 2 : 1;
+        maxb[n] = nblocks_grid(c, l) + (nlev[n] == 2 ? nblocks_grid(c, l + 1) : 0);
+    }
+    return n;
+}
+
+// Workgroups of the launch that leaves the CFL partials at the end of a
+// regrid (0: a regrid leaves none).
+int fused_cfl_grid(const eu_ctx *c)
+{
+    if (c->mode != MODE_HIER || c->L < 2) return 0;
+    int lvl[MAXLEV], nlev[MAXLEV];
+    int64_t maxb[MAXLEV];
+    const int n = predict_launches(c, lvl, nlev, maxb);
+    return predict_grid(maxb[n - 1]);
+}
+
 // flags, closure and tiling (finest first), lists, then either the
 // prediction of new cells and ghost cells (coarse to fine, two levels per
-// launch) or the ghost fill alone.
+// launch; the last launch also leaves the CFL partials of the new state) or
+// the ghost fill alone.
 void seq_flag_tile(eu_ctx *c, bool prolong)
 {
     for (int l = c->L - 2; l >= 0; --l) {
@@ -390,14 +423,20 @@ void seq_flag_tile(eu_ctx *c, bool prolong)
         launch_flag_tile(c->v, l, (int)ipow(nbp, c->dim), c->stream);
     }
     launch_build_lists(c->v, c->nbt, c->stream);
-    if (prolong)
-        for (int l = 1; l < c->L; l += 2) {
-            const int nlev = l + 1 < c->L ? 2 : 1;
-            c->ks->predict(c->v, ARR_Q, l, nlev, 3, 0.0,
-                           (int)(nblocks_grid(c, l) + (nlev == 2 ? nblocks_grid(c, l + 1) : 0)), c->stream);
+    c->cfl_parts = 0;
+    if (prolong) {
+        int lvl[MAXLEV], nlev[MAXLEV];
+        int64_t maxb[MAXLEV];
+        const int n = predict_launches(c, lvl, nlev, maxb);
+        for (int i = 0; i < n; ++i) {
+            const int fuse = i == n - 1 && c->mode == MODE_HIER ? 1 : 0;
+            c->ks->predict(c->v, ARR_Q, lvl[i], nlev[i], 3, 0.0, fuse,
+                           (int)std::min<int64_t>(maxb[i], INT32_MAX), c->stream);
+            if (fuse) c->cfl_parts = predict_grid(maxb[i]);
         }
-    else
+    } else {
         seq_ghost(c, ARR_Q);
+    }
 }
 
 // Local time stepping: advance level l by one of its steps (substep k of
@@ -413,14 +452,14 @@ void lts_advance(eu_ctx *c, int l, int k)
     prof_begin(c, &e);
     c->ks->fv_stage(c->v, 1, l, k, 0, nbl, c->variant, c->stream);
     prof_end(c, e);
-    if (l >= 1) c->ks->predict(c->v, ARR_QS, l, 1, 2, (double)(2 * k + 1) * 0.25, nbl, c->stream);
+    if (l >= 1) c->ks->predict(c->v, ARR_QS, l, 1, 2, (double)(2 * k + 1) * 0.25, 0, nbl, c->stream);
     prof_begin(c, &e);
     c->ks->fv_stage(c->v, 2, l, k, 1, nbl, c->variant, c->stream);
     prof_end(c, e);
     if (l + 1 < c->L) {
         const int nbf = (int)nblocks_grid(c, l + 1);
         for (int kk = 0; kk < 2; ++kk) {
-            c->ks->predict(c->v, ARR_Q, l + 1, 1, 2, (double)kk * 0.5, nbf, c->stream);
+            c->ks->predict(c->v, ARR_Q, l + 1, 1, 2, (double)kk * 0.5, 0, nbf, c->stream);
             lts_advance(c, l + 1, kk);
         }
         c->ks->restrict_cov(c->v, ARR_Q, l, nbl, c->stream);
@@ -546,6 +585,7 @@ InitArgs make_init(const eu_ctx *c, const eu_problem *p, int inst)
 // data; ghost fill.  t = 0.
 int finish_init(eu_ctx *c)
 {
+    c->cfl_parts = 0;
     HIPCHK(c, hipMemsetAsync(c->v.meta, 0, sizeof(Meta), c->stream));
     HIPCHK(c, hipMemsetAsync(c->v.t, 0, 8 * c->ngrid, c->stream));
     HIPCHK(c, hipMemsetAsync(c->v.dt, 0, 8 * c->ngrid, c->stream));
@@ -741,6 +781,7 @@ int eu_set_finest(eu_ctx *c, int inst, const double *q_host)
     if (!c || !q_host) return EU_EINVAL;
     const int g = c->mode == MODE_BATCH ? inst : c->L - 1;
     if (g < 0 || g >= c->ngrid) return set_err(c, EU_EINVAL, "bad instance");
+    c->cfl_parts = 0;
     const Grid &G = c->grids[g];
     const int64_t n = c->nv * G.ncell;
     if (c->cfg.precision == EU_FP64) {
@@ -759,6 +800,7 @@ int eu_mr_decompose(eu_ctx *c)
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
     if (c->mode != MODE_HIER) return set_err(c, EU_EINVAL, "a batch has no hierarchy");
+    c->cfl_parts = 0;
     if (!seq_restrict(c, ARR_Q, false, true)) seq_details(c);
     return check_launch(c);
 }
@@ -783,9 +825,11 @@ int eu_project(eu_ctx *c, int mode)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    c->cfl_parts = 0;
     if (mode == EU_RESTRICT) seq_restrict(c, ARR_Q);
     else if (mode == EU_PROLONG) {
-        for (int l = 1; l < c->L; ++l) c->ks->predict(c->v, ARR_Q, l, 1, 0, 0.0, (int)nblocks_grid(c, l), c->stream);
+        for (int l = 1; l < c->L; ++l)
+            c->ks->predict(c->v, ARR_Q, l, 1, 0, 0.0, 0, (int)nblocks_grid(c, l), c->stream);
     } else if (mode == EU_GHOST) seq_ghost(c, ARR_Q);
     else return set_err(c, EU_EINVAL, "bad projection mode");
     return check_launch(c);
@@ -809,6 +853,7 @@ int eu_fv_step(eu_ctx *c)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    c->cfl_parts = 0;
     if (c->v.lts) {
         lts_advance(c, 0, 0);
         seq_ghost(c, ARR_Q);
@@ -835,6 +880,13 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
     HIPCHK(c, hipMemcpy(&s0, &c->v.meta->steps, sizeof(int), hipMemcpyDeviceToHost));
     if (use_graph && !c->prof) {
         if (!c->stream) return set_err(c, EU_EINVAL, "graph capture needs a non-default stream");
+        // the graph starts from the CFL partials its last step leaves: the
+        // first replay needs them of the current state
+        const int nf = fused_cfl_grid(c);
+        if (nf && c->cfl_parts != nf) {
+            c->ks->cfl_partials(c->v, nf, c->stream);
+            c->cfl_parts = nf;
+        }
         if (!c->gexec[0]) {
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -868,6 +920,7 @@ int eu_conserved_totals(eu_ctx *c, double *totals_host)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    c->cfl_parts = 0;   // the totals reuse the partials' memory
     c->ks->totals(c->v, c->max_tiles, c->stream);
     launch_totals_final(c->v, c->ngroups, c->stream);
     int r = check_launch(c);

@@ -669,6 +669,60 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
 // Hierarchy: workgroup b writes its per-level maxima and its count of leaf
 // cells advanced to v.partial[b * CFL_STRIDE ...] (plain stores; the kernel
 // boundary publishes them).  Batch: one atomic max per tile on its instance.
+
+// Signal speed sum_d (|v_d| + c) of a cell from its conserved state (FP64);
+// bad when its density or pressure is not positive.
+template <int D>
+__device__ __forceinline__ double cell_speed(const double *q, double g, bool &bad)
+{
+#pragma clang fp contract(off)
+    double w[D + 2];
+    cons2prim<double, D>(q, w, g);
+    bad = !(w[0] > 0.0) || !(w[D + 1] > 0.0);
+    const double cs = __builtin_sqrt((g * w[D + 1]) / w[0]);
+    double S = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) S = S + (__builtin_fabs(w[1 + d]) + cs);
+    return S;
+}
+
+// Per-level maxima and leaf count of one workgroup (the wave's row; lane 0
+// adds the wave's share of a tile of level lv)
+__device__ __forceinline__ void cfl_tile_done(double (*lmax)[MAXLEV], unsigned long long *lcnt, const View &v,
+                                              int lv, double m, int nl)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double r = __shfl_xor(m, o);
+        m = r > m ? r : m;
+        nl += __shfl_xor(nl, o);
+    }
+    if (lane == 0) {
+        // leaf cells advanced this step (a level-l leaf 2^l times with local
+        // time stepping)
+        lcnt[wave] += (unsigned long long)nl << (v.lts ? lv : 0);
+        if (m > lmax[wave][lv]) lmax[wave][lv] = m;
+    }
+}
+
+// The workgroup's partials: maxima over its waves and the leaf count.
+template <int NW>
+__device__ __forceinline__ void cfl_write_partial(const double (*lmax)[MAXLEV], const unsigned long long *lcnt,
+                                                  const View &v)
+{
+    const int l = threadIdx.x;
+    double *P = v.partial + (int64_t)blockIdx.x * CFL_STRIDE;
+    if (l < MAXLEV) {
+        double mm = lmax[0][l];
+        for (int w = 1; w < NW; ++w) mm = lmax[w][l] > mm ? lmax[w][l] : mm;
+        P[l] = mm;
+    } else if (l == MAXLEV) {
+        unsigned long long c = lcnt[0];
+        if (NW == 4) c = (lcnt[0] + lcnt[1]) + (lcnt[2] + lcnt[3]);
+        P[MAXLEV] = (double)c;
+    }
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
 {
@@ -703,48 +757,29 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
             // the state is read whether or not the cell is covered (a
             // covered cell holds its children's mean); it only counts for
             // leaves
-            double q[D + 2], w[D + 2];
+            double q[D + 2];
 #pragma unroll
             for (int f = 0; f < D + 2; ++f) q[f] = (double)Q[f * G.ncell + id];
             const bool leaf = !(hasf && covered(v.act, GF, x, y, z));
-            cons2prim<double, D>(q, w, g);
-            if (leaf && (!(w[0] > 0.0) || !(w[D + 1] > 0.0))) bad = true;
-            const double cs = __builtin_sqrt((g * w[D + 1]) / w[0]);
-            double S = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) S = S + (__builtin_fabs(w[1 + d]) + cs);
+            bool b;
+            const double S = cell_speed<D>(q, g, b);
+            if (leaf && b) bad = true;
             if (leaf && S > m) m = S;
             nl += leaf ? 1 : 0;
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            const double r = __shfl_xor(m, o);
-            m = r > m ? r : m;
-            nl += __shfl_xor(nl, o);
-        }
-        if (lane == 0) {
-            if (hier) {
-                // leaf cells advanced this step (a level-l leaf 2^l times
-                // with local time stepping)
-                lcnt[wave] += (unsigned long long)nl << (v.lts ? tl.grid : 0);
-                if (m > lmax[wave][tl.grid]) lmax[wave][tl.grid] = m;
-            } else if (m > 0.0) {
-                atomicMax(&v.smax[tl.grid], (unsigned long long)__double_as_longlong(m));
+        if (hier) {
+            cfl_tile_done(lmax, lcnt, v, tl.grid, m, nl);
+        } else {
+            for (int o = 32; o > 0; o >>= 1) {
+                const double r = __shfl_xor(m, o);
+                m = r > m ? r : m;
             }
+            if (lane == 0 && m > 0.0) atomicMax(&v.smax[tl.grid], (unsigned long long)__double_as_longlong(m));
         }
     }
     if (__any(bad) && lane == 0) atomicOr(&v.meta->status, 1);
     __syncthreads();
-    if (hier) {
-        const int l = threadIdx.x;
-        double *P = v.partial + (int64_t)blockIdx.x * CFL_STRIDE;
-        if (l < MAXLEV) {
-            double mm = lmax[0][l];
-            for (int w = 1; w < 4; ++w) mm = lmax[w][l] > mm ? lmax[w][l] : mm;
-            P[l] = mm;
-        } else if (l == MAXLEV) {
-            P[MAXLEV] = (double)((lcnt[0] + lcnt[1]) + (lcnt[2] + lcnt[3]));
-        }
-    }
+    if (hier) cfl_write_partial<4>(lmax, lcnt, v);
 }
 
 // ----------------------------------------------------------------------------
@@ -1231,15 +1266,74 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
 //           block recomputes the new level-lvl cells its stencils read from
 //           level lvl-1 (the same prediction, so the same bits) instead of
 //           waiting for them.
+// CFL speeds of the leaf cells of leaf blocks ta and (two) tb, their reads
+// issued together; a new block of levels lvl .. lvl+nlev-1 counts nothing
+// (its prediction counts its cells).
+template <typename T, int D>
+__device__ __forceinline__ void leaf_speeds(const View &v, const T *A, const GridTab &tab, const Tile &ta, int lvl,
+                                            int nlev, double g, double (*lmax)[MAXLEV], unsigned long long *lcnt,
+                                            bool &bad, bool two, const Tile &tb)
+{
+    constexpr int TC = D == 2 ? BS * BS : BS * BS * BS, NV = D + 2;
+    constexpr int CPT = TC / (D == 2 ? 64 : 256);   // cells per thread (64 or 256 threads)
+    double q[2][CPT][NV];
+    bool leaf[2][CPT];
+    int lv[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const Tile &tl = k ? tb : ta;
+        lv[k] = tl.grid;
+        const Grid G = grid_tab(tab, tl.grid);
+        const bool hasf = G.fine >= 0;
+        const Grid GF = hasf ? grid_tab(tab, G.fine) : G;
+        const bool mine = tl.grid >= lvl && tl.grid < lvl + nlev && (v.code[G.boff + tl.block] & 8) != 0;
+        const int nb = G.nb;
+        const int ox = (tl.block % nb) * BS;
+        const int oy = ((tl.block / nb) % nb) * BS;
+        const int oz = D == 3 ? (tl.block / (nb * nb)) * BS : 0;
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+            const int c = threadIdx.x + i * (TC / CPT);
+            const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
+            const int64_t id = G.off + gidx(G.n, x, y, z);
+#pragma unroll
+            for (int f = 0; f < NV; ++f) q[k][i][f] = (double)A[f * G.ncell + id];
+            leaf[k][i] = !mine && !(hasf && covered(v.act, GF, x, y, z));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !two) break;
+        double m = 0.0;
+        int nl = 0;
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+            bool b;
+            const double S = cell_speed<D>(q[k][i], g, b);
+            if (leaf[k][i] && b) bad = true;
+            if (leaf[k][i] && S > m) m = S;
+            nl += leaf[k][i] ? 1 : 0;
+        }
+        cfl_tile_done(lmax, lcnt, v, lv[k], m, nl);
+    }
+}
+
 // Gl, Cl and Gh are the grids of levels lvl, lvl-1 and lvl+1 (modes 0, 2, 3),
 // passed at fixed argument offsets.
+// cfl (mode 3, the launch of the finest levels, A the state): the launch
+// also leaves the CFL partials of the new hierarchy, as k_cfl would compute
+// them from the state it leaves: the new blocks of its levels take the speeds
+// of the leaf cells they predict, the leaf tiles every other leaf block.
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta, int nlev, Grid Gl,
-                                                 Grid Cl, Grid Gh)
+                                                 Grid Cl, Grid Gh, int cfl)
 {
     constexpr int W = BS / 2 + 2, NS = D == 2 ? W * W : W * W * W;
+    constexpr int NW = D == 2 ? 1 : 4;   // waves per workgroup
     __shared__ GridTab tab;
     __shared__ T sA[D + 2][NS];
+    __shared__ double lmax[NW][MAXLEV];
+    __shared__ unsigned long long lcnt[NW];
     // first reads, independent of each other (grid index = level)
     const int done = v.meta->done;
     int off0 = 0, cnt0 = 0, off1 = 0, cnt1 = 0;   // ranges in the new and ghost lists
@@ -1252,13 +1346,21 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         off1 = v.meta->loff[LST_GHOST][lvl];
         cnt1 = v.meta->loff[LST_GHOST][lvl + nlev] - off1;
     }
+    const int nleaf = cfl ? v.meta->nleaf : 0;
     const bool all = mode == 1;
-    if (all) grid_tab_load(v, tab);
-    issued(off0, cnt0, off1, cnt1);
+    if (all || cfl) grid_tab_load(v, tab);
+    issued(off0, cnt0, off1, cnt1, nleaf);
     if (done) return;
-    if (all) __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (cfl) {
+        if (lane < MAXLEV) lmax[wave][lane] = 0.0;
+        if (lane == 0) lcnt[wave] = 0ull;
+    }
+    if (all || cfl) __syncthreads();
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
     constexpr int NV = D + 2;
+    const double g = v.gamma;
+    bool bad = false;
     const int count = cnt0 + cnt1;
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const bool fresh = t < cnt0;
@@ -1297,18 +1399,51 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
             }
         }
         __syncthreads();
+        const bool speeds = cfl && fresh;   // the leaf cells of a new block
+        const bool hasf = lv + 1 < v.L;
+        const Grid GF = speeds && hasf ? grid_tab(tab, lv + 1) : G;
+        double m = 0.0;
+        int nl = 0;
         for (int c = threadIdx.x; c < TC; c += blockDim.x) {
             const int x = ox + c % BS, y = oy + (c / BS) % BS, z = oz + (D == 3 ? c / (BS * BS) : 0);
             // every cell of a new block is predicted; in a ghost block only
             // the ghost cells
             if (!fresh && !ghost_cell<D>(gm, x, y, z)) continue;
+            const bool leaf = speeds && !(hasf && covered(v.act, GF, x, y, z));
             const int px = (x >> 1) - qx0, py = (y >> 1) - qy0, pz = D == 3 ? (z >> 1) - qz0 : 0;
             const int64_t id = gidx(G.n, x, y, z);
+            double q[NV];
 #pragma unroll
-            for (int f = 0; f < NV; ++f)
-                A[G.off + f * G.ncell + id] = predict_child_lds<T, D>(sA[f], px, py, pz, x & 1, y & 1, z & 1);
+            for (int f = 0; f < NV; ++f) {
+                const T val = predict_child_lds<T, D>(sA[f], px, py, pz, x & 1, y & 1, z & 1);
+                A[G.off + f * G.ncell + id] = val;
+                q[f] = (double)val;
+            }
+            if (speeds) {
+                bool b;
+                const double S = cell_speed<D>(q, g, b);
+                if (leaf && b) bad = true;
+                if (leaf && S > m) m = S;
+                nl += leaf ? 1 : 0;
+            }
         }
+        if (speeds) cfl_tile_done(lmax, lcnt, v, lv, m, nl);
         __syncthreads();
+    }
+    if (cfl) {
+        // the leaf blocks, on the workgroups without a prediction when there
+        // are such, two blocks at a time
+        const int G = gridDim.x, b = blockIdx.x;
+        const int nw = count < G ? G - count : G;
+        const int w = count < G ? b - count : b;
+        for (int u = w; w >= 0 && u < nleaf; u += 2 * nw) {
+            const bool two = u + nw < nleaf;
+            const Tile ta = v.leaf[u], tb = v.leaf[two ? u + nw : u];
+            leaf_speeds<T, D>(v, A, tab, ta, lvl, nlev, g, lmax, lcnt, bad, two, tb);
+        }
+        if (__any(bad) && lane == 0) atomicOr(&v.meta->status, 1);
+        __syncthreads();
+        cfl_write_partial<NW>(lmax, lcnt, v);
     }
 }
 

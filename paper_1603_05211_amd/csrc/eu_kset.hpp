@@ -31,16 +31,27 @@ struct KSet {
     void (*restrict_cov)(const View &, int arr, int lvl, int maxblocks, hipStream_t);
     void (*restrict2)(const View &, int arr, int lvl, int nlev, int ghosts, int64_t ndetails, int maxblocks,
                       hipStream_t);
-    void (*predict)(const View &, int arr, int lvl, int nlev, int mode, double theta, int maxblocks, hipStream_t);
+    // cfl: also the CFL partials of the state it leaves (mode 3 on the state,
+    // the launch of the finest levels), one per workgroup: predict_grid()
+    void (*predict)(const View &, int arr, int lvl, int nlev, int mode, double theta, int cfl, int maxblocks,
+                    hipStream_t);
     void (*fv_stage)(const View &, int stage, int lvl, int sub, int record, int maxtiles, int variant,
                      hipStream_t);
     void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*cfl)(const View &, int maxtiles, hipStream_t);
+    void (*cfl_partials)(const View &, int nblocks, hipStream_t);   // the partials alone, nblocks of them
     void (*totals)(const View &, int maxtiles, hipStream_t);
     void (*details)(const View &, int64_t ncell_coarse_levels, hipStream_t);
     void (*composite)(const View &, int lvl, int64_t ncell, hipStream_t);
 };
+
+// workgroups of a prediction launch over maxblocks blocks
+inline int predict_grid(int64_t maxblocks)
+{
+    constexpr int CAP = 1024;
+    return maxblocks < 1 ? 1 : maxblocks > CAP ? CAP : (int)maxblocks;
+}
 
 extern const KSet kset_f64;
 extern const KSet kset_f32;

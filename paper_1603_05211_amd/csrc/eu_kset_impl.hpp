@@ -56,14 +56,14 @@ template <typename T> void restrict2(const View &v, int a, int lvl, int nlev, in
     k_restrict2<T><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, nlev, g0, g1, g2, ghosts, ndet);
 }
 
-template <typename T> void predict(const View &v, int a, int lvl, int nlev, int mode, double theta, int maxb,
-                                   hipStream_t s)
+template <typename T> void predict(const View &v, int a, int lvl, int nlev, int mode, double theta, int cfl,
+                                   int maxb, hipStream_t s)
 {
-    const int nblk = clamp_grid(maxb, 1024);
+    const int nblk = predict_grid(maxb);
     const Grid Gl = v.gt[mode == 1 ? 0 : lvl], Cl = v.gt[mode == 1 ? 0 : lvl - 1];
     const Grid Gh = v.gt[nlev == 2 ? lvl + 1 : (mode == 1 ? 0 : lvl)];
-    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh);
-    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh);
+    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh, cfl);
+    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh, cfl);
 }
 
 // Stage-kernel schedules the autotuner chooses from (variant index):
@@ -131,6 +131,11 @@ template <typename T> void cfl(const View &v, int maxt, hipStream_t s)
     else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     launch_cfl_final(v, nblk, s);
 }
+template <typename T> void cfl_partials(const View &v, int nblk, hipStream_t s)
+{
+    if (v.dim == 2) k_cfl<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
+    else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
+}
 
 template <typename T> void totals(const View &v, int maxt, hipStream_t s)
 {
@@ -167,6 +172,7 @@ template <typename T> KSet make()
     k.copy_level = copy_level<T>;
     k.reflux = reflux<T>;
     k.cfl = cfl<T>;
+    k.cfl_partials = cfl_partials<T>;
     k.totals = totals<T>;
     k.details = details<T>;
     return k;

@@ -426,14 +426,23 @@ __global__ void __launch_bounds__(256) k_cfl_final(View v, int nblk)
     // per-level maxima and the leaf count over the workgroups' partials
     double m[MAXLEV], cnt = 0.0;
     for (int l = 0; l < MAXLEV; ++l) m[l] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-        const double *P = v.partial + (int64_t)b * CFL_STRIDE;
+    constexpr int U = 4;   // partials per thread in flight
+    for (int b0 = 0; b0 < nblk; b0 += U * blockDim.x) {
+        double q[U][MAXLEV + 1];
 #pragma unroll
-        for (int l = 0; l < MAXLEV; ++l) {
-            const double q = P[l];
-            m[l] = q > m[l] ? q : m[l];
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * blockDim.x + threadIdx.x;
+            const double *P = v.partial + (int64_t)(b < nblk ? b : 0) * CFL_STRIDE;
+#pragma unroll
+            for (int l = 0; l <= MAXLEV; ++l) q[u][l] = P[l];
         }
-        cnt = cnt + P[MAXLEV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (b0 + u * (int)blockDim.x + (int)threadIdx.x >= nblk) continue;
+#pragma unroll
+            for (int l = 0; l < MAXLEV; ++l) m[l] = q[u][l] > m[l] ? q[u][l] : m[l];
+            cnt = cnt + q[u][MAXLEV];
+        }
     }
 #pragma unroll
     for (int l = 0; l < MAXLEV; ++l)
