@@ -139,7 +139,10 @@ def traffic_from_profile(workload, precision, cells_per_launch):
         return None, "no counter summary"
     if d.get("source_hash") != source_hash():
         return None, "kernel changed since the counters were taken"
-    return d["traffic_bytes_per_cell"] * cells_per_launch, os.path.relpath(path, ROOT)
+    src = os.path.relpath(path, ROOT)
+    if "fetch_schedule" in d:
+        src += f" (counters taken with stage schedule {d['fetch_schedule']})"
+    return d["traffic_bytes_per_cell"] * cells_per_launch, src
 
 
 def cpu_baseline(workload, budget_s=15.0, seed=0):

@@ -132,6 +132,41 @@ def test_graph_replay_equals_eager():
         assert np.array_equal(a.level(l), b.level(l))
 
 
+def test_dt_across_entry_points():
+    """The time step of a step after a regrid comes from CFL partials the
+    regrid left; entry points between steps that change the state or reuse
+    the partials' memory must not leave stale ones.  The dt sequence and the
+    state stay those of the oracle through every such mix."""
+    h, s = make_pair(2, 4, 16)
+    init_pair(h, s, "quadrant", 5)
+    dts_o, dts_g = [], []
+
+    def both(regrid=True, graph=False):
+        dts_o.append(h.step(h.cfl_number, regrid=regrid))
+        if graph:
+            assert s.advance(1, use_graph=True) == 1
+        else:
+            s.step(regrid)
+        dts_g.append(s.time()[1])
+
+    both()
+    s.conserved_totals()          # reuses the partials' memory
+    both()
+    both(regrid=False)            # a step without regrid leaves no partials
+    both()
+    s.stage_time(2)               # stage passes leave the state as it was
+    both(graph=True)
+    s.conserved_totals()
+    both(graph=True)
+    both()
+    s.mr_decompose()              # projection and details, leaves unchanged
+    both(graph=True)
+    assert np.array_equal(np.array(dts_o), np.array(dts_g))
+    compare_masks(h, s)
+    linf, _ = state_errors(h, s)
+    assert linf.max() <= FP64_TOL
+
+
 def test_t_end_reached_exactly():
     h, s = make_pair(2, 3, 32, t_end=0.01)
     init_pair(h, s, "quadrant", 2)
