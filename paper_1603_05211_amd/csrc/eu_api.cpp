@@ -90,7 +90,7 @@ struct Layout {
     std::vector<int64_t> pbase;
     // scratch offsets
     size_t o_grids, o_act, o_nact, o_code, o_gmask, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
-        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
+        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_lword, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
     size_t scratch = 0, state = 0;
 };
 
@@ -230,6 +230,7 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.ncls = (int)std::min<int64_t>(std::max<int64_t>((lay.nbt + 255) / 256, 1), 256);
     lay.o_cpart = take(sizeof(long long) * eu::NPART * eu::MAXLEV * lay.ncls);
     lay.o_wcnt = take(sizeof(int) * 5 * lay.ncls);
+    lay.o_lword = take(sizeof(unsigned long long) * 2 * lay.ncls);
     lay.o_pbase = take(sizeof(int64_t) * (eu::MAXLEV + 1));
     lay.o_meta = take(sizeof(Meta));
     lay.o_smax = take(8 * lay.ngrid);
@@ -251,6 +252,7 @@ int sync_status(eu_ctx *c)
     int st = 0;
     HIPCHK(c, hipMemcpy(&st, &c->v.meta->status, sizeof(int), hipMemcpyDeviceToHost));
     if (st & 1) return set_err(c, EU_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN)");
+    if (st & 2) return set_err(c, EU_EHIP, "work-list build: a workgroup's wait for the counts before it timed out");
     return EU_OK;
 }
 
@@ -590,6 +592,8 @@ int finish_init(eu_ctx *c)
     HIPCHK(c, hipMemsetAsync(c->v.t, 0, 8 * c->ngrid, c->stream));
     HIPCHK(c, hipMemsetAsync(c->v.dt, 0, 8 * c->ngrid, c->stream));
     HIPCHK(c, hipMemsetAsync(c->v.smax, 0, 8 * c->ngrid, c->stream));
+    // the list build's words start with one epoch
+    HIPCHK(c, hipMemsetAsync(c->v.lword, 0, 2 * sizeof(unsigned long long) * c->v.ncls, c->stream));
     if (c->mode == MODE_HIER) {
         for (int l = c->L - 2; l >= 0; --l)
             c->ks->restrict_full(c->v, ARR_Q, l, c->grids[l].ncell, c->stream);
@@ -717,6 +721,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.cpart = at<long long>(scratch_dev, lay.o_cpart);
     v.ncls = lay.ncls;
     v.wcnt = at<int>(scratch_dev, lay.o_wcnt);
+    v.lword = at<unsigned long long>(scratch_dev, lay.o_lword);
     v.pbase = at<int64_t>(scratch_dev, lay.o_pbase);
     v.meta = at<Meta>(scratch_dev, lay.o_meta);
     v.smax = at<unsigned long long>(scratch_dev, lay.o_smax);

@@ -84,6 +84,8 @@ struct View {
                                       // leaf cells, patch cells
     int ncls;                         // workgroups of the classification kernel
     int *wcnt;                        // per classification workgroup: entries of each list
+    unsigned long long *lword;        // per classification workgroup: its list counts with an
+                                      // epoch, two words (single-launch list build)
     int64_t *pbase;                   // per-level offset into pslot / pcnt
     int64_t pb[MAXLEV + 1];           // the same offsets, by value
     Meta *meta;

@@ -217,6 +217,88 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
 //   bit 3 fresh (level >= 1, in a patch now but not before)
 //   bits 4-7    number of child blocks in finer patches
 // then the block's current patch membership becomes the new one.
+// Classification of block gb (the blocks of every level numbered
+// consecutively): code and ghost mask (written, with the new patch
+// membership); false when the step is done (nothing written).
+template <int D>
+__device__ __forceinline__ bool classify_block(const View &v, int64_t gb, int done, int &code, uint32_t &gm,
+                                               int &lvl, int &nchild)
+{
+    lvl = 0;
+    for (int k = 1; k < MAXLEV && k < v.L; ++k) lvl += gb >= v.gt[k].boff ? 1 : 0;
+    const Grid G = grid_lane(v, lvl);
+    const int nb = G.nb;
+    const int b = (int)(gb - G.boff);
+    const int bx = b % nb, by = (b / nb) % nb, bz = D == 3 ? b / (nb * nb) : 0;
+    // every mask read (the block, its children, its neighbours) is issued
+    // before any is tested
+    const uint8_t na = v.nact[gb];
+    const uint8_t oa = v.act[gb];
+    uint8_t ch[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (lvl + 1 < v.L) {
+        const Grid F = grid_lane(v, lvl + 1);
+        const int zs = D == 3 ? 2 : 1;
+        for (int z = 0; z < zs; ++z)
+            for (int y = 0; y < 2; ++y)
+                for (int x = 0; x < 2; ++x)
+                    ch[x + 2 * (y + 2 * z)] =
+                        v.nact[F.boff + (2 * bx + x) + (int64_t)F.nb * ((2 * by + y) + (int64_t)F.nb * (2 * bz + z))];
+    }
+    uint8_t nbv[27];
+    const int r3 = D == 3 ? 1 : 0;
+    int j = 0;
+    for (int dz = -r3; dz <= r3; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int qx = bcmap(bx + dx, nb, v.bc), qy = bcmap(by + dy, nb, v.bc);
+                const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
+                nbv[j++] = lvl >= 1 ? v.nact[G.boff + qx + (int64_t)nb * (qy + (int64_t)nb * qz)] : 0;
+            }
+    issued((int)na, (int)oa, (int)nbv[0]);
+    if (done) return false;   // read with the masks above: one round trip for both
+    const bool a = na != 0;
+    const bool old = oa != 0;
+    nchild = 0;
+    if (a)
+        for (int i = 0; i < 8; ++i) nchild += ch[i];
+    const int nch_all = D == 2 ? 4 : 8;
+    bool ghost = false;
+    gm = 0;
+    if (!a) {
+        for (int i = 0; i < j; ++i) gm |= (nbv[i] ? 1u : 0u) << i;
+        ghost = gm != 0;
+    }
+    code = 0;
+    if (a && nchild < nch_all) code |= 1;
+    if (a && nchild > 0) code |= 2;
+    if (ghost) code |= 4;
+    if (a && !old && lvl >= 1) code |= 8;
+    code |= nchild << 4;
+    v.code[gb] = (uint8_t)code;
+    v.gmask[gb] = gm;
+    v.act[gb] = a ? 1 : 0;
+    return true;
+}
+
+// Cells per level (leaf, patch) and entries per list of one classified block.
+template <int D>
+__device__ __forceinline__ void count_block(unsigned long long (*part)[NPART], int *lcnt, int lvl, int code,
+                                            int nchild)
+{
+    constexpr int cpb = D == 2 ? BS * BS : BS * BS * BS;
+    constexpr int cpc = cpb >> D;   // cells of a coarse block covered by one child block
+    if (code & 3) {
+        atomicAdd(&part[lvl][0], (unsigned long long)(cpb - nchild * cpc));
+        atomicAdd(&part[lvl][1], (unsigned long long)cpb);
+    }
+    // entries in the leaf, covered, ghost, new, patch lists
+    if (code & 1) atomicAdd(&lcnt[0], 1);
+    if (code & 2) atomicAdd(&lcnt[1], 1);
+    if (code & 4) atomicAdd(&lcnt[2], 1);
+    if (code & 8) atomicAdd(&lcnt[3], 1);
+    if (code & 3) atomicAdd(&lcnt[4], 1);
+}
+
 template <int D>
 __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
 {
@@ -226,75 +308,14 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
     if (threadIdx.x < MAXLEV * NPART) part[threadIdx.x / NPART][threadIdx.x % NPART] = 0ull;
     if (threadIdx.x < 5) lcnt[threadIdx.x] = 0;
     __syncthreads();
-    constexpr int cpb = D == 2 ? BS * BS : BS * BS * BS;
-    constexpr int cpc = cpb >> D;   // cells of a coarse block covered by one child block
     // workgroup w classifies the contiguous range [w chunk, (w+1) chunk)
     const int64_t chunk = (nbt + gridDim.x - 1) / gridDim.x;
     const int64_t g0 = blockIdx.x * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
     for (int64_t gb = g0 + threadIdx.x; gb < g1; gb += blockDim.x) {
-        int lvl = 0;
-        for (int k = 1; k < MAXLEV && k < v.L; ++k) lvl += gb >= v.gt[k].boff ? 1 : 0;
-        const Grid G = grid_lane(v, lvl);
-        const int nb = G.nb;
-        const int b = (int)(gb - G.boff);
-        const int bx = b % nb, by = (b / nb) % nb, bz = D == 3 ? b / (nb * nb) : 0;
-        // every mask read (the block, its children, its neighbours) is issued
-        // before any is tested
-        const uint8_t na = v.nact[gb];
-        const uint8_t oa = v.act[gb];
-        uint8_t ch[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (lvl + 1 < v.L) {
-            const Grid F = grid_lane(v, lvl + 1);
-            const int zs = D == 3 ? 2 : 1;
-            for (int z = 0; z < zs; ++z)
-                for (int y = 0; y < 2; ++y)
-                    for (int x = 0; x < 2; ++x)
-                        ch[x + 2 * (y + 2 * z)] =
-                            v.nact[F.boff + (2 * bx + x) + (int64_t)F.nb * ((2 * by + y) + (int64_t)F.nb * (2 * bz + z))];
-        }
-        uint8_t nbv[27];
-        const int r3 = D == 3 ? 1 : 0;
-        int j = 0;
-        for (int dz = -r3; dz <= r3; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int qx = bcmap(bx + dx, nb, v.bc), qy = bcmap(by + dy, nb, v.bc);
-                    const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
-                    nbv[j++] = lvl >= 1 ? v.nact[G.boff + qx + (int64_t)nb * (qy + (int64_t)nb * qz)] : 0;
-                }
-        issued((int)na, (int)oa, (int)nbv[0]);
-        if (done) break;   // read with the masks above: one round trip for both
-        const bool a = na != 0;
-        const bool old = oa != 0;
-        int nchild = 0;
-        if (a)
-            for (int i = 0; i < 8; ++i) nchild += ch[i];
-        const int nch_all = D == 2 ? 4 : 8;
-        bool ghost = false;
-        uint32_t gm = 0;
-        if (!a) {
-            for (int i = 0; i < j; ++i) gm |= (nbv[i] ? 1u : 0u) << i;
-            ghost = gm != 0;
-        }
-        int code = 0;
-        if (a && nchild < nch_all) code |= 1;
-        if (a && nchild > 0) code |= 2;
-        if (ghost) code |= 4;
-        if (a && !old && lvl >= 1) code |= 8;
-        code |= nchild << 4;
-        v.code[gb] = (uint8_t)code;
-        v.gmask[gb] = gm;
-        v.act[gb] = a ? 1 : 0;
-        if (a) {
-            atomicAdd(&part[lvl][0], (unsigned long long)(cpb - nchild * cpc));
-            atomicAdd(&part[lvl][1], (unsigned long long)cpb);
-        }
-        // entries of this range in the leaf, covered, ghost, new, patch lists
-        if (code & 1) atomicAdd(&lcnt[0], 1);
-        if (code & 2) atomicAdd(&lcnt[1], 1);
-        if (code & 4) atomicAdd(&lcnt[2], 1);
-        if (code & 8) atomicAdd(&lcnt[3], 1);
-        if (code & 3) atomicAdd(&lcnt[4], 1);
+        int code, lvl, nchild;
+        uint32_t gm;
+        if (!classify_block<D>(v, gb, done, code, gm, lvl, nchild)) break;
+        count_block<D>(part, lcnt, lvl, code, nchild);
     }
     if (done) return;
     __syncthreads();
@@ -304,60 +325,47 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
             (long long)part[threadIdx.x / NPART][threadIdx.x % NPART];
 }
 
-// Compaction of the classified blocks into the leaf, covered, ghost, new and
-// all-patch lists (order: level, then block index, x fastest), with the same
-// contiguous ranges as the classification: workgroup w sums the list counts
-// of the ranges before its own and writes its entries from there.  The
-// thread holding the first block of a level records where that level starts
-// in every list.  The last workgroup writes the list lengths.  (The patch
-// table is read from the per pmax-block slots when it is asked for.)
-template <int D>
-__global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
+// Sum over the workgroup of each thread's list counts acc[] into base[].
+__device__ __forceinline__ void workgroup_sum5(int *acc, int (*wsum)[5], int *base)
 {
-    constexpr int NL = 5;                  // leaf, covered, ghost, new, patch blocks
-    __shared__ int base[NL];
-    __shared__ int wsum[4][NL];
-    __shared__ int64_t lstart[MAXLEV + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int W = gridDim.x, w = blockIdx.x;
-    // first reads, independent of each other: the done flag, the level
-    // starts and the list counts of the ranges before this one
-    const int done = v.meta->done;
-    if (tid <= MAXLEV) lstart[tid] = tid < v.L && tid < MAXLEV ? v.gt[tid].boff : nbt;
-    const int64_t chunk = (nbt + W - 1) / W;
-    const int64_t g0 = w * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
-    // codes of the first chunk of this range
-    const int code0 = g0 + tid < g1 ? v.code[g0 + tid] : 0;
-    const uint32_t gm0 = g0 + tid < g1 ? v.gmask[g0 + tid] : 0u;
-    int acc[NL] = {0, 0, 0, 0, 0};
-    for (int i = tid; i < w; i += blockDim.x)
-        for (int k = 0; k < NL; ++k) acc[k] += v.wcnt[(int64_t)i * 5 + k];
-    issued(acc[0], acc[1], acc[2], acc[3], acc[4], code0, gm0);
-    if (done) return;
-    for (int k = 0; k < NL; ++k)
+    for (int k = 0; k < 5; ++k)
         for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o);
     if (lane == 0)
-        for (int k = 0; k < NL; ++k) wsum[wave][k] = acc[k];
+        for (int k = 0; k < 5; ++k) wsum[wave][k] = acc[k];
     __syncthreads();
-    if (tid < NL) {
+    if (tid < 5) {
         int s = 0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wsum[i][tid];
         base[tid] = s;
     }
     __syncthreads();
+}
+
+// Entries of blocks g0 .. g1-1 in the leaf, covered, ghost, new and patch
+// lists, from base[] on (order: level, then block index, x fastest); the
+// thread holding the first block of a level records where that level starts
+// in every list.  block(gb, k) gives the code and ghost mask of block gb, the
+// k-th of this range.
+template <typename F>
+__device__ __forceinline__ void write_lists(const View &v, int64_t g0, int64_t g1, int *base,
+                                            const int64_t *lstart, F block)
+{
+    constexpr int NL = 5;
+    __shared__ int wc[4][NL];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     Tile *lists[NL] = {v.leaf, v.cov, v.ghost, v.fresh, v.actv};
     for (int64_t c = g0; c < g1; c += blockDim.x) {
         const int64_t gb = c + tid;
         int code = 0, lvl = 0;
         uint32_t gm = 0;
         if (gb < g1) {
-            code = (c == g0 ? code0 : v.code[gb]) & 15;
-            gm = c == g0 ? gm0 : v.gmask[gb];
+            block(gb, gb - g0, code, gm);
+            code &= 15;
             if (code & 3) code |= 16;  // bit 4: in a patch
             while (gb >= lstart[lvl + 1]) ++lvl;
         }
         int pre[NL];
-        __shared__ int wc[4][NL];
         for (int k = 0; k < NL; ++k) {
             const unsigned long long mask = __ballot((code >> k) & 1);
             pre[k] = __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
@@ -380,14 +388,145 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
         }
         __syncthreads();
     }
-    if (w != W - 1) return;
-    // the last workgroup has seen every entry: list lengths
-    if (tid < NL)
+}
+
+// The last workgroup has seen every entry: the list lengths.
+__device__ __forceinline__ void write_list_lengths(const View &v, const int *base)
+{
+    const int tid = threadIdx.x;
+    if (tid < 5)
         for (int l = v.L; l <= MAXLEV; ++l) v.meta->loff[tid][l] = base[tid];
     if (tid == 0) {
         v.meta->nleaf = base[0];
         v.meta->nghost = base[2];
     }
+}
+
+// Compaction of the classified blocks into the leaf, covered, ghost, new and
+// all-patch lists, with the same contiguous ranges as the classification:
+// workgroup w sums the list counts of the ranges before its own and writes
+// its entries from there.  (The patch table is read from the per pmax-block
+// slots when it is asked for.)
+template <int D>
+__global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
+{
+    constexpr int NL = 5;                  // leaf, covered, ghost, new, patch blocks
+    __shared__ int base[NL];
+    __shared__ int wsum[4][NL];
+    __shared__ int64_t lstart[MAXLEV + 1];
+    const int tid = threadIdx.x;
+    const int W = gridDim.x, w = blockIdx.x;
+    // first reads, independent of each other: the done flag, the level
+    // starts and the list counts of the ranges before this one
+    const int done = v.meta->done;
+    if (tid <= MAXLEV) lstart[tid] = tid < v.L && tid < MAXLEV ? v.gt[tid].boff : nbt;
+    const int64_t chunk = (nbt + W - 1) / W;
+    const int64_t g0 = w * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
+    // codes of the first chunk of this range
+    const int code0 = g0 + tid < g1 ? v.code[g0 + tid] : 0;
+    const uint32_t gm0 = g0 + tid < g1 ? v.gmask[g0 + tid] : 0u;
+    int acc[NL] = {0, 0, 0, 0, 0};
+    for (int i = tid; i < w; i += blockDim.x)
+        for (int k = 0; k < NL; ++k) acc[k] += v.wcnt[(int64_t)i * 5 + k];
+    issued(acc[0], acc[1], acc[2], acc[3], acc[4], code0, gm0);
+    if (done) return;
+    workgroup_sum5(acc, wsum, base);
+    write_lists(v, g0, g1, base, lstart, [&](int64_t gb, int64_t k, int &code, uint32_t &gm) {
+        code = k < (int64_t)blockDim.x ? code0 : v.code[gb];
+        gm = k < (int64_t)blockDim.x ? gm0 : v.gmask[gb];
+    });
+    if (w == W - 1) write_list_lengths(v, base);
+}
+
+// Classification and compaction in one launch, for ranges of at most
+// LISTS_MAXCHUNK blocks (the codes stay in LDS).  Each workgroup classifies
+// its range, publishes its list counts as two words that carry an epoch
+// one above the previous build's, and adds up the counts of the ranges
+// before its own once their words carry the new epoch.  Only lower-numbered
+// workgroups are waited for, and the wait is bounded: past the bound the
+// workgroup sets status bit 2 and writes no entries.  The words start with
+// one epoch (cleared with the hierarchy) and every build that is not done
+// raises all of them, so they keep one epoch.
+constexpr int LISTS_MAXCHUNK = 1024;
+constexpr int LISTS_MAXSPIN = 1 << 20;
+
+template <int D>
+__global__ void __launch_bounds__(256) k_lists(View v, int64_t nbt)
+{
+    constexpr int NL = 5;
+    __shared__ uint8_t scode[LISTS_MAXCHUNK];
+    __shared__ uint32_t sgm[LISTS_MAXCHUNK];
+    __shared__ unsigned long long part[MAXLEV][NPART];
+    __shared__ int lcnt[NL];
+    __shared__ int base[NL];
+    __shared__ int wsum[4][NL];
+    __shared__ int64_t lstart[MAXLEV + 1];
+    __shared__ int late;
+    const int tid = threadIdx.x;
+    const int W = gridDim.x, w = blockIdx.x;
+    unsigned long long *word = v.lword;
+    const int done = v.meta->done;
+    const unsigned long long own = __hip_atomic_load(word + 2 * w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid < MAXLEV * NPART) part[tid / NPART][tid % NPART] = 0ull;
+    if (tid < NL) lcnt[tid] = 0;
+    if (tid <= MAXLEV) lstart[tid] = tid < v.L && tid < MAXLEV ? v.gt[tid].boff : nbt;
+    if (tid == 0) late = 0;
+    __syncthreads();
+    const int64_t chunk = (nbt + W - 1) / W;
+    const int64_t g0 = w * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
+    for (int64_t gb = g0 + tid; gb < g1; gb += blockDim.x) {
+        int code, lvl, nchild;
+        uint32_t gm;
+        if (!classify_block<D>(v, gb, done, code, gm, lvl, nchild)) break;
+        scode[gb - g0] = (uint8_t)code;
+        sgm[gb - g0] = gm;
+        count_block<D>(part, lcnt, lvl, code, nchild);
+    }
+    if (done) return;
+    __syncthreads();
+    const unsigned long long e = ((own & 0xffffull) + 1) & 0xffffull;
+    if (tid == 0) {
+        // counts of at most LISTS_MAXCHUNK: 16 bits each
+        const unsigned long long c[NL] = {(unsigned long long)lcnt[0], (unsigned long long)lcnt[1],
+                                          (unsigned long long)lcnt[2], (unsigned long long)lcnt[3],
+                                          (unsigned long long)lcnt[4]};
+        __hip_atomic_store(word + 2 * w, e | c[0] << 16 | c[1] << 32 | c[2] << 48, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(word + 2 * w + 1, e | c[3] << 16 | c[4] << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid < MAXLEV * NPART)
+        v.cpart[(int64_t)w * MAXLEV * NPART + tid] = (long long)part[tid / NPART][tid % NPART];
+    // the counts of the ranges before this one: thread i waits for range i
+    // (both of its words read in one trip)
+    int acc[NL] = {0, 0, 0, 0, 0};
+    for (int i = tid; i < w; i += blockDim.x) {
+        unsigned long long x0 = __hip_atomic_load(word + 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long x1 = __hip_atomic_load(word + 2 * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int spin = 0; (x0 & 0xffffull) != e || (x1 & 0xffffull) != e; ++spin) {
+            if (spin == LISTS_MAXSPIN) {
+                late = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            x0 = __hip_atomic_load(word + 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            x1 = __hip_atomic_load(word + 2 * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        acc[0] += (int)((x0 >> 16) & 0xffff);
+        acc[1] += (int)((x0 >> 32) & 0xffff);
+        acc[2] += (int)((x0 >> 48) & 0xffff);
+        acc[3] += (int)((x1 >> 16) & 0xffff);
+        acc[4] += (int)((x1 >> 32) & 0xffff);
+    }
+    workgroup_sum5(acc, wsum, base);   // its barriers also publish late
+    if (late) {
+        if (tid == 0) atomicOr(&v.meta->status, 2);
+        return;
+    }
+    write_lists(v, g0, g1, base, lstart, [&](int64_t, int64_t k, int &code, uint32_t &gm) {
+        code = scode[k];
+        gm = sgm[k];
+    });
+    if (w == W - 1) write_list_lengths(v, base);
 }
 
 // ----------------------------------------------------------------------------
@@ -536,6 +675,11 @@ void launch_cfl_final(const View &v, int nblk, hipStream_t s)
 
 void launch_build_lists(const View &v, int64_t nbt, hipStream_t s)
 {
+    if ((nbt + v.ncls - 1) / v.ncls <= LISTS_MAXCHUNK) {
+        if (v.dim == 2) k_lists<2><<<v.ncls, 256, 0, s>>>(v, nbt);
+        else k_lists<3><<<v.ncls, 256, 0, s>>>(v, nbt);
+        return;
+    }
     if (v.dim == 2) {
         k_classify<2><<<v.ncls, 256, 0, s>>>(v, nbt);
         k_compact<2><<<v.ncls, 256, 0, s>>>(v, nbt);
