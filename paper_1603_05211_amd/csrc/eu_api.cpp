@@ -720,6 +720,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.fcnt = at<int>(scratch_dev, lay.o_fcnt);
     v.cpart = at<long long>(scratch_dev, lay.o_cpart);
     v.ncls = lay.ncls;
+    v.nbt = (int)lay.nbt;
     v.wcnt = at<int>(scratch_dev, lay.o_wcnt);
     v.lword = at<unsigned long long>(scratch_dev, lay.o_lword);
     v.pbase = at<int64_t>(scratch_dev, lay.o_pbase);

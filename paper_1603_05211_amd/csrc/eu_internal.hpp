@@ -10,7 +10,10 @@ namespace eu {
 constexpr int BS = 8;          // block side in cells: the unit of patches and tiles
 constexpr int MAXLEV = 10;
 constexpr int NPART = 2;       // classification partial sums per level
-constexpr int CFL_STRIDE = MAXLEV + 1;   // CFL partials per workgroup: level maxima, leaf count
+// CFL partials, level-major: row l < MAXLEV holds each workgroup's maximum
+// speed on level l, row MAXLEV its leaf count (partial[row * CFL_MAXBLK + b]),
+// so that the final reduction reads each row coalesced
+constexpr int CFL_STRIDE = MAXLEV + 1;   // rows
 constexpr int CFL_MAXBLK = 2048;         // workgroups of the CFL reduction (at most)
 
 // One dense grid: a level of the hierarchy, the single uniform grid, or one
@@ -83,6 +86,7 @@ struct View {
     long long *cpart;                 // per classification workgroup and level (NPART values):
                                       // leaf cells, patch cells
     int ncls;                         // workgroups of the classification kernel
+    int nbt;                          // blocks of every grid (list capacity)
     int *wcnt;                        // per classification workgroup: entries of each list
     unsigned long long *lword;        // per classification workgroup: its list counts with an
                                       // epoch, two words (single-launch list build)

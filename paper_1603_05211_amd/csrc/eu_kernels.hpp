@@ -667,8 +667,9 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
 // dt (second kernel)
 // ----------------------------------------------------------------------------
 // Hierarchy: workgroup b writes its per-level maxima and its count of leaf
-// cells advanced to v.partial[b * CFL_STRIDE ...] (plain stores; the kernel
-// boundary publishes them).  Batch: one atomic max per tile on its instance.
+// cells advanced to column b of the level-major partials (plain stores; the
+// kernel boundary publishes them).  Batch: one atomic max per tile on its
+// instance.
 
 // Signal speed sum_d (|v_d| + c) of a cell from its conserved state (FP64);
 // bad when its density or pressure is not positive.
@@ -711,15 +712,15 @@ __device__ __forceinline__ void cfl_write_partial(const double (*lmax)[MAXLEV], 
                                                   const View &v)
 {
     const int l = threadIdx.x;
-    double *P = v.partial + (int64_t)blockIdx.x * CFL_STRIDE;
+    double *P = v.partial + blockIdx.x;
     if (l < MAXLEV) {
         double mm = lmax[0][l];
         for (int w = 1; w < NW; ++w) mm = lmax[w][l] > mm ? lmax[w][l] : mm;
-        P[l] = mm;
+        P[(int64_t)l * CFL_MAXBLK] = mm;
     } else if (l == MAXLEV) {
         unsigned long long c = lcnt[0];
         if (NW == 4) c = (lcnt[0] + lcnt[1]) + (lcnt[2] + lcnt[3]);
-        P[MAXLEV] = (double)c;
+        P[(int64_t)MAXLEV * CFL_MAXBLK] = (double)c;
     }
 }
 
@@ -936,9 +937,10 @@ __global__ void __launch_bounds__(256) k_restrict_cov(View v, T *A, int lvl)
 // Projection of the covered cells of levels lvl .. lvl+nlev-1 (nlev = 1 or
 // 2) in one launch (Sec. 2.1: a covered cell is the mean of its children),
 // 2D; with ghosts set, in the same launch, the ghost fill of every level
-// (used when lvl .. lvl+nlev-1 are the coarsest levels, projected last).  The covered
-// blocks of the two levels are adjacent in the covered list.  A cell of
-// level lvl+1 is the mean of its four children; a cell of level lvl is the
+// (used when lvl .. lvl+nlev-1 are the coarsest levels, projected last).
+// Every block of the two levels is a work item; those whose code has the
+// covered bit project their covered cells.  A cell of level lvl+1 is the
+// mean of its four children; a cell of level lvl is the
 // mean of its four children, each of which is either final (a leaf) or
 // itself the mean of its own four children.  The four children of a cell
 // lie in one block of the next level and its sixteen grandchildren in one
@@ -1077,11 +1079,12 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
     __shared__ GridTab tab;
     __shared__ T sA[NV][NS];
     __shared__ T sS[NSD], sC[CW * CW];
-    // first reads, independent of each other (the grids of levels lvl,
-    // lvl+1 and lvl+2 come at fixed argument offsets)
+    // Work items: MR details, then every block of the projected levels
+    // (walked directly: its code says whether it holds covered cells), then
+    // the ghost list.  No item waits for the done flag before its first
+    // reads: the flag is tested with them.  The grids of levels lvl, lvl+1
+    // and lvl+2 come at fixed argument offsets.
     const int done = v.meta->done;
-    const int off = v.meta->loff[LST_COV][lvl];
-    const int count = v.meta->loff[LST_COV][lvl + nlev] - off;
     const int ngh = ghosts ? v.meta->nghost : 0;
     // MR details of levels 0 .. L-2 (ndet cells in all, only with lvl = 0):
     // 8x8 blocks of the levels projected here, then chunks of 64 cells of
@@ -1089,13 +1092,15 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
     const int64_t dfirst = nlev == 2 ? g1.coff + g1.ncell : g0.coff + g0.ncell;
     const int nin = ndet ? g0.nb * g0.nb + (nlev == 2 ? g1.nb * g1.nb : 0) : 0;
     const int nch = ndet ? nin + (int)((ndet - dfirst + 63) / 64) : 0;
-    if (ghosts || ndet) grid_tab_load(v, tab);
-    issued(off, count, ngh);
-    if (done) return;
-    if (ghosts || ndet) __syncthreads();
-    for (int t = blockIdx.x; t < count + ngh + nch; t += gridDim.x) {
-        if (t >= count + ngh) {
-            const int r = t - count - ngh;
+    const int nb0 = g0.nb * g0.nb, ncov = nb0 + (nlev == 2 ? g1.nb * g1.nb : 0);
+    const int nitem = nch + ncov + (ghosts ? v.nbt : 0);   // ghost entries: at most one per block
+    if (ghosts || ndet) {
+        grid_tab_load(v, tab);
+        __syncthreads();
+    }
+    for (int t = blockIdx.x; t < nitem; t += gridDim.x) {
+        if (t < nch) {
+            const int r = t;
             if (r < nin) {
                 // 8x8 block of level lvl or lvl+1: the projected densities
                 // of its stencil region and of its children staged in LDS
@@ -1108,6 +1113,7 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
                 const int lx = threadIdx.x % BS, ly = threadIdx.x / BS;
                 const bool act = block_active(v, v.act, G, ox, oy, 0);
                 const bool cov = covered(v.act, F, ox + lx, oy + ly, 0);
+                if (done) break;
                 // every staging read in flight at once (64 threads)
                 T vs[2], vc[4];
 #pragma unroll
@@ -1153,6 +1159,7 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
                 const int x = (int)(i % G.n), y = (int)(i / G.n);
                 const bool act = block_active(v, v.act, G, x, y, 0);
                 const bool cov = covered(v.act, F, x, y, 0);
+                if (done) break;
                 double Dm = 0.0;
                 if (act && cov) {
 #pragma clang fp contract(off)
@@ -1169,11 +1176,13 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
             }
             continue;
         }
-        if (t >= count) {
+        if (t >= nch + ncov) {
             // ghost block of any level: predicted from the level below, whose
             // values are final or, for the levels projected in this pass,
-            // projected here
-            const Tile tl = v.ghost[t - count];
+            // projected here (the entry is read with the count)
+            const int g = t - nch - ncov;
+            const Tile tl = v.ghost[g];
+            if (done || g >= ngh) break;   // so are the later items of this workgroup
             const int lv = tl.grid & ((1 << Tile::GRID_BITS) - 1);
             const uint32_t gm = (uint32_t)tl.grid >> Tile::GRID_BITS;
             const Grid G = grid_tab(tab, lv), Cg = grid_tab(tab, lv - 1);
@@ -1206,15 +1215,20 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
             __syncthreads();
             continue;
         }
-        const Tile tl = v.cov[off + t];
-        const bool lo = tl.grid == lvl;
+        // block of level lvl or lvl+1, when it holds covered cells
+        const int cb = t - nch;
+        const bool lo = cb < nb0;
         const Grid G = lo ? g0 : g1;
         const Grid F1 = lo ? g1 : g2;
         const bool two = nlev == 2 && lo;   // through the children's children
         const Grid F2 = g2;
         const int nb = G.nb;
-        const int x = (tl.block % nb) * BS + threadIdx.x % BS;
-        const int y = ((tl.block / nb) % nb) * BS + threadIdx.x / BS;
+        const int block = lo ? cb : cb - nb0;
+        const int code = v.code[G.boff + block];
+        if (done) break;
+        if (!(code & 2)) continue;
+        const int x = (block % nb) * BS + threadIdx.x % BS;
+        const int y = ((block / nb) % nb) * BS + threadIdx.x / BS;
         const bool cov = covered(v.act, F1, x, y, 0);
         // the children's children lie in block (4x/8, 4y/8) of level +2
         const bool gcov = two && v.act[F2.boff + ((4 * x) >> 3) + (int64_t)F2.nb * ((4 * y) >> 3)] != 0;

@@ -22,67 +22,105 @@ struct FlagArgs {
     int64_t slot0;      // first pmax-block slot of level lvl+1
 };
 
-template <int D>
+// Offset of level k of the split tree in the node-count array: the nodes of
+// levels 0 .. k-1, (R >> j)^D of them each.
+template <int D, int R>
+__host__ __device__ constexpr int tree_offset(int k)
+{
+    int o = 0;
+    for (int j = 0; j < k; ++j) o += D == 2 ? (R >> j) * (R >> j) : (R >> j) * (R >> j) * (R >> j);
+    return o;
+}
+
+// R = pmax / BS (1, 2, 4 or 8): every size below is a compile-time constant,
+// so the loops unroll and no index needs a runtime division.
+template <int D, int R>
 __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
 {
-    constexpr int MAXSUB = D == 2 ? 64 : 512;       // (pmax / BS)^D, pmax <= 64
-    __shared__ int cnt8[MAXSUB];
-    __shared__ uint8_t emit8[MAXSUB];
-    __shared__ int wsum[4];
+    constexpr int NT = 256;                          // threads (the launch uses 256)
+    constexpr int NSUB = D == 2 ? R * R : R * R * R;  // BS-blocks of the pmax block
+    constexpr int K = R == 1 ? 0 : R == 2 ? 1 : R == 4 ? 2 : 3;   // levels of the split tree below the root
+    constexpr int HP = 4 * R;                        // footprint side (level-lvl cells)
+    constexpr int HE = HP + 2;                       // with a one-cell halo
+    constexpr int NRAW = D == 2 ? HE * HE : HE * HE * HE;
+    constexpr int NFOOT = D == 2 ? HP * HP : HP * HP * HP;
+    // level-(lvl+1) cells 2x-2 .. 2x+3 of the footprint's x lie in virtual
+    // level-(lvl+2) blocks (2x-2)>>2 .. (2x+3)>>2: NVB of them per axis
+    constexpr int NVB = ((2 * (HP - 1) + 3) >> 2) - ((-2) >> 2) + 1;
+    constexpr int NNEST = D == 2 ? NVB * NVB : NVB * NVB * NVB;
+    __shared__ int cnt8[NSUB];
+    __shared__ uint8_t emit8[NSUB];
+    __shared__ int wsum[NT / 64];
     // LDS staging of what the flags of the footprint read: the raw flags
     // (significant detail of the cell or of its parent) over the footprint
     // and a one-cell halo, and the new patch masks of level lvl+2 over the
     // blocks the nesting test reaches (virtual block indices; the boundary
     // map is applied when staging: clamping or wrapping a block index is the
     // same as mapping the cells and dividing)
-    constexpr int HM = 32 + 2;                             // footprint side + halo, pmax <= 64
-    constexpr int VM = 32 / 2 + 3;                         // nesting blocks per side
-    __shared__ uint8_t sraw[D == 2 ? HM * HM : HM * HM * HM];
-    __shared__ uint8_t snest[D == 2 ? VM * VM : VM * VM * VM];
+    __shared__ uint8_t sraw[NRAW];
+    __shared__ uint8_t snest[NNEST];
     const int done = v.meta->done;
     const Grid &G = fa.G, &F = fa.F, &Cg = fa.C, &F2 = fa.F2;
     const bool hasc = lvl >= 1, nest = lvl + 2 < v.L;
     const int64_t slot = fa.slot0 + blockIdx.x;
-    const int R = v.pmax / BS;
-    const int nsub = D == 2 ? R * R : R * R * R;
     const int m = blockIdx.x;
     int bp[3] = {0, 0, 0};
     {
-        const int nbp = F.n / v.pmax;
+        const int nbp = F.n / (R * BS);
         int bits = 0;
         while ((1 << bits) < nbp) ++bits;
         for (int k = 0; k < bits; ++k)
             for (int d = 0; d < D; ++d) bp[d] |= ((m >> (k * D + d)) & 1) << k;
     }
-    const int hp = v.pmax / 2, he = hp + 2, n = G.n;
-    const int o0[3] = {bp[0] * hp, bp[1] * hp, D == 3 ? bp[2] * hp : 0};
-    const int nraw = D == 2 ? he * he : he * he * he;
-    for (int i = threadIdx.x; i < nraw; i += blockDim.x) {
-        const int ex = i % he, ey = (i / he) % he, ez = D == 3 ? i / (he * he) : 0;
-        const int qx = bcmap(o0[0] - 1 + ex, n, v.bc), qy = bcmap(o0[1] - 1 + ey, n, v.bc);
-        const int qz = D == 3 ? bcmap(o0[2] - 1 + ez, n, v.bc) : 0;
-        const uint8_t a = v.sig[G.coff + gidx(n, qx, qy, qz)];
-        const uint8_t b = hasc ? v.sig[Cg.coff + gidx(Cg.n, qx >> 1, qy >> 1, qz >> 1)] : 0;
-        sraw[i] = a | b;
-    }
-    // level-(lvl+1) cells 2x-2 .. 2x+3 of the footprint's x lie in virtual
-    // level-(lvl+2) blocks (2x-2)>>2 .. (2x+3)>>2
-    int vb0[3] = {0, 0, 0}, nvb = 1;
-    if (nest) {
-        for (int d = 0; d < D; ++d) vb0[d] = (2 * o0[d] - 2) >> 2;
-        nvb = ((2 * (o0[0] + hp - 1) + 3) >> 2) - vb0[0] + 1;
-        const int nb2 = F2.nb, tot = D == 2 ? nvb * nvb : nvb * nvb * nvb;
-        for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-            int b[3] = {i % nvb, (i / nvb) % nvb, D == 3 ? i / (nvb * nvb) : 0};
-            for (int d = 0; d < D; ++d) {
-                const int q = vb0[d] + b[d];
-                b[d] = v.bc == 1 ? (q < 0 ? q + nb2 : q >= nb2 ? q - nb2 : q) : (q < 0 ? 0 : q >= nb2 ? nb2 - 1 : q);
+    const int n = G.n;
+    const int o0[3] = {bp[0] * HP, bp[1] * HP, D == 3 ? bp[2] * HP : 0};
+    int vb0[3] = {0, 0, 0};
+    for (int d = 0; d < D; ++d) vb0[d] = (2 * o0[d] - 2) >> 2;
+    // every staging read issued before the first LDS store (in chunks of
+    // eight per thread when there are more); addresses are clamped to valid
+    // ones so that no read waits behind a test (the grids of levels lvl-1
+    // and lvl+2 stand in for missing levels with valid ones)
+    constexpr int IR = (NRAW + NT - 1) / NT, IN = (NNEST + NT - 1) / NT, CH = 8;
+    const int nb2 = F2.nb;
+#pragma unroll
+    for (int c0 = 0; c0 < IR + IN; c0 += CH) {
+        uint8_t val[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int it = c0 + u;
+            val[u] = 0;
+            if (it < IR) {
+                const int i0 = threadIdx.x + it * NT, i = i0 < NRAW ? i0 : NRAW - 1;
+                const int ex = i % HE, ey = (i / HE) % HE, ez = D == 3 ? i / (HE * HE) : 0;
+                const int qx = bcmap(o0[0] - 1 + ex, n, v.bc), qy = bcmap(o0[1] - 1 + ey, n, v.bc);
+                const int qz = D == 3 ? bcmap(o0[2] - 1 + ez, n, v.bc) : 0;
+                const uint8_t a = v.sig[G.coff + gidx(n, qx, qy, qz)];
+                const uint8_t b = v.sig[Cg.coff + gidx(Cg.n, qx >> 1, qy >> 1, qz >> 1)];
+                val[u] = a | (hasc ? b : 0);
+            } else if (it < IR + IN) {
+                const int i0 = threadIdx.x + (it - IR) * NT, i = i0 < NNEST ? i0 : NNEST - 1;
+                int b[3] = {i % NVB, (i / NVB) % NVB, D == 3 ? i / (NVB * NVB) : 0};
+                for (int d = 0; d < D; ++d) {
+                    const int q = vb0[d] + b[d];
+                    b[d] = v.bc == 1 ? (q < 0 ? q + nb2 : q >= nb2 ? q - nb2 : q) : (q < 0 ? 0 : q >= nb2 ? nb2 - 1 : q);
+                }
+                val[u] = v.nact[F2.boff + b[0] + (int64_t)nb2 * (b[1] + (int64_t)nb2 * b[2])];
             }
-            snest[i] = v.nact[F2.boff + b[0] + (int64_t)nb2 * (b[1] + (int64_t)nb2 * b[2])];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int it = c0 + u;
+            if (it < IR) {
+                const int i = threadIdx.x + it * NT;
+                if (i < NRAW) sraw[i] = val[u];
+            } else if (it < IR + IN) {
+                const int i = threadIdx.x + (it - IR) * NT;
+                if (i < NNEST) snest[i] = val[u];
+            }
         }
     }
     if (done) return;
-    for (int s = threadIdx.x; s < nsub; s += blockDim.x) {
+    for (int s = threadIdx.x; s < NSUB; s += NT) {
         cnt8[s] = 0;
         emit8[s] = 0;
     }
@@ -90,15 +128,20 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
     // flag of each footprint cell: raw flags dilated by one cell, or the
     // nesting closure (a level-(lvl+1) cell within two cells of the new level
     // lvl+2)
-    const int nfoot = D == 2 ? hp * hp : hp * hp * hp;
     int mine = 0;
-    for (int k = threadIdx.x; k < nfoot; k += blockDim.x) {
-        const int lx = k % hp, ly = (k / hp) % hp, lz = D == 3 ? k / (hp * hp) : 0;
+#pragma unroll
+    for (int it = 0; it < (NFOOT + NT - 1) / NT; ++it) {
+        const int k = threadIdx.x + it * NT;
+        if (k >= NFOOT) break;
+        const int lx = k % HP, ly = (k / HP) % HP, lz = D == 3 ? k / (HP * HP) : 0;
         int any = 0;
+#pragma unroll
         for (int dz = (D == 3 ? 0 : 1); dz <= (D == 3 ? 2 : 1); ++dz)
+#pragma unroll
             for (int dy = 0; dy <= 2; ++dy)
+#pragma unroll
                 for (int dx = 0; dx <= 2; ++dx)
-                    any |= sraw[(lx + dx) + he * ((ly + dy) + (D == 3 ? he * (lz + dz) : 0))];
+                    any |= sraw[(lx + dx) + HE * ((ly + dy) + (D == 3 ? HE * (lz + dz) : 0))];
         if (nest && !any) {
             const int c[3] = {o0[0] + lx, o0[1] + ly, o0[2] + lz};
             int lo[3], hi[3];
@@ -108,7 +151,7 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
             }
             for (int bz = lo[2]; bz <= hi[2]; ++bz)
                 for (int by = lo[1]; by <= hi[1]; ++by)
-                    for (int bx = lo[0]; bx <= hi[0]; ++bx) any |= snest[bx + nvb * (by + nvb * bz)];
+                    for (int bx = lo[0]; bx <= hi[0]; ++bx) any |= snest[bx + NVB * (by + NVB * bz)];
         }
         const bool fl = any != 0;
         v.flag[G.coff + gidx(n, o0[0] + lx, o0[1] + ly, o0[2] + lz)] = fl ? 1 : 0;
@@ -121,31 +164,23 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = mine;
     // flagged-parent counts of every node of the split tree: level k holds
     // the nodes of 2^k BS-blocks per side, (R >> k)^D of them
-    __shared__ int ncnt[MAXSUB + MAXSUB / 4 + 16];
-    __shared__ int lvo[5];
-    __shared__ int wlead[8];
-    int K = 0;
-    while ((1 << K) < R) ++K;
-    if (threadIdx.x == 0) {
-        int o = 0;
-        for (int k = 0; k <= K; ++k) {
-            lvo[k] = o;
-            const int r = R >> k;
-            o += D == 2 ? r * r : r * r * r;
-        }
-    }
+    __shared__ int ncnt[tree_offset<D, R>(K + 1)];
+    __shared__ int wlead[NT / 64];
     __syncthreads();
-    for (int s = threadIdx.x; s < nsub; s += blockDim.x) ncnt[s] = cnt8[s];
+    for (int s = threadIdx.x; s < NSUB; s += NT) ncnt[s] = cnt8[s];
+#pragma unroll
     for (int k = 1; k <= K; ++k) {
         __syncthreads();
         const int r = R >> k, rc = R >> (k - 1);
         const int nn = D == 2 ? r * r : r * r * r;
-        for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+        const int o1 = tree_offset<D, R>(k - 1), o2 = tree_offset<D, R>(k);
+        for (int i = threadIdx.x; i < nn; i += NT) {
             const int ix = i % r, iy = (i / r) % r, iz = D == 3 ? i / (r * r) : 0;
             int c = 0;
+#pragma unroll
             for (int ch = 0; ch < (1 << D); ++ch)
-                c += ncnt[lvo[k - 1] + (2 * ix + (ch & 1)) + rc * ((2 * iy + ((ch >> 1) & 1)) + rc * (2 * iz + ((ch >> 2) & 1)))];
-            ncnt[lvo[k] + i] = c;
+                c += ncnt[o1 + (2 * ix + (ch & 1)) + rc * ((2 * iy + ((ch >> 1) & 1)) + rc * (2 * iz + ((ch >> 2) & 1)))];
+            ncnt[o2 + i] = c;
         }
     }
     __syncthreads();
@@ -153,30 +188,36 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
     // recursion over children, x fastest, meets it), walks from the root to
     // the node that is emitted as a patch (or is empty).  The node's first
     // sub-block writes the patch; patches are ranked by that Morton order.
-    int *out = v.pslot + slot * (int64_t)nsub * 5;
+    int *out = v.pslot + slot * (int64_t)NSUB * 5;
     int nlead_total = 0;
-    for (int c0 = 0; c0 < nsub; c0 += blockDim.x) {
+#pragma unroll
+    for (int c0 = 0; c0 < NSUB; c0 += NT) {
         const int mc = c0 + threadIdx.x;   // Morton code of this lane's sub-block
         int sx = 0, sy = 0, sz = 0;
+#pragma unroll
         for (int b = 0; b < K; ++b) {
             sx |= ((mc >> (b * D)) & 1) << b;
             sy |= ((mc >> (b * D + 1)) & 1) << b;
             if (D == 3) sz |= ((mc >> (b * D + 2)) & 1) << b;
         }
         int emit_k = -1;
-        if (mc < nsub) {
+        if (mc < NSUB) {
+#pragma unroll
             for (int k = K; k >= 0; --k) {
                 const int r = R >> k;
-                const int c = ncnt[lvo[k] + (sx >> k) + r * ((sy >> k) + r * (sz >> k))];
+                const int c = ncnt[tree_offset<D, R>(k) + (sx >> k) + r * ((sy >> k) + r * (sz >> k))];
                 if (c == 0) break;
                 const int S = BS << k, hsz = S / 2;
                 const long long cells = D == 2 ? (long long)hsz * hsz : (long long)hsz * hsz * hsz;
-                if (S == v.pmin || (double)c >= v.eta * (double)cells) { emit_k = k; break; }
+                if (S == v.pmin || (double)c >= v.eta * (double)cells) {
+                    emit_k = k;
+                    break;
+                }
             }
         }
         const int em = (1 << (emit_k < 0 ? 0 : emit_k)) - 1;
         const bool lead = emit_k >= 0 && (sx & em) == 0 && (sy & em) == 0 && (sz & em) == 0;
-        if (mc < nsub) emit8[sx + R * (sy + R * sz)] = emit_k >= 0 ? 1 : 0;
+        if (mc < NSUB) emit8[sx + R * (sy + R * sz)] = emit_k >= 0 ? 1 : 0;
         const unsigned long long mask = __ballot(lead);
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         if (lane == 0) wlead[wave] = __popcll(mask);
@@ -185,22 +226,23 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
         for (int w = 0; w < wave; ++w) pos += wlead[w];
         if (lead) {
             out[5 * pos + 0] = lvl + 1;
-            out[5 * pos + 1] = bp[0] * v.pmax + sx * BS;
-            out[5 * pos + 2] = bp[1] * v.pmax + sy * BS;
-            out[5 * pos + 3] = D == 3 ? bp[2] * v.pmax + sz * BS : 0;
+            out[5 * pos + 1] = bp[0] * R * BS + sx * BS;
+            out[5 * pos + 2] = bp[1] * R * BS + sy * BS;
+            out[5 * pos + 3] = D == 3 ? bp[2] * R * BS + sz * BS : 0;
             out[5 * pos + 4] = BS << emit_k;
         }
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) nlead_total += wlead[w];
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) nlead_total += wlead[w];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         int tot = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) tot += wsum[w];
         v.fcnt[slot] = tot;
         v.pcnt[slot] = nlead_total;
     }
-    __syncthreads();
-    for (int s = threadIdx.x; s < nsub; s += blockDim.x) {
+    for (int s = threadIdx.x; s < NSUB; s += NT) {
         const int sx = s % R, sy = (s / R) % R, sz = D == 3 ? s / (R * R) : 0;
         const int bx = bp[0] * R + sx, by = bp[1] * R + sy, bz = D == 3 ? bp[2] * R + sz : 0;
         v.nact[F.boff + bx + (int64_t)F.nb * (by + (int64_t)F.nb * bz)] = emit8[s];
@@ -538,70 +580,86 @@ __global__ void __launch_bounds__(256) k_lists(View v, int64_t nbt)
 // A step that starts at t >= t_end is marked done and skipped by every later
 // kernel of the step; otherwise the step is committed: t += dt, steps += 1,
 // leaf updates counted.  One workgroup.
+__global__ void __launch_bounds__(256) k_cfl_final_batch(View v)
+{
+#pragma clang fp contract(off)
+    for (int g = threadIdx.x; g < v.ngrid; g += blockDim.x) {
+        const unsigned long long b = atomicExch(&v.smax[g], 0ull);
+        const double s = __longlong_as_double((long long)b);
+        double dt = b ? (v.cfl * v.grids[g].dx) / s : 0.0;
+        const double t = v.t[g];
+        if (dt > v.t_end - t) dt = v.t_end - t;
+        if (!(dt > 0.0)) dt = 0.0;
+        v.dt[g] = dt;
+        v.t[g] = t + dt;
+    }
+    if (threadIdx.x == 0) {
+        v.meta->done = 0;
+        v.meta->steps += 1;
+    }
+}
+
+// Hierarchy of NG levels: the partial rows of those levels and the count
+// row; thread i reads columns 8i .. 8i+7 of each row in 16-byte loads, all
+// issued before any is used (columns past nblk are read from the row's
+// capacity and masked).  One workgroup of 256 threads: its cost is its
+// dependent instruction count, so only the rows of the NG levels are read.
+template <int NG>
 __global__ void __launch_bounds__(256) k_cfl_final(View v, int nblk)
 {
 #pragma clang fp contract(off)
-    if (v.mode != MODE_HIER) {
-        for (int g = threadIdx.x; g < v.ngrid; g += blockDim.x) {
-            const unsigned long long b = atomicExch(&v.smax[g], 0ull);
-            const double s = __longlong_as_double((long long)b);
-            double dt = b ? (v.cfl * v.grids[g].dx) / s : 0.0;
-            const double t = v.t[g];
-            if (dt > v.t_end - t) dt = v.t_end - t;
-            if (!(dt > 0.0)) dt = 0.0;
-            v.dt[g] = dt;
-            v.t[g] = t + dt;
-        }
-        if (threadIdx.x == 0) {
-            v.meta->done = 0;
-            v.meta->steps += 1;
-        }
-        return;
-    }
-    __shared__ double smax[4][MAXLEV];
+    static_assert(CFL_MAXBLK == 8 * 256, "eight columns per thread");
+    __shared__ double smax[4][NG];
     __shared__ double scnt[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double t = v.t[0];
-    // per-level maxima and the leaf count over the workgroups' partials
-    double m[MAXLEV], cnt = 0.0;
-    for (int l = 0; l < MAXLEV; ++l) m[l] = 0.0;
-    constexpr int U = 4;   // partials per thread in flight
-    for (int b0 = 0; b0 < nblk; b0 += U * blockDim.x) {
-        double q[U][MAXLEV + 1];
+    const int c0 = 8 * threadIdx.x;
+    double q[NG + 1][8];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int b = b0 + u * blockDim.x + threadIdx.x;
-            const double *P = v.partial + (int64_t)(b < nblk ? b : 0) * CFL_STRIDE;
+    for (int l = 0; l <= NG; ++l) {
+        const int row = l < NG ? l : MAXLEV;
+        const double2 *p = (const double2 *)(v.partial + (int64_t)row * CFL_MAXBLK + c0);
 #pragma unroll
-            for (int l = 0; l <= MAXLEV; ++l) q[u][l] = P[l];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (b0 + u * (int)blockDim.x + (int)threadIdx.x >= nblk) continue;
-#pragma unroll
-            for (int l = 0; l < MAXLEV; ++l) m[l] = q[u][l] > m[l] ? q[u][l] : m[l];
-            cnt = cnt + q[u][MAXLEV];
+        for (int u = 0; u < 4; ++u) {
+            const double2 x = p[u];
+            q[l][2 * u] = x.x;
+            q[l][2 * u + 1] = x.y;
         }
     }
+    double m[NG], cnt = 0.0;
 #pragma unroll
-    for (int l = 0; l < MAXLEV; ++l)
+    for (int l = 0; l < NG; ++l) m[l] = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const bool in = c0 + u < nblk;
+#pragma unroll
+        for (int l = 0; l < NG; ++l) {
+            const double x = in ? q[l][u] : 0.0;
+            m[l] = x > m[l] ? x : m[l];
+        }
+        cnt = cnt + (in ? q[NG][u] : 0.0);
+    }
+#pragma unroll
+    for (int l = 0; l < NG; ++l)
         for (int o = 32; o > 0; o >>= 1) {
             const double r = __shfl_xor(m[l], o);
             m[l] = r > m[l] ? r : m[l];
         }
     for (int o = 32; o > 0; o >>= 1) cnt = cnt + __shfl_xor(cnt, o);
     if (lane == 0) {
-        for (int l = 0; l < MAXLEV; ++l) smax[wave][l] = m[l];
+#pragma unroll
+        for (int l = 0; l < NG; ++l) smax[wave][l] = m[l];
         scnt[wave] = cnt;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
     double dt = __builtin_inf();
-    for (int l = 0; l < v.ngrid; ++l) {
+#pragma unroll
+    for (int l = 0; l < NG; ++l) {
         double sm = smax[0][l];
         for (int w = 1; w < 4; ++w) sm = smax[w][l] > sm ? smax[w][l] : sm;
         if (sm > 0.0) {
-            double d = (v.cfl * v.grids[l].dx) / sm;
+            double d = (v.cfl * v.gt[l].dx) / sm;
             if (v.lts) d = d * (double)(1 << l);
             if (d < dt) dt = d;
         }
@@ -611,7 +669,8 @@ __global__ void __launch_bounds__(256) k_cfl_final(View v, int nblk)
     if (dt > v.t_end - t) dt = v.t_end - t;
     if (v.lts) {
         double dl = dt;
-        for (int l = 0; l < v.ngrid; ++l) {
+#pragma unroll
+        for (int l = 0; l < NG; ++l) {
             v.dt[l] = dl;
             dl = dl * 0.5;
         }
@@ -664,13 +723,42 @@ void launch_flag_tile(const View &v, int lvl, int nblocks, hipStream_t s)
     fa.C = v.gt[lvl >= 1 ? lvl - 1 : lvl];
     fa.F2 = v.gt[lvl + 2 < v.L ? lvl + 2 : lvl];
     fa.slot0 = v.pb[lvl + 1];
-    if (v.dim == 2) k_flag_tile<2><<<nblocks, 256, 0, s>>>(v, lvl, fa);
-    else k_flag_tile<3><<<nblocks, 256, 0, s>>>(v, lvl, fa);
+    const int R = v.pmax / BS;
+    if (v.dim == 2) {
+        switch (R) {
+        case 1: k_flag_tile<2, 1><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        case 2: k_flag_tile<2, 2><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        case 4: k_flag_tile<2, 4><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        default: k_flag_tile<2, 8><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        }
+    } else {
+        switch (R) {
+        case 1: k_flag_tile<3, 1><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        case 2: k_flag_tile<3, 2><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        case 4: k_flag_tile<3, 4><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        default: k_flag_tile<3, 8><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        }
+    }
 }
 
 void launch_cfl_final(const View &v, int nblk, hipStream_t s)
 {
-    k_cfl_final<<<1, 256, 0, s>>>(v, nblk);
+    if (v.mode != MODE_HIER) {
+        k_cfl_final_batch<<<1, 256, 0, s>>>(v);
+        return;
+    }
+    switch (v.ngrid) {
+    case 1: k_cfl_final<1><<<1, 256, 0, s>>>(v, nblk); break;
+    case 2: k_cfl_final<2><<<1, 256, 0, s>>>(v, nblk); break;
+    case 3: k_cfl_final<3><<<1, 256, 0, s>>>(v, nblk); break;
+    case 4: k_cfl_final<4><<<1, 256, 0, s>>>(v, nblk); break;
+    case 5: k_cfl_final<5><<<1, 256, 0, s>>>(v, nblk); break;
+    case 6: k_cfl_final<6><<<1, 256, 0, s>>>(v, nblk); break;
+    case 7: k_cfl_final<7><<<1, 256, 0, s>>>(v, nblk); break;
+    case 8: k_cfl_final<8><<<1, 256, 0, s>>>(v, nblk); break;
+    case 9: k_cfl_final<9><<<1, 256, 0, s>>>(v, nblk); break;
+    default: k_cfl_final<MAXLEV><<<1, 256, 0, s>>>(v, nblk); break;
+    }
 }
 
 void launch_build_lists(const View &v, int64_t nbt, hipStream_t s)
