@@ -556,22 +556,56 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
         const int oz = D == 3 ? (tl.block / (nb * nb)) * B : 0;
         const T *S = src + G.off;
         const int64_t N = G.ncell;
-        for (int c = threadIdx.x; c < C::NE; c += NT) {
-            const int lx = c % E, ly = (c / E) % E, lz = D == 3 ? c / (E * E) : 0;
-            const int x = bcmap(ox + lx - H, n, v.bc);
-            const int y = bcmap(oy + ly - H, n, v.bc);
-            const int z = D == 3 ? bcmap(oz + lz - H, n, v.bc) : 0;
-            const int64_t id = gidx32(n, x, y, z);
-            T q[NV], w[NV];
+        // the tile with its halo.  2D: every read of the thread's cells
+        // (states and masks, from valid addresses) issued before any is used;
+        // 3D: cell by cell (the registers of all of them would cost occupancy)
+        if constexpr (D == 2) {
+            constexpr int IE = (C::NE + NT - 1) / NT;
+            T qh[IE][NV];
+            uint8_t cvb[IE], acb[IE];
 #pragma unroll
-            for (int f = 0; f < NV; ++f) q[f] = S[f * N + id];
-            const bool cv = hasf && covered(v.act, GF, x, y, z);
-            const bool ac = record && block_active(v, v.act, G, x, y, z);
-            cons2prim<T, D>(q, w, g);
+            for (int u = 0; u < IE; ++u) {
+                const int c0 = threadIdx.x + u * NT, c = c0 < C::NE ? c0 : C::NE - 1;
+                const int lx = c % E, ly = c / E;
+                const int x = bcmap(ox + lx - H, n, v.bc), y = bcmap(oy + ly - H, n, v.bc);
+                const int64_t id = gidx32(n, x, y, 0);
 #pragma unroll
-            for (int f = 0; f < NV; ++f) sW[f][c] = w[f];
-            sCov[c] = cv ? 1 : 0;
-            if (record) sAct[c] = ac ? 1 : 0;
+                for (int f = 0; f < NV; ++f) qh[u][f] = S[f * N + id];
+                // children's block on the finer grid (block 0 of the own grid
+                // when there is none: a valid address, the value unused)
+                const int64_t cb = hasf ? GF.boff + (int64_t)gidx32(GF.nb, x >> 2, y >> 2, 0) : G.boff;
+                cvb[u] = v.act[cb];
+                acb[u] = v.act[G.boff + (int64_t)gidx32(G.nb, x >> 3, y >> 3, 0)];
+            }
+#pragma unroll
+            for (int u = 0; u < IE; ++u) {
+                const int c = threadIdx.x + u * NT;
+                if (c >= C::NE) break;
+                T w[NV];
+                cons2prim<T, D>(qh[u], w, g);
+#pragma unroll
+                for (int f = 0; f < NV; ++f) sW[f][c] = w[f];
+                sCov[c] = hasf && cvb[u] != 0 ? 1 : 0;
+                if (record) sAct[c] = acb[u] != 0 ? 1 : 0;
+            }
+        } else {
+            for (int c = threadIdx.x; c < C::NE; c += NT) {
+                const int lx = c % E, ly = (c / E) % E, lz = c / (E * E);
+                const int x = bcmap(ox + lx - H, n, v.bc);
+                const int y = bcmap(oy + ly - H, n, v.bc);
+                const int z = bcmap(oz + lz - H, n, v.bc);
+                const int64_t id = gidx32(n, x, y, z);
+                T q[NV], w[NV];
+#pragma unroll
+                for (int f = 0; f < NV; ++f) q[f] = S[f * N + id];
+                const bool cv = hasf && covered(v.act, GF, x, y, z);
+                const bool ac = record && block_active(v, v.act, G, x, y, z);
+                cons2prim<T, D>(q, w, g);
+#pragma unroll
+                for (int f = 0; f < NV; ++f) sW[f][c] = w[f];
+                sCov[c] = cv ? 1 : 0;
+                if (record) sAct[c] = ac ? 1 : 0;
+            }
         }
         // base state of the thread's cells, read while the fluxes are computed
         T qb[C::CPT][NV];
