@@ -100,9 +100,9 @@ def timed_advance(s, steps, use_graph=True):
 
 def kernel_profile(s, steps, reps=5):
     """Average duration of the finite-volume stage kernel: after each of the
-    next `steps` time steps, `reps` back-to-back first-stage passes on that
-    state between two HIP events on the library's stream (the state is left
-    unchanged).  Returns ms per launch, launches timed, cells per launch and
+    next `steps` time steps, `reps` first-stage passes on that state replayed
+    from one HIP graph between two HIP events on the library's stream (the
+    state is left unchanged).  Returns ms per launch, launches timed, cells per launch and
     launches per pass."""
     ms_sum, cells_sum, launches = 0.0, 0, 0
     lpp = 1

@@ -226,17 +226,18 @@ int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
  * axis, axis by axis from per-cell face states, or all axes in one pass).  In FP64 every schedule gives bit-identical results;
  * in FP32 they agree to rounding (the compiler contracts each differently).
  * eu_autotune times each schedule (reps launches of the first stage on the
- * current state, HIP events on the context's stream; the state is left
- * unchanged) and keeps the fastest: *variant_host receives it, ms_host
+ * current state replayed from one HIP graph, HIP events on the context's
+ * stream; the state is left unchanged) and keeps the fastest: *variant_host receives it, ms_host
  * (nullable, EU_STAGE_SCHEDULES entries) the mean time of each.
  * eu_set_variant forces one (0 .. EU_STAGE_SCHEDULES-1).  Both drop captured
  * graphs. */
 int eu_autotune(eu_ctx *ctx, int reps, int *variant_host, float *ms_host);
 
 /* Duration of the finite-volume stage kernel on the current state, with the
- * current schedule: one untimed pass of the first stage (Sec. 2.2, the
- * midpoint rule's predictor), then reps passes back to back between two HIP
- * events on the context's stream; the state is left unchanged.  A pass is one
+ * current schedule: reps passes of the first stage (Sec. 2.2, the midpoint
+ * rule's predictor) captured in one HIP graph, replayed once untimed and
+ * once between two HIP events on the context's stream (eager launches on the
+ * default stream); the state is left unchanged.  A pass is one
  * launch (global time step, batch) or one launch per level (local time
  * stepping).  *ms_host: mean milliseconds per pass; *cells_host: cells one
  * pass advances (leaves; patch cells of every level with local time stepping;

@@ -264,9 +264,9 @@ class Solver:
         return var.value, list(ms)
 
     def stage_time(self, reps: int = 10):
-        """Mean duration of one first-stage pass on the current state (HIP
-        events around reps back-to-back passes); returns (ms, cells advanced
-        per pass, launches per pass)."""
+        """Mean duration of one first-stage pass on the current state (reps
+        passes replayed from one HIP graph between two HIP events); returns
+        (ms, cells advanced per pass, launches per pass)."""
         ms, cells, nl = C.c_float(0.0), C.c_int64(0), C.c_int(0)
         self._check(self._lib.eu_stage_time(self._ctx, reps, C.byref(ms), C.byref(cells), C.byref(nl)),
                     "eu_stage_time")

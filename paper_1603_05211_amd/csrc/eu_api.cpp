@@ -531,11 +531,37 @@ int time_stage1(eu_ctx *c, int var, int reps, float *ms_out)
         (void)hipEventDestroy(e0);
         return set_err(c, EU_EHIP, "hipEventCreate failed");
     }
-    stage1_pass(c, var);
+    // the passes replayed from one graph (as a step is), so that the host's
+    // launch rate does not pace them; eager launches on the default stream
+    hipGraphExec_t ge = nullptr;
+    if (c->stream) {
+        hipGraph_t g;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int r = 0; r < reps; ++r) stage1_pass(c, var);
+            e = hipStreamEndCapture(c->stream, &g);
+            if (e == hipSuccess) {
+                e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) ge = nullptr;
+            }
+        }
+        if (!ge) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return set_err(c, EU_EHIP, "stage timing: graph capture failed: %s", hipGetErrorString(e));
+        }
+        (void)hipGraphLaunch(ge, c->stream);   // untimed replay
+    } else {
+        stage1_pass(c, var);
+    }
     (void)hipEventRecord(e0, c->stream);
-    for (int r = 0; r < reps; ++r) stage1_pass(c, var);
+    if (ge) (void)hipGraphLaunch(ge, c->stream);
+    else
+        for (int r = 0; r < reps; ++r) stage1_pass(c, var);
     (void)hipEventRecord(e1, c->stream);
     hipError_t err = hipEventSynchronize(e1);
+    if (ge) (void)hipGraphExecDestroy(ge);
     float ms = 0.f;
     if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);

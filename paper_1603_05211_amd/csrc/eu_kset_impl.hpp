@@ -69,9 +69,10 @@ template <typename T> void predict(const View &v, int a, int lvl, int nlev, int 
 // Stage-kernel schedules the autotuner chooses from (variant index):
 //   2D: 0 = 64 threads, per-axis faces; 1 = 64 threads, merged faces;
 //       2 = 128 threads, per-axis;      3 = 128 threads, merged;
-//       4 = 64 threads, per-axis with per-cell face states;
+//       4 = 192 threads, merged (one face per thread, 144 faces);
 //       5 = 128 threads, per-axis with per-cell face states.
-//   3D: the same with 256 and 512 threads.
+//   3D: 0-3 and 5 the same with 256 and 512 threads; 4 = 256 threads,
+//       per-axis with per-cell face states.
 template <typename T, int D, int NT, int M>
 void fv_launch(const View &v, int nblk, const T *src, T *out, double fac, int lvl, int sub, int record,
                hipStream_t s)
@@ -82,7 +83,10 @@ void fv_launch(const View &v, int nblk, const T *src, T *out, double fac, int lv
 template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, int record, int maxt,
                                     int variant, hipStream_t s)
 {
-    const int nblk = xcd_grid(maxt, 16384);
+    // a 2D hierarchy has at most a few thousand leaf tiles: 2048 workgroups
+    // take them all at once, and fewer idle workgroups are dispatched (a
+    // batch or a 3D grid needs the larger grid to fill the chip)
+    const int nblk = xcd_grid(maxt, v.dim == 2 && v.mode == MODE_HIER ? 2048 : 16384);
     const T *src = (const T *)(stage == 1 ? v.Q : v.Qs);
     T *out = (T *)(stage == 1 ? v.Qs : v.Q);
     const double fac = stage == 1 ? 0.5 : 1.0;
@@ -91,7 +95,7 @@ template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, 
         case 1: fv_launch<T, 2, 64, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
         case 2: fv_launch<T, 2, 128, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
         case 3: fv_launch<T, 2, 128, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 4: fv_launch<T, 2, 64, 2>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 4: fv_launch<T, 2, 192, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
         case 5: fv_launch<T, 2, 128, 2>(v, nblk, src, out, fac, lvl, sub, record, s); break;
         default: fv_launch<T, 2, 64, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
         }
