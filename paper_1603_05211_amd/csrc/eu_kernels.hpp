@@ -1431,14 +1431,26 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
             const int ax = bcmap(qx0 + sx, Cg.n, v.bc), ay = bcmap(qy0 + sy, Cg.n, v.bc);
             const int az = D == 3 ? bcmap(qz0 + sz, Cg.n, v.bc) : 0;
             const int64_t ic = Cg.off + gidx(Cg.n, ax, ay, az);
-            // in a new block of level lvl: predicted here from level lvl-1
-            const bool pre = up && (v.code[Cg.boff + gidx(Cg.nb, ax >> 3, ay >> 3, az >> 3)] & 8) != 0;
+            if (up) {
+                // a cell of a new block of level lvl is predicted here from
+                // level lvl-1: both candidates read with the block's code, in
+                // one round trip, and the value selected
+                const int code = v.code[Cg.boff + gidx(Cg.nb, ax >> 3, ay >> 3, az >> 3)];
+                T pv[NV], sv[NV];
+#pragma unroll
+                for (int f = 0; f < NV; ++f) {
+                    pv[f] = predict_child<T, D, T>(A + Cl.off + f * Cl.ncell, Cl.n, v.bc, ax >> 1, ay >> 1, az >> 1,
+                                                   ax & 1, ay & 1, az & 1);
+                    sv[f] = A[ic + f * Cg.ncell];
+                }
+                const bool pre = (code & 8) != 0;
+#pragma unroll
+                for (int f = 0; f < NV; ++f) sA[f][i] = pre ? pv[f] : sv[f];
+                continue;
+            }
 #pragma unroll
             for (int f = 0; f < NV; ++f) {
-                if (pre) {
-                    sA[f][i] = predict_child<T, D, T>(A + Cl.off + f * Cl.ncell, Cl.n, v.bc, ax >> 1, ay >> 1,
-                                                      az >> 1, ax & 1, ay & 1, az & 1);
-                } else if (mode == 2) {
+                if (mode == 2) {
                     const T om = T(1) - (T)theta;
                     sA[f][i] = om * ((const T *)v.Qo)[ic + f * Cg.ncell] + (T)theta * ((const T *)v.Q)[ic + f * Cg.ncell];
                 } else {
