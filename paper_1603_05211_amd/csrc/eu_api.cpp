@@ -18,6 +18,9 @@
 
 using namespace eu;
 
+// state of the CFL slots (host view)
+enum { CFL_ZERO = 0, CFL_READY = 1, CFL_STALE = 2 };
+
 struct eu_ctx {
     eu_config cfg;
     std::vector<int32_t> sides;
@@ -33,7 +36,7 @@ struct eu_ctx {
     std::vector<int64_t> pbase; // per level: first pmax-block slot (levels 1 .. L-1)
     bool initialized = false;
     int variant = 0;            // stage-kernel schedule (eu_autotune)
-    int cfl_parts = 0;          // CFL partials of the current state left by the last regrid (0: none)
+    int cfl_state = 0;          // CFL slots: CFL_ZERO, CFL_READY (of the current state) or CFL_STALE
     std::string err;
     // graphs: [0] step with regrid, [1] step without
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -90,7 +93,7 @@ struct Layout {
     std::vector<int64_t> pbase;
     // scratch offsets
     size_t o_grids, o_act, o_nact, o_code, o_gmask, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
-        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_lword, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_partial, o_totals, o_goff, o_gcnt;
+        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_lword, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_partial, o_cfls, o_totals, o_goff, o_gcnt;
     size_t scratch = 0, state = 0;
 };
 
@@ -236,8 +239,9 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_smax = take(8 * lay.ngrid);
     lay.o_dt = take(8 * lay.ngrid);
     lay.o_t = take(8 * lay.ngrid);
-    // per-tile partial totals, or the CFL reduction's per-workgroup maxima
-    lay.o_partial = take(8 * std::max<int64_t>(lay.nv * lay.max_tiles, (int64_t)eu::CFL_MAXBLK * eu::CFL_STRIDE));
+    // per-tile partial totals
+    lay.o_partial = take(8 * std::max<int64_t>(lay.nv * lay.max_tiles, 1));
+    lay.o_cfls = take(8 * (int64_t)eu::cfl_slot(eu::CFL_STRIDE, 0));
     lay.o_totals = take(8 * lay.nv * lay.ngroups);
     lay.o_goff = take(sizeof(int) * lay.ngroups);
     lay.o_gcnt = take(sizeof(int) * lay.ngroups);
@@ -336,13 +340,30 @@ void seq_ghost(eu_ctx *c, int arr)
     if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, 1, 0.0, 0, (int)(c->nbt), c->stream);
 }
 
-// dt of the step: from the CFL partials the last regrid left, when the state
-// has not changed since, else from a reduction over the leaves
+// CFL slots of the current state: left by the last regrid when the state
+// has not changed since, else a reduction over the leaves (from zero)
+void cfl_ready(eu_ctx *c)
+{
+    if (c->cfl_state != CFL_READY) c->ks->cfl_slots(c->v, c->max_tiles, c->stream);
+    c->cfl_state = CFL_READY;
+}
+// The state changed: slots that held its partials are stale.
+void cfl_stale(eu_ctx *c)
+{
+    if (c->cfl_state == CFL_READY) c->cfl_state = CFL_STALE;
+}
+
+// dt of the step from the CFL slots (one-wave reduction kernel, which clears
+// them), or per instance for a batch
 void seq_cfl(eu_ctx *c)
 {
-    if (c->cfl_parts > 0) launch_cfl_final(c->v, c->cfl_parts, c->stream);
-    else c->ks->cfl(c->v, c->max_tiles, c->stream);
-    c->cfl_parts = 0;
+    if (c->mode != MODE_HIER) {
+        c->ks->cfl(c->v, c->max_tiles, c->stream);
+        return;
+    }
+    cfl_ready(c);
+    launch_cfl_final(c->v, c->stream);
+    c->cfl_state = CFL_ZERO;
 }
 
 void prof_begin(eu_ctx *c, hipEvent_t *a)
@@ -403,16 +424,9 @@ int predict_launches(const eu_ctx *c, int *lvl, int *nlev, int64_t *maxb)
     return n;
 }
 
-// Workgroups of the launch that leaves the CFL partials at the end of a
-// regrid (0: a regrid leaves none).
-int fused_cfl_grid(const eu_ctx *c)
-{
-    if (c->mode != MODE_HIER || c->L < 2) return 0;
-    int lvl[MAXLEV], nlev[MAXLEV];
-    int64_t maxb[MAXLEV];
-    const int n = predict_launches(c, lvl, nlev, maxb);
-    return predict_grid(maxb[n - 1]);
-}
+// Whether a step (with regrid) leaves the CFL slots of the next one: the
+// last prediction launch of the regrid of a hierarchy of two levels or more.
+bool step_leaves_slots(const eu_ctx *c) { return c->mode == MODE_HIER && c->L >= 2; }
 
 // flags, closure and tiling (finest first), lists, then either the
 // prediction of new cells and ghost cells (coarse to fine, two levels per
@@ -425,16 +439,19 @@ void seq_flag_tile(eu_ctx *c, bool prolong)
         launch_flag_tile(c->v, l, (int)ipow(nbp, c->dim), c->stream);
     }
     launch_build_lists(c->v, c->nbt, c->stream);
-    c->cfl_parts = 0;
+    cfl_stale(c);
     if (prolong) {
         int lvl[MAXLEV], nlev[MAXLEV];
         int64_t maxb[MAXLEV];
         const int n = predict_launches(c, lvl, nlev, maxb);
         for (int i = 0; i < n; ++i) {
             const int fuse = i == n - 1 && c->mode == MODE_HIER ? 1 : 0;
+            // the last launch adds into the CFL slots: they must be zero
+            if (fuse && c->cfl_state != CFL_ZERO)
+                launch_fill_u8((uint8_t *)c->v.cfls, 8 * (int64_t)cfl_slot(CFL_STRIDE, 0), 0, c->stream);
             c->ks->predict(c->v, ARR_Q, lvl[i], nlev[i], 3, 0.0, fuse,
                            (int)std::min<int64_t>(maxb[i], INT32_MAX), c->stream);
-            if (fuse) c->cfl_parts = predict_grid(maxb[i]);
+            if (fuse) c->cfl_state = CFL_READY;
         }
     } else {
         seq_ghost(c, ARR_Q);
@@ -471,8 +488,8 @@ void lts_advance(eu_ctx *c, int l, int k)
 
 void seq_step(eu_ctx *c, bool regrid)
 {
-    seq_cfl(c);
     const bool rg = regrid && c->L > 1;
+    seq_cfl(c);
     if (c->v.lts) {
         lts_advance(c, 0, 0);
         if (rg) {
@@ -506,7 +523,8 @@ void drop_graphs(eu_ctx *c)
 void stage1_pass(eu_ctx *c, int var)
 {
     if (c->v.lts)
-        for (int l = 0; l < c->L; ++l) c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, c->stream);
+        for (int l = 0; l < c->L; ++l)
+            c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, c->stream);
     else
         c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, var, c->stream);
 }
@@ -613,7 +631,8 @@ InitArgs make_init(const eu_ctx *c, const eu_problem *p, int inst)
 // data; ghost fill.  t = 0.
 int finish_init(eu_ctx *c)
 {
-    c->cfl_parts = 0;
+    HIPCHK(c, hipMemsetAsync(c->v.cfls, 0, 8 * (size_t)cfl_slot(CFL_STRIDE, 0), c->stream));
+    c->cfl_state = CFL_ZERO;
     HIPCHK(c, hipMemsetAsync(c->v.meta, 0, sizeof(Meta), c->stream));
     HIPCHK(c, hipMemsetAsync(c->v.t, 0, 8 * c->ngrid, c->stream));
     HIPCHK(c, hipMemsetAsync(c->v.dt, 0, 8 * c->ngrid, c->stream));
@@ -755,6 +774,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.dt = at<double>(scratch_dev, lay.o_dt);
     v.t = at<double>(scratch_dev, lay.o_t);
     v.partial = at<double>(scratch_dev, lay.o_partial);
+    v.cfls = at<unsigned long long>(scratch_dev, lay.o_cfls);
     v.totals = at<double>(scratch_dev, lay.o_totals);
     v.grp_off = at<int>(scratch_dev, lay.o_goff);
     v.grp_cnt = at<int>(scratch_dev, lay.o_gcnt);
@@ -813,7 +833,7 @@ int eu_set_finest(eu_ctx *c, int inst, const double *q_host)
     if (!c || !q_host) return EU_EINVAL;
     const int g = c->mode == MODE_BATCH ? inst : c->L - 1;
     if (g < 0 || g >= c->ngrid) return set_err(c, EU_EINVAL, "bad instance");
-    c->cfl_parts = 0;
+    cfl_stale(c);
     const Grid &G = c->grids[g];
     const int64_t n = c->nv * G.ncell;
     if (c->cfg.precision == EU_FP64) {
@@ -832,7 +852,7 @@ int eu_mr_decompose(eu_ctx *c)
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
     if (c->mode != MODE_HIER) return set_err(c, EU_EINVAL, "a batch has no hierarchy");
-    c->cfl_parts = 0;
+    cfl_stale(c);
     if (!seq_restrict(c, ARR_Q, false, true)) seq_details(c);
     return check_launch(c);
 }
@@ -857,7 +877,7 @@ int eu_project(eu_ctx *c, int mode)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
-    c->cfl_parts = 0;
+    cfl_stale(c);
     if (mode == EU_RESTRICT) seq_restrict(c, ARR_Q);
     else if (mode == EU_PROLONG) {
         for (int l = 1; l < c->L; ++l)
@@ -885,7 +905,7 @@ int eu_fv_step(eu_ctx *c)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
-    c->cfl_parts = 0;
+    cfl_stale(c);
     if (c->v.lts) {
         lts_advance(c, 0, 0);
         seq_ghost(c, ARR_Q);
@@ -912,13 +932,11 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
     HIPCHK(c, hipMemcpy(&s0, &c->v.meta->steps, sizeof(int), hipMemcpyDeviceToHost));
     if (use_graph && !c->prof) {
         if (!c->stream) return set_err(c, EU_EINVAL, "graph capture needs a non-default stream");
-        // the graph starts from the CFL partials its last step leaves: the
-        // first replay needs them of the current state
-        const int nf = fused_cfl_grid(c);
-        if (nf && c->cfl_parts != nf) {
-            c->ks->cfl_partials(c->v, nf, c->stream);
-            c->cfl_parts = nf;
-        }
+        // a step that leaves the CFL slots of the next starts from them:
+        // the first replay needs them of the current state; otherwise the
+        // step computes them itself, and the capture must record that
+        if (step_leaves_slots(c)) cfl_ready(c);
+        else if (c->cfl_state == CFL_READY) c->cfl_state = CFL_STALE;
         if (!c->gexec[0]) {
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -952,7 +970,6 @@ int eu_conserved_totals(eu_ctx *c, double *totals_host)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
-    c->cfl_parts = 0;   // the totals reuse the partials' memory
     c->ks->totals(c->v, c->max_tiles, c->stream);
     launch_totals_final(c->v, c->ngroups, c->stream);
     int r = check_launch(c);

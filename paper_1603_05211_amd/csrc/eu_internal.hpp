@@ -10,11 +10,18 @@ namespace eu {
 constexpr int BS = 8;          // block side in cells: the unit of patches and tiles
 constexpr int MAXLEV = 10;
 constexpr int NPART = 2;       // classification partial sums per level
-// CFL partials, level-major: row l < MAXLEV holds each workgroup's maximum
-// speed on level l, row MAXLEV its leaf count (partial[row * CFL_MAXBLK + b]),
-// so that the final reduction reads each row coalesced
+// CFL slots: row l < MAXLEV holds, in each of CFL_NSLOT slots, the largest
+// signal speed on level l over the workgroups that add into that slot
+// (workgroup b into slot b mod CFL_NSLOT, atomic max of the FP64 bits, which
+// order like the non-negative speeds); row MAXLEV the count of leaf cells
+// advanced (atomic add).  Each slot has a 128-byte line of its own: atomics
+// on one line serialise.  The slots start at zero and their reader clears
+// them.
 constexpr int CFL_STRIDE = MAXLEV + 1;   // rows
+constexpr int CFL_NSLOT = 64;            // slots per row
+constexpr int CFL_LINE = 16;             // 8-byte words per slot (one 128-byte line)
 constexpr int CFL_MAXBLK = 2048;         // workgroups of the CFL reduction (at most)
+__host__ __device__ constexpr int cfl_slot(int row, int slot) { return (row * CFL_NSLOT + slot) * CFL_LINE; }
 
 // One dense grid: a level of the hierarchy, the single uniform grid, or one
 // instance of a batch.  Field f of cell (x, y, z) lives at
@@ -96,6 +103,7 @@ struct View {
     unsigned long long *smax;         // per grid: max wave-speed sum (FP64 bits)
     double *dt, *t;                   // per grid (batch) or entry 0 (hierarchy)
     double *partial;                  // per tile x nv partial totals
+    unsigned long long *cfls;         // CFL slots (cfl_slot())
     double *totals;                   // per group x nv
     const int *grp_off, *grp_cnt;     // batch: tile range of each instance
     int64_t nslot;                    // pmax blocks of levels 1 .. L-1

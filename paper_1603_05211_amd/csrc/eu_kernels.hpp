@@ -740,21 +740,21 @@ __device__ __forceinline__ void cfl_tile_done(double (*lmax)[MAXLEV], unsigned l
     }
 }
 
-// The workgroup's partials: maxima over its waves and the leaf count.
+// The workgroup's maxima over its waves and its leaf count, added into CFL
+// slot blockIdx.x mod CFL_NSLOT (vector atomics; zeros add nothing).
 template <int NW>
-__device__ __forceinline__ void cfl_write_partial(const double (*lmax)[MAXLEV], const unsigned long long *lcnt,
-                                                  const View &v)
+__device__ __forceinline__ void cfl_publish(const double (*lmax)[MAXLEV], const unsigned long long *lcnt,
+                                            const View &v)
 {
-    const int l = threadIdx.x;
-    double *P = v.partial + blockIdx.x;
-    if (l < MAXLEV) {
+    const int l = threadIdx.x, slot = blockIdx.x % CFL_NSLOT;
+    if (l < MAXLEV && l < v.L) {
         double mm = lmax[0][l];
         for (int w = 1; w < NW; ++w) mm = lmax[w][l] > mm ? lmax[w][l] : mm;
-        P[(int64_t)l * CFL_MAXBLK] = mm;
+        if (mm > 0.0) atomicMax(v.cfls + cfl_slot(l, slot), (unsigned long long)__double_as_longlong(mm));
     } else if (l == MAXLEV) {
         unsigned long long c = lcnt[0];
         if (NW == 4) c = (lcnt[0] + lcnt[1]) + (lcnt[2] + lcnt[3]);
-        P[(int64_t)MAXLEV * CFL_MAXBLK] = (double)c;
+        if (c) atomicAdd(v.cfls + cfl_slot(MAXLEV, slot), c);
     }
 }
 
@@ -814,7 +814,7 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
     }
     if (__any(bad) && lane == 0) atomicOr(&v.meta->status, 1);
     __syncthreads();
-    if (hier) cfl_write_partial<4>(lmax, lcnt, v);
+    if (hier) cfl_publish<4>(lmax, lcnt, v);
 }
 
 // ----------------------------------------------------------------------------
@@ -1503,7 +1503,7 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
         }
         if (__any(bad) && lane == 0) atomicOr(&v.meta->status, 1);
         __syncthreads();
-        cfl_write_partial<NW>(lmax, lcnt, v);
+        cfl_publish<NW>(lmax, lcnt, v);
     }
 }
 

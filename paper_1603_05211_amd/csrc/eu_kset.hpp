@@ -31,16 +31,16 @@ struct KSet {
     void (*restrict_cov)(const View &, int arr, int lvl, int maxblocks, hipStream_t);
     void (*restrict2)(const View &, int arr, int lvl, int nlev, int ghosts, int64_t ndetails, int maxblocks,
                       hipStream_t);
-    // cfl: also the CFL partials of the state it leaves (mode 3 on the state,
-    // the launch of the finest levels), one per workgroup: predict_grid()
+    // cfl: also the CFL slots of the state it leaves (mode 3 on the state,
+    // the launch of the finest levels; the slots must be zero)
     void (*predict)(const View &, int arr, int lvl, int nlev, int mode, double theta, int cfl, int maxblocks,
                     hipStream_t);
     void (*fv_stage)(const View &, int stage, int lvl, int sub, int record, int maxtiles, int variant,
                      hipStream_t);
     void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
-    void (*cfl)(const View &, int maxtiles, hipStream_t);
-    void (*cfl_partials)(const View &, int nblocks, hipStream_t);   // the partials alone, nblocks of them
+    void (*cfl)(const View &, int maxtiles, hipStream_t);           // batch: maxima and dt
+    void (*cfl_slots)(const View &, int maxtiles, hipStream_t);     // hierarchy: the CFL slots, from zero
     void (*totals)(const View &, int maxtiles, hipStream_t);
     void (*details)(const View &, int64_t ncell_coarse_levels, hipStream_t);
     void (*composite)(const View &, int lvl, int64_t ncell, hipStream_t);
@@ -59,7 +59,7 @@ extern const KSet kset_f32;
 // precision-independent mesh kernels (eu_mesh.hip)
 void launch_flag_tile(const View &, int lvl, int nblocks, hipStream_t);
 void launch_build_lists(const View &, int64_t nblocks_total, hipStream_t);
-void launch_cfl_final(const View &, int nblocks_cfl, hipStream_t);
+void launch_cfl_final(const View &, hipStream_t);
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t val, hipStream_t);
 void launch_totals_final(const View &, int ngroups, hipStream_t);
 

@@ -125,18 +125,20 @@ template <typename T> void reflux(const View &v, int lvl, int maxb, hipStream_t 
     else k_reflux<T, 3><<<nblk, 256, 0, s>>>(v, lvl);
 }
 
+// Batch: per-instance maxima (atomics), then dt per instance.
 template <typename T> void cfl(const View &v, int maxt, hipStream_t s)
 {
-    // one wave per tile (up to CFL_MAXBLK workgroups), then one workgroup
-    // turns the partial maxima into dt
-    // (2D tiles are light: fewer workgroups keep the finishing kernel short)
     const int nblk = clamp_grid((maxt + 3) / 4, v.dim == 2 ? 512 : CFL_MAXBLK);
     if (v.dim == 2) k_cfl<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
-    launch_cfl_final(v, nblk, s);
+    launch_cfl_final(v, s);
 }
-template <typename T> void cfl_partials(const View &v, int nblk, hipStream_t s)
+// Hierarchy: the CFL slots of the current state, from zero (one wave per
+// tile; 2D tiles are light: fewer workgroups suffice)
+template <typename T> void cfl_slots(const View &v, int maxt, hipStream_t s)
 {
+    launch_fill_u8((uint8_t *)v.cfls, 8 * (int64_t)cfl_slot(CFL_STRIDE, 0), 0, s);
+    const int nblk = clamp_grid((maxt + 3) / 4, v.dim == 2 ? 512 : CFL_MAXBLK);
     if (v.dim == 2) k_cfl<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
 }
@@ -176,7 +178,7 @@ template <typename T> KSet make()
     k.copy_level = copy_level<T>;
     k.reflux = reflux<T>;
     k.cfl = cfl<T>;
-    k.cfl_partials = cfl_partials<T>;
+    k.cfl_slots = cfl_slots<T>;
     k.totals = totals<T>;
     k.details = details<T>;
     return k;

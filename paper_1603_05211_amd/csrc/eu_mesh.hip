@@ -599,72 +599,46 @@ __global__ void __launch_bounds__(256) k_cfl_final_batch(View v)
     }
 }
 
-// Hierarchy of NG levels: the partial rows of those levels and the count
-// row; thread i reads columns 8i .. 8i+7 of each row in 16-byte loads, all
-// issued before any is used (columns past nblk are read from the row's
-// capacity and masked).  One workgroup of 256 threads: its cost is its
-// dependent instruction count, so only the rows of the NG levels are read.
+// Hierarchy of NG levels: one wave reads the CFL slots of those levels and
+// of the leaf count (lane j slot j), clears them for the next producers,
+// and lane 0 turns the maxima into dt and commits the step.
 template <int NG>
-__global__ void __launch_bounds__(256) k_cfl_final(View v, int nblk)
+__global__ void __launch_bounds__(64) k_cfl_final(View v)
 {
 #pragma clang fp contract(off)
-    static_assert(CFL_MAXBLK == 8 * 256, "eight columns per thread");
-    __shared__ double smax[4][NG];
-    __shared__ double scnt[4];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    static_assert(CFL_NSLOT == 64, "one slot per lane");
+    const int lane = threadIdx.x;
     const double t = v.t[0];
-    const int c0 = 8 * threadIdx.x;
-    double q[NG + 1][8];
+    unsigned long long q[NG + 1];
 #pragma unroll
-    for (int l = 0; l <= NG; ++l) {
-        const int row = l < NG ? l : MAXLEV;
-        const double2 *p = (const double2 *)(v.partial + (int64_t)row * CFL_MAXBLK + c0);
+    for (int l = 0; l < NG; ++l) q[l] = v.cfls[cfl_slot(l, lane)];
+    q[NG] = v.cfls[cfl_slot(MAXLEV, lane)];
+    double sm[NG];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double2 x = p[u];
-            q[l][2 * u] = x.x;
-            q[l][2 * u + 1] = x.y;
-        }
-    }
-    double m[NG], cnt = 0.0;
-#pragma unroll
-    for (int l = 0; l < NG; ++l) m[l] = 0.0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const bool in = c0 + u < nblk;
-#pragma unroll
-        for (int l = 0; l < NG; ++l) {
-            const double x = in ? q[l][u] : 0.0;
-            m[l] = x > m[l] ? x : m[l];
-        }
-        cnt = cnt + (in ? q[NG][u] : 0.0);
-    }
-#pragma unroll
-    for (int l = 0; l < NG; ++l)
+    for (int l = 0; l < NG; ++l) {
+        double m = __longlong_as_double((long long)q[l]);
         for (int o = 32; o > 0; o >>= 1) {
-            const double r = __shfl_xor(m[l], o);
-            m[l] = r > m[l] ? r : m[l];
+            const double r = __shfl_xor(m, o);
+            m = r > m ? r : m;
         }
-    for (int o = 32; o > 0; o >>= 1) cnt = cnt + __shfl_xor(cnt, o);
-    if (lane == 0) {
-#pragma unroll
-        for (int l = 0; l < NG; ++l) smax[wave][l] = m[l];
-        scnt[wave] = cnt;
+        sm[l] = m;
     }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
+    unsigned long long cnt = q[NG];
+    for (int o = 32; o > 0; o >>= 1) cnt += (unsigned long long)__shfl_xor((long long)cnt, o);
+#pragma unroll
+    for (int l = 0; l < NG; ++l) v.cfls[cfl_slot(l, lane)] = 0ull;
+    v.cfls[cfl_slot(MAXLEV, lane)] = 0ull;
+    if (lane != 0) return;
     double dt = __builtin_inf();
 #pragma unroll
     for (int l = 0; l < NG; ++l) {
-        double sm = smax[0][l];
-        for (int w = 1; w < 4; ++w) sm = smax[w][l] > sm ? smax[w][l] : sm;
-        if (sm > 0.0) {
-            double d = (v.cfl * v.gt[l].dx) / sm;
+        if (sm[l] > 0.0) {
+            double d = (v.cfl * v.gt[l].dx) / sm[l];
             if (v.lts) d = d * (double)(1 << l);
             if (d < dt) dt = d;
         }
     }
-    const long long upd = (long long)((scnt[0] + scnt[1]) + (scnt[2] + scnt[3]));
+    const long long upd = (long long)cnt;
     const int done = t < v.t_end ? 0 : 1;
     if (dt > v.t_end - t) dt = v.t_end - t;
     if (v.lts) {
@@ -741,23 +715,23 @@ void launch_flag_tile(const View &v, int lvl, int nblocks, hipStream_t s)
     }
 }
 
-void launch_cfl_final(const View &v, int nblk, hipStream_t s)
+void launch_cfl_final(const View &v, hipStream_t s)
 {
     if (v.mode != MODE_HIER) {
         k_cfl_final_batch<<<1, 256, 0, s>>>(v);
         return;
     }
     switch (v.ngrid) {
-    case 1: k_cfl_final<1><<<1, 256, 0, s>>>(v, nblk); break;
-    case 2: k_cfl_final<2><<<1, 256, 0, s>>>(v, nblk); break;
-    case 3: k_cfl_final<3><<<1, 256, 0, s>>>(v, nblk); break;
-    case 4: k_cfl_final<4><<<1, 256, 0, s>>>(v, nblk); break;
-    case 5: k_cfl_final<5><<<1, 256, 0, s>>>(v, nblk); break;
-    case 6: k_cfl_final<6><<<1, 256, 0, s>>>(v, nblk); break;
-    case 7: k_cfl_final<7><<<1, 256, 0, s>>>(v, nblk); break;
-    case 8: k_cfl_final<8><<<1, 256, 0, s>>>(v, nblk); break;
-    case 9: k_cfl_final<9><<<1, 256, 0, s>>>(v, nblk); break;
-    default: k_cfl_final<MAXLEV><<<1, 256, 0, s>>>(v, nblk); break;
+    case 1: k_cfl_final<1><<<1, 64, 0, s>>>(v); break;
+    case 2: k_cfl_final<2><<<1, 64, 0, s>>>(v); break;
+    case 3: k_cfl_final<3><<<1, 64, 0, s>>>(v); break;
+    case 4: k_cfl_final<4><<<1, 64, 0, s>>>(v); break;
+    case 5: k_cfl_final<5><<<1, 64, 0, s>>>(v); break;
+    case 6: k_cfl_final<6><<<1, 64, 0, s>>>(v); break;
+    case 7: k_cfl_final<7><<<1, 64, 0, s>>>(v); break;
+    case 8: k_cfl_final<8><<<1, 64, 0, s>>>(v); break;
+    case 9: k_cfl_final<9><<<1, 64, 0, s>>>(v); break;
+    default: k_cfl_final<MAXLEV><<<1, 64, 0, s>>>(v); break;
     }
 }
 
