@@ -112,7 +112,10 @@ typedef struct eu_ctx eu_ctx;
 int eu_query_sizes(const eu_config *cfg, size_t *state_bytes, size_t *scratch_bytes);
 
 /* Create a context on caller buffers of at least the queried sizes (device
- * memory, 256-byte aligned).  *out receives the context. */
+ * memory, 256-byte aligned).  *out receives the context.  The work lists of
+ * a regrid are built in one launch, or in two for ranges of more than 1024
+ * blocks; the environment variable EU_LIST_BUILD=2, read here, selects the
+ * two-launch build for every hierarchy (same lists; for tests). */
 int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes,
               void *scratch_dev, size_t scratch_bytes, eu_ctx **out);
 

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -765,6 +766,12 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.fcnt = at<int>(scratch_dev, lay.o_fcnt);
     v.cpart = at<long long>(scratch_dev, lay.o_cpart);
     v.ncls = lay.ncls;
+    {
+        // EU_LIST_BUILD=2: the two-kernel list build also where one launch
+        // would do (it is otherwise reached only by very large hierarchies)
+        const char *lb = std::getenv("EU_LIST_BUILD");
+        v.lists2 = lb && lb[0] == '2' ? 1 : 0;
+    }
     v.nbt = (int)lay.nbt;
     v.wcnt = at<int>(scratch_dev, lay.o_wcnt);
     v.lword = at<unsigned long long>(scratch_dev, lay.o_lword);

@@ -93,6 +93,8 @@ struct View {
     long long *cpart;                 // per classification workgroup and level (NPART values):
                                       // leaf cells, patch cells
     int ncls;                         // workgroups of the classification kernel
+    int lists2;                       // build the lists with two kernels (ranges past the
+                                      // single launch's LDS, or forced for tests)
     int nbt;                          // blocks of every grid (list capacity)
     int *wcnt;                        // per classification workgroup: entries of each list
     unsigned long long *lword;        // per classification workgroup: its list counts with an

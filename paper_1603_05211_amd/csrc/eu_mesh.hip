@@ -128,12 +128,13 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
     // flag of each footprint cell: raw flags dilated by one cell, or the
     // nesting closure (a level-(lvl+1) cell within two cells of the new level
     // lvl+2)
-    int mine = 0;
+    int mine = 0;   // flagged cells of this wave (ballot counts, lane-uniform)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int it = 0; it < (NFOOT + NT - 1) / NT; ++it) {
         const int k = threadIdx.x + it * NT;
-        if (k >= NFOOT) break;
-        const int lx = k % HP, ly = (k / HP) % HP, lz = D == 3 ? k / (HP * HP) : 0;
+        const bool in = k < NFOOT;
+        const int lx = k % HP, ly = (k / HP) % HP, lz = D == 3 ? (k / (HP * HP)) % HP : 0;
         int any = 0;
 #pragma unroll
         for (int dz = (D == 3 ? 0 : 1); dz <= (D == 3 ? 2 : 1); ++dz)
@@ -153,15 +154,20 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
                 for (int by = lo[1]; by <= hi[1]; ++by)
                     for (int bx = lo[0]; bx <= hi[0]; ++bx) any |= snest[bx + NVB * (by + NVB * bz)];
         }
-        const bool fl = any != 0;
-        v.flag[G.coff + gidx(n, o0[0] + lx, o0[1] + ly, o0[2] + lz)] = fl ? 1 : 0;
-        if (fl) {
-            atomicAdd(&cnt8[(lx >> 2) + R * ((ly >> 2) + R * (lz >> 2))], 1);
-            ++mine;
+        const bool fl = in && any != 0;
+        if (in) v.flag[G.coff + gidx(n, o0[0] + lx, o0[1] + ly, o0[2] + lz)] = fl ? 1 : 0;
+        const unsigned long long bal = __ballot(fl);
+        mine += __popcll(bal);
+        if constexpr (D == 2 && R == 4) {
+            // a wave holds four footprint rows of 16 cells: sub-blocks
+            // (lane mod 16) / 4 = j, whole; lane j counts sub-block j
+            const int sy = (it * NT + wave * 64) / (4 * HP);
+            if (lane < 4) cnt8[lane + R * sy] = __popcll(bal & (0x000F000F000F000Full << (4 * lane)));
+        } else {
+            if (fl) atomicAdd(&cnt8[(lx >> 2) + R * ((ly >> 2) + R * (lz >> 2))], 1);
         }
     }
-    for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = mine;
+    if (lane == 0) wsum[wave] = mine;
     // flagged-parent counts of every node of the split tree: level k holds
     // the nodes of 2^k BS-blocks per side, (R >> k)^D of them
     __shared__ int ncnt[tree_offset<D, R>(K + 1)];
@@ -200,26 +206,29 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
             sy |= ((mc >> (b * D + 1)) & 1) << b;
             if (D == 3) sz |= ((mc >> (b * D + 2)) & 1) << b;
         }
+        // the walk from the root stops at the first node, from the top, that
+        // is empty (then every node below it is) or meets the split rule: the
+        // emitted node is the highest nonempty node that meets it (every
+        // level's count read at once)
         int emit_k = -1;
         if (mc < NSUB) {
+            int cn[K + 1];
 #pragma unroll
-            for (int k = K; k >= 0; --k) {
+            for (int k = 0; k <= K; ++k) {
                 const int r = R >> k;
-                const int c = ncnt[tree_offset<D, R>(k) + (sx >> k) + r * ((sy >> k) + r * (sz >> k))];
-                if (c == 0) break;
+                cn[k] = ncnt[tree_offset<D, R>(k) + (sx >> k) + r * ((sy >> k) + r * (sz >> k))];
+            }
+#pragma unroll
+            for (int k = 0; k <= K; ++k) {
                 const int S = BS << k, hsz = S / 2;
                 const long long cells = D == 2 ? (long long)hsz * hsz : (long long)hsz * hsz * hsz;
-                if (S == v.pmin || (double)c >= v.eta * (double)cells) {
-                    emit_k = k;
-                    break;
-                }
+                if (cn[k] > 0 && (S == v.pmin || (double)cn[k] >= v.eta * (double)cells)) emit_k = k;
             }
         }
         const int em = (1 << (emit_k < 0 ? 0 : emit_k)) - 1;
         const bool lead = emit_k >= 0 && (sx & em) == 0 && (sy & em) == 0 && (sz & em) == 0;
         if (mc < NSUB) emit8[sx + R * (sy + R * sz)] = emit_k >= 0 ? 1 : 0;
         const unsigned long long mask = __ballot(lead);
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         if (lane == 0) wlead[wave] = __popcll(mask);
         __syncthreads();
         int pos = nlead_total + __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
@@ -737,7 +746,7 @@ void launch_cfl_final(const View &v, hipStream_t s)
 
 void launch_build_lists(const View &v, int64_t nbt, hipStream_t s)
 {
-    if ((nbt + v.ncls - 1) / v.ncls <= LISTS_MAXCHUNK) {
+    if (!v.lists2 && (nbt + v.ncls - 1) / v.ncls <= LISTS_MAXCHUNK) {
         if (v.dim == 2) k_lists<2><<<v.ncls, 256, 0, s>>>(v, nbt);
         else k_lists<3><<<v.ncls, 256, 0, s>>>(v, nbt);
         return;

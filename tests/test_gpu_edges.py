@@ -92,3 +92,14 @@ def test_periodic_3d_adaptive():
     check(h, s, 3)
     T1 = s.conserved_totals()
     assert np.all(np.abs(T1 - T0) <= 2e-13 * np.maximum(1.0, np.abs(T0)))
+
+
+def test_two_launch_list_build_matches(monkeypatch):
+    """The two-launch list build (classification, then compaction), which
+    only very large hierarchies reach by themselves, forced on a 2D adaptive
+    run: masks, flags, patch tables, time steps and state as the oracle's."""
+    monkeypatch.setenv("EU_LIST_BUILD", "2")
+    say("two-launch list build")
+    h, s = pair(2, 4, 16)
+    init_pair(h, s, "quadrant", 13)
+    check(h, s, 4)
