@@ -1372,9 +1372,12 @@ __device__ __forceinline__ void leaf_speeds(const View &v, const T *A, const Gri
 // also leaves the CFL partials of the new hierarchy, as k_cfl would compute
 // them from the state it leaves: the new blocks of its levels take the speeds
 // of the leaf cells they predict, the leaf tiles every other leaf block.
+// direct (mode 3 without cfl): the work items are the blocks of the levels
+// themselves, each taken when its code marks it new or ghost (no list read
+// at a device offset).
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode, double theta, int nlev, Grid Gl,
-                                                 Grid Cl, Grid Gh, int cfl)
+                                                 Grid Cl, Grid Gh, int cfl, int direct)
 {
     constexpr int W = BS / 2 + 2, NS = D == 2 ? W * W : W * W * W;
     constexpr int NW = D == 2 ? 1 : 4;   // waves per workgroup
@@ -1385,20 +1388,22 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
     // first reads, independent of each other (grid index = level)
     const int done = v.meta->done;
     int off0 = 0, cnt0 = 0, off1 = 0, cnt1 = 0;   // ranges in the new and ghost lists
-    if (mode == 0 || mode == 3) {
+    if (!direct && (mode == 0 || mode == 3)) {
         off0 = v.meta->loff[LST_NEW][lvl];
         cnt0 = v.meta->loff[LST_NEW][lvl + nlev] - off0;
     }
     if (mode == 1) cnt1 = v.meta->nghost;
-    if (mode >= 2) {
+    if (!direct && mode >= 2) {
         off1 = v.meta->loff[LST_GHOST][lvl];
         cnt1 = v.meta->loff[LST_GHOST][lvl + nlev] - off1;
     }
     const int nleaf = cfl ? v.meta->nleaf : 0;
     const bool all = mode == 1;
     if (all || cfl) grid_tab_load(v, tab);
-    issued(off0, cnt0, off1, cnt1, nleaf);
-    if (done) return;
+    if (!direct) {
+        issued(off0, cnt0, off1, cnt1, nleaf);
+        if (done) return;
+    }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (cfl) {
         if (lane < MAXLEV) lmax[wave][lane] = 0.0;
@@ -1409,10 +1414,28 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
     constexpr int NV = D + 2;
     const double g = v.gamma;
     bool bad = false;
-    const int count = cnt0 + cnt1;
+    const int nb0 = D == 2 ? Gl.nb * Gl.nb : Gl.nb * Gl.nb * Gl.nb;
+    const int nbh = nlev == 2 ? (D == 2 ? Gh.nb * Gh.nb : Gh.nb * Gh.nb * Gh.nb) : 0;
+    const int count = direct ? nb0 + nbh : cnt0 + cnt1;
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
-        const bool fresh = t < cnt0;
-        const Tile tl = fresh ? v.fresh[off0 + t] : v.ghost[off1 + t - cnt0];
+        bool fresh;
+        Tile tl;
+        if (direct) {
+            // block t of level lvl, then of lvl+1: its code and neighbour
+            // mask, read with the done flag
+            const bool lo = t < nb0;
+            const int b = lo ? t : t - nb0;
+            const int64_t gb = (lo ? Gl.boff : Gh.boff) + b;
+            const int code = v.code[gb];
+            const uint32_t gmk = v.gmask[gb];
+            if (done) break;
+            if (!(code & 12)) continue;
+            fresh = (code & 8) != 0;
+            tl = Tile{(lo ? lvl : lvl + 1) | (fresh ? 0 : (int)(gmk << Tile::GRID_BITS)), b};
+        } else {
+            fresh = t < cnt0;
+            tl = fresh ? v.fresh[off0 + t] : v.ghost[off1 + t - cnt0];
+        }
         const int lv = fresh ? tl.grid : tl.grid & ((1 << Tile::GRID_BITS) - 1);
         const uint32_t gm = fresh ? 0u : (uint32_t)tl.grid >> Tile::GRID_BITS;
         const bool up = !all && lv != lvl;   // a level-(lvl+1) block of a two-level launch

@@ -62,8 +62,12 @@ template <typename T> void predict(const View &v, int a, int lvl, int nlev, int 
     const int nblk = predict_grid(maxb);
     const Grid Gl = v.gt[mode == 1 ? 0 : lvl], Cl = v.gt[mode == 1 ? 0 : lvl - 1];
     const Grid Gh = v.gt[nlev == 2 ? lvl + 1 : (mode == 1 ? 0 : lvl)];
-    if (v.dim == 2) k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh, cfl);
-    else k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh, cfl);
+    // the blocks of the levels walked directly when one pass takes them all
+    const int direct = mode == 3 && !cfl && maxb <= nblk ? 1 : 0;
+    if (v.dim == 2)
+        k_predict<T, 2><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh, cfl, direct);
+    else
+        k_predict<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl, mode, theta, nlev, Gl, Cl, Gh, cfl, direct);
 }
 
 // Stage-kernel schedules the autotuner chooses from (variant index):
