@@ -303,33 +303,40 @@ int level_flags(eu_ctx *c, int64_t *nflag)
 // ---- launch sequences ------------------------------------------------------
 
 // Projection of every covered cell, finest level first: in 2D two levels
-// per launch, in 3D one.  In 2D the last launch can also fill the ghost cells
-// of every level (ghosts) or compute the MR details (details), projecting
-// the values of the levels it projects itself where they are read (not both:
+// per launch (three make the coarsest items of a launch its long pole), in
+// 3D one.  fine_done: the stage kernel has projected
+// level L-2 (2D).  In 2D the last launch can also fill the ghost cells of
+// every level (ghosts) or compute the MR details (details), projecting the
+// values of the levels it projects itself where they are read (not both:
 // the details read ghost cells the fill writes).  Returns whether it did the
 // extra work.
-bool seq_restrict(eu_ctx *c, int arr, bool ghosts = false, bool details = false)
+bool seq_restrict(eu_ctx *c, int arr, bool ghosts = false, bool details = false, bool fine_done = false)
 {
     if (ghosts && details) ghosts = details = false;
     if (c->dim == 2) {
+        const int top = c->L - 2 - (fine_done ? 1 : 0);   // levels 0 .. top left to project
+        if (top < 0) return false;
         int64_t ndet = 0;
         if (details)
             for (int l = 0; l < c->L - 1; ++l) ndet += c->grids[l].ncell;
-        for (int l = c->L - 2; l >= 0; l -= 2) {
-            const int lo = l >= 1 ? l - 1 : l, nlev = l - lo + 1;
+        constexpr int GROUP = 2;   // levels per launch
+        for (int hi = top; hi >= 0; hi -= GROUP) {
+            const int lo = std::max(0, hi - GROUP + 1), nlev = hi - lo + 1;
             const bool last = lo == 0;
-            int64_t nb = nblocks_grid(c, lo) + (nlev == 2 ? nblocks_grid(c, l) : 0);
+            int64_t nbl = 0;
+            for (int k = lo; k <= hi; ++k) nbl += nblocks_grid(c, k);
+            int64_t nb = nbl;
             if (last && ghosts) nb += c->nbt;
             if (last && details) {
                 // 8x8 blocks of the levels projected here, 64-cell chunks of the rest
                 int64_t fine = ndet;
-                for (int k = 0; k <= l; ++k) fine -= c->grids[k].ncell;
-                nb += nblocks_grid(c, 0) + (nlev == 2 ? nblocks_grid(c, 1) : 0) + (fine + 63) / 64;
+                for (int k = 0; k <= hi; ++k) fine -= c->grids[k].ncell;
+                nb += nbl + (fine + 63) / 64;
             }
             c->ks->restrict2(c->v, arr, lo, nlev, last && ghosts ? 1 : 0, last ? ndet : 0,
                              (int)std::min<int64_t>(nb, INT32_MAX), c->stream);
         }
-        return c->L >= 2 && (ghosts || details);
+        return ghosts || details;
     }
     for (int l = c->L - 2; l >= 0; --l)
         c->ks->restrict_cov(c->v, arr, l, (int)nblocks_grid(c, l), c->stream);
@@ -390,15 +397,18 @@ void prof_end(eu_ctx *c, hipEvent_t e1)
 void seq_details(eu_ctx *c);
 void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
 {
+    // 2D hierarchy: the stage kernel also projects its finest tiles onto
+    // level L-2
+    const bool fine = c->dim == 2 && c->mode == MODE_HIER && c->L >= 2;
     hipEvent_t e;
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, c->variant, c->stream);
+    c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, c->variant, fine ? 1 : 0, c->stream);
     prof_end(c, e);
-    if (!seq_restrict(c, ARR_QS, true)) seq_ghost(c, ARR_QS);
+    if (!seq_restrict(c, ARR_QS, true, false, fine)) seq_ghost(c, ARR_QS);
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 2, -1, 0, 0, c->max_tiles, c->variant, c->stream);
+    c->ks->fv_stage(c->v, 2, -1, 0, 0, c->max_tiles, c->variant, fine ? 1 : 0, c->stream);
     prof_end(c, e);
-    if (!seq_restrict(c, ARR_Q, ghost_after, details)) {
+    if (!seq_restrict(c, ARR_Q, ghost_after, details, fine)) {
         if (ghost_after) seq_ghost(c, ARR_Q);
         if (details) seq_details(c);
     }
@@ -470,11 +480,11 @@ void lts_advance(eu_ctx *c, int l, int k)
     hipEvent_t e;
     c->ks->copy_level(c->v, l, nbl, c->stream);
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 1, l, k, 0, nbl, c->variant, c->stream);
+    c->ks->fv_stage(c->v, 1, l, k, 0, nbl, c->variant, 0, c->stream);
     prof_end(c, e);
     if (l >= 1) c->ks->predict(c->v, ARR_QS, l, 1, 2, (double)(2 * k + 1) * 0.25, 0, nbl, c->stream);
     prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 2, l, k, 1, nbl, c->variant, c->stream);
+    c->ks->fv_stage(c->v, 2, l, k, 1, nbl, c->variant, 0, c->stream);
     prof_end(c, e);
     if (l + 1 < c->L) {
         const int nbf = (int)nblocks_grid(c, l + 1);
@@ -525,9 +535,9 @@ void stage1_pass(eu_ctx *c, int var)
 {
     if (c->v.lts)
         for (int l = 0; l < c->L; ++l)
-            c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, c->stream);
+            c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, 0, c->stream);
     else
-        c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, var, c->stream);
+        c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, var, 0, c->stream);
 }
 
 int stage_ready(eu_ctx *c)

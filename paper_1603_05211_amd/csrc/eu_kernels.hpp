@@ -514,10 +514,15 @@ __device__ __forceinline__ void fv_collect(const T (*sF)[FV<D, NT>::NF], T (*R)[
 // once (slope, then W -/+ slope/2) instead of twice per cell, once for each
 // of its faces; SCHED 1 computes the
 // faces of all axes in one pass over all threads (one array per axis).
+// fineproj (2D hierarchy, global step): a tile of the finest level L-1
+// also writes the projection of its cells (the values it has just written)
+// onto its 4x4 parent cells of level L-2, all of them covered: every cell of
+// a finest block is a leaf, and no other workgroup of the launch reads those
+// cells of out.
 template <typename T, int D, int NT, int SCHED>
 __global__ void __launch_bounds__(NT)
 k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac, int lvl, int sub,
-           int record)
+           int record, int fineproj)
 {
     using C = FV<D, NT>;
     constexpr int E = C::E, H = C::H, B = C::B, NV = C::NV;
@@ -681,6 +686,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
         }
         const double dt = v.mode == MODE_BATCH ? v.dt[tl.grid] : dt0;
         const T lam = (T)((dt * fac) / G.dx);
+        const bool fp = D == 2 && fineproj && tl.grid == v.L - 1;
 #pragma unroll
         for (int k = 0; k < C::CPT; ++k) {
             const int c = threadIdx.x + k * NT;
@@ -690,7 +696,27 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             if (!lts && sCov[h]) continue;
             const int64_t id = G.off + (int64_t)gidx32(n, ox + x, oy + y, oz + z);
 #pragma unroll
-            for (int f = 0; f < NV; ++f) out[f * N + id] = qb[k][f] - lam * R[k][f];
+            for (int f = 0; f < NV; ++f) {
+                const T q = qb[k][f] - lam * R[k][f];
+                out[f * N + id] = q;
+                if (fp) sW[f][c] = q;   // the flux phase no longer reads sW
+            }
+        }
+        if (D == 2 && fp) {
+            __syncthreads();
+            if (threadIdx.x < (B / 2) * (B / 2)) {
+                // parent (px, py): the mean of its children in the pairwise
+                // order of the projection kernels
+                const int px = threadIdx.x % (B / 2), py = threadIdx.x / (B / 2);
+                const Grid P = grid_tab(tab, G.coarse);
+                const int64_t ip = P.off + gidx(P.n, (ox >> 1) + px, (oy >> 1) + py, 0);
+#pragma unroll
+                for (int f = 0; f < NV; ++f) {
+                    const int c0 = (2 * py) * B + 2 * px;
+                    out[ip + f * P.ncell] =
+                        T(0.25) * ((sW[f][c0] + sW[f][c0 + 1]) + (sW[f][c0 + B] + sW[f][c0 + B + 1]));
+                }
+            }
         }
         __syncthreads();
     }
@@ -969,18 +995,15 @@ __global__ void __launch_bounds__(256) k_restrict_cov(View v, T *A, int lvl)
 }
 
 // Projection of the covered cells of levels lvl .. lvl+nlev-1 (nlev = 1 or
-// 2) in one launch (Sec. 2.1: a covered cell is the mean of its children),
-// 2D; with ghosts set, in the same launch, the ghost fill of every level
-// (used when lvl .. lvl+nlev-1 are the coarsest levels, projected last).
-// Every block of the two levels is a work item; those whose code has the
-// covered bit project their covered cells.  A cell of level lvl+1 is the
-// mean of its four children; a cell of level lvl is the
-// mean of its four children, each of which is either final (a leaf) or
-// itself the mean of its own four children.  The four children of a cell
-// lie in one block of the next level and its sixteen grandchildren in one
-// block of the level after, so one mask read tells whether the children are
-// covered.  Every read is issued before any result is stored, and the
-// arithmetic is that of two successive one-level projections.
+// 2; level lvl+nlev final) in one launch (Sec. 2.1: a covered cell is
+// the mean of its children), 2D; with ghosts set, in the same launch, the
+// ghost fill of every level, with ndet the MR details (used when lvl = 0,
+// projected last).  Every block of the projected levels is a work item;
+// those whose code has the covered bit project their covered cells.  A cell
+// is the mean of its four children, each of which is final or, on a level
+// projected in the same pass, itself the mean of its own children (and so
+// on, proj_field): the arithmetic of successive one-level projections, every
+// read issued before any result is stored.
 // ghost cell of a ghost block (a block outside every patch of its level):
 // a cell within two cells of a patch.  Cells x-2 .. x+2 reach the lower
 // neighbour block along an axis when x mod 8 < 2 and the upper one when
@@ -1032,46 +1055,44 @@ __device__ __forceinline__ T predict_child_lds(const T *S, int px, int py, int p
     return pred1<T>(sz[0], sz[1], sz[2], cz);
 }
 
+// Field f of level-k cell (x, y) of a 2D hierarchy when the DEPTH levels
+// k .. k+DEPTH-1 are projected in the same pass and level k+DEPTH is final:
+// a covered cell is the mean of its four children in pairwise order, each
+// child taken the same way one level down (DEPTH 0: the stored value).  The
+// arithmetic of successive one-level projections; every read is issued and
+// the value selected.
+template <typename T, int DEPTH>
+__device__ __forceinline__ T proj_field(const View &v, const T *A, const GridTab &tab, int k, int x, int y, int f)
+{
+    const Grid G = grid_tab(tab, k);
+    const T own = A[G.off + f * G.ncell + gidx(G.n, x, y, 0)];
+    if constexpr (DEPTH == 0) {
+        return own;
+    } else {
+        const bool cov = covered(v.act, grid_tab(tab, k + 1), x, y, 0);
+        T c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            c[j] = proj_field<T, DEPTH - 1>(v, A, tab, k + 1, 2 * x + (j & 1), 2 * y + (j >> 1), f);
+        const T m = T(0.25) * ((c[0] + c[1]) + (c[2] + c[3]));
+        return cov ? m : own;
+    }
+}
+
 // Value of level-k cell (x, y) of a 2D hierarchy after the projection of
-// levels lo .. hi-1 (k in that range): a covered cell is the mean of its
-// children, each of them final or, when level k+1 is projected in the same
-// pass, itself the mean of its children (level k+2 is final).  The same
-// arithmetic as the projection kernel; every read issued before any test.
-// The first NV fields (all four, or the density alone).
+// levels k .. hi-1 in one pass (hi - k = 1 or 2 levels below it), the first
+// NV fields (all four, or the density alone).
 template <typename T, int NV = 4>
 __device__ __forceinline__ void projected_value(const View &v, const T *A, const GridTab &tab, int k, int hi,
                                                 int x, int y, T *out)
 {
-    const Grid G = grid_tab(tab, k), F1 = grid_tab(tab, k + 1);
-    const bool two = k + 1 < hi;
-    const Grid F2 = grid_tab(tab, two ? k + 2 : k + 1);
-    const bool cov = covered(v.act, F1, x, y, 0);
-    const bool gcov = two && v.act[F2.boff + ((4 * x) >> 3) + (int64_t)F2.nb * ((4 * y) >> 3)] != 0;
-    T own[NV], ch[NV][4], gc[NV][4] = {};
+    const int depth = hi - k;
+    if (depth >= 2) {
 #pragma unroll
-    for (int f = 0; f < NV; ++f) {
-        own[f] = A[G.off + f * G.ncell + gidx(G.n, x, y, 0)];
+        for (int f = 0; f < NV; ++f) out[f] = proj_field<T, 2>(v, A, tab, k, x, y, f);
+    } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            ch[f][j] = A[F1.off + f * F1.ncell + gidx(F1.n, 2 * x + (j & 1), 2 * y + (j >> 1), 0)];
-    }
-    if (two)
-#pragma unroll
-        for (int f = 0; f < NV; ++f)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                gc[f][j] = restrict_cell<T, 2>(A + F2.off + f * F2.ncell, F2.n, 2 * x + (j & 1), 2 * y + (j >> 1), 0);
-#pragma unroll
-    for (int f = 0; f < NV; ++f) {
-        T c[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const T a = gc[f][j], b = ch[f][j];
-            c[j] = gcov ? a : b;
-        }
-        const T m = T(0.25) * ((c[0] + c[1]) + (c[2] + c[3]));
-        const T o = own[f];
-        out[f] = cov ? m : o;
+        for (int f = 0; f < NV; ++f) out[f] = proj_field<T, 1>(v, A, tab, k, x, y, f);
     }
 }
 
@@ -1104,8 +1125,7 @@ __device__ __forceinline__ double detail_lds(const T *S, const T *C, int lx, int
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev, Grid g0, Grid g1, Grid g2,
-                                                  int ghosts, int64_t ndet)
+__global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nlev, int ghosts, int64_t ndet)
 {
     constexpr int NV = 4;
     constexpr int W = BS / 2 + 2, NS = W * W;
@@ -1113,36 +1133,46 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
     __shared__ GridTab tab;
     __shared__ T sA[NV][NS];
     __shared__ T sS[NSD], sC[CW * CW];
-    // Work items: MR details, then every block of the projected levels
-    // (walked directly: its code says whether it holds covered cells), then
-    // the ghost list.  No item waits for the done flag before its first
-    // reads: the flag is tested with them.  The grids of levels lvl, lvl+1
-    // and lvl+2 come at fixed argument offsets.
+    // Work items: MR details, then every block of the projected levels lvl ..
+    // hi-1 (walked directly: its code says whether it holds covered cells),
+    // then the ghost list.  Level hi is final.  No item waits for the done
+    // flag before its first reads: the flag is tested with them.
     const int done = v.meta->done;
     const int ngh = ghosts ? v.meta->nghost : 0;
+    const int hi = lvl + nlev;
+    grid_tab_load(v, tab);
+    __syncthreads();
+    int nbl[3];   // blocks of the projected levels (nlev <= 2: the last is zero)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int nb = i < nlev ? grid_tab(tab, lvl + i).nb : 0;
+        nbl[i] = nb * nb;
+    }
+    const int ncov = nbl[0] + nbl[1] + nbl[2];
     // MR details of levels 0 .. L-2 (ndet cells in all, only with lvl = 0):
     // 8x8 blocks of the levels projected here, then chunks of 64 cells of
     // the finer levels, from the first cell after those levels
-    const int64_t dfirst = nlev == 2 ? g1.coff + g1.ncell : g0.coff + g0.ncell;
-    const int nin = ndet ? g0.nb * g0.nb + (nlev == 2 ? g1.nb * g1.nb : 0) : 0;
+    const Grid Gt = grid_tab(tab, hi - 1);
+    const int64_t dfirst = Gt.coff + Gt.ncell;
+    const int nin = ndet ? ncov : 0;
     const int nch = ndet ? nin + (int)((ndet - dfirst + 63) / 64) : 0;
-    const int nb0 = g0.nb * g0.nb, ncov = nb0 + (nlev == 2 ? g1.nb * g1.nb : 0);
     const int nitem = nch + ncov + (ghosts ? v.nbt : 0);   // ghost entries: at most one per block
-    if (ghosts || ndet) {
-        grid_tab_load(v, tab);
-        __syncthreads();
-    }
+    // block r of the projected levels: its level and index within the level
+    auto level_block = [&](int r, int &k, int &b) {
+        const int i = (r >= nbl[0] ? 1 : 0) + (r >= nbl[0] + nbl[1] ? 1 : 0);
+        k = lvl + i;
+        b = r - (i >= 1 ? nbl[0] : 0) - (i >= 2 ? nbl[1] : 0);
+    };
     for (int t = blockIdx.x; t < nitem; t += gridDim.x) {
         if (t < nch) {
             const int r = t;
             if (r < nin) {
-                // 8x8 block of level lvl or lvl+1: the projected densities
-                // of its stencil region and of its children staged in LDS
-                const bool first = r < g0.nb * g0.nb;
-                const int k = first ? lvl : lvl + 1;
-                const int b = first ? r : r - g0.nb * g0.nb;
-                const Grid G = first ? g0 : g1, F = first ? g1 : g2;
-                const bool fin = k + 1 < lvl + nlev;   // children projected here too
+                // 8x8 block of a projected level: the projected densities of
+                // its stencil region and of its children staged in LDS
+                int k, b;
+                level_block(r, k, b);
+                const Grid G = grid_tab(tab, k), F = grid_tab(tab, k + 1);
+                const bool fin = k + 1 < hi;   // children projected here too
                 const int ox = (b % G.nb) * BS, oy = (b / G.nb) * BS;
                 const int lx = threadIdx.x % BS, ly = threadIdx.x / BS;
                 const bool act = block_active(v, v.act, G, ox, oy, 0);
@@ -1154,14 +1184,13 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
                 for (int u = 0; u < 2; ++u) {
                     const int i = threadIdx.x + 64 * u < NSD ? threadIdx.x + 64 * u : NSD - 1;
                     const int ax = bcmap(ox - 1 + i % SW, G.n, v.bc), ay = bcmap(oy - 1 + i / SW, G.n, v.bc);
-                    projected_value<T, 1>(v, A, tab, k, lvl + nlev, ax, ay, &vs[u]);
+                    projected_value<T, 1>(v, A, tab, k, hi, ax, ay, &vs[u]);
                 }
                 if (fin) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int i = threadIdx.x + 64 * u;
-                        projected_value<T, 1>(v, A, tab, k + 1, lvl + nlev, 2 * ox + i % CW, 2 * oy + i / CW,
-                                              &vc[u]);
+                        projected_value<T, 1>(v, A, tab, k + 1, hi, 2 * ox + i % CW, 2 * oy + i / CW, &vc[u]);
                     }
                 } else {
 #pragma unroll
@@ -1220,7 +1249,7 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
             const int lv = tl.grid & ((1 << Tile::GRID_BITS) - 1);
             const uint32_t gm = (uint32_t)tl.grid >> Tile::GRID_BITS;
             const Grid G = grid_tab(tab, lv), Cg = grid_tab(tab, lv - 1);
-            const bool otf = lv - 1 >= lvl && lv - 1 < lvl + nlev;
+            const bool otf = lv - 1 >= lvl && lv - 1 < hi;
             const int nb = G.nb;
             const int ox = (tl.block % nb) * BS, oy = ((tl.block / nb) % nb) * BS;
             const int qx0 = (ox >> 1) - 1, qy0 = (oy >> 1) - 1;
@@ -1228,7 +1257,7 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
                 const int ax = bcmap(qx0 + i % W, Cg.n, v.bc), ay = bcmap(qy0 + i / W, Cg.n, v.bc);
                 T val[NV];
                 if (otf) {
-                    projected_value<T>(v, A, tab, lv - 1, lvl + nlev, ax, ay, val);
+                    projected_value<T>(v, A, tab, lv - 1, hi, ax, ay, val);
                 } else {
 #pragma unroll
                     for (int f = 0; f < NV; ++f) val[f] = A[Cg.off + f * Cg.ncell + gidx(Cg.n, ax, ay, 0)];
@@ -1249,57 +1278,25 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
             __syncthreads();
             continue;
         }
-        // block of level lvl or lvl+1, when it holds covered cells
-        const int cb = t - nch;
-        const bool lo = cb < nb0;
-        const Grid G = lo ? g0 : g1;
-        const Grid F1 = lo ? g1 : g2;
-        const bool two = nlev == 2 && lo;   // through the children's children
-        const Grid F2 = g2;
-        const int nb = G.nb;
-        const int block = lo ? cb : cb - nb0;
+        // block of a projected level, when it holds covered cells: each
+        // covered cell the mean of its children, projected through the
+        // levels below it in this pass
+        int k, block;
+        level_block(t - nch, k, block);
+        const Grid G = grid_tab(tab, k);
         const int code = v.code[G.boff + block];
         if (done) break;
         if (!(code & 2)) continue;
+        const int nb = G.nb;
         const int x = (block % nb) * BS + threadIdx.x % BS;
         const int y = ((block / nb) % nb) * BS + threadIdx.x / BS;
-        const bool cov = covered(v.act, F1, x, y, 0);
-        // the children's children lie in block (4x/8, 4y/8) of level +2
-        const bool gcov = two && v.act[F2.boff + ((4 * x) >> 3) + (int64_t)F2.nb * ((4 * y) >> 3)] != 0;
-        T ch[NV][4];
-#pragma unroll
-        for (int f = 0; f < NV; ++f)
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                ch[f][k] = A[F1.off + f * F1.ncell + gidx(F1.n, 2 * x + (k & 1), 2 * y + (k >> 1), 0)];
-        T gc[NV][4] = {};
-        if (two) {
-#pragma unroll
-            for (int f = 0; f < NV; ++f)
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    gc[f][k] = restrict_cell<T, 2>(A + F2.off + f * F2.ncell, F2.n, 2 * x + (k & 1), 2 * y + (k >> 1), 0);
-#pragma unroll
-            for (int f = 0; f < NV; ++f)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) issued(gc[f][k]);
-        }
-#pragma unroll
-        for (int f = 0; f < NV; ++f)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) issued(ch[f][k]);
+        const bool cov = covered(v.act, grid_tab(tab, k + 1), x, y, 0);
+        T val[NV];
+        projected_value<T>(v, A, tab, k, hi, x, y, val);
         if (!cov) continue;
         const int64_t id = G.off + gidx(G.n, x, y, 0);
 #pragma unroll
-        for (int f = 0; f < NV; ++f) {
-            T c[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const T a = gc[f][k], b = ch[f][k];   // select values, not addresses
-                c[k] = gcov ? a : b;
-            }
-            A[id + f * G.ncell] = T(0.25) * ((c[0] + c[1]) + (c[2] + c[3]));
-        }
+        for (int f = 0; f < NV; ++f) A[id + f * G.ncell] = val[f];
     }
 }
 

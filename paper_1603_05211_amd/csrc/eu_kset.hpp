@@ -30,13 +30,15 @@ struct KSet {
     void (*restrict_full)(const View &, int arr, int grid_coarse, int64_t ncell, hipStream_t);
     void (*restrict_cov)(const View &, int arr, int lvl, int maxblocks, hipStream_t);
     void (*restrict2)(const View &, int arr, int lvl, int nlev, int ghosts, int64_t ndetails, int maxblocks,
-                      hipStream_t);
+                      hipStream_t);   // 2D, nlev = 1 or 2
     // cfl: also the CFL slots of the state it leaves (mode 3 on the state,
     // the launch of the finest levels; the slots must be zero)
     void (*predict)(const View &, int arr, int lvl, int nlev, int mode, double theta, int cfl, int maxblocks,
                     hipStream_t);
+    // fineproj (2D hierarchy, global step): tiles of level L-1 also write the
+    // projection of their cells onto level L-2
     void (*fv_stage)(const View &, int stage, int lvl, int sub, int record, int maxtiles, int variant,
-                     hipStream_t);
+                     int fineproj, hipStream_t);
     void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*cfl)(const View &, int maxtiles, hipStream_t);           // batch: maxima and dt

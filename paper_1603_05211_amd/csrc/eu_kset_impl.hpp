@@ -46,14 +46,13 @@ template <typename T> void restrict_cov(const View &v, int a, int lvl, int maxb,
     else k_restrict_cov<T, 3><<<nblk, 256, 0, s>>>(v, arr<T>(v, a), lvl);
 }
 
-// two levels per launch (2D only), optionally with the ghost fill of every
-// level or the MR details of levels 0 .. L-2
+// one or two levels per launch (2D only), optionally with the ghost fill of
+// every level or the MR details of levels 0 .. L-2
 template <typename T> void restrict2(const View &v, int a, int lvl, int nlev, int ghosts, int64_t ndet, int maxb,
                                      hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 2048);
-    const Grid g0 = v.gt[lvl], g1 = v.gt[lvl + 1], g2 = v.gt[lvl + 2 < v.L ? lvl + 2 : lvl + 1];
-    k_restrict2<T><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, nlev, g0, g1, g2, ghosts, ndet);
+    k_restrict2<T><<<nblk, 64, 0, s>>>(v, arr<T>(v, a), lvl, nlev, ghosts, ndet);
 }
 
 template <typename T> void predict(const View &v, int a, int lvl, int nlev, int mode, double theta, int cfl,
@@ -79,13 +78,13 @@ template <typename T> void predict(const View &v, int a, int lvl, int nlev, int 
 //       per-axis with per-cell face states.
 template <typename T, int D, int NT, int M>
 void fv_launch(const View &v, int nblk, const T *src, T *out, double fac, int lvl, int sub, int record,
-               hipStream_t s)
+               int fineproj, hipStream_t s)
 {
-    k_fv_stage<T, D, NT, M><<<nblk, NT, 0, s>>>(v, src, (const T *)v.Q, out, fac, lvl, sub, record);
+    k_fv_stage<T, D, NT, M><<<nblk, NT, 0, s>>>(v, src, (const T *)v.Q, out, fac, lvl, sub, record, fineproj);
 }
 
 template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, int record, int maxt,
-                                    int variant, hipStream_t s)
+                                    int variant, int fineproj, hipStream_t s)
 {
     // a 2D hierarchy has at most a few thousand leaf tiles: 2048 workgroups
     // take them all at once, and fewer idle workgroups are dispatched (a
@@ -96,21 +95,21 @@ template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, 
     const double fac = stage == 1 ? 0.5 : 1.0;
     if (v.dim == 2) {
         switch (variant) {
-        case 1: fv_launch<T, 2, 64, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 2: fv_launch<T, 2, 128, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 3: fv_launch<T, 2, 128, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 4: fv_launch<T, 2, 192, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 5: fv_launch<T, 2, 128, 2>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        default: fv_launch<T, 2, 64, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 1: fv_launch<T, 2, 64, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 2: fv_launch<T, 2, 128, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 3: fv_launch<T, 2, 128, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 4: fv_launch<T, 2, 192, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 5: fv_launch<T, 2, 128, 2>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        default: fv_launch<T, 2, 64, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
         }
     } else {
         switch (variant) {
-        case 1: fv_launch<T, 3, 256, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 2: fv_launch<T, 3, 512, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 3: fv_launch<T, 3, 512, 1>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 4: fv_launch<T, 3, 256, 2>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        case 5: fv_launch<T, 3, 512, 2>(v, nblk, src, out, fac, lvl, sub, record, s); break;
-        default: fv_launch<T, 3, 256, 0>(v, nblk, src, out, fac, lvl, sub, record, s); break;
+        case 1: fv_launch<T, 3, 256, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 2: fv_launch<T, 3, 512, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 3: fv_launch<T, 3, 512, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 4: fv_launch<T, 3, 256, 2>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 5: fv_launch<T, 3, 512, 2>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        default: fv_launch<T, 3, 256, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
         }
     }
 }
