@@ -348,11 +348,20 @@ void seq_ghost(eu_ctx *c, int arr)
     if (c->L > 1) c->ks->predict(c->v, arr, 0, 1, 1, 0.0, 0, (int)(c->nbt), c->stream);
 }
 
+// CFL slots cleared (a fill kernel: graph-safe)
+void cfl_zero(eu_ctx *c)
+{
+    launch_fill_u8((uint8_t *)c->v.cfls, 8 * (int64_t)cfl_slot(CFL_STRIDE, 0), 0, c->stream);
+    c->cfl_state = CFL_ZERO;
+}
 // CFL slots of the current state: left by the last regrid when the state
-// has not changed since, else a reduction over the leaves (from zero)
+// has not changed since, else a reduction over the leaves into zero slots
+// (the reduction kernel clears them after reading)
 void cfl_ready(eu_ctx *c)
 {
-    if (c->cfl_state != CFL_READY) c->ks->cfl_slots(c->v, c->max_tiles, c->stream);
+    if (c->cfl_state == CFL_READY) return;
+    if (c->cfl_state == CFL_STALE) cfl_zero(c);
+    c->ks->cfl_slots(c->v, c->max_tiles, c->stream);
     c->cfl_state = CFL_READY;
 }
 // The state changed: slots that held its partials are stale.
@@ -458,8 +467,7 @@ void seq_flag_tile(eu_ctx *c, bool prolong)
         for (int i = 0; i < n; ++i) {
             const int fuse = i == n - 1 && c->mode == MODE_HIER ? 1 : 0;
             // the last launch adds into the CFL slots: they must be zero
-            if (fuse && c->cfl_state != CFL_ZERO)
-                launch_fill_u8((uint8_t *)c->v.cfls, 8 * (int64_t)cfl_slot(CFL_STRIDE, 0), 0, c->stream);
+            if (fuse && c->cfl_state != CFL_ZERO) cfl_zero(c);
             c->ks->predict(c->v, ARR_Q, lvl[i], nlev[i], 3, 0.0, fuse,
                            (int)std::min<int64_t>(maxb[i], INT32_MAX), c->stream);
             if (fuse) c->cfl_state = CFL_READY;
@@ -953,7 +961,7 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
         // the first replay needs them of the current state; otherwise the
         // step computes them itself, and the capture must record that
         if (step_leaves_slots(c)) cfl_ready(c);
-        else if (c->cfl_state == CFL_READY) c->cfl_state = CFL_STALE;
+        else if (c->cfl_state != CFL_ZERO) cfl_zero(c);
         if (!c->gexec[0]) {
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));

@@ -42,7 +42,7 @@ struct KSet {
     void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*cfl)(const View &, int maxtiles, hipStream_t);           // batch: maxima and dt
-    void (*cfl_slots)(const View &, int maxtiles, hipStream_t);     // hierarchy: the CFL slots, from zero
+    void (*cfl_slots)(const View &, int maxtiles, hipStream_t);     // hierarchy: into zero CFL slots
     void (*totals)(const View &, int maxtiles, hipStream_t);
     void (*details)(const View &, int64_t ncell_coarse_levels, hipStream_t);
     void (*composite)(const View &, int lvl, int64_t ncell, hipStream_t);

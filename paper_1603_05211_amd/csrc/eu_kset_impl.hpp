@@ -136,11 +136,11 @@ template <typename T> void cfl(const View &v, int maxt, hipStream_t s)
     else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     launch_cfl_final(v, s);
 }
-// Hierarchy: the CFL slots of the current state, from zero (one wave per
-// tile; 2D tiles are light: fewer workgroups suffice)
+// Hierarchy: the CFL maxima of the current state added into the slots,
+// which must be zero (one wave per tile; 2D tiles are light: fewer
+// workgroups suffice)
 template <typename T> void cfl_slots(const View &v, int maxt, hipStream_t s)
 {
-    launch_fill_u8((uint8_t *)v.cfls, 8 * (int64_t)cfl_slot(CFL_STRIDE, 0), 0, s);
     const int nblk = clamp_grid((maxt + 3) / 4, v.dim == 2 ? 512 : CFL_MAXBLK);
     if (v.dim == 2) k_cfl<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
