@@ -94,7 +94,7 @@ struct Layout {
     std::vector<int64_t> pbase;
     // scratch offsets
     size_t o_grids, o_act, o_nact, o_code, o_gmask, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
-        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_lword, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_partial, o_cfls, o_totals, o_goff, o_gcnt;
+        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_lword, o_fword, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_partial, o_cfls, o_totals, o_goff, o_gcnt;
     size_t scratch = 0, state = 0;
 };
 
@@ -235,6 +235,7 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_cpart = take(sizeof(long long) * eu::NPART * eu::MAXLEV * lay.ncls);
     lay.o_wcnt = take(sizeof(int) * 5 * lay.ncls);
     lay.o_lword = take(sizeof(unsigned long long) * 2 * lay.ncls);
+    lay.o_fword = take(sizeof(unsigned long long) * std::max<int64_t>(lay.nslot, 1));
     lay.o_pbase = take(sizeof(int64_t) * (eu::MAXLEV + 1));
     lay.o_meta = take(sizeof(Meta));
     lay.o_smax = take(8 * lay.ngrid);
@@ -454,9 +455,18 @@ bool step_leaves_slots(const eu_ctx *c) { return c->mode == MODE_HIER && c->L >=
 // the ghost fill alone.
 void seq_flag_tile(eu_ctx *c, bool prolong)
 {
-    for (int l = c->L - 2; l >= 0; --l) {
-        const int nbp = c->grids[l + 1].n / c->cfg.patch_max;
-        launch_flag_tile(c->v, l, (int)ipow(nbp, c->dim), c->stream);
+    if (flag_chain_ok(c->v)) {
+        int wg0[MAXLEV], total = 0, nseg = 0;
+        for (int l = c->L - 2; l >= 0; --l) {
+            wg0[nseg++] = total;
+            total += (int)ipow(c->grids[l + 1].n / c->cfg.patch_max, c->dim);
+        }
+        launch_flag_chain(c->v, wg0, nseg, total, c->stream);
+    } else {
+        for (int l = c->L - 2; l >= 0; --l) {
+            const int nbp = c->grids[l + 1].n / c->cfg.patch_max;
+            launch_flag_tile(c->v, l, (int)ipow(nbp, c->dim), c->stream);
+        }
     }
     launch_build_lists(c->v, c->nbt, c->stream);
     cfl_stale(c);
@@ -658,6 +668,9 @@ int finish_init(eu_ctx *c)
     HIPCHK(c, hipMemsetAsync(c->v.smax, 0, 8 * c->ngrid, c->stream));
     // the list build's words start with one epoch
     HIPCHK(c, hipMemsetAsync(c->v.lword, 0, 2 * sizeof(unsigned long long) * c->v.ncls, c->stream));
+    // and so do the flagging words
+    HIPCHK(c, hipMemsetAsync(c->v.fword, 0, sizeof(unsigned long long) * std::max<int64_t>(c->v.nslot, 1),
+                             c->stream));
     if (c->mode == MODE_HIER) {
         for (int l = c->L - 2; l >= 0; --l)
             c->ks->restrict_full(c->v, ARR_Q, l, c->grids[l].ncell, c->stream);
@@ -789,10 +802,15 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
         // would do (it is otherwise reached only by very large hierarchies)
         const char *lb = std::getenv("EU_LIST_BUILD");
         v.lists2 = lb && lb[0] == '2' ? 1 : 0;
+        // EU_FLAG_BUILD=levels: one flagging launch per level also where one
+        // launch for all of them would do
+        const char *fb = std::getenv("EU_FLAG_BUILD");
+        v.flags1 = fb && std::strcmp(fb, "levels") == 0 ? 1 : 0;
     }
     v.nbt = (int)lay.nbt;
     v.wcnt = at<int>(scratch_dev, lay.o_wcnt);
     v.lword = at<unsigned long long>(scratch_dev, lay.o_lword);
+    v.fword = at<unsigned long long>(scratch_dev, lay.o_fword);
     v.pbase = at<int64_t>(scratch_dev, lay.o_pbase);
     v.meta = at<Meta>(scratch_dev, lay.o_meta);
     v.smax = at<unsigned long long>(scratch_dev, lay.o_smax);

@@ -99,6 +99,9 @@ struct View {
     int *wcnt;                        // per classification workgroup: entries of each list
     unsigned long long *lword;        // per classification workgroup: its list counts with an
                                       // epoch, two words (single-launch list build)
+    unsigned long long *fword;        // per pmax-block slot: the new patch mask of its blocks
+                                      // with an epoch (single-launch flagging)
+    int flags1;                       // flag the levels with one launch each (forced for tests)
     int64_t *pbase;                   // per-level offset into pslot / pcnt
     int64_t pb[MAXLEV + 1];           // the same offsets, by value
     Meta *meta;

@@ -22,6 +22,22 @@ struct FlagArgs {
     int64_t slot0;      // first pmax-block slot of level lvl+1
 };
 
+// Every flagged level of a regrid in one launch: the workgroups of level L-2
+// come first, then those of L-3, ..., 0 (wg0[k] is the first workgroup of
+// level L-2-k).  Level lvl needs the new patch masks of level lvl+2, which
+// the workgroups of level lvl+1 decide: each publishes the masks of its
+// pmax block (one bit per BS-block, Morton order) in a word of its slot,
+// above a 16-bit epoch one higher than the previous regrid's, and the
+// workgroups of level lvl read the masks from those words once they carry
+// the new epoch.  Only lower-numbered workgroups are waited for, and the
+// wait is bounded: past the bound the workgroup sets status bit 2 and goes
+// on (it still publishes, so every word keeps one epoch).
+struct FlagChain {
+    int wg0[MAXLEV];
+    int nseg;
+};
+constexpr int FLAG_MAXSPIN = 1 << 20;
+
 // Offset of level k of the split tree in the node-count array: the nodes of
 // levels 0 .. k-1, (R >> j)^D of them each.
 template <int D, int R>
@@ -34,8 +50,8 @@ __host__ __device__ constexpr int tree_offset(int k)
 
 // R = pmax / BS (1, 2, 4 or 8): every size below is a compile-time constant,
 // so the loops unroll and no index needs a runtime division.
-template <int D, int R>
-__global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
+template <int D, int R, bool CHAIN>
+__global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs fa, FlagChain fc)
 {
     constexpr int NT = 256;                          // threads (the launch uses 256)
     constexpr int NSUB = D == 2 ? R * R : R * R * R;  // BS-blocks of the pmax block
@@ -59,11 +75,38 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
     // same as mapping the cells and dividing)
     __shared__ uint8_t sraw[NRAW];
     __shared__ uint8_t snest[NNEST];
+    static_assert(!CHAIN || NSUB <= 48, "a pmax block's masks share a word with the epoch");
     const int done = v.meta->done;
-    const Grid &G = fa.G, &F = fa.F, &Cg = fa.C, &F2 = fa.F2;
+    // level and pmax block of this workgroup
+    int lvl = lvl_arg, m = blockIdx.x;
+    int64_t slot0 = fa.slot0, slot2 = 0;
+    Grid G = fa.G, F = fa.F, Cg = fa.C, F2 = fa.F2;
+    if constexpr (CHAIN) {
+        int seg = 0, first = 0;
+#pragma unroll
+        for (int k = 1; k < MAXLEV; ++k)
+            if (k < fc.nseg && (int)blockIdx.x >= fc.wg0[k]) {
+                seg = k;
+                first = fc.wg0[k];
+            }
+        lvl = v.L - 2 - seg;
+        m = blockIdx.x - first;
+        G = grid_lane(v, lvl);
+        F = grid_lane(v, lvl + 1);
+        Cg = grid_lane(v, lvl >= 1 ? lvl - 1 : lvl);
+        F2 = grid_lane(v, lvl + 2 < v.L ? lvl + 2 : lvl);
+#pragma unroll
+        for (int k = 1; k <= MAXLEV; ++k) {
+            if (k == lvl + 1) slot0 = v.pb[k];
+            if (k == lvl + 2) slot2 = v.pb[k];
+        }
+    }
     const bool hasc = lvl >= 1, nest = lvl + 2 < v.L;
-    const int64_t slot = fa.slot0 + blockIdx.x;
-    const int m = blockIdx.x;
+    const int64_t slot = slot0 + m;
+    // this regrid's epoch (the words of a chain keep one epoch)
+    const unsigned long long ep =
+        CHAIN ? ((__hip_atomic_load(v.fword + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 0xffffull) + 1) & 0xffffull
+              : 0ull;
     int bp[3] = {0, 0, 0};
     {
         const int nbp = F.n / (R * BS);
@@ -80,7 +123,8 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
     // eight per thread when there are more); addresses are clamped to valid
     // ones so that no read waits behind a test (the grids of levels lvl-1
     // and lvl+2 stand in for missing levels with valid ones)
-    constexpr int IR = (NRAW + NT - 1) / NT, IN = (NNEST + NT - 1) / NT, CH = 8;
+    // (a chain stages the nesting masks later, from the words)
+    constexpr int IR = (NRAW + NT - 1) / NT, IN = CHAIN ? 0 : (NNEST + NT - 1) / NT, CH = 8;
     const int nb2 = F2.nb;
 #pragma unroll
     for (int c0 = 0; c0 < IR + IN; c0 += CH) {
@@ -130,10 +174,11 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
     // lvl+2)
     int mine = 0;   // flagged cells of this wave (ballot counts, lane-uniform)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NIT = (NFOOT + NT - 1) / NT;
+    int anyv[NIT];
 #pragma unroll
-    for (int it = 0; it < (NFOOT + NT - 1) / NT; ++it) {
+    for (int it = 0; it < NIT; ++it) {
         const int k = threadIdx.x + it * NT;
-        const bool in = k < NFOOT;
         const int lx = k % HP, ly = (k / HP) % HP, lz = D == 3 ? (k / (HP * HP)) % HP : 0;
         int any = 0;
 #pragma unroll
@@ -143,6 +188,49 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
 #pragma unroll
                 for (int dx = 0; dx <= 2; ++dx)
                     any |= sraw[(lx + dx) + HE * ((ly + dy) + (D == 3 ? HE * (lz + dz) : 0))];
+        anyv[it] = any;
+    }
+    if constexpr (CHAIN) {
+        // the new patch masks of level lvl+2 from the words of the level-(lvl+1)
+        // workgroups that decided them: one word per virtual block
+        if (nest) {
+            const int nbp2 = nb2 / R;
+            int bits2 = 0;
+            while ((1 << bits2) < nbp2) ++bits2;
+            int late = 0;
+            for (int i = threadIdx.x; i < NNEST; i += NT) {
+                int b[3] = {i % NVB, (i / NVB) % NVB, D == 3 ? i / (NVB * NVB) : 0};
+                int pm = 0, bit = 0;
+                for (int d = 0; d < D; ++d) {
+                    const int q = vb0[d] + b[d];
+                    const int bb = v.bc == 1 ? (q < 0 ? q + nb2 : q >= nb2 ? q - nb2 : q) : (q < 0 ? 0 : q >= nb2 ? nb2 - 1 : q);
+                    const int hi = bb / R, lo = bb % R;
+                    for (int k = 0; k < bits2; ++k) pm |= ((hi >> k) & 1) << (k * D + d);
+#pragma unroll
+                    for (int k = 0; k < K; ++k) bit |= ((lo >> k) & 1) << (k * D + d);
+                }
+                const unsigned long long *wp = v.fword + slot2 + pm;
+                unsigned long long x = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int spin = 0; (x & 0xffffull) != ep; ++spin) {
+                    if (spin == FLAG_MAXSPIN) {
+                        late = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    x = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                snest[i] = (uint8_t)((x >> (16 + bit)) & 1ull);
+            }
+            if (late) atomicOr(&v.meta->status, 2);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int k = threadIdx.x + it * NT;
+        const bool in = k < NFOOT;
+        const int lx = k % HP, ly = (k / HP) % HP, lz = D == 3 ? (k / (HP * HP)) % HP : 0;
+        int any = anyv[it];
         if (nest && !any) {
             const int c[3] = {o0[0] + lx, o0[1] + ly, o0[2] + lz};
             int lo[3], hi[3];
@@ -228,6 +316,13 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl, FlagArgs fa)
         const int em = (1 << (emit_k < 0 ? 0 : emit_k)) - 1;
         const bool lead = emit_k >= 0 && (sx & em) == 0 && (sy & em) == 0 && (sz & em) == 0;
         if (mc < NSUB) emit8[sx + R * (sy + R * sz)] = emit_k >= 0 ? 1 : 0;
+        if constexpr (CHAIN) {
+            // every sub-block is in the first wave: publish its masks (bit =
+            // Morton code) for the next coarser level at once
+            const unsigned long long pub = __ballot(mc < NSUB && emit_k >= 0);
+            if (threadIdx.x == 0)
+                __hip_atomic_store(v.fword + slot, ep | pub << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         const unsigned long long mask = __ballot(lead);
         if (lane == 0) wlead[wave] = __popcll(mask);
         __syncthreads();
@@ -700,6 +795,7 @@ static inline int grid_for(int64_t n, int bs, int cap)
 
 void launch_flag_tile(const View &v, int lvl, int nblocks, hipStream_t s)
 {
+    const FlagChain fc{};
     FlagArgs fa;
     fa.G = v.gt[lvl];
     fa.F = v.gt[lvl + 1];
@@ -709,17 +805,45 @@ void launch_flag_tile(const View &v, int lvl, int nblocks, hipStream_t s)
     const int R = v.pmax / BS;
     if (v.dim == 2) {
         switch (R) {
-        case 1: k_flag_tile<2, 1><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
-        case 2: k_flag_tile<2, 2><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
-        case 4: k_flag_tile<2, 4><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
-        default: k_flag_tile<2, 8><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        case 1: k_flag_tile<2, 1, false><<<nblocks, 256, 0, s>>>(v, lvl, fa, fc); break;
+        case 2: k_flag_tile<2, 2, false><<<nblocks, 256, 0, s>>>(v, lvl, fa, fc); break;
+        case 4: k_flag_tile<2, 4, false><<<nblocks, 256, 0, s>>>(v, lvl, fa, fc); break;
+        default: k_flag_tile<2, 8, false><<<nblocks, 256, 0, s>>>(v, lvl, fa, fc); break;
         }
     } else {
         switch (R) {
-        case 1: k_flag_tile<3, 1><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
-        case 2: k_flag_tile<3, 2><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
-        case 4: k_flag_tile<3, 4><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
-        default: k_flag_tile<3, 8><<<nblocks, 256, 0, s>>>(v, lvl, fa); break;
+        case 1: k_flag_tile<3, 1, false><<<nblocks, 256, 0, s>>>(v, lvl, fa, fc); break;
+        case 2: k_flag_tile<3, 2, false><<<nblocks, 256, 0, s>>>(v, lvl, fa, fc); break;
+        case 4: k_flag_tile<3, 4, false><<<nblocks, 256, 0, s>>>(v, lvl, fa, fc); break;
+        default: k_flag_tile<3, 8, false><<<nblocks, 256, 0, s>>>(v, lvl, fa, fc); break;
+        }
+    }
+}
+
+bool flag_chain_ok(const View &v)
+{
+    const int R = v.pmax / BS;
+    return v.mode == MODE_HIER && !v.flags1 && v.L >= 3 &&
+           ((v.dim == 2 && R <= 4) || (v.dim == 3 && R <= 2));
+}
+
+void launch_flag_chain(const View &v, const int *wg0, int nseg, int total, hipStream_t s)
+{
+    FlagChain fc{};
+    for (int k = 0; k < nseg && k < MAXLEV; ++k) fc.wg0[k] = wg0[k];
+    fc.nseg = nseg;
+    const FlagArgs fa{};
+    const int R = v.pmax / BS;
+    if (v.dim == 2) {
+        switch (R) {
+        case 1: k_flag_tile<2, 1, true><<<total, 256, 0, s>>>(v, 0, fa, fc); break;
+        case 2: k_flag_tile<2, 2, true><<<total, 256, 0, s>>>(v, 0, fa, fc); break;
+        default: k_flag_tile<2, 4, true><<<total, 256, 0, s>>>(v, 0, fa, fc); break;
+        }
+    } else {
+        switch (R) {
+        case 1: k_flag_tile<3, 1, true><<<total, 256, 0, s>>>(v, 0, fa, fc); break;
+        default: k_flag_tile<3, 2, true><<<total, 256, 0, s>>>(v, 0, fa, fc); break;
         }
     }
 }

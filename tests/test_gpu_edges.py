@@ -85,6 +85,26 @@ def test_smallest_hierarchy():
     check(h, s, 5)
 
 
+def test_per_level_flagging_matches(monkeypatch):
+    """One flagging launch per level, forced on a 2D four-level run (by
+    default every level is flagged in one launch there): masks, flags, patch
+    tables, time steps and state as the oracle's."""
+    monkeypatch.setenv("EU_FLAG_BUILD", "levels")
+    say("per-level flagging")
+    h, s = pair(2, 4, 16)
+    init_pair(h, s, "quadrant", 13)
+    check(h, s, 4)
+
+
+def test_periodic_3d_adaptive_single_flag_launch():
+    """Periodic 3D hierarchy with patch_max 16: all levels flagged in one
+    launch, whose nesting masks wrap around the domain."""
+    say("3d periodic pmax 16, four levels")
+    h, s = pair(3, 4, 8, pmax=16, bc=orc.BC_PERIODIC)
+    init_pair(h, s, "ellipsoid", 6)
+    check(h, s, 2)
+
+
 def test_periodic_3d_adaptive():
     h, s = pair(3, 3, 16, bc=orc.BC_PERIODIC)
     init_pair(h, s, "ellipsoid", 5)
