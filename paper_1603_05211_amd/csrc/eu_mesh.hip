@@ -175,10 +175,8 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
     int mine = 0;   // flagged cells of this wave (ballot counts, lane-uniform)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NIT = (NFOOT + NT - 1) / NT;
-    int anyv[NIT];
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int k = threadIdx.x + it * NT;
+    // raw flags of footprint cell k dilated by one cell
+    auto dilated = [&](int k) {
         const int lx = k % HP, ly = (k / HP) % HP, lz = D == 3 ? (k / (HP * HP)) % HP : 0;
         int any = 0;
 #pragma unroll
@@ -188,9 +186,13 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
 #pragma unroll
                 for (int dx = 0; dx <= 2; ++dx)
                     any |= sraw[(lx + dx) + HE * ((ly + dy) + (D == 3 ? HE * (lz + dz) : 0))];
-        anyv[it] = any;
-    }
+        return any;
+    };
+    // a chain dilates while the finer level's masks are on their way
+    int anyv[CHAIN ? NIT : 1];
     if constexpr (CHAIN) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) anyv[it] = dilated(threadIdx.x + it * NT);
         // the new patch masks of level lvl+2 from the words of the level-(lvl+1)
         // workgroups that decided them: one word per virtual block
         if (nest) {
@@ -230,7 +232,9 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
         const int k = threadIdx.x + it * NT;
         const bool in = k < NFOOT;
         const int lx = k % HP, ly = (k / HP) % HP, lz = D == 3 ? (k / (HP * HP)) % HP : 0;
-        int any = anyv[it];
+        int any;
+        if constexpr (CHAIN) any = anyv[it];
+        else any = dilated(k);
         if (nest && !any) {
             const int c[3] = {o0[0] + lx, o0[1] + ly, o0[2] + lz};
             int lo[3], hi[3];
@@ -256,95 +260,145 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
         }
     }
     if (lane == 0) wsum[wave] = mine;
-    // flagged-parent counts of every node of the split tree: level k holds
-    // the nodes of 2^k BS-blocks per side, (R >> k)^D of them
-    __shared__ int ncnt[tree_offset<D, R>(K + 1)];
-    __shared__ int wlead[NT / 64];
-    __syncthreads();
-    for (int s = threadIdx.x; s < NSUB; s += NT) ncnt[s] = cnt8[s];
-#pragma unroll
-    for (int k = 1; k <= K; ++k) {
-        __syncthreads();
-        const int r = R >> k, rc = R >> (k - 1);
-        const int nn = D == 2 ? r * r : r * r * r;
-        const int o1 = tree_offset<D, R>(k - 1), o2 = tree_offset<D, R>(k);
-        for (int i = threadIdx.x; i < nn; i += NT) {
-            const int ix = i % r, iy = (i / r) % r, iz = D == 3 ? i / (r * r) : 0;
-            int c = 0;
-#pragma unroll
-            for (int ch = 0; ch < (1 << D); ++ch)
-                c += ncnt[o1 + (2 * ix + (ch & 1)) + rc * ((2 * iy + ((ch >> 1) & 1)) + rc * (2 * iz + ((ch >> 2) & 1)))];
-            ncnt[o2 + i] = c;
-        }
-    }
-    __syncthreads();
     // Each sub-block, taken in Morton order (the order in which a depth-first
     // recursion over children, x fastest, meets it), walks from the root to
     // the node that is emitted as a patch (or is empty).  The node's first
     // sub-block writes the patch; patches are ranked by that Morton order.
-    int *out = v.pslot + slot * (int64_t)NSUB * 5;
-    int nlead_total = 0;
+    // The walk stops at the first node, from the top, that is empty (then
+    // every node below it is) or meets the split rule: the emitted node is
+    // the highest nonempty node that meets it, found from the flagged-cell
+    // counts cn[k] of the sub-block's nodes (k = 0: the sub-block).
+    auto emit_level = [&](const int *cn) {
+        int emit_k = -1;
 #pragma unroll
-    for (int c0 = 0; c0 < NSUB; c0 += NT) {
-        const int mc = c0 + threadIdx.x;   // Morton code of this lane's sub-block
-        int sx = 0, sy = 0, sz = 0;
+        for (int k = 0; k <= K; ++k) {
+            const int S = BS << k, hsz = S / 2;
+            const long long cells = D == 2 ? (long long)hsz * hsz : (long long)hsz * hsz * hsz;
+            if (cn[k] > 0 && (S == v.pmin || (double)cn[k] >= v.eta * (double)cells)) emit_k = k;
+        }
+        return emit_k;
+    };
+    auto morton_split = [](int mc, int &sx, int &sy, int &sz) {
+        sx = sy = sz = 0;
 #pragma unroll
         for (int b = 0; b < K; ++b) {
             sx |= ((mc >> (b * D)) & 1) << b;
             sy |= ((mc >> (b * D + 1)) & 1) << b;
             if (D == 3) sz |= ((mc >> (b * D + 2)) & 1) << b;
         }
-        // the walk from the root stops at the first node, from the top, that
-        // is empty (then every node below it is) or meets the split rule: the
-        // emitted node is the highest nonempty node that meets it (every
-        // level's count read at once)
-        int emit_k = -1;
-        if (mc < NSUB) {
+    };
+    int *out = v.pslot + slot * (int64_t)NSUB * 5;
+    if constexpr (NSUB <= 64) {
+        // one wave walks: lane = Morton code, so the sub-blocks of a node of
+        // level k are an aligned group of 2^(D k) lanes and its count is a
+        // sum over the group
+        __syncthreads();
+        if (wave == 0) {
+            const int mc = lane;
+            int sx, sy, sz;
+            morton_split(mc, sx, sy, sz);
             int cn[K + 1];
+            cn[0] = mc < NSUB ? cnt8[sx + R * (sy + R * sz)] : 0;
 #pragma unroll
-            for (int k = 0; k <= K; ++k) {
-                const int r = R >> k;
-                cn[k] = ncnt[tree_offset<D, R>(k) + (sx >> k) + r * ((sy >> k) + r * (sz >> k))];
+            for (int k = 1; k <= K; ++k) {
+                int t = cn[k - 1];
+#pragma unroll
+                for (int o = 1 << (D * (k - 1)); o < (1 << (D * k)); o <<= 1) t += __shfl_xor(t, o);
+                cn[k] = t;
+            }
+            const int emit_k = mc < NSUB ? emit_level(cn) : -1;
+            const int em = (1 << (emit_k < 0 ? 0 : emit_k)) - 1;
+            const bool lead = emit_k >= 0 && (sx & em) == 0 && (sy & em) == 0 && (sz & em) == 0;
+            if (mc < NSUB) emit8[sx + R * (sy + R * sz)] = emit_k >= 0 ? 1 : 0;
+            if constexpr (CHAIN) {
+                // publish the masks (bit = Morton code) for the next coarser level
+                const unsigned long long pub = __ballot(emit_k >= 0);
+                if (lane == 0)
+                    __hip_atomic_store(v.fword + slot, ep | pub << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            const unsigned long long mask = __ballot(lead);
+            const int pos = __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
+            if (lead) {
+                out[5 * pos + 0] = lvl + 1;
+                out[5 * pos + 1] = bp[0] * R * BS + sx * BS;
+                out[5 * pos + 2] = bp[1] * R * BS + sy * BS;
+                out[5 * pos + 3] = D == 3 ? bp[2] * R * BS + sz * BS : 0;
+                out[5 * pos + 4] = BS << emit_k;
+            }
+            if (lane == 0) {
+                int tot = 0;
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) tot += wsum[w];
+                v.fcnt[slot] = tot;
+                v.pcnt[slot] = __popcll(mask);
+            }
+        }
+        __syncthreads();
+    } else {
+        // node counts in LDS: level k holds the nodes of 2^k BS-blocks per
+        // side, (R >> k)^D of them
+        __shared__ int ncnt[tree_offset<D, R>(K + 1)];
+        __shared__ int wlead[NT / 64];
+        __syncthreads();
+        for (int s = threadIdx.x; s < NSUB; s += NT) ncnt[s] = cnt8[s];
+#pragma unroll
+        for (int k = 1; k <= K; ++k) {
+            __syncthreads();
+            const int r = R >> k, rc = R >> (k - 1);
+            const int nn = D == 2 ? r * r : r * r * r;
+            const int o1 = tree_offset<D, R>(k - 1), o2 = tree_offset<D, R>(k);
+            for (int i = threadIdx.x; i < nn; i += NT) {
+                const int ix = i % r, iy = (i / r) % r, iz = D == 3 ? i / (r * r) : 0;
+                int c = 0;
+#pragma unroll
+                for (int ch = 0; ch < (1 << D); ++ch)
+                    c += ncnt[o1 + (2 * ix + (ch & 1)) + rc * ((2 * iy + ((ch >> 1) & 1)) + rc * (2 * iz + ((ch >> 2) & 1)))];
+                ncnt[o2 + i] = c;
+            }
+        }
+        __syncthreads();
+        int nlead_total = 0;
+#pragma unroll
+        for (int c0 = 0; c0 < NSUB; c0 += NT) {
+            const int mc = c0 + threadIdx.x;   // Morton code of this lane's sub-block
+            int sx, sy, sz;
+            morton_split(mc, sx, sy, sz);
+            int emit_k = -1;
+            if (mc < NSUB) {
+                int cn[K + 1];
+#pragma unroll
+                for (int k = 0; k <= K; ++k) {
+                    const int r = R >> k;
+                    cn[k] = ncnt[tree_offset<D, R>(k) + (sx >> k) + r * ((sy >> k) + r * (sz >> k))];
+                }
+                emit_k = emit_level(cn);
+            }
+            const int em = (1 << (emit_k < 0 ? 0 : emit_k)) - 1;
+            const bool lead = emit_k >= 0 && (sx & em) == 0 && (sy & em) == 0 && (sz & em) == 0;
+            if (mc < NSUB) emit8[sx + R * (sy + R * sz)] = emit_k >= 0 ? 1 : 0;
+            const unsigned long long mask = __ballot(lead);
+            if (lane == 0) wlead[wave] = __popcll(mask);
+            __syncthreads();
+            int pos = nlead_total + __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
+            for (int w = 0; w < wave; ++w) pos += wlead[w];
+            if (lead) {
+                out[5 * pos + 0] = lvl + 1;
+                out[5 * pos + 1] = bp[0] * R * BS + sx * BS;
+                out[5 * pos + 2] = bp[1] * R * BS + sy * BS;
+                out[5 * pos + 3] = D == 3 ? bp[2] * R * BS + sz * BS : 0;
+                out[5 * pos + 4] = BS << emit_k;
             }
 #pragma unroll
-            for (int k = 0; k <= K; ++k) {
-                const int S = BS << k, hsz = S / 2;
-                const long long cells = D == 2 ? (long long)hsz * hsz : (long long)hsz * hsz * hsz;
-                if (cn[k] > 0 && (S == v.pmin || (double)cn[k] >= v.eta * (double)cells)) emit_k = k;
-            }
+            for (int w = 0; w < NT / 64; ++w) nlead_total += wlead[w];
+            __syncthreads();
         }
-        const int em = (1 << (emit_k < 0 ? 0 : emit_k)) - 1;
-        const bool lead = emit_k >= 0 && (sx & em) == 0 && (sy & em) == 0 && (sz & em) == 0;
-        if (mc < NSUB) emit8[sx + R * (sy + R * sz)] = emit_k >= 0 ? 1 : 0;
-        if constexpr (CHAIN) {
-            // every sub-block is in the first wave: publish its masks (bit =
-            // Morton code) for the next coarser level at once
-            const unsigned long long pub = __ballot(mc < NSUB && emit_k >= 0);
-            if (threadIdx.x == 0)
-                __hip_atomic_store(v.fword + slot, ep | pub << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const unsigned long long mask = __ballot(lead);
-        if (lane == 0) wlead[wave] = __popcll(mask);
-        __syncthreads();
-        int pos = nlead_total + __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
-        for (int w = 0; w < wave; ++w) pos += wlead[w];
-        if (lead) {
-            out[5 * pos + 0] = lvl + 1;
-            out[5 * pos + 1] = bp[0] * R * BS + sx * BS;
-            out[5 * pos + 2] = bp[1] * R * BS + sy * BS;
-            out[5 * pos + 3] = D == 3 ? bp[2] * R * BS + sz * BS : 0;
-            out[5 * pos + 4] = BS << emit_k;
-        }
+        if (threadIdx.x == 0) {
+            int tot = 0;
 #pragma unroll
-        for (int w = 0; w < NT / 64; ++w) nlead_total += wlead[w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        int tot = 0;
-#pragma unroll
-        for (int w = 0; w < NT / 64; ++w) tot += wsum[w];
-        v.fcnt[slot] = tot;
-        v.pcnt[slot] = nlead_total;
+            for (int w = 0; w < NT / 64; ++w) tot += wsum[w];
+            v.fcnt[slot] = tot;
+            v.pcnt[slot] = nlead_total;
+        }
     }
     for (int s = threadIdx.x; s < NSUB; s += NT) {
         const int sx = s % R, sy = (s / R) % R, sz = D == 3 ? s / (R * R) : 0;
