@@ -461,14 +461,17 @@ void seq_flag_tile(eu_ctx *c, bool prolong)
             wg0[nseg++] = total;
             total += (int)ipow(c->grids[l + 1].n / c->cfg.patch_max, c->dim);
         }
-        launch_flag_chain(c->v, wg0, nseg, total, c->stream);
+        // the list build joins the launch when one launch can build them
+        const bool lists = flag_chain_lists(c->v, c->nbt);
+        launch_flag_chain(c->v, wg0, nseg, total, c->nbt, lists, c->stream);
+        if (!lists) launch_build_lists(c->v, c->nbt, c->stream);
     } else {
         for (int l = c->L - 2; l >= 0; --l) {
             const int nbp = c->grids[l + 1].n / c->cfg.patch_max;
             launch_flag_tile(c->v, l, (int)ipow(nbp, c->dim), c->stream);
         }
+        launch_build_lists(c->v, c->nbt, c->stream);
     }
-    launch_build_lists(c->v, c->nbt, c->stream);
     cfl_stale(c);
     if (prolong) {
         int lvl[MAXLEV], nlev[MAXLEV];

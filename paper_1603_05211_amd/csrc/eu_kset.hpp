@@ -60,9 +60,12 @@ extern const KSet kset_f32;
 
 // precision-independent mesh kernels (eu_mesh.hip)
 void launch_flag_tile(const View &, int lvl, int nblocks, hipStream_t);
-// every flagged level in one launch (workgroups of level L-2-k from wg0[k] on)
+// every flagged level in one launch (workgroups of level L-2-k from wg0[k] on,
+// nflag of them), optionally followed by the list build in the same launch
 bool flag_chain_ok(const View &);
-void launch_flag_chain(const View &, const int *wg0, int nseg, int total, hipStream_t);
+bool flag_chain_lists(const View &, int64_t nblocks_total);
+void launch_flag_chain(const View &, const int *wg0, int nseg, int nflag, int64_t nblocks_total, bool lists,
+                       hipStream_t);
 void launch_build_lists(const View &, int64_t nblocks_total, hipStream_t);
 void launch_cfl_final(const View &, hipStream_t);
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t val, hipStream_t);

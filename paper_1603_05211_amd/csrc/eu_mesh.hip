@@ -35,8 +35,44 @@ struct FlagArgs {
 struct FlagChain {
     int wg0[MAXLEV];
     int nseg;
+    int nflag;      // flagging workgroups; with lists, the list build follows them
+    int lists;      // the launch also builds the work lists (v.ncls workgroups)
+    int64_t nbt;    // blocks of every level
 };
 constexpr int FLAG_MAXSPIN = 1 << 20;
+
+// The list build of workgroup w of W (defined with the list kernels below);
+// WORDS: the new patch masks come from the flagging words of this launch.
+template <int D, bool WORDS, int R>
+__device__ void lists_body(const View &v, int64_t nbt, int w, int W);
+
+// Word and bit of the new patch mask of block (bx, by, bz) of level l >= 1
+// (grid G): the word of its pmax block (Morton order within the level), the
+// bit of its Morton code within that block.
+template <int D, int R>
+__device__ __forceinline__ const unsigned long long *flag_word(const View &v, const Grid &G, int l, int bx, int by,
+                                                               int bz, int &bit)
+{
+    constexpr int K = R == 1 ? 0 : R == 2 ? 1 : R == 4 ? 2 : 3;
+    const int nbp = G.nb / R;
+    int bits = 0;
+    while ((1 << bits) < nbp) ++bits;
+    const int b[3] = {bx, by, bz};
+    int pm = 0;
+    bit = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int hi = b[d] / R, lo = b[d] % R;
+        for (int k = 0; k < bits; ++k) pm |= ((hi >> k) & 1) << (k * D + d);
+#pragma unroll
+        for (int k = 0; k < K; ++k) bit |= ((lo >> k) & 1) << (k * D + d);
+    }
+    int64_t s0 = 0;
+#pragma unroll
+    for (int k = 1; k < MAXLEV; ++k)
+        if (k == l) s0 = v.pb[k];
+    return v.fword + s0 + pm;
+}
 
 // Offset of level k of the split tree in the node-count array: the nodes of
 // levels 0 .. k-1, (R >> j)^D of them each.
@@ -53,6 +89,12 @@ __host__ __device__ constexpr int tree_offset(int k)
 template <int D, int R, bool CHAIN>
 __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs fa, FlagChain fc)
 {
+    if constexpr (CHAIN) {
+        if (fc.lists && (int)blockIdx.x >= fc.nflag) {
+            lists_body<D, true, R>(v, fc.nbt, (int)blockIdx.x - fc.nflag, v.ncls);
+            return;
+        }
+    }
     constexpr int NT = 256;                          // threads (the launch uses 256)
     constexpr int NSUB = D == 2 ? R * R : R * R * R;  // BS-blocks of the pmax block
     constexpr int K = R == 1 ? 0 : R == 2 ? 1 : R == 4 ? 2 : 3;   // levels of the split tree below the root
@@ -419,10 +461,13 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
 // then the block's current patch membership becomes the new one.
 // Classification of block gb (the blocks of every level numbered
 // consecutively): code and ghost mask (written, with the new patch
-// membership); false when the step is done (nothing written).
-template <int D>
-__device__ __forceinline__ bool classify_block(const View &v, int64_t gb, int done, int &code, uint32_t &gm,
-                                               int &lvl, int &nchild)
+// membership); false when the step is done (nothing written).  The new
+// masks come from the mask array, or (WORDS) from the flagging words of
+// the same launch once they carry epoch ep (a bounded wait: past the bound
+// late is set).  Level 0 is always in a patch.
+template <int D, bool WORDS, int R>
+__device__ __forceinline__ bool classify_block(const View &v, int64_t gb, int done, unsigned long long ep, int &late,
+                                               int &code, uint32_t &gm, int &lvl, int &nchild)
 {
     lvl = 0;
     for (int k = 1; k < MAXLEV && k < v.L; ++k) lvl += gb >= v.gt[k].boff ? 1 : 0;
@@ -430,32 +475,78 @@ __device__ __forceinline__ bool classify_block(const View &v, int64_t gb, int do
     const int nb = G.nb;
     const int b = (int)(gb - G.boff);
     const int bx = b % nb, by = (b / nb) % nb, bz = D == 3 ? b / (nb * nb) : 0;
+    constexpr int NN = D == 3 ? 27 : 9, NC = D == 3 ? 8 : 4;
+    const int r3 = D == 3 ? 1 : 0;
+    const bool hasf = lvl + 1 < v.L;
+    const Grid F = grid_lane(v, hasf ? lvl + 1 : lvl);
+    uint8_t na, oa, ch[8] = {0, 0, 0, 0, 0, 0, 0, 0}, nbv[27];
     // every mask read (the block, its children, its neighbours) is issued
     // before any is tested
-    const uint8_t na = v.nact[gb];
-    const uint8_t oa = v.act[gb];
-    uint8_t ch[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (lvl + 1 < v.L) {
-        const Grid F = grid_lane(v, lvl + 1);
-        const int zs = D == 3 ? 2 : 1;
-        for (int z = 0; z < zs; ++z)
-            for (int y = 0; y < 2; ++y)
-                for (int x = 0; x < 2; ++x)
-                    ch[x + 2 * (y + 2 * z)] =
-                        v.nact[F.boff + (2 * bx + x) + (int64_t)F.nb * ((2 * by + y) + (int64_t)F.nb * (2 * bz + z))];
-    }
-    uint8_t nbv[27];
-    const int r3 = D == 3 ? 1 : 0;
-    int j = 0;
-    for (int dz = -r3; dz <= r3; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int qx = bcmap(bx + dx, nb, v.bc), qy = bcmap(by + dy, nb, v.bc);
-                const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
-                nbv[j++] = lvl >= 1 ? v.nact[G.boff + qx + (int64_t)nb * (qy + (int64_t)nb * qz)] : 0;
+    oa = v.act[gb];
+    if constexpr (!WORDS) {
+        na = v.nact[gb];
+        if (hasf) {
+            for (int i = 0; i < NC; ++i) {
+                const int x = i & 1, y = (i >> 1) & 1, z = i >> 2;
+                ch[i] = v.nact[F.boff + (2 * bx + x) + (int64_t)F.nb * ((2 * by + y) + (int64_t)F.nb * (2 * bz + z))];
             }
-    issued((int)na, (int)oa, (int)nbv[0]);
-    if (done) return false;   // read with the masks above: one round trip for both
+        }
+        int j = 0;
+        for (int dz = -r3; dz <= r3; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int qx = bcmap(bx + dx, nb, v.bc), qy = bcmap(by + dy, nb, v.bc);
+                    const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
+                    nbv[j++] = lvl >= 1 ? v.nact[G.boff + qx + (int64_t)nb * (qy + (int64_t)nb * qz)] : 0;
+                }
+        issued((int)na, (int)oa, (int)nbv[0]);
+        if (done) return false;   // read with the masks above: one round trip for both
+    } else {
+        // neighbours (the block itself in the middle) on level lvl >= 1,
+        // children on level lvl+1; unused words read at a valid address
+        const unsigned long long *pn[NN], *pc[NC];
+        int bn[NN], bcb[NC];
+        unsigned long long xn[NN], xc[NC];
+        int j = 0;
+        for (int dz = -r3; dz <= r3; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int qx = bcmap(bx + dx, nb, v.bc), qy = bcmap(by + dy, nb, v.bc);
+                    const int qz = D == 3 ? bcmap(bz + dz, nb, v.bc) : 0;
+                    pn[j] = lvl >= 1 ? flag_word<D, R>(v, G, lvl, qx, qy, qz, bn[j]) : v.fword;
+                    if (lvl < 1) bn[j] = 0;
+                    xn[j] = __hip_atomic_load(pn[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ++j;
+                }
+        for (int i = 0; i < NC; ++i) {
+            const int x = i & 1, y = (i >> 1) & 1, z = i >> 2;
+            pc[i] = hasf ? flag_word<D, R>(v, F, lvl + 1, 2 * bx + x, 2 * by + y, 2 * bz + z, bcb[i]) : v.fword;
+            if (!hasf) bcb[i] = 0;
+            xc[i] = __hip_atomic_load(pc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        issued((int)oa, (int)xn[0], (int)xc[0]);
+        if (done) return false;   // nothing was flagged: no word is raised
+        auto wait = [&](const unsigned long long *p, unsigned long long x) {
+            for (int spin = 0; (x & 0xffffull) != ep; ++spin) {
+                if (spin == FLAG_MAXSPIN) {
+                    late = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            return x;
+        };
+        if (lvl >= 1)
+            for (int i = 0; i < NN; ++i) xn[i] = wait(pn[i], xn[i]);
+        if (hasf)
+            for (int i = 0; i < NC; ++i) xc[i] = wait(pc[i], xc[i]);
+        for (int i = 0; i < NN; ++i) nbv[i] = lvl >= 1 ? (uint8_t)((xn[i] >> (16 + bn[i])) & 1ull) : 0;
+        for (int i = 0; i < NC; ++i) ch[i] = hasf ? (uint8_t)((xc[i] >> (16 + bcb[i])) & 1ull) : 0;
+        na = lvl >= 1 ? nbv[NN / 2] : 1;
+        if (lvl < 1) for (int i = 0; i < NN; ++i) nbv[i] = 0;
+    }
+    const int j = NN;
     const bool a = na != 0;
     const bool old = oa != 0;
     nchild = 0;
@@ -512,9 +603,9 @@ __global__ void __launch_bounds__(256) k_classify(View v, int64_t nbt)
     const int64_t chunk = (nbt + gridDim.x - 1) / gridDim.x;
     const int64_t g0 = blockIdx.x * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
     for (int64_t gb = g0 + threadIdx.x; gb < g1; gb += blockDim.x) {
-        int code, lvl, nchild;
+        int code, lvl, nchild, late = 0;
         uint32_t gm;
-        if (!classify_block<D>(v, gb, done, code, gm, lvl, nchild)) break;
+        if (!classify_block<D, false, 1>(v, gb, done, 0ull, late, code, gm, lvl, nchild)) break;
         count_block<D>(part, lcnt, lvl, code, nchild);
     }
     if (done) return;
@@ -650,8 +741,8 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
 constexpr int LISTS_MAXCHUNK = 1024;
 constexpr int LISTS_MAXSPIN = 1 << 20;
 
-template <int D>
-__global__ void __launch_bounds__(256) k_lists(View v, int64_t nbt)
+template <int D, bool WORDS, int R>
+__device__ void lists_body(const View &v, int64_t nbt, int w, int W)
 {
     constexpr int NL = 5;
     __shared__ uint8_t scode[LISTS_MAXCHUNK];
@@ -663,7 +754,6 @@ __global__ void __launch_bounds__(256) k_lists(View v, int64_t nbt)
     __shared__ int64_t lstart[MAXLEV + 1];
     __shared__ int late;
     const int tid = threadIdx.x;
-    const int W = gridDim.x, w = blockIdx.x;
     unsigned long long *word = v.lword;
     const int done = v.meta->done;
     const unsigned long long own = __hip_atomic_load(word + 2 * w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -674,17 +764,22 @@ __global__ void __launch_bounds__(256) k_lists(View v, int64_t nbt)
     __syncthreads();
     const int64_t chunk = (nbt + W - 1) / W;
     const int64_t g0 = w * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
+    // this build's epoch; with WORDS also that of the flagging words, which
+    // are raised with the list words by every such launch (both start at
+    // zero with the hierarchy)
+    const unsigned long long e = ((own & 0xffffull) + 1) & 0xffffull;
+    int mlate = 0;
     for (int64_t gb = g0 + tid; gb < g1; gb += blockDim.x) {
         int code, lvl, nchild;
         uint32_t gm;
-        if (!classify_block<D>(v, gb, done, code, gm, lvl, nchild)) break;
+        if (!classify_block<D, WORDS, R>(v, gb, done, e, mlate, code, gm, lvl, nchild)) break;
         scode[gb - g0] = (uint8_t)code;
         sgm[gb - g0] = gm;
         count_block<D>(part, lcnt, lvl, code, nchild);
     }
     if (done) return;
+    if (mlate) late = 1;
     __syncthreads();
-    const unsigned long long e = ((own & 0xffffull) + 1) & 0xffffull;
     if (tid == 0) {
         // counts of at most LISTS_MAXCHUNK: 16 bits each
         const unsigned long long c[NL] = {(unsigned long long)lcnt[0], (unsigned long long)lcnt[1],
@@ -727,6 +822,12 @@ __global__ void __launch_bounds__(256) k_lists(View v, int64_t nbt)
         gm = sgm[k];
     });
     if (w == W - 1) write_list_lengths(v, base);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_lists(View v, int64_t nbt)
+{
+    lists_body<D, false, 1>(v, nbt, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -881,11 +982,22 @@ bool flag_chain_ok(const View &v)
            ((v.dim == 2 && R <= 4) || (v.dim == 3 && R <= 2));
 }
 
-void launch_flag_chain(const View &v, const int *wg0, int nseg, int total, hipStream_t s)
+static bool lists_single(const View &v, int64_t nbt)
+{
+    return !v.lists2 && (nbt + v.ncls - 1) / v.ncls <= LISTS_MAXCHUNK;
+}
+
+bool flag_chain_lists(const View &v, int64_t nbt) { return flag_chain_ok(v) && lists_single(v, nbt); }
+
+void launch_flag_chain(const View &v, const int *wg0, int nseg, int nflag, int64_t nbt, bool lists, hipStream_t s)
 {
     FlagChain fc{};
     for (int k = 0; k < nseg && k < MAXLEV; ++k) fc.wg0[k] = wg0[k];
     fc.nseg = nseg;
+    fc.nflag = nflag;
+    fc.lists = lists ? 1 : 0;
+    fc.nbt = nbt;
+    const int total = nflag + (lists ? v.ncls : 0);
     const FlagArgs fa{};
     const int R = v.pmax / BS;
     if (v.dim == 2) {
@@ -924,7 +1036,7 @@ void launch_cfl_final(const View &v, hipStream_t s)
 
 void launch_build_lists(const View &v, int64_t nbt, hipStream_t s)
 {
-    if (!v.lists2 && (nbt + v.ncls - 1) / v.ncls <= LISTS_MAXCHUNK) {
+    if (lists_single(v, nbt)) {
         if (v.dim == 2) k_lists<2><<<v.ncls, 256, 0, s>>>(v, nbt);
         else k_lists<3><<<v.ncls, 256, 0, s>>>(v, nbt);
         return;
