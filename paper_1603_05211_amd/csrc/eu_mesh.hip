@@ -526,21 +526,28 @@ __device__ __forceinline__ bool classify_block(const View &v, int64_t gb, int do
         }
         issued((int)oa, (int)xn[0], (int)xc[0]);
         if (done) return false;   // nothing was flagged: no word is raised
-        auto wait = [&](const unsigned long long *p, unsigned long long x) {
-            for (int spin = 0; (x & 0xffffull) != ep; ++spin) {
-                if (spin == FLAG_MAXSPIN) {
-                    late = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // every round reads again all the words not yet raised, together
+        for (int spin = 0;; ++spin) {
+            bool ok = true;
+#pragma unroll
+            for (int i = 0; i < NN; ++i) ok = ok && (lvl < 1 || (xn[i] & 0xffffull) == ep);
+#pragma unroll
+            for (int i = 0; i < NC; ++i) ok = ok && (!hasf || (xc[i] & 0xffffull) == ep);
+            if (ok) break;
+            if (spin == FLAG_MAXSPIN) {
+                late = 1;
+                break;
             }
-            return x;
-        };
-        if (lvl >= 1)
-            for (int i = 0; i < NN; ++i) xn[i] = wait(pn[i], xn[i]);
-        if (hasf)
-            for (int i = 0; i < NC; ++i) xc[i] = wait(pc[i], xc[i]);
+            __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+            for (int i = 0; i < NN; ++i)
+                if (lvl >= 1 && (xn[i] & 0xffffull) != ep)
+                    xn[i] = __hip_atomic_load(pn[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+                if (hasf && (xc[i] & 0xffffull) != ep)
+                    xc[i] = __hip_atomic_load(pc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         for (int i = 0; i < NN; ++i) nbv[i] = lvl >= 1 ? (uint8_t)((xn[i] >> (16 + bn[i])) & 1ull) : 0;
         for (int i = 0; i < NC; ++i) ch[i] = hasf ? (uint8_t)((xc[i] >> (16 + bcb[i])) & 1ull) : 0;
         na = lvl >= 1 ? nbv[NN / 2] : 1;
