@@ -115,7 +115,14 @@ int eu_query_sizes(const eu_config *cfg, size_t *state_bytes, size_t *scratch_by
  * memory, 256-byte aligned).  *out receives the context.  The work lists of
  * a regrid are built in one launch, or in two for ranges of more than 1024
  * blocks; the environment variable EU_LIST_BUILD=2, read here, selects the
- * two-launch build for every hierarchy (same lists; for tests). */
+ * two-launch build for every hierarchy (same lists; for tests).  Where the
+ * patch masks of a pmax block fit one word (2D with patch_max <= 32, 3D
+ * with patch_max <= 16) and there are three levels or more, every level is
+ * flagged in one launch, which also builds the lists when they take one
+ * launch; EU_FLAG_BUILD=levels, read here, selects one flagging launch per
+ * level instead (same flags and lists; for tests).  The waits between the
+ * workgroups of these launches are bounded: a wait past its bound makes
+ * the next synchronising call return EU_EHIP. */
 int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes,
               void *scratch_dev, size_t scratch_bytes, eu_ctx **out);
 

@@ -258,7 +258,7 @@ int sync_status(eu_ctx *c)
     int st = 0;
     HIPCHK(c, hipMemcpy(&st, &c->v.meta->status, sizeof(int), hipMemcpyDeviceToHost));
     if (st & 1) return set_err(c, EU_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN)");
-    if (st & 2) return set_err(c, EU_EHIP, "work-list build: a workgroup's wait for the counts before it timed out");
+    if (st & 2) return set_err(c, EU_EHIP, "flagging or work-list build: a workgroup's wait for another timed out");
     return EU_OK;
 }
 

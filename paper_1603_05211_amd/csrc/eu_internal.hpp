@@ -54,7 +54,8 @@ struct Tile {
 struct Meta {
     int nleaf;                 // tiles in the leaf list (blocks holding leaves)
     int nghost;                // tiles in the ghost list
-    int status;                // bit 0: non-physical state met
+    int status;                // bit 0: non-physical state met; bit 1 (value 2): a bounded
+                               // wait between workgroups timed out
     int done;                  // the current step starts at t >= t_end: skip it
     int steps;                 // steps taken since initialisation
     long long leaf_updates;    // leaf cells advanced since initialisation

@@ -30,7 +30,7 @@ struct FlagArgs {
 // above a 16-bit epoch one higher than the previous regrid's, and the
 // workgroups of level lvl read the masks from those words once they carry
 // the new epoch.  Only lower-numbered workgroups are waited for, and the
-// wait is bounded: past the bound the workgroup sets status bit 2 and goes
+// wait is bounded: past the bound the workgroup sets status flag 2 and goes
 // on (it still publishes, so every word keeps one epoch).
 struct FlagChain {
     int wg0[MAXLEV];
@@ -742,7 +742,7 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
 // one above the previous build's, and adds up the counts of the ranges
 // before its own once their words carry the new epoch.  Only lower-numbered
 // workgroups are waited for, and the wait is bounded: past the bound the
-// workgroup sets status bit 2 and writes no entries.  The words start with
+// workgroup sets status flag 2 and writes no entries.  The words start with
 // one epoch (cleared with the hierarchy) and every build that is not done
 // raises all of them, so they keep one epoch.
 constexpr int LISTS_MAXCHUNK = 1024;
