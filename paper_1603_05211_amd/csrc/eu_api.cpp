@@ -326,7 +326,8 @@ bool seq_restrict(eu_ctx *c, int arr, bool ghosts = false, bool details = false,
             const bool last = lo == 0;
             int64_t nbl = 0;
             for (int k = lo; k <= hi; ++k) nbl += nblocks_grid(c, k);
-            int64_t nb = nbl;
+            // a block two levels deep is four work items (one per field)
+            int64_t nb = nbl + (nlev == 2 ? 3 * nblocks_grid(c, lo) : 0);
             if (last && ghosts) nb += c->nbt;
             if (last && details) {
                 // 8x8 blocks of the levels projected here, 64-cell chunks of the rest

@@ -1149,6 +1149,10 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
         nbl[i] = nb * nb;
     }
     const int ncov = nbl[0] + nbl[1] + nbl[2];
+    // projection items: with two levels, each block of level lvl (two levels
+    // deep, 21 reads a field) is four items, one per field
+    const int nsplit = nlev == 2 ? 4 : 1;
+    const int nproj = nsplit * nbl[0] + nbl[1] + nbl[2];
     // MR details of levels 0 .. L-2 (ndet cells in all, only with lvl = 0):
     // 8x8 blocks of the levels projected here, then chunks of 64 cells of
     // the finer levels, from the first cell after those levels
@@ -1156,7 +1160,7 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
     const int64_t dfirst = Gt.coff + Gt.ncell;
     const int nin = ndet ? ncov : 0;
     const int nch = ndet ? nin + (int)((ndet - dfirst + 63) / 64) : 0;
-    const int nitem = nch + ncov + (ghosts ? v.nbt : 0);   // ghost entries: at most one per block
+    const int nitem = nch + nproj + (ghosts ? v.nbt : 0);   // ghost entries: at most one per block
     // block r of the projected levels: its level and index within the level
     auto level_block = [&](int r, int &k, int &b) {
         const int i = (r >= nbl[0] ? 1 : 0) + (r >= nbl[0] + nbl[1] ? 1 : 0);
@@ -1239,11 +1243,11 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
             }
             continue;
         }
-        if (t >= nch + ncov) {
+        if (t >= nch + nproj) {
             // ghost block of any level: predicted from the level below, whose
             // values are final or, for the levels projected in this pass,
             // projected here (the entry is read with the count)
-            const int g = t - nch - ncov;
+            const int g = t - nch - nproj;
             const Tile tl = v.ghost[g];
             if (done || g >= ngh) break;   // so are the later items of this workgroup
             const int lv = tl.grid & ((1 << Tile::GRID_BITS) - 1);
@@ -1280,9 +1284,11 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
         }
         // block of a projected level, when it holds covered cells: each
         // covered cell the mean of its children, projected through the
-        // levels below it in this pass
+        // levels below it in this pass (a block two levels deep: one field)
+        const int r = t - nch;
+        const bool split = r < nsplit * nbl[0] && nsplit > 1;
         int k, block;
-        level_block(t - nch, k, block);
+        level_block(split ? r / nsplit : r - (nsplit - 1) * nbl[0], k, block);
         const Grid G = grid_tab(tab, k);
         const int code = v.code[G.boff + block];
         if (done) break;
@@ -1291,10 +1297,16 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
         const int x = (block % nb) * BS + threadIdx.x % BS;
         const int y = ((block / nb) % nb) * BS + threadIdx.x / BS;
         const bool cov = covered(v.act, grid_tab(tab, k + 1), x, y, 0);
+        const int64_t id = G.off + gidx(G.n, x, y, 0);
+        if (split) {
+            const int f = r % nsplit;
+            const T val = proj_field<T, 2>(v, A, tab, k, x, y, f);
+            if (cov) A[id + f * G.ncell] = val;
+            continue;
+        }
         T val[NV];
         projected_value<T>(v, A, tab, k, hi, x, y, val);
         if (!cov) continue;
-        const int64_t id = G.off + gidx(G.n, x, y, 0);
 #pragma unroll
         for (int f = 0; f < NV; ++f) A[id + f * G.ncell] = val[f];
     }
