@@ -542,16 +542,27 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     const Tile *list = lts ? v.actv + v.meta->loff[LST_ACT][lvl] : v.leaf;
     const int count = lts ? v.meta->loff[LST_ACT][lvl + 1] - v.meta->loff[LST_ACT][lvl] : v.meta->nleaf;
     const double dt0 = v.dt[lts ? lvl : 0];
+    // One pass over an adaptive hierarchy's leaf list (a few thousand tiles
+    // at most, latency-bound) takes tiles blockIdx.x, blockIdx.x + gridDim.x,
+    // ...: the first entry does not depend on the count and is read with it,
+    // one round trip less before the halo loads.  Other passes (uniform
+    // grids, batches, a level of local time stepping) walk their tiles XCD
+    // by XCD, neighbouring tiles sharing an L2.
+    const bool inter = hier && !lts && v.L > 1;
+    const int t0 = (int)blockIdx.x < v.max_tiles ? (int)blockIdx.x : v.max_tiles - 1;
+    const Tile first = inter ? v.leaf[t0] : Tile{0, 0};
     if (hier) grid_tab_load(v, tab);
-    issued(list, count, dt0);
+    issued(list, count, dt0, first.grid, first.block);
     if (done) return;
     __syncthreads();
     const T g = (T)v.gamma;
     const T gi = (T)(1.0 / (v.gamma - 1.0));
     XcdWalk walk(count);
-    int t;
-    while (walk.next(count, t)) {
-        const Tile tl = list[t];
+    int t = inter ? (int)blockIdx.x - (int)gridDim.x : 0;
+    while (inter ? (t += gridDim.x) < count : walk.next(count, t)) {
+        Tile tl;
+        if (inter && t == (int)blockIdx.x) tl = first;
+        else tl = list[t];
         const Grid G = hier ? grid_tab(tab, tl.grid) : v.grids[tl.grid];
         const bool hasf = G.fine >= 0;
         const Grid GF = hasf ? grid_tab(tab, G.fine) : G;
