@@ -279,14 +279,16 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
         else any = dilated(k);
         if (nest && !any) {
             const int c[3] = {o0[0] + lx, o0[1] + ly, o0[2] + lz};
-            int lo[3], hi[3];
-            for (int d = 0; d < 3; ++d) {
-                lo[d] = d < D ? ((2 * c[d] - 2) >> 2) - vb0[d] : 0;
-                hi[d] = d < D ? ((2 * c[d] + 3) >> 2) - vb0[d] : 0;
-            }
-            for (int bz = lo[2]; bz <= hi[2]; ++bz)
-                for (int by = lo[1]; by <= hi[1]; ++by)
-                    for (int bx = lo[0]; bx <= hi[0]; ++bx) any |= snest[bx + NVB * (by + NVB * bz)];
+            // level-(lvl+1) cells 2c-2 .. 2c+3 lie in virtual level-(lvl+2)
+            // blocks (2c-2)>>2 .. (2c+3)>>2: always two per axis
+            int lo[3];
+            for (int d = 0; d < 3; ++d) lo[d] = d < D ? ((2 * c[d] - 2) >> 2) - vb0[d] : 0;
+#pragma unroll
+            for (int bz = 0; bz < (D == 3 ? 2 : 1); ++bz)
+#pragma unroll
+                for (int by = 0; by < 2; ++by)
+#pragma unroll
+                    for (int bx = 0; bx < 2; ++bx) any |= snest[(lo[0] + bx) + NVB * ((lo[1] + by) + NVB * (lo[2] + bz))];
         }
         const bool fl = in && any != 0;
         if (in) v.flag[G.coff + gidx(n, o0[0] + lx, o0[1] + ly, o0[2] + lz)] = fl ? 1 : 0;
@@ -661,7 +663,7 @@ __device__ __forceinline__ void write_lists(const View &v, int64_t g0, int64_t g
             block(gb, gb - g0, code, gm);
             code &= 15;
             if (code & 3) code |= 16;  // bit 4: in a patch
-            while (gb >= lstart[lvl + 1]) ++lvl;
+            for (int k = 1; k < MAXLEV && k < v.L; ++k) lvl += gb >= v.gt[k].boff ? 1 : 0;
         }
         int pre[NL];
         for (int k = 0; k < NL; ++k) {
