@@ -672,18 +672,24 @@ __device__ __forceinline__ void write_lists(const View &v, int64_t g0, int64_t g
             if (lane == 0) wc[wave][k] = __popcll(mask);
         }
         __syncthreads();
-        const bool first = gb < g1 && gb == lstart[lvl];   // first block of its level
+        // every LDS read of the offsets issued at once (at most four waves)
+        const int64_t ls = lstart[lvl];
+        const bool first = gb < g1 && gb == ls;   // first block of its level
+#pragma unroll
         for (int k = 0; k < NL; ++k) {
             int off = base[k] + pre[k];
-            for (int i = 0; i < wave; ++i) off += wc[i][k];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) off += i < wave ? wc[i][k] : 0;
             if ((code >> k) & 1)
-                lists[k][off] = Tile{k == LST_GHOST ? (int)(lvl | (gm << Tile::GRID_BITS)) : lvl, (int)(gb - lstart[lvl])};
+                lists[k][off] = Tile{k == LST_GHOST ? (int)(lvl | (gm << Tile::GRID_BITS)) : lvl, (int)(gb - ls)};
             if (first) v.meta->loff[k][lvl] = off;
         }
         __syncthreads();
         if (tid < NL) {
+            const int nw = (int)(blockDim.x >> 6);
             int s = 0;
-            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wc[i][tid];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s += i < nw ? wc[i][tid] : 0;
             base[tid] += s;
         }
         __syncthreads();
