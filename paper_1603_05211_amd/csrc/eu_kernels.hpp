@@ -543,13 +543,20 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     const int count = lts ? v.meta->loff[LST_ACT][lvl + 1] - v.meta->loff[LST_ACT][lvl] : v.meta->nleaf;
     const double dt0 = v.dt[lts ? lvl : 0];
     // One pass over an adaptive hierarchy's leaf list (a few thousand tiles
-    // at most, latency-bound) takes tiles blockIdx.x, blockIdx.x + gridDim.x,
-    // ...: the first entry does not depend on the count and is read with it,
-    // one round trip less before the halo loads.  Other passes (uniform
-    // grids, batches, a level of local time stepping) walk their tiles XCD
-    // by XCD, neighbouring tiles sharing an L2.
+    // at most, latency-bound) gives workgroup b a tile that does not depend
+    // on the count, tf, then tf + gridDim.x, ...: the first entry is read
+    // with the count, one round trip less before the halo loads.  Workgroup
+    // b runs on XCD b mod 8; with a grid of a multiple of 64 workgroups each
+    // XCD takes runs of 8 consecutive tiles (list neighbours share its L2).
+    // Other passes (uniform grids, batches, a level of local time stepping)
+    // walk their tiles XCD by XCD.
     const bool inter = hier && !lts && v.L > 1;
-    const int t0 = (int)blockIdx.x < v.max_tiles ? (int)blockIdx.x : v.max_tiles - 1;
+    int tf = (int)blockIdx.x;
+    if (gridDim.x % 64 == 0) {
+        const int x = tf & 7, j = tf >> 3;
+        tf = (j >> 3) * 64 + x * 8 + (j & 7);
+    }
+    const int t0 = tf < v.max_tiles ? tf : v.max_tiles - 1;
     const Tile first = inter ? v.leaf[t0] : Tile{0, 0};
     if (hier) grid_tab_load(v, tab);
     issued(list, count, dt0, first.grid, first.block);
@@ -558,10 +565,10 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     const T g = (T)v.gamma;
     const T gi = (T)(1.0 / (v.gamma - 1.0));
     XcdWalk walk(count);
-    int t = inter ? (int)blockIdx.x - (int)gridDim.x : 0;
+    int t = inter ? tf - (int)gridDim.x : 0;
     while (inter ? (t += gridDim.x) < count : walk.next(count, t)) {
         Tile tl;
-        if (inter && t == (int)blockIdx.x) tl = first;
+        if (inter && t == tf) tl = first;
         else tl = list[t];
         const Grid G = hier ? grid_tab(tab, tl.grid) : v.grids[tl.grid];
         const bool hasf = G.fine >= 0;
