@@ -546,15 +546,16 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     // at most, latency-bound) gives workgroup b a tile that does not depend
     // on the count, tf, then tf + gridDim.x, ...: the first entry is read
     // with the count, one round trip less before the halo loads.  Workgroup
-    // b runs on XCD b mod 8; with a grid of a multiple of 64 workgroups each
-    // XCD takes runs of 8 consecutive tiles (list neighbours share its L2).
+    // b runs on XCD b mod 8; with a grid of a multiple of 256 workgroups
+    // each XCD takes runs of 32 consecutive tiles (list neighbours share its
+    // L2; runs of 4, 8 and 16 measured slower).
     // Other passes (uniform grids, batches, a level of local time stepping)
     // walk their tiles XCD by XCD.
     const bool inter = hier && !lts && v.L > 1;
     int tf = (int)blockIdx.x;
-    if (gridDim.x % 64 == 0) {
+    if (gridDim.x % 256 == 0) {
         const int x = tf & 7, j = tf >> 3;
-        tf = (j >> 3) * 64 + x * 8 + (j & 7);
+        tf = (j >> 5) * 256 + x * 32 + (j & 31);
     }
     const int t0 = tf < v.max_tiles ? tf : v.max_tiles - 1;
     const Tile first = inter ? v.leaf[t0] : Tile{0, 0};
