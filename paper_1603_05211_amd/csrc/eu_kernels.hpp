@@ -71,6 +71,19 @@ struct XcdWalk {
     }
 };
 
+// Virtual index of workgroup b of a grid of G: a permutation of 0 .. G-1
+// under which each XCD (b mod 8) takes runs of consecutive indices, 32 long
+// when G is a multiple of 256, 8 long when it is a multiple of 64.  A
+// workgroup's first work item, index xcd_run(b) (then + G, + 2G, ...), does
+// not depend on any count, and neighbouring items share an L2.
+__device__ __forceinline__ int xcd_run(int b, int G)
+{
+    const int x = b & 7, j = b >> 3;
+    if (G % 256 == 0) return (j >> 5) * 256 + x * 32 + (j & 31);
+    if (G % 64 == 0) return (j >> 3) * 64 + x * 8 + (j & 7);
+    return b;
+}
+
 // issued(a, b, ...): the values are needed at this point.  The compiler
 // would otherwise sink a load whose result is only used under a later
 // branch into that branch, after the loads that decide it, and pay two
@@ -552,11 +565,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
     // Other passes (uniform grids, batches, a level of local time stepping)
     // walk their tiles XCD by XCD.
     const bool inter = hier && !lts && v.L > 1;
-    int tf = (int)blockIdx.x;
-    if (gridDim.x % 256 == 0) {
-        const int x = tf & 7, j = tf >> 3;
-        tf = (j >> 5) * 256 + x * 32 + (j & 31);
-    }
+    const int tf = xcd_run(blockIdx.x, gridDim.x);
     const int t0 = tf < v.max_tiles ? tf : v.max_tiles - 1;
     const Tile first = inter ? v.leaf[t0] : Tile{0, 0};
     if (hier) grid_tab_load(v, tab);
@@ -1186,7 +1195,7 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
         k = lvl + i;
         b = r - (i >= 1 ? nbl[0] : 0) - (i >= 2 ? nbl[1] : 0);
     };
-    for (int t = blockIdx.x; t < nitem; t += gridDim.x) {
+    for (int t = xcd_run(blockIdx.x, gridDim.x); t < nitem; t += gridDim.x) {
         if (t < nch) {
             const int r = t;
             if (r < nin) {
@@ -1445,7 +1454,8 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
     const int nb0 = D == 2 ? Gl.nb * Gl.nb : Gl.nb * Gl.nb * Gl.nb;
     const int nbh = nlev == 2 ? (D == 2 ? Gh.nb * Gh.nb : Gh.nb * Gh.nb * Gh.nb) : 0;
     const int count = direct ? nb0 + nbh : cnt0 + cnt1;
-    for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const int bv = xcd_run(blockIdx.x, gridDim.x);   // this workgroup's virtual index
+    for (int t = bv; t < count; t += gridDim.x) {
         bool fresh;
         Tile tl;
         if (direct) {
@@ -1544,7 +1554,7 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
     if (cfl) {
         // the leaf blocks, on the workgroups without a prediction when there
         // are such, two blocks at a time
-        const int G = gridDim.x, b = blockIdx.x;
+        const int G = gridDim.x, b = bv;
         const int nw = count < G ? G - count : G;
         const int w = count < G ? b - count : b;
         for (int u = w; w >= 0 && u < nleaf; u += 2 * nw) {
