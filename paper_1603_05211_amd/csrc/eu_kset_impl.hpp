@@ -58,7 +58,10 @@ template <typename T> void restrict2(const View &v, int a, int lvl, int nlev, in
 template <typename T> void predict(const View &v, int a, int lvl, int nlev, int mode, double theta, int cfl,
                                    int maxb, hipStream_t s)
 {
-    const int nblk = predict_grid(maxb);
+    // the launch that also reduces the CFL speeds takes up to 2048
+    // workgroups: the ones without a prediction then take the leaf tiles in
+    // one round of two
+    const int nblk = cfl && v.dim == 2 && mode == 3 ? clamp_grid(maxb, 2048) : predict_grid(maxb);
     const Grid Gl = v.gt[mode == 1 ? 0 : lvl], Cl = v.gt[mode == 1 ? 0 : lvl - 1];
     const Grid Gh = v.gt[nlev == 2 ? lvl + 1 : (mode == 1 ? 0 : lvl)];
     // the blocks of the levels walked directly when one pass takes them all
