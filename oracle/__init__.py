@@ -11,14 +11,17 @@ What pins each part (tests/test_oracle_pins.py, tests/test_oracle_adaptive.py):
 * primitive/conserved maps ....... definitions of Sec. 2 (round trip, closed forms)
 * van Albada slope ............... limiter function phi(r) = (r^2 + r)/(r^2 + 1)
 * AUSM+ flux ..................... consistency F(w, w) = f(w) with the physical
-                                   flux; supersonic upwinding; exact stationary contact
+                                   flux; supersonic upwinding; exact stationary contact;
+                                   Liou's expanded split polynomials (alpha, beta) on
+                                   asymmetric subsonic pairs
 * MUSCL + AUSM+ + midpoint RK2 ... exact Riemann solutions (Sod, seeded), order on a
                                    smooth periodic wave, exact 2D/3D reduction to 1D,
                                    transpose symmetry, conservation, free stream
 * CFL time step .................. closed form for a uniform state
 * totals ......................... exact sum (math.fsum)
-* restriction / prediction ....... mean of children; exact-rational biquadratic
-                                   interpolation; exact on quadratics; conservative
+* restriction / prediction ....... mean of children; exact-rational bi- and
+                                   triquadratic interpolation; exact on 2D and 3D
+                                   tensor quadratics; conservative
 * details / flags / tiling ....... independent detail computation, flag coverage,
                                    the efficiency rule, nesting, gradedness,
                                    threshold monotonicity
@@ -26,6 +29,14 @@ What pins each part (tests/test_oracle_pins.py, tests/test_oracle_adaptive.py):
                                    eps = inf equals the uniform coarse run, periodic
                                    conservation, free stream, accuracy perturbation
                                    (Sec. 3) against the uniform finest run
+* local time stepping ............ one level = global step; eps = 0 = uniform substeps;
+                                   conservation; a linear profile reproduced to rounding
+                                   across refinement boundaries (pins the ghost times
+                                   theta); second order on a smooth wave
+
+Planted-mistake controls (``planted``) show that the AUSM+, 3D prediction and
+ghost-time pins fail when alpha = beta = 0, the z pass is mirrored, or theta
+is held at 0.
 """
 from __future__ import annotations
 
@@ -96,6 +107,8 @@ def lib():
             "orc_h_analyse": (None, [vp]),
             "orc_h_npatch": (C.c_int, [vp]),
             "orc_h_set_no_reflux": (None, [vp, C.c_int]),
+            "orc_set_plant": (None, [C.c_int]),
+            "orc_h_set_active": (None, [vp, C.c_int, u8p]),
             "orc_h_patches": (None, [vp, i32p]),
             "orc_h_stage": (None, [vp, C.c_int, C.c_double]),
             "orc_h_step": (C.c_double, [vp, C.c_double, C.c_double, C.c_double, C.c_int]),
@@ -113,6 +126,26 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+PLANT_NONE, PLANT_AUSM_AB, PLANT_PRED_ZSWAP, PLANT_LTS_THETA = 0, 1, 2, 3
+
+
+class planted:
+    """Context manager of the tests' planted-mistake controls: inside the
+    block the oracle computes with one known mistake (see oracle.c), so a
+    test can show that its pin would catch it."""
+
+    def __init__(self, which: int):
+        self.which = which
+
+    def __enter__(self):
+        lib().orc_set_plant(self.which)
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_plant(PLANT_NONE)
+        return False
 
 
 def _dp(a: np.ndarray):
@@ -269,6 +302,14 @@ class Hierarchy:
         return act
 
     # ---- set-up
+    def set_active(self, l: int, mask: np.ndarray):
+        """Impose the patch membership of level l >= 1 (test-only: a fixed
+        hierarchy for runs without regrid).  Project and fill ghost cells
+        afterwards (restrict_all, ghost)."""
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert m.shape == (self.n(l),) * self.dim
+        lib().orc_h_set_active(self._h, l, m.ctypes.data_as(C.POINTER(C.c_uint8)))
+
     def init_finest(self, Q: np.ndarray):
         """Write finest-level data, restrict, analyse, flag, tile, fill ghosts."""
         self.level(self.L - 1)[...] = Q

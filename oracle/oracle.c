@@ -31,6 +31,16 @@
 
 enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1 };
 
+/* Test-only planted mistakes (controls that show a pin can fail): 0 = none;
+ * 1 = AUSM+ without its alpha / beta terms (plain AUSM splitting);
+ * 2 = the z pass of the 3D prediction with the upper / lower child swapped;
+ * 3 = ghost cells of local time stepping taken from the coarse state at the
+ *     start of its step at every stage (constant theta = 0).
+ * With 0 every result is the method's, bit for bit. */
+enum { PLANT_NONE = 0, PLANT_AUSM_AB = 1, PLANT_PRED_ZSWAP = 2, PLANT_LTS_THETA = 3 };
+static int plant = PLANT_NONE;
+void orc_set_plant(int which) { plant = which; }
+
 /* ------------------------------------------------------------------------ */
 /* grid helpers                                                             */
 /* ------------------------------------------------------------------------ */
@@ -121,6 +131,11 @@ static void ausm_plus(int dim, double g, int dn, const double *wL,
     double ch = 0.5 * (cL + cR);
     double ML = uL / ch, MR = uR / ch;
     double Mp, Pp, Mm, Pm;
+    /* Liou's coefficients alpha = 3/16, beta = 1/8; 16 beta = 2 and
+     * 16 alpha = 3 exactly */
+    const double alpha = plant == PLANT_AUSM_AB ? 0.0 : 3.0 / 16.0;
+    const double beta = plant == PLANT_AUSM_AB ? 0.0 : 1.0 / 8.0;
+    const double b16 = 16.0 * beta, a16 = 16.0 * alpha;
     /* split Mach number M4+ and pressure P5+ of the left state */
     if (fabs(ML) >= 1.0) {
         Mp = 0.5 * (ML + fabs(ML));
@@ -128,8 +143,8 @@ static void ausm_plus(int dim, double g, int dn, const double *wL,
     } else {
         double a = ML + 1.0, b = ML - 1.0;
         double m2p = 0.25 * (a * a), m2m = -0.25 * (b * b);
-        Mp = m2p * (1.0 - 2.0 * m2m);                 /* 16 beta = 2  */
-        Pp = m2p * ((2.0 - ML) - (3.0 * ML) * m2m);   /* 16 alpha = 3 */
+        Mp = m2p * (1.0 - b16 * m2m);
+        Pp = m2p * ((2.0 - ML) - (a16 * ML) * m2m);
     }
     /* split Mach number M4- and pressure P5- of the right state */
     if (fabs(MR) >= 1.0) {
@@ -138,8 +153,8 @@ static void ausm_plus(int dim, double g, int dn, const double *wL,
     } else {
         double a = MR + 1.0, b = MR - 1.0;
         double m2p = 0.25 * (a * a), m2m = -0.25 * (b * b);
-        Mm = m2m * (1.0 + 2.0 * m2p);
-        Pm = m2m * ((-2.0 - MR) + (3.0 * MR) * m2p);
+        Mm = m2m * (1.0 + b16 * m2p);
+        Pm = m2m * ((-2.0 - MR) + (a16 * MR) * m2p);
     }
     double mh = Mp + Mm;
     double ph = Pp * pL + Pm * pR;
@@ -230,7 +245,7 @@ static double predict_child(int dim, int nc, int bc, const double *Ac,
             r[j] = pred1(AC(xs[0], ys[j], zs[k]), AC(xs[1], ys[j], zs[k]), AC(xs[2], ys[j], zs[k]), ch[0]);
         s[k] = pred1(r[0], r[1], r[2], ch[1]);
     }
-    return pred1(s[0], s[1], s[2], ch[2]);
+    return pred1(s[0], s[1], s[2], plant == PLANT_PRED_ZSWAP ? !ch[2] : ch[2]);
 #undef AC
 }
 
@@ -471,6 +486,16 @@ static void h_ghost_time(orc_h *h, int l, double **A, double **Aold, double **An
 }
 
 void orc_h_restrict(orc_h *h) { h_restrict(h, h->Q); }
+
+/* Test-only: impose the patch membership of level l >= 1 (a fixed
+ * hierarchy for runs without regrid); the caller keeps it properly nested
+ * and then projects and fills the ghost cells. */
+void orc_h_set_active(orc_h *h, int l, const uint8_t *mask)
+{
+    if (l < 1 || l >= h->L) return;
+    memcpy(h->act[l], mask, (size_t)hN(h, l));
+    memcpy(h->nact[l], mask, (size_t)hN(h, l));
+}
 void orc_h_ghost(orc_h *h) { h_ghost(h, h->Q); }
 
 /* ---- the finite-volume update ---- */
@@ -1057,12 +1082,15 @@ static void lts_advance(orc_h *h, int l, double dt, int k)
 {
     int64_t N = hN(h, l);
     memcpy(h->Qo[l], h->Q[l], (size_t)(h->nv * N) * sizeof(double));
+    /* stage times of substep k of level l within its parent's step: the
+     * start, k / 2, and the midpoint, (2k + 1) / 4, as fractions of it */
+    const int flat = plant == PLANT_LTS_THETA;
     h_fv_level_all(h, l, h->Q, h->Qs, (dt * 0.5) / h->dx[l], 0, k);
-    if (l >= 1) h_ghost_time(h, l, h->Qs, h->Qo, h->Q, (double)(2 * k + 1) * 0.25);
+    if (l >= 1) h_ghost_time(h, l, h->Qs, h->Qo, h->Q, flat ? 0.0 : (double)(2 * k + 1) * 0.25);
     h_fv_level_all(h, l, h->Qs, h->Q, dt / h->dx[l], 1, k);
     if (l + 1 < h->L) {
         for (int kk = 0; kk < 2; ++kk) {
-            h_ghost_time(h, l + 1, h->Q, h->Qo, h->Q, (double)kk * 0.5);
+            h_ghost_time(h, l + 1, h->Q, h->Qo, h->Q, flat ? 0.0 : (double)kk * 0.5);
             lts_advance(h, l + 1, dt * 0.5, kk);
         }
         h_restrict_level(h, h->Q, l);

@@ -417,3 +417,169 @@ def test_ellipsoid_volume(orc):
     Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")
     ref = (X / e.a) ** 2 + (Y / e.b) ** 2 + (Z / e.c) ** 2 < 1
     assert np.array_equal(Q0[0] == e.states[0], ref)
+
+
+# --------------------------------------------------------------------------
+# AUSM+ subsonic terms (alpha, beta) against Liou's expanded polynomials
+# --------------------------------------------------------------------------
+
+def _ausm_plus_expanded(w_l, w_r, axis, g=G, alpha=3.0 / 16.0, beta=1.0 / 8.0):
+    """AUSM+ (Liou 1996) written from the expanded split functions
+        M4+-(M) = +-(M +- 1)^2 / 4 +- beta (M^2 - 1)^2,
+        P5+-(M) = (M +- 1)^2 (2 -+ M) / 4 +- alpha M (M^2 - 1)^2   (|M| < 1),
+    and M4+- = (M +- |M|)/2, P5+- = (1 +- sign M)/2 for |M| >= 1; the mass
+    flux c_half m_half carries the upwind (rho, rho v, rho H), the pressure
+    p_half acts on the normal momentum.  c_half = (c_L + c_R) / 2."""
+    dim = len(w_l) - 2
+
+    def parts(w):
+        rho, v, p = w[0], np.asarray(w[1:1 + dim], dtype=float), w[-1]
+        return rho, v, p, math.sqrt(g * p / rho)
+
+    rl, vl, pl, cl = parts(w_l)
+    rr, vr, pr, cr = parts(w_r)
+    ch = 0.5 * (cl + cr)
+    Ml, Mr = vl[axis] / ch, vr[axis] / ch
+
+    def m4(M, s):
+        if abs(M) >= 1:
+            return 0.5 * (M + s * abs(M))
+        return s * 0.25 * (M + s) ** 2 + s * beta * (M * M - 1) ** 2
+
+    def p5(M, s):
+        if abs(M) >= 1:
+            return 0.5 * (1 + s * math.copysign(1.0, M)) if M != 0 else 0.5
+        return 0.25 * (M + s) ** 2 * (2 - s * M) + s * alpha * M * (M * M - 1) ** 2
+
+    mh = m4(Ml, +1) + m4(Mr, -1)
+    ph = p5(Ml, +1) * pl + p5(Mr, -1) * pr
+    rho, v, p = (rl, vl, pl) if mh >= 0 else (rr, vr, pr)
+    H = (p / (g - 1) + 0.5 * rho * float(v @ v) + p) / rho
+    F = ch * mh * np.concatenate([[rho], rho * v, [rho * H]])
+    F[1 + axis] += ph
+    return F
+
+
+def _ausm_subsonic_pairs(rng, dim, n=300):
+    """Asymmetric face states with both normal Mach numbers (relative to the
+    mean sound speed) below one, plus mixed pairs (one side supersonic)."""
+    out = []
+    while len(out) < n:
+        wl = np.concatenate([[rng.uniform(0.2, 3)], rng.uniform(-1, 1, dim), [rng.uniform(0.2, 3)]])
+        wr = np.concatenate([[rng.uniform(0.2, 3)], rng.uniform(-1, 1, dim), [rng.uniform(0.2, 3)]])
+        ax = int(rng.integers(dim))
+        out.append((wl, wr, ax))
+    return out
+
+
+def _ausm_max_dev(orc, dim, seed=11):
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    nsub = 0
+    for wl, wr, ax in _ausm_subsonic_pairs(rng, dim):
+        ch = 0.5 * (math.sqrt(G * wl[-1] / wl[0]) + math.sqrt(G * wr[-1] / wr[0]))
+        if abs(wl[1 + ax] / ch) < 1 and abs(wr[1 + ax] / ch) < 1:
+            nsub += 1
+        F = orc.ausm_plus(dim, G, ax, wl, wr)
+        ref = _ausm_plus_expanded(wl, wr, ax)
+        worst = max(worst, np.abs(F - ref).max() / max(np.abs(ref).max(), 1.0))
+    assert nsub > 100  # the subsonic branch, where alpha and beta act, is exercised
+    return worst
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ausm_plus_subsonic_split_functions(orc, dim):
+    """The oracle's factored split functions equal Liou's expanded
+    polynomials with alpha = 3/16 and beta = 1/8 (Sec. 2 cites AUSM+ [Liou
+    1996]) on asymmetric subsonic pairs, where F(w, w) = f(w) cannot see
+    either coefficient (their terms cancel between the + and - parts)."""
+    assert _ausm_max_dev(orc, dim) <= 1e-13
+
+
+def test_ausm_plus_pin_catches_missing_alpha_beta(orc):
+    """Control: with alpha = beta = 0 planted in the oracle (plain AUSM
+    splitting), the pin above fails by orders of magnitude, while the
+    consistency pin F(w, w) = f(w) still passes."""
+    w = np.array([0.9, 0.3, -0.2, 1.3])
+    with orc.planted(orc.PLANT_AUSM_AB):
+        dev = _ausm_max_dev(orc, 2)
+        F = orc.ausm_plus(2, G, 0, w, w)
+    assert dev > 1e-3, dev
+    assert np.allclose(F, phys_flux(w, 0), rtol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# 3D prediction (the z pass)
+# --------------------------------------------------------------------------
+
+def _pred3d_bruteforce_max_dev(orc, seed=12):
+    """Largest deviation of the oracle's 3D prediction from the child
+    averages of the triquadratic interpolant of a 3x3x3 block of coarse
+    averages, in exact rationals (the 1D definition applied along each axis:
+    the interpolant is a tensor product, so the axis order is immaterial)."""
+    rng = np.random.default_rng(seed)
+    Ac = rng.integers(-20, 20, size=(1, 3, 3, 3)).astype(np.float64) / 8.0
+    Af = orc.predict(3, Ac)
+    worst = Fraction(0)
+    for cz in (0, 1):
+        for cy in (0, 1):
+            for cx in (0, 1):
+                # z first, then y, then x (the oracle goes x, y, z)
+                zs = [[_quad_interp_child_avg(*(Fraction(Ac[0, k, j, i]) for k in range(3)), cz)
+                       for i in range(3)] for j in range(3)]
+                ys = [_quad_interp_child_avg(*(zs[j][i] for j in range(3)), cy) for i in range(3)]
+                exact = _quad_interp_child_avg(*ys, cx)
+                worst = max(worst, abs(Fraction(Af[0, 2 + cz, 2 + cy, 2 + cx]) - exact))
+    return float(worst)
+
+
+def _pred3d_quadratic_max_dev(orc):
+    """Largest deviation on cell averages of the monomials x^a y^b z^c (a,
+    b, c <= 2) of the fine cells inside the coarse grid's interior."""
+    n = 8
+    h = 1.0 / n
+    e = np.arange(n + 1) * h
+    fe = np.arange(2 * n + 1) * (h / 2)
+
+    def avg(k, ed):
+        return (ed[1:] ** (k + 1) - ed[:-1] ** (k + 1)) / ((k + 1) * (ed[1:] - ed[:-1]))
+
+    worst = 0.0
+    for (kx, ky, kz) in [(0, 0, 1), (0, 0, 2), (1, 0, 1), (2, 1, 2), (0, 2, 1), (2, 2, 2), (1, 1, 0)]:
+        Ac = np.einsum("k,j,i->kji", avg(kz, e), avg(ky, e), avg(kx, e))[None]
+        ex = np.einsum("k,j,i->kji", avg(kz, fe), avg(ky, fe), avg(kx, fe))
+        Af = orc.predict(3, Ac, orc.BC_PERIODIC)
+        inner = (slice(2, -2),) * 3
+        worst = max(worst, np.abs(Af[0][inner] - ex[inner]).max())
+    return worst
+
+
+def test_prediction_3d_matches_interpolation_definition(orc):
+    assert _pred3d_bruteforce_max_dev(orc) == 0.0
+
+
+def test_prediction_3d_exact_on_tensor_quadratics(orc):
+    """Sec. 2.1: the third-order prediction reproduces the cell averages of
+    polynomials of degree two per axis; a cubic in z is not reproduced."""
+    assert _pred3d_quadratic_max_dev(orc) <= 1e-14
+    n = 8
+    e = np.arange(n + 1) / n
+    fe = np.arange(2 * n + 1) / (2 * n)
+    avg = lambda k, ed: (ed[1:] ** (k + 1) - ed[:-1] ** (k + 1)) / ((k + 1) * (ed[1:] - ed[:-1]))
+    Ac = np.einsum("k,j,i->kji", avg(3, e), avg(0, e), avg(0, e))[None]
+    ex = np.einsum("k,j,i->kji", avg(3, fe), avg(0, fe), avg(0, fe))
+    Af = orc.predict(3, Ac, orc.BC_PERIODIC)
+    assert np.abs(Af[0][2:-2, 2:-2, 2:-2] - ex[2:-2, 2:-2, 2:-2]).max() > 1e-6
+
+
+def test_prediction_3d_pins_catch_z_swap(orc):
+    """Control: with the upper and lower child of the z pass swapped in the
+    oracle, both 3D pins fail, while conservation and constants (the only 3D
+    checks before) still hold."""
+    rng = np.random.default_rng(4)
+    with orc.planted(orc.PLANT_PRED_ZSWAP):
+        assert _pred3d_bruteforce_max_dev(orc) > 1e-3
+        assert _pred3d_quadratic_max_dev(orc) > 1e-4
+        Ac = rng.uniform(0.5, 2.0, size=(1, 6, 6, 6))
+        assert np.allclose(orc.restrict(3, orc.predict(3, Ac)), Ac, rtol=1e-15, atol=0)
+    assert _pred3d_bruteforce_max_dev(orc) == 0.0
