@@ -122,7 +122,10 @@ int eu_query_sizes(const eu_config *cfg, size_t *state_bytes, size_t *scratch_by
  * launch; EU_FLAG_BUILD=levels, read here, selects one flagging launch per
  * level instead (same flags and lists; for tests).  The waits between the
  * workgroups of these launches are bounded: a wait past its bound makes
- * the next synchronising call return EU_EHIP. */
+ * the next synchronising call return EU_EHIP.  EU_WAIT_TEST=stale, read
+ * here, makes the list build wait for an epoch no workgroup publishes, with
+ * a short bound (a test of that path: the lists are then left incomplete,
+ * every kernel ends, and the context is only fit to be destroyed). */
 int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes,
               void *scratch_dev, size_t scratch_bytes, eu_ctx **out);
 
@@ -150,9 +153,12 @@ int eu_mr_decompose(eu_ctx *ctx);
  * one-cell buffer and the nesting closure, finest level first, and are tiled
  * into aligned patches with the efficiency rule.  Old cells keep their data;
  * new cells are predicted from the next coarser level; ghost cells are
- * filled.  nflag_host (nullable, levels entries) receives the number of
- * flagged cells per level. */
-int eu_mr_flag(eu_ctx *ctx, int64_t *nflag_host);
+ * filled.  eps >= 0 replaces the threshold of the configuration (the
+ * details of the last eu_mr_decompose are taken against it, and later steps
+ * keep it); eps < 0 keeps the current one; NaN is EU_EINVAL.  nflag_host
+ * (nullable, levels entries) receives the number of flagged cells per level
+ * (synchronises). */
+int eu_mr_flag(eu_ctx *ctx, double eps, int64_t *nflag_host);
 
 /* Inter-level transfer (Sec. 2.1 projection / prediction, Sec. 2.2 ghost
  * cells): EU_RESTRICT projects every covered cell (finest first);
@@ -160,25 +166,40 @@ int eu_mr_flag(eu_ctx *ctx, int64_t *nflag_host);
  * every ghost cell by prediction from the next coarser level. */
 int eu_project(eu_ctx *ctx, int mode);
 
-/* CFL time step (FP64): dt = min over levels cfl dx_l / max over leaves of
- * sum_d (|v_d| + c), clipped to reach t_end, per instance for a batch.  The
- * result stays on the device for eu_fv_step; dt_host (nullable) receives it
- * (instance 0).  Computing dt commits the step it sizes: the context time
+/* CFL time step (FP64; the paper's runs use CFL about 0.4, Sec. 4.2):
+ * dt = min over levels cfl dx_l / max over leaves of sum_d (|v_d| + c) (with
+ * local time stepping the level-0 step min over levels of that times 2^l),
+ * clipped to reach t_end and to t_remaining, per instance for a batch.
+ * cfl > 0 replaces the configuration's CFL number for this call (else it is
+ * used); t_remaining >= 0 clips this step (a step with t_remaining = 0 is
+ * marked done), t_remaining < 0 or INFINITY does not.  NaN arguments are
+ * EU_EINVAL.  The result stays on the device for eu_fv_step; dt_dev
+ * (nullable, device memory, 1 double, or n_instances for a batch) receives
+ * a copy on the stream, dt_host (nullable) receives it for instance 0
+ * (synchronises).  Computing dt commits the step it sizes: the context time
  * advances to t + dt here (a step starting at t >= t_end is marked done and
  * every later kernel of that step does nothing).  Detects non-physical
  * leaves (EU_ENONPHYS at the next synchronising call). */
-int eu_cfl_dt(eu_ctx *ctx, double *dt_host);
+int eu_cfl_dt(eu_ctx *ctx, double cfl, double t_remaining, double *dt_dev, double *dt_host);
 
-/* One explicit midpoint (RK2) step of every leaf with the device dt of the
- * last eu_cfl_dt (Sec. 2): Q* = Q - dt/2 F(Q), Q <- Q - dt F(Q*), each
- * stage followed by projection onto covered cells and ghost fill; faces
- * between a leaf and a covered cell take the mean of the fine fluxes.
- * In EU_DT_LTS mode one call advances one level-0 step with the recursive
- * level cycle (Sec. 2.2, Fig. 2). */
-int eu_fv_step(eu_ctx *ctx);
+/* One explicit midpoint (RK2) step of every leaf (Sec. 2, dQ/dt = -F(Q)):
+ * Q* = Q - dt/2 F(Q), Q <- Q - dt F(Q*), each stage followed by projection
+ * onto covered cells and ghost fill; faces between a leaf and a covered cell
+ * take the mean of the fine fluxes.  dt_dev NULL: the dt of the last
+ * eu_cfl_dt; else device memory holding the step's dt (1 double, or
+ * n_instances for a batch; e.g. a minimum over several subdomains): the
+ * step committed by the last eu_cfl_dt takes it, and the context time
+ * becomes that step's start time plus it (negative values count as 0).
+ * level -1: every level; with EU_DT_LTS one level-0 step of the recursive
+ * level cycle (Sec. 2.2, Fig. 2).  level l >= 0 (EU_DT_LTS only): the
+ * cycle from level l (its step of dt_l = dt_0 / 2^l, then its finer levels'
+ * substeps, projection and flux correction) as the first substep of its
+ * parent's step, whose start and end states level l-1 must hold.  A level
+ * out of range, or level >= 0 with a global time step, is EU_EINVAL. */
+int eu_fv_step(eu_ctx *ctx, const double *dt_dev, int level);
 
 /* One full time step: eu_cfl_dt, eu_fv_step and, if regrid != 0,
- * eu_mr_decompose + eu_mr_flag. */
+ * eu_mr_decompose + eu_mr_flag (configuration CFL number and threshold). */
 int eu_step(eu_ctx *ctx, int regrid);
 
 /* nsteps calls of eu_step(ctx, 1) (or until t_end), replayed from one
@@ -187,8 +208,12 @@ int eu_step(eu_ctx *ctx, int regrid);
 int eu_advance(eu_ctx *ctx, int nsteps, int use_graph, int *steps_done_host);
 
 /* Conserved totals sum over leaves of Q_f |cell| in FP64 (fixed summation
- * order), per instance: totals_host receives n_instances x (d+2) values. */
-int eu_conserved_totals(eu_ctx *ctx, double *totals_host);
+ * order), per instance: the quantities the flux correction at refinement
+ * boundaries keeps constant up to boundary fluxes (Sec. 2.2).  totals_dev
+ * (nullable, device memory) receives n_instances x (d+2) values on the
+ * stream without synchronising (graph-capturable); totals_host (nullable)
+ * receives them after a synchronisation. */
+int eu_conserved_totals(eu_ctx *ctx, double *totals_dev, double *totals_host);
 
 /* Copy one level (instance inst for a batch, level ignored) of the current
  * state (which = 0) or the RK2 stage state (which = 1) to FP64 host memory
@@ -211,9 +236,11 @@ int eu_get_active(eu_ctx *ctx, int level, uint8_t *dst_host);
 int eu_get_flags(eu_ctx *ctx, int level, uint8_t *dst_host);
 int eu_get_details(eu_ctx *ctx, int level, double *dst_host);
 
-/* Patch table rows {level, ox, oy, oz, size} ordered by level, then Morton
- * order of the enclosing patch_max block, then recursive split order.  At
- * most cap rows are written; *npatch_host receives the total. */
+/* Patch table of the new mesh (the rectangular submeshes G_{l,m} of
+ * Sec. 2.2, generated with the efficiency rule eta_tol): rows {level, ox,
+ * oy, oz, size} ordered by level, then Morton order of the enclosing
+ * patch_max block, then recursive split order.  At most cap rows are
+ * written to dst_host; *npatch_host receives the total (synchronises). */
 int eu_patch_table(eu_ctx *ctx, int32_t *dst_host, int cap, int *npatch_host);
 
 /* Leaf and active (patch) cell counts per level (levels entries each). */

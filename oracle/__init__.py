@@ -105,6 +105,7 @@ def lib():
             "orc_h_init": (None, [vp]),
             "orc_h_regrid": (None, [vp]),
             "orc_h_analyse": (None, [vp]),
+            "orc_h_set_eps": (None, [vp, C.c_double]),
             "orc_h_npatch": (C.c_int, [vp]),
             "orc_h_set_no_reflux": (None, [vp, C.c_int]),
             "orc_set_plant": (None, [C.c_int]),
@@ -351,6 +352,11 @@ class Hierarchy:
 
     def regrid(self):
         lib().orc_h_regrid(self._h)
+
+    def set_eps(self, eps: float):
+        """Replace the detail threshold for later analyses."""
+        self.eps = eps
+        lib().orc_h_set_eps(self._h, eps)
 
     def totals(self) -> np.ndarray:
         tot = np.zeros(self.nv)

@@ -875,6 +875,9 @@ void orc_h_regrid(orc_h *h)
 
 void orc_h_analyse(orc_h *h) { h_details(h); }
 
+/* Replace the detail threshold (same on every level) for later analyses. */
+void orc_h_set_eps(orc_h *h, double eps) { h->eps = eps; }
+
 int orc_h_npatch(const orc_h *h) { return h->npatch; }
 
 /* Test-only: plant the mistake of skipping the flux correction. */

@@ -154,25 +154,43 @@ class Solver:
     def mr_decompose(self):
         self._check(self._lib.eu_mr_decompose(self._ctx), "eu_mr_decompose")
 
-    def mr_flag(self):
+    def mr_flag(self, eps: float = -1.0):
+        """Threshold, closure, tiling and new cells (eu_mr_flag); eps >= 0
+        replaces the threshold.  Returns the flagged cells per level."""
         out = np.zeros(self.levels, dtype=np.int64)
-        self._check(self._lib.eu_mr_flag(self._ctx, out.ctypes.data_as(C.POINTER(C.c_int64))),
+        self._check(self._lib.eu_mr_flag(self._ctx, float(eps), out.ctypes.data_as(C.POINTER(C.c_int64))),
                     "eu_mr_flag")
         return out
 
     def project(self, mode: int):
         self._check(self._lib.eu_project(self._ctx, mode), "eu_project")
 
-    def cfl_dt(self, host: bool = True):
+    def cfl_dt(self, host: bool = True, cfl: float = -1.0, t_remaining: float = -1.0, dt_out=None):
+        """eu_cfl_dt: cfl > 0 replaces the configured CFL number, t_remaining
+        >= 0 clips the step; dt_out (a float64 CUDA tensor, optional)
+        receives the step's dt on the device.  Returns dt (instance 0) when
+        host is set."""
+        dev = None
+        if dt_out is not None:
+            assert dt_out.dtype == self.torch.float64 and dt_out.is_cuda and dt_out.numel() >= self.n_instances
+            dev = C.c_void_p(dt_out.data_ptr())
         if not host:
-            self._check(self._lib.eu_cfl_dt(self._ctx, None), "eu_cfl_dt")
+            self._check(self._lib.eu_cfl_dt(self._ctx, float(cfl), float(t_remaining), dev, None), "eu_cfl_dt")
             return None
         dt = C.c_double(0.0)
-        self._check(self._lib.eu_cfl_dt(self._ctx, C.byref(dt)), "eu_cfl_dt")
+        self._check(self._lib.eu_cfl_dt(self._ctx, float(cfl), float(t_remaining), dev, C.byref(dt)),
+                    "eu_cfl_dt")
         return dt.value
 
-    def fv_step(self):
-        self._check(self._lib.eu_fv_step(self._ctx), "eu_fv_step")
+    def fv_step(self, dt=None, level: int = -1):
+        """eu_fv_step: dt (a float64 CUDA tensor, optional) replaces the dt of
+        the last cfl_dt; level -1 = every level (>= 0: local time stepping
+        from that level)."""
+        dev = None
+        if dt is not None:
+            assert dt.dtype == self.torch.float64 and dt.is_cuda and dt.numel() >= self.n_instances
+            dev = C.c_void_p(dt.data_ptr())
+        self._check(self._lib.eu_fv_step(self._ctx, dev, int(level)), "eu_fv_step")
 
     def step(self, regrid: bool = True):
         self._check(self._lib.eu_step(self._ctx, int(regrid)), "eu_step")
@@ -182,9 +200,20 @@ class Solver:
         self._check(self._lib.eu_advance(self._ctx, nsteps, int(use_graph), C.byref(done)), "eu_advance")
         return done.value
 
-    def conserved_totals(self) -> np.ndarray:
+    def conserved_totals(self, out_dev=None, host: bool = True):
+        """eu_conserved_totals: out_dev (a float64 CUDA tensor of n_instances
+        x nv, optional) receives the totals on the device without a
+        synchronisation; with host set they are also returned."""
+        dev = None
+        if out_dev is not None:
+            assert out_dev.dtype == self.torch.float64 and out_dev.is_cuda
+            assert out_dev.numel() >= self.n_instances * self.nv
+            dev = C.c_void_p(out_dev.data_ptr())
+        if not host:
+            self._check(self._lib.eu_conserved_totals(self._ctx, dev, None), "eu_conserved_totals")
+            return None
         out = np.zeros(self.n_instances * self.nv)
-        self._check(self._lib.eu_conserved_totals(self._ctx, _dp(out)), "eu_conserved_totals")
+        self._check(self._lib.eu_conserved_totals(self._ctx, dev, _dp(out)), "eu_conserved_totals")
         return out.reshape(self.n_instances, self.nv) if self.n_instances > 1 else out
 
     # ------------------------------------------------------------------ read-back

@@ -50,13 +50,13 @@ SIGNATURES = {
     "eu_init_state": (C.c_int, [_vp, C.POINTER(EuProblem)]),
     "eu_set_finest": (C.c_int, [_vp, C.c_int, _dp]),
     "eu_mr_decompose": (C.c_int, [_vp]),
-    "eu_mr_flag": (C.c_int, [_vp, _i64p]),
+    "eu_mr_flag": (C.c_int, [_vp, C.c_double, _i64p]),
     "eu_project": (C.c_int, [_vp, C.c_int]),
-    "eu_cfl_dt": (C.c_int, [_vp, _dp]),
-    "eu_fv_step": (C.c_int, [_vp]),
+    "eu_cfl_dt": (C.c_int, [_vp, C.c_double, C.c_double, _vp, _dp]),
+    "eu_fv_step": (C.c_int, [_vp, _vp, C.c_int]),
     "eu_step": (C.c_int, [_vp, C.c_int]),
     "eu_advance": (C.c_int, [_vp, C.c_int, C.c_int, _ip]),
-    "eu_conserved_totals": (C.c_int, [_vp, _dp]),
+    "eu_conserved_totals": (C.c_int, [_vp, _vp, _dp]),
     "eu_copy_level": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
     "eu_copy_uniform": (C.c_int, [_vp, _dp]),
     "eu_get_active": (C.c_int, [_vp, C.c_int, _u8p]),

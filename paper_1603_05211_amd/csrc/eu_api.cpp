@@ -94,7 +94,7 @@ struct Layout {
     std::vector<int64_t> pbase;
     // scratch offsets
     size_t o_grids, o_act, o_nact, o_code, o_gmask, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
-        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_lword, o_fword, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_partial, o_cfls, o_totals, o_goff, o_gcnt;
+        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_lword, o_fword, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_t0, o_partial, o_cfls, o_totals, o_goff, o_gcnt;
     size_t scratch = 0, state = 0;
 };
 
@@ -241,6 +241,7 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_smax = take(8 * lay.ngrid);
     lay.o_dt = take(8 * lay.ngrid);
     lay.o_t = take(8 * lay.ngrid);
+    lay.o_t0 = take(8 * lay.ngrid);
     // per-tile partial totals
     lay.o_partial = take(8 * std::max<int64_t>(lay.nv * lay.max_tiles, 1));
     lay.o_cfls = take(8 * (int64_t)eu::cfl_slot(eu::CFL_STRIDE, 0));
@@ -551,15 +552,19 @@ void drop_graphs(eu_ctx *c)
 }
 
 // Launches of the first stage over the current state (one per level for
-// local time stepping): it reads Q and writes the stage array, which every
-// step recomputes, so repeating it leaves the state untouched.
+// local time stepping), in the configuration a step launches them (a 2D
+// hierarchy's global step also projects the finest tiles): it reads Q and
+// writes the stage array, which every step recomputes, so repeating it
+// leaves the state untouched.
 void stage1_pass(eu_ctx *c, int var)
 {
-    if (c->v.lts)
+    if (c->v.lts) {
         for (int l = 0; l < c->L; ++l)
             c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, 0, c->stream);
-    else
-        c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, var, 0, c->stream);
+    } else {
+        const bool fine = c->dim == 2 && c->mode == MODE_HIER && c->L >= 2;
+        c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, var, fine ? 1 : 0, c->stream);
+    }
 }
 
 int stage_ready(eu_ctx *c)
@@ -668,6 +673,7 @@ int finish_init(eu_ctx *c)
     c->cfl_state = CFL_ZERO;
     HIPCHK(c, hipMemsetAsync(c->v.meta, 0, sizeof(Meta), c->stream));
     HIPCHK(c, hipMemsetAsync(c->v.t, 0, 8 * c->ngrid, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->v.t0, 0, 8 * c->ngrid, c->stream));
     HIPCHK(c, hipMemsetAsync(c->v.dt, 0, 8 * c->ngrid, c->stream));
     HIPCHK(c, hipMemsetAsync(c->v.smax, 0, 8 * c->ngrid, c->stream));
     // the list build's words start with one epoch
@@ -705,7 +711,9 @@ int finish_init(eu_ctx *c)
     int r = check_launch(c);
     if (r) return r;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    drop_graphs(c);
+    // captured step graphs stay valid: they depend on the buffers and the
+    // schedule, not on the data, and a replay starts from CFL slots that
+    // eu_advance prepares for the current state
     c->initialized = true;
     return EU_OK;
 }
@@ -810,6 +818,12 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
         // launch for all of them would do
         const char *fb = std::getenv("EU_FLAG_BUILD");
         v.flags1 = fb && std::strcmp(fb, "levels") == 0 ? 1 : 0;
+        // EU_WAIT_TEST=stale: the list build waits for an epoch that is never
+        // published, with a short bound, so its waits give up (tests of the
+        // give-up path; every kernel still ends)
+        const char *wt = std::getenv("EU_WAIT_TEST");
+        v.wait_stale = wt && std::strcmp(wt, "stale") == 0 ? 1 : 0;
+        if (v.wait_stale) v.wait_spin = 64;
     }
     v.nbt = (int)lay.nbt;
     v.wcnt = at<int>(scratch_dev, lay.o_wcnt);
@@ -820,6 +834,9 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.smax = at<unsigned long long>(scratch_dev, lay.o_smax);
     v.dt = at<double>(scratch_dev, lay.o_dt);
     v.t = at<double>(scratch_dev, lay.o_t);
+    v.t0 = at<double>(scratch_dev, lay.o_t0);
+    v.t_rem = INFINITY;
+    v.wait_spin = 1 << 20;
     v.partial = at<double>(scratch_dev, lay.o_partial);
     v.cfls = at<unsigned long long>(scratch_dev, lay.o_cfls);
     v.totals = at<double>(scratch_dev, lay.o_totals);
@@ -904,11 +921,22 @@ int eu_mr_decompose(eu_ctx *c)
     return check_launch(c);
 }
 
-int eu_mr_flag(eu_ctx *c, int64_t *nflag_host)
+int eu_mr_flag(eu_ctx *c, double eps, int64_t *nflag_host)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
     if (c->mode != MODE_HIER) return set_err(c, EU_EINVAL, "a batch has no hierarchy");
+    if (std::isnan(eps)) return set_err(c, EU_EINVAL, "eps is NaN");
+    if (eps >= 0.0 && eps != c->v.eps) {
+        // a new threshold: the significance of the details of the last
+        // decomposition is taken again against it, and kept for later steps
+        c->v.eps = eps;
+        c->cfg.eps = eps;
+        drop_graphs(c);
+        int64_t n = 0;
+        for (int l = 0; l < c->L - 1; ++l) n += c->grids[l].ncell;
+        if (n > 0) launch_threshold(c->v, n, c->stream);
+    }
     if (c->L > 1) seq_flag_tile(c, true);
     int r = check_launch(c);
     if (r) return r;
@@ -934,13 +962,25 @@ int eu_project(eu_ctx *c, int mode)
     return check_launch(c);
 }
 
-int eu_cfl_dt(eu_ctx *c, double *dt_host)
+int eu_cfl_dt(eu_ctx *c, double cfl, double t_remaining, double *dt_dev, double *dt_host)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    if (std::isnan(cfl) || std::isnan(t_remaining)) return set_err(c, EU_EINVAL, "cfl or t_remaining is NaN");
+    // this call's CFL number and clip, by value in the kernel arguments
+    View v = c->v;
+    if (cfl > 0.0) v.cfl = cfl;
+    if (t_remaining >= 0.0) v.t_rem = t_remaining;
+    std::swap(v, c->v);
     seq_cfl(c);
+    std::swap(v, c->v);
     int r = check_launch(c);
     if (r) return r;
+    if (dt_dev) {
+        const int n = c->mode == MODE_HIER ? 1 : c->ngrid;
+        launch_copy_f64(dt_dev, c->v.dt, n, c->stream);
+        if ((r = check_launch(c))) return r;
+    }
     if (dt_host) {
         if ((r = sync_status(c))) return r;
         HIPCHK(c, hipMemcpy(dt_host, c->v.dt, 8, hipMemcpyDeviceToHost));
@@ -948,13 +988,17 @@ int eu_cfl_dt(eu_ctx *c, double *dt_host)
     return EU_OK;
 }
 
-int eu_fv_step(eu_ctx *c)
+int eu_fv_step(eu_ctx *c, const double *dt_dev, int level)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    if (level < -1 || level >= c->L) return set_err(c, EU_EINVAL, "bad level");
+    if (level >= 0 && !c->v.lts)
+        return set_err(c, EU_EINVAL, "a global time step advances every level together (level -1)");
     cfl_stale(c);
+    if (dt_dev) launch_set_dt(c->v, dt_dev, c->stream);
     if (c->v.lts) {
-        lts_advance(c, 0, 0);
+        lts_advance(c, level < 0 ? 0 : level, 0);
         seq_ghost(c, ARR_Q);
     } else {
         seq_fv_step(c, true);
@@ -1013,12 +1057,13 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
     return r;
 }
 
-int eu_conserved_totals(eu_ctx *c, double *totals_host)
+int eu_conserved_totals(eu_ctx *c, double *totals_dev, double *totals_host)
 {
     if (!c) return EU_EINVAL;
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
     c->ks->totals(c->v, c->max_tiles, c->stream);
     launch_totals_final(c->v, c->ngroups, c->stream);
+    if (totals_dev) launch_copy_f64(totals_dev, c->v.totals, c->nv * c->ngroups, c->stream);
     int r = check_launch(c);
     if (r) return r;
     if (totals_host) {

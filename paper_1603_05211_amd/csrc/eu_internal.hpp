@@ -108,6 +108,11 @@ struct View {
     Meta *meta;
     unsigned long long *smax;         // per grid: max wave-speed sum (FP64 bits)
     double *dt, *t;                   // per grid (batch) or entry 0 (hierarchy)
+    double *t0;                       // time at the start of the step the CFL reduction committed
+    double t_rem;                     // the CFL step is also clipped to this (INFINITY: no clip)
+    int wait_spin;                    // bound of the waits between workgroups (polls)
+    int wait_stale;                   // tests: the list build waits for an epoch no workgroup
+                                      // publishes, so its bounded waits give up
     double *partial;                  // per tile x nv partial totals
     unsigned long long *cfls;         // CFL slots (cfl_slot())
     double *totals;                   // per group x nv

@@ -70,5 +70,8 @@ void launch_build_lists(const View &, int64_t nblocks_total, hipStream_t);
 void launch_cfl_final(const View &, hipStream_t);
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t val, hipStream_t);
 void launch_totals_final(const View &, int ngroups, hipStream_t);
+void launch_set_dt(const View &, const double *dt_ext, hipStream_t);
+void launch_copy_f64(double *dst, const double *src, int n, hipStream_t);
+void launch_threshold(const View &, int64_t ncell, hipStream_t);
 
 }  // namespace eu

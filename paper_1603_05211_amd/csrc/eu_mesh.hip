@@ -39,7 +39,6 @@ struct FlagChain {
     int lists;      // the launch also builds the work lists (v.ncls workgroups)
     int64_t nbt;    // blocks of every level
 };
-constexpr int FLAG_MAXSPIN = 1 << 20;
 
 // The list build of workgroup w of W (defined with the list kernels below);
 // WORDS: the new patch masks come from the flagging words of this launch.
@@ -256,7 +255,7 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
                 const unsigned long long *wp = v.fword + slot2 + pm;
                 unsigned long long x = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 for (int spin = 0; (x & 0xffffull) != ep; ++spin) {
-                    if (spin == FLAG_MAXSPIN) {
+                    if (spin >= v.wait_spin) {
                         late = 1;
                         break;
                     }
@@ -536,7 +535,7 @@ __device__ __forceinline__ bool classify_block(const View &v, int64_t gb, int do
 #pragma unroll
             for (int i = 0; i < NC; ++i) ok = ok && (!hasf || (xc[i] & 0xffffull) == ep);
             if (ok) break;
-            if (spin == FLAG_MAXSPIN) {
+            if (spin >= v.wait_spin) {
                 late = 1;
                 break;
             }
@@ -754,7 +753,6 @@ __global__ void __launch_bounds__(256) k_compact(View v, int64_t nbt)
 // one epoch (cleared with the hierarchy) and every build that is not done
 // raises all of them, so they keep one epoch.
 constexpr int LISTS_MAXCHUNK = 1024;
-constexpr int LISTS_MAXSPIN = 1 << 20;
 
 template <int D, bool WORDS, int R>
 __device__ void lists_body(const View &v, int64_t nbt, int w, int W)
@@ -809,11 +807,13 @@ __device__ void lists_body(const View &v, int64_t nbt, int w, int W)
     // the counts of the ranges before this one: thread i waits for range i
     // (both of its words read in one trip)
     int acc[NL] = {0, 0, 0, 0, 0};
+    // the epoch waited for (a test setting makes it one no workgroup publishes)
+    const unsigned long long ew = v.wait_stale ? ((e + 1) & 0xffffull) : e;
     for (int i = tid; i < w; i += blockDim.x) {
         unsigned long long x0 = __hip_atomic_load(word + 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long x1 = __hip_atomic_load(word + 2 * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int spin = 0; (x0 & 0xffffull) != e || (x1 & 0xffffull) != e; ++spin) {
-            if (spin == LISTS_MAXSPIN) {
+        for (int spin = 0; (x0 & 0xffffull) != ew || (x1 & 0xffffull) != ew; ++spin) {
+            if (spin >= v.wait_spin) {
                 late = 1;
                 break;
             }
@@ -863,8 +863,10 @@ __global__ void __launch_bounds__(256) k_cfl_final_batch(View v)
         double dt = b ? (v.cfl * v.grids[g].dx) / s : 0.0;
         const double t = v.t[g];
         if (dt > v.t_end - t) dt = v.t_end - t;
+        if (dt > v.t_rem) dt = v.t_rem;
         if (!(dt > 0.0)) dt = 0.0;
         v.dt[g] = dt;
+        v.t0[g] = t;
         v.t[g] = t + dt;
     }
     if (threadIdx.x == 0) {
@@ -913,8 +915,9 @@ __global__ void __launch_bounds__(64) k_cfl_final(View v)
         }
     }
     const long long upd = (long long)cnt;
-    const int done = t < v.t_end ? 0 : 1;
+    const int done = t < v.t_end && v.t_rem > 0.0 ? 0 : 1;
     if (dt > v.t_end - t) dt = v.t_end - t;
+    if (dt > v.t_rem) dt = v.t_rem;
     if (v.lts) {
         double dl = dt;
 #pragma unroll
@@ -926,11 +929,54 @@ __global__ void __launch_bounds__(64) k_cfl_final(View v)
         v.dt[0] = dt;
     }
     v.meta->done = done;
+    v.t0[0] = t;
     if (!done) {
         v.t[0] = t + dt;
         v.meta->steps += 1;
         v.meta->leaf_updates += upd;
     }
+}
+
+// The step committed by the last CFL reduction takes the time step dt_ext
+// instead (per instance for a batch; a hierarchy's level-0 step, halved per
+// level with local time stepping): t = t0 + dt.  One workgroup.
+__global__ void __launch_bounds__(256) k_set_dt(View v, const double *dt_ext)
+{
+#pragma clang fp contract(off)
+    if (v.mode != MODE_HIER) {
+        for (int g = threadIdx.x; g < v.ngrid; g += blockDim.x) {
+            const double dt = dt_ext[g] > 0.0 ? dt_ext[g] : 0.0;
+            v.dt[g] = dt;
+            v.t[g] = v.t0[g] + dt;
+        }
+        return;
+    }
+    if (threadIdx.x != 0) return;
+    const double dt = dt_ext[0] > 0.0 ? dt_ext[0] : 0.0;
+    if (v.lts) {
+        double dl = dt;
+        for (int l = 0; l < v.L && l < MAXLEV; ++l) {
+            v.dt[l] = dl;
+            dl = dl * 0.5;
+        }
+    } else {
+        v.dt[0] = dt;
+    }
+    if (!v.meta->done) v.t[0] = v.t0[0] + dt;
+}
+
+__global__ void k_copy_f64(double *dst, const double *src, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// Significance of every detail against the threshold (levels 0 .. L-2, the
+// per-cell arrays of the MR analysis): D >= eps.
+__global__ void k_threshold(View v, int64_t ncell)
+{
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ncell; j += (int64_t)gridDim.x * blockDim.x)
+        v.sig[j] = v.D[j] >= v.eps ? 1 : 0;
 }
 
 __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t val)
@@ -1073,6 +1119,18 @@ void launch_fill_u8(uint8_t *p, int64_t n, uint8_t val, hipStream_t s)
 void launch_totals_final(const View &v, int ngroups, hipStream_t s)
 {
     k_totals_final<<<grid_for((int64_t)ngroups * v.nv, 64, 4096), 64, 0, s>>>(v, ngroups);
+}
+
+void launch_set_dt(const View &v, const double *dt_ext, hipStream_t s) { k_set_dt<<<1, 256, 0, s>>>(v, dt_ext); }
+
+void launch_copy_f64(double *dst, const double *src, int n, hipStream_t s)
+{
+    k_copy_f64<<<grid_for(n, 64, 4096), 64, 0, s>>>(dst, src, n);
+}
+
+void launch_threshold(const View &v, int64_t ncell, hipStream_t s)
+{
+    k_threshold<<<grid_for(ncell, 256, 4096), 256, 0, s>>>(v, ncell);
 }
 
 }  // namespace eu

@@ -102,3 +102,28 @@ def test_null_context_calls_fail_cleanly():
     assert lib.eu_step(None, 1) == _abi.EU_EINVAL
     assert lib.eu_destroy(None) == _abi.EU_EINVAL
     assert lib.eu_last_error(None) == b"null context"
+
+
+def test_method_calls_take_their_arguments():
+    """The method calls carry the arguments of their definitions: the CFL
+    number and remaining-time clip plus a device output on eu_cfl_dt, an
+    external device dt and a level on eu_fv_step, a device output on
+    eu_conserved_totals, the threshold on eu_mr_flag (argument lists of the
+    header as the binding declares them; each call on a null context fails
+    cleanly before touching a device)."""
+    lib = _abi.load()
+    sig = _abi.SIGNATURES
+    assert sig["eu_cfl_dt"][1][1:3] == [C.c_double, C.c_double] and len(sig["eu_cfl_dt"][1]) == 5
+    assert len(sig["eu_fv_step"][1]) == 3 and sig["eu_fv_step"][1][2] == C.c_int
+    assert len(sig["eu_conserved_totals"][1]) == 3
+    assert sig["eu_mr_flag"][1][1] == C.c_double
+    assert lib.eu_cfl_dt(None, 0.4, -1.0, None, None) == _abi.EU_EINVAL
+    assert lib.eu_fv_step(None, None, -1) == _abi.EU_EINVAL
+    assert lib.eu_conserved_totals(None, None, None) == _abi.EU_EINVAL
+    assert lib.eu_mr_flag(None, 1e-3, None) == _abi.EU_EINVAL
+    text = open(_abi.HEADER).read()
+    for decl in ["int eu_cfl_dt(eu_ctx *ctx, double cfl, double t_remaining, double *dt_dev, double *dt_host);",
+                 "int eu_fv_step(eu_ctx *ctx, const double *dt_dev, int level);",
+                 "int eu_conserved_totals(eu_ctx *ctx, double *totals_dev, double *totals_host);",
+                 "int eu_mr_flag(eu_ctx *ctx, double eps, int64_t *nflag_host);"]:
+        assert decl in text, decl
