@@ -145,7 +145,7 @@ class Run:
             s.set_variant(best)
             self.variant = best
             self.tuning = {"samples": samples, "every_steps": tune_every,
-                           "ms_summed_per_schedule": [round(x, 5) for x in tot]}
+                           "ms_summed_per_schedule": [round(x, 5) if math.isfinite(x) else None for x in tot]}
         return done
 
     def timed(self, k):
@@ -381,7 +381,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-extra", action="store_true", help="skip the context configurations")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error report")
-    ap.add_argument("--schedule", type=int, default=-1, choices=list(range(-1, 6)),
+    ap.add_argument("--schedule", type=int, default=-1, choices=list(range(-1, 10)),
                     help="force a stage-kernel schedule instead of autotuning over the run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration)")

@@ -57,7 +57,7 @@ enum { EU_BC_TRANSMISSIVE = 0, EU_BC_PERIODIC = 1 };
 enum { EU_DT_GLOBAL = 0, EU_DT_LTS = 1 };        /* time stepping           */
 enum { EU_RESTRICT = 0, EU_PROLONG = 1, EU_GHOST = 2 }; /* eu_project modes */
 enum { EU_IC_QUADRANT = 0, EU_IC_ELLIPSOID = 1, EU_IC_RIEMANN1D = 2, EU_IC_UNIFORM = 3 };
-enum { EU_STAGE_SCHEDULES = 6 };                 /* see eu_autotune           */
+enum { EU_STAGE_SCHEDULES = 10, EU_STRIP_SCHEDULE0 = 6 }; /* see eu_autotune  */
 
 /* Problem size and method parameters (Sec. 2; Sec. 4 for the values used
  * there).  All fields are read by eu_query_sizes / eu_create. */
@@ -259,27 +259,40 @@ int eu_time(eu_ctx *ctx, double *t_host, double *dt_host);
 int eu_profile(eu_ctx *ctx, int enable);
 int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
 
-/* Schedule of the finite-volume stage kernel (threads per tile; faces axis by
- * axis, axis by axis from per-cell face states, or all axes in one pass).  In FP64 every schedule gives bit-identical results;
- * in FP32 they agree to rounding (the compiler contracts each differently).
- * eu_autotune times each schedule (reps launches of the first stage on the
- * current state replayed from one HIP graph, HIP events on the context's
- * stream; the state is left unchanged) and keeps the fastest: *variant_host receives it, ms_host
- * (nullable, EU_STAGE_SCHEDULES entries) the mean time of each.
- * eu_set_variant forces one (0 .. EU_STAGE_SCHEDULES-1).  Both drop captured
- * graphs. */
+/* Schedule of the finite-volume update (Sec. 2: both stages of the
+ * midpoint rule on every leaf).  Schedules 0 .. 5 apply everywhere: the
+ * tile kernel (one 8^d block with its halo in LDS per workgroup) with 64,
+ * 128 or 192 threads per tile in 2D (256 or 512 in 3D), faces axis by axis,
+ * axis by axis from per-cell face states, or all axes in one pass.
+ * Schedules EU_STRIP_SCHEDULE0 .. EU_STAGE_SCHEDULES-1 apply to 2D grids of
+ * one level (a uniform grid or a batch): the strip kernel (one wave per
+ * strip of 64 columns marching up the rows; slopes once per cell, x
+ * neighbours by lane exchange): 6 and 7 one stage per launch, 8 and 9 both
+ * stages fused in one launch that keeps the stage state in registers
+ * (outflow boundaries only; the state then alternates between the two
+ * state arrays, which the library tracks); 6 and 8 with strips of 32 rows,
+ * 7 and 9 of 128.  In FP64 every schedule gives bit-identical results; in
+ * FP32 they agree to rounding (the compiler contracts each differently).
+ * eu_autotune times each schedule that applies (reps passes of one step's
+ * finite-volume work on the current state -- both stages, the second in
+ * its form reading the current state, or the fused launch; with local time
+ * stepping the first stage of every level -- replayed from one HIP graph,
+ * HIP events on the context's stream; the state is left unchanged) and
+ * keeps the fastest: *variant_host receives it, ms_host (nullable,
+ * EU_STAGE_SCHEDULES entries) the mean time of a pass of each (INFINITY
+ * where a schedule does not apply).  eu_set_variant forces one
+ * (EU_EINVAL where it does not apply).  Both drop captured graphs. */
 int eu_autotune(eu_ctx *ctx, int reps, int *variant_host, float *ms_host);
 
-/* Duration of the finite-volume stage kernel on the current state, with the
- * current schedule: reps passes of the first stage (Sec. 2.2, the midpoint
- * rule's predictor) captured in one HIP graph, replayed once untimed and
- * once between two HIP events on the context's stream (eager launches on the
- * default stream); the state is left unchanged.  A pass is one
- * launch (global time step, batch) or one launch per level (local time
- * stepping).  *ms_host: mean milliseconds per pass; *cells_host: cells one
- * pass advances (leaves; patch cells of every level with local time stepping;
- * every cell of a uniform grid or batch); *launches_host: launches per pass.
- * Outputs are nullable.  EU_ESTATE before initialisation or after t_end. */
+/* Duration of the finite-volume update on the current state with the
+ * current schedule: reps passes as eu_autotune times them, captured in one
+ * HIP graph, replayed once untimed and once between two HIP events on the
+ * context's stream (eager launches on the default stream); the state is
+ * left unchanged.  *ms_host: mean milliseconds per pass; *cells_host:
+ * cell-stages one pass computes (twice the leaves, or every cell of a
+ * uniform grid or batch, for a global step; the patch cells of every level
+ * with local time stepping); *launches_host: launches per pass.  Outputs
+ * are nullable.  EU_ESTATE before initialisation or after t_end. */
 int eu_stage_time(eu_ctx *ctx, int reps, float *ms_host, int64_t *cells_host, int *launches_host);
 int eu_set_variant(eu_ctx *ctx, int variant);
 

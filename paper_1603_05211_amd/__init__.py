@@ -16,11 +16,12 @@ import numpy as np
 
 from . import _abi
 from ._abi import (EU_BC_PERIODIC, EU_BC_TRANSMISSIVE, EU_DT_GLOBAL, EU_DT_LTS, EU_FP32, EU_FP64,
-                   EU_GHOST, EU_STAGE_SCHEDULES, EU_IC_ELLIPSOID, EU_IC_QUADRANT, EU_IC_RIEMANN1D, EU_IC_UNIFORM,
+                   EU_GHOST, EU_STAGE_SCHEDULES, EU_STRIP_SCHEDULE0, EU_IC_ELLIPSOID, EU_IC_QUADRANT, EU_IC_RIEMANN1D, EU_IC_UNIFORM,
                    EU_PROLONG, EU_RESTRICT)
 
 __all__ = ["Solver", "EuError", "EU_FP32", "EU_FP64", "EU_BC_PERIODIC", "EU_BC_TRANSMISSIVE",
-           "EU_RESTRICT", "EU_PROLONG", "EU_GHOST", "EU_DT_GLOBAL", "EU_DT_LTS", "EU_STAGE_SCHEDULES"]
+           "EU_RESTRICT", "EU_PROLONG", "EU_GHOST", "EU_DT_GLOBAL", "EU_DT_LTS", "EU_STAGE_SCHEDULES",
+           "EU_STRIP_SCHEDULE0"]
 
 
 class EuError(RuntimeError):
@@ -285,17 +286,18 @@ class Solver:
         return ms.value, n.value
 
     def autotune(self, reps: int = 20):
-        """Time every stage-kernel schedule on the current state and keep the
-        fastest; returns (variant, per-variant ms)."""
+        """Time every finite-volume schedule that applies on the current state
+        and keep the fastest; returns (variant, per-variant ms per pass, inf
+        where a schedule does not apply)."""
         var = C.c_int(0)
         ms = (C.c_float * EU_STAGE_SCHEDULES)()
         self._check(self._lib.eu_autotune(self._ctx, reps, C.byref(var), ms), "eu_autotune")
         return var.value, list(ms)
 
     def stage_time(self, reps: int = 10):
-        """Mean duration of one first-stage pass on the current state (reps
-        passes replayed from one HIP graph between two HIP events); returns
-        (ms, cells advanced per pass, launches per pass)."""
+        """Mean duration of one pass of the finite-volume update on the
+        current state (reps passes replayed from one HIP graph between two HIP
+        events); returns (ms, cell-stages per pass, launches per pass)."""
         ms, cells, nl = C.c_float(0.0), C.c_int64(0), C.c_int(0)
         self._check(self._lib.eu_stage_time(self._ctx, reps, C.byref(ms), C.byref(cells), C.byref(nl)),
                     "eu_stage_time")

@@ -14,7 +14,8 @@ EU_BC_TRANSMISSIVE, EU_BC_PERIODIC = 0, 1
 EU_DT_GLOBAL, EU_DT_LTS = 0, 1
 EU_RESTRICT, EU_PROLONG, EU_GHOST = 0, 1, 2
 EU_IC_QUADRANT, EU_IC_ELLIPSOID, EU_IC_RIEMANN1D, EU_IC_UNIFORM = 0, 1, 2, 3
-EU_STAGE_SCHEDULES = 6
+EU_STAGE_SCHEDULES = 10
+EU_STRIP_SCHEDULE0 = 6
 
 STATUS_NAMES = {0: "EU_OK", 1: "EU_EINVAL", 2: "EU_ENOMEM", 3: "EU_EHIP", 4: "EU_ENONPHYS",
                 5: "EU_ESTATE"}

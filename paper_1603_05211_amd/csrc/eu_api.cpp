@@ -39,8 +39,15 @@ struct eu_ctx {
     int variant = 0;            // stage-kernel schedule (eu_autotune)
     int cfl_state = 0;          // CFL slots: CFL_ZERO, CFL_READY (of the current state) or CFL_STALE
     std::string err;
-    // graphs: [0] step with regrid, [1] step without
+    // graphs of one step, by qswap (the fused strip schedules alternate the
+    // state between the two arrays)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int qswap = 0;              // the current state is in the second array
+    // strip lists (2D, one level)
+    Strip *strips = nullptr;
+    int64_t max_strips = 0;
+    int nstrips = 0;
+    int strip_var = -1;         // schedule whose list is on the device
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -94,7 +101,8 @@ struct Layout {
     std::vector<int64_t> pbase;
     // scratch offsets
     size_t o_grids, o_act, o_nact, o_code, o_gmask, o_sig, o_flag, o_D, o_leaf, o_cov, o_ghost, o_fresh, o_pslot,
-        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_lword, o_fword, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_t0, o_partial, o_cfls, o_totals, o_goff, o_gcnt;
+        o_pcnt, o_fcnt, o_cpart, o_wcnt, o_lword, o_fword, o_pbase, o_actv, o_reg, o_meta, o_smax, o_dt, o_t, o_t0, o_partial, o_cfls, o_totals, o_goff, o_gcnt, o_strips;
+    int64_t max_strips = 0;
     size_t scratch = 0, state = 0;
 };
 
@@ -248,6 +256,13 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_totals = take(8 * lay.nv * lay.ngroups);
     lay.o_goff = take(sizeof(int) * lay.ngroups);
     lay.o_gcnt = take(sizeof(int) * lay.ngroups);
+    // strip lists of the strip schedules (2D, one level): at most the count
+    // of the narrowest strips with the fewest rows
+    if (D == 2 && lay.L == 1) {
+        const int w = eu::strip_width(true), ty = eu::strip_rows(eu::FV_STRIP0);
+        for (const Grid &G : lay.grids) lay.max_strips += (int64_t)((G.n + w - 1) / w) * ((G.n + ty - 1) / ty);
+    }
+    lay.o_strips = take(sizeof(eu::Strip) * lay.max_strips);
     lay.scratch = o;
 }
 
@@ -409,6 +424,26 @@ void prof_end(eu_ctx *c, hipEvent_t e1)
 void seq_details(eu_ctx *c);
 void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
 {
+    if (strip_variant(c->variant)) {
+        // one 2D level (uniform grid or batch): no projection, ghost fill or
+        // details; the fused form leaves the new state in the other array
+        hipEvent_t e;
+        if (strip_fused(c->variant)) {
+            prof_begin(c, &e);
+            c->ks->fv_strip(c->v, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
+            prof_end(c, e);
+            std::swap(c->v.Q, c->v.Qs);
+            c->qswap ^= 1;
+        } else {
+            prof_begin(c, &e);
+            c->ks->fv_strip(c->v, 0, 1, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
+            prof_end(c, e);
+            prof_begin(c, &e);
+            c->ks->fv_strip(c->v, 0, 0, c->strips, c->nstrips, c->v.Qs, c->v.Q, c->v.Q, 1.0, c->stream);
+            prof_end(c, e);
+        }
+        return;
+    }
     // 2D hierarchy: the stage kernel also projects its finest tiles onto
     // level L-2
     const bool fine = c->dim == 2 && c->mode == MODE_HIER && c->L >= 2;
@@ -551,19 +586,65 @@ void drop_graphs(eu_ctx *c)
         if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
-// Launches of the first stage over the current state (one per level for
-// local time stepping), in the configuration a step launches them (a 2D
-// hierarchy's global step also projects the finest tiles): it reads Q and
-// writes the stage array, which every step recomputes, so repeating it
-// leaves the state untouched.
-void stage1_pass(eu_ctx *c, int var)
+// Whether schedule var applies to this context: the strip schedules need a
+// 2D grid of one level (a uniform grid or a batch), the fused ones outflow
+// boundaries.
+bool variant_ok(const eu_ctx *c, int var)
+{
+    if (var < 0 || var >= FV_VARIANTS) return false;
+    if (!strip_variant(var)) return true;
+    if (c->dim != 2 || c->L != 1) return false;
+    return !strip_fused(var) || c->cfg.bc == EU_BC_TRANSMISSIVE;
+}
+
+// The strip list of schedule var on the device (a synchronous upload; not
+// during capture).  Strips of one grid in column-major order, so list
+// neighbours share their halo rows.
+int strips_for(eu_ctx *c, int var)
+{
+    if (!strip_variant(var) || c->strip_var == var) return EU_OK;
+    const bool fused = strip_fused(var);
+    const int w = strip_width(fused), h = strip_halo(fused), ty = strip_rows(var);
+    std::vector<Strip> st;
+    for (int g = 0; g < c->ngrid; ++g) {
+        const int n = c->grids[g].n;
+        for (int x0 = 0; x0 < n; x0 += w)
+            for (int y0 = 0; y0 < n; y0 += ty) st.push_back(Strip{g, x0 - h, y0, std::min(ty, n - y0)});
+    }
+    if ((int64_t)st.size() > c->max_strips) return set_err(c, EU_EHIP, "strip list exceeds its capacity");
+    int r = upload(c, c->strips, st.data(), sizeof(Strip) * st.size());
+    if (r) return r;
+    c->nstrips = (int)st.size();
+    c->strip_var = var;
+    return EU_OK;
+}
+
+// The finite-volume work of one step over the current state, without
+// changing it (the state Q is read; the stage array receives the results,
+// and every step recomputes it): a global step's two stages (the second in
+// its form reading Q: the same loads, arithmetic and stores), or both fused;
+// with local time stepping the first stage of every level.  The strip list
+// of var must be on the device.  Sets the cell-stages and launches of a pass.
+void fv_pass(eu_ctx *c, int var, int *launches)
 {
     if (c->v.lts) {
         for (int l = 0; l < c->L; ++l)
             c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, 0, c->stream);
+        *launches = c->L;
+    } else if (strip_variant(var)) {
+        if (strip_fused(var)) {
+            c->ks->fv_strip(c->v, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
+            *launches = 1;
+        } else {
+            c->ks->fv_strip(c->v, 0, 1, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
+            c->ks->fv_strip(c->v, 0, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
+            *launches = 2;
+        }
     } else {
         const bool fine = c->dim == 2 && c->mode == MODE_HIER && c->L >= 2;
         c->ks->fv_stage(c->v, 1, -1, 0, 0, c->max_tiles, var, fine ? 1 : 0, c->stream);
+        c->ks->fv_stage(c->v, 3, -1, 0, 0, c->max_tiles, var, fine ? 1 : 0, c->stream);
+        *launches = 2;
     }
 }
 
@@ -577,10 +658,12 @@ int stage_ready(eu_ctx *c)
     return EU_OK;
 }
 
-// Mean time of one first-stage pass of schedule var: one untimed pass, then
+// Mean time of one pass (fv_pass) of schedule var: one untimed pass, then
 // reps passes back to back between two events on the context's stream.
-int time_stage1(eu_ctx *c, int var, int reps, float *ms_out)
+int time_pass(eu_ctx *c, int var, int reps, float *ms_out, int *launches)
 {
+    int r0 = strips_for(c, var);
+    if (r0) return r0;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -594,7 +677,7 @@ int time_stage1(eu_ctx *c, int var, int reps, float *ms_out)
         hipGraph_t g;
         hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            for (int r = 0; r < reps; ++r) stage1_pass(c, var);
+            for (int r = 0; r < reps; ++r) fv_pass(c, var, launches);
             e = hipStreamEndCapture(c->stream, &g);
             if (e == hipSuccess) {
                 e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -609,12 +692,12 @@ int time_stage1(eu_ctx *c, int var, int reps, float *ms_out)
         }
         (void)hipGraphLaunch(ge, c->stream);   // untimed replay
     } else {
-        stage1_pass(c, var);
+        fv_pass(c, var, launches);
     }
     (void)hipEventRecord(e0, c->stream);
     if (ge) (void)hipGraphLaunch(ge, c->stream);
     else
-        for (int r = 0; r < reps; ++r) stage1_pass(c, var);
+        for (int r = 0; r < reps; ++r) fv_pass(c, var, launches);
     (void)hipEventRecord(e1, c->stream);
     hipError_t err = hipEventSynchronize(e1);
     if (ge) (void)hipGraphExecDestroy(ge);
@@ -843,6 +926,8 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.grp_off = at<int>(scratch_dev, lay.o_goff);
     v.grp_cnt = at<int>(scratch_dev, lay.o_gcnt);
     v.max_tiles = (int)lay.max_tiles;
+    c->strips = at<Strip>(scratch_dev, lay.o_strips);
+    c->max_strips = lay.max_strips;
 
     int r;
     if ((r = upload(c, (void *)v.grids, lay.grids.data(), sizeof(Grid) * lay.ngrid)) ||
@@ -1028,20 +1113,42 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
         // step computes them itself, and the capture must record that
         if (step_leaves_slots(c)) cfl_ready(c);
         else if (c->cfl_state != CFL_ZERO) cfl_zero(c);
-        if (!c->gexec[0]) {
+        // one graph per array holding the state (the fused strip schedules
+        // move it to the other array every step); recording a step changes
+        // only host bookkeeping, which is restored after each capture (the
+        // CFL slots are left by a step as the lines above prepare them)
+        const bool alt = strip_variant(c->variant) && strip_fused(c->variant);
+        for (int p = 0; p < (alt ? 2 : 1); ++p) {
+            const int q = c->qswap ^ p;
+            if (c->gexec[q]) continue;
+            const View saved = c->v;
+            const int sq = c->qswap, scfl = c->cfl_state;
+            if (p) {
+                std::swap(c->v.Q, c->v.Qs);
+                c->qswap ^= 1;
+            }
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             seq_step(c, true);
             hipError_t e = hipStreamEndCapture(c->stream, &g);
+            c->v = saved;
+            c->qswap = sq;
+            c->cfl_state = scfl;
             if (e != hipSuccess) return set_err(c, EU_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(&c->gexec[0], g, nullptr, nullptr, 0);
+            e = hipGraphInstantiate(&c->gexec[q], g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) {
-                c->gexec[0] = nullptr;
+                c->gexec[q] = nullptr;
                 return set_err(c, EU_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
             }
         }
-        for (int i = 0; i < nsteps; ++i) HIPCHK(c, hipGraphLaunch(c->gexec[0], c->stream));
+        for (int i = 0; i < nsteps; ++i) {
+            HIPCHK(c, hipGraphLaunch(c->gexec[c->qswap], c->stream));
+            if (alt) {
+                std::swap(c->v.Q, c->v.Qs);
+                c->qswap ^= 1;
+            }
+        }
     } else {
         for (int i = 0; i < nsteps; ++i) {
             seq_step(c, true);
@@ -1229,8 +1336,11 @@ int eu_kernel_time(eu_ctx *c, double *ms, int64_t *launches)
 int eu_set_variant(eu_ctx *c, int variant)
 {
     if (!c) return EU_EINVAL;
-    if (variant < 0 || variant >= FV_VARIANTS) return set_err(c, EU_EINVAL, "bad variant");
+    if (!variant_ok(c, variant))
+        return set_err(c, EU_EINVAL, "schedule %d does not apply to this configuration", variant);
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    int r = strips_for(c, variant);
+    if (r) return r;
     c->variant = variant;
     drop_graphs(c);
     return EU_OK;
@@ -1241,15 +1351,19 @@ int eu_autotune(eu_ctx *c, int reps, int *variant_host, float *ms_host)
     if (!c || reps < 1) return EU_EINVAL;
     int r = stage_ready(c);
     if (r) return r;
-    int best = 0;
+    int best = -1;
     float best_ms = 0.f;
     for (int var = 0; var < FV_VARIANTS; ++var) {
-        float ms = 0.f;
-        r = time_stage1(c, var, reps, &ms);
-        if (r) return r;
+        float ms = INFINITY;
+        if (variant_ok(c, var)) {
+            int launches = 0;
+            r = time_pass(c, var, reps, &ms, &launches);
+            if (r) return r;
+            if (best < 0 || ms < best_ms) { best = var; best_ms = ms; }
+        }
         if (ms_host) ms_host[var] = ms;
-        if (var == 0 || ms < best_ms) { best = var; best_ms = ms; }
     }
+    if ((r = strips_for(c, best))) return r;
     c->variant = best;
     drop_graphs(c);
     if (variant_host) *variant_host = best;
@@ -1262,7 +1376,8 @@ int eu_stage_time(eu_ctx *c, int reps, float *ms_host, int64_t *cells_host, int 
     int r = stage_ready(c);
     if (r) return r;
     float ms = 0.f;
-    r = time_stage1(c, c->variant, reps, &ms);
+    int launches = 0;
+    r = time_pass(c, c->variant, reps, &ms, &launches);
     if (r) return r;
     int64_t cells = 0;
     if (c->mode != MODE_HIER) {
@@ -1273,9 +1388,11 @@ int eu_stage_time(eu_ctx *c, int reps, float *ms_host, int64_t *cells_host, int 
         if (r) return r;
         for (int l = 0; l < c->L; ++l) cells += c->v.lts ? ac[l] : lc[l];
     }
+    // cell-stages of a pass: both stages of every leaf, or the first stage
+    // of every patch cell with local time stepping
     if (ms_host) *ms_host = ms;
-    if (cells_host) *cells_host = cells;
-    if (launches_host) *launches_host = c->v.lts ? c->L : 1;
+    if (cells_host) *cells_host = c->v.lts ? cells : 2 * cells;
+    if (launches_host) *launches_host = launches;
     return EU_OK;
 }
 

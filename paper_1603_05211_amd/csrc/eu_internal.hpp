@@ -50,6 +50,12 @@ struct Tile {
     int block;       // block index within the grid, x fastest
 };
 
+// Work item of the strip kernels (uniform 2D grids and batches): rows y0 ..
+// y0+ny-1 of the 64 columns xb .. xb+63 of grid `grid`, one wave.
+struct Strip {
+    int grid, xb, y0, ny;
+};
+
 // Device-resident counters written by the mesh kernels.
 struct Meta {
     int nleaf;                 // tiles in the leaf list (blocks holding leaves)

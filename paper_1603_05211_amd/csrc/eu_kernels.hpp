@@ -1723,3 +1723,5 @@ __global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q
 }
 
 }  // namespace eu
+
+#include "eu_strip.hpp"

@@ -22,7 +22,16 @@ struct InitArgs {
 // Which state array a launcher works on.
 enum { ARR_Q = 0, ARR_QS = 1, ARR_QO = 2 };
 
-constexpr int FV_VARIANTS = 6;   // schedules of the stage kernel (autotuned)
+constexpr int FV_VARIANTS = 10;  // schedules of the stage kernel (autotuned)
+// Schedules 6-9 (2D grids of one level: a uniform grid or a batch) run the
+// strip kernels: 6, 7 one stage per launch, 8, 9 both stages in one launch
+// (outflow boundaries only); 6 and 8 strips of 32 rows, 7 and 9 of 128.
+constexpr int FV_STRIP0 = 6;
+inline bool strip_variant(int var) { return var >= FV_STRIP0; }
+inline bool strip_fused(int var) { return var >= FV_STRIP0 + 2; }
+inline int strip_rows(int var) { return (var - FV_STRIP0) % 2 ? 128 : 32; }
+inline int strip_width(bool fused) { return fused ? 56 : 60; }   // columns written per strip
+inline int strip_halo(bool fused) { return fused ? 4 : 2; }
 
 struct KSet {
     size_t elem;  // bytes per state value
@@ -39,6 +48,10 @@ struct KSet {
     // projection of their cells onto level L-2
     void (*fv_stage)(const View &, int stage, int lvl, int sub, int record, int maxtiles, int variant,
                      int fineproj, hipStream_t);
+    // strip kernels: one stage (fused = 0; own_base: the base state is the
+    // source) or both (fused = 1) over count strips
+    void (*fv_strip)(const View &, int fused, int own_base, const Strip *list, int count, const void *src,
+                     const void *base, void *out, double fac, hipStream_t);
     void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*cfl)(const View &, int maxtiles, hipStream_t);           // batch: maxima and dt

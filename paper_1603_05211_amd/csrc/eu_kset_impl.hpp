@@ -93,8 +93,10 @@ template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, 
     // take them all at once, and fewer idle workgroups are dispatched (a
     // batch or a 3D grid needs the larger grid to fill the chip)
     const int nblk = xcd_grid(maxt, v.dim == 2 && v.mode == MODE_HIER ? 2048 : 16384);
-    const T *src = (const T *)(stage == 1 ? v.Q : v.Qs);
-    T *out = (T *)(stage == 1 ? v.Qs : v.Q);
+    // stage 3: the second stage's form reading Q and writing the stage array
+    // (timing passes that leave the state unchanged)
+    const T *src = (const T *)(stage == 2 ? v.Qs : v.Q);
+    T *out = (T *)(stage == 2 ? v.Q : v.Qs);
     const double fac = stage == 1 ? 0.5 : 1.0;
     if (v.dim == 2) {
         switch (variant) {
@@ -115,6 +117,17 @@ template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, 
         default: fv_launch<T, 3, 256, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
         }
     }
+}
+
+template <typename T> void fv_strip(const View &v, int fused, int own_base, const Strip *list, int count,
+                                    const void *src, const void *base, void *out, double fac, hipStream_t s)
+{
+    const int nblk = xcd_grid((count + 3) / 4, 16384);
+    if (fused)
+        k_fv_strip<T, 1><<<nblk, 256, 0, s>>>(v, list, count, (const T *)src, (const T *)base, (T *)out, fac, 0);
+    else
+        k_fv_strip<T, 0><<<nblk, 256, 0, s>>>(v, list, count, (const T *)src, (const T *)base, (T *)out, fac,
+                                              own_base);
 }
 
 template <typename T> void copy_level(const View &v, int lvl, int maxb, hipStream_t s)
@@ -181,6 +194,7 @@ template <typename T> KSet make()
     k.composite = composite<T>;
     k.predict = predict<T>;
     k.fv_stage = fv_stage<T>;
+    k.fv_strip = fv_strip<T>;
     k.copy_level = copy_level<T>;
     k.reflux = reflux<T>;
     k.cfl = cfl<T>;

@@ -4,7 +4,7 @@ untouched."""
 import numpy as np
 import pytest
 
-from paper_1603_05211_amd import EU_DT_LTS, EU_FP32, EU_FP64, EU_STAGE_SCHEDULES, Solver, inputs
+from paper_1603_05211_amd import EU_DT_LTS, EU_FP32, EU_FP64, EU_STAGE_SCHEDULES, EU_STRIP_SCHEDULE0, Solver, inputs
 
 from gpu_helpers import init_pair, make_pair, say
 
@@ -22,7 +22,7 @@ def _run(dim, lts, variant, precision=EU_FP64, steps=4):
 @pytest.mark.parametrize("dim,lts", [(2, False), (3, False), (2, True), (3, True)])
 def test_schedules_bit_identical(dim, lts):
     ref_q, ref_a = _run(dim, lts, 0)
-    for var in range(1, EU_STAGE_SCHEDULES):
+    for var in range(1, EU_STRIP_SCHEDULE0):   # the tile schedules (the strip ones need one level)
         q, a = _run(dim, lts, var)
         for l in range(3):
             assert np.array_equal(a[l], ref_a[l]), (var, l)
@@ -34,7 +34,7 @@ def test_fp32_schedules_agree():
     """FP32 kernels may contract multiply-adds differently per schedule, so
     schedules agree to FP32 rounding, not bit for bit."""
     ref_q, ref_a = _run(2, False, 0, precision=EU_FP32)
-    for var in range(1, EU_STAGE_SCHEDULES):
+    for var in range(1, EU_STRIP_SCHEDULE0):
         q, a = _run(2, False, var, precision=EU_FP32)
         for l in range(3):
             act = ref_a[l].astype(bool) & a[l].astype(bool)
@@ -49,7 +49,9 @@ def test_autotune_leaves_state_and_picks_a_schedule():
     before = [s.level(l) for l in range(4)]
     var, ms = s.autotune(reps=5)
     say("  autotune", var, ms)
-    assert 0 <= var < EU_STAGE_SCHEDULES and len(ms) == EU_STAGE_SCHEDULES and all(m > 0 for m in ms)
+    assert 0 <= var < EU_STRIP_SCHEDULE0 and len(ms) == EU_STAGE_SCHEDULES
+    assert all(0 < m < float("inf") for m in ms[:EU_STRIP_SCHEDULE0])
+    assert all(m == float("inf") for m in ms[EU_STRIP_SCHEDULE0:])
     for l in range(4):
         assert np.array_equal(s.level(l), before[l])
     t = Solver(2, n0=32, levels=4, precision=EU_FP32, cfl=0.45, t_end=0.25)
@@ -64,8 +66,9 @@ def test_autotune_leaves_state_and_picks_a_schedule():
 
 @pytest.mark.parametrize("lts", [False, True])
 def test_stage_time_leaves_state_and_counts_cells(lts):
-    """The event-timed stage passes change nothing, and the cells they report
-    are the leaves (global step) or the patch cells (local time stepping)."""
+    """The event-timed passes change nothing, and the cell-stages they report
+    are both stages of the leaves (global step, two launches) or the first
+    stage of the patch cells (local time stepping, one launch per level)."""
     if lts:
         s = Solver(3, n0=16, levels=3, precision=EU_FP32, cfl=0.4, lo=-1.0, hi=1.0, time_mode=EU_DT_LTS)
         e = inputs.ellipsoid(0)
@@ -77,8 +80,8 @@ def test_stage_time_leaves_state_and_counts_cells(lts):
     before = [s.level(l) for l in range(s.levels)]
     ms, cells, nl = s.stage_time(reps=4)
     say("  stage_time", ms, cells, nl)
-    assert ms > 0 and nl == (s.levels if lts else 1)
+    assert ms > 0 and nl == (s.levels if lts else 2)
     leaves, active = s.counters()
-    assert cells == int((active if lts else leaves).sum())
+    assert cells == (int(active.sum()) if lts else 2 * int(leaves.sum()))
     for l in range(s.levels):
         assert np.array_equal(s.level(l), before[l])
