@@ -22,7 +22,9 @@
  *    bytes of the two buffers the caller allocates (state, scratch); the
  *    library carves everything it needs out of them and never allocates or
  *    frees device memory itself.  The context owns only host metadata and
- *    the HIP graphs it creates.
+ *    the HIP graphs it creates.  The one exception is a static 4 MiB array
+ *    per GPU, part of the library's loaded code, used only by
+ *    eu_conserved_totals_static.
  *  - Pointers are device pointers unless the name ends in _host.  A _host
  *    output makes the call synchronise the context's stream.
  *  - All work is enqueued on the stream given in eu_config.stream (a
@@ -214,6 +216,22 @@ int eu_advance(eu_ctx *ctx, int nsteps, int use_graph, int *steps_done_host);
  * stream without synchronising (graph-capturable); totals_host (nullable)
  * receives them after a synchronisation. */
 int eu_conserved_totals(eu_ctx *ctx, double *totals_dev, double *totals_host);
+
+/* For callers that cannot allocate device memory or hand the library a
+ * workspace at the call (code under HIP graph capture, tight serving
+ * loops): eu_conserved_totals with its scratch -- the per-tile partial sums
+ * and the per-instance totals -- in a static array of the library's own
+ * device memory (4 MiB, one copy per GPU, held until the process ends)
+ * instead of the context's scratch buffer.  Same kernels, same summation
+ * order: the results equal eu_conserved_totals bit for bit.  totals_dev
+ * (device memory, n_instances x (d+2) doubles, required) receives them on
+ * the stream without synchronising.  EU_ENOMEM when the context's leaf-tile
+ * capacity times d+2, plus n_instances times d+2, exceeds 2^19 doubles
+ * (e.g. a batch of more than about 1.5e5 tiles of 8^2 cells); no device
+ * memory is allocated or freed.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (several streams or host threads)
+ * race and must be serialised by the caller. */
+int eu_conserved_totals_static(eu_ctx *ctx, double *totals_dev);
 
 /* Copy one level (instance inst for a batch, level ignored) of the current
  * state (which = 0) or the RK2 stage state (which = 1) to FP64 host memory

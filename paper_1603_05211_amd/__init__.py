@@ -217,6 +217,15 @@ class Solver:
         self._check(self._lib.eu_conserved_totals(self._ctx, dev, _dp(out)), "eu_conserved_totals")
         return out.reshape(self.n_instances, self.nv) if self.n_instances > 1 else out
 
+    def conserved_totals_static(self, out_dev):
+        """eu_conserved_totals_static: the totals into out_dev (a float64
+        CUDA tensor of n_instances x nv) on the stream, with the library's
+        static device scratch instead of the context's (no allocation)."""
+        assert out_dev.dtype == self.torch.float64 and out_dev.is_cuda
+        assert out_dev.numel() >= self.n_instances * self.nv
+        self._check(self._lib.eu_conserved_totals_static(self._ctx, C.c_void_p(out_dev.data_ptr())),
+                    "eu_conserved_totals_static")
+
     # ------------------------------------------------------------------ read-back
     def level(self, level: int = 0, which: int = 0, inst: int = 0) -> np.ndarray:
         n = self.n(inst if self.n_instances > 1 else level)

@@ -58,6 +58,7 @@ SIGNATURES = {
     "eu_step": (C.c_int, [_vp, C.c_int]),
     "eu_advance": (C.c_int, [_vp, C.c_int, C.c_int, _ip]),
     "eu_conserved_totals": (C.c_int, [_vp, _vp, _dp]),
+    "eu_conserved_totals_static": (C.c_int, [_vp, _vp]),
     "eu_copy_level": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _dp]),
     "eu_copy_uniform": (C.c_int, [_vp, _dp]),
     "eu_get_active": (C.c_int, [_vp, C.c_int, _u8p]),

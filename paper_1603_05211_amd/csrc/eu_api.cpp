@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,18 @@ using namespace eu;
 
 // state of the CFL slots (host view)
 enum { CFL_ZERO = 0, CFL_READY = 1, CFL_STALE = 2 };
+
+// Scratch of eu_conserved_totals_static, in the library's own device memory:
+// the per-tile partial sums, then the per-group totals.  Every GPU the
+// library runs on holds one copy until the process ends; every call on that
+// GPU shares it (overlapping calls race).  In host code the name is only a
+// host-side handle: kernels take the device address that
+// hipGetSymbolAddress returns for the current device (scratch_addr).
+constexpr int64_t STATIC_SCRATCH_DOUBLES = int64_t(1) << 19;   // 4 MiB
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+constexpr int STATIC_MAX_DEV = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[STATIC_MAX_DEV];   // device address of scratch per device
 
 struct eu_ctx {
     eu_config cfg;
@@ -36,6 +49,8 @@ struct eu_ctx {
     int64_t state_elems = 0;    // elements of one state array
     std::vector<int64_t> pbase; // per level: first pmax-block slot (levels 1 .. L-1)
     bool initialized = false;
+    int device = 0;             // device of the caller's buffers
+    double *static_scratch = nullptr;   // that device's address of scratch (nullptr: unresolved)
     int variant = 0;            // stage-kernel schedule (eu_autotune)
     int cfl_state = 0;          // CFL slots: CFL_ZERO, CFL_READY (of the current state) or CFL_STALE
     std::string err;
@@ -286,6 +301,28 @@ int check_launch(eu_ctx *c)
 }
 
 int64_t nblocks_grid(const eu_ctx *c, int g) { return ipow(c->grids[g].nb, c->dim); }
+
+// Device address of scratch on device dev, resolved once per device with
+// that device current (the current device is restored).
+hipError_t scratch_addr(int dev, double **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= STATIC_MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
 
 // Leaf and patch cells per level of the current hierarchy: host sums of the
 // classification partials (one pair per workgroup and level).
@@ -943,6 +980,17 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
         delete c;
         return EU_EHIP;
     }
+    // the device of the caller's buffers, and its copy of the static scratch
+    hipPointerAttribute_t pa;
+    e = hipPointerGetAttributes(&pa, state_dev);
+    if (e == hipSuccess) {
+        c->device = pa.device;
+        e = scratch_addr(c->device, &c->static_scratch);
+    }
+    if (e != hipSuccess) {
+        delete c;
+        return EU_EHIP;
+    }
     *out = c;
     return EU_OK;
 }
@@ -1178,6 +1226,29 @@ int eu_conserved_totals(eu_ctx *c, double *totals_dev, double *totals_host)
         HIPCHK(c, hipMemcpy(totals_host, c->v.totals, 8 * c->nv * c->ngroups, hipMemcpyDeviceToHost));
     }
     return EU_OK;
+}
+
+int eu_conserved_totals_static(eu_ctx *c, double *totals_dev)
+{
+    if (!c || !totals_dev) return EU_EINVAL;
+    if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
+    if (!c->static_scratch) return set_err(c, EU_EHIP, "no device address of the static scratch");
+    // partial sums of every tile the leaf list can hold, then the totals
+    const int64_t npart = ((int64_t)c->max_tiles * c->nv + 31) / 32 * 32;
+    const int64_t need = npart + (int64_t)c->ngroups * c->nv;
+    if (need > STATIC_SCRATCH_DOUBLES)
+        return set_err(c, EU_ENOMEM,
+                       "eu_conserved_totals_static: %lld tiles x %d fields and %d groups need %lld doubles of "
+                       "scratch; the static scratch holds %lld",
+                       (long long)c->max_tiles, c->nv, c->ngroups, (long long)need,
+                       (long long)STATIC_SCRATCH_DOUBLES);
+    View v = c->v;
+    v.partial = c->static_scratch;
+    v.totals = c->static_scratch + npart;
+    c->ks->totals(v, c->max_tiles, c->stream);
+    launch_totals_final(v, c->ngroups, c->stream);
+    launch_copy_f64(totals_dev, v.totals, c->nv * c->ngroups, c->stream);
+    return check_launch(c);
 }
 
 int eu_copy_level(eu_ctx *c, int inst, int level, int which, double *dst)
