@@ -407,6 +407,7 @@ void seq_ghost(eu_ctx *c, int arr)
 void cfl_zero(eu_ctx *c)
 {
     launch_fill_u8((uint8_t *)c->v.cfls, 8 * (int64_t)cfl_slot(CFL_STRIDE, 0), 0, c->stream);
+    if (c->mode == MODE_BATCH) launch_fill_u8((uint8_t *)c->v.smax, 8 * (int64_t)c->ngrid, 0, c->stream);
     c->cfl_state = CFL_ZERO;
 }
 // CFL slots of the current state: left by the last regrid when the state
@@ -426,13 +427,9 @@ void cfl_stale(eu_ctx *c)
 }
 
 // dt of the step from the CFL slots (one-wave reduction kernel, which clears
-// them), or per instance for a batch
+// them), or per instance from the batch's maxima (also cleared)
 void seq_cfl(eu_ctx *c)
 {
-    if (c->mode != MODE_HIER) {
-        c->ks->cfl(c->v, c->max_tiles, c->stream);
-        return;
-    }
     cfl_ready(c);
     launch_cfl_final(c->v, c->stream);
     c->cfl_state = CFL_ZERO;
@@ -464,21 +461,24 @@ void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
     if (strip_variant(c->variant)) {
         // one 2D level (uniform grid or batch): no projection, ghost fill or
         // details; the fused form leaves the new state in the other array
+        // the launch that writes the new state leaves its CFL partials
         hipEvent_t e;
+        if (c->cfl_state != CFL_ZERO) cfl_zero(c);
         if (strip_fused(c->variant)) {
             prof_begin(c, &e);
-            c->ks->fv_strip(c->v, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
+            c->ks->fv_strip(c->v, 1, 0, 1, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
             prof_end(c, e);
             std::swap(c->v.Q, c->v.Qs);
             c->qswap ^= 1;
         } else {
             prof_begin(c, &e);
-            c->ks->fv_strip(c->v, 0, 1, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
+            c->ks->fv_strip(c->v, 0, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
             prof_end(c, e);
             prof_begin(c, &e);
-            c->ks->fv_strip(c->v, 0, 0, c->strips, c->nstrips, c->v.Qs, c->v.Q, c->v.Q, 1.0, c->stream);
+            c->ks->fv_strip(c->v, 0, 0, 1, c->strips, c->nstrips, c->v.Qs, c->v.Q, c->v.Q, 1.0, c->stream);
             prof_end(c, e);
         }
+        c->cfl_state = CFL_READY;
         return;
     }
     // 2D hierarchy: the stage kernel also projects its finest tiles onto
@@ -521,7 +521,10 @@ int predict_launches(const eu_ctx *c, int *lvl, int *nlev, int64_t *maxb)
 
 // Whether a step (with regrid) leaves the CFL slots of the next one: the
 // last prediction launch of the regrid of a hierarchy of two levels or more.
-bool step_leaves_slots(const eu_ctx *c) { return c->mode == MODE_HIER && c->L >= 2; }
+bool step_leaves_slots(const eu_ctx *c)
+{
+    return (c->mode == MODE_HIER && c->L >= 2) || strip_variant(c->variant);
+}
 
 // flags, closure and tiling (finest first), lists, then either the
 // prediction of new cells and ghost cells (coarse to fine, two levels per
@@ -670,11 +673,11 @@ void fv_pass(eu_ctx *c, int var, int *launches)
         *launches = c->L;
     } else if (strip_variant(var)) {
         if (strip_fused(var)) {
-            c->ks->fv_strip(c->v, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
+            c->ks->fv_strip(c->v, 1, 0, 2, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
             *launches = 1;
         } else {
-            c->ks->fv_strip(c->v, 0, 1, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
-            c->ks->fv_strip(c->v, 0, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
+            c->ks->fv_strip(c->v, 0, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
+            c->ks->fv_strip(c->v, 0, 0, 2, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
             *launches = 2;
         }
     } else {

@@ -49,13 +49,14 @@ struct KSet {
     void (*fv_stage)(const View &, int stage, int lvl, int sub, int record, int maxtiles, int variant,
                      int fineproj, hipStream_t);
     // strip kernels: one stage (fused = 0; own_base: the base state is the
-    // source) or both (fused = 1) over count strips
-    void (*fv_strip)(const View &, int fused, int own_base, const Strip *list, int count, const void *src,
+    // source) or both (fused = 1) over count strips; cfl = 1: the launch
+    // adds the CFL partials of the state it writes (zero partials needed),
+    // cfl = 2: computes them without publishing
+    void (*fv_strip)(const View &, int fused, int own_base, int cfl, const Strip *list, int count, const void *src,
                      const void *base, void *out, double fac, hipStream_t);
     void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
-    void (*cfl)(const View &, int maxtiles, hipStream_t);           // batch: maxima and dt
-    void (*cfl_slots)(const View &, int maxtiles, hipStream_t);     // hierarchy: into zero CFL slots
+    void (*cfl_slots)(const View &, int maxtiles, hipStream_t);     // into zero CFL slots / batch maxima
     void (*totals)(const View &, int maxtiles, hipStream_t);
     void (*details)(const View &, int64_t ncell_coarse_levels, hipStream_t);
     void (*composite)(const View &, int lvl, int64_t ncell, hipStream_t);

@@ -119,15 +119,16 @@ template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, 
     }
 }
 
-template <typename T> void fv_strip(const View &v, int fused, int own_base, const Strip *list, int count,
+template <typename T> void fv_strip(const View &v, int fused, int own_base, int cfl, const Strip *list, int count,
                                     const void *src, const void *base, void *out, double fac, hipStream_t s)
 {
     const int nblk = xcd_grid((count + 3) / 4, 16384);
     if (fused)
-        k_fv_strip<T, 1><<<nblk, 256, 0, s>>>(v, list, count, (const T *)src, (const T *)base, (T *)out, fac, 0);
+        k_fv_strip<T, 1><<<nblk, 256, 0, s>>>(v, list, count, (const T *)src, (const T *)base, (T *)out, fac, 0,
+                                              cfl);
     else
         k_fv_strip<T, 0><<<nblk, 256, 0, s>>>(v, list, count, (const T *)src, (const T *)base, (T *)out, fac,
-                                              own_base);
+                                              own_base, cfl);
 }
 
 template <typename T> void copy_level(const View &v, int lvl, int maxb, hipStream_t s)
@@ -144,20 +145,14 @@ template <typename T> void reflux(const View &v, int lvl, int maxb, hipStream_t 
     else k_reflux<T, 3><<<nblk, 256, 0, s>>>(v, lvl);
 }
 
-// Batch: per-instance maxima (atomics), then dt per instance.
-template <typename T> void cfl(const View &v, int maxt, hipStream_t s)
-{
-    const int nblk = clamp_grid((maxt + 3) / 4, v.dim == 2 ? 512 : CFL_MAXBLK);
-    if (v.dim == 2) k_cfl<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
-    else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
-    launch_cfl_final(v, s);
-}
-// Hierarchy: the CFL maxima of the current state added into the slots,
-// which must be zero (one wave per tile; 2D tiles are light: fewer
-// workgroups suffice)
+// The CFL maxima of the current state added into the slots (hierarchy) or
+// the per-instance maxima (batch), which must be zero (one wave per tile;
+// 2D tiles are light: fewer workgroups suffice)
 template <typename T> void cfl_slots(const View &v, int maxt, hipStream_t s)
 {
-    const int nblk = clamp_grid((maxt + 3) / 4, v.dim == 2 ? 512 : CFL_MAXBLK);
+    // (a batch's hundreds of thousands of tiles need the chip: more workgroups)
+    const int cap = v.mode == MODE_BATCH ? 8192 : v.dim == 2 ? 512 : CFL_MAXBLK;
+    const int nblk = clamp_grid((maxt + 3) / 4, cap);
     if (v.dim == 2) k_cfl<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
     else k_cfl<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q);
 }
@@ -197,7 +192,6 @@ template <typename T> KSet make()
     k.fv_strip = fv_strip<T>;
     k.copy_level = copy_level<T>;
     k.reflux = reflux<T>;
-    k.cfl = cfl<T>;
     k.cfl_slots = cfl_slots<T>;
     k.totals = totals<T>;
     k.details = details<T>;

@@ -18,6 +18,14 @@
 // consumes it and never leaves registers; its ghost cells are the clamped
 // cells' stage values (outflow boundaries), taken from their lanes.  It
 // reads Q^n and writes Q^{n+1} to the other state array.
+//
+// CFL partials of the new state: with cfl set, the launch that writes the
+// step's new state also takes, in FP64 from the values it writes, the
+// largest signal speed sum_d (|v_d| + c) of its cells (as the CFL reduction
+// kernel would on that state) and adds it into the grid's maximum (a batch)
+// or a CFL slot with the count of cells advanced (a uniform grid), and
+// raises the non-physical status flag; cfl = 2 computes them without
+// publishing (timing passes).
 #pragma once
 
 namespace eu {
@@ -134,6 +142,39 @@ __device__ __forceinline__ void strip_load(const T *S, int64_t N, int n, int xc,
     for (int f = 0; f < 4; ++f) q[f] = S[f * N + id];
 }
 
+// Signal speed of a written cell into the lane's running maximum (FP64
+// from the stored values, the CFL reduction's expression).
+template <typename T>
+__device__ __forceinline__ void strip_speed(const T *q, double g, double &m, bool &bad)
+{
+    double qd[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) qd[f] = (double)q[f];
+    bool b;
+    const double S = cell_speed<2>(qd, g, b);
+    bad = bad || b;
+    m = S > m ? S : m;
+}
+
+// The wave's maximum speed and cell count into the grid's CFL partials.
+__device__ __forceinline__ void strip_publish(const View &v, int grid, double m, bool bad, int ncell, int wave)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const double r = __shfl_xor(m, o);
+        m = r > m ? r : m;
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&v.meta->status, 1);
+    if ((threadIdx.x & 63) != 0) return;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(m);
+    if (v.mode == MODE_BATCH) {
+        if (m > 0.0) atomicMax(&v.smax[grid], b);
+    } else {
+        const int slot = wave % CFL_NSLOT;
+        if (m > 0.0) atomicMax(v.cfls + cfl_slot(0, slot), b);
+        atomicAdd(v.cfls + cfl_slot(MAXLEV, slot), (unsigned long long)ncell);
+    }
+}
+
 // One stage (FUSED = 0; stage 1: src = Q, base = Q, out = Q*, own_base
 // set: the base rows are the source rows already loaded; stage 2: src = Q*,
 // base = Q, out = Q) or both stages (FUSED = 1: src = base = Q^n, out = the
@@ -143,7 +184,7 @@ __device__ __forceinline__ void strip_load(const T *S, int64_t N, int n, int xc,
 template <typename T, int FUSED>
 __global__ void __launch_bounds__(256) k_fv_strip(View v, const Strip *__restrict__ list, int count,
                                                   const T *__restrict__ src, const T *base, T *out, double fac,
-                                                  int own_base)
+                                                  int own_base, int cfl)
 {
     const int done = v.meta->done;
     const int lane = threadIdx.x & 63;
@@ -168,6 +209,8 @@ __global__ void __launch_bounds__(256) k_fv_strip(View v, const Strip *__restric
         const T *S = src + G.off;
         const T *B = base + G.off;
         T *O = out + G.off;
+        double smax = 0.0;   // CFL: largest speed of the lane's written cells
+        bool bad = false;
         if (done) {
             // a step past t_end: the fused form still leaves the state in
             // the array it writes
@@ -197,10 +240,15 @@ __global__ void __launch_bounds__(256) k_fv_strip(View v, const Strip *__restric
                     if (own_base)
 #pragma unroll
                         for (int f = 0; f < 4; ++f) qo[f] = qa[f];
-                    if (wr)
+                    if (wr) {
+                        T qn[4];
 #pragma unroll
-                        for (int f = 0; f < 4; ++f)
-                            O[f * N + (uint32_t)x + (uint32_t)n * (uint32_t)ro] = qo[f] - lam * R[f];
+                        for (int f = 0; f < 4; ++f) {
+                            qn[f] = qo[f] - lam * R[f];
+                            O[f * N + (uint32_t)x + (uint32_t)n * (uint32_t)ro] = qn[f];
+                        }
+                        if (cfl) strip_speed<T>(qn, v.gamma, smax, bad);
+                    }
                 }
 #pragma unroll
                 for (int f = 0; f < 4; ++f) {
@@ -242,11 +290,14 @@ __global__ void __launch_bounds__(256) k_fv_strip(View v, const Strip *__restric
                         const bool res2 = pipe_enter<T>(P2, g, gi, ws, R2);
                         ++ro2;
                         if (res2 && wr) {
-                            T qo[4];
+                            T qo[4], qn[4];
                             strip_load<T>(B, N, n, xc, ro2, qo);
 #pragma unroll
-                            for (int f = 0; f < 4; ++f)
-                                O[f * N + (uint32_t)x + (uint32_t)n * (uint32_t)ro2] = qo[f] - lam2 * R2[f];
+                            for (int f = 0; f < 4; ++f) {
+                                qn[f] = qo[f] - lam2 * R2[f];
+                                O[f * N + (uint32_t)x + (uint32_t)n * (uint32_t)ro2] = qn[f];
+                            }
+                            if (cfl) strip_speed<T>(qn, v.gamma, smax, bad);
                         }
                     }
                 }
@@ -256,6 +307,13 @@ __global__ void __launch_bounds__(256) k_fv_strip(View v, const Strip *__restric
                     qb[f] = q[f];
                 }
             }
+        }
+        if (cfl) {
+            const int w = 64 - 2 * H;
+            const int nx = n - (st.xb + H) < w ? n - (st.xb + H) : w;   // columns written
+            const double m = cfl == 1 ? smax : -smax;   // cfl == 2: computed, not published
+            if (cfl == 1) strip_publish(v, st.grid, m, bad, nx * st.ny, 4 * t + wid);
+            else if (m > 1e300) atomicOr(&v.meta->status, 0);
         }
     }
 }

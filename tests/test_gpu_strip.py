@@ -161,3 +161,33 @@ def test_autotune_and_stage_time_batch_leave_state():
     assert nl == (1 if var in FUSED else 2)
     for i in range(12):
         assert np.array_equal(s.level(0, inst=i), before[i])
+
+
+@pytest.mark.parametrize("var", STRIP)
+def test_cfl_partials_from_the_update(var):
+    """The launch writing the new state leaves the next step's CFL partials:
+    eager steps, fv_step twice without a CFL reduction between (the partials
+    are cleared first), an external dt, and the count of cells advanced."""
+    prim = inputs.quadrant_states(8)
+    n = 64
+    h = orc.Hierarchy(2, 1, n)
+    h.init_finest(orc.init_quadrant(n, G, prim))
+    s = Solver(2, n0=n, levels=1, precision=EU_FP64, cfl=0.45)
+    s.init_quadrant(prim)
+    s.set_variant(var)
+    for k in range(4):
+        dt_o = h.step(0.45)
+        s.step(False)
+        assert s.time()[1] == dt_o
+    upd, steps = s.leaf_updates()
+    assert steps == 4 and upd == 4 * n * n
+    # two updates with the last dt, no reduction between, then the reduction
+    dt = s.time()[1]
+    import torch
+    d = torch.tensor([dt], dtype=torch.float64, device=s.device)
+    s.fv_step(dt=d)
+    s.fv_step(dt=d)
+    h.step_fixed(dt)
+    h.step_fixed(dt)
+    assert np.array_equal(s.level(0), h.level(0))
+    assert s.cfl_dt() == h.cfl(0.45)[0]
