@@ -29,6 +29,15 @@ What pins each part (tests/test_oracle_pins.py, tests/test_oracle_adaptive.py):
                                    eps = inf equals the uniform coarse run, periodic
                                    conservation, free stream, accuracy perturbation
                                    (Sec. 3) against the uniform finest run
+* Minmod slope .................. the minmod function (sign(a) + sign(b))/2 min(|a|, |b|)
+* AUSMDV flux .................... consistency with the physical flux; supersonic
+                                   upwinding; stationary contact (zero mass flux);
+                                   moving contact = exact upwind flux (pins the
+                                   pressure-ratio weights); Wada-Liou's blended form of
+                                   the split velocities and expanded pressure polynomials
+* MUSCL-Hancock + AUSMDV ......... exact Riemann solutions, second order on a smooth
+                                   wave (fails without the half-step evolution),
+                                   reduction to 1D, symmetry, conservation, free stream
 * local time stepping ............ one level = global step; eps = 0 = uniform substeps;
                                    conservation; a linear profile reproduced to rounding
                                    across refinement boundaries (pins the ghost times
@@ -85,6 +94,10 @@ def lib():
             "orc_cons2prim": (None, [C.c_int, C.c_double, C.c_int64, dp, dp]),
             "orc_ausm_plus": (None, [C.c_int, C.c_double, C.c_int, dp, dp, dp]),
             "orc_slope": (C.c_double, [C.c_double, C.c_double, C.c_double]),
+            "orc_minmod": (C.c_double, [C.c_double, C.c_double, C.c_double]),
+            "orc_ausmdv": (None, [C.c_int, C.c_double, C.c_int, dp, dp, dp]),
+            "orc_phys_flux": (None, [C.c_int, C.c_double, C.c_int, dp, dp]),
+            "orc_h_set_scheme": (C.c_int, [vp, C.c_int]),
             "orc_restrict": (None, [C.c_int, C.c_int, C.c_int, dp, dp]),
             "orc_predict": (None, [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]),
             "orc_h_new": (vp, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -130,6 +143,8 @@ def lib():
 
 
 PLANT_NONE, PLANT_AUSM_AB, PLANT_PRED_ZSWAP, PLANT_LTS_THETA = 0, 1, 2, 3
+PLANT_AUSMDV_ALPHA, PLANT_HANCOCK_NOPRED = 4, 5
+SCHEME_MR, SCHEME_AMR = 0, 1
 
 
 class planted:
@@ -187,6 +202,24 @@ def slope(wm: float, w0: float, wp: float) -> float:
     return lib().orc_slope(wm, w0, wp)
 
 
+def minmod(wm: float, w0: float, wp: float) -> float:
+    return lib().orc_minmod(wm, w0, wp)
+
+
+def ausmdv(dim: int, gamma: float, axis: int, wL, wR) -> np.ndarray:
+    wL, wR = _f64(wL), _f64(wR)
+    F = np.empty(dim + 2)
+    lib().orc_ausmdv(dim, gamma, axis, _dp(wL), _dp(wR), _dp(F))
+    return F
+
+
+def phys_flux(dim: int, gamma: float, axis: int, w) -> np.ndarray:
+    w = _f64(w)
+    F = np.empty(dim + 2)
+    lib().orc_phys_flux(dim, gamma, axis, _dp(w), _dp(F))
+    return F
+
+
 def restrict(dim: int, Af: np.ndarray) -> np.ndarray:
     """Af: (nv, nf, nf[, nf]) -> (nv, nf/2, ...)."""
     Af = _f64(Af)
@@ -242,7 +275,7 @@ class Hierarchy:
 
     def __init__(self, dim: int, levels: int, n0: int, bc: int = BC_TRANSMISSIVE,
                  gamma: float = 1.4, lo: float = 0.0, hi: float = 1.0, eps: float = 1e-3,
-                 eta: float = 0.8, pmin: int = 8, pmax: int = 32):
+                 eta: float = 0.8, pmin: int = 8, pmax: int = 32, scheme: int = SCHEME_MR):
         self.dim, self.L, self.n0, self.bc = dim, levels, n0, bc
         self.gamma, self.lo, self.hi, self.eps, self.eta = gamma, lo, hi, eps, eta
         self.pmin, self.pmax = pmin, pmax
@@ -250,6 +283,9 @@ class Hierarchy:
         self._h = lib().orc_h_new(dim, levels, n0, bc, gamma, lo, hi, eps, eta, pmin, pmax)
         if not self._h:
             raise ValueError("invalid hierarchy parameters")
+        if lib().orc_h_set_scheme(self._h, scheme) != 0:
+            raise ValueError("the AMR scheme runs on grids of one level")
+        self.scheme = scheme
         self.t = 0.0
 
     def __del__(self):

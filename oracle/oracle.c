@@ -35,9 +35,12 @@ enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1 };
  * 1 = AUSM+ without its alpha / beta terms (plain AUSM splitting);
  * 2 = the z pass of the 3D prediction with the upper / lower child swapped;
  * 3 = ghost cells of local time stepping taken from the coarse state at the
- *     start of its step at every stage (constant theta = 0).
+ *     start of its step at every stage (constant theta = 0);
+ * 4 = AUSMDV with its pressure-ratio weights alpha_L = alpha_R = 1;
+ * 5 = MUSCL-Hancock without the half-step evolution of the face states.
  * With 0 every result is the method's, bit for bit. */
-enum { PLANT_NONE = 0, PLANT_AUSM_AB = 1, PLANT_PRED_ZSWAP = 2, PLANT_LTS_THETA = 3 };
+enum { PLANT_NONE = 0, PLANT_AUSM_AB = 1, PLANT_PRED_ZSWAP = 2, PLANT_LTS_THETA = 3,
+       PLANT_AUSMDV_ALPHA = 4, PLANT_HANCOCK_NOPRED = 5 };
 static int plant = PLANT_NONE;
 void orc_set_plant(int which) { plant = which; }
 
@@ -195,6 +198,169 @@ static void face_flux(int dim, int n, int bc, double g, const double *A,
 }
 
 /* ------------------------------------------------------------------------ */
+/* the AMR scheme of Sec. 2: unsplit MUSCL-Hancock, Minmod, AUSMDV           */
+/* ------------------------------------------------------------------------ */
+
+/* Minmod limited slope: the difference of smaller magnitude when the
+ * backward and forward differences have the same sign, else 0. */
+static double slope_minmod(double wm, double w0, double wp)
+{
+    double a = w0 - wm, b = wp - w0;
+    if (!(a * b > 0.0)) return 0.0;
+    return fabs(a) <= fabs(b) ? a : b;
+}
+
+/* Physical flux f_dn of the Euler equations (Sec. 2, the conservation law)
+ * at a primitive state w: (rho u, rho u v + p e_dn, u (rho e + p)), u the
+ * velocity along dn. */
+static void phys_flux(int dim, double g, int dn, const double *w, double *F)
+{
+    double gi = 1.0 / (g - 1.0);
+    double r = w[0], u = w[1 + dn], p = w[dim + 1], K = 0.0;
+    for (int k = 0; k < dim; ++k) K = K + w[1 + k] * w[1 + k];
+    double E = p * gi + (0.5 * r) * K;
+    double m = r * u;
+    F[0] = m;
+    for (int k = 0; k < dim; ++k) {
+        F[1 + k] = m * w[1 + k];
+        if (k == dn) F[1 + k] = F[1 + k] + p;
+    }
+    F[dim + 1] = u * (E + p);
+}
+
+/* AUSMDV flux-vector splitting (Wada and Liou 1997, cited in Sec. 2 for the
+ * AMR scheme) across a face with normal along axis dn; wL / wR primitive.
+ * Common sound speed c_m = max(c_L, c_R); the split velocities blend the
+ * AUSM polynomial and the upwind velocity with the pressure-ratio weights
+ * alpha = 2 (p/rho) / ((p/rho)_L + (p/rho)_R); third-order pressure
+ * polynomials; the normal momentum flux blends the AUSMV form (weight
+ * 1/2 + s) and the AUSMD form (1/2 - s), s = min(1, 10 |dp| / min p) / 2;
+ * tangential momentum and total enthalpy are upwinded with the mass flux.
+ * Plain AUSMDV: neither the entropy fix nor the shock fix. */
+static void ausmdv(int dim, double g, int dn, const double *wL,
+                   const double *wR, double *F)
+{
+    double gi = 1.0 / (g - 1.0);
+    double rL = wL[0], pL = wL[dim + 1], uL = wL[1 + dn];
+    double rR = wR[0], pR = wR[dim + 1], uR = wR[1 + dn];
+    double cL = sqrt((g * pL) / rL);
+    double cR = sqrt((g * pR) / rR);
+    double cm = cL >= cR ? cL : cR;
+    double sL = pL / rL, sR = pR / rR;
+    double aL = (2.0 * sL) / (sL + sR), aR = (2.0 * sR) / (sL + sR);
+    if (plant == PLANT_AUSMDV_ALPHA) aL = aR = 1.0;
+    double upL = 0.5 * (uL + fabs(uL)), umR = 0.5 * (uR - fabs(uR));
+    double Up, Um, Pp, Pm;
+    if (fabs(uL) <= cm) {
+        double a = uL + cm, M = uL / cm, b = M + 1.0;
+        Up = aL * ((a * a) / (4.0 * cm) - upL) + upL;
+        Pp = pL * (((b * b) * (2.0 - M)) * 0.25);
+    } else {
+        Up = upL;
+        Pp = uL > 0.0 ? pL : 0.0;
+    }
+    if (fabs(uR) <= cm) {
+        double a = uR - cm, M = uR / cm, b = M - 1.0;
+        Um = aR * (-((a * a) / (4.0 * cm)) - umR) + umR;
+        Pm = pR * (((b * b) * (2.0 + M)) * 0.25);
+    } else {
+        Um = umR;
+        Pm = uR < 0.0 ? pR : 0.0;
+    }
+    double mh = Up * rL + Um * rR;                 /* (rho u)_{1/2} */
+    double am = fabs(mh);
+    double ph = Pp + Pm;
+    double dp = fabs(pR - pL), pmin = pL <= pR ? pL : pR;
+    double sw = (10.0 * dp) / pmin;
+    double s = 0.5 * (sw < 1.0 ? sw : 1.0);
+    double fV = Up * (rL * uL) + Um * (rR * uR);   /* AUSMV normal momentum */
+    double fD = 0.5 * (mh * (uL + uR) - am * (uR - uL));   /* AUSMD */
+    double KL = 0.0, KR = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        KL = KL + wL[1 + k] * wL[1 + k];
+        KR = KR + wR[1 + k] * wR[1 + k];
+    }
+    double HL = ((pL * gi + (0.5 * rL) * KL) + pL) / rL;
+    double HR = ((pR * gi + (0.5 * rR) * KR) + pR) / rR;
+    F[0] = mh;
+    for (int k = 0; k < dim; ++k) {
+        if (k == dn) F[1 + k] = ((0.5 + s) * fV + (0.5 - s) * fD) + ph;
+        else F[1 + k] = 0.5 * (mh * (wL[1 + k] + wR[1 + k]) - am * (wR[1 + k] - wL[1 + k]));
+    }
+    F[dim + 1] = 0.5 * (mh * (HL + HR) - am * (HR - HL));
+}
+
+/* Conserved state at cell position c of array A (positions outside the
+ * domain are mapped by the boundary map axis by axis), as primitives. */
+static void prim_at(int dim, int n, int bc, double g, const double *A, const int *c, double *w)
+{
+    int64_t N = ncells(dim, n);
+    int p[3] = {bcmap(c[0], n, bc), bcmap(c[1], n, bc), dim == 3 ? bcmap(c[2], n, bc) : 0};
+    double q[NVMAX];
+    for (int f = 0; f < dim + 2; ++f) q[f] = A[f * N + cidx(n, p)];
+    cons2prim(dim, g, q, w);
+}
+
+/* MUSCL-Hancock predictor of cell c (Sec. 2, AMR scheme): Minmod slopes of
+ * the primitive variables along each axis give the face values
+ * W -/+ slope/2; each is advanced half a step in conservative form with the
+ * exact flux, dQ = (dt / 2 dx) sum_d [f_d(W^-_d) - f_d(W^+_d)] (summed
+ * ((d = 1 + d = 2) + d = 3)), the same increment for every face value of
+ * the cell, and returned as primitives Wb[d][0] (lower face of axis d),
+ * Wb[d][1] (upper face).  hl = (dt / 2) / dx. */
+static void hancock_cell(int dim, int n, int bc, double g, const double *A,
+                         const int *c, double hl, double Wb[3][2][NVMAX])
+{
+    int nv = dim + 2;
+    double w0[NVMAX], Wf[3][2][NVMAX], D[3][NVMAX];
+    prim_at(dim, n, bc, g, A, c, w0);
+    for (int d = 0; d < dim; ++d) {
+        double wm[NVMAX], wp[NVMAX];
+        int cm[3] = {c[0], c[1], c[2]}, cp[3] = {c[0], c[1], c[2]};
+        cm[d] -= 1;
+        cp[d] += 1;
+        prim_at(dim, n, bc, g, A, cm, wm);
+        prim_at(dim, n, bc, g, A, cp, wp);
+        for (int f = 0; f < nv; ++f) {
+            double sl = slope_minmod(wm[f], w0[f], wp[f]);
+            Wf[d][0][f] = w0[f] - 0.5 * sl;
+            Wf[d][1][f] = w0[f] + 0.5 * sl;
+        }
+        double fm[NVMAX], fp[NVMAX];
+        phys_flux(dim, g, d, Wf[d][0], fm);
+        phys_flux(dim, g, d, Wf[d][1], fp);
+        for (int f = 0; f < nv; ++f) D[d][f] = fm[f] - fp[f];
+    }
+    double dQ[NVMAX];
+    for (int f = 0; f < nv; ++f) {
+        double S = D[0][f] + D[1][f];
+        if (dim == 3) S = S + D[2][f];
+        dQ[f] = hl * S;
+    }
+    for (int d = 0; d < dim; ++d)
+        for (int sd = 0; sd < 2; ++sd) {
+            double q[NVMAX];
+            prim2cons(dim, g, Wf[d][sd], q);
+            if (plant != PLANT_HANCOCK_NOPRED)
+                for (int f = 0; f < nv; ++f) q[f] = q[f] + dQ[f];
+            cons2prim(dim, g, q, Wb[d][sd]);
+        }
+}
+
+/* AMR-scheme flux at the face between cell c and c + e_dn: AUSMDV of the
+ * evolved upper face value of c and lower face value of c + e_dn. */
+static void face_flux_hancock(int dim, int n, int bc, double g, const double *A,
+                              int dn, const int *c, double hl, double *F)
+{
+    double Wl[3][2][NVMAX], Wr[3][2][NVMAX];
+    int cr[3] = {c[0], c[1], c[2]};
+    cr[dn] += 1;
+    hancock_cell(dim, n, bc, g, A, c, hl, Wl);
+    hancock_cell(dim, n, bc, g, A, cr, hl, Wr);
+    ausmdv(dim, g, dn, Wl[dn][1], Wr[dn][0], F);
+}
+
+/* ------------------------------------------------------------------------ */
 /* multiresolution operators: Sec. 2.1 (projection / prediction, details)    */
 /* ------------------------------------------------------------------------ */
 
@@ -282,6 +448,12 @@ void orc_ausm_plus(int dim, double g, int dn, const double *wL, const double *wR
 }
 
 double orc_slope(double wm, double w0, double wp) { return slope_va(wm, w0, wp); }
+double orc_minmod(double wm, double w0, double wp) { return slope_minmod(wm, w0, wp); }
+void orc_ausmdv(int dim, double g, int dn, const double *wL, const double *wR, double *F)
+{
+    ausmdv(dim, g, dn, wL, wR, F);
+}
+void orc_phys_flux(int dim, double g, int dn, const double *w, double *F) { phys_flux(dim, g, dn, w, F); }
 
 /* Restrict one field-major array (nv fields) from an (2 nc)^d grid to nc^d. */
 void orc_restrict(int dim, int nv, int nc, const double *Af, double *Ac)
@@ -337,6 +509,8 @@ typedef struct {
     orc_patch *patches;
     int npatch, cappatch;
     int no_reflux;       /* test-only planted mistake: skip the flux correction */
+    int scheme;          /* 0: MR scheme (MUSCL, van Albada, AUSM+, midpoint RK2);
+                            1: AMR scheme (MUSCL-Hancock, Minmod, AUSMDV), one level */
 } orc_h;
 
 static int64_t hN(const orc_h *h, int l) { return ncells(h->dim, h->n[l]); }
@@ -917,6 +1091,47 @@ void orc_h_stage(orc_h *h, int stage, double dt)
     }
 }
 
+/* One step of the AMR scheme on a grid of one level (Sec. 2: MUSCL-Hancock,
+ * a single corrector stage): Q^{n+1} = Q^n - (dt/dx) ((dF_1 + dF_2) + dF_3)
+ * with the AUSMDV fluxes of the evolved face values; computed into the stage
+ * array, then copied. */
+static void h_hancock(orc_h *h, double dt)
+{
+    int dim = h->dim, n = h->n[0], nv = h->nv;
+    int64_t N = hN(h, 0);
+    double lam = dt / h->dx[0], hl = (dt * 0.5) / h->dx[0];
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < N; ++i) {
+        int p[3];
+        cdecode(dim, n, i, p);
+        double dF[3][NVMAX];
+        for (int d = 0; d < dim; ++d) {
+            double Fhi[NVMAX], Flo[NVMAX];
+            int lc[3] = {p[0], p[1], p[2]};
+            lc[d] = p[d] - 1;
+            face_flux_hancock(dim, n, h->bc, h->g, h->Q[0], d, p, hl, Fhi);
+            face_flux_hancock(dim, n, h->bc, h->g, h->Q[0], d, lc, hl, Flo);
+            for (int f = 0; f < nv; ++f) dF[d][f] = Fhi[f] - Flo[f];
+        }
+        for (int f = 0; f < nv; ++f) {
+            double R = dF[0][f] + dF[1][f];
+            if (dim == 3) R = R + dF[2][f];
+            h->Qs[0][f * N + i] = h->Q[0][f * N + i] - lam * R;
+        }
+    }
+    memcpy(h->Q[0], h->Qs[0], sizeof(double) * (size_t)(nv * N));
+}
+
+/* Select the finite-volume scheme: 0 the MR scheme, 1 the AMR scheme (grids
+ * of one level only).  Returns 0, or -1 when the scheme does not apply. */
+int orc_h_set_scheme(orc_h *h, int scheme)
+{
+    if (scheme != 0 && scheme != 1) return -1;
+    if (scheme == 1 && h->L != 1) return -1;
+    h->scheme = scheme;
+    return 0;
+}
+
 /* One global time step (Sec. 2: explicit second-order midpoint rule):
  *   Q* = Q^n - (dt/2) F(Q^n),   Q^{n+1} = Q^n - dt F(Q*),
  * on the leaves of every level, then the MR coarsening / refinement.
@@ -924,6 +1139,10 @@ void orc_h_stage(orc_h *h, int stage, double dt)
 double orc_h_step(orc_h *h, double cfl, double t, double t_end, int regrid)
 {
     double dt = orc_h_cfl(h, cfl, t, t_end, NULL);
+    if (h->scheme == 1) {
+        h_hancock(h, dt);
+        return dt;
+    }
     h_stage(h, h->Q, h->Qs, dt, 0.5);
     h_ghost(h, h->Qs);
     h_stage(h, h->Qs, h->Q, dt, 1.0);
@@ -935,6 +1154,10 @@ double orc_h_step(orc_h *h, double cfl, double t, double t_end, int regrid)
 /* One step with a caller-given dt, no regrid (tests). */
 void orc_h_step_fixed(orc_h *h, double dt)
 {
+    if (h->scheme == 1) {
+        h_hancock(h, dt);
+        return;
+    }
     h_stage(h, h->Q, h->Qs, dt, 0.5);
     h_ghost(h, h->Qs);
     h_stage(h, h->Qs, h->Q, dt, 1.0);
