@@ -59,6 +59,7 @@ enum { EU_BC_TRANSMISSIVE = 0, EU_BC_PERIODIC = 1 };
 enum { EU_DT_GLOBAL = 0, EU_DT_LTS = 1 };        /* time stepping           */
 enum { EU_RESTRICT = 0, EU_PROLONG = 1, EU_GHOST = 2 }; /* eu_project modes */
 enum { EU_IC_QUADRANT = 0, EU_IC_ELLIPSOID = 1, EU_IC_RIEMANN1D = 2, EU_IC_UNIFORM = 3 };
+enum { EU_SCHEME_MR = 0, EU_SCHEME_AMR = 1 };      /* finite-volume scheme     */
 enum { EU_STAGE_SCHEDULES = 10, EU_STRIP_SCHEDULE0 = 6 }; /* see eu_autotune  */
 
 /* Problem size and method parameters (Sec. 2; Sec. 4 for the values used
@@ -87,6 +88,13 @@ typedef struct {
     const int32_t *inst_side_host; /* per-instance cells per side (multiples
                             of 8), n_instances entries; NULL when 1 instance  */
     void *stream;        /* hipStream_t                                       */
+    int scheme;          /* EU_SCHEME_MR (0): MUSCL, van Albada, AUSM+,
+                            midpoint RK2 (the paper's MR runs); EU_SCHEME_AMR:
+                            unsplit MUSCL-Hancock with Minmod in primitive
+                            variables and AUSMDV (Wada and Liou 1997), the
+                            paper's AMR runs (Sec. 2) -- 2D grids of one
+                            level (uniform grid or batch), strip schedules 6
+                            and 7, one launch per step                        */
 } eu_config;
 
 /* Initial data (Sec. 4.1 four-quadrant Riemann problem, Sec. 4.2 ellipsoid,
@@ -308,8 +316,9 @@ int eu_autotune(eu_ctx *ctx, int reps, int *variant_host, float *ms_host);
  * context's stream (eager launches on the default stream); the state is
  * left unchanged.  *ms_host: mean milliseconds per pass; *cells_host:
  * cell-stages one pass computes (twice the leaves, or every cell of a
- * uniform grid or batch, for a global step; the patch cells of every level
- * with local time stepping); *launches_host: launches per pass.  Outputs
+ * uniform grid or batch, for a global step; every cell once with the AMR
+ * scheme; the patch cells of every level with local time stepping);
+ * *launches_host: launches per pass.  Outputs
  * are nullable.  EU_ESTATE before initialisation or after t_end. */
 int eu_stage_time(eu_ctx *ctx, int reps, float *ms_host, int64_t *cells_host, int *launches_host);
 int eu_set_variant(eu_ctx *ctx, int variant);

@@ -14,6 +14,7 @@ EU_BC_TRANSMISSIVE, EU_BC_PERIODIC = 0, 1
 EU_DT_GLOBAL, EU_DT_LTS = 0, 1
 EU_RESTRICT, EU_PROLONG, EU_GHOST = 0, 1, 2
 EU_IC_QUADRANT, EU_IC_ELLIPSOID, EU_IC_RIEMANN1D, EU_IC_UNIFORM = 0, 1, 2, 3
+EU_SCHEME_MR, EU_SCHEME_AMR = 0, 1
 EU_STAGE_SCHEDULES = 10
 EU_STRIP_SCHEDULE0 = 6
 
@@ -28,7 +29,7 @@ class EuConfig(C.Structure):
         ("bc", C.c_int), ("cfl", C.c_double), ("t_end", C.c_double), ("eps", C.c_double),
         ("eta", C.c_double), ("patch_min", C.c_int), ("patch_max", C.c_int),
         ("time_mode", C.c_int), ("n_instances", C.c_int),
-        ("inst_side_host", C.POINTER(C.c_int32)), ("stream", C.c_void_p),
+        ("inst_side_host", C.POINTER(C.c_int32)), ("stream", C.c_void_p), ("scheme", C.c_int),
     ]
 
 

@@ -131,6 +131,11 @@ int validate(const eu_config *c, std::string &why)
     if (c->bc != EU_BC_TRANSMISSIVE && c->bc != EU_BC_PERIODIC) { why = "bad bc"; return EU_EINVAL; }
     if (!(c->cfl > 0.0)) { why = "cfl must be positive"; return EU_EINVAL; }
     if (c->time_mode != EU_DT_GLOBAL && c->time_mode != EU_DT_LTS) { why = "bad time_mode"; return EU_EINVAL; }
+    if (c->scheme != EU_SCHEME_MR && c->scheme != EU_SCHEME_AMR) { why = "bad scheme"; return EU_EINVAL; }
+    if (c->scheme == EU_SCHEME_AMR && (c->dim != 2 || (c->n_instances <= 1 && c->levels != 1))) {
+        why = "the AMR scheme runs on 2D grids of one level (uniform grid or batch)";
+        return EU_EINVAL;
+    }
     if (c->time_mode == EU_DT_LTS && c->n_instances > 1) { why = "a batch has no levels to step locally"; return EU_EINVAL; }
     if (c->n_instances > 1) {
         if (!c->inst_side_host) { why = "inst_side_host required for a batch"; return EU_EINVAL; }
@@ -460,11 +465,18 @@ void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
 {
     if (strip_variant(c->variant)) {
         // one 2D level (uniform grid or batch): no projection, ghost fill or
-        // details; the fused form leaves the new state in the other array
-        // the launch that writes the new state leaves its CFL partials
+        // details; the fused form and the AMR scheme leave the new state in
+        // the other array; the launch that writes the new state leaves its
+        // CFL partials
         hipEvent_t e;
         if (c->cfl_state != CFL_ZERO) cfl_zero(c);
-        if (strip_fused(c->variant)) {
+        if (c->cfg.scheme == EU_SCHEME_AMR) {
+            prof_begin(c, &e);
+            c->ks->hancock_strip(c->v, 1, c->strips, c->nstrips, c->v.Q, c->v.Qs, c->stream);
+            prof_end(c, e);
+            std::swap(c->v.Q, c->v.Qs);
+            c->qswap ^= 1;
+        } else if (strip_fused(c->variant)) {
             prof_begin(c, &e);
             c->ks->fv_strip(c->v, 1, 0, 1, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
             prof_end(c, e);
@@ -632,6 +644,7 @@ void drop_graphs(eu_ctx *c)
 bool variant_ok(const eu_ctx *c, int var)
 {
     if (var < 0 || var >= FV_VARIANTS) return false;
+    if (c->cfg.scheme == EU_SCHEME_AMR) return strip_variant(var) && !strip_fused(var);
     if (!strip_variant(var)) return true;
     if (c->dim != 2 || c->L != 1) return false;
     return !strip_fused(var) || c->cfg.bc == EU_BC_TRANSMISSIVE;
@@ -671,6 +684,9 @@ void fv_pass(eu_ctx *c, int var, int *launches)
         for (int l = 0; l < c->L; ++l)
             c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, 0, c->stream);
         *launches = c->L;
+    } else if (c->cfg.scheme == EU_SCHEME_AMR) {
+        c->ks->hancock_strip(c->v, 2, c->strips, c->nstrips, c->v.Q, c->v.Qs, c->stream);
+        *launches = 1;
     } else if (strip_variant(var)) {
         if (strip_fused(var)) {
             c->ks->fv_strip(c->v, 1, 0, 2, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
@@ -994,6 +1010,14 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
         delete c;
         return EU_EHIP;
     }
+    // the AMR scheme runs on the strip kernels only
+    if (cfg->scheme == EU_SCHEME_AMR) {
+        c->variant = FV_STRIP0;
+        if ((r = strips_for(c, c->variant))) {
+            delete c;
+            return r;
+        }
+    }
     *out = c;
     return EU_OK;
 }
@@ -1168,7 +1192,7 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
         // move it to the other array every step); recording a step changes
         // only host bookkeeping, which is restored after each capture (the
         // CFL slots are left by a step as the lines above prepare them)
-        const bool alt = strip_variant(c->variant) && strip_fused(c->variant);
+        const bool alt = strip_variant(c->variant) && (strip_fused(c->variant) || c->cfg.scheme == EU_SCHEME_AMR);
         for (int p = 0; p < (alt ? 2 : 1); ++p) {
             const int q = c->qswap ^ p;
             if (c->gexec[q]) continue;
@@ -1465,7 +1489,7 @@ int eu_stage_time(eu_ctx *c, int reps, float *ms_host, int64_t *cells_host, int 
     // cell-stages of a pass: both stages of every leaf, or the first stage
     // of every patch cell with local time stepping
     if (ms_host) *ms_host = ms;
-    if (cells_host) *cells_host = c->v.lts ? cells : 2 * cells;
+    if (cells_host) *cells_host = c->v.lts || c->cfg.scheme == EU_SCHEME_AMR ? cells : 2 * cells;
     if (launches_host) *launches_host = launches;
     return EU_OK;
 }

@@ -54,6 +54,9 @@ struct KSet {
     // cfl = 2: computes them without publishing
     void (*fv_strip)(const View &, int fused, int own_base, int cfl, const Strip *list, int count, const void *src,
                      const void *base, void *out, double fac, hipStream_t);
+    // the AMR scheme's MUSCL-Hancock step over count strips (src -> out)
+    void (*hancock_strip)(const View &, int cfl, const Strip *list, int count, const void *src, void *out,
+                          hipStream_t);
     void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*cfl_slots)(const View &, int maxtiles, hipStream_t);     // into zero CFL slots / batch maxima

@@ -131,6 +131,13 @@ template <typename T> void fv_strip(const View &v, int fused, int own_base, int 
                                               own_base, cfl);
 }
 
+template <typename T> void hancock_strip(const View &v, int cfl, const Strip *list, int count, const void *src,
+                                         void *out, hipStream_t s)
+{
+    const int nblk = xcd_grid((count + 3) / 4, 16384);
+    k_hancock_strip<T><<<nblk, 256, 0, s>>>(v, list, count, (const T *)src, (T *)out, cfl);
+}
+
 template <typename T> void copy_level(const View &v, int lvl, int maxb, hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 2048);
@@ -190,6 +197,7 @@ template <typename T> KSet make()
     k.predict = predict<T>;
     k.fv_stage = fv_stage<T>;
     k.fv_strip = fv_strip<T>;
+    k.hancock_strip = hancock_strip<T>;
     k.copy_level = copy_level<T>;
     k.reflux = reflux<T>;
     k.cfl_slots = cfl_slots<T>;

@@ -127,3 +127,14 @@ def test_method_calls_take_their_arguments():
                  "int eu_conserved_totals(eu_ctx *ctx, double *totals_dev, double *totals_host);",
                  "int eu_mr_flag(eu_ctx *ctx, double eps, int64_t *nflag_host);"]:
         assert decl in text, decl
+
+
+@pytest.mark.parametrize("kw", [dict(scheme=2), dict(scheme=1, levels=3), dict(scheme=1, dim=3, n0=32, levels=1)])
+def test_scheme_checks(kw):
+    """The AMR scheme (MUSCL-Hancock, AUSMDV) runs on 2D grids of one level."""
+    base = dict(levels=1, n0=64)
+    base.update(kw)
+    r, _, _ = sizes(cfg(**base))
+    assert r == _abi.EU_EINVAL
+    r, _, _ = sizes(cfg(scheme=1, levels=1, n0=64))
+    assert r == _abi.EU_OK
