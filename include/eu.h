@@ -290,14 +290,16 @@ int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
  * tile kernel (one 8^d block with its halo in LDS per workgroup) with 64,
  * 128 or 192 threads per tile in 2D (256 or 512 in 3D), faces axis by axis,
  * axis by axis from per-cell face states, or all axes in one pass.
- * Schedules EU_STRIP_SCHEDULE0 .. EU_STAGE_SCHEDULES-1 apply to 2D grids of
- * one level (a uniform grid or a batch): the strip kernel (one wave per
- * strip of 64 columns marching up the rows; slopes once per cell, x
- * neighbours by lane exchange): 6 and 7 one stage per launch, 8 and 9 both
+ * Schedules EU_STRIP_SCHEDULE0 .. EU_STAGE_SCHEDULES-1 apply to grids of
+ * one level (a uniform grid or a batch): the strip kernels (64 columns per
+ * wave, slopes once per cell, x neighbours by lane exchange).  2D: one wave
+ * per strip marching up the rows; 6 and 7 one stage per launch, 8 and 9 both
  * stages fused in one launch that keeps the stage state in registers
  * (outflow boundaries only; the state then alternates between the two
  * state arrays, which the library tracks); 6 and 8 with strips of 32 rows,
- * 7 and 9 of 128.  In FP64 every schedule gives bit-identical results; in
+ * 7 and 9 of 128.  3D: one workgroup per strip of 8 rows (6, 8) or 16 rows
+ * (7, 9), two of them halo, marching through 32 (6, 7) or 64 (8, 9)
+ * planes, y neighbours through LDS; one stage per launch.  In FP64 every schedule gives bit-identical results; in
  * FP32 they agree to rounding (the compiler contracts each differently).
  * eu_autotune times each schedule that applies (reps passes of one step's
  * finite-volume work on the current state -- both stages, the second in

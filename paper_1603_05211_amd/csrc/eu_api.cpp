@@ -281,6 +281,11 @@ void make_layout(const eu_config *c, Layout &lay)
     if (D == 2 && lay.L == 1) {
         const int w = eu::strip_width(true), ty = eu::strip_rows(eu::FV_STRIP0);
         for (const Grid &G : lay.grids) lay.max_strips += (int64_t)((G.n + w - 1) / w) * ((G.n + ty - 1) / ty);
+    } else if (D == 3 && lay.L == 1) {
+        const int w = eu::strip_width(false), ny = eu::strip3_waves(eu::FV_STRIP0) - 4;
+        const int nz = eu::strip3_planes(eu::FV_STRIP0);
+        for (const Grid &G : lay.grids)
+            lay.max_strips += (int64_t)((G.n + w - 1) / w) * ((G.n + ny - 1) / ny) * ((G.n + nz - 1) / nz);
     }
     lay.o_strips = take(sizeof(eu::Strip) * lay.max_strips);
     lay.scratch = o;
@@ -470,7 +475,15 @@ void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
         // CFL partials
         hipEvent_t e;
         if (c->cfl_state != CFL_ZERO) cfl_zero(c);
-        if (c->cfg.scheme == EU_SCHEME_AMR) {
+        if (c->dim == 3) {
+            const int wv = strip3_waves(c->variant);
+            prof_begin(c, &e);
+            c->ks->fv_strip3(c->v, wv, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
+            prof_end(c, e);
+            prof_begin(c, &e);
+            c->ks->fv_strip3(c->v, wv, 0, 1, c->strips, c->nstrips, c->v.Qs, c->v.Q, c->v.Q, 1.0, c->stream);
+            prof_end(c, e);
+        } else if (c->cfg.scheme == EU_SCHEME_AMR) {
             prof_begin(c, &e);
             c->ks->hancock_strip(c->v, 1, c->strips, c->nstrips, c->v.Q, c->v.Qs, c->stream);
             prof_end(c, e);
@@ -646,7 +659,8 @@ bool variant_ok(const eu_ctx *c, int var)
     if (var < 0 || var >= FV_VARIANTS) return false;
     if (c->cfg.scheme == EU_SCHEME_AMR) return strip_variant(var) && !strip_fused(var);
     if (!strip_variant(var)) return true;
-    if (c->dim != 2 || c->L != 1) return false;
+    if (c->L != 1) return false;
+    if (c->dim == 3) return true;
     return !strip_fused(var) || c->cfg.bc == EU_BC_TRANSMISSIVE;
 }
 
@@ -656,13 +670,23 @@ bool variant_ok(const eu_ctx *c, int var)
 int strips_for(eu_ctx *c, int var)
 {
     if (!strip_variant(var) || c->strip_var == var) return EU_OK;
-    const bool fused = strip_fused(var);
+    const bool fused = c->dim == 2 && strip_fused(var);
     const int w = strip_width(fused), h = strip_halo(fused), ty = strip_rows(var);
     std::vector<Strip> st;
     for (int g = 0; g < c->ngrid; ++g) {
         const int n = c->grids[g].n;
+        if (c->dim == 3) {
+            // planes outermost, then columns, rows innermost: list neighbours
+            // share their halo rows
+            const int ny = strip3_waves(var) - 4, tz = strip3_planes(var);
+            for (int z0 = 0; z0 < n; z0 += tz)
+                for (int x0 = 0; x0 < n; x0 += w)
+                    for (int y0 = 0; y0 < n; y0 += ny)
+                        st.push_back(Strip{g, x0 - h, y0, std::min(ny, n - y0), z0, std::min(tz, n - z0)});
+            continue;
+        }
         for (int x0 = 0; x0 < n; x0 += w)
-            for (int y0 = 0; y0 < n; y0 += ty) st.push_back(Strip{g, x0 - h, y0, std::min(ty, n - y0)});
+            for (int y0 = 0; y0 < n; y0 += ty) st.push_back(Strip{g, x0 - h, y0, std::min(ty, n - y0), 0, 1});
     }
     if ((int64_t)st.size() > c->max_strips) return set_err(c, EU_EHIP, "strip list exceeds its capacity");
     int r = upload(c, c->strips, st.data(), sizeof(Strip) * st.size());
@@ -684,6 +708,11 @@ void fv_pass(eu_ctx *c, int var, int *launches)
         for (int l = 0; l < c->L; ++l)
             c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, 0, c->stream);
         *launches = c->L;
+    } else if (strip_variant(var) && c->dim == 3) {
+        const int wv = strip3_waves(var);
+        c->ks->fv_strip3(c->v, wv, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
+        c->ks->fv_strip3(c->v, wv, 0, 2, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
+        *launches = 2;
     } else if (c->cfg.scheme == EU_SCHEME_AMR) {
         c->ks->hancock_strip(c->v, 2, c->strips, c->nstrips, c->v.Q, c->v.Qs, c->stream);
         *launches = 1;
@@ -1192,7 +1221,8 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
         // move it to the other array every step); recording a step changes
         // only host bookkeeping, which is restored after each capture (the
         // CFL slots are left by a step as the lines above prepare them)
-        const bool alt = strip_variant(c->variant) && (strip_fused(c->variant) || c->cfg.scheme == EU_SCHEME_AMR);
+        const bool alt = strip_variant(c->variant) && c->dim == 2 &&
+                         (strip_fused(c->variant) || c->cfg.scheme == EU_SCHEME_AMR);
         for (int p = 0; p < (alt ? 2 : 1); ++p) {
             const int q = c->qswap ^ p;
             if (c->gexec[q]) continue;

@@ -50,10 +50,11 @@ struct Tile {
     int block;       // block index within the grid, x fastest
 };
 
-// Work item of the strip kernels (uniform 2D grids and batches): rows y0 ..
-// y0+ny-1 of the 64 columns xb .. xb+63 of grid `grid`, one wave.
+// Work item of the strip kernels (grids of one level): the 64 columns xb ..
+// xb+63 of grid `grid`.  2D: rows y0 .. y0+ny-1, one wave.  3D: output
+// rows y0 .. y0+ny-1 of planes z0 .. z0+nz-1, one workgroup.
 struct Strip {
-    int grid, xb, y0, ny;
+    int grid, xb, y0, ny, z0, nz;
 };
 
 // Device-resident counters written by the mesh kernels.

@@ -1725,3 +1725,4 @@ __global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q
 }  // namespace eu
 
 #include "eu_strip.hpp"
+#include "eu_strip3.hpp"

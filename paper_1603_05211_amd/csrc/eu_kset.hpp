@@ -23,13 +23,17 @@ struct InitArgs {
 enum { ARR_Q = 0, ARR_QS = 1, ARR_QO = 2 };
 
 constexpr int FV_VARIANTS = 10;  // schedules of the stage kernel (autotuned)
-// Schedules 6-9 (2D grids of one level: a uniform grid or a batch) run the
-// strip kernels: 6, 7 one stage per launch, 8, 9 both stages in one launch
-// (outflow boundaries only); 6 and 8 strips of 32 rows, 7 and 9 of 128.
+// Schedules 6-9 (grids of one level: a uniform grid or a batch) run the
+// strip kernels.  2D: 6, 7 one stage per launch, 8, 9 both stages in one
+// launch (outflow boundaries only); 6 and 8 strips of 32 rows, 7 and 9 of
+// 128.  3D (one stage per launch): workgroups of 8 rows (6, 8) or 16 rows
+// (7, 9), strips of 32 planes (6, 7) or 64 (8, 9).
 constexpr int FV_STRIP0 = 6;
 inline bool strip_variant(int var) { return var >= FV_STRIP0; }
 inline bool strip_fused(int var) { return var >= FV_STRIP0 + 2; }
 inline int strip_rows(int var) { return (var - FV_STRIP0) % 2 ? 128 : 32; }
+inline int strip3_waves(int var) { return (var - FV_STRIP0) % 2 ? 16 : 8; }
+inline int strip3_planes(int var) { return var >= FV_STRIP0 + 2 ? 64 : 32; }
 inline int strip_width(bool fused) { return fused ? 56 : 60; }   // columns written per strip
 inline int strip_halo(bool fused) { return fused ? 4 : 2; }
 
@@ -54,6 +58,10 @@ struct KSet {
     // cfl = 2: computes them without publishing
     void (*fv_strip)(const View &, int fused, int own_base, int cfl, const Strip *list, int count, const void *src,
                      const void *base, void *out, double fac, hipStream_t);
+    // 3D strip kernel: one stage over count strips with workgroups of waves
+    // rows (8 or 16)
+    void (*fv_strip3)(const View &, int waves, int own_base, int cfl, const Strip *list, int count, const void *src,
+                      const void *base, void *out, double fac, hipStream_t);
     // the AMR scheme's MUSCL-Hancock step over count strips (src -> out)
     void (*hancock_strip)(const View &, int cfl, const Strip *list, int count, const void *src, void *out,
                           hipStream_t);

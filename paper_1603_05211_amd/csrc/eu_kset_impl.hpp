@@ -131,6 +131,18 @@ template <typename T> void fv_strip(const View &v, int fused, int own_base, int 
                                               own_base, cfl);
 }
 
+template <typename T> void fv_strip3(const View &v, int waves, int own_base, int cfl, const Strip *list, int count,
+                                     const void *src, const void *base, void *out, double fac, hipStream_t s)
+{
+    const int nblk = xcd_grid(count, 16384);
+    if (waves == 16)
+        k_fv_strip3<T, 16><<<nblk, 1024, 0, s>>>(v, list, count, (const T *)src, (const T *)base, (T *)out, fac,
+                                                 own_base, cfl);
+    else
+        k_fv_strip3<T, 8><<<nblk, 512, 0, s>>>(v, list, count, (const T *)src, (const T *)base, (T *)out, fac,
+                                               own_base, cfl);
+}
+
 template <typename T> void hancock_strip(const View &v, int cfl, const Strip *list, int count, const void *src,
                                          void *out, hipStream_t s)
 {
@@ -198,6 +210,7 @@ template <typename T> KSet make()
     k.fv_stage = fv_stage<T>;
     k.fv_strip = fv_strip<T>;
     k.hancock_strip = hancock_strip<T>;
+    k.fv_strip3 = fv_strip3<T>;
     k.copy_level = copy_level<T>;
     k.reflux = reflux<T>;
     k.cfl_slots = cfl_slots<T>;

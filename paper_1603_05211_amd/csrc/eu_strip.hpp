@@ -144,14 +144,14 @@ __device__ __forceinline__ void strip_load(const T *S, int64_t N, int n, int xc,
 
 // Signal speed of a written cell into the lane's running maximum (FP64
 // from the stored values, the CFL reduction's expression).
-template <typename T>
+template <typename T, int D = 2>
 __device__ __forceinline__ void strip_speed(const T *q, double g, double &m, bool &bad)
 {
-    double qd[4];
+    double qd[D + 2];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) qd[f] = (double)q[f];
+    for (int f = 0; f < D + 2; ++f) qd[f] = (double)q[f];
     bool b;
-    const double S = cell_speed<2>(qd, g, b);
+    const double S = cell_speed<D>(qd, g, b);
     bad = bad || b;
     m = S > m ? S : m;
 }

@@ -119,10 +119,70 @@ def test_strip_schedules_rejected_on_hierarchies():
     for var in STRIP:
         with pytest.raises(EuError):
             s.set_variant(var)
-    t = Solver(3, n0=16, levels=1, precision=EU_FP64, lo=-1.0)
+    t = Solver(3, n0=16, levels=2, precision=EU_FP64, lo=-1.0)
     for var in STRIP:
         with pytest.raises(EuError):
             t.set_variant(var)
+
+
+def oracle_ellipsoid(n, e, steps, bc=0, cfl=0.4, t_end=math.inf):
+    h = orc.Hierarchy(3, 1, n, bc=bc, lo=-1.0, hi=1.0)
+    h.init_finest(orc.init_ellipsoid(n, G, e.a, e.b, e.c, e.theta, e.phi, e.states, -1.0, 1.0, e.rc))
+    dts = []
+    for _ in range(steps):
+        if h.t >= t_end:
+            break
+        dts.append(h.step(cfl, t_end))
+    return h, dts
+
+
+@pytest.mark.parametrize("var", STRIP)
+@pytest.mark.parametrize("n", [32, 64])
+def test_uniform3d_fp64_bit_exact(var, n):
+    """3D strips (8 or 16 rows per workgroup, 32 or 64 planes per strip):
+    the ellipsoid blast, step by step with the time steps compared; 64 is
+    not a multiple of the strip's 60 columns or its 4 / 12 output rows."""
+    e = inputs.ellipsoid(2)
+    steps = 12 if n == 32 else 6
+    h, dts = oracle_ellipsoid(n, e, steps)
+    say("strip 3d fp64 schedule", var, "n", n)
+    s = Solver(3, n0=n, levels=1, precision=EU_FP64, cfl=0.4, lo=-1.0, hi=1.0)
+    s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
+    s.set_variant(var)
+    got = []
+    for _ in range(steps):
+        s.step(False)
+        got.append(s.time()[1])
+    assert np.array_equal(np.array(dts), np.array(got))
+    assert np.array_equal(s.level(0), h.level(0)), np.abs(s.level(0) - h.level(0)).max()
+
+
+@pytest.mark.parametrize("var", [EU_STRIP_SCHEDULE0, EU_STRIP_SCHEDULE0 + 3])
+def test_uniform3d_periodic_and_graph(var):
+    e = inputs.ellipsoid(4)
+    h, _ = oracle_ellipsoid(32, e, 10, bc=orc.BC_PERIODIC)
+    s = Solver(3, n0=32, levels=1, precision=EU_FP64, cfl=0.4, lo=-1.0, hi=1.0, bc=1)
+    s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
+    s.set_variant(var)
+    s.advance(10, use_graph=True)
+    assert np.array_equal(s.level(0), h.level(0))
+
+
+@pytest.mark.parametrize("var", STRIP)
+def test_uniform3d_fp32_within_bound(var):
+    e = inputs.ellipsoid(0)
+    h, _ = oracle_ellipsoid(32, e, 20)
+    s = Solver(3, n0=32, levels=1, precision=EU_FP32, cfl=0.4, lo=-1.0, hi=1.0)
+    s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
+    s.set_variant(var)
+    s.advance(20, use_graph=True)
+    g, o = s.level(0), h.level(0)
+    scale = np.abs(o[0]).sum()
+    for f in range(5):
+        l1 = np.abs(g[f] - o[f]).sum() / scale
+        linf = np.abs(g[f] - o[f]).max() / np.abs(o[f]).max()
+        say(f"  3d fp32 schedule {var} field {f}: L1 rel {l1:.2e}, Linf rel {linf:.2e}")
+        assert l1 <= 1e-5 and linf <= 1e-3
 
 
 @pytest.mark.parametrize("var", STRIP)
