@@ -41,12 +41,16 @@ sys.path.insert(0, ROOT)
 
 # algorithmic floating-point operations of one finite-volume stage per leaf
 # cell: adds, multiplies, divides and square roots of the expression tree
-# (one primitive conversion per cell, one flux per face, the update)
+# (one primitive conversion per cell, one flux per face, the update).  MR
+# scheme: a midpoint-rule stage; AMR scheme (2D): the whole MUSCL-Hancock
+# step (predictor of the face values and the AUSMDV corrector).
 FLOPS_PER_CELL_STAGE = {2: 325, 3: 568}
+FLOPS_PER_CELL_AMR = {2: 445}
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}      # MI355X vector peaks
 HBM_PEAK_GBS = 8000.0
 FV_SOURCES = ["paper_1603_05211_amd/csrc/eu_kernels.hpp", "paper_1603_05211_amd/csrc/eu_kset_impl.hpp",
-              "paper_1603_05211_amd/csrc/eu_internal.hpp"]
+              "paper_1603_05211_amd/csrc/eu_internal.hpp", "paper_1603_05211_amd/csrc/eu_strip.hpp",
+              "paper_1603_05211_amd/csrc/eu_strip3.hpp"]
 METRIC = "cell-updates/s (FP32 batched vs FP64 plain) at stated L1 err; % HBM roofline"
 
 WORKLOADS = {
@@ -74,9 +78,9 @@ def log(*a):
 class Run:
     """A workload on the library: the solver and how to (re)initialise it."""
 
-    def __init__(self, workload, precision, seed=0):
+    def __init__(self, workload, precision, seed=0, scheme=0):
         from paper_1603_05211_amd import EU_DT_LTS, EU_FP32, EU_FP64, Solver, inputs
-        self.workload, self.precision = workload, precision
+        self.workload, self.precision, self.scheme = workload, precision, scheme
         prec = EU_FP32 if precision == "fp32" else EU_FP64
         if workload == "quad2d_adaptive5":
             s = Solver(2, n0=32, levels=5, precision=prec, cfl=0.45, t_end=0.25, eps=1e-3, eta=0.8,
@@ -97,11 +101,11 @@ class Run:
             self.dim = 3
         elif workload == "quad2d_batch512":
             b = inputs.batch(seed)
-            s = Solver(2, sides=list(b.sides), precision=prec, cfl=0.45)
+            s = Solver(2, sides=list(b.sides), precision=prec, cfl=0.45, scheme=scheme)
             self.init = lambda: s.init_quadrant_batch(b.states)
             self.dim = 2
         elif workload == "quad2d_uniform128":
-            s = Solver(2, n0=128, levels=1, precision=prec, cfl=0.45)
+            s = Solver(2, n0=128, levels=1, precision=prec, cfl=0.45, scheme=scheme)
             prim = inputs.quadrant_states(seed)
             self.init = lambda: s.init_quadrant(prim)
             self.dim = 2
@@ -115,6 +119,17 @@ class Run:
 
     def close(self):
         self.s.close()
+
+    def kernel(self):
+        """The finite-volume kernel the chosen schedule launches."""
+        if self.variant is None or self.variant < 6:
+            return "k_fv_stage"
+        if self.scheme == 1:
+            return "k_hancock_strip"
+        return "k_fv_strip3" if self.dim == 3 else "k_fv_strip"
+
+    def flops_per_cell_stage(self):
+        return FLOPS_PER_CELL_AMR[self.dim] if self.scheme == 1 else FLOPS_PER_CELL_STAGE[self.dim]
 
     def extent(self, tune_every=0, reps=5):
         """One untimed run over the workload's extent from the initial state;
@@ -180,15 +195,19 @@ class Run:
         s = self.s
         self.init()
         every = max(1, self.nsteps // samples)
-        ms_sum, cells_sum, launches, lpp, done = 0.0, 0.0, 0, 1, 0
+        ms_sum, cells_sum, launches, lpp, done, nsamp = 0.0, 0.0, 0, 1, 0, 0
         while done + every < self.nsteps:
             done += s.advance(every, use_graph=True)
             ms, cells, lpp = s.stage_time(reps)
             ms_sum += ms * reps
             cells_sum += cells * reps
             launches += lpp * reps
+            nsamp += 1
         n = max(launches, 1)
-        flops = FLOPS_PER_CELL_STAGE[self.dim] * cells_sum
+        flops = self.flops_per_cell_stage() * cells_sum
+        # finite-volume launches of this phase: the steps between samples
+        # (launches per pass each) and each sample's untimed and timed replay
+        self.phase_launches = nsamp * lpp * (every + 2 * reps)
         return ms_sum / n, launches, cells_sum / n, lpp, flops / (ms_sum * 1e-3) / 1e12 if ms_sum else 0.0
 
 
@@ -200,13 +219,14 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload, precision, cells_per_launch):
-    """HBM bytes per stage launch: the committed counter summary of this
-    workload (FETCH_SIZE and WRITE_SIZE per launch, scaled by the readings of
-    a plain 256 MiB device copy) gives bytes per cell advanced, which is
-    scaled to this run's cells per launch.  None when the summary is missing
-    or the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"k_fv_stage_{workload}_{precision}_traffic.json")
+def traffic_from_profile(workload, precision, kernel, cells_per_launch):
+    """HBM bytes per launch of the finite-volume kernel: the committed counter
+    summary of this workload and kernel (FETCH_SIZE and WRITE_SIZE per
+    launch, scaled by the readings of a plain 256 MiB device copy) gives
+    bytes per cell-stage, which is scaled to this run's cell-stages per
+    launch.  None when the summary is missing or the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
@@ -223,14 +243,16 @@ def traffic_from_profile(workload, precision, cells_per_launch):
 def roofline(r, precision, samples=64):
     ms, nl, cells, lpp, tflops = r.stage_samples(samples)
     peak = PEAK_TFLOPS[precision]
-    traffic, src = traffic_from_profile(r.workload, precision, cells)
-    return {"bound": "alu", "kernel": "k_fv_stage", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+    kern = r.kernel()
+    traffic, src = traffic_from_profile(r.workload, precision, kern, cells)
+    return {"bound": "alu", "kernel": kern, "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
             "frac": tflops / peak, "traffic": traffic, "traffic_source": src, "avg_launch_ms": ms,
-            "launches": nl, "launches_per_pass": lpp, "cells_per_launch": cells,
-            "flops_per_cell": FLOPS_PER_CELL_STAGE[r.dim],
-            "timing": "HIP events on the library's stream around graphs of 5 first-stage passes at "
-                      f"{samples} evenly spaced steps of the run (the tracer's kernel durations are "
-                      "in profiles/)"}
+            "launches": nl, "launches_per_pass": lpp, "cell_stages_per_launch": cells,
+            "phase_launches": getattr(r, "phase_launches", None),
+            "flops_per_cell_stage": r.flops_per_cell_stage(),
+            "timing": "HIP events on the library's stream around graphs of 5 passes of one step's "
+                      f"finite-volume work at {samples} evenly spaced steps of the run (the tracer's "
+                      "kernel durations are in profiles/)"}
 
 
 # ---------------------------------------------------------------------------
@@ -348,21 +370,25 @@ def cpu_sample_1thread(workload, budget_s):
 
 # ---------------------------------------------------------------------------
 
-def extra_line(workload, precision, runs, tune=True, after=None):
+def extra_line(workload, precision, runs, tune=True, after=None, scheme=0):
     """A context line: the workload timed over its extent (runs runs),
     `after(run)` called on the final state of the last timed run (its
-    result, when a dict, is the line's accuracy), then the stage kernel's
-    rate over the run."""
-    r = Run(workload, precision)
+    result, when a dict, is the line's accuracy), then the finite-volume
+    kernel's rate over the run."""
+    r = Run(workload, precision, scheme=scheme)
     r.extent(tune_every=max(1, (FIXED_STEPS.get(workload) or 200) // 4) if tune else 0, reps=3)
     upd, sec, k = r.timed(runs)
     out = {"value": upd / sec, "runs": k, "steps_per_run": r.nsteps, "ms_per_run": 1e3 * sec / k,
-           "stage_schedule": r.variant, "tuning": r.tuning, "precision": precision}
+           "stage_schedule": r.variant, "tuning": r.tuning, "precision": precision,
+           "scheme": "AMR (MUSCL-Hancock, Minmod, AUSMDV)" if scheme else "MR (MUSCL, van Albada, AUSM+, RK2)"}
     if after is not None:
         acc = after(r)
         if isinstance(acc, dict):
             out["accuracy"] = acc
     out["roofline"] = roofline(r, precision, samples=16)
+    es, nv = (4 if precision == "fp32" else 8), r.dim + 2
+    out["roofline"]["hbm_algorithmic_GBs"] = out["value"] * 2 * nv * es / 1e9
+    out["roofline"]["hbm_algorithmic_frac"] = out["value"] * 2 * nv * es / 1e9 / HBM_PEAK_GBS
     r.close()
     return out
 
@@ -504,11 +530,15 @@ def main():
                          "(tests/test_gpu_parity.py)"}
         ex["ellip3d_adaptive4_lts_fp32"] = extra_line("ellip3d_adaptive4_lts", "fp32", 1)
         ex["quad2d_uniform128_fp64"] = extra_line("quad2d_uniform128", "fp64", 3, after=uniform128_error)
+        ex["quad2d_batch512_amr_fp32"] = extra_line("quad2d_batch512", "fp32", 2, scheme=1,
+                                                    after=lambda rr: batch_error(rr, scheme=1))
+        ex["quad2d_uniform128_amr_fp64"] = extra_line("quad2d_uniform128", "fp64", 3, scheme=1,
+                                                      after=lambda rr: uniform128_error(rr, scheme=1))
         result["extra"] = ex
     print(json.dumps(result), flush=True)
 
 
-def batch_error(r, ninst=4):
+def batch_error(r, ninst=4, scheme=0):
     """The batch's first instances of the two smallest sides against the
     FP64 oracle over the same 100 steps."""
     import numpy as np
@@ -519,7 +549,7 @@ def batch_error(r, ninst=4):
     out = []
     for i in order:
         n = int(b.sides[i])
-        h = orc.Hierarchy(2, 1, n)
+        h = orc.Hierarchy(2, 1, n, scheme=scheme)
         h.init_finest(orc.init_quadrant(n, 1.4, b.states[i]))
         for _ in range(r.nsteps):
             h.step(0.45)
@@ -529,10 +559,10 @@ def batch_error(r, ninst=4):
     return {"sampled_instances": out, "reference": "FP64 oracle, the same 100 steps of those instances"}
 
 
-def uniform128_error(r):
+def uniform128_error(r, scheme=0):
     import oracle as orc
     from paper_1603_05211_amd import inputs
-    h = orc.Hierarchy(2, 1, 128)
+    h = orc.Hierarchy(2, 1, 128, scheme=scheme)
     h.init_finest(orc.init_quadrant(128, 1.4, inputs.quadrant_states(0)))
     for _ in range(r.nsteps):
         h.step(0.45)
