@@ -297,8 +297,8 @@ int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
  * stages fused in one launch that keeps the stage state in registers
  * (outflow boundaries only; the state then alternates between the two
  * state arrays, which the library tracks); 6 and 8 with strips of 32 rows,
- * 7 and 9 of 128.  3D: one workgroup per strip of 8 rows (6, 8) or 16 rows
- * (7, 9), two of them halo, marching through 32 (6, 7) or 64 (8, 9)
+ * 7 and 9 of 128.  3D: one workgroup per strip of 8 output rows (6, 8) or
+ * 16 (7, 9), one wave per row, marching through 32 (6, 7) or 64 (8, 9)
  * planes, y neighbours through LDS; one stage per launch.  In FP64 every schedule gives bit-identical results; in
  * FP32 they agree to rounding (the compiler contracts each differently).
  * eu_autotune times each schedule that applies (reps passes of one step's

@@ -282,7 +282,7 @@ void make_layout(const eu_config *c, Layout &lay)
         const int w = eu::strip_width(true), ty = eu::strip_rows(eu::FV_STRIP0);
         for (const Grid &G : lay.grids) lay.max_strips += (int64_t)((G.n + w - 1) / w) * ((G.n + ty - 1) / ty);
     } else if (D == 3 && lay.L == 1) {
-        const int w = eu::strip_width(false), ny = eu::strip3_waves(eu::FV_STRIP0) - 4;
+        const int w = eu::strip_width(false), ny = eu::strip3_waves(eu::FV_STRIP0);
         const int nz = eu::strip3_planes(eu::FV_STRIP0);
         for (const Grid &G : lay.grids)
             lay.max_strips += (int64_t)((G.n + w - 1) / w) * ((G.n + ny - 1) / ny) * ((G.n + nz - 1) / nz);
@@ -678,7 +678,7 @@ int strips_for(eu_ctx *c, int var)
         if (c->dim == 3) {
             // planes outermost, then columns, rows innermost: list neighbours
             // share their halo rows
-            const int ny = strip3_waves(var) - 4, tz = strip3_planes(var);
+            const int ny = strip3_waves(var), tz = strip3_planes(var);
             for (int z0 = 0; z0 < n; z0 += tz)
                 for (int x0 = 0; x0 < n; x0 += w)
                     for (int y0 = 0; y0 < n; y0 += ny)

@@ -26,7 +26,7 @@ constexpr int FV_VARIANTS = 10;  // schedules of the stage kernel (autotuned)
 // Schedules 6-9 (grids of one level: a uniform grid or a batch) run the
 // strip kernels.  2D: 6, 7 one stage per launch, 8, 9 both stages in one
 // launch (outflow boundaries only); 6 and 8 strips of 32 rows, 7 and 9 of
-// 128.  3D (one stage per launch): workgroups of 8 rows (6, 8) or 16 rows
+// 128.  3D (one stage per launch): workgroups of 8 output rows (6, 8) or 16
 // (7, 9), strips of 32 planes (6, 7) or 64 (8, 9).
 constexpr int FV_STRIP0 = 6;
 inline bool strip_variant(int var) { return var >= FV_STRIP0; }

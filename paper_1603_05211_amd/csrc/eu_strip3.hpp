@@ -2,18 +2,19 @@
 // workgroup per strip.
 //
 // A strip is 64 consecutive columns (lane l holds column xb + l) of W
-// consecutive rows (wave w holds row y0 - 2 + w: two halo rows at each
-// end) and a run of planes.  The workgroup marches through the planes: each
-// wave converts its row of the entering plane to primitive variables once
+// consecutive output rows (wave w holds row y0 + w; waves 0, 1, W-2 and W-1
+// also hold one of the two halo rows at each end) and a run of planes.  The
+// workgroup marches through the planes: each wave converts its row of the entering plane to primitive variables once
 // and keeps a window of three planes in registers for the z slopes, face
 // states and fluxes; the x slopes and fluxes of a row come from the
 // neighbouring lanes (DPP wave shifts), the y ones from the neighbouring
 // rows through LDS (three workgroup barriers per plane: rows published,
 // upper face states published, face fluxes published).  Halo rows only load
-// (and, next to the output rows, provide y face states and fluxes), so
-// their waves cost little issue time.  The arithmetic is the stage kernel's
-// expression tree operation for operation (slope, face states, AUSM+,
-// ((dF_1 + dF_2) + dF_3), q - lam R): FP64 results are identical to it.
+// and, next to the output rows, provide y face states and fluxes.  Four
+// waves per SIMD are asked for (two workgroups of 8 rows, or one of 16, per
+// CU).  The arithmetic is the stage kernel's expression tree operation for
+// operation (slope, face states, AUSM+, ((dF_1 + dF_2) + dF_3), q - lam R):
+// FP64 results are identical to it.
 #pragma once
 
 namespace eu {
@@ -38,26 +39,42 @@ __device__ __forceinline__ void strip_rx3(T g, T gi, const T *w, T *R)
     for (int f = 0; f < 5; ++f) R[f] = F[f] - lane_from_left(F[f]);
 }
 
+// One row of a 3D strip: its z window of primitive states (wa, wb) and,
+// for an output row, the base window (qa, qb) and the z faces (sp, fl).
+template <typename T>
+struct Row3 {
+    T wa[5], wb[5], qa[5], qb[5], sp[5], fl[5];
+};
+
 // One stage (stage 1: src = Q, base = Q, out = Q*, own_base set; stage 2:
 // src = Q*, base = Q, out = Q) over the strips of the list; with cfl set the
 // CFL partials of the state it writes (as k_fv_strip).  W waves per
-// workgroup (W - 4 output rows per strip); strips walked XCD by XCD.
+// workgroup, wave w on output row y0 + w; the two halo rows below the first
+// output row go to waves 0 and 1, the two above the last to waves W-2 and
+// W-1 (a second row each: loads, and the y face values or fluxes the
+// output rows need), so every wave has an output row.  Strips walked XCD
+// by XCD.
 template <typename T, int W>
-__global__ void __launch_bounds__(W * 64) k_fv_strip3(View v, const Strip *__restrict__ list, int count,
+__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) k_fv_strip3(View v, const Strip *__restrict__ list, int count,
                                                       const T *__restrict__ src, const T *base, T *out, double fac,
                                                       int own_base, int cfl)
 {
-    constexpr int NV = 5, H = 2;
-    // per row: the primitive states of the plane being finished, then the
-    // flux through its lower y face (two planes in flight, by parity)
-    __shared__ T sW[2][W][NV][64];
+    constexpr int NV = 5, H = 2, NR = W + 4;
+    // per row (row index j + 2): the primitive states of the plane being
+    // finished, then the flux through its lower y face (two planes in
+    // flight, by parity)
+    __shared__ T sW[2][NR][NV][64];
     // per row: the upper y face state of the plane being finished
-    __shared__ T sP[W][NV][64];
+    __shared__ T sP[NR][NV][64];
     if (v.meta->done) return;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const T g = (T)v.gamma;
     const T gi = (T)(1.0 / (v.gamma - 1.0));
+    // the wave's second row: halo rows -2, -1 (waves 0, 1) and W, W+1
+    // (waves W-2, W-1)
+    const bool has2 = w < 2 || w >= W - 2;
+    const int j2 = w < 2 ? w - 2 : w + 2;
     XcdWalk walk(count);
     int si;
     while (walk.next(count, si)) {
@@ -67,79 +84,106 @@ __global__ void __launch_bounds__(W * 64) k_fv_strip3(View v, const Strip *__res
         const int64_t N = G.ncell;
         const int x = st.xb + lane;
         const int xc = bcmap(x, n, v.bc);
-        const int j = w - 2;   // this wave's row relative to the first output row
-        const int yc = bcmap(st.y0 + j, n, v.bc);
-        const bool live = j <= st.ny + 1;            // row loaded
-        const bool slope = j >= -1 && j <= st.ny;    // y face states needed
-        const bool face = j >= 0 && j <= st.ny;      // its lower y face flux needed
-        const bool outr = j >= 0 && j < st.ny;       // output row
+        const int ny = st.ny;
+        // roles of a row j (relative to the first output row): loaded, its y
+        // face values needed, its lower y face flux needed, output
+        const int j1 = w;
+        const bool live1 = j1 <= ny + 1, slope1 = j1 <= ny, face1 = j1 <= ny, outr = j1 < ny;
+        const bool live2 = has2 && j2 <= ny + 1, slope2 = has2 && j2 >= -1 && j2 <= ny;
+        const bool face2 = has2 && j2 >= 0 && j2 <= ny;
         const bool wr = outr && lane >= H && lane < 64 - H && x < n;
         const double dt = v.mode == MODE_BATCH ? v.dt[st.grid] : v.dt[0];
         const T lam = (T)((dt * fac) / G.dx);
         const T *S = src + G.off;
         const T *B = base + G.off;
         T *O = out + G.off;
-        const uint32_t rowoff = (uint32_t)xc + (uint32_t)n * (uint32_t)yc;
         const uint32_t nn = (uint32_t)n * (uint32_t)n;
-        T wa[NV], wb[NV], sp[NV], fl[NV], qa[NV], qb[NV];
+        const uint32_t off1 = (uint32_t)xc + (uint32_t)n * (uint32_t)bcmap(st.y0 + j1, n, v.bc);
+        const uint32_t off2 = (uint32_t)xc + (uint32_t)n * (uint32_t)bcmap(st.y0 + j2, n, v.bc);
+        Row3<T> A;                 // primary row
+        T wa2[NV], wb2[NV];        // second row's window
         double smax = 0.0;
         bool bad = false;
         for (int k = 0; k < st.nz + 4; ++k) {
             const int z = st.z0 - 2 + k;
-            T q[NV], wc[NV];
-            if (live) {
-                const uint32_t id = rowoff + nn * (uint32_t)bcmap(z, n, v.bc);
+            const uint32_t zo = nn * (uint32_t)bcmap(z, n, v.bc);
+            T q[NV], wc[NV], q2[NV], wc2[NV];
+            if (live1) {
 #pragma unroll
-                for (int f = 0; f < NV; ++f) q[f] = S[f * N + id];
-                cons2prim<T, 3>(q, wc, g);
+                for (int f = 0; f < NV; ++f) q[f] = S[f * N + off1 + zo];
             }
+            if (live2) {
+#pragma unroll
+                for (int f = 0; f < NV; ++f) q2[f] = S[f * N + off2 + zo];
+            }
+            if (live1) cons2prim<T, 3>(q, wc, g);
+            if (live2) cons2prim<T, 3>(q2, wc2, g);
             // z slope of plane wb; the z face between planes wa and wb
             T spn[NV], Fz[NV];
             if (outr && k >= 2) {
                 T sm[NV];
 #pragma unroll
                 for (int f = 0; f < NV; ++f) {
-                    const T sl = slope_va<T>(wa[f], wb[f], wc[f]);
-                    sm[f] = wb[f] - T(0.5) * sl;
-                    spn[f] = wb[f] + T(0.5) * sl;
+                    const T sl = slope_va<T>(A.wa[f], A.wb[f], wc[f]);
+                    sm[f] = A.wb[f] - T(0.5) * sl;
+                    spn[f] = A.wb[f] + T(0.5) * sl;
                 }
-                if (k >= 3) ausm_plus<T, 3>(g, gi, 2, sp, sm, Fz);
+                if (k >= 3) ausm_plus<T, 3>(g, gi, 2, A.sp, sm, Fz);
             }
             if (k >= 4) {
                 // plane wa (z - 2) is finished: y faces through LDS, x faces
                 // by lane shifts, the update
                 const int par = k & 1;
-                if (live)
+                if (live1)
 #pragma unroll
-                    for (int f = 0; f < NV; ++f) sW[par][w][f][lane] = wa[f];
+                    for (int f = 0; f < NV; ++f) sW[par][j1 + 2][f][lane] = A.wa[f];
+                if (live2)
+#pragma unroll
+                    for (int f = 0; f < NV; ++f) sW[par][j2 + 2][f][lane] = wa2[f];
                 __syncthreads();
-                T ym[NV];
-                if (slope) {
+                T ym1[NV], ym2[NV];
+                if (slope1) {
 #pragma unroll
                     for (int f = 0; f < NV; ++f) {
-                        const T sl = slope_va<T>(sW[par][w - 1][f][lane], wa[f], sW[par][w + 1][f][lane]);
-                        ym[f] = wa[f] - T(0.5) * sl;
-                        sP[w][f][lane] = wa[f] + T(0.5) * sl;
+                        const T sl = slope_va<T>(sW[par][j1 + 1][f][lane], A.wa[f], sW[par][j1 + 3][f][lane]);
+                        ym1[f] = A.wa[f] - T(0.5) * sl;
+                        sP[j1 + 2][f][lane] = A.wa[f] + T(0.5) * sl;
+                    }
+                }
+                if (slope2) {
+#pragma unroll
+                    for (int f = 0; f < NV; ++f) {
+                        const T sl = slope_va<T>(sW[par][j2 + 1][f][lane], wa2[f], sW[par][j2 + 3][f][lane]);
+                        ym2[f] = wa2[f] - T(0.5) * sl;
+                        sP[j2 + 2][f][lane] = wa2[f] + T(0.5) * sl;
                     }
                 }
                 __syncthreads();
                 T Fy[NV];
-                if (face) {
+                if (face1) {
                     T yl[NV];
 #pragma unroll
-                    for (int f = 0; f < NV; ++f) yl[f] = sP[w - 1][f][lane];
-                    ausm_plus<T, 3>(g, gi, 1, yl, ym, Fy);
+                    for (int f = 0; f < NV; ++f) yl[f] = sP[j1 + 1][f][lane];
+                    ausm_plus<T, 3>(g, gi, 1, yl, ym1, Fy);
 #pragma unroll
-                    for (int f = 0; f < NV; ++f) sW[par][w][f][lane] = Fy[f];
+                    for (int f = 0; f < NV; ++f) sW[par][j1 + 2][f][lane] = Fy[f];
+                }
+                if (face2) {
+                    T yl[NV], F2[NV];
+#pragma unroll
+                    for (int f = 0; f < NV; ++f) yl[f] = sP[j2 + 1][f][lane];
+                    ausm_plus<T, 3>(g, gi, 1, yl, ym2, F2);
+#pragma unroll
+                    for (int f = 0; f < NV; ++f) sW[par][j2 + 2][f][lane] = F2[f];
                 }
                 __syncthreads();
                 if (outr) {
                     T Rx[NV], qo[NV];
-                    strip_rx3<T>(g, gi, wa, Rx);
-                    const uint32_t ido = rowoff + nn * (uint32_t)(z - 2);
+                    strip_rx3<T>(g, gi, A.wa, Rx);
+                    const uint32_t ido = off1 + nn * (uint32_t)(z - 2);
                     if (own_base) {
 #pragma unroll
-                        for (int f = 0; f < NV; ++f) qo[f] = qa[f];
+                        for (int f = 0; f < NV; ++f) qo[f] = A.qa[f];
                     } else {
 #pragma unroll
                         for (int f = 0; f < NV; ++f) qo[f] = B[f * N + ido];
@@ -148,7 +192,7 @@ __global__ void __launch_bounds__(W * 64) k_fv_strip3(View v, const Strip *__res
                         T qn[NV];
 #pragma unroll
                         for (int f = 0; f < NV; ++f) {
-                            const T R = (Rx[f] + (sW[par][w + 1][f][lane] - Fy[f])) + (Fz[f] - fl[f]);
+                            const T R = (Rx[f] + (sW[par][j1 + 3][f][lane] - Fy[f])) + (Fz[f] - A.fl[f]);
                             qn[f] = qo[f] - lam * R;
                             O[f * N + ido] = qn[f];
                         }
@@ -158,16 +202,18 @@ __global__ void __launch_bounds__(W * 64) k_fv_strip3(View v, const Strip *__res
             }
             if (outr && k >= 3)
 #pragma unroll
-                for (int f = 0; f < NV; ++f) fl[f] = Fz[f];
+                for (int f = 0; f < NV; ++f) A.fl[f] = Fz[f];
             if (outr && k >= 2)
 #pragma unroll
-                for (int f = 0; f < NV; ++f) sp[f] = spn[f];
+                for (int f = 0; f < NV; ++f) A.sp[f] = spn[f];
 #pragma unroll
             for (int f = 0; f < NV; ++f) {
-                wa[f] = wb[f];
-                wb[f] = wc[f];
-                qa[f] = qb[f];
-                qb[f] = q[f];
+                A.wa[f] = A.wb[f];
+                A.wb[f] = wc[f];
+                A.qa[f] = A.qb[f];
+                A.qb[f] = q[f];
+                wa2[f] = wb2[f];
+                wb2[f] = wc2[f];
             }
         }
         if (outr) {
