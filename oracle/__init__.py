@@ -38,6 +38,10 @@ What pins each part (tests/test_oracle_pins.py, tests/test_oracle_adaptive.py):
 * MUSCL-Hancock + AUSMDV ......... exact Riemann solutions, second order on a smooth
                                    wave (fails without the half-step evolution),
                                    reduction to 1D, symmetry, conservation, free stream
+* gradient criterion (AMR) ....... independent numpy brute force of the indicators and
+                                   of the flags they give; strict threshold; density only
+                                   vs density and pressure; monotone in the thresholds;
+                                   adaptive runs: conservation, free stream, accuracy
 * local time stepping ............ one level = global step; eps = 0 = uniform substeps;
                                    conservation; a linear profile reproduced to rounding
                                    across refinement boundaries (pins the ghost times
@@ -98,6 +102,7 @@ def lib():
             "orc_ausmdv": (None, [C.c_int, C.c_double, C.c_int, dp, dp, dp]),
             "orc_phys_flux": (None, [C.c_int, C.c_double, C.c_int, dp, dp]),
             "orc_h_set_scheme": (C.c_int, [vp, C.c_int]),
+            "orc_h_set_criterion": (C.c_int, [vp, C.c_int, C.c_double]),
             "orc_restrict": (None, [C.c_int, C.c_int, C.c_int, dp, dp]),
             "orc_predict": (None, [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]),
             "orc_h_new": (vp, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -145,6 +150,7 @@ def lib():
 PLANT_NONE, PLANT_AUSM_AB, PLANT_PRED_ZSWAP, PLANT_LTS_THETA = 0, 1, 2, 3
 PLANT_AUSMDV_ALPHA, PLANT_HANCOCK_NOPRED = 4, 5
 SCHEME_MR, SCHEME_AMR = 0, 1
+CRIT_MR, CRIT_GRADIENT = 0, 1
 
 
 class planted:
@@ -275,7 +281,8 @@ class Hierarchy:
 
     def __init__(self, dim: int, levels: int, n0: int, bc: int = BC_TRANSMISSIVE,
                  gamma: float = 1.4, lo: float = 0.0, hi: float = 1.0, eps: float = 1e-3,
-                 eta: float = 0.8, pmin: int = 8, pmax: int = 32, scheme: int = SCHEME_MR):
+                 eta: float = 0.8, pmin: int = 8, pmax: int = 32, scheme: int = SCHEME_MR,
+                 criterion: int = CRIT_MR, eps_p: float = 0.0):
         self.dim, self.L, self.n0, self.bc = dim, levels, n0, bc
         self.gamma, self.lo, self.hi, self.eps, self.eta = gamma, lo, hi, eps, eta
         self.pmin, self.pmax = pmin, pmax
@@ -286,6 +293,9 @@ class Hierarchy:
         if lib().orc_h_set_scheme(self._h, scheme) != 0:
             raise ValueError("the AMR scheme runs on grids of one level")
         self.scheme = scheme
+        if lib().orc_h_set_criterion(self._h, criterion, eps_p) != 0:
+            raise ValueError("unknown refinement criterion")
+        self.criterion, self.eps_p = criterion, eps_p
         self.t = 0.0
 
     def __del__(self):

@@ -511,6 +511,9 @@ typedef struct {
     int no_reflux;       /* test-only planted mistake: skip the flux correction */
     int scheme;          /* 0: MR scheme (MUSCL, van Albada, AUSM+, midpoint RK2);
                             1: AMR scheme (MUSCL-Hancock, Minmod, AUSMDV), one level */
+    int crit;            /* refinement criterion: 0 MR details (Sec. 2.1), 1 the
+                            scaled-gradient indicators of the AMR method (Sec. 2.2) */
+    double eps_p;        /* criterion 1: pressure threshold (<= 0: density only) */
 } orc_h;
 
 static int64_t hN(const orc_h *h, int l) { return ncells(h->dim, h->n[l]); }
@@ -832,8 +835,54 @@ void orc_h_counts(orc_h *h, int64_t *leaves, int64_t *active)
  * prediction errors between consecutive levels).  A detail is significant
  * when it is not smaller than eps (hard thresholding; the same eps on every
  * level). */
+/* Refinement indicators of the AMR method (Sec. 2.2): a cell P of level l
+ * (in a patch of that level) is flagged when |w(P + a) - w(P)| > eps_w for
+ * one of its neighbours P + a, a in {0,1}^d other than 0, with w = rho
+ * (eps_rho = eps) and w = p (eps_p, when positive).  Neighbours outside the
+ * patches are ghost cells (filled first, by prediction); D receives the
+ * largest density difference. */
+static void h_gradient(orc_h *h)
+{
+    h_ghost(h, h->Q);
+    int dim = h->dim, nv = h->nv;
+    for (int l = 0; l < h->L - 1; ++l) {
+        int n = h->n[l];
+        int64_t N = hN(h, l);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            int p[3];
+            cdecode(dim, n, i, p);
+            h->D[l][i] = 0.0;
+            h->sig[l][i] = 0;
+            if (!h->act[l][i]) continue;
+            double q[NVMAX], w0[NVMAX];
+            for (int f = 0; f < nv; ++f) q[f] = h->Q[l][f * N + i];
+            cons2prim(dim, h->g, q, w0);
+            double dr = 0.0, dpm = 0.0;
+            int na = 1 << dim;
+            for (int a = 1; a < na; ++a) {
+                int c[3] = {bcmap(p[0] + (a & 1), n, h->bc), bcmap(p[1] + ((a >> 1) & 1), n, h->bc),
+                            dim == 3 ? bcmap(p[2] + ((a >> 2) & 1), n, h->bc) : 0};
+                double qa[NVMAX], wa[NVMAX];
+                int64_t j = cidx(n, c);
+                for (int f = 0; f < nv; ++f) qa[f] = h->Q[l][f * N + j];
+                cons2prim(dim, h->g, qa, wa);
+                double er = fabs(wa[0] - w0[0]), ep = fabs(wa[dim + 1] - w0[dim + 1]);
+                if (er > dr) dr = er;
+                if (ep > dpm) dpm = ep;
+            }
+            h->D[l][i] = dr;
+            h->sig[l][i] = dr > h->eps || (h->eps_p > 0.0 && dpm > h->eps_p);
+        }
+    }
+}
+
 static void h_details(orc_h *h)
 {
+    if (h->crit == 1) {
+        h_gradient(h);
+        return;
+    }
     for (int l = 0; l < h->L - 1; ++l) {
         int n = h->n[l], nf = h->n[l + 1];
         int64_t N = hN(h, l);
@@ -868,7 +917,7 @@ static int raw_flag(const orc_h *h, int l, const int *p)
 {
     int n = h->n[l];
     if (h->sig[l][cidx(n, p)]) return 1;
-    if (l >= 1) {
+    if (l >= 1 && h->crit == 0) {
         int q[3] = {p[0] / 2, p[1] / 2, p[2] / 2};
         if (h->sig[l - 1][cidx(h->n[l - 1], q)]) return 1;
     }
@@ -1120,6 +1169,18 @@ static void h_hancock(orc_h *h, double dt)
         }
     }
     memcpy(h->Q[0], h->Qs[0], sizeof(double) * (size_t)(nv * N));
+}
+
+/* Select the refinement criterion: 0 the MR details (Sec. 2.1), 1 the
+ * scaled-gradient indicators of the AMR method (Sec. 2.2) with the density
+ * threshold eps of the hierarchy and pressure threshold eps_p (<= 0: none).
+ * Returns 0, or -1 for an unknown criterion. */
+int orc_h_set_criterion(orc_h *h, int crit, double eps_p)
+{
+    if (crit != 0 && crit != 1) return -1;
+    h->crit = crit;
+    h->eps_p = eps_p;
+    return 0;
 }
 
 /* Select the finite-volume scheme: 0 the MR scheme, 1 the AMR scheme (grids
