@@ -60,6 +60,7 @@ enum { EU_DT_GLOBAL = 0, EU_DT_LTS = 1 };        /* time stepping           */
 enum { EU_RESTRICT = 0, EU_PROLONG = 1, EU_GHOST = 2 }; /* eu_project modes */
 enum { EU_IC_QUADRANT = 0, EU_IC_ELLIPSOID = 1, EU_IC_RIEMANN1D = 2, EU_IC_UNIFORM = 3 };
 enum { EU_SCHEME_MR = 0, EU_SCHEME_AMR = 1 };      /* finite-volume scheme     */
+enum { EU_CRIT_MR = 0, EU_CRIT_GRADIENT = 1 };     /* refinement criterion     */
 enum { EU_STAGE_SCHEDULES = 10, EU_STRIP_SCHEDULE0 = 6 }; /* see eu_autotune  */
 
 /* Problem size and method parameters (Sec. 2; Sec. 4 for the values used
@@ -95,6 +96,16 @@ typedef struct {
                             paper's AMR runs (Sec. 2) -- 2D grids of one
                             level (uniform grid or batch), strip schedules 6
                             and 7, one launch per step                        */
+    int criterion;       /* EU_CRIT_MR (0): MR details against eps with one
+                            level of preventive refinement (Sec. 2.1);
+                            EU_CRIT_GRADIENT: the AMR method's scaled-gradient
+                            indicators (Sec. 2.2): a cell of a level, in a
+                            patch of it, is flagged when |w(Q_{i+a}) -
+                            w(Q_i)| > eps_w for a neighbour i+a, a in {0,1}^d,
+                            w = rho (eps_w = eps) and w = p (eps_p);
+                            hierarchies (levels >= 2) only                    */
+    double eps_p;        /* EU_CRIT_GRADIENT: pressure threshold (<= 0: the
+                            density alone)                                    */
 } eu_config;
 
 /* Initial data (Sec. 4.1 four-quadrant Riemann problem, Sec. 4.2 ellipsoid,

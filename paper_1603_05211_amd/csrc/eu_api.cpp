@@ -132,6 +132,12 @@ int validate(const eu_config *c, std::string &why)
     if (!(c->cfl > 0.0)) { why = "cfl must be positive"; return EU_EINVAL; }
     if (c->time_mode != EU_DT_GLOBAL && c->time_mode != EU_DT_LTS) { why = "bad time_mode"; return EU_EINVAL; }
     if (c->scheme != EU_SCHEME_MR && c->scheme != EU_SCHEME_AMR) { why = "bad scheme"; return EU_EINVAL; }
+    if (c->criterion != EU_CRIT_MR && c->criterion != EU_CRIT_GRADIENT) { why = "bad criterion"; return EU_EINVAL; }
+    if (c->criterion == EU_CRIT_GRADIENT && (c->n_instances > 1 || c->levels < 2)) {
+        why = "the gradient criterion refines a hierarchy (levels >= 2)";
+        return EU_EINVAL;
+    }
+    if (std::isnan(c->eps_p)) { why = "eps_p is NaN"; return EU_EINVAL; }
     if (c->scheme == EU_SCHEME_AMR && (c->dim != 2 || (c->n_instances <= 1 && c->levels != 1))) {
         why = "the AMR scheme runs on 2D grids of one level (uniform grid or batch)";
         return EU_EINVAL;
@@ -523,12 +529,15 @@ void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
     }
 }
 
+// The refinement analysis of levels 0 .. L-2: MR details, or the gradient
+// indicators (which read ghost cells: the caller fills them first).
 void seq_details(eu_ctx *c)
 {
     if (c->L < 2) return;
     int64_t n = 0;
     for (int l = 0; l < c->L - 1; ++l) n += c->grids[l].ncell;
-    c->ks->details(c->v, n, c->stream);
+    if (c->v.crit == EU_CRIT_GRADIENT) c->ks->gradient(c->v, n, c->stream);
+    else c->ks->details(c->v, n, c->stream);
 }
 
 // Prediction launches of a regrid, coarse to fine, two levels per launch:
@@ -624,9 +633,11 @@ void seq_step(eu_ctx *c, bool regrid)
 {
     const bool rg = regrid && c->L > 1;
     seq_cfl(c);
+    const bool grad = c->v.crit == EU_CRIT_GRADIENT;
     if (c->v.lts) {
         lts_advance(c, 0, 0);
         if (rg) {
+            if (grad) seq_ghost(c, ARR_Q);
             seq_details(c);
             seq_flag_tile(c, true);
         } else {
@@ -634,7 +645,13 @@ void seq_step(eu_ctx *c, bool regrid)
         }
         return;
     }
-    seq_fv_step(c, !rg, rg);
+    if (grad && rg) {
+        // the indicators read ghost cells: the last projection fills them
+        seq_fv_step(c, true, false);
+        seq_details(c);
+    } else {
+        seq_fv_step(c, !rg, rg);
+    }
     if (rg) seq_flag_tile(c, true);
 }
 
@@ -949,6 +966,8 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.cfl = cfg->cfl;
     v.t_end = cfg->t_end;
     v.eps = cfg->eps;
+    v.crit = cfg->criterion;
+    v.eps_p = cfg->eps_p;
     v.eta = cfg->eta;
     const size_t es = cfg->precision == EU_FP64 ? 8 : 4;
     v.Q = state_dev;
@@ -1106,7 +1125,12 @@ int eu_mr_decompose(eu_ctx *c)
     if (!c->initialized) return set_err(c, EU_ESTATE, "not initialised");
     if (c->mode != MODE_HIER) return set_err(c, EU_EINVAL, "a batch has no hierarchy");
     cfl_stale(c);
-    if (!seq_restrict(c, ARR_Q, false, true)) seq_details(c);
+    if (c->v.crit == EU_CRIT_GRADIENT) {
+        if (!seq_restrict(c, ARR_Q, true, false)) seq_ghost(c, ARR_Q);
+        seq_details(c);
+    } else if (!seq_restrict(c, ARR_Q, false, true)) {
+        seq_details(c);
+    }
     return check_launch(c);
 }
 
@@ -1124,7 +1148,9 @@ int eu_mr_flag(eu_ctx *c, double eps, int64_t *nflag_host)
         drop_graphs(c);
         int64_t n = 0;
         for (int l = 0; l < c->L - 1; ++l) n += c->grids[l].ncell;
-        if (n > 0) launch_threshold(c->v, n, c->stream);
+        // the gradient indicators are evaluated again on the current state
+        if (c->v.crit == EU_CRIT_GRADIENT) seq_details(c);
+        else if (n > 0) launch_threshold(c->v, n, c->stream);
     }
     if (c->L > 1) seq_flag_tile(c, true);
     int r = check_launch(c);

@@ -1722,6 +1722,52 @@ __global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q
     }
 }
 
+// ----------------------------------------------------------------------------
+// the AMR method's refinement indicators (Sec. 2.2): scaled gradients of
+// density and pressure, every cell of levels 0 .. L-2 in a patch of its
+// level, one launch over the concatenated cells of those levels; ghost cells
+// must be filled.  D receives the largest density difference.
+// ----------------------------------------------------------------------------
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_gradient(View v, const T *__restrict__ Q, int64_t ntot)
+{
+#pragma clang fp contract(off)
+    const int done = v.meta->done;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ntot;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int lvl = 0;
+        for (int k = 1; k < MAXLEV && k < v.L - 1; ++k) lvl += j >= v.gt[k].coff ? 1 : 0;
+        const Grid G = grid_lane(v, lvl);
+        const int n = G.n;
+        const int64_t i = j - G.coff;
+        const int x = (int)(i % n), y = (int)((i / n) % n), z = D == 3 ? (int)(i / ((int64_t)n * n)) : 0;
+        const bool act = block_active(v, v.act, G, x, y, z);
+        issued((int)act);
+        if (done) return;
+        double dr = 0.0, dpm = 0.0;
+        if (act) {
+            const T *A = Q + G.off;
+            double q[D + 2], w0[D + 2];
+#pragma unroll
+            for (int f = 0; f < D + 2; ++f) q[f] = (double)A[f * G.ncell + i];
+            cons2prim<double, D>(q, w0, v.gamma);
+            for (int a = 1; a < (1 << D); ++a) {
+                const int64_t ja = gidx(n, bcmap(x + (a & 1), n, v.bc), bcmap(y + ((a >> 1) & 1), n, v.bc),
+                                        D == 3 ? bcmap(z + ((a >> 2) & 1), n, v.bc) : 0);
+                double qa[D + 2], wa[D + 2];
+#pragma unroll
+                for (int f = 0; f < D + 2; ++f) qa[f] = (double)A[f * G.ncell + ja];
+                cons2prim<double, D>(qa, wa, v.gamma);
+                const double er = __builtin_fabs(wa[0] - w0[0]), ep = __builtin_fabs(wa[D + 1] - w0[D + 1]);
+                if (er > dr) dr = er;
+                if (ep > dpm) dpm = ep;
+            }
+        }
+        v.D[j] = dr;
+        v.sig[j] = act && (dr > v.eps || (v.eps_p > 0.0 && dpm > v.eps_p)) ? 1 : 0;
+    }
+}
+
 }  // namespace eu
 
 #include "eu_strip.hpp"

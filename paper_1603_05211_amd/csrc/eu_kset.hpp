@@ -70,6 +70,7 @@ struct KSet {
     void (*cfl_slots)(const View &, int maxtiles, hipStream_t);     // into zero CFL slots / batch maxima
     void (*totals)(const View &, int maxtiles, hipStream_t);
     void (*details)(const View &, int64_t ncell_coarse_levels, hipStream_t);
+    void (*gradient)(const View &, int64_t ncell_coarse_levels, hipStream_t);
     void (*composite)(const View &, int lvl, int64_t ncell, hipStream_t);
 };
 

@@ -197,6 +197,13 @@ template <typename T> void details(const View &v, int64_t ncell, hipStream_t s)
     else k_details<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q, ncell);
 }
 
+template <typename T> void gradient(const View &v, int64_t ncell, hipStream_t s)
+{
+    const int nblk = clamp_grid((ncell + 255) / 256, 8192);
+    if (v.dim == 2) k_gradient<T, 2><<<nblk, 256, 0, s>>>(v, (const T *)v.Q, ncell);
+    else k_gradient<T, 3><<<nblk, 256, 0, s>>>(v, (const T *)v.Q, ncell);
+}
+
 template <typename T> KSet make()
 {
     KSet k;
@@ -216,6 +223,7 @@ template <typename T> KSet make()
     k.cfl_slots = cfl_slots<T>;
     k.totals = totals<T>;
     k.details = details<T>;
+    k.gradient = gradient<T>;
     return k;
 }
 

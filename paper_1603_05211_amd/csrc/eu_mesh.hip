@@ -181,7 +181,8 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
                 const int qz = D == 3 ? bcmap(o0[2] - 1 + ez, n, v.bc) : 0;
                 const uint8_t a = v.sig[G.coff + gidx(n, qx, qy, qz)];
                 const uint8_t b = v.sig[Cg.coff + gidx(Cg.n, qx >> 1, qy >> 1, qz >> 1)];
-                val[u] = a | (hasc ? b : 0);
+                // preventive refinement (MR criterion): the parent's significance
+                val[u] = a | (hasc && v.crit == 0 ? b : 0);
             } else if (it < IR + IN) {
                 const int i0 = threadIdx.x + (it - IR) * NT, i = i0 < NNEST ? i0 : NNEST - 1;
                 int b[3] = {i % NVB, (i / NVB) % NVB, D == 3 ? i / (NVB * NVB) : 0};

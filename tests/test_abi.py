@@ -138,3 +138,14 @@ def test_scheme_checks(kw):
     assert r == _abi.EU_EINVAL
     r, _, _ = sizes(cfg(scheme=1, levels=1, n0=64))
     assert r == _abi.EU_OK
+
+
+@pytest.mark.parametrize("kw", [dict(criterion=2), dict(criterion=1, levels=1), dict(criterion=1, eps_p=math.nan)])
+def test_criterion_checks(kw):
+    """The gradient criterion (Sec. 2.2) refines hierarchies only."""
+    base = dict(levels=4)
+    base.update(kw)
+    r, _, _ = sizes(cfg(**base))
+    assert r == _abi.EU_EINVAL
+    r, _, _ = sizes(cfg(criterion=1, levels=4, eps=0.05, eps_p=0.05))
+    assert r == _abi.EU_OK
