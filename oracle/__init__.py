@@ -148,7 +148,7 @@ def lib():
 
 
 PLANT_NONE, PLANT_AUSM_AB, PLANT_PRED_ZSWAP, PLANT_LTS_THETA = 0, 1, 2, 3
-PLANT_AUSMDV_ALPHA, PLANT_HANCOCK_NOPRED = 4, 5
+PLANT_AUSMDV_ALPHA, PLANT_HANCOCK_NOPRED, PLANT_NO_FINE_MEAN = 4, 5, 6
 SCHEME_MR, SCHEME_AMR = 0, 1
 CRIT_MR, CRIT_GRADIENT = 0, 1
 
@@ -291,7 +291,7 @@ class Hierarchy:
         if not self._h:
             raise ValueError("invalid hierarchy parameters")
         if lib().orc_h_set_scheme(self._h, scheme) != 0:
-            raise ValueError("the AMR scheme runs on grids of one level")
+            raise ValueError("unknown finite-volume scheme")
         self.scheme = scheme
         if lib().orc_h_set_criterion(self._h, criterion, eps_p) != 0:
             raise ValueError("unknown refinement criterion")
@@ -378,6 +378,8 @@ class Hierarchy:
         """One level-0 step with local time steps; returns (dt_0, leaf updates)."""
         upd = C.c_int64(0)
         dt = lib().orc_h_step_lts(self._h, cfl, self.t, t_end, int(regrid), C.byref(upd))
+        if dt == -2.0:
+            raise ValueError("local time steps run the MR scheme only")
         if dt < 0:
             raise MemoryError("oracle: local time stepping buffers")
         self.t = self.t + dt

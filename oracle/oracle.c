@@ -37,10 +37,12 @@ enum { BC_TRANSMISSIVE = 0, BC_PERIODIC = 1 };
  * 3 = ghost cells of local time stepping taken from the coarse state at the
  *     start of its step at every stage (constant theta = 0);
  * 4 = AUSMDV with its pressure-ratio weights alpha_L = alpha_R = 1;
- * 5 = MUSCL-Hancock without the half-step evolution of the face states.
+ * 5 = MUSCL-Hancock without the half-step evolution of the face states;
+ * 6 = a leaf next to a covered cell takes its own level's flux at that face
+ *     instead of the mean of the finer level's fluxes (global time step).
  * With 0 every result is the method's, bit for bit. */
 enum { PLANT_NONE = 0, PLANT_AUSM_AB = 1, PLANT_PRED_ZSWAP = 2, PLANT_LTS_THETA = 3,
-       PLANT_AUSMDV_ALPHA = 4, PLANT_HANCOCK_NOPRED = 5 };
+       PLANT_AUSMDV_ALPHA = 4, PLANT_HANCOCK_NOPRED = 5, PLANT_NO_FINE_MEAN = 6 };
 static int plant = PLANT_NONE;
 void orc_set_plant(int which) { plant = which; }
 
@@ -510,7 +512,7 @@ typedef struct {
     int npatch, cappatch;
     int no_reflux;       /* test-only planted mistake: skip the flux correction */
     int scheme;          /* 0: MR scheme (MUSCL, van Albada, AUSM+, midpoint RK2);
-                            1: AMR scheme (MUSCL-Hancock, Minmod, AUSMDV), one level */
+                            1: AMR scheme (MUSCL-Hancock, Minmod, AUSMDV), global dt */
     int crit;            /* refinement criterion: 0 MR details (Sec. 2.1), 1 the
                             scaled-gradient indicators of the AMR method (Sec. 2.2) */
     double eps_p;        /* criterion 1: pressure threshold (<= 0: density only) */
@@ -677,13 +679,23 @@ void orc_h_ghost(orc_h *h) { h_ghost(h, h->Q); }
 
 /* ---- the finite-volume update ---- */
 
+/* Face flux of the hierarchy's scheme at the face between cell c and
+ * c + e_dn of a level of n cells per side: the MR scheme's AUSM+ of the
+ * MUSCL face states, or the AMR scheme's AUSMDV of the evolved Hancock face
+ * values, hl = (dt / 2) / dx of that level (unused by the MR scheme). */
+static void level_flux(const orc_h *h, int n, const double *A, int dn, const int *c, double hl, double *F)
+{
+    if (h->scheme == 1) face_flux_hancock(h->dim, n, h->bc, h->g, A, dn, c, hl, F);
+    else face_flux(h->dim, n, h->bc, h->g, A, dn, c, F);
+}
+
 /* Flux across the face between coarse cell p (level l) and its covered
  * neighbour on side s (+1 / -1) of axis dn: the mean of the 2^(d-1) level
  * l+1 fluxes along that face, computed from level l+1 data (the virtual
  * leaves of Sec. 2.1, which keep the flux balance between levels
- * conservative). */
+ * conservative).  hlf: the AMR scheme's (dt / 2) / dx of level l+1. */
 static void flux_fine_mean(const orc_h *h, int l, double **src, int dn,
-                           const int *p, int s, double *F)
+                           const int *p, int s, double hlf, double *F)
 {
     int dim = h->dim, nf = h->n[l + 1], nv = h->nv;
     int t1 = dn == 0 ? 1 : 0, t2 = dn == 2 ? 1 : 2;
@@ -693,8 +705,8 @@ static void flux_fine_mean(const orc_h *h, int l, double **src, int dn,
         double Fa[NVMAX], Fb[NVMAX];
         int c0[3] = {base[0], base[1], 0}, c1[3] = {base[0], base[1], 0};
         c1[t1] += 1;
-        face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c0, Fa);
-        face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c1, Fb);
+        level_flux(h, nf, src[l + 1], dn, c0, hlf, Fa);
+        level_flux(h, nf, src[l + 1], dn, c1, hlf, Fb);
         for (int f = 0; f < nv; ++f) F[f] = 0.5 * (Fa[f] + Fb[f]);
         return;
     }
@@ -704,22 +716,25 @@ static void flux_fine_mean(const orc_h *h, int l, double **src, int dn,
     int c01[3] = {base[0], base[1], base[2]};
     int c11[3] = {base[0], base[1], base[2]};
     c10[t1] += 1; c01[t2] += 1; c11[t1] += 1; c11[t2] += 1;
-    face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c00, F00);
-    face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c10, F10);
-    face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c01, F01);
-    face_flux(dim, nf, h->bc, h->g, src[l + 1], dn, c11, F11);
+    level_flux(h, nf, src[l + 1], dn, c00, hlf, F00);
+    level_flux(h, nf, src[l + 1], dn, c10, hlf, F10);
+    level_flux(h, nf, src[l + 1], dn, c01, hlf, F01);
+    level_flux(h, nf, src[l + 1], dn, c11, hlf, F11);
     for (int f = 0; f < nv; ++f) F[f] = 0.25 * ((F00[f] + F10[f]) + (F01[f] + F11[f]));
 }
 
 /* One explicit stage on every leaf of level l:
  *   out = base - lam * ((dF_1 + dF_2) + dF_3),  dF_d = F_{+1/2} - F_{-1/2},
  * the semi-discrete form dQ/dt = -F(Q) of Sec. 2 with fluxes from src.
- * A face next to a covered cell takes the fine-flux mean (flux_fine_mean). */
+ * A face next to a covered cell takes the fine-flux mean (flux_fine_mean).
+ * dt: the step, for the AMR scheme's half-step predictor of each level. */
 static void h_fv_level(orc_h *h, int l, double **src, double **base,
-                       double **out, double lam)
+                       double **out, double lam, double dt)
 {
     int dim = h->dim, n = h->n[l], nv = h->nv;
     int64_t N = hN(h, l);
+    double hl = (dt * 0.5) / h->dx[l];
+    double hlf = l + 1 < h->L ? (dt * 0.5) / h->dx[l + 1] : 0.0;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < N; ++i) {
         int p[3];
@@ -730,17 +745,18 @@ static void h_fv_level(orc_h *h, int l, double **src, double **base,
             double Fhi[NVMAX], Flo[NVMAX];
             int nb[3] = {p[0], p[1], p[2]};
             nb[d] = bcmap(p[d] + 1, n, h->bc);
-            if (covered(h, (const uint8_t *const *)h->act, l, nb))
-                flux_fine_mean(h, l, src, d, p, +1, Fhi);
+            int fm = plant != PLANT_NO_FINE_MEAN;
+            if (fm && covered(h, (const uint8_t *const *)h->act, l, nb))
+                flux_fine_mean(h, l, src, d, p, +1, hlf, Fhi);
             else
-                face_flux(dim, n, h->bc, h->g, src[l], d, p, Fhi);
+                level_flux(h, n, src[l], d, p, hl, Fhi);
             nb[d] = bcmap(p[d] - 1, n, h->bc);
-            if (covered(h, (const uint8_t *const *)h->act, l, nb)) {
-                flux_fine_mean(h, l, src, d, p, -1, Flo);
+            if (fm && covered(h, (const uint8_t *const *)h->act, l, nb)) {
+                flux_fine_mean(h, l, src, d, p, -1, hlf, Flo);
             } else {
                 int lc[3] = {p[0], p[1], p[2]};
                 lc[d] = p[d] - 1;
-                face_flux(dim, n, h->bc, h->g, src[l], d, lc, Flo);
+                level_flux(h, n, src[l], d, lc, hl, Flo);
             }
             for (int f = 0; f < nv; ++f) dF[d][f] = Fhi[f] - Flo[f];
         }
@@ -1124,7 +1140,7 @@ static void h_stage(orc_h *h, double **src, double **out, double dt, double fac)
 {
     for (int l = 0; l < h->L; ++l) {
         double lam = (dt * fac) / h->dx[l];
-        h_fv_level(h, l, src, h->Q, out, lam);
+        h_fv_level(h, l, src, h->Q, out, lam, dt);
     }
     h_restrict(h, out);
 }
@@ -1140,35 +1156,29 @@ void orc_h_stage(orc_h *h, int stage, double dt)
     }
 }
 
-/* One step of the AMR scheme on a grid of one level (Sec. 2: MUSCL-Hancock,
- * a single corrector stage): Q^{n+1} = Q^n - (dt/dx) ((dF_1 + dF_2) + dF_3)
- * with the AUSMDV fluxes of the evolved face values; computed into the stage
- * array, then copied. */
+/* One step of the AMR scheme (Sec. 2: MUSCL-Hancock, a single corrector
+ * stage) on the leaves of every level:
+ *   Q^{n+1} = Q^n - (dt/dx) ((dF_1 + dF_2) + dF_3)
+ * with the AUSMDV fluxes of the evolved face values, a face next to a
+ * covered cell taking the mean of the finer level's fluxes; computed into
+ * the stage arrays, the leaves copied back, then projected onto the covered
+ * cells.
+ * Ghost cells are left for the caller to fill. */
 static void h_hancock(orc_h *h, double dt)
 {
-    int dim = h->dim, n = h->n[0], nv = h->nv;
-    int64_t N = hN(h, 0);
-    double lam = dt / h->dx[0], hl = (dt * 0.5) / h->dx[0];
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t i = 0; i < N; ++i) {
-        int p[3];
-        cdecode(dim, n, i, p);
-        double dF[3][NVMAX];
-        for (int d = 0; d < dim; ++d) {
-            double Fhi[NVMAX], Flo[NVMAX];
-            int lc[3] = {p[0], p[1], p[2]};
-            lc[d] = p[d] - 1;
-            face_flux_hancock(dim, n, h->bc, h->g, h->Q[0], d, p, hl, Fhi);
-            face_flux_hancock(dim, n, h->bc, h->g, h->Q[0], d, lc, hl, Flo);
-            for (int f = 0; f < nv; ++f) dF[d][f] = Fhi[f] - Flo[f];
-        }
-        for (int f = 0; f < nv; ++f) {
-            double R = dF[0][f] + dF[1][f];
-            if (dim == 3) R = R + dF[2][f];
-            h->Qs[0][f * N + i] = h->Q[0][f * N + i] - lam * R;
-        }
+    for (int l = 0; l < h->L; ++l)
+        h_fv_level(h, l, h->Q, h->Q, h->Qs, dt / h->dx[l], dt);
+    for (int l = 0; l < h->L; ++l) {
+        int64_t N = hN(h, l);
+        for (int64_t i = 0; i < N; ++i)
+            if (h->act[l][i]) {
+                int p[3];
+                cdecode(h->dim, h->n[l], i, p);
+                if (!is_leaf(h, l, p)) continue;
+                for (int f = 0; f < h->nv; ++f) h->Q[l][f * N + i] = h->Qs[l][f * N + i];
+            }
     }
-    memcpy(h->Q[0], h->Qs[0], sizeof(double) * (size_t)(nv * N));
+    h_restrict(h, h->Q);
 }
 
 /* Select the refinement criterion: 0 the MR details (Sec. 2.1), 1 the
@@ -1183,12 +1193,11 @@ int orc_h_set_criterion(orc_h *h, int crit, double eps_p)
     return 0;
 }
 
-/* Select the finite-volume scheme: 0 the MR scheme, 1 the AMR scheme (grids
- * of one level only).  Returns 0, or -1 when the scheme does not apply. */
+/* Select the finite-volume scheme: 0 the MR scheme, 1 the AMR scheme (global
+ * time steps only).  Returns 0, or -1 for an unknown scheme. */
 int orc_h_set_scheme(orc_h *h, int scheme)
 {
     if (scheme != 0 && scheme != 1) return -1;
-    if (scheme == 1 && h->L != 1) return -1;
     h->scheme = scheme;
     return 0;
 }
@@ -1196,12 +1205,19 @@ int orc_h_set_scheme(orc_h *h, int scheme)
 /* One global time step (Sec. 2: explicit second-order midpoint rule):
  *   Q* = Q^n - (dt/2) F(Q^n),   Q^{n+1} = Q^n - dt F(Q*),
  * on the leaves of every level, then the MR coarsening / refinement.
+ * The AMR scheme takes its single Hancock step instead, then fills the
+ * ghost cells (the refinement analysis reads them) before the regrid.
  * Returns dt.  When regrid is 0 the hierarchy is left as it is. */
 double orc_h_step(orc_h *h, double cfl, double t, double t_end, int regrid)
 {
     double dt = orc_h_cfl(h, cfl, t, t_end, NULL);
     if (h->scheme == 1) {
         h_hancock(h, dt);
+        h_ghost(h, h->Q);
+        if (regrid && h->L > 1) {
+            h_regrid(h, 1);
+            h_ghost(h, h->Q);
+        }
         return dt;
     }
     h_stage(h, h->Q, h->Qs, dt, 0.5);
@@ -1217,6 +1233,7 @@ void orc_h_step_fixed(orc_h *h, double dt)
 {
     if (h->scheme == 1) {
         h_hancock(h, dt);
+        h_ghost(h, h->Q);
         return;
     }
     h_stage(h, h->Q, h->Qs, dt, 0.5);
@@ -1389,10 +1406,12 @@ static void lts_advance(orc_h *h, int l, double dt, int k)
  * MRLT; Sec. 2.2, AMRLT): dt_0 = min over levels of (cfl dx_l / smax_l) 2^l
  * from the leaves, clipped to reach t_end; then the MR coarsening /
  * refinement when regrid is set and a spatial ghost fill.  Returns dt_0;
- * *leaf_updates receives sum over levels of leaves_l 2^l. */
+ * *leaf_updates receives sum over levels of leaves_l 2^l.  -1: out of
+ * memory; -2: the hierarchy runs the AMR scheme (not with local steps). */
 double orc_h_step_lts(orc_h *h, double cfl, double t, double t_end, int regrid,
                       int64_t *leaf_updates)
 {
+    if (h->scheme != 0) return -2.0;   /* the MR scheme's two-stage cycle only */
     if (lts_alloc(h)) return -1.0;
     double smax[MAXL];
     orc_h_cfl(h, cfl, t, t_end, smax);
