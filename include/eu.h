@@ -93,9 +93,15 @@ typedef struct {
                             midpoint RK2 (the paper's MR runs); EU_SCHEME_AMR:
                             unsplit MUSCL-Hancock with Minmod in primitive
                             variables and AUSMDV (Wada and Liou 1997), the
-                            paper's AMR runs (Sec. 2) -- 2D grids of one
-                            level (uniform grid or batch), strip schedules 6
-                            and 7, one launch per step                        */
+                            paper's AMR runs (Sec. 2) -- 2D, global time
+                            step; one launch per step: on grids of one level
+                            (uniform grid or batch) strip schedules 6 and 7,
+                            on hierarchies the Hancock tile kernel
+                            (schedules 0-2: 128, 192, 256 threads per tile),
+                            a face next to a covered cell taking the mean of
+                            the finer level's fluxes; the state alternates
+                            between the two state arrays (tracked by the
+                            library)                                          */
     int criterion;       /* EU_CRIT_MR (0): MR details against eps with one
                             level of preventive refinement (Sec. 2.1);
                             EU_CRIT_GRADIENT: the AMR method's scaled-gradient
@@ -310,7 +316,8 @@ int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
  * state arrays, which the library tracks); 6 and 8 with strips of 32 rows,
  * 7 and 9 of 128.  3D: one workgroup per strip of 8 output rows (6, 8) or
  * 16 (7, 9), one wave per row, marching through 32 (6, 7) or 64 (8, 9)
- * planes, y neighbours through LDS; one stage per launch.  In FP64 every schedule gives bit-identical results; in
+ * planes, y neighbours through LDS; one stage per launch.  The AMR scheme
+ * takes the schedules its scheme field names.  In FP64 every schedule gives bit-identical results; in
  * FP32 they agree to rounding (the compiler contracts each differently).
  * eu_autotune times each schedule that applies (reps passes of one step's
  * finite-volume work on the current state -- both stages, the second in

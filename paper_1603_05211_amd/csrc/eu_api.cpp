@@ -138,8 +138,9 @@ int validate(const eu_config *c, std::string &why)
         return EU_EINVAL;
     }
     if (std::isnan(c->eps_p)) { why = "eps_p is NaN"; return EU_EINVAL; }
-    if (c->scheme == EU_SCHEME_AMR && (c->dim != 2 || (c->n_instances <= 1 && c->levels != 1))) {
-        why = "the AMR scheme runs on 2D grids of one level (uniform grid or batch)";
+    if (c->scheme == EU_SCHEME_AMR && c->dim != 2) { why = "the AMR scheme runs in 2D"; return EU_EINVAL; }
+    if (c->scheme == EU_SCHEME_AMR && c->time_mode == EU_DT_LTS) {
+        why = "the AMR scheme runs with a global time step";
         return EU_EINVAL;
     }
     if (c->time_mode == EU_DT_LTS && c->n_instances > 1) { why = "a batch has no levels to step locally"; return EU_EINVAL; }
@@ -512,6 +513,21 @@ void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
         c->cfl_state = CFL_READY;
         return;
     }
+    if (c->cfg.scheme == EU_SCHEME_AMR) {
+        // the AMR scheme on a 2D hierarchy: one Hancock launch (Q -> Qs; the
+        // finest tiles also project onto level L-2), the state moves to the
+        // other array, the projection and the ghost fill (the refinement
+        // analysis reads ghost cells), then the details
+        hipEvent_t e;
+        prof_begin(c, &e);
+        c->ks->hancock_tile(c->v, c->variant, 1, c->state_elems, c->max_tiles, c->stream);
+        prof_end(c, e);
+        std::swap(c->v.Q, c->v.Qs);
+        c->qswap ^= 1;
+        if (!seq_restrict(c, ARR_Q, true, false, true)) seq_ghost(c, ARR_Q);
+        if (details) seq_details(c);
+        return;
+    }
     // 2D hierarchy: the stage kernel also projects its finest tiles onto
     // level L-2
     const bool fine = c->dim == 2 && c->mode == MODE_HIER && c->L >= 2;
@@ -670,11 +686,13 @@ void drop_graphs(eu_ctx *c)
 
 // Whether schedule var applies to this context: the strip schedules need a
 // 2D grid of one level (a uniform grid or a batch), the fused ones outflow
-// boundaries.
+// boundaries; the AMR scheme runs the Hancock strips on grids of one level
+// and the Hancock tile kernel (schedules 0-2) on hierarchies.
 bool variant_ok(const eu_ctx *c, int var)
 {
     if (var < 0 || var >= FV_VARIANTS) return false;
-    if (c->cfg.scheme == EU_SCHEME_AMR) return strip_variant(var) && !strip_fused(var);
+    if (c->cfg.scheme == EU_SCHEME_AMR)
+        return c->L > 1 ? var < HANCOCK_TILE_VARIANTS : strip_variant(var) && !strip_fused(var);
     if (!strip_variant(var)) return true;
     if (c->L != 1) return false;
     if (c->dim == 3) return true;
@@ -730,6 +748,9 @@ void fv_pass(eu_ctx *c, int var, int *launches)
         c->ks->fv_strip3(c->v, wv, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
         c->ks->fv_strip3(c->v, wv, 0, 2, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
         *launches = 2;
+    } else if (c->cfg.scheme == EU_SCHEME_AMR && c->L > 1) {
+        c->ks->hancock_tile(c->v, var, 1, c->state_elems, c->max_tiles, c->stream);
+        *launches = 1;
     } else if (c->cfg.scheme == EU_SCHEME_AMR) {
         c->ks->hancock_strip(c->v, 2, c->strips, c->nstrips, c->v.Q, c->v.Qs, c->stream);
         *launches = 1;
@@ -1058,9 +1079,10 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
         delete c;
         return EU_EHIP;
     }
-    // the AMR scheme runs on the strip kernels only
+    // the AMR scheme runs on the Hancock strip kernel (grids of one level)
+    // or the Hancock tile kernel (hierarchies)
     if (cfg->scheme == EU_SCHEME_AMR) {
-        c->variant = FV_STRIP0;
+        c->variant = c->L > 1 ? 0 : FV_STRIP0;
         if ((r = strips_for(c, c->variant))) {
             delete c;
             return r;
@@ -1247,8 +1269,8 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
         // move it to the other array every step); recording a step changes
         // only host bookkeeping, which is restored after each capture (the
         // CFL slots are left by a step as the lines above prepare them)
-        const bool alt = strip_variant(c->variant) && c->dim == 2 &&
-                         (strip_fused(c->variant) || c->cfg.scheme == EU_SCHEME_AMR);
+        const bool alt = c->cfg.scheme == EU_SCHEME_AMR ||
+                         (strip_variant(c->variant) && c->dim == 2 && strip_fused(c->variant));
         for (int p = 0; p < (alt ? 2 : 1); ++p) {
             const int q = c->qswap ^ p;
             if (c->gexec[q]) continue;

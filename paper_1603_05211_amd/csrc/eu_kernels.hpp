@@ -1772,3 +1772,4 @@ __global__ void __launch_bounds__(256) k_gradient(View v, const T *__restrict__ 
 
 #include "eu_strip.hpp"
 #include "eu_strip3.hpp"
+#include "eu_hancock.hpp"

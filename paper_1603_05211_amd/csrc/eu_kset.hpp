@@ -36,6 +36,9 @@ inline int strip3_waves(int var) { return (var - FV_STRIP0) % 2 ? 16 : 8; }
 inline int strip3_planes(int var) { return var >= FV_STRIP0 + 2 ? 64 : 32; }
 inline int strip_width(bool fused) { return fused ? 56 : 60; }   // columns written per strip
 inline int strip_halo(bool fused) { return fused ? 4 : 2; }
+// The AMR scheme on a 2D hierarchy runs the Hancock tile kernel: schedules
+// 0, 1, 2 with 128, 192, 256 threads per tile.
+constexpr int HANCOCK_TILE_VARIANTS = 3;
 
 struct KSet {
     size_t elem;  // bytes per state value
@@ -65,6 +68,9 @@ struct KSet {
     // the AMR scheme's MUSCL-Hancock step over count strips (src -> out)
     void (*hancock_strip)(const View &, int cfl, const Strip *list, int count, const void *src, void *out,
                           hipStream_t);
+    // the AMR scheme's MUSCL-Hancock step on every leaf of a 2D hierarchy
+    // (Q -> Qs; past t_end the whole state of nstate elements is copied)
+    void (*hancock_tile)(const View &, int variant, int fineproj, int64_t nstate, int maxtiles, hipStream_t);
     void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*cfl_slots)(const View &, int maxtiles, hipStream_t);     // into zero CFL slots / batch maxima

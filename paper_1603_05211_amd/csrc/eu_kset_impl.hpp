@@ -150,6 +150,19 @@ template <typename T> void hancock_strip(const View &v, int cfl, const Strip *li
     k_hancock_strip<T><<<nblk, 256, 0, s>>>(v, list, count, (const T *)src, (T *)out, cfl);
 }
 
+template <typename T> void hancock_tile(const View &v, int variant, int fineproj, int64_t nstate, int maxt,
+                                        hipStream_t s)
+{
+    const int nblk = xcd_grid(maxt, 2048);
+    const T *src = (const T *)v.Q;
+    T *out = (T *)v.Qs;
+    switch (variant) {
+    case 1: k_hancock_tile<T, 192><<<nblk, 192, 0, s>>>(v, src, out, fineproj, nstate); break;
+    case 2: k_hancock_tile<T, 256><<<nblk, 256, 0, s>>>(v, src, out, fineproj, nstate); break;
+    default: k_hancock_tile<T, 128><<<nblk, 128, 0, s>>>(v, src, out, fineproj, nstate); break;
+    }
+}
+
 template <typename T> void copy_level(const View &v, int lvl, int maxb, hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 2048);
@@ -217,6 +230,7 @@ template <typename T> KSet make()
     k.fv_stage = fv_stage<T>;
     k.fv_strip = fv_strip<T>;
     k.hancock_strip = hancock_strip<T>;
+    k.hancock_tile = hancock_tile<T>;
     k.fv_strip3 = fv_strip3<T>;
     k.copy_level = copy_level<T>;
     k.reflux = reflux<T>;

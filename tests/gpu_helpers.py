@@ -63,12 +63,14 @@ def state_errors(h, s, which=0):
 
 
 def make_pair(dim, levels, n0, precision=EU_FP64, bc=0, eps=1e-3, lo=None, hi=None, cfl=0.45,
-              t_end=math.inf, pmax=32, lts=False):
+              t_end=math.inf, pmax=32, lts=False, scheme=0, criterion=0, eps_p=0.0):
     lo = (0.0 if dim == 2 else -1.0) if lo is None else lo
     hi = 1.0 if hi is None else hi
-    h = orc.Hierarchy(dim, levels, n0, bc=bc, lo=lo, hi=hi, eps=eps, pmax=pmax)
+    h = orc.Hierarchy(dim, levels, n0, bc=bc, lo=lo, hi=hi, eps=eps, pmax=pmax, scheme=scheme,
+                      criterion=criterion, eps_p=eps_p)
     s = Solver(dim, n0=n0, levels=levels, precision=precision, bc=bc, cfl=cfl, t_end=t_end, eps=eps,
-               lo=lo, hi=hi, patch_max=pmax, time_mode=EU_DT_LTS if lts else EU_DT_GLOBAL)
+               lo=lo, hi=hi, patch_max=pmax, time_mode=EU_DT_LTS if lts else EU_DT_GLOBAL, scheme=scheme,
+               criterion=criterion, eps_p=eps_p)
     h.cfl_number = cfl
     h.lts = lts
     return h, s

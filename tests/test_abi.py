@@ -129,15 +129,18 @@ def test_method_calls_take_their_arguments():
         assert decl in text, decl
 
 
-@pytest.mark.parametrize("kw", [dict(scheme=2), dict(scheme=1, levels=3), dict(scheme=1, dim=3, n0=32, levels=1)])
+@pytest.mark.parametrize("kw", [dict(scheme=2), dict(scheme=1, levels=3, time_mode=1),
+                                dict(scheme=1, dim=3, n0=32, levels=1)])
 def test_scheme_checks(kw):
-    """The AMR scheme (MUSCL-Hancock, AUSMDV) runs on 2D grids of one level."""
+    """The AMR scheme (MUSCL-Hancock, AUSMDV) runs in 2D with a global time
+    step: on grids of one level and on hierarchies."""
     base = dict(levels=1, n0=64)
     base.update(kw)
     r, _, _ = sizes(cfg(**base))
     assert r == _abi.EU_EINVAL
-    r, _, _ = sizes(cfg(scheme=1, levels=1, n0=64))
-    assert r == _abi.EU_OK
+    for ok in (dict(levels=1, n0=64), dict(levels=5, n0=32)):
+        r, _, _ = sizes(cfg(scheme=1, **ok))
+        assert r == _abi.EU_OK
 
 
 @pytest.mark.parametrize("kw", [dict(criterion=2), dict(criterion=1, levels=1), dict(criterion=1, eps_p=math.nan)])

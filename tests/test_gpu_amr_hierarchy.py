@@ -1,0 +1,122 @@
+"""The AMR scheme (Sec. 2: unsplit MUSCL-Hancock, Minmod, AUSMDV) on 2D
+adaptive hierarchies on the GPU (Hancock tile kernel, global time step)
+against the FP64 oracle on identical seeded inputs: FP64 bit for bit with
+either refinement criterion, every tile schedule, periodic boundaries,
+graph replays past t_end (the state alternates between the two arrays);
+FP32 on the five-level benchmark hierarchy within the FP32 bounds."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1603_05211_amd import EU_CRIT_GRADIENT, EU_CRIT_MR, EU_FP32, EU_SCHEME_AMR, EU_STAGE_SCHEDULES, EuError
+
+from gpu_helpers import compare_masks, init_pair, make_pair, run_pair, say, state_errors
+
+pytestmark = pytest.mark.gpu
+
+TILE_SCHEDULES = [0, 1, 2]
+
+
+def check_fp64(h, s):
+    compare_masks(h, s)
+    linf, _ = state_errors(h, s)
+    say("  linf", linf)
+    assert linf.max() <= 1e-12
+    assert np.allclose(s.conserved_totals(), h.totals(), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("var", TILE_SCHEDULES)
+@pytest.mark.parametrize("seed", [0, 3])
+def test_mr_criterion_fp64(var, seed):
+    say("amr hierarchy fp64 mr criterion schedule", var, "seed", seed)
+    h, s = make_pair(2, 3, 32, eps=1e-3, scheme=EU_SCHEME_AMR)
+    init_pair(h, s, "quadrant", seed)
+    s.set_variant(var)
+    compare_masks(h, s)
+    do, dg = run_pair(h, s, 24)
+    assert np.array_equal(do, dg)
+    check_fp64(h, s)
+
+
+@pytest.mark.parametrize("levels,n0", [(3, 32), (4, 16)])
+def test_gradient_criterion_fp64(levels, n0):
+    """The AMR method proper: AMR scheme and scaled-gradient criterion."""
+    say("amr hierarchy fp64 gradient criterion", levels, n0)
+    h, s = make_pair(2, levels, n0, eps=0.05, scheme=EU_SCHEME_AMR, criterion=EU_CRIT_GRADIENT, eps_p=0.05)
+    init_pair(h, s, "quadrant", 5)
+    compare_masks(h, s)
+    do, dg = run_pair(h, s, 20)
+    assert np.array_equal(do, dg)
+    check_fp64(h, s)
+
+
+def test_periodic_fp64():
+    say("amr hierarchy fp64 periodic")
+    h, s = make_pair(2, 3, 32, bc=orc.BC_PERIODIC, eps=1e-3, scheme=EU_SCHEME_AMR)
+    init_pair(h, s, "quadrant", 6)
+    do, dg = run_pair(h, s, 16)
+    assert np.array_equal(do, dg)
+    check_fp64(h, s)
+
+
+def test_graph_replays_past_t_end():
+    """Graph replays (two graphs, one per state array) run to t_end and on:
+    the steps past t_end leave the state as it was."""
+    say("amr hierarchy fp64 graph past t_end")
+    t_end = 0.03
+    h, s = make_pair(2, 3, 32, eps=1e-3, scheme=EU_SCHEME_AMR, t_end=t_end)
+    init_pair(h, s, "quadrant", 2)
+    steps = 0
+    while h.t < t_end:
+        h.step(0.45, t_end)
+        steps += 1
+    done = s.advance(steps + 7, use_graph=True)
+    say("  oracle steps", steps, "gpu", done, "t", s.time()[0])
+    assert done == steps and s.time()[0] == t_end
+    check_fp64(h, s)
+    # once more, with an odd number of replays past the end
+    assert s.advance(3, use_graph=True) == 0
+    check_fp64(h, s)
+
+
+def test_schedules_and_autotune():
+    h, s = make_pair(2, 3, 32, eps=1e-3, scheme=EU_SCHEME_AMR)
+    init_pair(h, s, "quadrant", 0)
+    for var in range(EU_STAGE_SCHEDULES):
+        if var in TILE_SCHEDULES:
+            s.set_variant(var)
+        else:
+            with pytest.raises(EuError):
+                s.set_variant(var)
+    var, ms = s.autotune(reps=3)
+    assert var in TILE_SCHEDULES
+    assert all((m < math.inf) == (i in TILE_SCHEDULES) for i, m in enumerate(ms))
+    _, cells, nl = s.stage_time(reps=3)
+    leaves, _ = s.counters()
+    assert cells == int(leaves.sum()) and nl == 1
+
+
+def test_headline_hierarchy_fp32_against_oracle():
+    """The five-level benchmark hierarchy (32^2 .. 512^2, eps 1e-3) with the
+    AMR scheme in FP32 for 60 steps against the FP64 oracle: every field's
+    L1 (relative to the density's) within 1e-5 and normwise L-inf within
+    2e-3 on the composite, flag disagreements at most 2 % per level."""
+    say("amr hierarchy fp32 headline 60 steps")
+    h, s = make_pair(2, 5, 32, precision=EU_FP32, eps=1e-3, scheme=EU_SCHEME_AMR)
+    init_pair(h, s, "quadrant", 0)
+    for _ in range(60):
+        h.step(0.45)
+    assert s.advance(60, use_graph=True) == 60
+    g, o = s.composite(), h.composite()
+    scale = np.abs(o[0]).sum()
+    l1 = [float(np.abs(g[f] - o[f]).sum() / scale) for f in range(4)]
+    linf = [float(np.abs(g[f] - o[f]).max() / np.abs(o[f]).max()) for f in range(4)]
+    say("  L1 rel", l1, "Linf rel", linf)
+    assert max(l1) <= 1e-5 and max(linf) <= 2e-3
+    for l in range(h.L - 1):
+        fo, fg = h.flags(l).astype(bool), s.flags(l).astype(bool)
+        dis = int((fo != fg).sum())
+        say(f"  level {l}: flagged {int(fo.sum())}, disagreements {dis}")
+        assert dis <= max(2, 0.02 * fo.sum())
