@@ -17,6 +17,10 @@ run to t = 0.25, FP32 state and flux with FP64 CFL / totals / threshold.
 Every result carries its error against the FP64 oracle (or the FP64 path,
 where the oracle cannot run the workload in minutes).
 
+Context lines also time the AMR method (AMR scheme with the scaled-gradient
+criterion, eps_rho = 0.05) on the same five-level hierarchy and the AMR
+scheme on the batch and the 128^2 grid.
+
 Other workloads (--workload): ellip3d_adaptive4_lts (3D, 4 levels, local time
 stepping, to t = 0.2), ellip3d_uniform256 (200 steps), quad2d_batch512 (512
 instances, 100 steps, one launch per stage for all), quad2d_uniform128 (100
@@ -50,7 +54,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}      # MI355X vector peaks
 HBM_PEAK_GBS = 8000.0
 FV_SOURCES = ["paper_1603_05211_amd/csrc/eu_kernels.hpp", "paper_1603_05211_amd/csrc/eu_kset_impl.hpp",
               "paper_1603_05211_amd/csrc/eu_internal.hpp", "paper_1603_05211_amd/csrc/eu_strip.hpp",
-              "paper_1603_05211_amd/csrc/eu_strip3.hpp"]
+              "paper_1603_05211_amd/csrc/eu_strip3.hpp", "paper_1603_05211_amd/csrc/eu_hancock.hpp"]
 METRIC = "cell-updates/s (FP32 batched vs FP64 plain) at stated L1 err; % HBM roofline"
 
 WORKLOADS = {
@@ -79,10 +83,18 @@ class Run:
     """A workload on the library: the solver and how to (re)initialise it."""
 
     def __init__(self, workload, precision, seed=0, scheme=0):
-        from paper_1603_05211_amd import EU_DT_LTS, EU_FP32, EU_FP64, Solver, inputs
+        from paper_1603_05211_amd import EU_CRIT_GRADIENT, EU_DT_LTS, EU_FP32, EU_FP64, Solver, inputs
         self.workload, self.precision, self.scheme = workload, precision, scheme
         prec = EU_FP32 if precision == "fp32" else EU_FP64
-        if workload == "quad2d_adaptive5":
+        if workload == "quad2d_adaptive5" and scheme == 1:
+            # the AMR method on the same hierarchy: AMR scheme and the
+            # scaled-gradient criterion on density (the paper's 2D eps_rho)
+            s = Solver(2, n0=32, levels=5, precision=prec, cfl=0.45, t_end=0.25, eps=0.05, eta=0.8,
+                       patch_min=8, patch_max=32, scheme=1, criterion=EU_CRIT_GRADIENT)
+            prim = inputs.quadrant_states(seed)
+            self.init = lambda: s.init_quadrant(prim)
+            self.dim = 2
+        elif workload == "quad2d_adaptive5":
             s = Solver(2, n0=32, levels=5, precision=prec, cfl=0.45, t_end=0.25, eps=1e-3, eta=0.8,
                        patch_min=8, patch_max=32)
             prim = inputs.quadrant_states(seed)
@@ -122,10 +134,10 @@ class Run:
 
     def kernel(self):
         """The finite-volume kernel the chosen schedule launches."""
+        if self.scheme == 1:
+            return "k_hancock_tile" if self.variant is None or self.variant < 6 else "k_hancock_strip"
         if self.variant is None or self.variant < 6:
             return "k_fv_stage"
-        if self.scheme == 1:
-            return "k_hancock_strip"
         return "k_fv_strip3" if self.dim == 3 else "k_fv_strip"
 
     def flops_per_cell_stage(self):
@@ -530,6 +542,11 @@ def main():
                          "(tests/test_gpu_parity.py)"}
         ex["ellip3d_adaptive4_lts_fp32"] = extra_line("ellip3d_adaptive4_lts", "fp32", 1)
         ex["quad2d_uniform128_fp64"] = extra_line("quad2d_uniform128", "fp64", 3, after=uniform128_error)
+        ex["quad2d_adaptive5_amr_fp32"] = extra_line("quad2d_adaptive5", "fp32", 2, scheme=1)
+        ex["quad2d_adaptive5_amr_fp32"]["accuracy"] = {
+            "reference": "FP64 oracle on the same hierarchy: FP64 bit for bit on 3- and 4-level runs, FP32 "
+                         "L1 <= 1e-5 and no flag disagreement over 60 steps of this hierarchy "
+                         "(tests/test_gpu_amr_hierarchy.py)"}
         ex["quad2d_batch512_amr_fp32"] = extra_line("quad2d_batch512", "fp32", 2, scheme=1,
                                                     after=lambda rr: batch_error(rr, scheme=1))
         ex["quad2d_uniform128_amr_fp64"] = extra_line("quad2d_uniform128", "fp64", 3, scheme=1,

@@ -94,12 +94,12 @@ typedef struct {
                             unsplit MUSCL-Hancock with Minmod in primitive
                             variables and AUSMDV (Wada and Liou 1997), the
                             paper's AMR runs (Sec. 2) -- 2D, global time
-                            step; one launch per step: on grids of one level
-                            (uniform grid or batch) strip schedules 6 and 7,
-                            on hierarchies the Hancock tile kernel
-                            (schedules 0-2: 128, 192, 256 threads per tile),
-                            a face next to a covered cell taking the mean of
-                            the finer level's fluxes; the state alternates
+                            step; one launch per step: the Hancock tile
+                            kernel (schedules 0-2: 128, 192, 256 threads per
+                            tile; hierarchies and uniform grids), a face next
+                            to a covered cell taking the mean of the finer
+                            level's fluxes, or the Hancock strips (schedules
+                            6 and 7; uniform grids and batches); the state alternates
                             between the two state arrays (tracked by the
                             library)                                          */
     int criterion;       /* EU_CRIT_MR (0): MR details against eps with one

@@ -475,6 +475,23 @@ void prof_end(eu_ctx *c, hipEvent_t e1)
 void seq_details(eu_ctx *c);
 void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
 {
+    if (c->cfg.scheme == EU_SCHEME_AMR && !strip_variant(c->variant)) {
+        // the AMR scheme on the tile kernel (2D hierarchy or uniform grid):
+        // one Hancock launch (Q -> Qs; the finest tiles also project onto
+        // level L-2), the state moves to the other array, the projection
+        // and the ghost fill (the refinement analysis reads ghost cells),
+        // then the details
+        hipEvent_t e;
+        const bool fine = c->L >= 2;
+        prof_begin(c, &e);
+        c->ks->hancock_tile(c->v, c->variant, fine ? 1 : 0, c->state_elems, c->max_tiles, c->stream);
+        prof_end(c, e);
+        std::swap(c->v.Q, c->v.Qs);
+        c->qswap ^= 1;
+        if (fine && !seq_restrict(c, ARR_Q, true, false, true)) seq_ghost(c, ARR_Q);
+        if (details) seq_details(c);
+        return;
+    }
     if (strip_variant(c->variant)) {
         // one 2D level (uniform grid or batch): no projection, ghost fill or
         // details; the fused form and the AMR scheme leave the new state in
@@ -511,21 +528,6 @@ void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
             prof_end(c, e);
         }
         c->cfl_state = CFL_READY;
-        return;
-    }
-    if (c->cfg.scheme == EU_SCHEME_AMR) {
-        // the AMR scheme on a 2D hierarchy: one Hancock launch (Q -> Qs; the
-        // finest tiles also project onto level L-2), the state moves to the
-        // other array, the projection and the ghost fill (the refinement
-        // analysis reads ghost cells), then the details
-        hipEvent_t e;
-        prof_begin(c, &e);
-        c->ks->hancock_tile(c->v, c->variant, 1, c->state_elems, c->max_tiles, c->stream);
-        prof_end(c, e);
-        std::swap(c->v.Q, c->v.Qs);
-        c->qswap ^= 1;
-        if (!seq_restrict(c, ARR_Q, true, false, true)) seq_ghost(c, ARR_Q);
-        if (details) seq_details(c);
         return;
     }
     // 2D hierarchy: the stage kernel also projects its finest tiles onto
@@ -686,13 +688,16 @@ void drop_graphs(eu_ctx *c)
 
 // Whether schedule var applies to this context: the strip schedules need a
 // 2D grid of one level (a uniform grid or a batch), the fused ones outflow
-// boundaries; the AMR scheme runs the Hancock strips on grids of one level
-// and the Hancock tile kernel (schedules 0-2) on hierarchies.
+// boundaries; the AMR scheme runs the Hancock tile kernel (schedules 0-2)
+// on hierarchies and uniform grids, the Hancock strips (6, 7) on uniform
+// grids and batches.
 bool variant_ok(const eu_ctx *c, int var)
 {
     if (var < 0 || var >= FV_VARIANTS) return false;
-    if (c->cfg.scheme == EU_SCHEME_AMR)
-        return c->L > 1 ? var < HANCOCK_TILE_VARIANTS : strip_variant(var) && !strip_fused(var);
+    if (c->cfg.scheme == EU_SCHEME_AMR) {
+        const bool tile = var < HANCOCK_TILE_VARIANTS, strip = strip_variant(var) && !strip_fused(var);
+        return c->mode == MODE_BATCH ? strip : c->L > 1 ? tile : tile || strip;
+    }
     if (!strip_variant(var)) return true;
     if (c->L != 1) return false;
     if (c->dim == 3) return true;
@@ -748,8 +753,8 @@ void fv_pass(eu_ctx *c, int var, int *launches)
         c->ks->fv_strip3(c->v, wv, 1, 0, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 0.5, c->stream);
         c->ks->fv_strip3(c->v, wv, 0, 2, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
         *launches = 2;
-    } else if (c->cfg.scheme == EU_SCHEME_AMR && c->L > 1) {
-        c->ks->hancock_tile(c->v, var, 1, c->state_elems, c->max_tiles, c->stream);
+    } else if (c->cfg.scheme == EU_SCHEME_AMR && !strip_variant(var)) {
+        c->ks->hancock_tile(c->v, var, c->L >= 2 ? 1 : 0, c->state_elems, c->max_tiles, c->stream);
         *launches = 1;
     } else if (c->cfg.scheme == EU_SCHEME_AMR) {
         c->ks->hancock_strip(c->v, 2, c->strips, c->nstrips, c->v.Q, c->v.Qs, c->stream);

@@ -8,9 +8,9 @@ average number of cells of the whole hierarchy, and of leaves, over the
 time steps, per cell of the finest uniform grid), CPU-time compression and
 the overhead per leaf, Gamma^a / Gamma^FV - 1.  This module computes the same
 measures with the library: the reference is a uniform FP64 run of the AMR
-scheme on a fine grid, as in Sec. 4.1; the adaptive runs use the MR
-criterion (details against eps) or the AMR method's gradient criterion,
-with global or local time steps; "CPU time" is the GPU time of the run.
+scheme on a fine grid, as in Sec. 4.1; the runs are the discretizations of
+Sec. 2 the library has (MR-FV, MR, MRLT, AMR-FV, AMR; not AMRLT); "CPU
+time" is the GPU time of the run.
 
     python -m paper_1603_05211_amd.study [--levels 4 5 6] [--ref 4096]
 
@@ -122,14 +122,20 @@ def _history(s, init, t_end: float, lts_substeps: int):
     return leaves, cells
 
 
+ADAPTIVE = ("MR", "MRLT", "AMR")
+
+
 def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 0.25, cfl: float = 0.45,
               eps: float = 0.0023, eps_grad: float = 0.05, prim=None, log=None) -> dict:
     """Lax-Liu configuration #6 (Table 1, the default) on [0,1]^2 with
     outflow boundaries to t_end: a uniform FP64 reference of the AMR scheme
     on n_ref^2, then for every number of levels L (finest grid N = n0
-    2^(L-1)): the uniform FV run on N^2 (MR scheme) and the adaptive runs
-    MR (criterion eps), MRLT (the same with local time steps) and "AMR
-    criterion" (gradient of density, eps_grad, global time step), all FP64."""
+    2^(L-1)) the discretizations of Sec. 2 that the library runs, all FP64:
+    MR-FV and AMR-FV (the MR and AMR schemes on the uniform N^2 grid), MR
+    (MR scheme, MR criterion eps, global step), MRLT (the same with local
+    time steps) and AMR (AMR scheme, scaled-gradient criterion on density
+    eps_grad, global step).  Accuracy perturbation and time compression of
+    an adaptive run are taken against the uniform run of its scheme."""
     log = log or (lambda *a: None)
     prim = inputs.lax_liu_6() if prim is None else prim
     init = lambda s: s.init_quadrant(prim)
@@ -147,36 +153,38 @@ def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 
         N = n0 << (L - 1)
         NC = N * N
         rr = project(rho_ref[None], N)[0]
-        log(f"L = {L}: uniform FV {N}^2")
-        fv, t_fv, steps_fv = _timed_run(
-            lambda: Solver(2, n0=N, levels=1, precision=EU_FP64, cfl=cfl, t_end=t_end), init, t_end)
-        e_fv = l1_error(fv.level(0)[0], rr)
-        fv.close()
-        row = {"levels": L, "N": N, "fv": {"l1": e_fv, "gpu_s": t_fv, "steps": steps_fv}}
-        variants = (("MR", EU_CRIT_MR, eps, EU_DT_GLOBAL), ("MRLT", EU_CRIT_MR, eps, EU_DT_LTS),
-                    ("AMR criterion", EU_CRIT_GRADIENT, eps_grad, EU_DT_GLOBAL))
-        for name, crit, e, tm in variants:
+        row = {"levels": L, "N": N}
+        for name, sch in (("MR-FV", EU_SCHEME_MR), ("AMR-FV", EU_SCHEME_AMR)):
+            log(f"L = {L}: {name} {N}^2")
+            fv, t_fv, steps_fv = _timed_run(
+                lambda: Solver(2, n0=N, levels=1, precision=EU_FP64, cfl=cfl, t_end=t_end, scheme=sch), init, t_end)
+            row[name] = {"l1": l1_error(fv.level(0)[0], rr), "gpu_s": t_fv, "steps": steps_fv}
+            fv.close()
+        variants = (("MR", EU_SCHEME_MR, EU_CRIT_MR, eps, EU_DT_GLOBAL, "MR-FV"),
+                    ("MRLT", EU_SCHEME_MR, EU_CRIT_MR, eps, EU_DT_LTS, "MR-FV"),
+                    ("AMR", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, EU_DT_GLOBAL, "AMR-FV"))
+        for name, sch, crit, e, tm, base in variants:
             log(f"  {name}")
             mk = lambda: Solver(2, n0=n0, levels=L, precision=EU_FP64, cfl=cfl, t_end=t_end, eps=e, eta=0.8,
-                                patch_max=32, time_mode=tm, criterion=crit)
+                                patch_max=32, time_mode=tm, scheme=sch, criterion=crit)
             s, t_a, steps_a = _timed_run(mk, init, t_end)
             e_a = l1_error(s.composite()[0], rr)
             sub = 2 ** (L - 1) if tm == EU_DT_LTS else 1
             leaves, cells = _history(s, init, t_end, sub)
             s.close()
             leaf_steps = float(np.sum(leaves))
+            fv = row[base]
             row[name] = {"threshold": e, "l1": e_a, "gpu_s": t_a, "steps": steps_a,
                          "finest_steps": len(leaves),
-                         "accuracy_perturbation": accuracy_perturbation(e_fv, e_a),
+                         "accuracy_perturbation": accuracy_perturbation(fv["l1"], e_a),
                          "memory_compression": memory_compression(cells, NC),
                          "mesh_compression": mesh_compression(leaves, NC),
-                         "time_compression": time_compression(t_a, t_fv),
-                         "overhead": overhead(t_a, leaf_steps, t_fv, float(NC) * steps_fv)}
+                         "time_compression": time_compression(t_a, fv["gpu_s"]),
+                         "overhead": overhead(t_a, leaf_steps, fv["gpu_s"], float(NC) * fv["steps"])}
         out["runs"].append(row)
     for k in range(1, len(out["runs"])):
         a, b = out["runs"][k - 1], out["runs"][k]
-        b["fv"]["rate"] = math.log2(a["fv"]["l1"] / b["fv"]["l1"])
-        for name in ("MR", "MRLT", "AMR criterion"):
+        for name in ("MR-FV", "AMR-FV") + ADAPTIVE:
             b[name]["rate"] = math.log2(a[name]["l1"] / b[name]["l1"])
     return out
 
@@ -185,15 +193,18 @@ def markdown(res: dict) -> str:
     rows = ["| L | N | run | L1(rho) | rate | accuracy perturbation | memory | mesh | GPU-time compression | "
             "overhead | GPU s |", "|---:|---:|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for r in res["runs"]:
-        f = r["fv"]
-        rows.append(f"| {r['levels']} | {r['N']} | FV | {f['l1']:.6f} | {f.get('rate', float('nan')):.2f} | | | | | | "
-                    f"{f['gpu_s']:.3f} |")
-        for name in ("MR", "MRLT", "AMR criterion"):
+        first = True
+        for name in ("MR-FV", "AMR-FV") + ADAPTIVE:
             a = r[name]
-            rows.append(f"| | | {name} | {a['l1']:.6f} | {a.get('rate', float('nan')):.2f} | "
-                        f"{a['accuracy_perturbation']:.3f} | {a['memory_compression']:.3f} | "
-                        f"{a['mesh_compression']:.3f} | {a['time_compression']:.3f} | {a['overhead']:.2f} | "
-                        f"{a['gpu_s']:.3f} |")
+            lead = f"| {r['levels']} | {r['N']} |" if first else "| | |"
+            first = False
+            rate = f"{a['rate']:.2f}" if "rate" in a else ""
+            if name.endswith("FV"):
+                rows.append(f"{lead} {name} | {a['l1']:.6f} | {rate} | | | | | | {a['gpu_s']:.3f} |")
+            else:
+                rows.append(f"{lead} {name} | {a['l1']:.6f} | {rate} | {a['accuracy_perturbation']:.3f} | "
+                            f"{a['memory_compression']:.3f} | {a['mesh_compression']:.3f} | "
+                            f"{a['time_compression']:.3f} | {a['overhead']:.2f} | {a['gpu_s']:.3f} |")
     return "\n".join(rows)
 
 

@@ -15,9 +15,10 @@ def test_small_study():
     res = study.run_study(levels=(3, 4), n0=32, n_ref=512, t_end=0.05, log=say)
     say(study.markdown(res))
     a, b = res["runs"]
-    assert b["fv"]["l1"] < a["fv"]["l1"] and b["fv"]["rate"] > 0.3
+    for name in ("MR-FV", "AMR-FV"):
+        assert b[name]["l1"] < a[name]["l1"] and b[name]["rate"] > 0.3
     for r in res["runs"]:
-        for name in ("MR", "MRLT", "AMR criterion"):
+        for name in study.ADAPTIVE:
             m = r[name]
             assert 0 < m["mesh_compression"] <= m["memory_compression"] <= 2.0
             assert m["mesh_compression"] <= 1.0
