@@ -378,8 +378,6 @@ class Hierarchy:
         """One level-0 step with local time steps; returns (dt_0, leaf updates)."""
         upd = C.c_int64(0)
         dt = lib().orc_h_step_lts(self._h, cfl, self.t, t_end, int(regrid), C.byref(upd))
-        if dt == -2.0:
-            raise ValueError("local time steps run the MR scheme only")
         if dt < 0:
             raise MemoryError("oracle: local time stepping buffers")
         self.t = self.t + dt

@@ -512,7 +512,7 @@ typedef struct {
     int npatch, cappatch;
     int no_reflux;       /* test-only planted mistake: skip the flux correction */
     int scheme;          /* 0: MR scheme (MUSCL, van Albada, AUSM+, midpoint RK2);
-                            1: AMR scheme (MUSCL-Hancock, Minmod, AUSMDV), global dt */
+                            1: AMR scheme (MUSCL-Hancock, Minmod, AUSMDV) */
     int crit;            /* refinement criterion: 0 MR details (Sec. 2.1), 1 the
                             scaled-gradient indicators of the AMR method (Sec. 2.2) */
     double eps_p;        /* criterion 1: pressure threshold (<= 0: density only) */
@@ -1193,8 +1193,8 @@ int orc_h_set_criterion(orc_h *h, int crit, double eps_p)
     return 0;
 }
 
-/* Select the finite-volume scheme: 0 the MR scheme, 1 the AMR scheme (global
- * time steps only).  Returns 0, or -1 for an unknown scheme. */
+/* Select the finite-volume scheme: 0 the MR scheme, 1 the AMR scheme.
+ * Returns 0, or -1 for an unknown scheme. */
 int orc_h_set_scheme(orc_h *h, int scheme)
 {
     if (scheme != 0 && scheme != 1) return -1;
@@ -1268,7 +1268,7 @@ static int lts_alloc(orc_h *h)
  * in regC[l], fine side (a cell next to a ghost cell) in regF[l] for
  * substep sub. */
 static void h_fv_level_all(orc_h *h, int l, double **src, double **out, double lam,
-                           int record, int sub)
+                           double hl, int record, int sub)
 {
     int dim = h->dim, n = h->n[l], nv = h->nv;
     int64_t N = hN(h, l);
@@ -1283,8 +1283,8 @@ static void h_fv_level_all(orc_h *h, int l, double **src, double **out, double l
             double Fhi[NVMAX], Flo[NVMAX];
             int lc[3] = {p[0], p[1], p[2]};
             lc[d] = p[d] - 1;
-            face_flux(dim, n, h->bc, h->g, src[l], d, p, Fhi);
-            face_flux(dim, n, h->bc, h->g, src[l], d, lc, Flo);
+            level_flux(h, n, src[l], d, p, hl, Fhi);
+            level_flux(h, n, src[l], d, lc, hl, Flo);
             if (record) {
                 int nh[3] = {p[0], p[1], p[2]}, nl[3] = {p[0], p[1], p[2]};
                 nh[d] = bcmap(p[d] + 1, n, h->bc);
@@ -1379,9 +1379,10 @@ static void h_reflux(orc_h *h, int l, double lam)
 /* Advance level l by one step of dt_l (substep k of its parent's step):
  * keep the level's state at the start of the step (for the time
  * interpolation of finer ghost cells), two explicit stages on every cell of
- * the level, with second-stage ghost cells interpolated at the stage time,
- * then two substeps of level l+1 with ghost cells interpolated in time, the
- * projection of level l+1 onto level l and the flux correction. */
+ * the level, with second-stage ghost cells interpolated at the stage time
+ * (the AMR scheme: its single Hancock step), then two substeps of level l+1
+ * with ghost cells interpolated in time, the projection of level l+1 onto
+ * level l and the flux correction with the fluxes of the updating stage. */
 static void lts_advance(orc_h *h, int l, double dt, int k)
 {
     int64_t N = hN(h, l);
@@ -1389,9 +1390,18 @@ static void lts_advance(orc_h *h, int l, double dt, int k)
     /* stage times of substep k of level l within its parent's step: the
      * start, k / 2, and the midpoint, (2k + 1) / 4, as fractions of it */
     const int flat = plant == PLANT_LTS_THETA;
-    h_fv_level_all(h, l, h->Q, h->Qs, (dt * 0.5) / h->dx[l], 0, k);
-    if (l >= 1) h_ghost_time(h, l, h->Qs, h->Qo, h->Q, flat ? 0.0 : (double)(2 * k + 1) * 0.25);
-    h_fv_level_all(h, l, h->Qs, h->Q, dt / h->dx[l], 1, k);
+    if (h->scheme == 1) {
+        /* the AMR scheme: one Hancock step of every cell of the level into
+         * the stage array (its fluxes recorded), copied back */
+        h_fv_level_all(h, l, h->Q, h->Qs, dt / h->dx[l], (dt * 0.5) / h->dx[l], 1, k);
+        for (int64_t i = 0; i < N; ++i)
+            if (h->act[l][i])
+                for (int f = 0; f < h->nv; ++f) h->Q[l][f * N + i] = h->Qs[l][f * N + i];
+    } else {
+        h_fv_level_all(h, l, h->Q, h->Qs, (dt * 0.5) / h->dx[l], 0.0, 0, k);
+        if (l >= 1) h_ghost_time(h, l, h->Qs, h->Qo, h->Q, flat ? 0.0 : (double)(2 * k + 1) * 0.25);
+        h_fv_level_all(h, l, h->Qs, h->Q, dt / h->dx[l], 0.0, 1, k);
+    }
     if (l + 1 < h->L) {
         for (int kk = 0; kk < 2; ++kk) {
             h_ghost_time(h, l + 1, h->Q, h->Qo, h->Q, flat ? 0.0 : (double)kk * 0.5);
@@ -1407,11 +1417,10 @@ static void lts_advance(orc_h *h, int l, double dt, int k)
  * from the leaves, clipped to reach t_end; then the MR coarsening /
  * refinement when regrid is set and a spatial ghost fill.  Returns dt_0;
  * *leaf_updates receives sum over levels of leaves_l 2^l.  -1: out of
- * memory; -2: the hierarchy runs the AMR scheme (not with local steps). */
+ * memory. */
 double orc_h_step_lts(orc_h *h, double cfl, double t, double t_end, int regrid,
                       int64_t *leaf_updates)
 {
-    if (h->scheme != 0) return -2.0;   /* the MR scheme's two-stage cycle only */
     if (lts_alloc(h)) return -1.0;
     double smax[MAXL];
     orc_h_cfl(h, cfl, t, t_end, smax);

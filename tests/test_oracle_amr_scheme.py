@@ -223,13 +223,6 @@ def run_amr(orc, dim, n, Q0, steps=None, t_end=np.inf, cfl=0.45, bc=0, lo=0.0, h
     return h
 
 
-def test_amr_scheme_not_with_local_time_steps(orc):
-    h = orc.Hierarchy(2, 3, 16, scheme=orc.SCHEME_AMR)
-    h.init_finest(orc.init_quadrant(64, G, inputs.quadrant_states(1)))
-    with pytest.raises(ValueError):
-        h.step_lts(0.4)
-
-
 @pytest.mark.parametrize("axis", [0, 1])
 def test_hancock_sod_converges_to_exact_solution(orc, axis):
     L, R = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
