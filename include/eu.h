@@ -93,13 +93,16 @@ typedef struct {
                             midpoint RK2 (the paper's MR runs); EU_SCHEME_AMR:
                             unsplit MUSCL-Hancock with Minmod in primitive
                             variables and AUSMDV (Wada and Liou 1997), the
-                            paper's AMR runs (Sec. 2) -- 2D, global time
-                            step; one launch per step: the Hancock tile
-                            kernel (schedules 0-2: 128, 192, 256 threads per
-                            tile; hierarchies and uniform grids), a face next
-                            to a covered cell taking the mean of the finer
-                            level's fluxes, or the Hancock strips (schedules
-                            6 and 7; uniform grids and batches); the state alternates
+                            paper's AMR runs (Sec. 2) -- 2D; one launch per
+                            step: the Hancock tile kernel (schedules 0-2:
+                            128, 192, 256 threads per tile; hierarchies and
+                            uniform grids), a face next to a covered cell
+                            taking the mean of the finer level's fluxes, or
+                            the Hancock strips (schedules 6 and 7; uniform
+                            grids and batches); with EU_DT_LTS (AMRLT) one
+                            Hancock step per level step in the recursive
+                            cycle, flux correction from the recorded fluxes;
+                            with a global step the state alternates
                             between the two state arrays (tracked by the
                             library)                                          */
     int criterion;       /* EU_CRIT_MR (0): MR details against eps with one

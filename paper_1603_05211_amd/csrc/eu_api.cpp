@@ -139,10 +139,7 @@ int validate(const eu_config *c, std::string &why)
     }
     if (std::isnan(c->eps_p)) { why = "eps_p is NaN"; return EU_EINVAL; }
     if (c->scheme == EU_SCHEME_AMR && c->dim != 2) { why = "the AMR scheme runs in 2D"; return EU_EINVAL; }
-    if (c->scheme == EU_SCHEME_AMR && c->time_mode == EU_DT_LTS) {
-        why = "the AMR scheme runs with a global time step";
-        return EU_EINVAL;
-    }
+
     if (c->time_mode == EU_DT_LTS && c->n_instances > 1) { why = "a batch has no levels to step locally"; return EU_EINVAL; }
     if (c->n_instances > 1) {
         if (!c->inst_side_host) { why = "inst_side_host required for a batch"; return EU_EINVAL; }
@@ -484,7 +481,7 @@ void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
         hipEvent_t e;
         const bool fine = c->L >= 2;
         prof_begin(c, &e);
-        c->ks->hancock_tile(c->v, c->variant, fine ? 1 : 0, c->state_elems, c->max_tiles, c->stream);
+        c->ks->hancock_tile(c->v, c->variant, fine ? 1 : 0, c->state_elems, c->max_tiles, -1, 0, 0, c->stream);
         prof_end(c, e);
         std::swap(c->v.Q, c->v.Qs);
         c->qswap ^= 1;
@@ -628,14 +625,23 @@ void lts_advance(eu_ctx *c, int l, int k)
 {
     const int nbl = (int)nblocks_grid(c, l);
     hipEvent_t e;
-    c->ks->copy_level(c->v, l, nbl, c->stream);
-    prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 1, l, k, 0, nbl, c->variant, 0, c->stream);
-    prof_end(c, e);
-    if (l >= 1) c->ks->predict(c->v, ARR_QS, l, 1, 2, (double)(2 * k + 1) * 0.25, 0, nbl, c->stream);
-    prof_begin(c, &e);
-    c->ks->fv_stage(c->v, 2, l, k, 1, nbl, c->variant, 0, c->stream);
-    prof_end(c, e);
+    c->ks->copy_level(c->v, l, nbl, 0, c->stream);
+    if (c->cfg.scheme == EU_SCHEME_AMR) {
+        // the AMR scheme: one Hancock step of the level's patches into the
+        // stage array (fluxes recorded), copied back
+        prof_begin(c, &e);
+        c->ks->hancock_tile(c->v, c->variant, 0, c->state_elems, nbl, l, k, 1, c->stream);
+        prof_end(c, e);
+        c->ks->copy_level(c->v, l, nbl, 1, c->stream);
+    } else {
+        prof_begin(c, &e);
+        c->ks->fv_stage(c->v, 1, l, k, 0, nbl, c->variant, 0, c->stream);
+        prof_end(c, e);
+        if (l >= 1) c->ks->predict(c->v, ARR_QS, l, 1, 2, (double)(2 * k + 1) * 0.25, 0, nbl, c->stream);
+        prof_begin(c, &e);
+        c->ks->fv_stage(c->v, 2, l, k, 1, nbl, c->variant, 0, c->stream);
+        prof_end(c, e);
+    }
     if (l + 1 < c->L) {
         const int nbf = (int)nblocks_grid(c, l + 1);
         for (int kk = 0; kk < 2; ++kk) {
@@ -696,7 +702,7 @@ bool variant_ok(const eu_ctx *c, int var)
     if (var < 0 || var >= FV_VARIANTS) return false;
     if (c->cfg.scheme == EU_SCHEME_AMR) {
         const bool tile = var < HANCOCK_TILE_VARIANTS, strip = strip_variant(var) && !strip_fused(var);
-        return c->mode == MODE_BATCH ? strip : c->L > 1 ? tile : tile || strip;
+        return c->mode == MODE_BATCH ? strip : c->L > 1 || c->v.lts ? tile : tile || strip;
     }
     if (!strip_variant(var)) return true;
     if (c->L != 1) return false;
@@ -745,8 +751,12 @@ int strips_for(eu_ctx *c, int var)
 void fv_pass(eu_ctx *c, int var, int *launches)
 {
     if (c->v.lts) {
-        for (int l = 0; l < c->L; ++l)
-            c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, 0, c->stream);
+        for (int l = 0; l < c->L; ++l) {
+            if (c->cfg.scheme == EU_SCHEME_AMR)
+                c->ks->hancock_tile(c->v, var, 0, c->state_elems, (int)nblocks_grid(c, l), l, 0, 0, c->stream);
+            else
+                c->ks->fv_stage(c->v, 1, l, 0, 0, (int)nblocks_grid(c, l), var, 0, c->stream);
+        }
         *launches = c->L;
     } else if (strip_variant(var) && c->dim == 3) {
         const int wv = strip3_waves(var);
@@ -754,7 +764,7 @@ void fv_pass(eu_ctx *c, int var, int *launches)
         c->ks->fv_strip3(c->v, wv, 0, 2, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
         *launches = 2;
     } else if (c->cfg.scheme == EU_SCHEME_AMR && !strip_variant(var)) {
-        c->ks->hancock_tile(c->v, var, c->L >= 2 ? 1 : 0, c->state_elems, c->max_tiles, c->stream);
+        c->ks->hancock_tile(c->v, var, c->L >= 2 ? 1 : 0, c->state_elems, c->max_tiles, -1, 0, 0, c->stream);
         *launches = 1;
     } else if (c->cfg.scheme == EU_SCHEME_AMR) {
         c->ks->hancock_strip(c->v, 2, c->strips, c->nstrips, c->v.Q, c->v.Qs, c->stream);
@@ -1087,7 +1097,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     // the AMR scheme runs on the Hancock strip kernel (grids of one level)
     // or the Hancock tile kernel (hierarchies)
     if (cfg->scheme == EU_SCHEME_AMR) {
-        c->variant = c->L > 1 ? 0 : FV_STRIP0;
+        c->variant = c->L > 1 || c->v.lts ? 0 : FV_STRIP0;
         if ((r = strips_for(c, c->variant))) {
             delete c;
             return r;
@@ -1274,7 +1284,7 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
         // move it to the other array every step); recording a step changes
         // only host bookkeeping, which is restored after each capture (the
         // CFL slots are left by a step as the lines above prepare them)
-        const bool alt = c->cfg.scheme == EU_SCHEME_AMR ||
+        const bool alt = (c->cfg.scheme == EU_SCHEME_AMR && !c->v.lts) ||
                          (strip_variant(c->variant) && c->dim == 2 && strip_fused(c->variant));
         for (int p = 0; p < (alt ? 2 : 1); ++p) {
             const int q = c->qswap ^ p;

@@ -99,18 +99,23 @@ __device__ void fine_mean_hancock(const View &v, const Grid &gf, const T *src, i
     for (int f = 0; f < 4; ++f) F[f] = T(0.5) * (Fs[0][f] + Fs[1][f]);
 }
 
-// One MUSCL-Hancock step on every leaf of the leaf list of a 2D hierarchy:
-// out = src - (dt / dx) ((dF_1 + dF_2)) on the leaf cells of each tile (out
-// the other state array).  Per tile: the tile with a 2-cell halo converted
-// to primitive variables in LDS; the evolved face values of cells -1 .. B
-// of both axes; the fluxes of the faces next to a leaf (the fine-flux mean
-// where the other side is covered); the update.  fineproj: a tile of the
-// finest level also writes the projection of its new values onto its 4x4
-// parent cells (as k_fv_stage).  Past t_end the launch copies the whole
-// state (nstate elements), so that the step leaves it as it was.
+// One MUSCL-Hancock step, out = src - (dt / dx) ((dF_1 + dF_2)), into the
+// other state array.  Global time step (lvl < 0): the leaf cells of every
+// tile of the leaf list of a 2D hierarchy (or uniform grid); a face next to
+// a covered cell takes the fine-flux mean.  Local time stepping (lvl >= 0):
+// every cell of the patches of level lvl with the level's own fluxes and
+// step dt_lvl; with record set, the fluxes across refinement boundaries go
+// to the flux registers (substep sub), as k_fv_stage records them.  Per
+// tile: the tile with a 2-cell halo converted to primitive variables in
+// LDS; the evolved face values of cells -1 .. B of both axes; the fluxes of
+// the faces the tile needs; the update.  fineproj (global step): a tile of
+// the finest level also writes the projection of its new values onto its
+// 4x4 parent cells (as k_fv_stage).  Past t_end a global step copies the
+// whole state (nstate elements), so that the step leaves it as it was; a
+// local step writes nothing.
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_hancock_tile(View v, const T *__restrict__ src, T *out, int fineproj,
-                                                     int64_t nstate)
+                                                     int64_t nstate, int lvl, int sub, int record)
 {
     constexpr int B = BS, H = 2, E = BS + 4, NE = E * E, NV = 4;
     constexpr int HW = B + 2, NH = HW * HW;   // cells -1 .. B of both axes
@@ -120,26 +125,30 @@ __global__ void __launch_bounds__(NT) k_hancock_tile(View v, const T *__restrict
     __shared__ T sE[4][NV][NH];
     __shared__ T sF[2][NV][NF];
     __shared__ uint8_t sCov[NE];
+    __shared__ uint8_t sAct[NE];
     __shared__ GridTab tab;
+    const bool lts = lvl >= 0;
     const int done = v.meta->done;
-    const int count = v.meta->nleaf;
-    const double dt = v.dt[0];
-    // workgroup b's first tile read with the count (as k_fv_stage)
+    const Tile *list = lts ? v.actv + v.meta->loff[LST_ACT][lvl] : v.leaf;
+    const int count = lts ? v.meta->loff[LST_ACT][lvl + 1] - v.meta->loff[LST_ACT][lvl] : v.meta->nleaf;
+    const double dt = v.dt[lts ? lvl : 0];
+    // workgroup b's first leaf tile read with the count (as k_fv_stage)
     const int tf = xcd_run(blockIdx.x, gridDim.x);
     const int t0 = tf < v.max_tiles ? tf : v.max_tiles - 1;
-    const Tile first = v.leaf[t0];
+    const Tile first = lts ? Tile{0, 0} : v.leaf[t0];
     grid_tab_load(v, tab);
-    issued(count, dt, first.grid, first.block);
+    issued(list, count, dt, first.grid, first.block);
     if (done) {
-        for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nstate; i += (int64_t)gridDim.x * NT)
-            out[i] = src[i];
+        if (!lts)
+            for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nstate; i += (int64_t)gridDim.x * NT)
+                out[i] = src[i];
         return;
     }
     __syncthreads();
     const T g = (T)v.gamma;
     const T gi = (T)(1.0 / (v.gamma - 1.0));
     for (int t = tf; t < count; t += gridDim.x) {
-        const Tile tl = t == tf ? first : v.leaf[t];
+        const Tile tl = t == tf && !lts ? first : list[t];
         const Grid G = grid_tab(tab, tl.grid);
         const bool hasf = G.fine >= 0;
         const Grid GF = hasf ? grid_tab(tab, G.fine) : G;
@@ -151,7 +160,7 @@ __global__ void __launch_bounds__(NT) k_hancock_tile(View v, const T *__restrict
         // before any is used
         constexpr int IE = (NE + NT - 1) / NT;
         T qh[IE][NV];
-        uint8_t cvb[IE];
+        uint8_t cvb[IE], acb[IE];
 #pragma unroll
         for (int u = 0; u < IE; ++u) {
             const int c0 = threadIdx.x + u * NT, c = c0 < NE ? c0 : NE - 1;
@@ -161,6 +170,7 @@ __global__ void __launch_bounds__(NT) k_hancock_tile(View v, const T *__restrict
             for (int f = 0; f < NV; ++f) qh[u][f] = S[f * N + id];
             const int64_t cb = hasf ? GF.boff + (int64_t)gidx32(GF.nb, x >> 2, y >> 2, 0) : G.boff;
             cvb[u] = v.act[cb];
+            acb[u] = record ? v.act[G.boff + (int64_t)gidx32(G.nb, x >> 3, y >> 3, 0)] : 0;
         }
         T qb[CPT][NV];
 #pragma unroll
@@ -180,6 +190,7 @@ __global__ void __launch_bounds__(NT) k_hancock_tile(View v, const T *__restrict
 #pragma unroll
             for (int f = 0; f < NV; ++f) sW[f][c] = w[f];
             sCov[c] = hasf && cvb[u] != 0 ? 1 : 0;
+            sAct[c] = acb[u] != 0 ? 1 : 0;
         }
         __syncthreads();
         // evolved face values of cells (-1 .. B)^2 (entry c: cell (c % HW - 1, c / HW - 1))
@@ -220,11 +231,14 @@ __global__ void __launch_bounds__(NT) k_hancock_tile(View v, const T *__restrict
             const int hl_ = (lx + H) + E * (ly + H), hr_ = hl_ + (dn == 0 ? 1 : E);
             const bool lin = a >= 1, rin = a <= B - 1;
             const bool lcov = sCov[hl_] != 0, rcov = sCov[hr_] != 0;
+            // global step: faces next to a leaf of the tile; local step:
+            // every face of the tile (whole patches are updated)
+            const bool need = lts ? (lin || rin) : ((lin && !lcov) || (rin && !rcov));
             T F[NV];
-            if (!((lin && !lcov) || (rin && !rcov))) {
+            if (!need) {
 #pragma unroll
                 for (int f = 0; f < NV; ++f) F[f] = T(0);
-            } else if (lcov || rcov) {
+            } else if (!lts && (lcov || rcov)) {
                 int px = ox + lx, py = oy + ly, s = +1;
                 if (lcov) {
                     s = -1;
@@ -241,19 +255,35 @@ __global__ void __launch_bounds__(NT) k_hancock_tile(View v, const T *__restrict
                     wr[f] = sE[2 * dn][f][er];
                 }
                 ausmdv2<T>(g, gi, dn, wl, wr, F);
+                if (record) {
+                    // registers are indexed by the cell on the low side of the face
+                    const int qx = dn == 0 ? bcmap(ox + lx, n, v.bc) : ox + lx;
+                    const int qy = dn == 1 ? bcmap(oy + ly, n, v.bc) : oy + ly;
+                    const int64_t iq = gidx(n, qx, qy, 0);
+                    const bool lact = sAct[hl_] != 0, ract = sAct[hr_] != 0;
+                    const bool lleaf = lact && !lcov, rleaf = ract && !rcov;
+                    T *reg = (T *)v.reg;
+                    if (G.rcoff >= 0 && ((lleaf && rcov) || (rleaf && lcov)))
+#pragma unroll
+                        for (int f = 0; f < NV; ++f) reg[G.rcoff + ((int64_t)dn * NV + f) * N + iq] = F[f];
+                    if (G.rfoff >= 0 && lact != ract)
+#pragma unroll
+                        for (int f = 0; f < NV; ++f)
+                            reg[G.rfoff + (((int64_t)sub * 2 + dn) * NV + f) * N + iq] = F[f];
+                }
             }
 #pragma unroll
             for (int f = 0; f < NV; ++f) sF[dn][f][fi] = F[f];
         }
         __syncthreads();
         const T lam = (T)(dt / G.dx);
-        const bool fp = fineproj && tl.grid == v.L - 1;
+        const bool fp = !lts && fineproj && tl.grid == v.L - 1;
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int c = threadIdx.x + k * NT;
             if (c >= TC) break;
             const int x = c % B, y = c / B;
-            if (sCov[(x + H) + E * (y + H)]) continue;
+            if (!lts && sCov[(x + H) + E * (y + H)]) continue;
             const int fx = x + (B + 1) * y, fy = x + B * y;
             const int64_t id = G.off + (int64_t)gidx32(n, ox + x, oy + y, 0);
 #pragma unroll

@@ -1596,16 +1596,16 @@ __global__ void __launch_bounds__(256) k_composite(View v, int lvl)
     }
 }
 
-// Local time stepping: keep level lvl's state at the start of its step (the
-// cells of its patches) for the time interpolation of finer ghost cells.
+// Local time stepping: copy the cells of level lvl's patches from Q to Qo:
+// the level's state at the start of its step, kept for the time
+// interpolation of finer ghost cells (Q -> Qo), or the AMR scheme's new
+// state from the stage array (Qs -> Q).
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_copy_level(View v, int lvl)
+__global__ void __launch_bounds__(256) k_copy_level(View v, int lvl, const T *__restrict__ Q, T *Qo)
 {
     if (v.meta->done) return;
     const int off = v.meta->loff[LST_ACT][lvl], count = v.meta->loff[LST_ACT][lvl + 1] - off;
     constexpr int TC = D == 2 ? BS * BS : BS * BS * BS;
-    const T *Q = (const T *)v.Q;
-    T *Qo = (T *)v.Qo;
     for (int t = blockIdx.x; t < count; t += gridDim.x) {
         const Tile tl = v.actv[off + t];
         const Grid G = v.grids[tl.grid];

@@ -68,10 +68,14 @@ struct KSet {
     // the AMR scheme's MUSCL-Hancock step over count strips (src -> out)
     void (*hancock_strip)(const View &, int cfl, const Strip *list, int count, const void *src, void *out,
                           hipStream_t);
-    // the AMR scheme's MUSCL-Hancock step on every leaf of a 2D hierarchy
-    // (Q -> Qs; past t_end the whole state of nstate elements is copied)
-    void (*hancock_tile)(const View &, int variant, int fineproj, int64_t nstate, int maxtiles, hipStream_t);
-    void (*copy_level)(const View &, int lvl, int maxblocks, hipStream_t);
+    // the AMR scheme's MUSCL-Hancock step (Q -> Qs) on every leaf of a 2D
+    // hierarchy (lvl < 0; past t_end the whole state of nstate elements is
+    // copied) or on the patches of level lvl (local time stepping; record:
+    // flux registers of substep sub)
+    void (*hancock_tile)(const View &, int variant, int fineproj, int64_t nstate, int maxtiles, int lvl, int sub,
+                         int record, hipStream_t);
+    // the patch cells of level lvl: Q -> Qo, or Qs -> Q (back)
+    void (*copy_level)(const View &, int lvl, int maxblocks, int back, hipStream_t);
     void (*reflux)(const View &, int lvl, int maxblocks, hipStream_t);
     void (*cfl_slots)(const View &, int maxtiles, hipStream_t);     // into zero CFL slots / batch maxima
     void (*totals)(const View &, int maxtiles, hipStream_t);

@@ -150,24 +150,26 @@ template <typename T> void hancock_strip(const View &v, int cfl, const Strip *li
     k_hancock_strip<T><<<nblk, 256, 0, s>>>(v, list, count, (const T *)src, (T *)out, cfl);
 }
 
-template <typename T> void hancock_tile(const View &v, int variant, int fineproj, int64_t nstate, int maxt,
-                                        hipStream_t s)
+template <typename T> void hancock_tile(const View &v, int variant, int fineproj, int64_t nstate, int maxt, int lvl,
+                                        int sub, int record, hipStream_t s)
 {
     const int nblk = xcd_grid(maxt, 2048);
     const T *src = (const T *)v.Q;
     T *out = (T *)v.Qs;
     switch (variant) {
-    case 1: k_hancock_tile<T, 192><<<nblk, 192, 0, s>>>(v, src, out, fineproj, nstate); break;
-    case 2: k_hancock_tile<T, 256><<<nblk, 256, 0, s>>>(v, src, out, fineproj, nstate); break;
-    default: k_hancock_tile<T, 128><<<nblk, 128, 0, s>>>(v, src, out, fineproj, nstate); break;
+    case 1: k_hancock_tile<T, 192><<<nblk, 192, 0, s>>>(v, src, out, fineproj, nstate, lvl, sub, record); break;
+    case 2: k_hancock_tile<T, 256><<<nblk, 256, 0, s>>>(v, src, out, fineproj, nstate, lvl, sub, record); break;
+    default: k_hancock_tile<T, 128><<<nblk, 128, 0, s>>>(v, src, out, fineproj, nstate, lvl, sub, record); break;
     }
 }
 
-template <typename T> void copy_level(const View &v, int lvl, int maxb, hipStream_t s)
+template <typename T> void copy_level(const View &v, int lvl, int maxb, int back, hipStream_t s)
 {
     const int nblk = clamp_grid(maxb, 2048);
-    if (v.dim == 2) k_copy_level<T, 2><<<nblk, 64, 0, s>>>(v, lvl);
-    else k_copy_level<T, 3><<<nblk, 256, 0, s>>>(v, lvl);
+    const T *src = (const T *)(back ? v.Qs : v.Q);
+    T *dst = (T *)(back ? v.Q : v.Qo);
+    if (v.dim == 2) k_copy_level<T, 2><<<nblk, 64, 0, s>>>(v, lvl, src, dst);
+    else k_copy_level<T, 3><<<nblk, 256, 0, s>>>(v, lvl, src, dst);
 }
 
 template <typename T> void reflux(const View &v, int lvl, int maxb, hipStream_t s)

@@ -120,3 +120,63 @@ def test_headline_hierarchy_fp32_against_oracle():
         dis = int((fo != fg).sum())
         say(f"  level {l}: flagged {int(fo.sum())}, disagreements {dis}")
         assert dis <= max(2, 0.02 * fo.sum())
+
+
+# --------------------------------------------------------------------------
+# AMRLT: the AMR scheme in the recursive level cycle (local time steps)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("var", TILE_SCHEDULES)
+def test_amrlt_fp64(var):
+    say("amrlt fp64 schedule", var)
+    h, s = make_pair(2, 3, 32, eps=1e-3, scheme=EU_SCHEME_AMR, lts=True, cfl=0.4)
+    init_pair(h, s, "quadrant", 1)
+    s.set_variant(var)
+    do, dg = run_pair(h, s, 8)
+    assert np.array_equal(do, dg)
+    check_fp64(h, s)
+
+
+@pytest.mark.parametrize("bc,crit", [(0, EU_CRIT_GRADIENT), (1, EU_CRIT_MR)])
+def test_amrlt_four_levels_fp64(bc, crit):
+    say("amrlt fp64 four levels bc", bc, "criterion", crit)
+    eps = 0.05 if crit == EU_CRIT_GRADIENT else 1e-3
+    h, s = make_pair(2, 4, 16, bc=bc, eps=eps, scheme=EU_SCHEME_AMR, lts=True, cfl=0.4, criterion=crit)
+    init_pair(h, s, "quadrant", 4)
+    do, dg = run_pair(h, s, 6)
+    assert np.array_equal(do, dg)
+    check_fp64(h, s)
+
+
+def test_amrlt_graph_past_t_end():
+    say("amrlt fp64 graph past t_end")
+    t_end = 0.03
+    h, s = make_pair(2, 3, 32, eps=1e-3, scheme=EU_SCHEME_AMR, lts=True, cfl=0.4, t_end=t_end)
+    init_pair(h, s, "quadrant", 2)
+    steps = 0
+    while h.t < t_end:
+        h.step_lts(0.4, t_end)
+        steps += 1
+    done = s.advance(steps + 3, use_graph=True)
+    assert done == steps and s.time()[0] == t_end
+    check_fp64(h, s)
+
+
+def test_amrlt_headline_hierarchy_fp32():
+    """AMRLT on the five-level benchmark hierarchy in FP32, 6 level-0 steps
+    (96 finest substeps) against the FP64 oracle."""
+    say("amrlt fp32 headline hierarchy")
+    h, s = make_pair(2, 5, 32, precision=EU_FP32, eps=1e-3, scheme=EU_SCHEME_AMR, lts=True, cfl=0.4)
+    init_pair(h, s, "quadrant", 0)
+    for _ in range(6):
+        h.step_lts(0.4)
+    assert s.advance(6, use_graph=True) == 6
+    g, o = s.composite(), h.composite()
+    scale = np.abs(o[0]).sum()
+    l1 = [float(np.abs(g[f] - o[f]).sum() / scale) for f in range(4)]
+    linf = [float(np.abs(g[f] - o[f]).max() / np.abs(o[f]).max()) for f in range(4)]
+    say("  L1 rel", l1, "Linf rel", linf)
+    assert max(l1) <= 1e-5 and max(linf) <= 2e-3
+    for l in range(h.L - 1):
+        fo, fg = h.flags(l).astype(bool), s.flags(l).astype(bool)
+        assert int((fo != fg).sum()) <= max(2, 0.02 * fo.sum())
