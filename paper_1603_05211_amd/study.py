@@ -9,8 +9,8 @@ time steps, per cell of the finest uniform grid), CPU-time compression and
 the overhead per leaf, Gamma^a / Gamma^FV - 1.  This module computes the same
 measures with the library: the reference is a uniform FP64 run of the AMR
 scheme on a fine grid, as in Sec. 4.1; the runs are the discretizations of
-Sec. 2 the library has (MR-FV, MR, MRLT, AMR-FV, AMR; not AMRLT); "CPU
-time" is the GPU time of the run.
+Sec. 2 (MR-FV, MR, MRLT, AMR-FV, AMR, AMRLT); "CPU time" is the GPU time of
+the run.
 
     python -m paper_1603_05211_amd.study [--levels 4 5 6] [--ref 4096]
 
@@ -122,7 +122,7 @@ def _history(s, init, t_end: float, lts_substeps: int):
     return leaves, cells
 
 
-ADAPTIVE = ("MR", "MRLT", "AMR")
+ADAPTIVE = ("MR", "MRLT", "AMR", "AMRLT")
 
 
 def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 0.25, cfl: float = 0.45,
@@ -130,12 +130,13 @@ def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 
     """Lax-Liu configuration #6 (Table 1, the default) on [0,1]^2 with
     outflow boundaries to t_end: a uniform FP64 reference of the AMR scheme
     on n_ref^2, then for every number of levels L (finest grid N = n0
-    2^(L-1)) the discretizations of Sec. 2 that the library runs, all FP64:
-    MR-FV and AMR-FV (the MR and AMR schemes on the uniform N^2 grid), MR
-    (MR scheme, MR criterion eps, global step), MRLT (the same with local
-    time steps) and AMR (AMR scheme, scaled-gradient criterion on density
-    eps_grad, global step).  Accuracy perturbation and time compression of
-    an adaptive run are taken against the uniform run of its scheme."""
+    2^(L-1)) the six discretizations of Sec. 2, all FP64: MR-FV and AMR-FV
+    (the MR and AMR schemes on the uniform N^2 grid), MR (MR scheme, MR
+    criterion eps, global step), MRLT (the same with local time steps), AMR
+    (AMR scheme, scaled-gradient criterion on density eps_grad, global
+    step) and AMRLT (the same with local time steps).  Accuracy
+    perturbation and time compression of an adaptive run are taken against
+    the uniform run of its scheme."""
     log = log or (lambda *a: None)
     prim = inputs.lax_liu_6() if prim is None else prim
     init = lambda s: s.init_quadrant(prim)
@@ -162,7 +163,8 @@ def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 
             fv.close()
         variants = (("MR", EU_SCHEME_MR, EU_CRIT_MR, eps, EU_DT_GLOBAL, "MR-FV"),
                     ("MRLT", EU_SCHEME_MR, EU_CRIT_MR, eps, EU_DT_LTS, "MR-FV"),
-                    ("AMR", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, EU_DT_GLOBAL, "AMR-FV"))
+                    ("AMR", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, EU_DT_GLOBAL, "AMR-FV"),
+                    ("AMRLT", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, EU_DT_LTS, "AMR-FV"))
         for name, sch, crit, e, tm, base in variants:
             log(f"  {name}")
             mk = lambda: Solver(2, n0=n0, levels=L, precision=EU_FP64, cfl=cfl, t_end=t_end, eps=e, eta=0.8,
