@@ -13,6 +13,7 @@ Sec. 2 (MR-FV, MR, MRLT, AMR-FV, AMR, AMRLT); "CPU time" is the GPU time of
 the run.
 
     python -m paper_1603_05211_amd.study [--levels 4 5 6] [--ref 4096]
+    python -m paper_1603_05211_amd.study --3d [--levels 3 4 5] [--ref 1024]
 
 prints one JSON object (and a markdown table on stderr).
 """
@@ -83,21 +84,32 @@ def overhead(t_adaptive: float, leaf_steps_adaptive: float, t_fv: float, leaf_st
 # ----------------------------------------------------------------------------
 
 
-def _timed_run(make, init, t_end: float):
+def _timed_run(make, init, t_end: float, log=None, once=False):
     """A run to t_end replayed from the step graph, timed between two device
     synchronisations: one untimed run first (in chunks of 64 steps, until a
     chunk ends early: steps past t_end do nothing but still launch) counts
-    the steps, then the timed run replays exactly that many."""
+    the steps, then the timed run replays exactly that many.  log: called
+    with the step count after every chunk of the untimed run.  once: the
+    chunked run alone, its time taken around it (references)."""
     import torch
     s = make()
     init(s)
     s.autotune(reps=3)
+    if once:
+        init(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     steps = 0
     while True:
         k = s.advance(64, use_graph=True)
         steps += k
+        if log is not None:
+            log(f"    {steps} steps, t = {s.time()[0]:.4f}")
         if k < 64:
             break
+    if once:
+        torch.cuda.synchronize()
+        return s, time.perf_counter() - t0, steps
     init(s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -143,8 +155,8 @@ def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 
     log(f"reference: AMR scheme, uniform {n_ref}^2, FP64")
     ref, t_ref, steps_ref = _timed_run(
         lambda: Solver(2, n0=n_ref, levels=1, precision=EU_FP64, cfl=cfl, t_end=t_end, scheme=EU_SCHEME_AMR),
-        init, t_end)
-    rho_ref = ref.level(0)[0]
+        init, t_end, log, once=True)
+    rho_ref = ref.level(0)[0].copy()   # drops the other fields
     ref.close()
     out = {"problem": "Lax-Liu configuration #6 (Table 1), [0,1]^2, outflow, t_end %g" % t_end,
            "reference": {"scheme": "AMR (MUSCL-Hancock, Minmod, AUSMDV)", "n": n_ref, "steps": steps_ref,
@@ -191,12 +203,77 @@ def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 
     return out
 
 
+ADAPTIVE_3D = ("MR", "MRLT")
+
+
+def run_study_3d(levels=(3, 4, 5), n0: int = 32, n_ref: int = 1024, t_end: float = 0.28, cfl: float = 0.4,
+                 eps: float = 0.013, log=None) -> dict:
+    """The 3D ellipsoidal shock of Sec. 4.2 as printed (inputs.paper_ellipsoid:
+    Omega = [-2,2]^3, outflow, t_e = 0.28, r_c = 3/5, a = 1/3, b = 1, c = 3,
+    the printed densities and energy densities): a uniform FP64 reference of
+    the MR scheme on n_ref^3, then for every number of levels L (finest grid
+    N = n0 2^(L-1)) MR-FV (the MR scheme on the uniform N^3 grid), MR (MR
+    criterion eps = 0.013, the paper's 3D threshold, global step) and MRLT
+    (the same with local time steps), all FP64.  The AMR scheme runs in 2D
+    only, so the AMR rows of the paper's 3D tables have no counterpart."""
+    log = log or (lambda *a: None)
+    e = inputs.paper_ellipsoid()
+    lo, hi = -2.0, 2.0
+    init = lambda s: s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
+    log(f"reference: MR scheme, uniform {n_ref}^3, FP64")
+    ref, t_ref, steps_ref = _timed_run(
+        lambda: Solver(3, n0=n_ref, levels=1, precision=EU_FP64, cfl=cfl, t_end=t_end, lo=lo, hi=hi), init, t_end,
+        log, once=True)
+    log(f"  {steps_ref} steps in {t_ref:.1f} s")
+    rho_ref = ref.level(0)[0].copy()   # drops the other fields
+    ref.close()
+    out = {"problem": "3D ellipsoidal shock (Sec. 4.2, initial data as printed), [-2,2]^3, outflow, t_end %g"
+                      % t_end,
+           "reference": {"scheme": "MR (MUSCL, van Albada, AUSM+, RK2)", "n": n_ref, "steps": steps_ref,
+                         "gpu_s": t_ref},
+           "cfl": cfl, "runs": []}
+    for L in levels:
+        N = n0 << (L - 1)
+        NC = N ** 3
+        rr = project(rho_ref[None], N)[0]
+        log(f"L = {L}: MR-FV {N}^3")
+        fv, t_fv, steps_fv = _timed_run(
+            lambda: Solver(3, n0=N, levels=1, precision=EU_FP64, cfl=cfl, t_end=t_end, lo=lo, hi=hi), init, t_end)
+        row = {"levels": L, "N": N,
+               "MR-FV": {"l1": l1_error(fv.level(0)[0], rr, lo, hi), "gpu_s": t_fv, "steps": steps_fv}}
+        fv.close()
+        for name, tm in (("MR", EU_DT_GLOBAL), ("MRLT", EU_DT_LTS)):
+            log(f"  {name}")
+            mk = lambda: Solver(3, n0=n0, levels=L, precision=EU_FP64, cfl=cfl, t_end=t_end, eps=eps, eta=0.8,
+                                patch_max=32, time_mode=tm, lo=lo, hi=hi)
+            s, t_a, steps_a = _timed_run(mk, init, t_end)
+            e_a = l1_error(s.composite()[0], rr, lo, hi)
+            sub = 2 ** (L - 1) if tm == EU_DT_LTS else 1
+            leaves, cells = _history(s, init, t_end, sub)
+            s.close()
+            f = row["MR-FV"]
+            row[name] = {"threshold": eps, "l1": e_a, "gpu_s": t_a, "steps": steps_a, "finest_steps": len(leaves),
+                         "accuracy_perturbation": accuracy_perturbation(f["l1"], e_a),
+                         "memory_compression": memory_compression(cells, NC),
+                         "mesh_compression": mesh_compression(leaves, NC),
+                         "time_compression": time_compression(t_a, f["gpu_s"]),
+                         "overhead": overhead(t_a, float(np.sum(leaves)), f["gpu_s"], float(NC) * f["steps"])}
+        out["runs"].append(row)
+    for k in range(1, len(out["runs"])):
+        a, b = out["runs"][k - 1], out["runs"][k]
+        for name in ("MR-FV",) + ADAPTIVE_3D:
+            b[name]["rate"] = math.log2(a[name]["l1"] / b[name]["l1"])
+    return out
+
+
 def markdown(res: dict) -> str:
     rows = ["| L | N | run | L1(rho) | rate | accuracy perturbation | memory | mesh | GPU-time compression | "
             "overhead | GPU s |", "|---:|---:|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for r in res["runs"]:
         first = True
         for name in ("MR-FV", "AMR-FV") + ADAPTIVE:
+            if name not in r:
+                continue
             a = r[name]
             lead = f"| {r['levels']} | {r['N']} |" if first else "| | |"
             first = False
@@ -218,8 +295,19 @@ def main(argv=None):
     ap.add_argument("--t-end", type=float, default=0.25)
     ap.add_argument("--eps", type=float, default=0.0023)
     ap.add_argument("--eps-grad", type=float, default=0.05)
+    ap.add_argument("--3d", dest="three", action="store_true",
+                    help="the 3D ellipsoidal shock instead (defaults --levels 3 4 5 --ref 1024 --t-end 0.28 "
+                         "--eps 0.013)")
     a = ap.parse_args(argv)
     log = lambda *m: print(*m, file=sys.stderr, flush=True)
+    if a.three:
+        given = lambda name: any(x == name or x.startswith(name + "=") for x in (argv or sys.argv[1:]))
+        res = run_study_3d(tuple(a.levels) if given("--levels") else (3, 4, 5), a.n0,
+                           a.ref if given("--ref") else 1024, a.t_end if given("--t-end") else 0.28,
+                           eps=a.eps if given("--eps") else 0.013, log=log)
+        log(markdown(res))
+        print(json.dumps(res), flush=True)
+        return
     res = run_study(tuple(a.levels), a.n0, a.ref, a.t_end, eps=a.eps, eps_grad=a.eps_grad, log=log)
     log(markdown(res))
     print(json.dumps(res), flush=True)

@@ -24,3 +24,17 @@ def test_small_study():
             assert m["mesh_compression"] <= 1.0
             assert math.isfinite(m["overhead"]) and m["l1"] > 0
             assert m["accuracy_perturbation"] < 1.0
+
+
+def test_small_study_3d():
+    res = study.run_study_3d(levels=(2, 3), n0=16, n_ref=128, t_end=0.05, log=say)
+    say(study.markdown(res))
+    a, b = res["runs"]
+    assert b["MR-FV"]["l1"] < a["MR-FV"]["l1"]
+    for r in res["runs"]:
+        for name in study.ADAPTIVE_3D:
+            m = r[name]
+            assert 0 < m["mesh_compression"] <= m["memory_compression"] <= 2.0
+            assert m["mesh_compression"] <= 1.0
+            assert math.isfinite(m["overhead"]) and m["l1"] > 0
+            assert m["accuracy_perturbation"] < 1.0
