@@ -93,13 +93,13 @@ typedef struct {
                             midpoint RK2 (the paper's MR runs); EU_SCHEME_AMR:
                             unsplit MUSCL-Hancock with Minmod in primitive
                             variables and AUSMDV (Wada and Liou 1997), the
-                            paper's AMR runs (Sec. 2) -- 2D; one launch per
-                            step: the Hancock tile kernel (schedules 0-2:
-                            128, 192, 256 threads per tile; hierarchies and
-                            uniform grids), a face next to a covered cell
-                            taking the mean of the finer level's fluxes, or
-                            the Hancock strips (schedules 6 and 7; uniform
-                            grids and batches); with EU_DT_LTS (AMRLT) one
+                            paper's AMR runs (Sec. 2); one launch per step:
+                            the Hancock tile kernel (hierarchies and uniform
+                            grids; schedules 0-2: 128, 192, 256 threads per
+                            tile in 2D, 0-1: 256, 512 in 3D), a face next to
+                            a covered cell taking the mean of the finer
+                            level's fluxes, or the Hancock strips (2D
+                            schedules 6 and 7; uniform grids and batches); with EU_DT_LTS (AMRLT) one
                             Hancock step per level step in the recursive
                             cycle, flux correction from the recorded fluxes;
                             with a global step the state alternates

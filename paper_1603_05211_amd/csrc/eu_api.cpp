@@ -138,7 +138,6 @@ int validate(const eu_config *c, std::string &why)
         return EU_EINVAL;
     }
     if (std::isnan(c->eps_p)) { why = "eps_p is NaN"; return EU_EINVAL; }
-    if (c->scheme == EU_SCHEME_AMR && c->dim != 2) { why = "the AMR scheme runs in 2D"; return EU_EINVAL; }
 
     if (c->time_mode == EU_DT_LTS && c->n_instances > 1) { why = "a batch has no levels to step locally"; return EU_EINVAL; }
     if (c->n_instances > 1) {
@@ -479,13 +478,13 @@ void seq_fv_step(eu_ctx *c, bool ghost_after, bool details = false)
         // and the ghost fill (the refinement analysis reads ghost cells),
         // then the details
         hipEvent_t e;
-        const bool fine = c->L >= 2;
+        const bool fine = c->dim == 2 && c->L >= 2;
         prof_begin(c, &e);
         c->ks->hancock_tile(c->v, c->variant, fine ? 1 : 0, c->state_elems, c->max_tiles, -1, 0, 0, c->stream);
         prof_end(c, e);
         std::swap(c->v.Q, c->v.Qs);
         c->qswap ^= 1;
-        if (fine && !seq_restrict(c, ARR_Q, true, false, true)) seq_ghost(c, ARR_Q);
+        if (c->L >= 2 && !seq_restrict(c, ARR_Q, true, false, fine)) seq_ghost(c, ARR_Q);
         if (details) seq_details(c);
         return;
     }
@@ -701,7 +700,8 @@ bool variant_ok(const eu_ctx *c, int var)
 {
     if (var < 0 || var >= FV_VARIANTS) return false;
     if (c->cfg.scheme == EU_SCHEME_AMR) {
-        const bool tile = var < HANCOCK_TILE_VARIANTS, strip = strip_variant(var) && !strip_fused(var);
+        const bool tile = var < hancock_tile_variants(c->dim);
+        const bool strip = c->dim == 2 && strip_variant(var) && !strip_fused(var);
         return c->mode == MODE_BATCH ? strip : c->L > 1 || c->v.lts ? tile : tile || strip;
     }
     if (!strip_variant(var)) return true;
@@ -764,7 +764,8 @@ void fv_pass(eu_ctx *c, int var, int *launches)
         c->ks->fv_strip3(c->v, wv, 0, 2, c->strips, c->nstrips, c->v.Q, c->v.Q, c->v.Qs, 1.0, c->stream);
         *launches = 2;
     } else if (c->cfg.scheme == EU_SCHEME_AMR && !strip_variant(var)) {
-        c->ks->hancock_tile(c->v, var, c->L >= 2 ? 1 : 0, c->state_elems, c->max_tiles, -1, 0, 0, c->stream);
+        c->ks->hancock_tile(c->v, var, c->dim == 2 && c->L >= 2 ? 1 : 0, c->state_elems, c->max_tiles, -1, 0, 0,
+                            c->stream);
         *launches = 1;
     } else if (c->cfg.scheme == EU_SCHEME_AMR) {
         c->ks->hancock_strip(c->v, 2, c->strips, c->nstrips, c->v.Q, c->v.Qs, c->stream);
@@ -1097,7 +1098,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     // the AMR scheme runs on the Hancock strip kernel (grids of one level)
     // or the Hancock tile kernel (hierarchies)
     if (cfg->scheme == EU_SCHEME_AMR) {
-        c->variant = c->L > 1 || c->v.lts ? 0 : FV_STRIP0;
+        c->variant = c->L > 1 || c->v.lts || c->dim == 3 ? 0 : FV_STRIP0;
         if ((r = strips_for(c, c->variant))) {
             delete c;
             return r;

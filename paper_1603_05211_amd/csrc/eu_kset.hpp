@@ -36,9 +36,10 @@ inline int strip3_waves(int var) { return (var - FV_STRIP0) % 2 ? 16 : 8; }
 inline int strip3_planes(int var) { return var >= FV_STRIP0 + 2 ? 64 : 32; }
 inline int strip_width(bool fused) { return fused ? 56 : 60; }   // columns written per strip
 inline int strip_halo(bool fused) { return fused ? 4 : 2; }
-// The AMR scheme on a 2D hierarchy runs the Hancock tile kernel: schedules
-// 0, 1, 2 with 128, 192, 256 threads per tile.
-constexpr int HANCOCK_TILE_VARIANTS = 3;
+// The AMR scheme on a hierarchy runs the Hancock tile kernel: schedules 0,
+// 1, 2 with 128, 192, 256 threads per tile in 2D; 0, 1 with 256, 512 in 3D
+// (its LDS holds one tile per CU).
+inline int hancock_tile_variants(int dim) { return dim == 2 ? 3 : 2; }
 
 struct KSet {
     size_t elem;  // bytes per state value
@@ -68,8 +69,8 @@ struct KSet {
     // the AMR scheme's MUSCL-Hancock step over count strips (src -> out)
     void (*hancock_strip)(const View &, int cfl, const Strip *list, int count, const void *src, void *out,
                           hipStream_t);
-    // the AMR scheme's MUSCL-Hancock step (Q -> Qs) on every leaf of a 2D
-    // hierarchy (lvl < 0; past t_end the whole state of nstate elements is
+    // the AMR scheme's MUSCL-Hancock step (Q -> Qs) on every leaf of a
+    // hierarchy or uniform grid (lvl < 0; past t_end the whole state of nstate elements is
     // copied) or on the patches of level lvl (local time stepping; record:
     // flux registers of substep sub)
     void (*hancock_tile)(const View &, int variant, int fineproj, int64_t nstate, int maxtiles, int lvl, int sub,

@@ -153,9 +153,15 @@ template <typename T> void hancock_strip(const View &v, int cfl, const Strip *li
 template <typename T> void hancock_tile(const View &v, int variant, int fineproj, int64_t nstate, int maxt, int lvl,
                                         int sub, int record, hipStream_t s)
 {
-    const int nblk = xcd_grid(maxt, 2048);
     const T *src = (const T *)v.Q;
     T *out = (T *)v.Qs;
+    if (v.dim == 3) {
+        const int nb3 = xcd_grid(maxt, 16384);
+        if (variant == 1) k_hancock_tile3<T, 512><<<nb3, 512, 0, s>>>(v, src, out, nstate, lvl, sub, record);
+        else k_hancock_tile3<T, 256><<<nb3, 256, 0, s>>>(v, src, out, nstate, lvl, sub, record);
+        return;
+    }
+    const int nblk = xcd_grid(maxt, 2048);
     switch (variant) {
     case 1: k_hancock_tile<T, 192><<<nblk, 192, 0, s>>>(v, src, out, fineproj, nstate, lvl, sub, record); break;
     case 2: k_hancock_tile<T, 256><<<nblk, 256, 0, s>>>(v, src, out, fineproj, nstate, lvl, sub, record); break;

@@ -129,16 +129,16 @@ def test_method_calls_take_their_arguments():
         assert decl in text, decl
 
 
-@pytest.mark.parametrize("kw", [dict(scheme=2), dict(scheme=1, dim=3, n0=32, levels=1),
-                                dict(scheme=1, dim=3, n0=32, levels=3, time_mode=1)])
+@pytest.mark.parametrize("kw", [dict(scheme=2), dict(scheme=-1)])
 def test_scheme_checks(kw):
-    """The AMR scheme (MUSCL-Hancock, AUSMDV) runs in 2D: on grids of one
-    level and on hierarchies, with global or local time steps."""
+    """The AMR scheme (MUSCL-Hancock, AUSMDV) runs on grids of one level and
+    on hierarchies, with global or local time steps, in 2D and 3D."""
     base = dict(levels=1, n0=64)
     base.update(kw)
     r, _, _ = sizes(cfg(**base))
     assert r == _abi.EU_EINVAL
-    for ok in (dict(levels=1, n0=64), dict(levels=5, n0=32), dict(levels=4, n0=32, time_mode=1)):
+    for ok in (dict(levels=1, n0=64), dict(levels=5, n0=32), dict(levels=4, n0=32, time_mode=1),
+               dict(dim=3, levels=1, n0=32, lo=-1.0), dict(dim=3, levels=3, n0=16, lo=-1.0, time_mode=1)):
         r, _, _ = sizes(cfg(scheme=1, **ok))
         assert r == _abi.EU_OK
 
