@@ -203,19 +203,19 @@ def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 
     return out
 
 
-ADAPTIVE_3D = ("MR", "MRLT")
+ADAPTIVE_3D = ("MR", "MRLT", "AMR", "AMRLT")
 
 
 def run_study_3d(levels=(3, 4, 5), n0: int = 32, n_ref: int = 1024, t_end: float = 0.28, cfl: float = 0.4,
-                 eps: float = 0.013, log=None) -> dict:
+                 eps: float = 0.013, eps_grad: float = 0.05, log=None) -> dict:
     """The 3D ellipsoidal shock of Sec. 4.2 as printed (inputs.paper_ellipsoid:
     Omega = [-2,2]^3, outflow, t_e = 0.28, r_c = 3/5, a = 1/3, b = 1, c = 3,
     the printed densities and energy densities): a uniform FP64 reference of
     the MR scheme on n_ref^3, then for every number of levels L (finest grid
-    N = n0 2^(L-1)) MR-FV (the MR scheme on the uniform N^3 grid), MR (MR
-    criterion eps = 0.013, the paper's 3D threshold, global step) and MRLT
-    (the same with local time steps), all FP64.  The AMR scheme runs in 2D
-    only, so the AMR rows of the paper's 3D tables have no counterpart."""
+    N = n0 2^(L-1)) the six discretizations, all FP64: MR-FV and AMR-FV on
+    the uniform N^3 grid, MR and MRLT (MR criterion eps = 0.013, the paper's
+    3D threshold), AMR and AMRLT (scaled gradients of density and pressure,
+    eps_grad = 0.05 each, the paper's 3D thresholds)."""
     log = log or (lambda *a: None)
     e = inputs.paper_ellipsoid()
     lo, hi = -2.0, 2.0
@@ -236,23 +236,29 @@ def run_study_3d(levels=(3, 4, 5), n0: int = 32, n_ref: int = 1024, t_end: float
         N = n0 << (L - 1)
         NC = N ** 3
         rr = project(rho_ref[None], N)[0]
-        log(f"L = {L}: MR-FV {N}^3")
-        fv, t_fv, steps_fv = _timed_run(
-            lambda: Solver(3, n0=N, levels=1, precision=EU_FP64, cfl=cfl, t_end=t_end, lo=lo, hi=hi), init, t_end)
-        row = {"levels": L, "N": N,
-               "MR-FV": {"l1": l1_error(fv.level(0)[0], rr, lo, hi), "gpu_s": t_fv, "steps": steps_fv}}
-        fv.close()
-        for name, tm in (("MR", EU_DT_GLOBAL), ("MRLT", EU_DT_LTS)):
+        row = {"levels": L, "N": N}
+        for name, sch in (("MR-FV", EU_SCHEME_MR), ("AMR-FV", EU_SCHEME_AMR)):
+            log(f"L = {L}: {name} {N}^3")
+            fv, t_fv, steps_fv = _timed_run(
+                lambda: Solver(3, n0=N, levels=1, precision=EU_FP64, cfl=cfl, t_end=t_end, lo=lo, hi=hi, scheme=sch),
+                init, t_end, log)
+            row[name] = {"l1": l1_error(fv.level(0)[0], rr, lo, hi), "gpu_s": t_fv, "steps": steps_fv}
+            fv.close()
+        variants = (("MR", EU_SCHEME_MR, EU_CRIT_MR, eps, 0.0, EU_DT_GLOBAL, "MR-FV"),
+                    ("MRLT", EU_SCHEME_MR, EU_CRIT_MR, eps, 0.0, EU_DT_LTS, "MR-FV"),
+                    ("AMR", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, eps_grad, EU_DT_GLOBAL, "AMR-FV"),
+                    ("AMRLT", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, eps_grad, EU_DT_LTS, "AMR-FV"))
+        for name, sch, crit, e_r, e_p, tm, base in variants:
             log(f"  {name}")
-            mk = lambda: Solver(3, n0=n0, levels=L, precision=EU_FP64, cfl=cfl, t_end=t_end, eps=eps, eta=0.8,
-                                patch_max=32, time_mode=tm, lo=lo, hi=hi)
-            s, t_a, steps_a = _timed_run(mk, init, t_end)
+            mk = lambda: Solver(3, n0=n0, levels=L, precision=EU_FP64, cfl=cfl, t_end=t_end, eps=e_r, eta=0.8,
+                                patch_max=32, time_mode=tm, lo=lo, hi=hi, scheme=sch, criterion=crit, eps_p=e_p)
+            s, t_a, steps_a = _timed_run(mk, init, t_end, log)
             e_a = l1_error(s.composite()[0], rr, lo, hi)
             sub = 2 ** (L - 1) if tm == EU_DT_LTS else 1
             leaves, cells = _history(s, init, t_end, sub)
             s.close()
-            f = row["MR-FV"]
-            row[name] = {"threshold": eps, "l1": e_a, "gpu_s": t_a, "steps": steps_a, "finest_steps": len(leaves),
+            f = row[base]
+            row[name] = {"threshold": e_r, "l1": e_a, "gpu_s": t_a, "steps": steps_a, "finest_steps": len(leaves),
                          "accuracy_perturbation": accuracy_perturbation(f["l1"], e_a),
                          "memory_compression": memory_compression(cells, NC),
                          "mesh_compression": mesh_compression(leaves, NC),
@@ -261,7 +267,7 @@ def run_study_3d(levels=(3, 4, 5), n0: int = 32, n_ref: int = 1024, t_end: float
         out["runs"].append(row)
     for k in range(1, len(out["runs"])):
         a, b = out["runs"][k - 1], out["runs"][k]
-        for name in ("MR-FV",) + ADAPTIVE_3D:
+        for name in ("MR-FV", "AMR-FV") + ADAPTIVE_3D:
             b[name]["rate"] = math.log2(a[name]["l1"] / b[name]["l1"])
     return out
 
@@ -304,7 +310,7 @@ def main(argv=None):
         given = lambda name: any(x == name or x.startswith(name + "=") for x in (argv or sys.argv[1:]))
         res = run_study_3d(tuple(a.levels) if given("--levels") else (3, 4, 5), a.n0,
                            a.ref if given("--ref") else 1024, a.t_end if given("--t-end") else 0.28,
-                           eps=a.eps if given("--eps") else 0.013, log=log)
+                           eps=a.eps if given("--eps") else 0.013, eps_grad=a.eps_grad, log=log)
         log(markdown(res))
         print(json.dumps(res), flush=True)
         return
