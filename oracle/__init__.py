@@ -102,6 +102,7 @@ def lib():
             "orc_ausmdv": (None, [C.c_int, C.c_double, C.c_int, dp, dp, dp]),
             "orc_phys_flux": (None, [C.c_int, C.c_double, C.c_int, dp, dp]),
             "orc_h_set_scheme": (C.c_int, [vp, C.c_int]),
+            "orc_h_set_eps_levels": (None, [vp, C.c_int]),
             "orc_h_set_criterion": (C.c_int, [vp, C.c_int, C.c_double]),
             "orc_restrict": (None, [C.c_int, C.c_int, C.c_int, dp, dp]),
             "orc_predict": (None, [C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]),
@@ -282,7 +283,7 @@ class Hierarchy:
     def __init__(self, dim: int, levels: int, n0: int, bc: int = BC_TRANSMISSIVE,
                  gamma: float = 1.4, lo: float = 0.0, hi: float = 1.0, eps: float = 1e-3,
                  eta: float = 0.8, pmin: int = 8, pmax: int = 32, scheme: int = SCHEME_MR,
-                 criterion: int = CRIT_MR, eps_p: float = 0.0):
+                 criterion: int = CRIT_MR, eps_p: float = 0.0, eps_levels: bool = False):
         self.dim, self.L, self.n0, self.bc = dim, levels, n0, bc
         self.gamma, self.lo, self.hi, self.eps, self.eta = gamma, lo, hi, eps, eta
         self.pmin, self.pmax = pmin, pmax
@@ -296,6 +297,8 @@ class Hierarchy:
         if lib().orc_h_set_criterion(self._h, criterion, eps_p) != 0:
             raise ValueError("unknown refinement criterion")
         self.criterion, self.eps_p = criterion, eps_p
+        lib().orc_h_set_eps_levels(self._h, int(eps_levels))
+        self.eps_levels = bool(eps_levels)
         self.t = 0.0
 
     def __del__(self):

@@ -516,6 +516,7 @@ typedef struct {
     int crit;            /* refinement criterion: 0 MR details (Sec. 2.1), 1 the
                             scaled-gradient indicators of the AMR method (Sec. 2.2) */
     double eps_p;        /* criterion 1: pressure threshold (<= 0: density only) */
+    int eps_levels;      /* criterion 0: 1 = level-dependent thresholds (eps_at) */
 } orc_h;
 
 static int64_t hN(const orc_h *h, int l) { return ncells(h->dim, h->n[l]); }
@@ -893,6 +894,15 @@ static void h_gradient(orc_h *h)
     }
 }
 
+/* Threshold of the details of level l: eps, or with level-dependent
+ * thresholds eps_l = 2^(d (l + 2 - L)) eps, eps on the finest details
+ * (l = L-2) and halved d times per coarser level (Harten's scaling of the
+ * thresholds with the cell volume). */
+static double eps_at(const orc_h *h, int l)
+{
+    return h->eps_levels ? ldexp(h->eps, h->dim * (l + 2 - h->L)) : h->eps;
+}
+
 static void h_details(orc_h *h)
 {
     if (h->crit == 1) {
@@ -920,7 +930,7 @@ static void h_details(orc_h *h)
                 if (dd > Dm) Dm = dd;
             }
             h->D[l][i] = Dm;
-            h->sig[l][i] = Dm >= h->eps;
+            h->sig[l][i] = Dm >= eps_at(h, l);
         }
     }
 }
@@ -1116,6 +1126,7 @@ void orc_h_analyse(orc_h *h) { h_details(h); }
 
 /* Replace the detail threshold (same on every level) for later analyses. */
 void orc_h_set_eps(orc_h *h, double eps) { h->eps = eps; }
+void orc_h_set_eps_levels(orc_h *h, int on) { h->eps_levels = on != 0; }
 
 int orc_h_npatch(const orc_h *h) { return h->npatch; }
 
