@@ -115,6 +115,12 @@ typedef struct {
                             hierarchies (levels >= 2) only                    */
     double eps_p;        /* EU_CRIT_GRADIENT: pressure threshold (<= 0: the
                             density alone)                                    */
+    int eps_levels;      /* EU_CRIT_MR: 0 (the paper's runs) eps on every
+                            level; 1 level-dependent thresholds eps_l =
+                            2^(d (l + 2 - L)) eps for the details of level
+                            l = 0 .. L-2 (eps on the finest details, halved
+                            d times per coarser level, as in Harten's MR
+                            analysis)                                         */
 } eu_config;
 
 /* Initial data (Sec. 4.1 four-quadrant Riemann problem, Sec. 4.2 ellipsoid,

@@ -46,7 +46,8 @@ class Solver:
                  eps: float = 1e-3, eta: float = 0.8, patch_min: int = 8, patch_max: int = 32,
                  lo: float = 0.0, hi: float = 1.0, gamma: float = 1.4, sides=None,
                  time_mode: int = EU_DT_GLOBAL, device: str = "cuda:0", stream=None,
-                 scheme: int = EU_SCHEME_MR, criterion: int = EU_CRIT_MR, eps_p: float = 0.0):
+                 scheme: int = EU_SCHEME_MR, criterion: int = EU_CRIT_MR, eps_p: float = 0.0,
+                 eps_levels: int = 0):
         import torch
         self._lib = _abi.load()
         self.torch = torch
@@ -65,6 +66,7 @@ class Solver:
         self.scheme = scheme
         cfg.criterion, cfg.eps_p = criterion, eps_p
         self.criterion, self.eps_p = criterion, eps_p
+        cfg.eps_levels = eps_levels
         if sides is not None:
             self._sides = (C.c_int32 * len(sides))(*[int(s) for s in sides])
             cfg.n_instances = len(sides)

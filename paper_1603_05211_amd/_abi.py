@@ -31,7 +31,7 @@ class EuConfig(C.Structure):
         ("eta", C.c_double), ("patch_min", C.c_int), ("patch_max", C.c_int),
         ("time_mode", C.c_int), ("n_instances", C.c_int),
         ("inst_side_host", C.POINTER(C.c_int32)), ("stream", C.c_void_p), ("scheme", C.c_int),
-        ("criterion", C.c_int), ("eps_p", C.c_double),
+        ("criterion", C.c_int), ("eps_p", C.c_double), ("eps_levels", C.c_int),
     ]
 
 

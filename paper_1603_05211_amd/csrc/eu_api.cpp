@@ -138,6 +138,11 @@ int validate(const eu_config *c, std::string &why)
         return EU_EINVAL;
     }
     if (std::isnan(c->eps_p)) { why = "eps_p is NaN"; return EU_EINVAL; }
+    if (c->eps_levels != 0 && c->eps_levels != 1) { why = "eps_levels must be 0 or 1"; return EU_EINVAL; }
+    if (c->eps_levels && c->criterion != EU_CRIT_MR) {
+        why = "level-dependent thresholds apply to the MR criterion";
+        return EU_EINVAL;
+    }
 
     if (c->time_mode == EU_DT_LTS && c->n_instances > 1) { why = "a batch has no levels to step locally"; return EU_EINVAL; }
     if (c->n_instances > 1) {
@@ -947,6 +952,13 @@ int finish_init(eu_ctx *c)
 // ============================================================================
 extern "C" {
 
+// Thresholds of the details of levels 0 .. L-2: eps, or with eps_levels set
+// eps_l = 2^(d (l + 2 - L)) eps (exact powers of two).
+static void set_eps_levels(View &v, int L, int dim, double eps, int mode)
+{
+    for (int l = 0; l < MAXLEV; ++l) v.eps_lv[l] = mode ? std::ldexp(eps, dim * (l + 2 - L)) : eps;
+}
+
 int eu_query_sizes(const eu_config *cfg, size_t *state_bytes, size_t *scratch_bytes)
 {
     std::string why;
@@ -1003,6 +1015,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.cfl = cfg->cfl;
     v.t_end = cfg->t_end;
     v.eps = cfg->eps;
+    set_eps_levels(v, lay.L, cfg->dim, cfg->eps, cfg->eps_levels);
     v.crit = cfg->criterion;
     v.eps_p = cfg->eps_p;
     v.eta = cfg->eta;
@@ -1183,6 +1196,7 @@ int eu_mr_flag(eu_ctx *c, double eps, int64_t *nflag_host)
         // decomposition is taken again against it, and kept for later steps
         c->v.eps = eps;
         c->cfg.eps = eps;
+        set_eps_levels(c->v, c->L, c->dim, eps, c->cfg.eps_levels);
         drop_graphs(c);
         int64_t n = 0;
         for (int l = 0; l < c->L - 1; ++l) n += c->grids[l].ncell;

@@ -84,6 +84,7 @@ struct View {
     double gamma, cfl, t_end, eps, eta;
     int crit;                         // refinement criterion: 0 MR details, 1 scaled gradients
     double eps_p;                     // gradient criterion: pressure threshold (<= 0: none)
+    double eps_lv[MAXLEV];            // MR criterion: threshold of the details of each level
     const Grid *grids;                // device copy of the grid table
     Grid gt[MAXLEV];                  // the first MAXLEV grids (every level of a hierarchy), by
                                       // value: kernels read them with their arguments

@@ -1240,7 +1240,7 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
                 const double Dm = act && cov ? detail_lds<T>(sS, sC, lx, ly) : 0.0;
                 const int64_t j = G.coff + gidx(G.n, ox + lx, oy + ly, 0);
                 v.D[j] = Dm;
-                v.sig[j] = Dm >= v.eps ? 1 : 0;
+                v.sig[j] = Dm >= v.eps_lv[k] ? 1 : 0;
                 __syncthreads();
                 continue;
             }
@@ -1267,7 +1267,7 @@ __global__ void __launch_bounds__(64) k_restrict2(View v, T *A, int lvl, int nle
                     }
                 }
                 v.D[j] = Dm;
-                v.sig[j] = Dm >= v.eps ? 1 : 0;
+                v.sig[j] = Dm >= v.eps_lv[k] ? 1 : 0;
             }
             continue;
         }
@@ -1718,7 +1718,7 @@ __global__ void __launch_bounds__(256) k_details(View v, const T *__restrict__ Q
             }
         }
         v.D[j] = Dm;
-        v.sig[j] = Dm >= v.eps ? 1 : 0;
+        v.sig[j] = Dm >= v.eps_lv[lvl] ? 1 : 0;
     }
 }
 

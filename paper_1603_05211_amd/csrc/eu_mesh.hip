@@ -972,12 +972,15 @@ __global__ void k_copy_f64(double *dst, const double *src, int n)
     if (i < n) dst[i] = src[i];
 }
 
-// Significance of every detail against the threshold (levels 0 .. L-2, the
-// per-cell arrays of the MR analysis): D >= eps.
+// Significance of every detail against the threshold of its level (levels
+// 0 .. L-2, the per-cell arrays of the MR analysis): D >= eps_l.
 __global__ void k_threshold(View v, int64_t ncell)
 {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ncell; j += (int64_t)gridDim.x * blockDim.x)
-        v.sig[j] = v.D[j] >= v.eps ? 1 : 0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ncell; j += (int64_t)gridDim.x * blockDim.x) {
+        int k = 0;
+        for (int q = 1; q < MAXLEV && q < v.L - 1; ++q) k += j >= v.gt[q].coff ? 1 : 0;
+        v.sig[j] = v.D[j] >= v.eps_lv[k] ? 1 : 0;
+    }
 }
 
 __global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t val)
