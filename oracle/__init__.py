@@ -102,6 +102,8 @@ def lib():
             "orc_ausmdv": (None, [C.c_int, C.c_double, C.c_int, dp, dp, dp]),
             "orc_phys_flux": (None, [C.c_int, C.c_double, C.c_int, dp, dp]),
             "orc_h_set_scheme": (C.c_int, [vp, C.c_int]),
+            "orc_h_set_variants": (C.c_int, [vp, C.c_int, C.c_int]),
+            "orc_ausm_plus_speed": (None, [C.c_int, C.c_double, C.c_int, dp, dp, dp, C.c_int]),
             "orc_h_set_eps_levels": (None, [vp, C.c_int]),
             "orc_h_set_criterion": (C.c_int, [vp, C.c_int, C.c_double]),
             "orc_restrict": (None, [C.c_int, C.c_int, C.c_int, dp, dp]),
@@ -151,6 +153,8 @@ def lib():
 PLANT_NONE, PLANT_AUSM_AB, PLANT_PRED_ZSWAP, PLANT_LTS_THETA = 0, 1, 2, 3
 PLANT_AUSMDV_ALPHA, PLANT_HANCOCK_NOPRED, PLANT_NO_FINE_MEAN = 4, 5, 6
 SCHEME_MR, SCHEME_AMR = 0, 1
+RK_MIDPOINT, RK_HEUN = 0, 1
+AUSM_MEAN, AUSM_CRITICAL = 0, 1
 CRIT_MR, CRIT_GRADIENT = 0, 1
 
 
@@ -198,10 +202,14 @@ def cons2prim(dim: int, gamma: float, Q: np.ndarray) -> np.ndarray:
     return W
 
 
-def ausm_plus(dim: int, gamma: float, axis: int, wL, wR) -> np.ndarray:
+def ausm_plus(dim: int, gamma: float, axis: int, wL, wR, speed: int = AUSM_MEAN) -> np.ndarray:
+    """AUSM+ across a face; speed selects the interface sound speed."""
     wL, wR = _f64(wL), _f64(wR)
     F = np.empty(dim + 2)
-    lib().orc_ausm_plus(dim, gamma, axis, _dp(wL), _dp(wR), _dp(F))
+    if speed == AUSM_MEAN:
+        lib().orc_ausm_plus(dim, gamma, axis, _dp(wL), _dp(wR), _dp(F))
+    else:
+        lib().orc_ausm_plus_speed(dim, gamma, axis, _dp(wL), _dp(wR), _dp(F), speed)
     return F
 
 
@@ -283,7 +291,8 @@ class Hierarchy:
     def __init__(self, dim: int, levels: int, n0: int, bc: int = BC_TRANSMISSIVE,
                  gamma: float = 1.4, lo: float = 0.0, hi: float = 1.0, eps: float = 1e-3,
                  eta: float = 0.8, pmin: int = 8, pmax: int = 32, scheme: int = SCHEME_MR,
-                 criterion: int = CRIT_MR, eps_p: float = 0.0, eps_levels: bool = False):
+                 criterion: int = CRIT_MR, eps_p: float = 0.0, eps_levels: bool = False, rk: int = RK_MIDPOINT,
+                 ausm_speed: int = AUSM_MEAN):
         self.dim, self.L, self.n0, self.bc = dim, levels, n0, bc
         self.gamma, self.lo, self.hi, self.eps, self.eta = gamma, lo, hi, eps, eta
         self.pmin, self.pmax = pmin, pmax
@@ -299,6 +308,9 @@ class Hierarchy:
         self.criterion, self.eps_p = criterion, eps_p
         lib().orc_h_set_eps_levels(self._h, int(eps_levels))
         self.eps_levels = bool(eps_levels)
+        if lib().orc_h_set_variants(self._h, rk, ausm_speed) != 0:
+            raise ValueError("unknown time stepping or AUSM+ sound speed")
+        self.rk, self.ausm_speed = rk, ausm_speed
         self.t = 0.0
 
     def __del__(self):
@@ -381,6 +393,8 @@ class Hierarchy:
         """One level-0 step with local time steps; returns (dt_0, leaf updates)."""
         upd = C.c_int64(0)
         dt = lib().orc_h_step_lts(self._h, cfl, self.t, t_end, int(regrid), C.byref(upd))
+        if dt == -2.0:
+            raise ValueError("local time steps use the midpoint rule")
         if dt < 0:
             raise MemoryError("oracle: local time stepping buffers")
         self.t = self.t + dt

@@ -124,16 +124,37 @@ static double slope_va(double wm, double w0, double wp)
 
 /* AUSM+ flux-vector splitting (Liou 1996; Sec. 2, MR scheme) across a face
  * with normal along axis dn.  wL / wR are the primitive face states.
- * Interface sound speed: arithmetic mean; alpha = 3/16, beta = 1/8. */
+ * Interface sound speed (speed): 0 the arithmetic mean of the two sound
+ * speeds (the runs of this build); 1 Liou's critical speed, c_1/2 =
+ * min(c*_L^2 / max(c*_L, u_L), c*_R^2 / max(c*_R, -u_R)) with c*^2 =
+ * 2 (gamma - 1) / (gamma + 1) H, H the total enthalpy (a variant).
+ * alpha = 3/16, beta = 1/8. */
 static void ausm_plus(int dim, double g, int dn, const double *wL,
-                      const double *wR, double *F)
+                      const double *wR, double *F, int speed)
 {
     double gi = 1.0 / (g - 1.0);
     double rL = wL[0], pL = wL[dim + 1], uL = wL[1 + dn];
     double rR = wR[0], pR = wR[dim + 1], uR = wR[1 + dn];
-    double cL = sqrt((g * pL) / rL);
-    double cR = sqrt((g * pR) / rR);
-    double ch = 0.5 * (cL + cR);
+    double ch;
+    if (speed == 1) {
+        double KL = 0.0, KR = 0.0;
+        for (int k = 0; k < dim; ++k) {
+            KL = KL + wL[1 + k] * wL[1 + k];
+            KR = KR + wR[1 + k] * wR[1 + k];
+        }
+        double HL = ((pL * gi + (0.5 * rL) * KL) + pL) / rL;
+        double HR = ((pR * gi + (0.5 * rR) * KR) + pR) / rR;
+        double kc = (2.0 * (g - 1.0)) / (g + 1.0);
+        double sL = kc * HL, sR = kc * HR;     /* c*^2 */
+        double csL = sqrt(sL), csR = sqrt(sR);
+        double tL = sL / (csL >= uL ? csL : uL);
+        double tR = sR / (csR >= -uR ? csR : -uR);
+        ch = tL <= tR ? tL : tR;
+    } else {
+        double cL = sqrt((g * pL) / rL);
+        double cR = sqrt((g * pR) / rR);
+        ch = 0.5 * (cL + cR);
+    }
     double ML = uL / ch, MR = uR / ch;
     double Mp, Pp, Mm, Pm;
     /* Liou's coefficients alpha = 3/16, beta = 1/8; 16 beta = 2 and
@@ -180,7 +201,7 @@ static void ausm_plus(int dim, double g, int dn, const double *wL,
  * outside the domain) and c + e_dn, from the 4-cell stencil c-1 .. c+2 along
  * dn of array A on an n^d grid: primitive MUSCL face states + AUSM+. */
 static void face_flux(int dim, int n, int bc, double g, const double *A,
-                      int dn, const int *c, double *F)
+                      int dn, const int *c, double *F, int speed)
 {
     int64_t N = ncells(dim, n);
     double w[4][NVMAX], q[NVMAX], wL[NVMAX], wR[NVMAX];
@@ -196,7 +217,7 @@ static void face_flux(int dim, int n, int bc, double g, const double *A,
         wL[f] = w[1][f] + 0.5 * slope_va(w[0][f], w[1][f], w[2][f]);
         wR[f] = w[2][f] - 0.5 * slope_va(w[1][f], w[2][f], w[3][f]);
     }
-    ausm_plus(dim, g, dn, wL, wR, F);
+    ausm_plus(dim, g, dn, wL, wR, F, speed);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -446,7 +467,12 @@ void orc_cons2prim(int dim, double g, int64_t ncell, const double *Q, double *W)
 /* AUSM+ flux of a single face; wL, wR primitive (nv values each). */
 void orc_ausm_plus(int dim, double g, int dn, const double *wL, const double *wR, double *F)
 {
-    ausm_plus(dim, g, dn, wL, wR, F);
+    ausm_plus(dim, g, dn, wL, wR, F, 0);
+}
+
+void orc_ausm_plus_speed(int dim, double g, int dn, const double *wL, const double *wR, double *F, int speed)
+{
+    ausm_plus(dim, g, dn, wL, wR, F, speed);
 }
 
 double orc_slope(double wm, double w0, double wp) { return slope_va(wm, w0, wp); }
@@ -517,6 +543,8 @@ typedef struct {
                             scaled-gradient indicators of the AMR method (Sec. 2.2) */
     double eps_p;        /* criterion 1: pressure threshold (<= 0: density only) */
     int eps_levels;      /* criterion 0: 1 = level-dependent thresholds (eps_at) */
+    int rk;              /* MR scheme time stepping: 0 the midpoint rule, 1 Heun */
+    int ausm_speed;      /* MR scheme: AUSM+ interface sound speed (ausm_plus) */
 } orc_h;
 
 static int64_t hN(const orc_h *h, int l) { return ncells(h->dim, h->n[l]); }
@@ -687,7 +715,7 @@ void orc_h_ghost(orc_h *h) { h_ghost(h, h->Q); }
 static void level_flux(const orc_h *h, int n, const double *A, int dn, const int *c, double hl, double *F)
 {
     if (h->scheme == 1) face_flux_hancock(h->dim, n, h->bc, h->g, A, dn, c, hl, F);
-    else face_flux(h->dim, n, h->bc, h->g, A, dn, c, F);
+    else face_flux(h->dim, n, h->bc, h->g, A, dn, c, F, h->ausm_speed);
 }
 
 /* Flux across the face between coarse cell p (level l) and its covered
@@ -728,9 +756,10 @@ static void flux_fine_mean(const orc_h *h, int l, double **src, int dn,
  *   out = base - lam * ((dF_1 + dF_2) + dF_3),  dF_d = F_{+1/2} - F_{-1/2},
  * the semi-discrete form dQ/dt = -F(Q) of Sec. 2 with fluxes from src.
  * A face next to a covered cell takes the fine-flux mean (flux_fine_mean).
- * dt: the step, for the AMR scheme's half-step predictor of each level. */
+ * dt: the step, for the AMR scheme's half-step predictor of each level.
+ * blend (Heun's second stage): the base is (base + src) / 2. */
 static void h_fv_level(orc_h *h, int l, double **src, double **base,
-                       double **out, double lam, double dt)
+                       double **out, double lam, double dt, int blend)
 {
     int dim = h->dim, n = h->n[l], nv = h->nv;
     int64_t N = hN(h, l);
@@ -764,7 +793,8 @@ static void h_fv_level(orc_h *h, int l, double **src, double **base,
         for (int f = 0; f < nv; ++f) {
             double R = dF[0][f] + dF[1][f];
             if (dim == 3) R = R + dF[2][f];
-            out[l][f * N + i] = base[l][f * N + i] - lam * R;
+            double b = blend ? 0.5 * (base[l][f * N + i] + src[l][f * N + i]) : base[l][f * N + i];
+            out[l][f * N + i] = b - lam * R;
         }
     }
 }
@@ -1147,24 +1177,49 @@ void orc_h_patches(const orc_h *h, int32_t *out)
 
 /* One explicit stage on every level (FV on leaves, projection onto covered
  * cells).  Ghost cells are filled separately. */
-static void h_stage(orc_h *h, double **src, double **out, double dt, double fac)
+static void h_stage(orc_h *h, double **src, double **out, double dt, double fac, int blend)
 {
     for (int l = 0; l < h->L; ++l) {
         double lam = (dt * fac) / h->dx[l];
-        h_fv_level(h, l, src, h->Q, out, lam, dt);
+        h_fv_level(h, l, src, h->Q, out, lam, dt, blend);
     }
     h_restrict(h, out);
+}
+
+/* The two stages of the MR scheme's RK2 step (Sec. 2), each followed by the
+ * projection and the ghost fill:
+ *   midpoint rule: Q* = Q - (dt/2) F(Q),  Q <- Q - dt F(Q*);
+ *   Heun (a variant): Q* = Q - dt F(Q),  Q <- (Q + Q*)/2 - (dt/2) F(Q*). */
+static void rk_stage1(orc_h *h, double dt)
+{
+    h_stage(h, h->Q, h->Qs, dt, h->rk ? 1.0 : 0.5, 0);
+    h_ghost(h, h->Qs);
+}
+
+static void rk_stage2(orc_h *h, double dt)
+{
+    h_stage(h, h->Qs, h->Q, dt, h->rk ? 0.5 : 1.0, h->rk);
 }
 
 void orc_h_stage(orc_h *h, int stage, double dt)
 {
     if (stage == 1) {
-        h_stage(h, h->Q, h->Qs, dt, 0.5);
-        h_ghost(h, h->Qs);
+        rk_stage1(h, dt);
     } else {
-        h_stage(h, h->Qs, h->Q, dt, 1.0);
+        rk_stage2(h, dt);
         h_ghost(h, h->Q);
     }
+}
+
+/* Variants of the MR scheme: time stepping rk (0 midpoint, 1 Heun) and the
+ * AUSM+ interface sound speed (0 mean, 1 critical).  Returns 0, or -1 for
+ * an unknown value. */
+int orc_h_set_variants(orc_h *h, int rk, int ausm_speed)
+{
+    if ((rk != 0 && rk != 1) || (ausm_speed != 0 && ausm_speed != 1)) return -1;
+    h->rk = rk;
+    h->ausm_speed = ausm_speed;
+    return 0;
 }
 
 /* One step of the AMR scheme (Sec. 2: MUSCL-Hancock, a single corrector
@@ -1178,7 +1233,7 @@ void orc_h_stage(orc_h *h, int stage, double dt)
 static void h_hancock(orc_h *h, double dt)
 {
     for (int l = 0; l < h->L; ++l)
-        h_fv_level(h, l, h->Q, h->Q, h->Qs, dt / h->dx[l], dt);
+        h_fv_level(h, l, h->Q, h->Q, h->Qs, dt / h->dx[l], dt, 0);
     for (int l = 0; l < h->L; ++l) {
         int64_t N = hN(h, l);
         for (int64_t i = 0; i < N; ++i)
@@ -1231,9 +1286,8 @@ double orc_h_step(orc_h *h, double cfl, double t, double t_end, int regrid)
         }
         return dt;
     }
-    h_stage(h, h->Q, h->Qs, dt, 0.5);
-    h_ghost(h, h->Qs);
-    h_stage(h, h->Qs, h->Q, dt, 1.0);
+    rk_stage1(h, dt);
+    rk_stage2(h, dt);
     if (regrid && h->L > 1) h_regrid(h, 1);
     h_ghost(h, h->Q);
     return dt;
@@ -1247,9 +1301,8 @@ void orc_h_step_fixed(orc_h *h, double dt)
         h_ghost(h, h->Q);
         return;
     }
-    h_stage(h, h->Q, h->Qs, dt, 0.5);
-    h_ghost(h, h->Qs);
-    h_stage(h, h->Qs, h->Q, dt, 1.0);
+    rk_stage1(h, dt);
+    rk_stage2(h, dt);
     h_ghost(h, h->Q);
 }
 
@@ -1428,10 +1481,12 @@ static void lts_advance(orc_h *h, int l, double dt, int k)
  * from the leaves, clipped to reach t_end; then the MR coarsening /
  * refinement when regrid is set and a spatial ghost fill.  Returns dt_0;
  * *leaf_updates receives sum over levels of leaves_l 2^l.  -1: out of
- * memory. */
+ * memory; -2: Heun time stepping selected (the cycle uses the midpoint
+ * rule). */
 double orc_h_step_lts(orc_h *h, double cfl, double t, double t_end, int regrid,
                       int64_t *leaf_updates)
 {
+    if (h->rk != 0) return -2.0;   /* the recursive cycle steps with the midpoint rule */
     if (lts_alloc(h)) return -1.0;
     double smax[MAXL];
     orc_h_cfl(h, cfl, t, t_end, smax);
