@@ -61,6 +61,8 @@ enum { EU_RESTRICT = 0, EU_PROLONG = 1, EU_GHOST = 2 }; /* eu_project modes */
 enum { EU_IC_QUADRANT = 0, EU_IC_ELLIPSOID = 1, EU_IC_RIEMANN1D = 2, EU_IC_UNIFORM = 3 };
 enum { EU_SCHEME_MR = 0, EU_SCHEME_AMR = 1 };      /* finite-volume scheme     */
 enum { EU_CRIT_MR = 0, EU_CRIT_GRADIENT = 1 };     /* refinement criterion     */
+enum { EU_RK_MIDPOINT = 0, EU_RK_HEUN = 1 };       /* MR scheme time stepping  */
+enum { EU_AUSM_MEAN = 0, EU_AUSM_CRITICAL = 1 };   /* AUSM+ sound speed        */
 enum { EU_STAGE_SCHEDULES = 10, EU_STRIP_SCHEDULE0 = 6 }; /* see eu_autotune  */
 
 /* Problem size and method parameters (Sec. 2; Sec. 4 for the values used
@@ -121,6 +123,15 @@ typedef struct {
                             l = 0 .. L-2 (eps on the finest details, halved
                             d times per coarser level, as in Harten's MR
                             analysis)                                         */
+    int rk;              /* MR scheme: EU_RK_MIDPOINT (0, the runs of this
+                            build) Q* = Q - dt/2 F(Q), Q <- Q - dt F(Q*);
+                            EU_RK_HEUN: Q* = Q - dt F(Q), Q <- (Q + Q*)/2 -
+                            dt/2 F(Q*) (global time step; tile schedules)     */
+    int ausm_speed;      /* MR scheme: AUSM+ interface sound speed,
+                            EU_AUSM_MEAN (0) the mean of the two sound
+                            speeds; EU_AUSM_CRITICAL Liou's min(c*_L^2 /
+                            max(c*_L, u_L), c*_R^2 / max(c*_R, -u_R)), c*^2
+                            = 2 (gamma-1)/(gamma+1) H (tile schedules)       */
 } eu_config;
 
 /* Initial data (Sec. 4.1 four-quadrant Riemann problem, Sec. 4.2 ellipsoid,
@@ -326,7 +337,8 @@ int eu_kernel_time(eu_ctx *ctx, double *ms_host, int64_t *launches_host);
  * 7 and 9 of 128.  3D: one workgroup per strip of 8 output rows (6, 8) or
  * 16 (7, 9), one wave per row, marching through 32 (6, 7) or 64 (8, 9)
  * planes, y neighbours through LDS; one stage per launch.  The AMR scheme
- * takes the schedules its scheme field names.  In FP64 every schedule gives bit-identical results; in
+ * takes the schedules its scheme field names; the MR-scheme variants (rk,
+ * ausm_speed) run on schedules 0 .. 5.  In FP64 every schedule gives bit-identical results; in
  * FP32 they agree to rounding (the compiler contracts each differently).
  * eu_autotune times each schedule that applies (reps passes of one step's
  * finite-volume work on the current state -- both stages, the second in

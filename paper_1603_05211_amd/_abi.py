@@ -16,6 +16,8 @@ EU_RESTRICT, EU_PROLONG, EU_GHOST = 0, 1, 2
 EU_IC_QUADRANT, EU_IC_ELLIPSOID, EU_IC_RIEMANN1D, EU_IC_UNIFORM = 0, 1, 2, 3
 EU_SCHEME_MR, EU_SCHEME_AMR = 0, 1
 EU_CRIT_MR, EU_CRIT_GRADIENT = 0, 1
+EU_RK_MIDPOINT, EU_RK_HEUN = 0, 1
+EU_AUSM_MEAN, EU_AUSM_CRITICAL = 0, 1
 EU_STAGE_SCHEDULES = 10
 EU_STRIP_SCHEDULE0 = 6
 
@@ -31,7 +33,8 @@ class EuConfig(C.Structure):
         ("eta", C.c_double), ("patch_min", C.c_int), ("patch_max", C.c_int),
         ("time_mode", C.c_int), ("n_instances", C.c_int),
         ("inst_side_host", C.POINTER(C.c_int32)), ("stream", C.c_void_p), ("scheme", C.c_int),
-        ("criterion", C.c_int), ("eps_p", C.c_double), ("eps_levels", C.c_int),
+        ("criterion", C.c_int), ("eps_p", C.c_double), ("eps_levels", C.c_int), ("rk", C.c_int),
+        ("ausm_speed", C.c_int),
     ]
 
 

@@ -139,6 +139,16 @@ int validate(const eu_config *c, std::string &why)
     }
     if (std::isnan(c->eps_p)) { why = "eps_p is NaN"; return EU_EINVAL; }
     if (c->eps_levels != 0 && c->eps_levels != 1) { why = "eps_levels must be 0 or 1"; return EU_EINVAL; }
+    if (c->rk != EU_RK_MIDPOINT && c->rk != EU_RK_HEUN) { why = "bad rk"; return EU_EINVAL; }
+    if (c->ausm_speed != EU_AUSM_MEAN && c->ausm_speed != EU_AUSM_CRITICAL) { why = "bad ausm_speed"; return EU_EINVAL; }
+    if ((c->rk || c->ausm_speed) && c->scheme != EU_SCHEME_MR) {
+        why = "rk and ausm_speed are variants of the MR scheme";
+        return EU_EINVAL;
+    }
+    if (c->rk == EU_RK_HEUN && c->time_mode == EU_DT_LTS) {
+        why = "local time steps use the midpoint rule";
+        return EU_EINVAL;
+    }
     if (c->eps_levels && c->criterion != EU_CRIT_MR) {
         why = "level-dependent thresholds apply to the MR criterion";
         return EU_EINVAL;
@@ -711,6 +721,7 @@ bool variant_ok(const eu_ctx *c, int var)
     }
     if (!strip_variant(var)) return true;
     if (c->L != 1) return false;
+    if (c->v.rk || c->v.ausm_cs) return false;   // the variants run on the tile kernel
     if (c->dim == 3) return true;
     return !strip_fused(var) || c->cfg.bc == EU_BC_TRANSMISSIVE;
 }
@@ -1016,6 +1027,8 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.t_end = cfg->t_end;
     v.eps = cfg->eps;
     set_eps_levels(v, lay.L, cfg->dim, cfg->eps, cfg->eps_levels);
+    v.rk = cfg->rk;
+    v.ausm_cs = cfg->ausm_speed;
     v.crit = cfg->criterion;
     v.eps_p = cfg->eps_p;
     v.eta = cfg->eta;

@@ -85,6 +85,8 @@ struct View {
     int crit;                         // refinement criterion: 0 MR details, 1 scaled gradients
     double eps_p;                     // gradient criterion: pressure threshold (<= 0: none)
     double eps_lv[MAXLEV];            // MR criterion: threshold of the details of each level
+    int rk;                           // MR scheme: 0 midpoint rule, 1 Heun
+    int ausm_cs;                      // AUSM+ interface sound speed: 0 mean, 1 critical
     const Grid *grids;                // device copy of the grid table
     Grid gt[MAXLEV];                  // the first MAXLEV grids (every level of a hierarchy), by
                                       // value: kernels read them with their arguments

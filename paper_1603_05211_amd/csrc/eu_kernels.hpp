@@ -180,14 +180,35 @@ __device__ __forceinline__ T vel_along(const T *w, int dn)
 
 // AUSM+ (Liou 1996) across a face with normal along axis dn; wL, wR are the
 // primitive face states; gi = 1 / (gamma - 1).
+// cs selects the interface sound speed: 0 the mean of the two sound speeds,
+// 1 Liou's critical speed min(c*_L^2 / max(c*_L, u_L), c*_R^2 / max(c*_R,
+// -u_R)), c*^2 = 2 (gamma - 1) / (gamma + 1) H with H the total enthalpy.
 template <typename T, int D>
-__device__ __forceinline__ void ausm_plus(T g, T gi, int dn, const T *wL, const T *wR, T *F)
+__device__ __forceinline__ void ausm_plus(T g, T gi, int dn, const T *wL, const T *wR, T *F, int cs = 0)
 {
     const T rL = wL[0], pL = wL[D + 1], uL = vel_along<T, D>(wL, dn);
     const T rR = wR[0], pR = wR[D + 1], uR = vel_along<T, D>(wR, dn);
-    const T cL = Ar<T>::sqrt(Ar<T>::div(g * pL, rL));
-    const T cR = Ar<T>::sqrt(Ar<T>::div(g * pR, rR));
-    const T ch = T(0.5) * (cL + cR);
+    T ch;
+    if (cs) {
+        T KL = T(0), KR = T(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            KL = KL + wL[1 + k] * wL[1 + k];
+            KR = KR + wR[1 + k] * wR[1 + k];
+        }
+        const T HL = Ar<T>::div((pL * gi + (T(0.5) * rL) * KL) + pL, rL);
+        const T HR = Ar<T>::div((pR * gi + (T(0.5) * rR) * KR) + pR, rR);
+        const T kc = (T)((2.0 * ((double)g - 1.0)) / ((double)g + 1.0));
+        const T sL = kc * HL, sR = kc * HR;
+        const T csL = Ar<T>::sqrt(sL), csR = Ar<T>::sqrt(sR);
+        const T tL = Ar<T>::div(sL, csL >= uL ? csL : uL);
+        const T tR = Ar<T>::div(sR, csR >= -uR ? csR : -uR);
+        ch = tL <= tR ? tL : tR;
+    } else {
+        const T cL = Ar<T>::sqrt(Ar<T>::div(g * pL, rL));
+        const T cR = Ar<T>::sqrt(Ar<T>::div(g * pR, rR));
+        ch = T(0.5) * (cL + cR);
+    }
     const T ML = Ar<T>::div(uL, ch), MR = Ar<T>::div(uR, ch);
     T Mp, Pp, Mm, Pm;
     if (Ar<T>::abs(ML) >= T(1)) {
@@ -235,7 +256,7 @@ __device__ __forceinline__ void ausm_plus(T g, T gi, int dn, const T *wL, const 
 // Face flux from the primitive states of the 4 cells i-1, i, i+1, i+2 along dn.
 template <typename T, int D>
 __device__ __forceinline__ void face_flux4(T g, T gi, int dn, const T *wa, const T *wb, const T *wc,
-                                           const T *wd, T *F)
+                                           const T *wd, T *F, int cs = 0)
 {
     T wL[D + 2], wR[D + 2];
 #pragma unroll
@@ -243,7 +264,7 @@ __device__ __forceinline__ void face_flux4(T g, T gi, int dn, const T *wa, const
         wL[f] = wb[f] + T(0.5) * slope_va<T>(wa[f], wb[f], wc[f]);
         wR[f] = wc[f] - T(0.5) * slope_va<T>(wb[f], wc[f], wd[f]);
     }
-    ausm_plus<T, D>(g, gi, dn, wL, wR, F);
+    ausm_plus<T, D>(g, gi, dn, wL, wR, F, cs);
 }
 
 // Mean of the 2^(D-1) fine fluxes on the face between coarse cell p (global
@@ -280,7 +301,7 @@ __device__ void fine_mean(const View &v, const Grid &gf, const T *src, int px, i
             for (int f = 0; f < D + 2; ++f) q[f] = S[f * Nf + id];
             cons2prim<T, D>(q, w[j], g);
         }
-        face_flux4<T, D>(g, gi, dn, w[0], w[1], w[2], w[3], Fs[k]);
+        face_flux4<T, D>(g, gi, dn, w[0], w[1], w[2], w[3], Fs[k], v.ausm_cs);
     }
 #pragma unroll
     for (int f = 0; f < D + 2; ++f) {
@@ -460,7 +481,7 @@ __device__ __forceinline__ void fv_face(const View &v, const Grid &G, const Grid
             wL[f] = sFp[f][cell_state_idx<B>(dn, lx, ly, lz, a)];
             wR[f] = sFm[f][cell_state_idx<B>(dn, lx, ly, lz, a + 1)];
         }
-        ausm_plus<T, D>(g, gi, dn, wL, wR, F);
+        ausm_plus<T, D>(g, gi, dn, wL, wR, F, v.ausm_cs);
     } else {
         T wa[D + 2], wb[D + 2], wc[D + 2], wd[D + 2];
 #pragma unroll
@@ -470,7 +491,7 @@ __device__ __forceinline__ void fv_face(const View &v, const Grid &G, const Grid
             wc[f] = sW[f][hr];
             wd[f] = sW[f][hr + SD];
         }
-        face_flux4<T, D>(g, gi, dn, wa, wb, wc, wd, F);
+        face_flux4<T, D>(g, gi, dn, wa, wb, wc, wd, F, v.ausm_cs);
     }
     if (record) {
         // registers are indexed by the cell on the low side of the face
@@ -521,6 +542,7 @@ __device__ __forceinline__ void fv_collect(const T (*sF)[FV<D, NT>::NF], T (*R)[
 // the fine-flux mean.  Local time stepping (lvl >= 0): every cell in a patch
 // of level lvl with the level's own fluxes; with record set, fluxes across
 // refinement boundaries go to the flux registers (substep sub).
+// blend (Heun's second stage): out = (base + src) / 2 - lam R.
 // Schedules (bit-identical FP64 results): SCHED 0 computes the faces axis
 // by axis (one LDS flux array reused per axis); SCHED 2 does the same but
 // first reconstructs the two face states of every cell of the axis' lines
@@ -535,7 +557,7 @@ __device__ __forceinline__ void fv_collect(const T (*sF)[FV<D, NT>::NF], T (*R)[
 template <typename T, int D, int NT, int SCHED>
 __global__ void __launch_bounds__(NT)
 k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac, int lvl, int sub,
-           int record, int fineproj)
+           int record, int fineproj, int blend)
 {
     using C = FV<D, NT>;
     constexpr int E = C::E, H = C::H, B = C::B, NV = C::NV;
@@ -641,6 +663,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             }
         }
         // base state of the thread's cells, read while the fluxes are computed
+        // (blend: Heun's second stage, the base is (base + src) / 2)
         T qb[C::CPT][NV];
 #pragma unroll
         for (int k = 0; k < C::CPT; ++k) {
@@ -650,6 +673,9 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
             const int64_t id = G.off + (int64_t)gidx32(n, ox + x, oy + y, oz + z);
 #pragma unroll
             for (int f = 0; f < NV; ++f) qb[k][f] = base[f * N + id];
+            if (blend)
+#pragma unroll
+                for (int f = 0; f < NV; ++f) qb[k][f] = T(0.5) * (qb[k][f] + src[f * N + id]);
         }
         __syncthreads();
         T R[C::CPT][NV];

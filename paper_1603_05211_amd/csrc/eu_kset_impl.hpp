@@ -81,9 +81,10 @@ template <typename T> void predict(const View &v, int a, int lvl, int nlev, int 
 //       per-axis with per-cell face states.
 template <typename T, int D, int NT, int M>
 void fv_launch(const View &v, int nblk, const T *src, T *out, double fac, int lvl, int sub, int record,
-               int fineproj, hipStream_t s)
+               int fineproj, int blend, hipStream_t s)
 {
-    k_fv_stage<T, D, NT, M><<<nblk, NT, 0, s>>>(v, src, (const T *)v.Q, out, fac, lvl, sub, record, fineproj);
+    k_fv_stage<T, D, NT, M><<<nblk, NT, 0, s>>>(v, src, (const T *)v.Q, out, fac, lvl, sub, record, fineproj,
+                                                blend);
 }
 
 template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, int record, int maxt,
@@ -97,24 +98,27 @@ template <typename T> void fv_stage(const View &v, int stage, int lvl, int sub, 
     // (timing passes that leave the state unchanged)
     const T *src = (const T *)(stage == 2 ? v.Qs : v.Q);
     T *out = (T *)(stage == 2 ? v.Q : v.Qs);
-    const double fac = stage == 1 ? 0.5 : 1.0;
+    // midpoint rule: dt/2 then dt; Heun: dt, then dt/2 from the mean of the
+    // base and the stage state
+    const double fac = stage == 1 ? (v.rk ? 1.0 : 0.5) : (v.rk ? 0.5 : 1.0);
+    const int blend = stage != 1 && v.rk ? 1 : 0;
     if (v.dim == 2) {
         switch (variant) {
-        case 1: fv_launch<T, 2, 64, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        case 2: fv_launch<T, 2, 128, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        case 3: fv_launch<T, 2, 128, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        case 4: fv_launch<T, 2, 192, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        case 5: fv_launch<T, 2, 128, 2>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        default: fv_launch<T, 2, 64, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 1: fv_launch<T, 2, 64, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        case 2: fv_launch<T, 2, 128, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        case 3: fv_launch<T, 2, 128, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        case 4: fv_launch<T, 2, 192, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        case 5: fv_launch<T, 2, 128, 2>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        default: fv_launch<T, 2, 64, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
         }
     } else {
         switch (variant) {
-        case 1: fv_launch<T, 3, 256, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        case 2: fv_launch<T, 3, 512, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        case 3: fv_launch<T, 3, 512, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        case 4: fv_launch<T, 3, 256, 2>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        case 5: fv_launch<T, 3, 512, 2>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
-        default: fv_launch<T, 3, 256, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, s); break;
+        case 1: fv_launch<T, 3, 256, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        case 2: fv_launch<T, 3, 512, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        case 3: fv_launch<T, 3, 512, 1>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        case 4: fv_launch<T, 3, 256, 2>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        case 5: fv_launch<T, 3, 512, 2>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
+        default: fv_launch<T, 3, 256, 0>(v, nblk, src, out, fac, lvl, sub, record, fineproj, blend, s); break;
         }
     }
 }

@@ -49,6 +49,8 @@ def state_errors(h, s, which=0):
     l1 = np.zeros(h.nv)
     for l in range(h.L):
         act = h.active(l).astype(bool)
+        if not act.any():   # a level with no patch holds no cell to compare
+            continue
         mask = act | (dilate(act, 2, periodic) if l > 0 else act)
         Qo = h.level(l) if which == 0 else h.level_stage(l)
         Qg = s.level(l, which)
