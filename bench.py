@@ -197,7 +197,7 @@ class Run:
             sec += t1 - t0
         return upd, sec, k
 
-    def stage_samples(self, samples=64, reps=5):
+    def stage_samples(self, samples=64, reps=20):
         """Average duration of the finite-volume stage kernel over the run:
         at `samples` evenly spaced steps, reps first-stage passes on the live
         state (in the configuration the step launches them) replayed from one
@@ -247,13 +247,16 @@ def traffic_from_profile(workload, precision, kernel, cells_per_launch):
     if d.get("source_hash") != source_hash():
         return None, "kernel changed since the counters were taken"
     src = os.path.relpath(path, ROOT)
-    if "fetch_schedule" in d:
-        src += f" (counters taken with stage schedule {d['fetch_schedule']})"
-    return d["traffic_bytes_per_cell"] * cells_per_launch, src
+    if "schedule" in d:
+        src += f" (counters taken with stage schedule {d['schedule']})"
+    return d["traffic_bytes_per_cell_stage"] * cells_per_launch, src
+
+
+STAGE_REPS = 20   # passes per timed graph replay (the replay's own launch cost spread over them)
 
 
 def roofline(r, precision, samples=64):
-    ms, nl, cells, lpp, tflops = r.stage_samples(samples)
+    ms, nl, cells, lpp, tflops = r.stage_samples(samples, STAGE_REPS)
     peak = PEAK_TFLOPS[precision]
     kern = r.kernel()
     traffic, src = traffic_from_profile(r.workload, precision, kern, cells)
@@ -262,7 +265,7 @@ def roofline(r, precision, samples=64):
             "launches": nl, "launches_per_pass": lpp, "cell_stages_per_launch": cells,
             "phase_launches": getattr(r, "phase_launches", None),
             "flops_per_cell_stage": r.flops_per_cell_stage(),
-            "timing": "HIP events on the library's stream around graphs of 5 passes of one step's "
+            "timing": f"HIP events on the library's stream around graphs of {STAGE_REPS} passes of one step's "
                       f"finite-volume work at {samples} evenly spaced steps of the run (the tracer's "
                       "kernel durations are in profiles/)"}
 
