@@ -106,9 +106,9 @@ def test_full_headline_fp32_whole_run_against_oracle():
     the FP64 oracle's run of the same workload.  Every field's L1 and
     normwise L-inf on the composite, and the flags of every level.
 
-    Bounds: L1 relative 1e-5 per field (two decades above the FP32 rounding
-    estimate of the design notes, which a dropped term or a transposed operand
-    exceeds by far); L-inf 2e-3 (cells at a discontinuity whose position the
+    Bounds: L1 relative 1e-5 per field (two decades above an FP32 rounding
+    estimate: unit roundoff 6e-8 times O(10) roundings per stage, growing at
+    most linearly; a dropped term or a transposed operand exceeds it by far); L-inf 2e-3 (cells at a discontinuity whose position the
     two runs resolve a fraction of a cell apart dominate it: observed about
     2e-4); flag disagreements per level at most 2 % of that level's flagged
     cells (a detail at the threshold may fall on either side in FP32)."""

@@ -4,8 +4,11 @@ seeded inputs.
 Bar: FP64 state within normwise relative L-inf 1e-12 (the expression trees are
 the same, so agreement is expected to be bit for bit), time steps, patch
 membership, refinement flags and patch tables bit-exact.  FP32 runs report
-their error against the FP64 oracle and must stay within the FP32 bound
-derived in the design notes (rho L1 relative 1e-5 after the run).
+their error against the FP64 oracle and must keep the density's relative L1
+error within 1e-5 after the run: FP32 unit roundoff is 6e-8, an update
+accumulates O(10) roundings per stage and the error grows at most linearly
+over the 20-100 steps of these runs, so 1e-5 leaves two decades of margin,
+while a dropped term or a transposed operand exceeds it by far.
 """
 import math
 
