@@ -103,6 +103,8 @@ def lib():
             "orc_phys_flux": (None, [C.c_int, C.c_double, C.c_int, dp, dp]),
             "orc_h_set_scheme": (C.c_int, [vp, C.c_int]),
             "orc_h_set_variants": (C.c_int, [vp, C.c_int, C.c_int]),
+            "orc_h_set_tiler": (C.c_int, [vp, C.c_int]),
+            "orc_br_cluster": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, i32p, i32p]),
             "orc_ausm_plus_speed": (None, [C.c_int, C.c_double, C.c_int, dp, dp, dp, C.c_int]),
             "orc_h_set_eps_levels": (None, [vp, C.c_int]),
             "orc_h_set_criterion": (C.c_int, [vp, C.c_int, C.c_double]),
@@ -155,6 +157,7 @@ PLANT_AUSMDV_ALPHA, PLANT_HANCOCK_NOPRED, PLANT_NO_FINE_MEAN = 4, 5, 6
 SCHEME_MR, SCHEME_AMR = 0, 1
 RK_MIDPOINT, RK_HEUN = 0, 1
 AUSM_MEAN, AUSM_CRITICAL = 0, 1
+TILER_BLOCKS, TILER_BR = 0, 1
 CRIT_MR, CRIT_GRADIENT = 0, 1
 
 
@@ -211,6 +214,18 @@ def ausm_plus(dim: int, gamma: float, axis: int, wL, wR, speed: int = AUSM_MEAN)
     else:
         lib().orc_ausm_plus_speed(dim, gamma, axis, _dp(wL), _dp(wR), _dp(F), speed)
     return F
+
+
+def br_cluster(W: np.ndarray, q: int, eta: float) -> np.ndarray:
+    """Berger-Rigoutsos boxes of a (R, R) or (R, R, R) grid of sub-block
+    weights (index [(z,) y, x]; q^d parent cells per sub-block): rows
+    {lo_x, lo_y, lo_z, hi_x, hi_y, hi_z} in the order found."""
+    W = np.ascontiguousarray(W, dtype=np.int32)
+    dim, R = W.ndim, W.shape[0]
+    out = np.zeros((512, 6), dtype=np.int32)
+    n = lib().orc_br_cluster(dim, R, q, eta, W.ctypes.data_as(C.POINTER(C.c_int32)),
+                             out.ctypes.data_as(C.POINTER(C.c_int32)))
+    return out[:n]
 
 
 def slope(wm: float, w0: float, wp: float) -> float:
@@ -292,7 +307,7 @@ class Hierarchy:
                  gamma: float = 1.4, lo: float = 0.0, hi: float = 1.0, eps: float = 1e-3,
                  eta: float = 0.8, pmin: int = 8, pmax: int = 32, scheme: int = SCHEME_MR,
                  criterion: int = CRIT_MR, eps_p: float = 0.0, eps_levels: bool = False, rk: int = RK_MIDPOINT,
-                 ausm_speed: int = AUSM_MEAN):
+                 ausm_speed: int = AUSM_MEAN, tiler: int = TILER_BLOCKS):
         self.dim, self.L, self.n0, self.bc = dim, levels, n0, bc
         self.gamma, self.lo, self.hi, self.eps, self.eta = gamma, lo, hi, eps, eta
         self.pmin, self.pmax = pmin, pmax
@@ -311,6 +326,9 @@ class Hierarchy:
         if lib().orc_h_set_variants(self._h, rk, ausm_speed) != 0:
             raise ValueError("unknown time stepping or AUSM+ sound speed")
         self.rk, self.ausm_speed = rk, ausm_speed
+        if lib().orc_h_set_tiler(self._h, tiler) != 0:
+            raise ValueError("unknown tiler, or pmax / pmin above 8 for Berger-Rigoutsos")
+        self.tiler = tiler
         self.t = 0.0
 
     def __del__(self):
@@ -434,8 +452,9 @@ class Hierarchy:
         return leaves, active
 
     def patches(self) -> np.ndarray:
+        """Rows {level, ox, oy, oz, sx, sy, sz} (2D: oz = 0, sz = 1)."""
         npch = lib().orc_h_npatch(self._h)
-        out = np.zeros((max(npch, 1), 5), dtype=np.int32)
+        out = np.zeros((max(npch, 1), 7), dtype=np.int32)
         lib().orc_h_patches(self._h, out.ctypes.data_as(C.POINTER(C.c_int32)))
         return out[:npch]
 

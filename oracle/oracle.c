@@ -515,7 +515,7 @@ void orc_predict(int dim, int nv, int nc, int bc, const double *Ac, double *Af)
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    int lvl, o[3], size;
+    int lvl, o[3], size[3];   /* origin and extents in cells of level lvl (2D: size[2] = 1) */
 } orc_patch;
 
 typedef struct {
@@ -545,6 +545,7 @@ typedef struct {
     int eps_levels;      /* criterion 0: 1 = level-dependent thresholds (eps_at) */
     int rk;              /* MR scheme time stepping: 0 the midpoint rule, 1 Heun */
     int ausm_speed;      /* MR scheme: AUSM+ interface sound speed (ausm_plus) */
+    int tiler;           /* 0 block tiler (tile_block), 1 Berger-Rigoutsos (br_block) */
 } orc_h;
 
 static int64_t hN(const orc_h *h, int l) { return ncells(h->dim, h->n[l]); }
@@ -1017,7 +1018,9 @@ static void h_flags(orc_h *h, int l)
     }
 }
 
-static void emit_patch(orc_h *h, int lvl, const int *o, int S)
+/* A patch of level lvl: origin o, extents S[0..2] cells (S[2] = 1 in 2D);
+ * its cells join the new hierarchy. */
+static void emit_patch(orc_h *h, int lvl, const int *o, const int *S)
 {
     if (h->npatch == h->cappatch) {
         h->cappatch = h->cappatch ? 2 * h->cappatch : 256;
@@ -1025,13 +1028,14 @@ static void emit_patch(orc_h *h, int lvl, const int *o, int S)
     }
     orc_patch *P = &h->patches[h->npatch++];
     P->lvl = lvl;
-    P->o[0] = o[0]; P->o[1] = o[1]; P->o[2] = o[2];
-    P->size = S;
+    for (int d = 0; d < 3; ++d) {
+        P->o[d] = o[d];
+        P->size[d] = S[d];
+    }
     int nf = h->n[lvl];
-    int z1 = h->dim == 3 ? S : 1;
-    for (int z = 0; z < z1; ++z)
-        for (int y = 0; y < S; ++y)
-            for (int x = 0; x < S; ++x) {
+    for (int z = 0; z < S[2]; ++z)
+        for (int y = 0; y < S[1]; ++y)
+            for (int x = 0; x < S[0]; ++x) {
                 int c[3] = {o[0] + x, o[1] + y, h->dim == 3 ? o[2] + z : 0};
                 h->nact[lvl][cidx(nf, c)] = 1;
             }
@@ -1055,13 +1059,185 @@ static void tile_block(orc_h *h, int l, const int *o, int S)
             }
     if (cnt == 0) return;
     if (S == h->pmin || (double)cnt >= h->eta * (double)cells) {
-        emit_patch(h, l + 1, o, S);
+        int ext[3] = {S, S, dim == 3 ? S : 1};
+        emit_patch(h, l + 1, o, ext);
         return;
     }
     int nch = 1 << dim;
     for (int k = 0; k < nch; ++k) {
         int oc[3] = {o[0] + hs * (k & 1), o[1] + hs * ((k >> 1) & 1), dim == 3 ? o[2] + hs * ((k >> 2) & 1) : 0};
         tile_block(h, l, oc, hs);
+    }
+}
+
+/* Berger-Rigoutsos clustering (the AMR method's clustering, Sec. 2.2;
+ * Berger and Rigoutsos 1991), a variant tiler: inside one block of pmax^d
+ * level-(l+1) cells at o, on the grid of its R^d sub-blocks of pmin^d cells
+ * (R = pmax / pmin; patches stay unions of whole sub-blocks), each
+ * sub-block weighted by the flagged level-l cells among its parents.  A box
+ * of sub-blocks (inclusive bounds lo..hi per axis) is
+ *   1. shrunk to the sub-blocks with flagged cells (nothing left: dropped);
+ *   2. emitted when its flagged fraction of parent cells reaches eta, or it
+ *      is a single sub-block;
+ *   3. otherwise cut at a hole: a zero of the signature (flagged cells per
+ *      slice) along an axis, the axes taken longest first (ties: x, y, z),
+ *      the hole nearest the middle (ties: the lower one), the cut just
+ *      above it;
+ *   4. else at the strongest inflection of the signature: between slices k
+ *      and k+1 where the second differences D[i] = s[i-1] - 2 s[i] + s[i+1]
+ *      change sign, strength |D[k] - D[k+1]|, the strongest over all axes
+ *      (ties: axis order of step 3, then nearest the middle, then lower k);
+ *   5. else halved along its longest axis (ties: x, y, z), the lower half
+ *      taking the smaller share;
+ *   and the two parts are clustered in turn, the lower one first. */
+/* Boxes found so far: inclusive sub-block bounds lo[3], hi[3] each. */
+typedef struct {
+    int n, lo[512][3], hi[512][3];
+} br_out;
+
+static void br_box(int dim, int q, double eta, const int W[8][8][8], const int *lo0, const int *hi0, br_out *out)
+{
+    int lo[3], hi[3];
+    /* 1. shrink */
+    int any = 0;
+    for (int d = 0; d < 3; ++d) { lo[d] = hi0[d] + 1; hi[d] = lo0[d] - 1; }
+    for (int z = lo0[2]; z <= hi0[2]; ++z)
+        for (int y = lo0[1]; y <= hi0[1]; ++y)
+            for (int x = lo0[0]; x <= hi0[0]; ++x)
+                if (W[z][y][x] > 0) {
+                    int c[3] = {x, y, z};
+                    for (int d = 0; d < 3; ++d) {
+                        if (c[d] < lo[d]) lo[d] = c[d];
+                        if (c[d] > hi[d]) hi[d] = c[d];
+                    }
+                    any = 1;
+                }
+    if (!any) return;
+    /* 2. efficiency: flagged parent cells over the box's parent cells */
+    int64_t flagged = 0;
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int x = lo[0]; x <= hi[0]; ++x) flagged += W[z][y][x];
+    int64_t cells = 1;
+    for (int d = 0; d < dim; ++d) cells *= (int64_t)(hi[d] - lo[d] + 1) * q;
+    int single = lo[0] == hi[0] && lo[1] == hi[1] && lo[2] == hi[2];
+    if (single || (double)flagged >= eta * (double)cells) {
+        for (int d = 0; d < 3; ++d) {
+            out->lo[out->n][d] = lo[d];
+            out->hi[out->n][d] = hi[d];
+        }
+        out->n++;
+        return;
+    }
+    /* signatures */
+    int sig[3][8];
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < 8; ++i) sig[d][i] = 0;
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int x = lo[0]; x <= hi[0]; ++x) {
+                sig[0][x] += W[z][y][x];
+                sig[1][y] += W[z][y][x];
+                sig[2][z] += W[z][y][x];
+            }
+    /* axes, longest first (ties: lower axis) */
+    int ax[3] = {0, 1, 2}, na = dim;
+    for (int i = 0; i < na; ++i)
+        for (int j = i + 1; j < na; ++j) {
+            int li = hi[ax[i]] - lo[ax[i]], lj = hi[ax[j]] - lo[ax[j]];
+            if (lj > li || (lj == li && ax[j] < ax[i])) { int t = ax[i]; ax[i] = ax[j]; ax[j] = t; }
+        }
+    int cut_axis = -1, cut_at = 0;   /* halves [lo, cut_at] and [cut_at + 1, hi] */
+    /* 3. holes */
+    for (int k = 0; k < na && cut_axis < 0; ++k) {
+        int a = ax[k], best = -1, bd = 0;
+        for (int i = lo[a] + 1; i <= hi[a] - 1; ++i)
+            if (sig[a][i] == 0) {
+                int dd = abs(2 * i - (lo[a] + hi[a]));
+                if (best < 0 || dd < bd) { best = i; bd = dd; }
+            }
+        if (best >= 0) { cut_axis = a; cut_at = best; }
+    }
+    /* 4. inflections */
+    if (cut_axis < 0) {
+        int bs = 0, bdist = 0;
+        for (int k = 0; k < na; ++k) {
+            int a = ax[k];
+            for (int i = lo[a] + 1; i + 1 <= hi[a] - 1; ++i) {
+                int d0 = sig[a][i - 1] - 2 * sig[a][i] + sig[a][i + 1];
+                int d1 = sig[a][i] - 2 * sig[a][i + 1] + sig[a][i + 2];
+                if (!((d0 < 0 && d1 > 0) || (d0 > 0 && d1 < 0))) continue;
+                int st = abs(d0 - d1), dist = abs(2 * i + 1 - (lo[a] + hi[a]));
+                if (cut_axis < 0 || st > bs || (st == bs && a == cut_axis && dist < bdist)) {
+                    cut_axis = a; cut_at = i; bs = st; bdist = dist;
+                }
+            }
+        }
+    }
+    /* 5. bisection of the longest axis */
+    if (cut_axis < 0) {
+        cut_axis = ax[0];
+        cut_at = lo[cut_axis] + (hi[cut_axis] - lo[cut_axis] + 1) / 2 - 1;
+    }
+    int h1[3] = {hi[0], hi[1], hi[2]}, l2[3] = {lo[0], lo[1], lo[2]};
+    h1[cut_axis] = cut_at;
+    l2[cut_axis] = cut_at + 1;
+    br_box(dim, q, eta, W, lo, h1, out);
+    br_box(dim, q, eta, W, l2, hi, out);
+}
+
+/* Clustering of an R^d grid of sub-block weights W (flagged parent cells,
+ * q^d parent cells per sub-block; index [z][y][x], R <= 8): the boxes in
+ * the order found, as rows {lo_x, lo_y, lo_z, hi_x, hi_y, hi_z}.  Returns
+ * their number. */
+int orc_br_cluster(int dim, int R, int q, double eta, const int32_t *W, int32_t *boxes)
+{
+    int G[8][8][8];
+    memset(G, 0, sizeof(G));
+    for (int z = 0; z < (dim == 3 ? R : 1); ++z)
+        for (int y = 0; y < R; ++y)
+            for (int x = 0; x < R; ++x) G[z][y][x] = W[x + R * (y + R * z)];
+    br_out *out = (br_out *)calloc(1, sizeof(br_out));
+    int lo[3] = {0, 0, 0}, hi[3] = {R - 1, R - 1, dim == 3 ? R - 1 : 0};
+    br_box(dim, q, eta, (const int (*)[8][8])G, lo, hi, out);
+    int n = out->n;
+    for (int i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            boxes[6 * i + d] = out->lo[i][d];
+            boxes[6 * i + 3 + d] = out->hi[i][d];
+        }
+    free(out);
+    return n;
+}
+
+/* One pmax block at o: the weights of its sub-blocks from the level-l flags,
+ * clustered, each box a patch of level l+1. */
+static void br_block(orc_h *h, int l, const int *o)
+{
+    int dim = h->dim, R = h->pmax / h->pmin, q = h->pmin / 2, n = h->n[l];
+    int32_t W[512];
+    int32_t boxes[6 * 512];
+    for (int sz = 0; sz < (dim == 3 ? R : 1); ++sz)
+        for (int sy = 0; sy < R; ++sy)
+            for (int sx = 0; sx < R; ++sx) {
+                int w = 0;
+                for (int z = 0; z < (dim == 3 ? q : 1); ++z)
+                    for (int y = 0; y < q; ++y)
+                        for (int x = 0; x < q; ++x) {
+                            int c[3] = {o[0] / 2 + sx * q + x, o[1] / 2 + sy * q + y,
+                                        dim == 3 ? o[2] / 2 + sz * q + z : 0};
+                            w += h->flag[l][cidx(n, c)];
+                        }
+                W[sx + R * (sy + R * sz)] = w;
+            }
+    int nb = orc_br_cluster(dim, R, q, h->eta, W, boxes);
+    for (int i = 0; i < nb; ++i) {
+        int oo[3], ext[3];
+        for (int d = 0; d < 3; ++d) {
+            oo[d] = d < dim ? o[d] + boxes[6 * i + d] * h->pmin : 0;
+            ext[d] = d < dim ? (boxes[6 * i + 3 + d] - boxes[6 * i + d] + 1) * h->pmin : 1;
+        }
+        emit_patch(h, l + 1, oo, ext);
     }
 }
 
@@ -1085,7 +1261,8 @@ static void h_tile(orc_h *h, int l)
         if (b[0] >= nb || b[1] >= nb || b[2] >= nb) continue;
         ++seen;
         int o[3] = {b[0] * h->pmax, b[1] * h->pmax, b[2] * h->pmax};
-        tile_block(h, l, o, h->pmax);
+        if (h->tiler == 1) br_block(h, l, o);
+        else tile_block(h, l, o, h->pmax);
     }
 }
 
@@ -1163,16 +1340,26 @@ int orc_h_npatch(const orc_h *h) { return h->npatch; }
 /* Test-only: plant the mistake of skipping the flux correction. */
 void orc_h_set_no_reflux(orc_h *h, int on) { h->no_reflux = on; }
 
-/* patches as int32 rows {level, ox, oy, oz, size} */
+/* patches as int32 rows {level, ox, oy, oz, sx, sy, sz} (2D: oz = 0, sz = 1) */
 void orc_h_patches(const orc_h *h, int32_t *out)
 {
     for (int i = 0; i < h->npatch; ++i) {
-        out[5 * i + 0] = h->patches[i].lvl;
-        out[5 * i + 1] = h->patches[i].o[0];
-        out[5 * i + 2] = h->patches[i].o[1];
-        out[5 * i + 3] = h->patches[i].o[2];
-        out[5 * i + 4] = h->patches[i].size;
+        out[7 * i + 0] = h->patches[i].lvl;
+        for (int d = 0; d < 3; ++d) {
+            out[7 * i + 1 + d] = h->patches[i].o[d];
+            out[7 * i + 4 + d] = h->patches[i].size[d];
+        }
     }
+}
+
+/* Tiler: 0 the efficiency-rule block tiler (tile_block), 1 Berger-Rigoutsos
+ * clustering (br_block; pmax / pmin <= 8).  Returns 0, or -1. */
+int orc_h_set_tiler(orc_h *h, int tiler)
+{
+    if (tiler != 0 && tiler != 1) return -1;
+    if (tiler == 1 && h->pmax / h->pmin > 8) return -1;
+    h->tiler = tiler;
+    return 0;
 }
 
 /* One explicit stage on every level (FV on leaves, projection onto covered

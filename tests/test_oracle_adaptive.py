@@ -40,15 +40,27 @@ def check_hierarchy(h, periodic=False):
     P = h.patches()
     acts = [h.active(l).astype(bool) for l in range(L)]
     assert acts[0].all()
-    # patches: aligned, sizes in {pmin..pmax} powers of two, disjoint, union = active
+    # patches: block tiler: aligned cubes of pmin..pmax cells (powers of
+    # two); Berger-Rigoutsos: boxes of whole pmin-blocks inside one
+    # pmax-block; disjoint, union = active
+    br = getattr(h, "tiler", 0) == 1
     for l in range(1, L):
         cover = np.zeros_like(acts[l], dtype=np.int32)
-        for lv, ox, oy, oz, S in P:
+        for lv, ox, oy, oz, sx, sy, sz in P:
             if lv != l:
                 continue
-            assert S in (8, 16, 32) and ox % S == 0 and oy % S == 0 and oz % S == 0
-            sl = (slice(oy, oy + S), slice(ox, ox + S)) if dim == 2 else \
-                (slice(oz, oz + S), slice(oy, oy + S), slice(ox, ox + S))
+            ext = (sx, sy, sz) if dim == 3 else (sx, sy)
+            org = (ox, oy, oz) if dim == 3 else (ox, oy)
+            if dim == 2:
+                assert oz == 0 and sz == 1
+            if br:
+                for o_, e_ in zip(org, ext):
+                    assert o_ % h.pmin == 0 and e_ % h.pmin == 0 and 0 < e_ <= h.pmax
+                    assert o_ // h.pmax == (o_ + e_ - 1) // h.pmax
+            else:
+                S = sx
+                assert all(e_ == S for e_ in ext) and S in (8, 16, 32) and all(o_ % S == 0 for o_ in org)
+            sl = tuple(slice(o_, o_ + e_) for o_, e_ in zip(org[::-1], ext[::-1]))
             cover[sl] += 1
         assert cover.max() <= 1
         assert np.array_equal(cover.astype(bool), acts[l])
@@ -106,7 +118,7 @@ def test_tiling_rule_and_flag_coverage(orc):
         F = h.flags(l).astype(bool)
         child_cov = coarsen_mask(acts[l + 1], 2)
         assert not (F & ~child_cov).any()
-        for lv, ox, oy, oz, S in P:
+        for lv, ox, oy, oz, S, _, _ in P:
             if lv != l + 1:
                 continue
             fill = F[oy // 2:(oy + S) // 2, ox // 2:(ox + S) // 2].mean()
