@@ -26,7 +26,7 @@ stepping, to t = 0.2), ellip3d_uniform256 (200 steps), quad2d_batch512 (512
 instances, 100 steps, one launch per stage for all), quad2d_uniform128 (100
 steps).
 
-Prints ONE JSON line.  --gpus N > 1 is not supported: this build runs on one
+Prints ONE JSON line.  --gpus N > 1 is not supported: the benchmark runs on one
 GPU.
 """
 from __future__ import annotations
@@ -435,7 +435,7 @@ def main():
         print(json.dumps({"updates": upd, "seconds": sec, "steps": steps}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design note only)", file=sys.stderr)
         sys.exit(2)
 

@@ -63,6 +63,7 @@ enum { EU_SCHEME_MR = 0, EU_SCHEME_AMR = 1 };      /* finite-volume scheme     *
 enum { EU_CRIT_MR = 0, EU_CRIT_GRADIENT = 1 };     /* refinement criterion     */
 enum { EU_RK_MIDPOINT = 0, EU_RK_HEUN = 1 };       /* MR scheme time stepping  */
 enum { EU_AUSM_MEAN = 0, EU_AUSM_CRITICAL = 1 };   /* AUSM+ sound speed        */
+enum { EU_TILER_BLOCKS = 0, EU_TILER_BR = 1 };     /* patch generation        */
 enum { EU_STAGE_SCHEDULES = 10, EU_STRIP_SCHEDULE0 = 6 }; /* see eu_autotune  */
 
 /* Problem size and method parameters (Sec. 2; Sec. 4 for the values used
@@ -123,8 +124,8 @@ typedef struct {
                             l = 0 .. L-2 (eps on the finest details, halved
                             d times per coarser level, as in Harten's MR
                             analysis)                                         */
-    int rk;              /* MR scheme: EU_RK_MIDPOINT (0, the runs of this
-                            build) Q* = Q - dt/2 F(Q), Q <- Q - dt F(Q*);
+    int rk;              /* MR scheme: EU_RK_MIDPOINT (0, the paper's MR
+                            scheme) Q* = Q - dt/2 F(Q), Q <- Q - dt F(Q*);
                             EU_RK_HEUN: Q* = Q - dt F(Q), Q <- (Q + Q*)/2 -
                             dt/2 F(Q*) (global time step; tile schedules)     */
     int ausm_speed;      /* MR scheme: AUSM+ interface sound speed,
@@ -132,6 +133,21 @@ typedef struct {
                             speeds; EU_AUSM_CRITICAL Liou's min(c*_L^2 /
                             max(c*_L, u_L), c*_R^2 / max(c*_R, -u_R)), c*^2
                             = 2 (gamma-1)/(gamma+1) H (tile schedules)       */
+    int tiler;           /* patch generation inside each patch_max block from
+                            the flags of the next coarser level (Sec. 2.2):
+                            EU_TILER_BLOCKS (0) aligned square blocks, split
+                            in 2^d halves until the flagged fraction of a
+                            block reaches eta (or the block is a smallest
+                            patch); EU_TILER_BR Berger-Rigoutsos clustering
+                            (Berger and Rigoutsos 1991) into rectangular
+                            unions of 8^d blocks: shrink to the flagged
+                            blocks, emit when the flagged fraction reaches
+                            eta or one block is left, else cut at the zero of
+                            the flag signature nearest the middle (longest
+                            axis first), else at its strongest inflection,
+                            else halve the longest axis; the lower part
+                            first.  EU_TILER_BR needs (patch_max / 8)^d <= 64
+                            (3D: patch_max <= 32)                           */
 } eu_config;
 
 /* Initial data (Sec. 4.1 four-quadrant Riemann problem, Sec. 4.2 ellipsoid,
@@ -300,10 +316,13 @@ int eu_get_flags(eu_ctx *ctx, int level, uint8_t *dst_host);
 int eu_get_details(eu_ctx *ctx, int level, double *dst_host);
 
 /* Patch table of the new mesh (the rectangular submeshes G_{l,m} of
- * Sec. 2.2, generated with the efficiency rule eta_tol): rows {level, ox,
- * oy, oz, size} ordered by level, then Morton order of the enclosing
- * patch_max block, then recursive split order.  At most cap rows are
- * written to dst_host; *npatch_host receives the total (synchronises). */
+ * Sec. 2.2, generated with the efficiency rule eta_tol): rows of 7 ints
+ * {level, ox, oy, oz, sx, sy, sz} (origin and extents in cells of the
+ * level; 2D: oz = 0, sz = 1) ordered by level, then Morton order of the
+ * enclosing patch_max block, then the order the tiler emitted them (the
+ * recursive split order, or the depth-first order of the clustering).  At
+ * most cap rows are written to dst_host; *npatch_host receives the total
+ * (synchronises). */
 int eu_patch_table(eu_ctx *ctx, int32_t *dst_host, int cap, int *npatch_host);
 
 /* Leaf and active (patch) cell counts per level (levels entries each). */

@@ -125,7 +125,7 @@ static double slope_va(double wm, double w0, double wp)
 /* AUSM+ flux-vector splitting (Liou 1996; Sec. 2, MR scheme) across a face
  * with normal along axis dn.  wL / wR are the primitive face states.
  * Interface sound speed (speed): 0 the arithmetic mean of the two sound
- * speeds (the runs of this build); 1 Liou's critical speed, c_1/2 =
+ * speeds (the default); 1 Liou's critical speed, c_1/2 =
  * min(c*_L^2 / max(c*_L, u_L), c*_R^2 / max(c*_R, -u_R)) with c*^2 =
  * 2 (gamma - 1) / (gamma + 1) H, H the total enthalpy (a variant).
  * alpha = 3/16, beta = 1/8. */

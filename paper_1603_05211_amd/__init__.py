@@ -17,12 +17,14 @@ import numpy as np
 from . import _abi
 from ._abi import (EU_BC_PERIODIC, EU_BC_TRANSMISSIVE, EU_DT_GLOBAL, EU_DT_LTS, EU_FP32, EU_FP64,
                    EU_CRIT_GRADIENT, EU_CRIT_MR, EU_GHOST, EU_SCHEME_AMR, EU_SCHEME_MR, EU_STAGE_SCHEDULES, EU_STRIP_SCHEDULE0, EU_IC_ELLIPSOID, EU_IC_QUADRANT, EU_IC_RIEMANN1D, EU_IC_UNIFORM,
-                   EU_PROLONG, EU_RESTRICT, EU_RK_MIDPOINT, EU_RK_HEUN, EU_AUSM_MEAN, EU_AUSM_CRITICAL)
+                   EU_PROLONG, EU_RESTRICT, EU_RK_MIDPOINT, EU_RK_HEUN, EU_AUSM_MEAN, EU_AUSM_CRITICAL,
+                   EU_TILER_BLOCKS, EU_TILER_BR)
 
 __all__ = ["Solver", "EuError", "EU_FP32", "EU_FP64", "EU_BC_PERIODIC", "EU_BC_TRANSMISSIVE",
            "EU_RESTRICT", "EU_PROLONG", "EU_GHOST", "EU_DT_GLOBAL", "EU_DT_LTS", "EU_STAGE_SCHEDULES",
            "EU_STRIP_SCHEDULE0", "EU_SCHEME_MR", "EU_SCHEME_AMR", "EU_CRIT_MR", "EU_CRIT_GRADIENT",
-           "EU_RK_MIDPOINT", "EU_RK_HEUN", "EU_AUSM_MEAN", "EU_AUSM_CRITICAL"]
+           "EU_RK_MIDPOINT", "EU_RK_HEUN", "EU_AUSM_MEAN", "EU_AUSM_CRITICAL",
+           "EU_TILER_BLOCKS", "EU_TILER_BR"]
 
 
 class EuError(RuntimeError):
@@ -48,7 +50,8 @@ class Solver:
                  lo: float = 0.0, hi: float = 1.0, gamma: float = 1.4, sides=None,
                  time_mode: int = EU_DT_GLOBAL, device: str = "cuda:0", stream=None,
                  scheme: int = EU_SCHEME_MR, criterion: int = EU_CRIT_MR, eps_p: float = 0.0,
-                 eps_levels: int = 0, rk: int = EU_RK_MIDPOINT, ausm_speed: int = EU_AUSM_MEAN):
+                 eps_levels: int = 0, rk: int = EU_RK_MIDPOINT, ausm_speed: int = EU_AUSM_MEAN,
+                 tiler: int = EU_TILER_BLOCKS):
         import torch
         self._lib = _abi.load()
         self.torch = torch
@@ -68,7 +71,7 @@ class Solver:
         cfg.criterion, cfg.eps_p = criterion, eps_p
         self.criterion, self.eps_p = criterion, eps_p
         cfg.eps_levels = eps_levels
-        cfg.rk, cfg.ausm_speed = rk, ausm_speed
+        cfg.rk, cfg.ausm_speed, cfg.tiler = rk, ausm_speed, tiler
         if sides is not None:
             self._sides = (C.c_int32 * len(sides))(*[int(s) for s in sides])
             cfg.n_instances = len(sides)
@@ -273,7 +276,7 @@ class Solver:
     def patches(self) -> np.ndarray:
         npch = C.c_int(0)
         self._check(self._lib.eu_patch_table(self._ctx, None, 0, C.byref(npch)), "eu_patch_table")
-        out = np.zeros((max(npch.value, 1), 5), dtype=np.int32)
+        out = np.zeros((max(npch.value, 1), 7), dtype=np.int32)
         self._check(self._lib.eu_patch_table(self._ctx, out.ctypes.data_as(C.POINTER(C.c_int32)),
                                              npch.value, C.byref(npch)), "eu_patch_table")
         return out[:npch.value]

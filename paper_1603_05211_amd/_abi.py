@@ -18,6 +18,7 @@ EU_SCHEME_MR, EU_SCHEME_AMR = 0, 1
 EU_CRIT_MR, EU_CRIT_GRADIENT = 0, 1
 EU_RK_MIDPOINT, EU_RK_HEUN = 0, 1
 EU_AUSM_MEAN, EU_AUSM_CRITICAL = 0, 1
+EU_TILER_BLOCKS, EU_TILER_BR = 0, 1
 EU_STAGE_SCHEDULES = 10
 EU_STRIP_SCHEDULE0 = 6
 
@@ -35,6 +36,7 @@ class EuConfig(C.Structure):
         ("inst_side_host", C.POINTER(C.c_int32)), ("stream", C.c_void_p), ("scheme", C.c_int),
         ("criterion", C.c_int), ("eps_p", C.c_double), ("eps_levels", C.c_int), ("rk", C.c_int),
         ("ausm_speed", C.c_int),
+        ("tiler", C.c_int),
     ]
 
 

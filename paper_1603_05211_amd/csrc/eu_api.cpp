@@ -183,6 +183,12 @@ int validate(const eu_config *c, std::string &why)
         if (!(c->eta > 0.0 && c->eta <= 1.0)) { why = "eta must lie in (0, 1]"; return EU_EINVAL; }
         if (!(c->eps >= 0.0)) { why = "eps must be >= 0"; return EU_EINVAL; }
     }
+    if (c->tiler != EU_TILER_BLOCKS && c->tiler != EU_TILER_BR) { why = "bad tiler"; return EU_EINVAL; }
+    // the clustering runs on one wave: one lane per 8^d block of a patch_max block
+    if (c->tiler == EU_TILER_BR && c->levels > 1 && ipow(c->patch_max / eu::BS, c->dim) > 64) {
+        why = "the Berger-Rigoutsos tiler needs (patch_max / 8)^dim <= 64";
+        return EU_EINVAL;
+    }
     if (c->bc == EU_BC_PERIODIC && c->n0 < 4) { why = "periodic grids need n0 >= 4"; return EU_EINVAL; }
     // every grid must have fewer than 2^31 cells (32-bit cell indices)
     if (c->levels >= 1 && c->n0 > 0) {
@@ -274,7 +280,7 @@ void make_layout(const eu_config *c, Layout &lay)
     lay.o_fresh = take(sizeof(Tile) * lay.nbt);
     lay.o_actv = take(sizeof(Tile) * lay.nbt);
     lay.o_reg = take(es * lay.reg_elems);
-    lay.o_pslot = take(sizeof(int) * 5 * lay.nslot * nsub);
+    lay.o_pslot = take(sizeof(int) * 7 * lay.nslot * nsub);
     lay.o_pcnt = take(sizeof(int) * lay.nslot);
     lay.o_fcnt = take(sizeof(int) * lay.nslot);
     lay.ncls = (int)std::min<int64_t>(std::max<int64_t>((lay.nbt + 255) / 256, 1), 256);
@@ -1029,6 +1035,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     set_eps_levels(v, lay.L, cfg->dim, cfg->eps, cfg->eps_levels);
     v.rk = cfg->rk;
     v.ausm_cs = cfg->ausm_speed;
+    v.tiler = cfg->tiler;
     v.crit = cfg->criterion;
     v.eps_p = cfg->eps_p;
     v.eta = cfg->eta;
@@ -1478,14 +1485,14 @@ int eu_patch_table(eu_ctx *c, int32_t *dst, int cap, int *npatch)
     if (c->mode != MODE_HIER || c->v.nslot == 0) return EU_OK;
     const int R = c->cfg.patch_max / BS;
     const int64_t nsub = c->dim == 2 ? R * R : R * R * R;
-    std::vector<int> cnt((size_t)c->v.nslot), rows((size_t)(c->v.nslot * nsub * 5));
+    std::vector<int> cnt((size_t)c->v.nslot), rows((size_t)(c->v.nslot * nsub * 7));
     HIPCHK(c, hipMemcpy(cnt.data(), c->v.pcnt, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(rows.data(), c->v.pslot, sizeof(int) * rows.size(), hipMemcpyDeviceToHost));
     int n = 0;
     for (int64_t sl = 0; sl < c->v.nslot; ++sl)
         for (int j = 0; j < cnt[(size_t)sl]; ++j, ++n)
             if (n < cap)
-                for (int e = 0; e < 5; ++e) dst[5 * (int64_t)n + e] = rows[(size_t)((sl * nsub + j) * 5 + e)];
+                for (int e = 0; e < 7; ++e) dst[7 * (int64_t)n + e] = rows[(size_t)((sl * nsub + j) * 7 + e)];
     *npatch = n;
     return EU_OK;
 }

@@ -87,6 +87,7 @@ struct View {
     double eps_lv[MAXLEV];            // MR criterion: threshold of the details of each level
     int rk;                           // MR scheme: 0 midpoint rule, 1 Heun
     int ausm_cs;                      // AUSM+ interface sound speed: 0 mean, 1 critical
+    int tiler;                        // 0 block split, 1 Berger-Rigoutsos clustering
     const Grid *grids;                // device copy of the grid table
     Grid gt[MAXLEV];                  // the first MAXLEV grids (every level of a hierarchy), by
                                       // value: kernels read them with their arguments
@@ -100,7 +101,7 @@ struct View {
     Tile *leaf, *cov, *ghost, *fresh; // work lists
     Tile *actv;                       // every block in a patch, by level
     void *reg;                        // local time stepping flux registers (state type)
-    int *pslot;                       // per pmax-block patch slots (5 ints each)
+    int *pslot;                       // per pmax-block patch rows (7 ints each)
     int *pcnt;                        // per pmax-block patch counts
     int *fcnt;                        // per pmax-block flagged-cell counts
     long long *cpart;                 // per classification workgroup and level (NPART values):

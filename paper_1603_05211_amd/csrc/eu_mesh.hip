@@ -83,6 +83,163 @@ __host__ __device__ constexpr int tree_offset(int k)
     return o;
 }
 
+// Berger-Rigoutsos clustering of one pmax block (the AMR method's patch
+// generation, Sec. 2.2; Berger and Rigoutsos 1991) on the grid of its R^D
+// blocks of BS^D cells, the smallest patches.  One wave runs it, one lane per
+// block (lanes past the R^D blocks hold none); a block's weight is the count
+// of flagged cells among its (BS/2)^D parents (cnt, x fastest).  A box of
+// blocks (inclusive bounds) is
+//   shrunk to its weighted blocks (none: dropped);
+//   a patch when its weighted fraction of parent cells reaches eta, or when
+//   it is one block;
+//   else cut just above the zero of its signature (the weight per slice)
+//   nearest the middle (ties: the lower slice), the axes taken longest
+//   first (ties: x, y, z); else between slices i and i+1 where the second
+//   difference of the signature changes sign, the largest jump of it over
+//   all axes (ties: the axis order, then nearest the middle, then the lower
+//   i); else halved along the longest axis, the lower half the smaller;
+// and the lower part is clustered before the upper one.  Parts waiting for
+// their turn sit on a stack with one entry per lane (they are disjoint and
+// nonempty: at most R^D of them).  Every branch is wave-uniform.  Writes the
+// patch rows (7 ints: level, origin, extents) to out in the order found and
+// returns their number; inbox: whether the lane's block lies in a patch.
+template <int D, int R>
+__device__ __forceinline__ int br_cluster_wave(const int *cnt, int lane, int sx, int sy, int sz, bool valid,
+                                               double eta, int lvl, const int *bp, int *out, bool &inbox)
+{
+    constexpr int NSUB = D == 2 ? R * R : R * R * R;
+    constexpr int q = BS / 2;
+    const int w = valid ? cnt[sx + R * (sy + R * sz)] : 0;
+    // the box's bounds, wave-uniform, and access to them by a runtime axis
+    int lo0 = 0, lo1 = 0, lo2 = 0, hi0 = R - 1, hi1 = R - 1, hi2 = D == 3 ? R - 1 : 0;
+    auto lo_of = [&](int a) { return a == 0 ? lo0 : a == 1 ? lo1 : lo2; };
+    auto hi_of = [&](int a) { return a == 0 ? hi0 : a == 1 ? hi1 : hi2; };
+    inbox = false;
+    int np = 0, sp = 0, stk = 0;
+    for (;;) {
+        const bool in = valid && sx >= lo0 && sx <= hi0 && sy >= lo1 && sy <= hi1 && sz >= lo2 && sz <= hi2;
+        const int wl = in ? w : 0;
+        // occupied slices of each axis (8 bits per axis) and the box's weight
+        int occ = wl > 0 ? (1 << sx) | (1 << (8 + sy)) | (1 << (16 + sz)) : 0, tot = wl;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            occ |= __shfl_xor(occ, o);
+            tot += __shfl_xor(tot, o);
+        }
+        occ = __builtin_amdgcn_readfirstlane(occ);
+        tot = __builtin_amdgcn_readfirstlane(tot);
+        if (occ != 0) {
+            // shrink to the weighted blocks
+            lo0 = __builtin_ctz(occ & 0xff);
+            hi0 = 31 - __builtin_clz(occ & 0xff);
+            lo1 = __builtin_ctz((occ >> 8) & 0xff);
+            hi1 = 31 - __builtin_clz((occ >> 8) & 0xff);
+            lo2 = __builtin_ctz((occ >> 16) & 0xff);
+            hi2 = 31 - __builtin_clz((occ >> 16) & 0xff);
+            int64_t cells = (int64_t)(hi0 - lo0 + 1) * q * ((hi1 - lo1 + 1) * q);
+            if (D == 3) cells *= (int64_t)(hi2 - lo2 + 1) * q;
+            const bool single = lo0 == hi0 && lo1 == hi1 && lo2 == hi2;
+            if (single || (double)tot >= eta * (double)cells) {
+                inbox = inbox || (in && sx >= lo0 && sx <= hi0 && sy >= lo1 && sy <= hi1 && sz >= lo2 && sz <= hi2);
+                int val = lvl;
+                val = lane == 1 ? (bp[0] * R + lo0) * BS : val;
+                val = lane == 2 ? (bp[1] * R + lo1) * BS : val;
+                val = lane == 3 ? (D == 3 ? (bp[2] * R + lo2) * BS : 0) : val;
+                val = lane == 4 ? (hi0 - lo0 + 1) * BS : val;
+                val = lane == 5 ? (hi1 - lo1 + 1) * BS : val;
+                val = lane == 6 ? (D == 3 ? (hi2 - lo2 + 1) * BS : 1) : val;
+                if (lane < 7) out[7 * np + lane] = val;
+                ++np;
+            } else {
+                // axes, longest first (ties: the lower axis)
+                int ax0 = 0, ax1 = 1, ax2 = 2;
+                auto longer = [&](int a, int b) {
+                    const int la = hi_of(a) - lo_of(a), lb = hi_of(b) - lo_of(b);
+                    return lb > la || (lb == la && b < a);
+                };
+                if (longer(ax0, ax1)) { const int t = ax0; ax0 = ax1; ax1 = t; }
+                if (D == 3) {
+                    if (longer(ax0, ax2)) { const int t = ax0; ax0 = ax2; ax2 = t; }
+                    if (longer(ax1, ax2)) { const int t = ax1; ax1 = ax2; ax2 = t; }
+                }
+                auto axis = [&](int k) { return k == 0 ? ax0 : k == 1 ? ax1 : ax2; };
+                int cut_axis = -1, cut_at = 0;
+                // a zero of the signature: an unoccupied slice inside the box
+                for (int k = 0; k < D && cut_axis < 0; ++k) {
+                    const int a = axis(k), la = lo_of(a), ha = hi_of(a), f = (occ >> (8 * a)) & 0xff;
+                    int best = -1, bd = 0;
+                    for (int i = la + 1; i <= ha - 1; ++i)
+                        if (!((f >> i) & 1)) {
+                            const int dd = abs(2 * i - (la + ha));
+                            if (best < 0 || dd < bd) {
+                                best = i;
+                                bd = dd;
+                            }
+                        }
+                    if (best >= 0) {
+                        cut_axis = a;
+                        cut_at = best;
+                    }
+                }
+                if (cut_axis < 0) {
+                    // signatures: lane 8 a + i holds slice i of axis a
+                    const int sa = (lane >> 3) < 3 ? lane >> 3 : 0, si = lane & 7;
+                    int sig = 0;
+                    for (int b = 0; b < NSUB; ++b) {
+                        const int bx = b % R, by = (b / R) % R, bz = D == 3 ? b / (R * R) : 0;
+                        const int bc = sa == 0 ? bx : sa == 1 ? by : bz;
+                        const bool inb = bx >= lo0 && bx <= hi0 && by >= lo1 && by <= hi1 && bz >= lo2 && bz <= hi2;
+                        if (inb && bc == si) sig += cnt[b];
+                    }
+                    int bs = 0, bdist = 0;
+                    for (int k = 0; k < D; ++k) {
+                        const int a = axis(k), la = lo_of(a), ha = hi_of(a);
+                        for (int i = la + 1; i + 1 <= ha - 1; ++i) {
+                            const int s0 = __shfl(sig, 8 * a + i - 1), s1 = __shfl(sig, 8 * a + i);
+                            const int s2 = __shfl(sig, 8 * a + i + 1), s3 = __shfl(sig, 8 * a + i + 2);
+                            const int d0 = s0 - 2 * s1 + s2, d1 = s1 - 2 * s2 + s3;
+                            if (!((d0 < 0 && d1 > 0) || (d0 > 0 && d1 < 0))) continue;
+                            const int st = abs(d0 - d1), dist = abs(2 * i + 1 - (la + ha));
+                            if (cut_axis < 0 || st > bs || (st == bs && a == cut_axis && dist < bdist)) {
+                                cut_axis = a;
+                                cut_at = i;
+                                bs = st;
+                                bdist = dist;
+                            }
+                        }
+                    }
+                }
+                if (cut_axis < 0) {
+                    cut_axis = ax0;
+                    cut_at = lo_of(ax0) + (hi_of(ax0) - lo_of(ax0) + 1) / 2 - 1;
+                }
+                // push the upper part (bounds packed 3 bits each), go on with the lower
+                int ulo0 = lo0, ulo1 = lo1, ulo2 = lo2;
+                if (cut_axis == 0) ulo0 = cut_at + 1;
+                if (cut_axis == 1) ulo1 = cut_at + 1;
+                if (cut_axis == 2) ulo2 = cut_at + 1;
+                const int pk = ulo0 | ulo1 << 3 | ulo2 << 6 | hi0 << 9 | hi1 << 12 | hi2 << 15;
+                if (lane == sp) stk = pk;
+                ++sp;
+                if (cut_axis == 0) hi0 = cut_at;
+                if (cut_axis == 1) hi1 = cut_at;
+                if (cut_axis == 2) hi2 = cut_at;
+                continue;
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        const int pk = __builtin_amdgcn_readfirstlane(__shfl(stk, sp));
+        lo0 = pk & 7;
+        lo1 = (pk >> 3) & 7;
+        lo2 = (pk >> 6) & 7;
+        hi0 = (pk >> 9) & 7;
+        hi1 = (pk >> 12) & 7;
+        hi2 = (pk >> 15) & 7;
+    }
+    return np;
+}
+
 // R = pmax / BS (1, 2, 4 or 8): every size below is a compile-time constant,
 // so the loops unroll and no index needs a runtime division.
 template <int D, int R, bool CHAIN>
@@ -331,7 +488,17 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
             if (D == 3) sz |= ((mc >> (b * D + 2)) & 1) << b;
         }
     };
-    int *out = v.pslot + slot * (int64_t)NSUB * 5;
+    int *out = v.pslot + slot * (int64_t)NSUB * 7;
+    // a square patch of side S at block (sx, sy, sz) as row pos
+    auto put_row = [&](int pos, int sx, int sy, int sz, int S) {
+        out[7 * pos + 0] = lvl + 1;
+        out[7 * pos + 1] = bp[0] * R * BS + sx * BS;
+        out[7 * pos + 2] = bp[1] * R * BS + sy * BS;
+        out[7 * pos + 3] = D == 3 ? bp[2] * R * BS + sz * BS : 0;
+        out[7 * pos + 4] = S;
+        out[7 * pos + 5] = S;
+        out[7 * pos + 6] = D == 3 ? S : 1;
+    };
     if constexpr (NSUB <= 64) {
         // one wave walks: lane = Morton code, so the sub-blocks of a node of
         // level k are an aligned group of 2^(D k) lanes and its count is a
@@ -341,40 +508,42 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
             const int mc = lane;
             int sx, sy, sz;
             morton_split(mc, sx, sy, sz);
-            int cn[K + 1];
-            cn[0] = mc < NSUB ? cnt8[sx + R * (sy + R * sz)] : 0;
+            bool inp;
+            int npatch;
+            if (v.tiler == 1) {
+                npatch = br_cluster_wave<D, R>(cnt8, lane, sx, sy, sz, mc < NSUB, v.eta, lvl + 1, bp, out, inp);
+            } else {
+                int cn[K + 1];
+                cn[0] = mc < NSUB ? cnt8[sx + R * (sy + R * sz)] : 0;
 #pragma unroll
-            for (int k = 1; k <= K; ++k) {
-                int t = cn[k - 1];
+                for (int k = 1; k <= K; ++k) {
+                    int t = cn[k - 1];
 #pragma unroll
-                for (int o = 1 << (D * (k - 1)); o < (1 << (D * k)); o <<= 1) t += __shfl_xor(t, o);
-                cn[k] = t;
+                    for (int o = 1 << (D * (k - 1)); o < (1 << (D * k)); o <<= 1) t += __shfl_xor(t, o);
+                    cn[k] = t;
+                }
+                const int emit_k = mc < NSUB ? emit_level(cn) : -1;
+                const int em = (1 << (emit_k < 0 ? 0 : emit_k)) - 1;
+                const bool lead = emit_k >= 0 && (sx & em) == 0 && (sy & em) == 0 && (sz & em) == 0;
+                const unsigned long long mask = __ballot(lead);
+                const int pos = __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
+                if (lead) put_row(pos, sx, sy, sz, BS << emit_k);
+                inp = emit_k >= 0;
+                npatch = __popcll(mask);
             }
-            const int emit_k = mc < NSUB ? emit_level(cn) : -1;
-            const int em = (1 << (emit_k < 0 ? 0 : emit_k)) - 1;
-            const bool lead = emit_k >= 0 && (sx & em) == 0 && (sy & em) == 0 && (sz & em) == 0;
-            if (mc < NSUB) emit8[sx + R * (sy + R * sz)] = emit_k >= 0 ? 1 : 0;
+            if (mc < NSUB) emit8[sx + R * (sy + R * sz)] = inp ? 1 : 0;
             if constexpr (CHAIN) {
                 // publish the masks (bit = Morton code) for the next coarser level
-                const unsigned long long pub = __ballot(emit_k >= 0);
+                const unsigned long long pub = __ballot(inp && mc < NSUB);
                 if (lane == 0)
                     __hip_atomic_store(v.fword + slot, ep | pub << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            const unsigned long long mask = __ballot(lead);
-            const int pos = __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
-            if (lead) {
-                out[5 * pos + 0] = lvl + 1;
-                out[5 * pos + 1] = bp[0] * R * BS + sx * BS;
-                out[5 * pos + 2] = bp[1] * R * BS + sy * BS;
-                out[5 * pos + 3] = D == 3 ? bp[2] * R * BS + sz * BS : 0;
-                out[5 * pos + 4] = BS << emit_k;
             }
             if (lane == 0) {
                 int tot = 0;
 #pragma unroll
                 for (int w = 0; w < NT / 64; ++w) tot += wsum[w];
                 v.fcnt[slot] = tot;
-                v.pcnt[slot] = __popcll(mask);
+                v.pcnt[slot] = npatch;
             }
         }
         __syncthreads();
@@ -425,13 +594,7 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
             __syncthreads();
             int pos = nlead_total + __popcll(mask & (lane ? (~0ull >> (64 - lane)) : 0ull));
             for (int w = 0; w < wave; ++w) pos += wlead[w];
-            if (lead) {
-                out[5 * pos + 0] = lvl + 1;
-                out[5 * pos + 1] = bp[0] * R * BS + sx * BS;
-                out[5 * pos + 2] = bp[1] * R * BS + sy * BS;
-                out[5 * pos + 3] = D == 3 ? bp[2] * R * BS + sz * BS : 0;
-                out[5 * pos + 4] = BS << emit_k;
-            }
+            if (lead) put_row(pos, sx, sy, sz, BS << emit_k);
 #pragma unroll
             for (int w = 0; w < NT / 64; ++w) nlead_total += wlead[w];
             __syncthreads();
@@ -778,7 +941,7 @@ __device__ void lists_body(const View &v, int64_t nbt, int w, int W)
     __syncthreads();
     const int64_t chunk = (nbt + W - 1) / W;
     const int64_t g0 = w * chunk, g1 = g0 + chunk < nbt ? g0 + chunk : nbt;
-    // this build's epoch; with WORDS also that of the flagging words, which
+    // the epoch of this launch; with WORDS also that of the flagging words, which
     // are raised with the list words by every such launch (both start at
     // zero with the hierarchy)
     const unsigned long long e = ((own & 0xffffull) + 1) & 0xffffull;

@@ -152,3 +152,14 @@ def test_criterion_checks(kw):
     assert r == _abi.EU_EINVAL
     r, _, _ = sizes(cfg(criterion=1, levels=4, eps=0.05, eps_p=0.05))
     assert r == _abi.EU_OK
+
+
+def test_tiler_checks():
+    """Berger-Rigoutsos clustering runs on one wave per patch_max block: at
+    most 64 blocks of 8^d cells in it."""
+    assert sizes(cfg(tiler=_abi.EU_TILER_BR))[0] == _abi.EU_OK
+    assert sizes(cfg(tiler=_abi.EU_TILER_BR, patch_max=64))[0] == _abi.EU_OK
+    assert sizes(cfg(tiler=_abi.EU_TILER_BR, dim=3, n0=32, levels=3, lo=-1.0, patch_max=32))[0] == _abi.EU_OK
+    assert sizes(cfg(tiler=_abi.EU_TILER_BR, dim=3, n0=32, levels=3, lo=-1.0, patch_max=64))[0] == _abi.EU_EINVAL
+    assert sizes(cfg(tiler=2))[0] == _abi.EU_EINVAL
+    assert sizes(cfg(tiler=-1))[0] == _abi.EU_EINVAL
