@@ -83,12 +83,26 @@ __host__ __device__ constexpr int tree_offset(int k)
     return o;
 }
 
+// Bit masks over the R^D blocks of a pmax block, bit s for the block at
+// s = x + R (y + R z) (R^D <= 64): bits [lo u, (hi+1) u), and a bit at every
+// multiple of stride, count of them.
+__device__ __forceinline__ unsigned long long br_field(int lo, int hi, int u)
+{
+    const int top = (hi + 1) * u;
+    return (top >= 64 ? ~0ull : (1ull << top) - 1ull) & ~((1ull << (lo * u)) - 1ull);
+}
+__host__ __device__ constexpr unsigned long long br_rep(int stride, int count)
+{
+    unsigned long long m = 0;
+    for (int k = 0; k < count; ++k) m |= 1ull << (k * stride);
+    return m;
+}
+
 // Berger-Rigoutsos clustering of one pmax block (the AMR method's patch
 // generation, Sec. 2.2; Berger and Rigoutsos 1991) on the grid of its R^D
-// blocks of BS^D cells, the smallest patches.  One wave runs it, one lane per
-// block (lanes past the R^D blocks hold none); a block's weight is the count
-// of flagged cells among its (BS/2)^D parents (cnt, x fastest).  A box of
-// blocks (inclusive bounds) is
+// blocks of BS^D cells, the smallest patches; a block's weight is the count
+// of flagged cells among its (BS/2)^D parents.  A box of blocks (inclusive
+// bounds) is
 //   shrunk to its weighted blocks (none: dropped);
 //   a patch when its weighted fraction of parent cells reaches eta, or when
 //   it is one block;
@@ -98,49 +112,165 @@ __host__ __device__ constexpr int tree_offset(int k)
 //   difference of the signature changes sign, the largest jump of it over
 //   all axes (ties: the axis order, then nearest the middle, then the lower
 //   i); else halved along the longest axis, the lower half the smaller;
-// and the lower part is clustered before the upper one.  Parts waiting for
-// their turn sit on a stack with one entry per lane (they are disjoint and
-// nonempty: at most R^D of them).  Every branch is wave-uniform.  Writes the
-// patch rows (7 ints: level, origin, extents) to out in the order found and
-// returns their number; inbox: whether the lane's block lies in a patch.
+// and the lower part is clustered before the upper one.
+//
+// The weights are held as bit planes of 64-bit masks (W[b]: the blocks
+// whose weight has bit b; M: the blocks with weight), so a box is a mask
+// and every weight over a box or a slice is a sum of popcounts.  The
+// outcome for a box depends on the box alone; br_decide computes it, packed:
+// bits 0-17 the shrunk box (lo x, y, z, hi x, y, z, 3 bits each), 18-19
+// the cut axis, 20-22 the last slice of the lower part, bit 23 a patch,
+// bit 24 empty.
+constexpr int BR_AX = 18, BR_AT = 20, BR_EMIT = 1 << 23, BR_EMPTY = 1 << 24;
+
 template <int D, int R>
-__device__ __forceinline__ int br_cluster_wave(const int *cnt, int lane, int sx, int sy, int sz, bool valid,
-                                               double eta, int lvl, const int *bp, int *out, bool &inbox)
+__device__ __forceinline__ int br_decide(int lo0, int lo1, int lo2, int hi0, int hi1, int hi2,
+                                         const unsigned long long *W, unsigned long long M, double eta)
 {
     constexpr int NSUB = D == 2 ? R * R : R * R * R;
     constexpr int q = BS / 2;
-    const int w = valid ? cnt[sx + R * (sy + R * sz)] : 0;
-    // the box's bounds, wave-uniform, and access to them by a runtime axis
-    int lo0 = 0, lo1 = 0, lo2 = 0, hi0 = R - 1, hi1 = R - 1, hi2 = D == 3 ? R - 1 : 0;
+    constexpr int WB = D == 2 ? 5 : 7;   // bits of a weight (at most q^D = 16 or 64)
+    constexpr unsigned long long X0 = br_rep(R, NSUB / R);            // slice x = 0
+    constexpr unsigned long long Y0 = D == 2 ? br_rep(1, R) : br_rep(1, R) * br_rep(R * R, R);   // y = 0
+    constexpr unsigned long long Z0 = br_rep(1, R * R);               // z = 0 (3D)
+    auto slice = [&](int a, int i) { return a == 0 ? X0 << i : a == 1 ? Y0 << (R * i) : Z0 << (R * R * i); };
+    auto weight = [&](unsigned long long m) {
+        int t = 0;
+#pragma unroll
+        for (int bit = 0; bit < WB; ++bit) t += __popcll(W[bit] & m) << bit;
+        return t;
+    };
+    unsigned long long m = (br_field(lo0, hi0, 1) * br_rep(R, NSUB / R)) &
+                           br_field(lo1, hi1, R) * (D == 2 ? 1ull : br_rep(R * R, R));
+    if (D == 3) m &= br_field(lo2, hi2, R * R);
+    m &= M;
+    if (m == 0) return BR_EMPTY;
+    // shrink to the weighted blocks
+    int occ0 = 0, occ1 = 0, occ2 = D == 3 ? 0 : 1;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        occ0 |= (m & (X0 << i)) ? 1 << i : 0;
+        occ1 |= (m & (Y0 << (R * i))) ? 1 << i : 0;
+        if (D == 3) occ2 |= (m & (Z0 << (R * R * i))) ? 1 << i : 0;
+    }
+    lo0 = __builtin_ctz(occ0);
+    hi0 = 31 - __builtin_clz(occ0);
+    lo1 = __builtin_ctz(occ1);
+    hi1 = 31 - __builtin_clz(occ1);
+    lo2 = __builtin_ctz(occ2);
+    hi2 = 31 - __builtin_clz(occ2);
+    const int shrunk = lo0 | lo1 << 3 | lo2 << 6 | hi0 << 9 | hi1 << 12 | hi2 << 15;
+    const int tot = weight(m);   // every weighted block of the box lies in the shrunk one
+    int64_t cells = (int64_t)(hi0 - lo0 + 1) * q * ((hi1 - lo1 + 1) * q);
+    if (D == 3) cells *= (int64_t)(hi2 - lo2 + 1) * q;
+    const bool single = lo0 == hi0 && lo1 == hi1 && lo2 == hi2;
+    if (single || (double)tot >= eta * (double)cells) return shrunk | BR_EMIT;
     auto lo_of = [&](int a) { return a == 0 ? lo0 : a == 1 ? lo1 : lo2; };
     auto hi_of = [&](int a) { return a == 0 ? hi0 : a == 1 ? hi1 : hi2; };
+    auto occ_of = [&](int a) { return a == 0 ? occ0 : a == 1 ? occ1 : occ2; };
+    // axes, longest first (ties: the lower axis)
+    int ax0 = 0, ax1 = 1, ax2 = 2;
+    auto longer = [&](int a, int b) {
+        const int la = hi_of(a) - lo_of(a), lb = hi_of(b) - lo_of(b);
+        return lb > la || (lb == la && b < a);
+    };
+    if (longer(ax0, ax1)) { const int t = ax0; ax0 = ax1; ax1 = t; }
+    if (D == 3) {
+        if (longer(ax0, ax2)) { const int t = ax0; ax0 = ax2; ax2 = t; }
+        if (longer(ax1, ax2)) { const int t = ax1; ax1 = ax2; ax2 = t; }
+    }
+    auto axis = [&](int k) { return k == 0 ? ax0 : k == 1 ? ax1 : ax2; };
+    int cut_axis = -1, cut_at = 0;
+    // a zero of the signature: an unoccupied slice inside the box
+    for (int k = 0; k < D && cut_axis < 0; ++k) {
+        const int a = axis(k), la = lo_of(a), ha = hi_of(a), f = occ_of(a);
+        int best = -1, bd = 0;
+        for (int i = la + 1; i <= ha - 1; ++i)
+            if (!((f >> i) & 1)) {
+                const int dd = abs(2 * i - (la + ha));
+                if (best < 0 || dd < bd) {
+                    best = i;
+                    bd = dd;
+                }
+            }
+        if (best >= 0) {
+            cut_axis = a;
+            cut_at = best;
+        }
+    }
+    if (cut_axis < 0) {
+        // the strongest inflection of the signatures
+        int bs = 0, bdist = 0;
+        for (int k = 0; k < D; ++k) {
+            const int a = axis(k), la = lo_of(a), ha = hi_of(a);
+            for (int i = la + 1; i + 1 <= ha - 1; ++i) {
+                const int s0 = weight(m & slice(a, i - 1)), s1 = weight(m & slice(a, i));
+                const int s2 = weight(m & slice(a, i + 1)), s3 = weight(m & slice(a, i + 2));
+                const int d0 = s0 - 2 * s1 + s2, d1 = s1 - 2 * s2 + s3;
+                if (!((d0 < 0 && d1 > 0) || (d0 > 0 && d1 < 0))) continue;
+                const int st = abs(d0 - d1), dist = abs(2 * i + 1 - (la + ha));
+                if (cut_axis < 0 || st > bs || (st == bs && a == cut_axis && dist < bdist)) {
+                    cut_axis = a;
+                    cut_at = i;
+                    bs = st;
+                    bdist = dist;
+                }
+            }
+        }
+    }
+    if (cut_axis < 0) {
+        cut_axis = ax0;
+        cut_at = lo_of(ax0) + (hi_of(ax0) - lo_of(ax0) + 1) / 2 - 1;
+    }
+    return shrunk | cut_axis << BR_AX | cut_at << BR_AT;
+}
+
+// Boxes of an R^D grid of blocks numbered by their intervals: interval
+// (lo, hi) of an axis is number lo R - lo (lo - 1) / 2 + hi - lo of NI =
+// R (R + 1) / 2, the box is x + NI (y + NI z).
+template <int D, int R>
+struct BrBoxes {
+    static constexpr int NI = R * (R + 1) / 2;
+    static constexpr int N = D == 2 ? NI * NI : NI * NI * NI;
+    static __device__ __forceinline__ int interval(int lo, int hi) { return lo * R - lo * (lo - 1) / 2 + hi - lo; }
+    static __device__ __forceinline__ void bounds(int iv, int &lo, int &hi)
+    {
+        lo = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (iv >= R - lo) {
+                iv -= R - lo;
+                ++lo;
+            }
+        hi = lo + iv;
+    }
+};
+
+// The clustering's depth-first walk, in wave-uniform scalar code on one
+// wave, each box decided as it is met (grids whose boxes do not fit one
+// pass of the workgroup).  Parts waiting for their turn sit on a stack with
+// one entry per lane (they are disjoint and nonempty: at most R^D of them).
+// Writes the patch rows (7 ints: level, origin, extents) to out in the order
+// found and returns their number; inbox: whether the lane's block (sx, sy,
+// sz; valid) lies in a patch.
+template <int D, int R>
+__device__ __forceinline__ int br_walk(const unsigned long long *W, unsigned long long M, double eta, int lane, int sx,
+                                       int sy, int sz, bool valid, int lvl, const int *bp, int *out, bool &inbox)
+{
+    int lo0 = 0, lo1 = 0, lo2 = 0, hi0 = R - 1, hi1 = R - 1, hi2 = D == 3 ? R - 1 : 0;
     inbox = false;
     int np = 0, sp = 0, stk = 0;
     for (;;) {
-        const bool in = valid && sx >= lo0 && sx <= hi0 && sy >= lo1 && sy <= hi1 && sz >= lo2 && sz <= hi2;
-        const int wl = in ? w : 0;
-        // occupied slices of each axis (8 bits per axis) and the box's weight
-        int occ = wl > 0 ? (1 << sx) | (1 << (8 + sy)) | (1 << (16 + sz)) : 0, tot = wl;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            occ |= __shfl_xor(occ, o);
-            tot += __shfl_xor(tot, o);
-        }
-        occ = __builtin_amdgcn_readfirstlane(occ);
-        tot = __builtin_amdgcn_readfirstlane(tot);
-        if (occ != 0) {
-            // shrink to the weighted blocks
-            lo0 = __builtin_ctz(occ & 0xff);
-            hi0 = 31 - __builtin_clz(occ & 0xff);
-            lo1 = __builtin_ctz((occ >> 8) & 0xff);
-            hi1 = 31 - __builtin_clz((occ >> 8) & 0xff);
-            lo2 = __builtin_ctz((occ >> 16) & 0xff);
-            hi2 = 31 - __builtin_clz((occ >> 16) & 0xff);
-            int64_t cells = (int64_t)(hi0 - lo0 + 1) * q * ((hi1 - lo1 + 1) * q);
-            if (D == 3) cells *= (int64_t)(hi2 - lo2 + 1) * q;
-            const bool single = lo0 == hi0 && lo1 == hi1 && lo2 == hi2;
-            if (single || (double)tot >= eta * (double)cells) {
-                inbox = inbox || (in && sx >= lo0 && sx <= hi0 && sy >= lo1 && sy <= hi1 && sz >= lo2 && sz <= hi2);
+        const int d = br_decide<D, R>(lo0, lo1, lo2, hi0, hi1, hi2, W, M, eta);
+        if (!(d & BR_EMPTY)) {
+            lo0 = d & 7;
+            lo1 = (d >> 3) & 7;
+            lo2 = (d >> 6) & 7;
+            hi0 = (d >> 9) & 7;
+            hi1 = (d >> 12) & 7;
+            hi2 = (d >> 15) & 7;
+            if (d & BR_EMIT) {
+                inbox = inbox || (valid && sx >= lo0 && sx <= hi0 && sy >= lo1 && sy <= hi1 && sz >= lo2 && sz <= hi2);
                 int val = lvl;
                 val = lane == 1 ? (bp[0] * R + lo0) * BS : val;
                 val = lane == 2 ? (bp[1] * R + lo1) * BS : val;
@@ -151,74 +281,9 @@ __device__ __forceinline__ int br_cluster_wave(const int *cnt, int lane, int sx,
                 if (lane < 7) out[7 * np + lane] = val;
                 ++np;
             } else {
-                // axes, longest first (ties: the lower axis)
-                int ax0 = 0, ax1 = 1, ax2 = 2;
-                auto longer = [&](int a, int b) {
-                    const int la = hi_of(a) - lo_of(a), lb = hi_of(b) - lo_of(b);
-                    return lb > la || (lb == la && b < a);
-                };
-                if (longer(ax0, ax1)) { const int t = ax0; ax0 = ax1; ax1 = t; }
-                if (D == 3) {
-                    if (longer(ax0, ax2)) { const int t = ax0; ax0 = ax2; ax2 = t; }
-                    if (longer(ax1, ax2)) { const int t = ax1; ax1 = ax2; ax2 = t; }
-                }
-                auto axis = [&](int k) { return k == 0 ? ax0 : k == 1 ? ax1 : ax2; };
-                int cut_axis = -1, cut_at = 0;
-                // a zero of the signature: an unoccupied slice inside the box
-                for (int k = 0; k < D && cut_axis < 0; ++k) {
-                    const int a = axis(k), la = lo_of(a), ha = hi_of(a), f = (occ >> (8 * a)) & 0xff;
-                    int best = -1, bd = 0;
-                    for (int i = la + 1; i <= ha - 1; ++i)
-                        if (!((f >> i) & 1)) {
-                            const int dd = abs(2 * i - (la + ha));
-                            if (best < 0 || dd < bd) {
-                                best = i;
-                                bd = dd;
-                            }
-                        }
-                    if (best >= 0) {
-                        cut_axis = a;
-                        cut_at = best;
-                    }
-                }
-                if (cut_axis < 0) {
-                    // signatures: lane 8 a + i holds slice i of axis a
-                    const int sa = (lane >> 3) < 3 ? lane >> 3 : 0, si = lane & 7;
-                    int sig = 0;
-                    for (int b = 0; b < NSUB; ++b) {
-                        const int bx = b % R, by = (b / R) % R, bz = D == 3 ? b / (R * R) : 0;
-                        const int bc = sa == 0 ? bx : sa == 1 ? by : bz;
-                        const bool inb = bx >= lo0 && bx <= hi0 && by >= lo1 && by <= hi1 && bz >= lo2 && bz <= hi2;
-                        if (inb && bc == si) sig += cnt[b];
-                    }
-                    int bs = 0, bdist = 0;
-                    for (int k = 0; k < D; ++k) {
-                        const int a = axis(k), la = lo_of(a), ha = hi_of(a);
-                        for (int i = la + 1; i + 1 <= ha - 1; ++i) {
-                            const int s0 = __shfl(sig, 8 * a + i - 1), s1 = __shfl(sig, 8 * a + i);
-                            const int s2 = __shfl(sig, 8 * a + i + 1), s3 = __shfl(sig, 8 * a + i + 2);
-                            const int d0 = s0 - 2 * s1 + s2, d1 = s1 - 2 * s2 + s3;
-                            if (!((d0 < 0 && d1 > 0) || (d0 > 0 && d1 < 0))) continue;
-                            const int st = abs(d0 - d1), dist = abs(2 * i + 1 - (la + ha));
-                            if (cut_axis < 0 || st > bs || (st == bs && a == cut_axis && dist < bdist)) {
-                                cut_axis = a;
-                                cut_at = i;
-                                bs = st;
-                                bdist = dist;
-                            }
-                        }
-                    }
-                }
-                if (cut_axis < 0) {
-                    cut_axis = ax0;
-                    cut_at = lo_of(ax0) + (hi_of(ax0) - lo_of(ax0) + 1) / 2 - 1;
-                }
-                // push the upper part (bounds packed 3 bits each), go on with the lower
-                int ulo0 = lo0, ulo1 = lo1, ulo2 = lo2;
-                if (cut_axis == 0) ulo0 = cut_at + 1;
-                if (cut_axis == 1) ulo1 = cut_at + 1;
-                if (cut_axis == 2) ulo2 = cut_at + 1;
-                const int pk = ulo0 | ulo1 << 3 | ulo2 << 6 | hi0 << 9 | hi1 << 12 | hi2 << 15;
+                // push the upper part (packed as the decision's box), go on with the lower
+                const int cut_axis = (d >> BR_AX) & 3, cut_at = (d >> BR_AT) & 7;
+                const int pk = (d & 0x3ffff & ~(7 << (3 * cut_axis))) | (cut_at + 1) << (3 * cut_axis);
                 if (lane == sp) stk = pk;
                 ++sp;
                 if (cut_axis == 0) hi0 = cut_at;
@@ -229,7 +294,7 @@ __device__ __forceinline__ int br_cluster_wave(const int *cnt, int lane, int sx,
         }
         if (sp == 0) break;
         --sp;
-        const int pk = __builtin_amdgcn_readfirstlane(__shfl(stk, sp));
+        const int pk = __builtin_amdgcn_readlane(stk, sp);
         lo0 = pk & 7;
         lo1 = (pk >> 3) & 7;
         lo2 = (pk >> 6) & 7;
@@ -504,6 +569,94 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
         // level k are an aligned group of 2^(D k) lanes and its count is a
         // sum over the group
         __syncthreads();
+        // clustering: the weight planes (every wave takes the same ballots);
+        // where the boxes fit one pass of the workgroup (thread = box) it
+        // runs in parallel: every box's outcome, then the patch count of the
+        // clustering below every box (bottom-up, one pass per level of the
+        // tree: a box's height is at most D (R - 1)), then the position of
+        // every box the depth-first walk meets (top-down from the whole
+        // block: a cut box's lower part at its own position, its upper part
+        // after the lower part's patches); the boxes met that are patches
+        // write their rows.  Elsewhere wave 0 walks the boxes one by one.
+        using BB = BrBoxes<D, R>;
+        constexpr bool BR_PRE = BB::N <= NT;
+        constexpr int BR_PASSES = D * (R - 1);
+        constexpr int BR_ROOT = (R - 1) + BB::NI * ((R - 1) + BB::NI * (D == 3 ? R - 1 : 0));
+        __shared__ int scnt[2][BR_PRE ? BB::N : 1], spos[BR_PRE ? BB::N : 1];
+        __shared__ unsigned long long smember;
+        __shared__ int snp;
+        unsigned long long Wp[D == 2 ? 5 : 7], Mp = 0;
+        if (v.tiler == 1) {
+            const int wlin = lane < NSUB ? cnt8[lane] : 0;
+#pragma unroll
+            for (int bit = 0; bit < (D == 2 ? 5 : 7); ++bit) Wp[bit] = __ballot((wlin >> bit) & 1);
+            Mp = __ballot(wlin > 0);
+            if constexpr (BR_PRE) {
+                const int b = threadIdx.x;
+                const bool own = b < BB::N;
+                int d = BR_EMPTY, cl = 0, cu = 0;
+                if (own) {
+                    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+                    BB::bounds(b % BB::NI, lo[0], hi[0]);
+                    BB::bounds((b / BB::NI) % BB::NI, lo[1], hi[1]);
+                    if (D == 3) BB::bounds(b / (BB::NI * BB::NI), lo[2], hi[2]);
+                    d = br_decide<D, R>(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], Wp, Mp, v.eta);
+                    if (!(d & (BR_EMPTY | BR_EMIT))) {
+                        // the two parts of the cut
+                        const int a = (d >> BR_AX) & 3, at = (d >> BR_AT) & 7;
+                        int slo[3] = {d & 7, (d >> 3) & 7, (d >> 6) & 7};
+                        int shi[3] = {(d >> 9) & 7, (d >> 12) & 7, (d >> 15) & 7};
+                        int il[3], iu[3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            il[k] = BB::interval(slo[k], k == a ? at : shi[k]);
+                            iu[k] = BB::interval(k == a ? at + 1 : slo[k], shi[k]);
+                        }
+                        cl = il[0] + BB::NI * (il[1] + BB::NI * (D == 3 ? il[2] : 0));
+                        cu = iu[0] + BB::NI * (iu[1] + BB::NI * (D == 3 ? iu[2] : 0));
+                    }
+                    scnt[0][b] = (d & BR_EMIT) ? 1 : 0;
+                    spos[b] = b == BR_ROOT ? 0 : -1;
+                }
+                if (threadIdx.x == 0) smember = 0ull;
+                const bool cut = own && !(d & (BR_EMPTY | BR_EMIT));
+                __syncthreads();
+#pragma unroll
+                for (int p = 0; p < BR_PASSES; ++p) {
+                    if (own) scnt[(p + 1) & 1][b] = cut ? scnt[p & 1][cl] + scnt[p & 1][cu] : scnt[p & 1][b];
+                    __syncthreads();
+                }
+                const int *cnt = scnt[BR_PASSES & 1];
+#pragma unroll
+                for (int p = 0; p < BR_PASSES; ++p) {
+                    const int at = own ? spos[b] : -1;
+                    __syncthreads();
+                    if (cut && at >= 0) {
+                        spos[cl] = at;
+                        spos[cu] = at + cnt[cl];
+                    }
+                    __syncthreads();
+                }
+                if (own && (d & BR_EMIT) && spos[b] >= 0) {
+                    const int pos = spos[b];
+                    const int lo0 = d & 7, lo1 = (d >> 3) & 7, lo2 = (d >> 6) & 7;
+                    const int hi0 = (d >> 9) & 7, hi1 = (d >> 12) & 7, hi2 = (d >> 15) & 7;
+                    out[7 * pos + 0] = lvl + 1;
+                    out[7 * pos + 1] = (bp[0] * R + lo0) * BS;
+                    out[7 * pos + 2] = (bp[1] * R + lo1) * BS;
+                    out[7 * pos + 3] = D == 3 ? (bp[2] * R + lo2) * BS : 0;
+                    out[7 * pos + 4] = (hi0 - lo0 + 1) * BS;
+                    out[7 * pos + 5] = (hi1 - lo1 + 1) * BS;
+                    out[7 * pos + 6] = D == 3 ? (hi2 - lo2 + 1) * BS : 1;
+                    unsigned long long bm = (br_field(lo0, hi0, 1) * br_rep(R, NSUB / R)) &
+                                            br_field(lo1, hi1, R) * (D == 2 ? 1ull : br_rep(R * R, R));
+                    if (D == 3) bm &= br_field(lo2, hi2, R * R);
+                    atomicOr(&smember, bm);
+                }
+                if (threadIdx.x == 0) snp = cnt[BR_ROOT];
+                __syncthreads();
+            }
+        }
         if (wave == 0) {
             const int mc = lane;
             int sx, sy, sz;
@@ -511,7 +664,12 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
             bool inp;
             int npatch;
             if (v.tiler == 1) {
-                npatch = br_cluster_wave<D, R>(cnt8, lane, sx, sy, sz, mc < NSUB, v.eta, lvl + 1, bp, out, inp);
+                if constexpr (BR_PRE) {
+                    npatch = snp;
+                    inp = mc < NSUB && ((smember >> (sx + R * (sy + R * sz))) & 1ull);
+                } else {
+                    npatch = br_walk<D, R>(Wp, Mp, v.eta, lane, sx, sy, sz, mc < NSUB, lvl + 1, bp, out, inp);
+                }
             } else {
                 int cn[K + 1];
                 cn[0] = mc < NSUB ? cnt8[sx + R * (sy + R * sz)] : 0;

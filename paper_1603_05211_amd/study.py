@@ -27,8 +27,8 @@ import time
 
 import numpy as np
 
-from . import (EU_CRIT_GRADIENT, EU_CRIT_MR, EU_DT_GLOBAL, EU_DT_LTS, EU_FP64, EU_SCHEME_AMR, EU_SCHEME_MR, Solver,
-               inputs)
+from . import (EU_CRIT_GRADIENT, EU_CRIT_MR, EU_DT_GLOBAL, EU_DT_LTS, EU_FP64, EU_SCHEME_AMR, EU_SCHEME_MR,
+               EU_TILER_BLOCKS, EU_TILER_BR, Solver, inputs)
 
 # ----------------------------------------------------------------------------
 # the measures of Sec. 3
@@ -145,8 +145,9 @@ def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 
     2^(L-1)) the six discretizations of Sec. 2, all FP64: MR-FV and AMR-FV
     (the MR and AMR schemes on the uniform N^2 grid), MR (MR scheme, MR
     criterion eps, global step), MRLT (the same with local time steps), AMR
-    (AMR scheme, scaled-gradient criterion on density eps_grad, global
-    step) and AMRLT (the same with local time steps).  Accuracy
+    (AMR scheme, scaled-gradient criterion on density eps_grad,
+    Berger-Rigoutsos clustering, global step) and AMRLT (the same with local
+    time steps); the MR runs tile with the block tiler.  Accuracy
     perturbation and time compression of an adaptive run are taken against
     the uniform run of its scheme."""
     log = log or (lambda *a: None)
@@ -173,14 +174,14 @@ def run_study(levels=(4, 5, 6), n0: int = 32, n_ref: int = 4096, t_end: float = 
                 lambda: Solver(2, n0=N, levels=1, precision=EU_FP64, cfl=cfl, t_end=t_end, scheme=sch), init, t_end)
             row[name] = {"l1": l1_error(fv.level(0)[0], rr), "gpu_s": t_fv, "steps": steps_fv}
             fv.close()
-        variants = (("MR", EU_SCHEME_MR, EU_CRIT_MR, eps, EU_DT_GLOBAL, "MR-FV"),
-                    ("MRLT", EU_SCHEME_MR, EU_CRIT_MR, eps, EU_DT_LTS, "MR-FV"),
-                    ("AMR", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, EU_DT_GLOBAL, "AMR-FV"),
-                    ("AMRLT", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, EU_DT_LTS, "AMR-FV"))
-        for name, sch, crit, e, tm, base in variants:
+        variants = (("MR", EU_SCHEME_MR, EU_CRIT_MR, eps, EU_DT_GLOBAL, "MR-FV", EU_TILER_BLOCKS),
+                    ("MRLT", EU_SCHEME_MR, EU_CRIT_MR, eps, EU_DT_LTS, "MR-FV", EU_TILER_BLOCKS),
+                    ("AMR", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, EU_DT_GLOBAL, "AMR-FV", EU_TILER_BR),
+                    ("AMRLT", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, EU_DT_LTS, "AMR-FV", EU_TILER_BR))
+        for name, sch, crit, e, tm, base, tiler in variants:
             log(f"  {name}")
             mk = lambda: Solver(2, n0=n0, levels=L, precision=EU_FP64, cfl=cfl, t_end=t_end, eps=e, eta=0.8,
-                                patch_max=32, time_mode=tm, scheme=sch, criterion=crit)
+                                patch_max=32, time_mode=tm, scheme=sch, criterion=crit, tiler=tiler)
             s, t_a, steps_a = _timed_run(mk, init, t_end)
             e_a = l1_error(s.composite()[0], rr)
             sub = 2 ** (L - 1) if tm == EU_DT_LTS else 1
@@ -215,7 +216,8 @@ def run_study_3d(levels=(3, 4, 5), n0: int = 32, n_ref: int = 1024, t_end: float
     N = n0 2^(L-1)) the six discretizations, all FP64: MR-FV and AMR-FV on
     the uniform N^3 grid, MR and MRLT (MR criterion eps = 0.013, the paper's
     3D threshold), AMR and AMRLT (scaled gradients of density and pressure,
-    eps_grad = 0.05 each, the paper's 3D thresholds)."""
+    eps_grad = 0.05 each, the paper's 3D thresholds; Berger-Rigoutsos
+    clustering)."""
     log = log or (lambda *a: None)
     e = inputs.paper_ellipsoid()
     lo, hi = -2.0, 2.0
@@ -244,14 +246,15 @@ def run_study_3d(levels=(3, 4, 5), n0: int = 32, n_ref: int = 1024, t_end: float
                 init, t_end, log)
             row[name] = {"l1": l1_error(fv.level(0)[0], rr, lo, hi), "gpu_s": t_fv, "steps": steps_fv}
             fv.close()
-        variants = (("MR", EU_SCHEME_MR, EU_CRIT_MR, eps, 0.0, EU_DT_GLOBAL, "MR-FV"),
-                    ("MRLT", EU_SCHEME_MR, EU_CRIT_MR, eps, 0.0, EU_DT_LTS, "MR-FV"),
-                    ("AMR", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, eps_grad, EU_DT_GLOBAL, "AMR-FV"),
-                    ("AMRLT", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, eps_grad, EU_DT_LTS, "AMR-FV"))
-        for name, sch, crit, e_r, e_p, tm, base in variants:
+        variants = (("MR", EU_SCHEME_MR, EU_CRIT_MR, eps, 0.0, EU_DT_GLOBAL, "MR-FV", EU_TILER_BLOCKS),
+                    ("MRLT", EU_SCHEME_MR, EU_CRIT_MR, eps, 0.0, EU_DT_LTS, "MR-FV", EU_TILER_BLOCKS),
+                    ("AMR", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, eps_grad, EU_DT_GLOBAL, "AMR-FV", EU_TILER_BR),
+                    ("AMRLT", EU_SCHEME_AMR, EU_CRIT_GRADIENT, eps_grad, eps_grad, EU_DT_LTS, "AMR-FV", EU_TILER_BR))
+        for name, sch, crit, e_r, e_p, tm, base, tiler in variants:
             log(f"  {name}")
             mk = lambda: Solver(3, n0=n0, levels=L, precision=EU_FP64, cfl=cfl, t_end=t_end, eps=e_r, eta=0.8,
-                                patch_max=32, time_mode=tm, lo=lo, hi=hi, scheme=sch, criterion=crit, eps_p=e_p)
+                                patch_max=32, time_mode=tm, lo=lo, hi=hi, scheme=sch, criterion=crit, eps_p=e_p,
+                                tiler=tiler)
             s, t_a, steps_a = _timed_run(mk, init, t_end, log)
             e_a = l1_error(s.composite()[0], rr, lo, hi)
             sub = 2 ** (L - 1) if tm == EU_DT_LTS else 1

@@ -6,7 +6,7 @@ the MR and the AMR scheme, global and local time steps."""
 import pytest
 
 import oracle as orc
-from paper_1603_05211_amd import EU_DT_GLOBAL, EU_DT_LTS, EU_FP64, EU_TILER_BR, Solver, inputs
+from paper_1603_05211_amd import EU_DT_GLOBAL, EU_DT_LTS, EU_FP32, EU_FP64, EU_TILER_BR, Solver, inputs
 
 from gpu_helpers import G, compare_masks, say, state_errors
 
@@ -87,3 +87,36 @@ def test_clustering_lts_fp64():
     linf = run(h, s, cfl, 2, lts=True)
     say("  linf", linf, "patches", len(h.patches()))
     assert linf.max() <= 1e-12
+
+
+def test_amr_method_headline_hierarchy_fp32():
+    """The AMR method as benchmarked on the five-level hierarchy (32^2 ..
+    512^2): AMR scheme, scaled-gradient criterion on density (eps 0.05),
+    Berger-Rigoutsos clustering, FP32, 60 steps against the FP64 oracle:
+    every field's L1 (relative to the density's) within 1e-5 and normwise
+    L-inf within 2e-3 on the composite, flag disagreements at most 2 % per
+    level."""
+    import numpy as np
+
+    say("clustering: AMR method fp32, headline hierarchy, 60 steps")
+    h = orc.Hierarchy(2, 5, 32, eps=0.05, eta=0.8, pmax=32, scheme=orc.SCHEME_AMR, criterion=orc.CRIT_GRADIENT,
+                      tiler=orc.TILER_BR)
+    s = Solver(2, n0=32, levels=5, precision=EU_FP32, cfl=0.45, eps=0.05, eta=0.8, patch_max=32,
+               scheme=orc.SCHEME_AMR, criterion=orc.CRIT_GRADIENT, tiler=EU_TILER_BR)
+    prim = inputs.quadrant_states(0)
+    h.init_finest(orc.init_quadrant(512, G, prim))
+    s.init_quadrant(prim)
+    for _ in range(60):
+        h.step(0.45)
+    assert s.advance(60, use_graph=True) == 60
+    g, o = s.composite(), h.composite()
+    scale = np.abs(o[0]).sum()
+    l1 = [float(np.abs(g[f] - o[f]).sum() / scale) for f in range(4)]
+    linf = [float(np.abs(g[f] - o[f]).max() / np.abs(o[f]).max()) for f in range(4)]
+    say("  L1 rel", l1, "Linf rel", linf, "patches", len(h.patches()), len(s.patches()))
+    assert max(l1) <= 1e-5 and max(linf) <= 2e-3
+    for l in range(h.L - 1):
+        fo, fg = h.flags(l).astype(bool), s.flags(l).astype(bool)
+        dis = int((fo != fg).sum())
+        say(f"  level {l}: flagged {int(fo.sum())}, disagreements {dis}")
+        assert dis <= max(2, 0.02 * fo.sum())
