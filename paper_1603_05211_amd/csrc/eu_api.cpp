@@ -54,9 +54,11 @@ struct eu_ctx {
     int variant = 0;            // stage-kernel schedule (eu_autotune)
     int cfl_state = 0;          // CFL slots: CFL_ZERO, CFL_READY (of the current state) or CFL_STALE
     std::string err;
-    // graphs of one step, by qswap (the fused strip schedules alternate the
-    // state between the two arrays)
+    // graphs of one step and of GRAPH_RUN steps, by qswap (the fused strip
+    // schedules and the AMR scheme's global step alternate the state between
+    // the two arrays)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraphExec_t grun[2] = {nullptr, nullptr};
     int qswap = 0;              // the current state is in the second array
     // strip lists (2D, one level)
     Strip *strips = nullptr;
@@ -710,6 +712,8 @@ void drop_graphs(eu_ctx *c)
 {
     for (auto &g : c->gexec)
         if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    for (auto &g : c->grun)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
 // Whether schedule var applies to this context: the strip schedules need a
@@ -1301,6 +1305,9 @@ int eu_step(eu_ctx *c, int regrid)
     return check_launch(c);
 }
 
+// steps per graph of a run (even)
+constexpr int GRAPH_RUN = 8;
+
 int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
 {
     if (!c || nsteps < 0) return EU_EINVAL;
@@ -1321,31 +1328,55 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
         // CFL slots are left by a step as the lines above prepare them)
         const bool alt = (c->cfg.scheme == EU_SCHEME_AMR && !c->v.lts) ||
                          (strip_variant(c->variant) && c->dim == 2 && strip_fused(c->variant));
-        for (int p = 0; p < (alt ? 2 : 1); ++p) {
-            const int q = c->qswap ^ p;
-            if (c->gexec[q]) continue;
+        // capture n consecutive steps from the state in array q (steps
+        // after the end time are skipped by the kernels themselves)
+        auto capture = [&](int q, int n, hipGraphExec_t *out) -> int {
             const View saved = c->v;
             const int sq = c->qswap, scfl = c->cfl_state;
-            if (p) {
+            if (q != c->qswap) {
                 std::swap(c->v.Q, c->v.Qs);
                 c->qswap ^= 1;
             }
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            seq_step(c, true);
+            // (a step that moves the state to the other array says so in
+            // the host bookkeeping, so the next recorded step starts there)
+            for (int k = 0; k < n; ++k) seq_step(c, true);
             hipError_t e = hipStreamEndCapture(c->stream, &g);
             c->v = saved;
             c->qswap = sq;
             c->cfl_state = scfl;
             if (e != hipSuccess) return set_err(c, EU_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(&c->gexec[q], g, nullptr, nullptr, 0);
+            e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) {
-                c->gexec[q] = nullptr;
+                *out = nullptr;
                 return set_err(c, EU_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
             }
+            return EU_OK;
+        };
+        // one graph per array holding the state; recording steps changes
+        // only host bookkeeping, which is restored after each capture (the
+        // CFL slots are left by a step as the lines above prepare them).
+        // Runs of GRAPH_RUN steps replay one graph (an even count: a run
+        // ends in the array it started from), which saves the gap between
+        // graph launches; the rest replays the graphs of one step.
+        int i = 0;
+        if (nsteps >= GRAPH_RUN) {
+            const int q = c->qswap;
+            if (!c->grun[q]) {
+                int r = capture(q, GRAPH_RUN, &c->grun[q]);
+                if (r) return r;
+            }
+            for (; i + GRAPH_RUN <= nsteps; i += GRAPH_RUN) HIPCHK(c, hipGraphLaunch(c->grun[q], c->stream));
         }
-        for (int i = 0; i < nsteps; ++i) {
+        for (int p = 0; p < (alt ? 2 : 1) && i < nsteps; ++p) {
+            const int q = c->qswap ^ p;
+            if (c->gexec[q]) continue;
+            int r = capture(q, 1, &c->gexec[q]);
+            if (r) return r;
+        }
+        for (; i < nsteps; ++i) {
             HIPCHK(c, hipGraphLaunch(c->gexec[c->qswap], c->stream));
             if (alt) {
                 std::swap(c->v.Q, c->v.Qs);

@@ -18,7 +18,7 @@ import pytest
 import oracle as orc
 from paper_1603_05211_amd import EU_FP32, EU_FP64, EuError, Solver, inputs
 
-from gpu_helpers import G, compare_masks, init_pair, make_pair, run_pair, say, state_errors
+from gpu_helpers import G, compare_masks, dilate, init_pair, make_pair, run_pair, say, state_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -133,6 +133,34 @@ def test_graph_replay_equals_eager():
         b.step(True)
     for l in range(3):
         assert np.array_equal(a.level(l), b.level(l))
+
+
+@pytest.mark.parametrize("kw", [dict(levels=3), dict(levels=3, scheme=1), dict(levels=1, n0=64, scheme=1)])
+def test_graph_runs_equal_eager(kw):
+    """Runs of eight steps replay one graph; the rest replays the graphs of
+    one step.  Either way the state (patch cells and ghost cells) is that of
+    eager steps, bit for bit, also where every step moves the state to the
+    other array (the AMR scheme) and a run starts from the second array.
+    Cells outside the patches and their ghost layers hold no state (with
+    the AMR scheme they are whatever the other array held) and are not
+    compared."""
+    kw = dict(kw)
+    n0 = kw.pop("n0", 32)
+    a = Solver(2, n0=n0, precision=EU_FP64, **kw)
+    b = Solver(2, n0=n0, precision=EU_FP64, **kw)
+    prim = inputs.quadrant_states(4)
+    a.init_quadrant(prim)
+    b.init_quadrant(prim)
+    for n in (3, 19, 8):
+        assert a.advance(n, use_graph=True) == n
+        for _ in range(n):
+            b.step(True)
+        for l in range(kw["levels"]):
+            act = a.active(l).astype(bool)
+            assert np.array_equal(act, b.active(l).astype(bool))
+            m = act | (dilate(act, 2, False) if l > 0 else act)
+            assert np.array_equal(a.level(l)[:, m], b.level(l)[:, m]), (n, l)
+        assert a.time() == b.time()
 
 
 def test_dt_across_entry_points():
