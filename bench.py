@@ -232,18 +232,24 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload, precision, kernel, cells_per_launch):
+def traffic_from_profile(workload, precision, kernel, cells_per_launch, schedule=None):
     """HBM bytes per launch of the finite-volume kernel: the committed counter
-    summary of this workload and kernel (FETCH_SIZE and WRITE_SIZE per
-    launch, scaled by the readings of a plain 256 MiB device copy) gives
-    bytes per cell-stage, which is scaled to this run's cell-stages per
-    launch.  None when the summary is missing or the kernel sources changed
-    since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_traffic.json")
-    try:
-        with open(path) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
+    summary of this workload, kernel and stage schedule (FETCH_SIZE and
+    WRITE_SIZE per launch, scaled by the readings of a plain 256 MiB device
+    copy) gives bytes per cell-stage, which is scaled to this run's
+    cell-stages per launch.  None when the summary is missing or the kernel
+    sources changed since the counters were taken."""
+    d = path = None
+    for name in ([f"{kernel}_{workload}_{precision}_s{schedule}_traffic.json"] if schedule is not None else []) + \
+            [f"{kernel}_{workload}_{precision}_traffic.json"]:
+        path = os.path.join(ROOT, "profiles", name)
+        try:
+            with open(path) as f:
+                d = json.load(f)
+            break
+        except (OSError, ValueError):
+            d = None
+    if d is None:
         return None, "no counter summary"
     if d.get("source_hash") != source_hash():
         return None, "kernel changed since the counters were taken"
@@ -260,7 +266,7 @@ def roofline(r, precision, samples=64):
     ms, nl, cells, lpp, tflops = r.stage_samples(samples, STAGE_REPS)
     peak = PEAK_TFLOPS[precision]
     kern = r.kernel()
-    traffic, src = traffic_from_profile(r.workload, precision, kern, cells)
+    traffic, src = traffic_from_profile(r.workload, precision, kern, cells, r.variant)
     return {"bound": "alu", "kernel": kern, "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
             "frac": tflops / peak, "traffic": traffic, "traffic_source": src, "avg_launch_ms": ms,
             "launches": nl, "launches_per_pass": lpp, "cell_stages_per_launch": cells,
