@@ -64,6 +64,7 @@ enum { EU_CRIT_MR = 0, EU_CRIT_GRADIENT = 1 };     /* refinement criterion     *
 enum { EU_RK_MIDPOINT = 0, EU_RK_HEUN = 1 };       /* MR scheme time stepping  */
 enum { EU_AUSM_MEAN = 0, EU_AUSM_CRITICAL = 1 };   /* AUSM+ sound speed        */
 enum { EU_TILER_BLOCKS = 0, EU_TILER_BR = 1 };     /* patch generation        */
+enum { EU_CFL_SUM = 0, EU_CFL_MAX = 1 };           /* CFL signal speed        */
 enum { EU_STAGE_SCHEDULES = 10, EU_STRIP_SCHEDULE0 = 6 }; /* see eu_autotune  */
 
 /* Problem size and method parameters (Sec. 2; Sec. 4 for the values used
@@ -148,6 +149,15 @@ typedef struct {
                             else halve the longest axis; the lower part
                             first.  EU_TILER_BR needs (patch_max / 8)^d <= 64
                             (3D: patch_max <= 32)                           */
+    int cfl_mode;        /* CFL signal speed of a cell: EU_CFL_SUM (0) the sum
+                            over axes of |v_d| + c, the stable choice for the
+                            unsplit schemes; EU_CFL_MAX the largest |v_d| + c
+                            (for runs with paper-style step sizes)          */
+    int regrid_every;    /* eu_advance rebuilds the hierarchy after step n
+                            (counted from initialisation; level-0 steps with
+                            local time stepping) when n is a multiple of
+                            regrid_every; 0 or 1: after every step (the
+                            paper's AMR runs, Sec. 4)                       */
 } eu_config;
 
 /* Initial data (Sec. 4.1 four-quadrant Riemann problem, Sec. 4.2 ellipsoid,
@@ -230,7 +240,8 @@ int eu_mr_flag(eu_ctx *ctx, double eps, int64_t *nflag_host);
 int eu_project(eu_ctx *ctx, int mode);
 
 /* CFL time step (FP64; the paper's runs use CFL about 0.4, Sec. 4.2):
- * dt = min over levels cfl dx_l / max over leaves of sum_d (|v_d| + c) (with
+ * dt = min over levels cfl dx_l / max over leaves of the signal speed
+ * (cfl_mode: sum_d (|v_d| + c), or max_d (|v_d| + c)) (with
  * local time stepping the level-0 step min over levels of that times 2^l),
  * clipped to reach t_end and to t_remaining, per instance for a batch.
  * cfl > 0 replaces the configuration's CFL number for this call (else it is
@@ -265,8 +276,10 @@ int eu_fv_step(eu_ctx *ctx, const double *dt_dev, int level);
  * eu_mr_decompose + eu_mr_flag (configuration CFL number and threshold). */
 int eu_step(eu_ctx *ctx, int regrid);
 
-/* nsteps calls of eu_step(ctx, 1) (or until t_end), replayed from one
- * captured HIP graph when use_graph != 0.  steps_done_host (nullable)
+/* nsteps calls of eu_step(ctx, regrid) (or until t_end), regrid as
+ * regrid_every says, replayed from captured HIP graphs when use_graph != 0
+ * (runs of eight steps, or of regrid_every steps from a regrid to the next,
+ * in one graph; other steps one at a time).  steps_done_host (nullable)
  * receives the number of steps taken. */
 int eu_advance(eu_ctx *ctx, int nsteps, int use_graph, int *steps_done_host);
 

@@ -104,6 +104,7 @@ def lib():
             "orc_h_set_scheme": (C.c_int, [vp, C.c_int]),
             "orc_h_set_variants": (C.c_int, [vp, C.c_int, C.c_int]),
             "orc_h_set_tiler": (C.c_int, [vp, C.c_int]),
+            "orc_h_set_cfl_mode": (C.c_int, [vp, C.c_int]),
             "orc_br_cluster": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_double, i32p, i32p]),
             "orc_ausm_plus_speed": (None, [C.c_int, C.c_double, C.c_int, dp, dp, dp, C.c_int]),
             "orc_h_set_eps_levels": (None, [vp, C.c_int]),
@@ -158,6 +159,7 @@ SCHEME_MR, SCHEME_AMR = 0, 1
 RK_MIDPOINT, RK_HEUN = 0, 1
 AUSM_MEAN, AUSM_CRITICAL = 0, 1
 TILER_BLOCKS, TILER_BR = 0, 1
+CFL_SUM, CFL_MAX = 0, 1
 CRIT_MR, CRIT_GRADIENT = 0, 1
 
 
@@ -307,7 +309,8 @@ class Hierarchy:
                  gamma: float = 1.4, lo: float = 0.0, hi: float = 1.0, eps: float = 1e-3,
                  eta: float = 0.8, pmin: int = 8, pmax: int = 32, scheme: int = SCHEME_MR,
                  criterion: int = CRIT_MR, eps_p: float = 0.0, eps_levels: bool = False, rk: int = RK_MIDPOINT,
-                 ausm_speed: int = AUSM_MEAN, tiler: int = TILER_BLOCKS):
+                 ausm_speed: int = AUSM_MEAN, tiler: int = TILER_BLOCKS, cfl_mode: int = CFL_SUM,
+                 regrid_every: int = 1):
         self.dim, self.L, self.n0, self.bc = dim, levels, n0, bc
         self.gamma, self.lo, self.hi, self.eps, self.eta = gamma, lo, hi, eps, eta
         self.pmin, self.pmax = pmin, pmax
@@ -329,6 +332,16 @@ class Hierarchy:
         if lib().orc_h_set_tiler(self._h, tiler) != 0:
             raise ValueError("unknown tiler, or pmax / pmin above 8 for Berger-Rigoutsos")
         self.tiler = tiler
+        if lib().orc_h_set_cfl_mode(self._h, cfl_mode) != 0:
+            raise ValueError("unknown CFL signal speed")
+        self.cfl_mode = cfl_mode
+        if regrid_every < 1:
+            raise ValueError("regrid_every must be >= 1")
+        # the hierarchy is rebuilt after step n (counted from initialisation,
+        # level-0 steps with local time stepping) when n is a multiple of
+        # regrid_every
+        self.regrid_every = regrid_every
+        self.nsteps = 0
         self.t = 0.0
 
     def __del__(self):
@@ -395,6 +408,7 @@ class Hierarchy:
         self.level(self.L - 1)[...] = Q
         lib().orc_h_init(self._h)
         self.t = 0.0
+        self.nsteps = 0
 
     # ---- operations
     def cfl(self, cfl: float, t_end: float = np.inf):
@@ -402,20 +416,33 @@ class Hierarchy:
         dt = lib().orc_h_cfl(self._h, cfl, self.t, t_end, _dp(smax))
         return dt, smax
 
-    def step(self, cfl: float, t_end: float = np.inf, regrid: bool = True) -> float:
-        dt = lib().orc_h_step(self._h, cfl, self.t, t_end, int(regrid))
+    def _regrid_now(self, regrid):
+        """regrid True / False as given; None: by the step count and
+        regrid_every (this step is step nsteps + 1)."""
+        return (self.nsteps + 1) % self.regrid_every == 0 if regrid is None else bool(regrid)
+
+    def step(self, cfl: float, t_end: float = np.inf, regrid=True) -> float:
+        """One step (regrid=None: regrid as regrid_every says)."""
+        rg = self._regrid_now(regrid)
+        taken = self.t < t_end
+        dt = lib().orc_h_step(self._h, cfl, self.t, t_end, int(rg))
         self.t = self.t + dt
+        self.nsteps += 1 if taken else 0
         return dt
 
-    def step_lts(self, cfl: float, t_end: float = np.inf, regrid: bool = True):
-        """One level-0 step with local time steps; returns (dt_0, leaf updates)."""
+    def step_lts(self, cfl: float, t_end: float = np.inf, regrid=True):
+        """One level-0 step with local time steps; returns (dt_0, leaf updates)
+        (regrid=None: regrid as regrid_every says)."""
+        rg = self._regrid_now(regrid)
+        taken = self.t < t_end
         upd = C.c_int64(0)
-        dt = lib().orc_h_step_lts(self._h, cfl, self.t, t_end, int(regrid), C.byref(upd))
+        dt = lib().orc_h_step_lts(self._h, cfl, self.t, t_end, int(rg), C.byref(upd))
         if dt == -2.0:
             raise ValueError("local time steps use the midpoint rule")
         if dt < 0:
             raise MemoryError("oracle: local time stepping buffers")
         self.t = self.t + dt
+        self.nsteps += 1 if taken else 0
         return dt, upd.value
 
     def step_fixed(self, dt: float):

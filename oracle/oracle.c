@@ -546,6 +546,7 @@ typedef struct {
     int rk;              /* MR scheme time stepping: 0 the midpoint rule, 1 Heun */
     int ausm_speed;      /* MR scheme: AUSM+ interface sound speed (ausm_plus) */
     int tiler;           /* 0 block tiler (tile_block), 1 Berger-Rigoutsos (br_block) */
+    int cfl_max;         /* CFL signal speed: 0 sum_d (|v_d| + c), 1 max_d (|v_d| + c) */
 } orc_h;
 
 static int64_t hN(const orc_h *h, int l) { return ncells(h->dim, h->n[l]); }
@@ -800,8 +801,9 @@ static void h_fv_level(orc_h *h, int l, double **src, double **base,
     }
 }
 
-/* CFL time step over all leaves: dt = min over levels of
- * cfl dx_l / max_leaves sum_d (|v_d| + c), clipped to reach t_end. */
+/* CFL time step over all leaves: dt = min over levels of cfl dx_l / S_l,
+ * S_l the largest signal speed of the level's leaves, sum_d (|v_d| + c) (the
+ * default) or max_d (|v_d| + c) (cfl_max), clipped to reach t_end. */
 double orc_h_cfl(orc_h *h, double cfl, double t, double t_end, double *smax_out)
 {
     int dim = h->dim;
@@ -820,7 +822,10 @@ double orc_h_cfl(orc_h *h, double cfl, double t, double t_end, double *smax_out)
             cons2prim(dim, h->g, q, w);
             double c = sqrt((h->g * w[dim + 1]) / w[0]);
             double S = 0.0;
-            for (int d = 0; d < dim; ++d) S = S + (fabs(w[1 + d]) + c);
+            for (int d = 0; d < dim; ++d) {
+                double sd = fabs(w[1 + d]) + c;
+                S = h->cfl_max ? (sd > S ? sd : S) : S + sd;
+            }
             if (S > smax) smax = S;
             any = 1;
         }
@@ -1350,6 +1355,15 @@ void orc_h_patches(const orc_h *h, int32_t *out)
             out[7 * i + 4 + d] = h->patches[i].size[d];
         }
     }
+}
+
+/* CFL signal speed: 0 the sum over axes of |v_d| + c, 1 the largest of them.
+ * Returns 0, or -1. */
+int orc_h_set_cfl_mode(orc_h *h, int mode)
+{
+    if (mode != 0 && mode != 1) return -1;
+    h->cfl_max = mode;
+    return 0;
 }
 
 /* Tiler: 0 the efficiency-rule block tiler (tile_block), 1 Berger-Rigoutsos

@@ -18,13 +18,13 @@ from . import _abi
 from ._abi import (EU_BC_PERIODIC, EU_BC_TRANSMISSIVE, EU_DT_GLOBAL, EU_DT_LTS, EU_FP32, EU_FP64,
                    EU_CRIT_GRADIENT, EU_CRIT_MR, EU_GHOST, EU_SCHEME_AMR, EU_SCHEME_MR, EU_STAGE_SCHEDULES, EU_STRIP_SCHEDULE0, EU_IC_ELLIPSOID, EU_IC_QUADRANT, EU_IC_RIEMANN1D, EU_IC_UNIFORM,
                    EU_PROLONG, EU_RESTRICT, EU_RK_MIDPOINT, EU_RK_HEUN, EU_AUSM_MEAN, EU_AUSM_CRITICAL,
-                   EU_TILER_BLOCKS, EU_TILER_BR)
+                   EU_TILER_BLOCKS, EU_TILER_BR, EU_CFL_SUM, EU_CFL_MAX)
 
 __all__ = ["Solver", "EuError", "EU_FP32", "EU_FP64", "EU_BC_PERIODIC", "EU_BC_TRANSMISSIVE",
            "EU_RESTRICT", "EU_PROLONG", "EU_GHOST", "EU_DT_GLOBAL", "EU_DT_LTS", "EU_STAGE_SCHEDULES",
            "EU_STRIP_SCHEDULE0", "EU_SCHEME_MR", "EU_SCHEME_AMR", "EU_CRIT_MR", "EU_CRIT_GRADIENT",
            "EU_RK_MIDPOINT", "EU_RK_HEUN", "EU_AUSM_MEAN", "EU_AUSM_CRITICAL",
-           "EU_TILER_BLOCKS", "EU_TILER_BR"]
+           "EU_TILER_BLOCKS", "EU_TILER_BR", "EU_CFL_SUM", "EU_CFL_MAX"]
 
 
 class EuError(RuntimeError):
@@ -51,7 +51,7 @@ class Solver:
                  time_mode: int = EU_DT_GLOBAL, device: str = "cuda:0", stream=None,
                  scheme: int = EU_SCHEME_MR, criterion: int = EU_CRIT_MR, eps_p: float = 0.0,
                  eps_levels: int = 0, rk: int = EU_RK_MIDPOINT, ausm_speed: int = EU_AUSM_MEAN,
-                 tiler: int = EU_TILER_BLOCKS):
+                 tiler: int = EU_TILER_BLOCKS, cfl_mode: int = EU_CFL_SUM, regrid_every: int = 1):
         import torch
         self._lib = _abi.load()
         self.torch = torch
@@ -72,6 +72,7 @@ class Solver:
         self.criterion, self.eps_p = criterion, eps_p
         cfg.eps_levels = eps_levels
         cfg.rk, cfg.ausm_speed, cfg.tiler = rk, ausm_speed, tiler
+        cfg.cfl_mode, cfg.regrid_every = cfl_mode, regrid_every
         if sides is not None:
             self._sides = (C.c_int32 * len(sides))(*[int(s) for s in sides])
             cfg.n_instances = len(sides)

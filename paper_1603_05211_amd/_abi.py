@@ -19,6 +19,7 @@ EU_CRIT_MR, EU_CRIT_GRADIENT = 0, 1
 EU_RK_MIDPOINT, EU_RK_HEUN = 0, 1
 EU_AUSM_MEAN, EU_AUSM_CRITICAL = 0, 1
 EU_TILER_BLOCKS, EU_TILER_BR = 0, 1
+EU_CFL_SUM, EU_CFL_MAX = 0, 1
 EU_STAGE_SCHEDULES = 10
 EU_STRIP_SCHEDULE0 = 6
 
@@ -37,6 +38,8 @@ class EuConfig(C.Structure):
         ("criterion", C.c_int), ("eps_p", C.c_double), ("eps_levels", C.c_int), ("rk", C.c_int),
         ("ausm_speed", C.c_int),
         ("tiler", C.c_int),
+        ("cfl_mode", C.c_int),
+        ("regrid_every", C.c_int),
     ]
 
 

@@ -59,6 +59,7 @@ struct eu_ctx {
     // the two arrays)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraphExec_t grun[2] = {nullptr, nullptr};
+    hipGraphExec_t gcycle[2] = {nullptr, nullptr};   // regrid_every steps, the last regrids
     int qswap = 0;              // the current state is in the second array
     // strip lists (2D, one level)
     Strip *strips = nullptr;
@@ -155,6 +156,8 @@ int validate(const eu_config *c, std::string &why)
         why = "level-dependent thresholds apply to the MR criterion";
         return EU_EINVAL;
     }
+    if (c->cfl_mode != EU_CFL_SUM && c->cfl_mode != EU_CFL_MAX) { why = "bad cfl_mode"; return EU_EINVAL; }
+    if (c->regrid_every < 0) { why = "regrid_every must be >= 0"; return EU_EINVAL; }
 
     if (c->time_mode == EU_DT_LTS && c->n_instances > 1) { why = "a batch has no levels to step locally"; return EU_EINVAL; }
     if (c->n_instances > 1) {
@@ -714,6 +717,8 @@ void drop_graphs(eu_ctx *c)
         if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
     for (auto &g : c->grun)
         if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    for (auto &g : c->gcycle)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
 // Whether schedule var applies to this context: the strip schedules need a
@@ -1040,6 +1045,7 @@ int eu_create(const eu_config *cfg, void *state_dev, size_t state_bytes, void *s
     v.rk = cfg->rk;
     v.ausm_cs = cfg->ausm_speed;
     v.tiler = cfg->tiler;
+    v.cfl_max = cfg->cfl_mode;
     v.crit = cfg->criterion;
     v.eps_p = cfg->eps_p;
     v.eta = cfg->eta;
@@ -1315,6 +1321,10 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
     int s0 = 0;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(&s0, &c->v.meta->steps, sizeof(int), hipMemcpyDeviceToHost));
+    // regrid after step n (counted from initialisation) when n is a
+    // multiple of regrid_every (every step with 0 or 1)
+    const int every = c->cfg.regrid_every > 1 && c->L > 1 ? c->cfg.regrid_every : 1;
+    auto regrid_after = [&](int i) { return (s0 + i + 1) % every == 0; };
     if (use_graph && !c->prof) {
         if (!c->stream) return set_err(c, EU_EINVAL, "graph capture needs a non-default stream");
         // a step that leaves the CFL slots of the next starts from them:
@@ -1329,8 +1339,9 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
         const bool alt = (c->cfg.scheme == EU_SCHEME_AMR && !c->v.lts) ||
                          (strip_variant(c->variant) && c->dim == 2 && strip_fused(c->variant));
         // capture n consecutive steps from the state in array q (steps
-        // after the end time are skipped by the kernels themselves)
-        auto capture = [&](int q, int n, hipGraphExec_t *out) -> int {
+        // after the end time are skipped by the kernels themselves); a
+        // cycle regrids after its last step only
+        auto capture = [&](int q, int n, bool cycle, hipGraphExec_t *out) -> int {
             const View saved = c->v;
             const int sq = c->qswap, scfl = c->cfl_state;
             if (q != c->qswap) {
@@ -1341,7 +1352,7 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             // (a step that moves the state to the other array says so in
             // the host bookkeeping, so the next recorded step starts there)
-            for (int k = 0; k < n; ++k) seq_step(c, true);
+            for (int k = 0; k < n; ++k) seq_step(c, !cycle || k == n - 1);
             hipError_t e = hipStreamEndCapture(c->stream, &g);
             c->v = saved;
             c->qswap = sq;
@@ -1355,17 +1366,48 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
             }
             return EU_OK;
         };
+        // a replayed graph of n steps leaves the state in the other array
+        // after an odd number of alternating steps
+        auto moved = [&](int n) {
+            if (alt && (n & 1)) {
+                std::swap(c->v.Q, c->v.Qs);
+                c->qswap ^= 1;
+            }
+        };
+        int i = 0;
+        if (every > 1) {
+            // steps up to the next regrid eagerly, then whole cycles from a
+            // regrid to the next from one graph each, then the rest eagerly
+            for (; i < nsteps && (s0 + i) % every != 0; ++i) {
+                seq_step(c, regrid_after(i));
+                int r = check_launch(c);
+                if (r) return r;
+            }
+            for (; i + every <= nsteps; i += every) {
+                const int q = c->qswap;
+                if (!c->gcycle[q]) {
+                    int r = capture(q, every, true, &c->gcycle[q]);
+                    if (r) return r;
+                }
+                HIPCHK(c, hipGraphLaunch(c->gcycle[q], c->stream));
+                moved(every);
+            }
+            for (; i < nsteps; ++i) {
+                seq_step(c, regrid_after(i));
+                int r = check_launch(c);
+                if (r) return r;
+            }
+        }
         // one graph per array holding the state; recording steps changes
         // only host bookkeeping, which is restored after each capture (the
         // CFL slots are left by a step as the lines above prepare them).
         // Runs of GRAPH_RUN steps replay one graph (an even count: a run
         // ends in the array it started from), which saves the gap between
         // graph launches; the rest replays the graphs of one step.
-        int i = 0;
-        if (nsteps >= GRAPH_RUN) {
+        if (nsteps - i >= GRAPH_RUN) {
             const int q = c->qswap;
             if (!c->grun[q]) {
-                int r = capture(q, GRAPH_RUN, &c->grun[q]);
+                int r = capture(q, GRAPH_RUN, false, &c->grun[q]);
                 if (r) return r;
             }
             for (; i + GRAPH_RUN <= nsteps; i += GRAPH_RUN) HIPCHK(c, hipGraphLaunch(c->grun[q], c->stream));
@@ -1373,19 +1415,16 @@ int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
         for (int p = 0; p < (alt ? 2 : 1) && i < nsteps; ++p) {
             const int q = c->qswap ^ p;
             if (c->gexec[q]) continue;
-            int r = capture(q, 1, &c->gexec[q]);
+            int r = capture(q, 1, false, &c->gexec[q]);
             if (r) return r;
         }
         for (; i < nsteps; ++i) {
             HIPCHK(c, hipGraphLaunch(c->gexec[c->qswap], c->stream));
-            if (alt) {
-                std::swap(c->v.Q, c->v.Qs);
-                c->qswap ^= 1;
-            }
+            moved(1);
         }
     } else {
         for (int i = 0; i < nsteps; ++i) {
-            seq_step(c, true);
+            seq_step(c, regrid_after(i));
             int r = check_launch(c);
             if (r) return r;
         }

@@ -88,6 +88,7 @@ struct View {
     int rk;                           // MR scheme: 0 midpoint rule, 1 Heun
     int ausm_cs;                      // AUSM+ interface sound speed: 0 mean, 1 critical
     int tiler;                        // 0 block split, 1 Berger-Rigoutsos clustering
+    int cfl_max;                      // CFL signal speed: 0 sum_d (|v_d| + c), 1 max_d (|v_d| + c)
     const Grid *grids;                // device copy of the grid table
     Grid gt[MAXLEV];                  // the first MAXLEV grids (every level of a hierarchy), by
                                       // value: kernels read them with their arguments

@@ -777,7 +777,7 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
 }
 
 // ----------------------------------------------------------------------------
-// CFL reduction over leaves (FP64): per-grid max of sum_d (|v_d| + c), then
+// CFL reduction over leaves (FP64): per-grid max of the signal speed, then
 // dt (second kernel)
 // ----------------------------------------------------------------------------
 // Hierarchy: workgroup b writes its per-level maxima and its count of leaf
@@ -785,10 +785,11 @@ k_fv_stage(View v, const T *__restrict__ src, const T *base, T *out, double fac,
 // kernel boundary publishes them).  Batch: one atomic max per tile on its
 // instance.
 
-// Signal speed sum_d (|v_d| + c) of a cell from its conserved state (FP64);
-// bad when its density or pressure is not positive.
+// Signal speed of a cell from its conserved state (FP64): sum_d (|v_d| + c),
+// or with mx the largest |v_d| + c; bad when its density or pressure is not
+// positive.
 template <int D>
-__device__ __forceinline__ double cell_speed(const double *q, double g, bool &bad)
+__device__ __forceinline__ double cell_speed(const double *q, double g, int mx, bool &bad)
 {
 #pragma clang fp contract(off)
     double w[D + 2];
@@ -797,7 +798,10 @@ __device__ __forceinline__ double cell_speed(const double *q, double g, bool &ba
     const double cs = __builtin_sqrt((g * w[D + 1]) / w[0]);
     double S = 0.0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) S = S + (__builtin_fabs(w[1 + d]) + cs);
+    for (int d = 0; d < D; ++d) {
+        const double sd = __builtin_fabs(w[1 + d]) + cs;
+        S = mx ? (sd > S ? sd : S) : S + sd;
+    }
     return S;
 }
 
@@ -877,7 +881,7 @@ __global__ void __launch_bounds__(256) k_cfl(View v, const T *__restrict__ Q)
             for (int f = 0; f < D + 2; ++f) q[f] = (double)Q[f * G.ncell + id];
             const bool leaf = !(hasf && covered(v.act, GF, x, y, z));
             bool b;
-            const double S = cell_speed<D>(q, g, b);
+            const double S = cell_speed<D>(q, g, v.cfl_max, b);
             if (leaf && b) bad = true;
             if (leaf && S > m) m = S;
             nl += leaf ? 1 : 0;
@@ -1420,7 +1424,7 @@ __device__ __forceinline__ void leaf_speeds(const View &v, const T *A, const Gri
 #pragma unroll
         for (int i = 0; i < CPT; ++i) {
             bool b;
-            const double S = cell_speed<D>(q[k][i], g, b);
+            const double S = cell_speed<D>(q[k][i], g, v.cfl_max, b);
             if (leaf[k][i] && b) bad = true;
             if (leaf[k][i] && S > m) m = S;
             nl += leaf[k][i] ? 1 : 0;
@@ -1568,7 +1572,7 @@ __global__ void __launch_bounds__(256) k_predict(View v, T *A, int lvl, int mode
             }
             if (speeds) {
                 bool b;
-                const double S = cell_speed<D>(q, g, b);
+                const double S = cell_speed<D>(q, g, v.cfl_max, b);
                 if (leaf && b) bad = true;
                 if (leaf && S > m) m = S;
                 nl += leaf ? 1 : 0;

@@ -21,8 +21,8 @@
 //
 // CFL partials of the new state: with cfl set, the launch that writes the
 // step's new state also takes, in FP64 from the values it writes, the
-// largest signal speed sum_d (|v_d| + c) of its cells (as the CFL reduction
-// kernel would on that state) and adds it into the grid's maximum (a batch)
+// largest signal speed of its cells (the CFL reduction's: the sum or the
+// largest over axes of |v_d| + c) and adds it into the grid's maximum (a batch)
 // or a CFL slot with the count of cells advanced (a uniform grid), and
 // raises the non-physical status flag; cfl = 2 computes them without
 // publishing (timing passes).
@@ -145,13 +145,13 @@ __device__ __forceinline__ void strip_load(const T *S, int64_t N, int n, int xc,
 // Signal speed of a written cell into the lane's running maximum (FP64
 // from the stored values, the CFL reduction's expression).
 template <typename T, int D = 2>
-__device__ __forceinline__ void strip_speed(const T *q, double g, double &m, bool &bad)
+__device__ __forceinline__ void strip_speed(const T *q, double g, int mx, double &m, bool &bad)
 {
     double qd[D + 2];
 #pragma unroll
     for (int f = 0; f < D + 2; ++f) qd[f] = (double)q[f];
     bool b;
-    const double S = cell_speed<D>(qd, g, b);
+    const double S = cell_speed<D>(qd, g, mx, b);
     bad = bad || b;
     m = S > m ? S : m;
 }
@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(256) k_fv_strip(View v, const Strip *__restric
                             qn[f] = qo[f] - lam * R[f];
                             O[f * N + (uint32_t)x + (uint32_t)n * (uint32_t)ro] = qn[f];
                         }
-                        if (cfl) strip_speed<T>(qn, v.gamma, smax, bad);
+                        if (cfl) strip_speed<T>(qn, v.gamma, v.cfl_max, smax, bad);
                     }
                 }
 #pragma unroll
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(256) k_fv_strip(View v, const Strip *__restric
                                 qn[f] = qo[f] - lam2 * R2[f];
                                 O[f * N + (uint32_t)x + (uint32_t)n * (uint32_t)ro2] = qn[f];
                             }
-                            if (cfl) strip_speed<T>(qn, v.gamma, smax, bad);
+                            if (cfl) strip_speed<T>(qn, v.gamma, v.cfl_max, smax, bad);
                         }
                     }
                 }
@@ -563,7 +563,7 @@ __global__ void __launch_bounds__(256) k_hancock_strip(View v, const Strip *__re
                     qn[f] = qa[f] - lam * R[f];
                     O[f * N + (uint32_t)x + (uint32_t)n * (uint32_t)ro] = qn[f];
                 }
-                if (cfl) strip_speed<T>(qn, v.gamma, smax, bad);
+                if (cfl) strip_speed<T>(qn, v.gamma, v.cfl_max, smax, bad);
             }
 #pragma unroll
             for (int f = 0; f < 4; ++f) {

@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))
                             qn[f] = qo[f] - lam * R;
                             O[f * N + ido] = qn[f];
                         }
-                        if (cfl) strip_speed<T, 3>(qn, v.gamma, smax, bad);
+                        if (cfl) strip_speed<T, 3>(qn, v.gamma, v.cfl_max, smax, bad);
                     }
                 }
             }

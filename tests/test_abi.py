@@ -163,3 +163,16 @@ def test_tiler_checks():
     assert sizes(cfg(tiler=_abi.EU_TILER_BR, dim=3, n0=32, levels=3, lo=-1.0, patch_max=64))[0] == _abi.EU_EINVAL
     assert sizes(cfg(tiler=2))[0] == _abi.EU_EINVAL
     assert sizes(cfg(tiler=-1))[0] == _abi.EU_EINVAL
+
+
+def test_cfl_mode_and_regrid_interval_checks():
+    assert sizes(cfg(cfl_mode=_abi.EU_CFL_MAX))[0] == _abi.EU_OK
+    assert sizes(cfg(cfl_mode=2))[0] == _abi.EU_EINVAL
+    assert sizes(cfg(cfl_mode=-1))[0] == _abi.EU_EINVAL
+    for every in (0, 1, 5):
+        assert sizes(cfg(regrid_every=every))[0] == _abi.EU_OK
+    assert sizes(cfg(regrid_every=-1))[0] == _abi.EU_EINVAL
+    sides = (C.c_int32 * 2)(32, 64)
+    batch = cfg(levels=1, n_instances=2, inst_side_host=C.cast(sides, C.POINTER(C.c_int32)))
+    batch.cfl_mode = 3
+    assert sizes(batch)[0] == _abi.EU_EINVAL
