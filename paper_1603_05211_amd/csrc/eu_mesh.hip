@@ -565,9 +565,6 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
         out[7 * pos + 6] = D == 3 ? S : 1;
     };
     if constexpr (NSUB <= 64) {
-        // one wave walks: lane = Morton code, so the sub-blocks of a node of
-        // level k are an aligned group of 2^(D k) lanes and its count is a
-        // sum over the group
         __syncthreads();
         // clustering: the weight planes (every wave takes the same ballots);
         // where the boxes fit one pass of the workgroup (thread = box) it
@@ -657,6 +654,9 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
                 __syncthreads();
             }
         }
+        // the block tiler: one wave walks, lane = Morton code, so the
+        // sub-blocks of a node of level k are an aligned group of 2^(D k)
+        // lanes and its count is a sum over the group
         if (wave == 0) {
             const int mc = lane;
             int sx, sy, sz;
