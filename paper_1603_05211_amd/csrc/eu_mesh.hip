@@ -246,65 +246,6 @@ struct BrBoxes {
     }
 };
 
-// The clustering's depth-first walk, in wave-uniform scalar code on one
-// wave, each box decided as it is met (grids whose boxes do not fit one
-// pass of the workgroup).  Parts waiting for their turn sit on a stack with
-// one entry per lane (they are disjoint and nonempty: at most R^D of them).
-// Writes the patch rows (7 ints: level, origin, extents) to out in the order
-// found and returns their number; inbox: whether the lane's block (sx, sy,
-// sz; valid) lies in a patch.
-template <int D, int R>
-__device__ __forceinline__ int br_walk(const unsigned long long *W, unsigned long long M, double eta, int lane, int sx,
-                                       int sy, int sz, bool valid, int lvl, const int *bp, int *out, bool &inbox)
-{
-    int lo0 = 0, lo1 = 0, lo2 = 0, hi0 = R - 1, hi1 = R - 1, hi2 = D == 3 ? R - 1 : 0;
-    inbox = false;
-    int np = 0, sp = 0, stk = 0;
-    for (;;) {
-        const int d = br_decide<D, R>(lo0, lo1, lo2, hi0, hi1, hi2, W, M, eta);
-        if (!(d & BR_EMPTY)) {
-            lo0 = d & 7;
-            lo1 = (d >> 3) & 7;
-            lo2 = (d >> 6) & 7;
-            hi0 = (d >> 9) & 7;
-            hi1 = (d >> 12) & 7;
-            hi2 = (d >> 15) & 7;
-            if (d & BR_EMIT) {
-                inbox = inbox || (valid && sx >= lo0 && sx <= hi0 && sy >= lo1 && sy <= hi1 && sz >= lo2 && sz <= hi2);
-                int val = lvl;
-                val = lane == 1 ? (bp[0] * R + lo0) * BS : val;
-                val = lane == 2 ? (bp[1] * R + lo1) * BS : val;
-                val = lane == 3 ? (D == 3 ? (bp[2] * R + lo2) * BS : 0) : val;
-                val = lane == 4 ? (hi0 - lo0 + 1) * BS : val;
-                val = lane == 5 ? (hi1 - lo1 + 1) * BS : val;
-                val = lane == 6 ? (D == 3 ? (hi2 - lo2 + 1) * BS : 1) : val;
-                if (lane < 7) out[7 * np + lane] = val;
-                ++np;
-            } else {
-                // push the upper part (packed as the decision's box), go on with the lower
-                const int cut_axis = (d >> BR_AX) & 3, cut_at = (d >> BR_AT) & 7;
-                const int pk = (d & 0x3ffff & ~(7 << (3 * cut_axis))) | (cut_at + 1) << (3 * cut_axis);
-                if (lane == sp) stk = pk;
-                ++sp;
-                if (cut_axis == 0) hi0 = cut_at;
-                if (cut_axis == 1) hi1 = cut_at;
-                if (cut_axis == 2) hi2 = cut_at;
-                continue;
-            }
-        }
-        if (sp == 0) break;
-        --sp;
-        const int pk = __builtin_amdgcn_readlane(stk, sp);
-        lo0 = pk & 7;
-        lo1 = (pk >> 3) & 7;
-        lo2 = (pk >> 6) & 7;
-        hi0 = (pk >> 9) & 7;
-        hi1 = (pk >> 12) & 7;
-        hi2 = (pk >> 15) & 7;
-    }
-    return np;
-}
-
 // R = pmax / BS (1, 2, 4 or 8): every size below is a compile-time constant,
 // so the loops unroll and no index needs a runtime division.
 template <int D, int R, bool CHAIN>
@@ -566,78 +507,96 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
     };
     if constexpr (NSUB <= 64) {
         __syncthreads();
-        // clustering: the weight planes (every wave takes the same ballots);
-        // where the boxes fit one pass of the workgroup (thread = box) it
-        // runs in parallel: every box's outcome, then the patch count of the
-        // clustering below every box (bottom-up, one pass per level of the
-        // tree: a box's height is at most D (R - 1)), then the position of
-        // every box the depth-first walk meets (top-down from the whole
-        // block: a cut box's lower part at its own position, its upper part
-        // after the lower part's patches); the boxes met that are patches
-        // write their rows.  Elsewhere wave 0 walks the boxes one by one.
+        // clustering, in parallel (thread = box; a thread takes KB boxes
+        // where the R^D grid has more boxes than the workgroup threads):
+        // the weight planes (every wave takes the same ballots), every box's
+        // outcome, then the patch count of the clustering below every box
+        // (bottom-up, one pass per level of the tree: a box's height is at
+        // most D (R - 1)), then the position of every box the depth-first
+        // walk meets (top-down from the whole block: a cut box's lower part
+        // at its own position, its upper part after the lower part's
+        // patches); the boxes met that are patches write their rows
         using BB = BrBoxes<D, R>;
-        constexpr bool BR_PRE = BB::N <= NT;
+        constexpr int KB = (BB::N + NT - 1) / NT;
         constexpr int BR_PASSES = D * (R - 1);
         constexpr int BR_ROOT = (R - 1) + BB::NI * ((R - 1) + BB::NI * (D == 3 ? R - 1 : 0));
-        __shared__ int scnt[2][BR_PRE ? BB::N : 1], spos[BR_PRE ? BB::N : 1];
+        __shared__ int scnt[2][BB::N], spos[BB::N];
         __shared__ unsigned long long smember;
         __shared__ int snp;
-        unsigned long long Wp[D == 2 ? 5 : 7], Mp = 0;
         if (v.tiler == 1) {
+            unsigned long long Wp[D == 2 ? 5 : 7], Mp;
             const int wlin = lane < NSUB ? cnt8[lane] : 0;
 #pragma unroll
             for (int bit = 0; bit < (D == 2 ? 5 : 7); ++bit) Wp[bit] = __ballot((wlin >> bit) & 1);
             Mp = __ballot(wlin > 0);
-            if constexpr (BR_PRE) {
-                const int b = threadIdx.x;
-                const bool own = b < BB::N;
-                int d = BR_EMPTY, cl = 0, cu = 0;
-                if (own) {
+            int d[KB], cl[KB], cu[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int b = threadIdx.x + k * NT;
+                d[k] = BR_EMPTY;
+                cl[k] = cu[k] = 0;
+                if (b < BB::N) {
                     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
                     BB::bounds(b % BB::NI, lo[0], hi[0]);
                     BB::bounds((b / BB::NI) % BB::NI, lo[1], hi[1]);
                     if (D == 3) BB::bounds(b / (BB::NI * BB::NI), lo[2], hi[2]);
-                    d = br_decide<D, R>(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], Wp, Mp, v.eta);
-                    if (!(d & (BR_EMPTY | BR_EMIT))) {
+                    d[k] = br_decide<D, R>(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], Wp, Mp, v.eta);
+                    if (!(d[k] & (BR_EMPTY | BR_EMIT))) {
                         // the two parts of the cut
-                        const int a = (d >> BR_AX) & 3, at = (d >> BR_AT) & 7;
-                        int slo[3] = {d & 7, (d >> 3) & 7, (d >> 6) & 7};
-                        int shi[3] = {(d >> 9) & 7, (d >> 12) & 7, (d >> 15) & 7};
+                        const int a = (d[k] >> BR_AX) & 3, at = (d[k] >> BR_AT) & 7;
+                        const int slo[3] = {d[k] & 7, (d[k] >> 3) & 7, (d[k] >> 6) & 7};
+                        const int shi[3] = {(d[k] >> 9) & 7, (d[k] >> 12) & 7, (d[k] >> 15) & 7};
                         int il[3], iu[3];
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            il[k] = BB::interval(slo[k], k == a ? at : shi[k]);
-                            iu[k] = BB::interval(k == a ? at + 1 : slo[k], shi[k]);
+                        for (int j = 0; j < 3; ++j) {
+                            il[j] = BB::interval(slo[j], j == a ? at : shi[j]);
+                            iu[j] = BB::interval(j == a ? at + 1 : slo[j], shi[j]);
                         }
-                        cl = il[0] + BB::NI * (il[1] + BB::NI * (D == 3 ? il[2] : 0));
-                        cu = iu[0] + BB::NI * (iu[1] + BB::NI * (D == 3 ? iu[2] : 0));
+                        cl[k] = il[0] + BB::NI * (il[1] + BB::NI * (D == 3 ? il[2] : 0));
+                        cu[k] = iu[0] + BB::NI * (iu[1] + BB::NI * (D == 3 ? iu[2] : 0));
                     }
-                    scnt[0][b] = (d & BR_EMIT) ? 1 : 0;
+                    scnt[0][b] = (d[k] & BR_EMIT) ? 1 : 0;
                     spos[b] = b == BR_ROOT ? 0 : -1;
                 }
-                if (threadIdx.x == 0) smember = 0ull;
-                const bool cut = own && !(d & (BR_EMPTY | BR_EMIT));
+            }
+            auto is_cut = [&](int k) { return !(d[k] & (BR_EMPTY | BR_EMIT)); };
+            if (threadIdx.x == 0) smember = 0ull;
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < BR_PASSES; ++p) {
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    const int b = threadIdx.x + k * NT;
+                    if (b < BB::N)
+                        scnt[(p + 1) & 1][b] = is_cut(k) ? scnt[p & 1][cl[k]] + scnt[p & 1][cu[k]] : scnt[p & 1][b];
+                }
+                __syncthreads();
+            }
+            const int *cnt = scnt[BR_PASSES & 1];
+#pragma unroll
+            for (int p = 0; p < BR_PASSES; ++p) {
+                int at[KB];
+#pragma unroll
+                for (int k = 0; k < KB; ++k) {
+                    const int b = threadIdx.x + k * NT;
+                    at[k] = b < BB::N ? spos[b] : -1;
+                }
                 __syncthreads();
 #pragma unroll
-                for (int p = 0; p < BR_PASSES; ++p) {
-                    if (own) scnt[(p + 1) & 1][b] = cut ? scnt[p & 1][cl] + scnt[p & 1][cu] : scnt[p & 1][b];
-                    __syncthreads();
-                }
-                const int *cnt = scnt[BR_PASSES & 1];
-#pragma unroll
-                for (int p = 0; p < BR_PASSES; ++p) {
-                    const int at = own ? spos[b] : -1;
-                    __syncthreads();
-                    if (cut && at >= 0) {
-                        spos[cl] = at;
-                        spos[cu] = at + cnt[cl];
+                for (int k = 0; k < KB; ++k)
+                    if (is_cut(k) && at[k] >= 0) {
+                        spos[cl[k]] = at[k];
+                        spos[cu[k]] = at[k] + cnt[cl[k]];
                     }
-                    __syncthreads();
-                }
-                if (own && (d & BR_EMIT) && spos[b] >= 0) {
-                    const int pos = spos[b];
-                    const int lo0 = d & 7, lo1 = (d >> 3) & 7, lo2 = (d >> 6) & 7;
-                    const int hi0 = (d >> 9) & 7, hi1 = (d >> 12) & 7, hi2 = (d >> 15) & 7;
+                __syncthreads();
+            }
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int b = threadIdx.x + k * NT;
+                if (b < BB::N && (d[k] & BR_EMIT) && spos[b] >= 0) {
+                    const int pos = spos[b], dk = d[k];
+                    const int lo0 = dk & 7, lo1 = (dk >> 3) & 7, lo2 = (dk >> 6) & 7;
+                    const int hi0 = (dk >> 9) & 7, hi1 = (dk >> 12) & 7, hi2 = (dk >> 15) & 7;
                     out[7 * pos + 0] = lvl + 1;
                     out[7 * pos + 1] = (bp[0] * R + lo0) * BS;
                     out[7 * pos + 2] = (bp[1] * R + lo1) * BS;
@@ -650,9 +609,9 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
                     if (D == 3) bm &= br_field(lo2, hi2, R * R);
                     atomicOr(&smember, bm);
                 }
-                if (threadIdx.x == 0) snp = cnt[BR_ROOT];
-                __syncthreads();
             }
+            if (threadIdx.x == 0) snp = cnt[BR_ROOT];
+            __syncthreads();
         }
         // the block tiler: one wave walks, lane = Morton code, so the
         // sub-blocks of a node of level k are an aligned group of 2^(D k)
@@ -664,12 +623,8 @@ __global__ void __launch_bounds__(256) k_flag_tile(View v, int lvl_arg, FlagArgs
             bool inp;
             int npatch;
             if (v.tiler == 1) {
-                if constexpr (BR_PRE) {
-                    npatch = snp;
-                    inp = mc < NSUB && ((smember >> (sx + R * (sy + R * sz))) & 1ull);
-                } else {
-                    npatch = br_walk<D, R>(Wp, Mp, v.eta, lane, sx, sy, sz, mc < NSUB, lvl + 1, bp, out, inp);
-                }
+                npatch = snp;
+                inp = mc < NSUB && ((smember >> (sx + R * (sy + R * sz))) & 1ull);
             } else {
                 int cn[K + 1];
                 cn[0] = mc < NSUB ? cnt8[sx + R * (sy + R * sz)] : 0;
