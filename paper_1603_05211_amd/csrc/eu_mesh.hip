@@ -199,14 +199,18 @@ __device__ __forceinline__ int br_decide(int lo0, int lo1, int lo2, int hi0, int
         }
     }
     if (cut_axis < 0) {
-        // the strongest inflection of the signatures
+        // the strongest inflection of the signatures (each slice's weight
+        // taken once; the slices indexed by unrolled constants)
         int bs = 0, bdist = 0;
         for (int k = 0; k < D; ++k) {
             const int a = axis(k), la = lo_of(a), ha = hi_of(a);
-            for (int i = la + 1; i + 1 <= ha - 1; ++i) {
-                const int s0 = weight(m & slice(a, i - 1)), s1 = weight(m & slice(a, i));
-                const int s2 = weight(m & slice(a, i + 1)), s3 = weight(m & slice(a, i + 2));
-                const int d0 = s0 - 2 * s1 + s2, d1 = s1 - 2 * s2 + s3;
+            int sg[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) sg[i] = i >= la && i <= ha ? weight(m & slice(a, i)) : 0;
+#pragma unroll
+            for (int i = 1; i + 2 < R; ++i) {
+                if (i < la + 1 || i + 1 > ha - 1) continue;
+                const int d0 = sg[i - 1] - 2 * sg[i] + sg[i + 1], d1 = sg[i] - 2 * sg[i + 1] + sg[i + 2];
                 if (!((d0 < 0 && d1 > 0) || (d0 > 0 && d1 < 0))) continue;
                 const int st = abs(d0 - d1), dist = abs(2 * i + 1 - (la + ha));
                 if (cut_axis < 0 || st > bs || (st == bs && a == cut_axis && dist < bdist)) {
