@@ -120,3 +120,35 @@ def test_amr_method_headline_hierarchy_fp32():
         dis = int((fo != fg).sum())
         say(f"  level {l}: flagged {int(fo.sum())}, disagreements {dis}")
         assert dis <= max(2, 0.02 * fo.sum())
+
+
+def test_amr_method_3d_fp32():
+    """The AMR method in 3D (scaled gradients of density and pressure, eps
+    0.05 each, clustering with 4^3 blocks per pmax block) in FP32 for 12
+    steps against the FP64 oracle: every field's L1 (relative to the
+    density's) within 1e-5, normwise L-inf within 2e-3 on the composite, flag
+    disagreements at most 2 % per level."""
+    import numpy as np
+
+    say("clustering: AMR method fp32, 3D")
+    e = inputs.ellipsoid(6)
+    h = orc.Hierarchy(3, 3, 16, lo=-1.0, eps=0.05, eta=0.8, pmax=32, scheme=orc.SCHEME_AMR,
+                      criterion=orc.CRIT_GRADIENT, eps_p=0.05, tiler=orc.TILER_BR)
+    s = Solver(3, n0=16, levels=3, precision=EU_FP32, cfl=0.4, eps=0.05, eta=0.8, lo=-1.0, patch_max=32,
+               scheme=orc.SCHEME_AMR, criterion=orc.CRIT_GRADIENT, eps_p=0.05, tiler=EU_TILER_BR)
+    h.init_finest(orc.init_ellipsoid(64, G, e.a, e.b, e.c, e.theta, e.phi, e.states, -1.0, 1.0, e.rc))
+    s.init_ellipsoid(e.a, e.b, e.c, e.theta, e.phi, e.states, e.rc)
+    for _ in range(12):
+        h.step(0.4)
+    assert s.advance(12, use_graph=True) == 12
+    g, o = s.composite(), h.composite()
+    scale = np.abs(o[0]).sum()
+    l1 = [float(np.abs(g[f] - o[f]).sum() / scale) for f in range(5)]
+    linf = [float(np.abs(g[f] - o[f]).max() / np.abs(o[f]).max()) for f in range(5)]
+    say("  L1 rel", l1, "Linf rel", linf, "patches", len(h.patches()), len(s.patches()))
+    assert max(l1) <= 1e-5 and max(linf) <= 2e-3
+    for l in range(h.L - 1):
+        fo, fg = h.flags(l).astype(bool), s.flags(l).astype(bool)
+        dis = int((fo != fg).sum())
+        say(f"  level {l}: flagged {int(fo.sum())}, disagreements {dis}")
+        assert dis <= max(2, 0.02 * fo.sum())
