@@ -81,9 +81,16 @@ def test_clustering_amr_gradient_fp64(dim, L, n0, pmax):
     assert linf.max() <= 1e-12
 
 
-def test_clustering_lts_fp64():
-    say("clustering MRLT")
-    h, s, cfl = pair(2, 4, 32, 32, lts=True, seed=5)
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_clustering_lts_fp64(scheme):
+    """MRLT, and AMRLT with the gradient criterion (the AMR method's own
+    configuration), clustered."""
+    say("clustering with local time steps, scheme", scheme)
+    if scheme == 0:
+        h, s, cfl = pair(2, 4, 32, 32, lts=True, seed=5)
+    else:
+        h, s, cfl = pair(2, 4, 32, 32, lts=True, seed=5, scheme=orc.SCHEME_AMR, criterion=orc.CRIT_GRADIENT,
+                         eps=0.05, eps_p=0.05)
     linf = run(h, s, cfl, 2, lts=True)
     say("  linf", linf, "patches", len(h.patches()))
     assert linf.max() <= 1e-12
