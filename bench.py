@@ -55,6 +55,7 @@ HBM_PEAK_GBS = 8000.0
 FV_SOURCES = ["paper_1603_05211_amd/csrc/eu_kernels.hpp", "paper_1603_05211_amd/csrc/eu_kset_impl.hpp",
               "paper_1603_05211_amd/csrc/eu_internal.hpp", "paper_1603_05211_amd/csrc/eu_strip.hpp",
               "paper_1603_05211_amd/csrc/eu_strip3.hpp", "paper_1603_05211_amd/csrc/eu_hancock.hpp"]
+SCHEME_NAMES = ["MR (MUSCL, van Albada, AUSM+, RK2)", "AMR (MUSCL-Hancock, Minmod, AUSMDV)"]
 METRIC = "cell-updates/s (FP32 batched vs FP64 plain) at stated L1 err; % HBM roofline"
 
 WORKLOADS = {
@@ -402,7 +403,7 @@ def extra_line(workload, precision, runs, tune=True, after=None, scheme=0):
     upd, sec, k = r.timed(runs)
     out = {"value": upd / sec, "runs": k, "steps_per_run": r.nsteps, "ms_per_run": 1e3 * sec / k,
            "stage_schedule": r.variant, "tuning": r.tuning, "precision": precision,
-           "scheme": "AMR (MUSCL-Hancock, Minmod, AUSMDV)" if scheme else "MR (MUSCL, van Albada, AUSM+, RK2)"}
+           "scheme": SCHEME_NAMES[scheme]}
     if after is not None:
         acc = after(r)
         if isinstance(acc, dict):
@@ -431,6 +432,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error report")
     ap.add_argument("--schedule", type=int, default=-1, choices=list(range(-1, 10)),
                     help="force a stage-kernel schedule instead of autotuning over the run")
+    ap.add_argument("--scheme", default="mr", choices=["mr", "amr"],
+                    help="amr: time the AMR method (MUSCL-Hancock scheme; on the five-level hierarchy also "
+                         "the gradient criterion and clustering) instead of the MR scheme; needs --no-cpu")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (counter calibration)")
     ap.add_argument("--cpu-sample", default=None, help=argparse.SUPPRESS)
@@ -446,6 +450,11 @@ def main():
               "(the multi-GPU decomposition is a design note only)", file=sys.stderr)
         sys.exit(2)
 
+    if args.scheme == "amr" and not args.no_cpu:
+        print("bench.py: --scheme amr needs --no-cpu (the CPU baseline and error report run the MR scheme)",
+              file=sys.stderr)
+        sys.exit(2)
+
     import numpy as np
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -458,7 +467,8 @@ def main():
         del a, c
 
     wl = args.workload
-    r = Run(wl, args.precision)
+    scheme = 1 if args.scheme == "amr" else 0
+    r = Run(wl, args.precision, scheme=scheme)
     if args.schedule >= 0:
         r.s.set_variant(args.schedule)
         r.variant = args.schedule
@@ -503,7 +513,8 @@ def main():
                    "step": "one whole run over the workload's extent from the initial state "
                            "(initialisation untimed)",
                    "time_steps_per_run": r.nsteps, "leaf_updates_per_run": upd // k,
-                   "stage_schedule": r.variant, "stage_tuning": r.tuning},
+                   "stage_schedule": r.variant, "stage_tuning": r.tuning,
+                   "scheme": SCHEME_NAMES[scheme]},
         "roofline": roof,
     }
     oracle_h = None

@@ -1,6 +1,7 @@
 """Host logic of bench.py (no GPU): the committed counter summaries belong to
 the current kernel sources, the traffic lookup takes the summary of the
-schedule that ran, and more than one GPU is refused."""
+schedule that ran, more than one GPU is refused, and the AMR method is
+timed only without the CPU legs."""
 import json
 import os
 import subprocess
@@ -44,3 +45,11 @@ def test_more_than_one_gpu_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_amr_scheme_needs_no_cpu():
+    """The CPU baseline and the error report run the MR scheme, so timing the
+    AMR method asks for --no-cpu before anything touches the GPU."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--scheme", "amr"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "--no-cpu" in r.stderr and r.stdout == ""
