@@ -4,7 +4,7 @@
 A bench step is one whole run of a workload from its initial state over its
 defined extent (the 2D adaptive workload to t = 0.25, 936 time steps for
 seed 0): initialisation (untimed), then every time step of the run replayed
-from captured HIP graphs (runs of eight steps per graph).  A time step is the whole hot path: CFL
+from captured HIP graphs (runs of sixteen steps per graph).  A time step is the whole hot path: CFL
 reduction, two finite-volume stages on every leaf with projection and ghost
 fill, MR analysis, flags, tiling, lists, prediction of new cells.  value =
 leaf cell-updates per second over the timed runs, with the state resident in

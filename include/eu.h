@@ -278,7 +278,7 @@ int eu_step(eu_ctx *ctx, int regrid);
 
 /* nsteps calls of eu_step(ctx, regrid) (or until t_end), regrid as
  * regrid_every says, replayed from captured HIP graphs when use_graph != 0
- * (runs of eight steps, or of regrid_every steps from a regrid to the next,
+ * (runs of sixteen steps, or of regrid_every steps from a regrid to the next,
  * in one graph; other steps one at a time).  steps_done_host (nullable)
  * receives the number of steps taken. */
 int eu_advance(eu_ctx *ctx, int nsteps, int use_graph, int *steps_done_host);

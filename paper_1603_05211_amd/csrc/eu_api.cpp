@@ -1312,7 +1312,7 @@ int eu_step(eu_ctx *c, int regrid)
 }
 
 // steps per graph of a run (even)
-constexpr int GRAPH_RUN = 8;
+constexpr int GRAPH_RUN = 16;
 
 int eu_advance(eu_ctx *c, int nsteps, int use_graph, int *steps_done)
 {

@@ -137,7 +137,7 @@ def test_graph_replay_equals_eager():
 
 @pytest.mark.parametrize("kw", [dict(levels=3), dict(levels=3, scheme=1), dict(levels=1, n0=64, scheme=1)])
 def test_graph_runs_equal_eager(kw):
-    """Runs of eight steps replay one graph; the rest replays the graphs of
+    """Runs of sixteen steps replay one graph; the rest replays the graphs of
     one step.  Either way the state (patch cells and ghost cells) is that of
     eager steps, bit for bit, also where every step moves the state to the
     other array (the AMR scheme) and a run starts from the second array.
