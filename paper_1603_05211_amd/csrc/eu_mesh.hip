@@ -1165,11 +1165,22 @@ __global__ void __launch_bounds__(64) k_cfl_final(View v)
 #pragma clang fp contract(off)
     static_assert(CFL_NSLOT == 64, "one slot per lane");
     const int lane = threadIdx.x;
+    // every read in one trip: the time, the step counters (read after the
+    // slots are cleared below, which may alias them, they would take a
+    // second trip), the level spacings and the slots
     const double t = v.t[0];
+    const int steps0 = v.meta->steps;
+    const long long upd0 = v.meta->leaf_updates;
+    double dx[NG];
+#pragma unroll
+    for (int l = 0; l < NG; ++l) dx[l] = v.gt[l].dx;
     unsigned long long q[NG + 1];
 #pragma unroll
     for (int l = 0; l < NG; ++l) q[l] = v.cfls[cfl_slot(l, lane)];
     q[NG] = v.cfls[cfl_slot(MAXLEV, lane)];
+    issued(steps0, upd0);
+#pragma unroll
+    for (int l = 0; l < NG; ++l) issued(dx[l]);
     double sm[NG];
 #pragma unroll
     for (int l = 0; l < NG; ++l) {
@@ -1190,7 +1201,7 @@ __global__ void __launch_bounds__(64) k_cfl_final(View v)
 #pragma unroll
     for (int l = 0; l < NG; ++l) {
         if (sm[l] > 0.0) {
-            double d = (v.cfl * v.gt[l].dx) / sm[l];
+            double d = (v.cfl * dx[l]) / sm[l];
             if (v.lts) d = d * (double)(1 << l);
             if (d < dt) dt = d;
         }
@@ -1213,8 +1224,8 @@ __global__ void __launch_bounds__(64) k_cfl_final(View v)
     v.t0[0] = t;
     if (!done) {
         v.t[0] = t + dt;
-        v.meta->steps += 1;
-        v.meta->leaf_updates += upd;
+        v.meta->steps = steps0 + 1;
+        v.meta->leaf_updates = upd0 + upd;
     }
 }
 
