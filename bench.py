@@ -56,6 +56,8 @@ FV_SOURCES = ["paper_1603_05211_amd/csrc/eu_kernels.hpp", "paper_1603_05211_amd/
               "paper_1603_05211_amd/csrc/eu_internal.hpp", "paper_1603_05211_amd/csrc/eu_strip.hpp",
               "paper_1603_05211_amd/csrc/eu_strip3.hpp", "paper_1603_05211_amd/csrc/eu_hancock.hpp"]
 SCHEME_NAMES = ["MR (MUSCL, van Albada, AUSM+, RK2)", "AMR (MUSCL-Hancock, Minmod, AUSMDV)"]
+# workloads set up with the AMR scheme when asked for (Run below)
+AMR_WORKLOADS = {"quad2d_adaptive5", "quad2d_batch512", "quad2d_uniform128"}
 METRIC = "cell-updates/s (FP32 batched vs FP64 plain) at stated L1 err; % HBM roofline"
 
 WORKLOADS = {
@@ -452,6 +454,10 @@ def main():
 
     if args.scheme == "amr" and not args.no_cpu:
         print("bench.py: --scheme amr needs --no-cpu (the CPU baseline and error report run the MR scheme)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.scheme == "amr" and args.workload not in AMR_WORKLOADS:
+        print(f"bench.py: --scheme amr runs on {', '.join(sorted(AMR_WORKLOADS))}, not {args.workload}",
               file=sys.stderr)
         sys.exit(2)
 

@@ -53,3 +53,9 @@ def test_amr_scheme_needs_no_cpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--scheme", "amr"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "--no-cpu" in r.stderr and r.stdout == ""
+
+
+def test_amr_scheme_only_where_set_up():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--scheme", "amr", "--no-cpu", "--workload",
+                        "ellip3d_uniform256"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "ellip3d_uniform256" in r.stderr and r.stdout == ""
