@@ -515,7 +515,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic: seeded inputs (seed 0) shaped like the paper's test problems",
-        "config": {"workload": f"{wl}: {WORKLOADS[wl]}", "precision": args.precision,
+        "config": {"workload": f"{wl}: {WORKLOADS[wl]}" + (
+                       "; run with the AMR method: scaled-gradient criterion on density (eps 0.05), "
+                       "Berger-Rigoutsos clustering" if scheme and wl == "quad2d_adaptive5" else ""),
+                   "precision": args.precision,
                    "step": "one whole run over the workload's extent from the initial state "
                            "(initialisation untimed)",
                    "time_steps_per_run": r.nsteps, "leaf_updates_per_run": upd // k,
